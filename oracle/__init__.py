@@ -1,0 +1,253 @@
+"""Plain FP64 CPU oracle (test infrastructure only).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  It wraps ``pf_oracle.c`` (plain loops, double precision, built with
+``-O2 -ffp-contract=off``) through ctypes and shares nothing with the HIP library.
+Every function follows a definition of the paper (arXiv 2404.16039); the C source names
+the section each one comes from.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pf_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle into oracle/liboracle.so (plain gcc, no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+               "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = C.CDLL(_LIB)
+        P = C.c_void_p
+        I64 = C.c_int64
+        INT = C.c_int
+        D = C.c_double
+        lib.or_page_det.argtypes = [INT, I64, P, P, P]
+        lib.or_page_inv.argtypes = [INT, I64, P, P, P, P]
+        lib.or_page_transpose.argtypes = [INT, INT, I64, P, P]
+        lib.or_page_mtimes.argtypes = [INT, INT, INT, I64, P, INT, I64, P, INT, I64, P, P]
+        lib.or_page_scale.argtypes = [INT, INT, I64, P, P, P]
+        lib.or_page_bilinear.argtypes = [INT, I64, P, P, P, P]
+        lib.or_p1_elements.argtypes = [INT, I64, P, I64, P, P, P, P, P, P, P, P]
+        lib.or_p1_elements.restype = I64
+        lib.or_create_coords3d.argtypes = [INT, INT, I64, P, I64, P, P, P]
+        lib.or_route_predicate.argtypes = [INT, P, I64, D, D, P, P]
+        lib.or_assemble.argtypes = [INT, I64, I64, P, P, P, P, P, P, P, P, P, P, I64]
+        lib.or_assemble.restype = I64
+        lib.or_assemble_rows.argtypes = [INT, I64, P, I64, P, INT, P, INT, P, P, P, P, P, P]
+        lib.or_boundary.argtypes = [INT, I64, P, I64, P, P, P, P]
+        for f in ("or_page_det", "or_page_inv", "or_page_transpose", "or_page_mtimes", "or_page_scale",
+                  "or_page_bilinear", "or_create_coords3d", "or_route_predicate", "or_assemble_rows",
+                  "or_boundary"):
+            getattr(lib, f).restype = INT
+        _lib = lib
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+    return rc
+
+
+# ----------------------------------------------------------------------------- page ops
+def page_det(a, n):
+    """Leibniz determinant of each n x n column-major page. Returns (det, perm(|A|))."""
+    a = _f64(a).reshape(-1, n * n)
+    det = np.empty(a.shape[0])
+    pa = np.empty(a.shape[0])
+    _check(_load().or_page_det(n, a.shape[0], _p(a), _p(det), _p(pa)), "page_det")
+    return det, pa
+
+
+def page_inv(a, n):
+    """Gauss-Jordan inverse of each page. Returns (inv, singular flags, |A^-1||A||A^-1|)."""
+    a = _f64(a).reshape(-1, n * n)
+    inv = np.empty_like(a)
+    sing = np.empty(a.shape[0], dtype=np.uint8)
+    sc = np.empty_like(a)
+    _check(_load().or_page_inv(n, a.shape[0], _p(a), _p(inv), _p(sing), _p(sc)), "page_inv")
+    return inv, sing, sc
+
+
+def page_transpose(a, rows, cols):
+    a = _f64(a).reshape(-1, rows * cols)
+    t = np.empty_like(a)
+    _check(_load().or_page_transpose(rows, cols, a.shape[0], _p(a), _p(t)), "page_transpose")
+    return t
+
+
+def page_mtimes(A, B, m, k, n, transA=False, transB=False, count=None):
+    """C_k = op(A_k) op(B_k) (m x k times k x n). A or B with a single page is broadcast.
+    Returns (C, (|op A||op B|))."""
+    A = _f64(A).reshape(-1, m * k)
+    B = _f64(B).reshape(-1, k * n)
+    if count is None:
+        count = max(A.shape[0], B.shape[0])
+    sA = 0 if A.shape[0] == 1 and count != 1 else m * k
+    sB = 0 if B.shape[0] == 1 and count != 1 else k * n
+    Cm = np.empty((count, m * n))
+    absC = np.empty_like(Cm)
+    _check(_load().or_page_mtimes(m, k, n, count, _p(A), int(transA), sA, _p(B), int(transB), sB,
+                                  _p(Cm), _p(absC)), "page_mtimes")
+    return Cm, absC
+
+
+def page_scale(s, a, rows, cols):
+    a = _f64(a).reshape(-1, rows * cols)
+    s = _f64(s).reshape(-1)
+    c = np.empty_like(a)
+    _check(_load().or_page_scale(rows, cols, a.shape[0], _p(s), _p(a), _p(c)), "page_scale")
+    return c
+
+
+def page_bilinear(u, a, v, n):
+    a = _f64(a).reshape(-1, n * n)
+    u = _f64(u).reshape(-1, n)
+    v = _f64(v).reshape(-1, n)
+    q = np.empty(a.shape[0])
+    _check(_load().or_page_bilinear(n, a.shape[0], _p(u), _p(a), _p(v), _p(q)), "page_bilinear")
+    return q
+
+
+# ----------------------------------------------------------------------------- elements
+def p1_elements(coords, elems):
+    """Per-element det, vol, grads (dim x nlb col-major), Ke, Me, Kabs, facet measures."""
+    coords = _f64(coords)
+    elems = _i32(elems)
+    nn, dim = coords.shape
+    ne, nlb = elems.shape
+    assert nlb == dim + 1
+    det = np.empty(ne)
+    vol = np.empty(ne)
+    grads = np.empty((ne, dim * nlb))
+    Ke = np.empty((ne, nlb * nlb))
+    Me = np.empty((ne, nlb * nlb))
+    Ka = np.empty((ne, nlb * nlb))
+    fac = np.empty((ne, nlb))
+    rc = _load().or_p1_elements(dim, nn, _p(coords), ne, _p(elems), _p(det), _p(vol), _p(grads), _p(Ke),
+                                _p(Me), _p(Ka), _p(fac))
+    _check(rc, "p1_elements")
+    return {"det": det, "vol": vol, "grads": grads, "Ke": Ke, "Me": Me, "Kabs": Ka, "facet": fac,
+            "nsingular": int(rc)}
+
+
+def create_coords3d(coords, elems):
+    """coords3D (ne, dim*nlb) and vectors3D (ne, dim*(nlb-1)), column-major pages."""
+    coords = _f64(coords)
+    elems = _i32(elems)
+    nn, dim = coords.shape
+    ne, nlb = elems.shape
+    c3 = np.empty((ne, dim * nlb))
+    v3 = np.empty((ne, dim * (nlb - 1)))
+    _check(_load().or_create_coords3d(dim, nlb, nn, _p(coords), ne, _p(elems), _p(c3), _p(v3)), "coords3d")
+    return c3, v3
+
+
+def route_predicate(tjac_pages, dim, tau_abs, tau_cond):
+    t = _f64(tjac_pages).reshape(-1, dim * dim)
+    routed = np.empty(t.shape[0], dtype=np.uint8)
+    cond = np.empty(t.shape[0])
+    _check(_load().or_route_predicate(dim, _p(t), t.shape[0], float(tau_abs), float(tau_cond), _p(routed),
+                                      _p(cond)), "route_predicate")
+    return routed.astype(bool), cond
+
+
+def jacobians(coords, elems):
+    """tjac pages (first-node origin, column-major dim x dim): column c holds d x_c / d xi."""
+    c3, _ = create_coords3d(coords, elems)
+    dim = _f64(coords).shape[1]
+    nlb = dim + 1
+    ds = np.zeros((dim, nlb))
+    ds[:, 0] = -1.0
+    ds[np.arange(dim), np.arange(1, nlb)] = 1.0
+    # tjac = dshape * coords3D^T  (smamt of the derivative routine)
+    Cm, _ = page_mtimes(ds.T.reshape(1, -1), c3, dim, nlb, dim, transA=False, transB=True)
+    return Cm
+
+
+# ----------------------------------------------------------------------------- assembly
+def assemble(elems, nn, Ke, Me=None, Kabs=None):
+    """sparse() of the listings: CSR (row_ptr, col_idx, valK, valM, scaleK, scaleM)."""
+    elems = _i32(elems)
+    ne, nlb = elems.shape
+    Ke = _f64(Ke)
+    Me = None if Me is None else _f64(Me)
+    Kabs = None if Kabs is None else _f64(Kabs)
+    cap = ne * nlb * nlb
+    row_ptr = np.empty(nn + 1, dtype=np.int64)
+    col = np.empty(max(cap, 1), dtype=np.int32)
+    vk = np.empty(max(cap, 1))
+    vm = np.empty(max(cap, 1))
+    sk = np.empty(max(cap, 1))
+    sm = np.empty(max(cap, 1))
+    nnz = _load().or_assemble(nlb, nn, ne, _p(elems), _p(Ke), _p(Me), _p(Kabs), _p(row_ptr), _p(col),
+                              _p(vk), _p(vm), _p(sk), _p(sm), cap)
+    _check(nnz, "assemble")
+    return {"row_ptr": row_ptr, "col_idx": col[:nnz].copy(), "valK": vk[:nnz].copy(),
+            "valM": vm[:nnz].copy() if Me is not None else None, "scaleK": sk[:nnz].copy(),
+            "scaleM": sm[:nnz].copy() if Me is not None else None, "nnz": int(nnz)}
+
+
+def assemble_rows(coords, elems, rows, cap=64):
+    """Sampled CSR rows computed one by one. Returns list of (cols, valK, valM, scaleK, scaleM)."""
+    coords = _f64(coords)
+    elems = _i32(elems)
+    rows = _i32(rows)
+    nn, dim = coords.shape
+    ne = elems.shape[0]
+    nr = rows.shape[0]
+    cols = np.zeros((nr, cap), dtype=np.int32)
+    vk = np.zeros((nr, cap))
+    vm = np.zeros((nr, cap))
+    sk = np.zeros((nr, cap))
+    sm = np.zeros((nr, cap))
+    ln = np.zeros(nr, dtype=np.int32)
+    _check(_load().or_assemble_rows(dim, nn, _p(coords), ne, _p(elems), nr, _p(rows), cap, _p(cols), _p(vk),
+                                    _p(vm), _p(sk), _p(sm), _p(ln)), "assemble_rows")
+    return [(cols[r, :ln[r]].copy(), vk[r, :ln[r]].copy(), vm[r, :ln[r]].copy(), sk[r, :ln[r]].copy(),
+             sm[r, :ln[r]].copy()) for r in range(nr)]
+
+
+def boundary(coords, faces):
+    """Boundary facets: (unit normals, measures, raw normals)."""
+    coords = _f64(coords)
+    faces = _i32(faces)
+    nn, dim = coords.shape
+    nf = faces.shape[0]
+    unit = np.empty((nf, dim))
+    meas = np.empty(nf)
+    raw = np.empty((nf, dim))
+    _check(_load().or_boundary(dim, nn, _p(coords), nf, _p(faces), _p(unit), _p(meas), _p(raw)), "boundary")
+    return unit, meas, raw

@@ -1,0 +1,489 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix (no GPU).
+
+Each test checks the oracle against something other than itself: values the paper prints
+(worked example, mesh counts), exact rational arithmetic by a different algorithm,
+closed forms (reference elements, stencils, energies of linear functions, divergence
+theorem), library routines on special cases, and brute force on tiny inputs.
+"""
+import itertools
+import math
+import os
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_16039_amd import gen
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    out = {}
+    with open(os.path.join(GOLD, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            key, *vals = line.split()
+            out[key] = vals
+    return out
+
+
+def _rows(vals, r, c):
+    return np.array([float(Fr(v)) for v in vals]).reshape(r, c)
+
+
+def _colmajor(m):
+    """flatten a 2-D numpy matrix into a column-major page"""
+    return np.asarray(m, dtype=np.float64).T.reshape(-1)
+
+
+def _page(flat, r, c):
+    """column-major page -> 2-D numpy matrix"""
+    return np.asarray(flat).reshape(c, r).T
+
+
+# ------------------------------------------------------------------ worked example (3.2)
+def test_worked_example_vectors_det_normals():
+    g = _golden("worked_tet.txt")
+    nodes = _rows(g["nodes_x4"], 4, 3) / 4.0
+    elems = np.array([[0, 1, 2, 3]], dtype=np.int32)
+    c3, v3 = oracle.create_coords3d(nodes, elems)
+    V = _page(v3[0], 3, 3)
+    assert np.array_equal(V * 4.0, _rows(g["vectors3D_x4"], 3, 3))
+    det, _ = oracle.page_det(v3, 3)
+    assert det[0] / 6.0 == float(Fr(g["det_over_6"][0]))
+    # normals3D = amsm(amt(aminv(vectors3D)), normalsRef)
+    inv, sing, _ = oracle.page_inv(v3, 3)
+    assert sing[0] == 0
+    invT = oracle.page_transpose(inv, 3, 3)
+    nref = _rows(g["normalsRef"], 3, 4)
+    N, _ = oracle.page_mtimes(invT, _colmajor(nref)[None, :], 3, 3, 4)
+    expect = _rows(g["normals3D"], 3, 4)
+    assert np.allclose(_page(N[0], 3, 4), expect, rtol=0, atol=1e-15)
+    assert np.allclose(_page(N[0], 3, 4).sum(axis=1), 0.0, atol=1e-15)
+
+
+def test_worked_example_element_outputs():
+    g = _golden("worked_tet.txt")
+    nodes = _rows(g["nodes_x4"], 4, 3) / 4.0
+    el = oracle.p1_elements(nodes, np.array([[0, 1, 2, 3]], dtype=np.int32))
+    vol = float(-Fr(g["det_over_6"][0]))
+    assert abs(el["vol"][0] - vol) < 1e-15
+    # tet normals of the example are minus the barycentric gradients
+    N = _rows(g["normals3D"], 3, 4)
+    G = _page(el["grads"][0], 3, 4)
+    assert np.allclose(-G, N, atol=1e-14)
+    # facet measures against direct cross products of the faces
+    for j in range(4):
+        f = [k for k in range(4) if k != j]
+        a, b, c = nodes[f]
+        area = 0.5 * np.linalg.norm(np.cross(b - a, c - a))
+        assert abs(el["facet"][0, j] - area) < 1e-14
+
+
+# ------------------------------------------------------------ reference elements (3.5)
+def test_reference_tetrahedron():
+    nodes = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], dtype=float)
+    el = oracle.p1_elements(nodes, np.array([[0, 1, 2, 3]], dtype=np.int32))
+    assert el["det"][0] == 1.0
+    assert el["vol"][0] == 1.0 / 6.0
+    K = _page(el["Ke"][0], 4, 4)
+    K6 = np.array([[3, -1, -1, -1], [-1, 1, 0, 0], [-1, 0, 1, 0], [-1, 0, 0, 1]], float)
+    assert np.allclose(6 * K, K6, atol=1e-15)
+    M = _page(el["Me"][0], 4, 4)
+    assert np.allclose(M * 120.0, np.ones((4, 4)) + np.eye(4), atol=1e-14)
+
+
+def test_reference_triangle():
+    nodes = np.array([[0, 0], [1, 0], [0, 1]], dtype=float)
+    el = oracle.p1_elements(nodes, np.array([[0, 1, 2]], dtype=np.int32))
+    assert el["det"][0] == 1.0 and el["vol"][0] == 0.5
+    K = _page(el["Ke"][0], 3, 3)
+    assert np.allclose(2 * K, [[2, -1, -1], [-1, 1, 0], [-1, 0, 1]], atol=1e-15)
+    M = _page(el["Me"][0], 3, 3)
+    assert np.allclose(M * 24.0, np.ones((3, 3)) + np.eye(3), atol=1e-14)
+
+
+# ------------------------------------------------------------------ page determinant
+def _det_laplace(m):
+    """exact determinant by Laplace expansion along the first row (Fractions)"""
+    n = len(m)
+    if n == 1:
+        return m[0][0]
+    s = Fr(0)
+    for j in range(n):
+        minor = [row[:j] + row[j + 1:] for row in m[1:]]
+        s += (-1) ** j * m[0][j] * _det_laplace(minor)
+    return s
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_det_exact_integer_pages(n):
+    g = np.random.default_rng(1)
+    A = g.integers(-9, 10, size=(300, n, n)).astype(float)
+    det, pa = oracle.page_det(np.transpose(A, (0, 2, 1)).reshape(300, -1), n)
+    for k in range(300):
+        ex = _det_laplace([[Fr(int(v)) for v in row] for row in A[k]])
+        assert det[k] == float(ex)
+    # perm(|A|) bounds |det|
+    assert np.all(np.abs(det) <= pa)
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_det_float_pages_exact_rational(n):
+    A = gen.page_batch(400, n, sub=7)  # column-major pages
+    det, pa = oracle.page_det(A, n)
+    for k in range(400):
+        m = _page(A[k], n, n)
+        ex = _det_laplace([[Fr(float(v)) for v in row] for row in m])
+        assert abs(det[k] - float(ex)) <= 8 * 2.0 ** -53 * pa[k]
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_det_identities(n):
+    g = np.random.default_rng(2)
+    A = g.standard_normal((50, n, n))
+    B = g.standard_normal((50, n, n))
+    fa = np.transpose(A, (0, 2, 1)).reshape(50, -1)
+    fb = np.transpose(B, (0, 2, 1)).reshape(50, -1)
+    AB, _ = oracle.page_mtimes(fa, fb, n, n, n)
+    da, _ = oracle.page_det(fa, n)
+    db, _ = oracle.page_det(fb, n)
+    dab, _ = oracle.page_det(AB, n)
+    assert np.allclose(dab, da * db, rtol=1e-12, atol=1e-12)
+    # library routine on the same pages
+    assert np.allclose(da, np.linalg.det(A), rtol=1e-12, atol=1e-13)
+    # triangular pages: product of the diagonal; permutation matrices: their sign
+    T = np.triu(A)
+    dt, _ = oracle.page_det(np.transpose(T, (0, 2, 1)).reshape(50, -1), n)
+    assert np.allclose(dt, np.prod(np.diagonal(T, axis1=1, axis2=2), axis=1), rtol=1e-14)
+    for p in itertools.permutations(range(n)):
+        P = np.eye(n)[list(p)]
+        d, _ = oracle.page_det(_colmajor(P)[None, :], n)
+        s = round(np.linalg.det(P))
+        assert d[0] == s
+    dI, _ = oracle.page_det(_colmajor(np.eye(n))[None, :], n)
+    assert dI[0] == 1.0
+
+
+# ------------------------------------------------------------------ page inverse
+def _inv_exact(m):
+    n = len(m)
+    d = _det_laplace(m)
+    adj = [[None] * n for _ in range(n)]
+    for i in range(n):
+        for j in range(n):
+            minor = [row[:j] + row[j + 1:] for r, row in enumerate(m) if r != i]
+            adj[j][i] = (-1) ** (i + j) * (_det_laplace(minor) if n > 1 else Fr(1))
+    return [[adj[i][j] / d for j in range(n)] for i in range(n)]
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_inverse_exact_rational(n):
+    A = gen.page_batch(200, n, sub=11)
+    inv, sing, scale = oracle.page_inv(A, n)
+    assert not sing.any()
+    for k in range(200):
+        m = _page(A[k], n, n)
+        ex = _inv_exact([[Fr(float(v)) for v in row] for row in m])
+        X = _page(inv[k], n, n)
+        S = _page(scale[k], n, n)
+        for i in range(n):
+            for j in range(n):
+                assert abs(X[i, j] - float(ex[i][j])) <= 64 * 2.0 ** -53 * S[i, j]
+
+
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_inverse_identities_and_singular(n):
+    A = gen.page_batch(100, n, sub=12)
+    inv, sing, _ = oracle.page_inv(A, n)
+    P, _ = oracle.page_mtimes(A, inv, n, n, n)
+    I = _colmajor(np.eye(n))
+    assert np.allclose(P, I[None, :], atol=1e-12)
+    assert np.allclose(inv, np.transpose(np.linalg.inv(np.transpose(A.reshape(-1, n, n), (0, 2, 1))),
+                                         (0, 2, 1)).reshape(100, -1), rtol=1e-11, atol=1e-12)
+    # pages with a repeated or a zero column are singular; elimination keeps equal columns
+    # equal, so the zero pivot is met exactly
+    g = np.random.default_rng(3)
+    R = g.integers(-5, 6, size=(20, n, n)).astype(float)
+    R[:10, :, -1] = R[:10, :, 0]
+    R[10:, :, n // 2] = 0.0
+    _, s2, _ = oracle.page_inv(np.transpose(R, (0, 2, 1)).reshape(20, -1), n)
+    assert s2.all()
+
+
+# --------------------------------------------------------- transpose / products / scale
+def test_transpose_and_products_vs_library():
+    g = np.random.default_rng(4)
+    for (m, k, n) in [(3, 3, 3), (2, 2, 2), (4, 4, 4), (3, 4, 2), (1, 3, 3), (3, 3, 1), (1, 4, 1)]:
+        A = g.standard_normal((30, m, k))
+        B = g.standard_normal((30, k, n))
+        fa = np.transpose(A, (0, 2, 1)).reshape(30, -1)
+        fb = np.transpose(B, (0, 2, 1)).reshape(30, -1)
+        Cm, absC = oracle.page_mtimes(fa, fb, m, k, n)
+        ref = A @ B
+        assert np.allclose(Cm, np.transpose(ref, (0, 2, 1)).reshape(30, -1), rtol=1e-13, atol=1e-13)
+        assert np.all(np.abs(Cm) <= absC * (1 + 1e-15))
+        # transposed storage of the operands gives the same product
+        At = oracle.page_transpose(fa, m, k)
+        Bt = oracle.page_transpose(fb, k, n)
+        C2, _ = oracle.page_mtimes(At, Bt, m, k, n, transA=True, transB=True)
+        assert np.array_equal(C2, Cm)
+        # broadcast of a single B page equals explicit copies (the copy map)
+        C3, _ = oracle.page_mtimes(fa, fb[:1], m, k, n)
+        C4, _ = oracle.page_mtimes(fa, np.repeat(fb[:1], 30, axis=0), m, k, n)
+        assert np.array_equal(C3, C4)
+    T = oracle.page_transpose(oracle.page_transpose(fa, m, k), k, m)
+    assert np.array_equal(T, fa)
+    s = g.standard_normal(30)
+    Sc = oracle.page_scale(s, fa, m, k)
+    assert np.array_equal(Sc, fa * s[:, None])
+    u = g.standard_normal((30, 3))
+    v = g.standard_normal((30, 3))
+    M3 = g.standard_normal((30, 3, 3))
+    q = oracle.page_bilinear(u, np.transpose(M3, (0, 2, 1)).reshape(30, -1), v, 3)
+    assert np.allclose(q, np.einsum("ki,kij,kj->k", u, M3, v), rtol=1e-13)
+
+
+# ------------------------------------------------------------------ element properties
+@pytest.mark.parametrize("dim", [2, 3])
+def test_element_properties(dim):
+    if dim == 2:
+        coords, elems, _ = gen.square_mesh(6)
+    else:
+        coords, elems, _ = gen.cube_mesh(3)
+    el = oracle.p1_elements(coords, elems)
+    nlb = dim + 1
+    ne = elems.shape[0]
+    K = el["Ke"].reshape(ne, nlb, nlb)
+    M = el["Me"].reshape(ne, nlb, nlb)
+    G = el["grads"].reshape(ne, nlb, dim).transpose(0, 2, 1)
+    assert np.all(el["det"] > 0)
+    assert np.allclose(K.sum(axis=2), 0.0, atol=1e-12)
+    assert np.allclose(K, np.transpose(K, (0, 2, 1)), atol=1e-14)
+    assert np.all(np.linalg.eigvalsh(K) > -1e-12)
+    # mass: exact integral of barycentric products |T| (1 + delta) / ((d+1)(d+2))
+    fac = (dim + 1) * (dim + 2)
+    ex = el["vol"][:, None, None] * (np.ones((nlb, nlb)) + np.eye(nlb)) / fac
+    assert np.allclose(M, ex, rtol=1e-13, atol=0)
+    assert np.allclose(M.sum(axis=(1, 2)), el["vol"], rtol=1e-13)
+    # gradients reproduce linear functions: sum_j x_j grad(phi_j)^T = I, sum_j grad phi_j = 0
+    X = coords[elems]  # ne x nlb x dim
+    Gx = np.einsum("kij,kjl->kil", G, X)
+    assert np.allclose(Gx, np.eye(dim)[None], atol=1e-11)
+    assert np.allclose(G.sum(axis=2), 0.0, atol=1e-10)
+    # volume: scalar triple product / cross product of the edges
+    E = X[:, 1:, :] - X[:, :1, :]
+    if dim == 3:
+        vol = np.abs(np.einsum("ki,ki->k", E[:, 0], np.cross(E[:, 1], E[:, 2]))) / 6
+    else:
+        vol = np.abs(E[:, 0, 0] * E[:, 1, 1] - E[:, 0, 1] * E[:, 1, 0]) / 2
+    assert np.allclose(el["vol"], vol, rtol=1e-13)
+    # facet measures: direct lengths / cross products of the opposite facet
+    for j in range(nlb):
+        f = [q for q in range(nlb) if q != j]
+        if dim == 3:
+            a, b, c = X[:, f[0]], X[:, f[1]], X[:, f[2]]
+            meas = 0.5 * np.linalg.norm(np.cross(b - a, c - a), axis=1)
+        else:
+            meas = np.linalg.norm(X[:, f[1]] - X[:, f[0]], axis=1)
+        assert np.allclose(el["facet"][:, j], meas, rtol=1e-12)
+    # tet normals (= -grads) are orthogonal to the edges of their facet
+    for j in range(nlb):
+        f = [q for q in range(nlb) if q != j]
+        for a, b in itertools.combinations(f, 2):
+            assert np.allclose(np.einsum("ki,ki->k", G[:, :, j], X[:, a] - X[:, b]), 0, atol=1e-11)
+
+
+# ------------------------------------------------------------------ assembly
+def _dense(elems, nn, Ke):
+    ne, nlb = elems.shape
+    D = np.zeros((nn, nn))
+    for e in range(ne):
+        for a in range(nlb):
+            for b in range(nlb):
+                D[elems[e, a], elems[e, b]] += Ke[e, a + b * nlb]
+    return D
+
+
+def _csr_to_dense(csr, nn, key):
+    D = np.zeros((nn, nn))
+    rp = csr["row_ptr"]
+    for i in range(nn):
+        for p in range(rp[i], rp[i + 1]):
+            D[i, csr["col_idx"][p]] += csr[key][p]
+    return D
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_assembly_brute_force_and_closed_forms(dim):
+    if dim == 2:
+        coords, elems, _ = gen.square_mesh(8)
+        cnt = gen.square_counts(8)
+    else:
+        coords, elems, _ = gen.cube_mesh(3)
+        cnt = gen.kuhn_counts(3)
+    nn = coords.shape[0]
+    el = oracle.p1_elements(coords, elems)
+    csr = oracle.assemble(elems, nn, el["Ke"], el["Me"], el["Kabs"])
+    assert csr["nnz"] == cnt["nnz"]
+    rp, ci = csr["row_ptr"], csr["col_idx"]
+    for i in range(nn):
+        seg = ci[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(seg) > 0)
+    DK = _csr_to_dense(csr, nn, "valK")
+    DM = _csr_to_dense(csr, nn, "valM")
+    assert np.allclose(DK, _dense(elems, nn, el["Ke"]), atol=1e-13)
+    assert np.allclose(DM, _dense(elems, nn, el["Me"]), atol=1e-15)
+    # pattern = all element node pairs
+    P = np.zeros((nn, nn), bool)
+    for e in elems:
+        P[np.ix_(e, e)] = True
+    assert P.sum() == csr["nnz"]
+    assert np.allclose(DK.sum(axis=1), 0.0, atol=1e-12)  # K 1 = 0
+    assert abs(DM.sum() - 1.0) < 1e-13  # 1^T M 1 = |Omega|
+    # energies of a linear function v = g.x + c: v^T K v = |g|^2 |Omega|; v^T M v = int v^2
+    gv = np.array([0.7, -1.3, 0.4][:dim])
+    c0 = 0.25
+    v = coords @ gv + c0
+    assert abs(v @ DK @ v - gv @ gv) < 1e-11
+    # int over the unit square/cube of (g.x + c)^2 = sum_i g_i^2/3 + sum_{i<j} g_i g_j/2 + c sum g + c^2
+    ex = (gv ** 2).sum() / 3 + sum(gv[i] * gv[j] for i in range(dim) for j in range(i + 1, dim)) / 2 \
+        + c0 * gv.sum() + c0 ** 2
+    assert abs(v @ DM @ v - ex) < 1e-12
+    # sampled rows computed one by one equal the full assembly bit for bit
+    rows = np.array([0, nn // 3, nn // 2, nn - 1], dtype=np.int32)
+    rr = oracle.assemble_rows(coords, elems, rows)
+    for r, (cols, vk, vm, sk, sm) in zip(rows, rr):
+        sl = slice(rp[r], rp[r + 1])
+        assert np.array_equal(cols, ci[sl])
+        assert np.array_equal(vk, csr["valK"][sl])
+        assert np.array_equal(vm, csr["valM"][sl])
+        assert np.array_equal(sk, csr["scaleK"][sl])
+
+
+def _stencil(spec):
+    out = {}
+    for tok in spec:
+        off, val = tok.split(":")
+        out[tuple(int(x) for x in off.split(","))] = float(val)
+    return out
+
+
+def test_unjittered_stencils():
+    g = _golden("stencils.txt")
+    n = 6
+    # 2-D
+    coords, elems, _ = gen.square_mesh(n, jitter=0.0)
+    el = oracle.p1_elements(coords, elems)
+    csr = oracle.assemble(elems, coords.shape[0], el["Ke"], el["Me"])
+    m = n + 1
+    i0 = 3 + m * 3
+    rp, ci = csr["row_ptr"], csr["col_idx"]
+    got_k = {}
+    got_m = {}
+    for p in range(rp[i0], rp[i0 + 1]):
+        j = ci[p]
+        off = (j % m - 3, j // m - 3)
+        got_k[off] = csr["valK"][p]
+        got_m[off] = csr["valM"][p] * 12 * n * n
+    ek, em = _stencil(g["2d_K"]), _stencil(g["2d_M12"])
+    assert set(got_k) == set(ek)
+    for k in ek:
+        assert abs(got_k[k] - ek[k]) < 1e-13 and abs(got_m[k] - em[k]) < 1e-12
+    # 3-D
+    coords, elems, _ = gen.cube_mesh(n, jitter=0.0)
+    el = oracle.p1_elements(coords, elems)
+    csr = oracle.assemble(elems, coords.shape[0], el["Ke"], el["Me"])
+    i0 = 3 + m * 3 + m * m * 3
+    rp, ci = csr["row_ptr"], csr["col_idx"]
+    got_k, got_m = {}, {}
+    h = 1.0 / n
+    for p in range(rp[i0], rp[i0 + 1]):
+        j = ci[p]
+        off = (j % m - 3, (j // m) % m - 3, j // (m * m) - 3)
+        got_k[off] = csr["valK"][p] / h
+        got_m[off] = csr["valM"][p] * 120 / h ** 3
+    ek, em = _stencil(g["3d_Kh"]), _stencil(g["3d_M120"])
+    assert set(got_k) == set(ek)
+    for k in ek:
+        assert abs(got_k[k] - ek[k]) < 1e-12 and abs(got_m[k] - em[k]) < 1e-11
+
+
+# ------------------------------------------------------------------ meshes and boundary
+def test_mesh_counts_match_paper_levels():
+    rows = _golden("sphere_levels.txt")
+    with open(os.path.join(GOLD, "sphere_levels.txt")) as f:
+        lines = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    for lv, ne, nn, nf, nfb in lines:
+        c = gen.kuhn_counts(2 ** (int(lv) + 1))
+        assert (c["tets"], c["nodes"], c["faces"], c["bfaces"]) == (int(ne), int(nn), int(nf), int(nfb))
+    assert rows  # fixture parsed
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_kuhn_mesh_brute_force_faces(n):
+    coords, elems, faces = gen.cube_mesh(n, jitter=0.15)
+    c = gen.kuhn_counts(n)
+    assert elems.shape[0] == c["tets"] and coords.shape[0] == c["nodes"]
+    count = {}
+    opp = {}
+    for e in elems:
+        for j in range(4):
+            f = tuple(sorted(int(e[q]) for q in range(4) if q != j))
+            count[f] = count.get(f, 0) + 1
+            opp[f] = int(e[j])
+    bset = {f for f, k in count.items() if k == 1}
+    assert len(count) == c["faces"] and len(bset) == c["bfaces"] == faces.shape[0]
+    assert {tuple(sorted(map(int, f))) for f in faces} == bset
+    unit, area, raw = oracle.boundary(coords, faces)
+    for f, nrm in zip(faces, raw):
+        q = coords[opp[tuple(sorted(map(int, f)))]]
+        assert nrm @ (q - coords[f[0]]) < 0  # outward
+    assert abs(area.sum() - 6.0) < 1e-12
+    assert np.allclose((area[:, None] * unit).sum(axis=0), 0, atol=1e-12)
+    cent = coords[faces].mean(axis=1)
+    flux = (area * np.einsum("ki,ki->k", cent, unit)).sum()  # div(x) = 3 -> 3 |Omega|
+    assert abs(flux - 3.0) < 1e-12
+    el = oracle.p1_elements(coords, elems)
+    assert abs(el["vol"].sum() - 1.0) < 1e-13
+
+
+def test_square_boundary():
+    coords, elems, bed = gen.square_mesh(5)
+    c = gen.square_counts(5)
+    assert elems.shape[0] == c["tris"] and bed.shape[0] == c["bedges"]
+    unit, length, raw = oracle.boundary(coords, bed)
+    assert abs(length.sum() - 4.0) < 1e-13
+    cent = coords[bed].mean(axis=1)
+    assert abs((length * np.einsum("ki,ki->k", cent, unit)).sum() - 2.0) < 1e-13
+    assert np.allclose((length[:, None] * unit).sum(axis=0), 0, atol=1e-13)
+    el = oracle.p1_elements(coords, elems)
+    assert np.all(el["det"] > 0) and abs(el["vol"].sum() - 1.0) < 1e-13
+
+
+def test_routing_predicate_slivers():
+    coords, elems, _ = gen.cube_mesh(4)
+    h = 0.25
+    c2, e2, t = gen.append_slivers(coords, elems, 64, h)
+    tj = oracle.jacobians(c2, e2)
+    routed, cond = oracle.route_predicate(tj, 3, 1e-3 * h ** 3, 1e6)
+    ne0 = elems.shape[0]
+    assert not routed[:ne0].any()
+    assert routed[ne0:].all()
+    det, _ = oracle.page_det(tj, 3)
+    assert np.allclose(np.abs(det[ne0:]), t * h ** 3, rtol=1e-6)
+    # jitter of 0.15 h never brings a Kuhn element below 0.1 h^3
+    assert det[:ne0].min() >= 0.1 * h ** 3 * (1 - 1e-12)
+
+
+def test_integer_pages_exact():
+    g = np.random.default_rng(5)
+    A = g.integers(-4, 5, size=(100, 9)).astype(float)
+    B = g.integers(-4, 5, size=(100, 9)).astype(float)
+    Cm, _ = oracle.page_mtimes(A, B, 3, 3, 3)
+    ref = np.einsum("kij,kjl->kil", A.reshape(100, 3, 3).transpose(0, 2, 1), B.reshape(100, 3, 3).transpose(0, 2, 1))
+    assert np.array_equal(Cm, ref.transpose(0, 2, 1).reshape(100, 9))
