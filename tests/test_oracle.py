@@ -487,3 +487,21 @@ def test_integer_pages_exact():
     Cm, _ = oracle.page_mtimes(A, B, 3, 3, 3)
     ref = np.einsum("kij,kjl->kil", A.reshape(100, 3, 3).transpose(0, 2, 1), B.reshape(100, 3, 3).transpose(0, 2, 1))
     assert np.array_equal(Cm, ref.transpose(0, 2, 1).reshape(100, 9))
+
+
+def test_det_condition_hand_worked():
+    g = _golden("det_condition.txt")
+    A = _rows(g["matrix_rows"], 3, 3)
+    routed, cond = oracle.route_predicate(_colmajor(A)[None, :], 3, 0.0, 100.0)
+    assert cond[0] == float(g["kappa"][0]) and not routed[0]
+    routed, cond = oracle.route_predicate(_colmajor(A)[None, :], 3, 0.0, 78.0)
+    assert routed[0]
+    routed, _ = oracle.route_predicate(_colmajor(A)[None, :], 3, 1.5, 1e9)  # |det| = 1 < 1.5
+    assert routed[0]
+    # kappa >= 1 (triangle inequality), = 1 on diagonal pages, scale invariant
+    P = gen.page_batch(200, 3, sub=13)
+    _, c1 = oracle.route_predicate(P, 3, 0.0, 1e30)
+    _, c2 = oracle.route_predicate(P * 8.0, 3, 0.0, 1e30)
+    assert np.all(c1 >= 1.0 - 1e-12) and np.allclose(c1, c2, rtol=1e-13)
+    _, cd = oracle.route_predicate(_colmajor(np.diag([2.0, -3.0, 0.5]))[None, :], 3, 0.0, 1e30)
+    assert cd[0] == 1.0
