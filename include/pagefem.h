@@ -1,0 +1,205 @@
+/*
+ * pagefem.h -- C ABI of libpagefem.so: page-wise small dense linear algebra and P1 finite
+ * element assembly on AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow "On a vectorized basic linear algebra package for prototyping
+ * codes in MATLAB" (Moskovka, Rahman, Valdman, Vatne, arXiv 2404.16039):
+ *   section 2.2  page-wise multiplication, transpose, scalar multiplication, bilinear form
+ *                evaluation, page-wise determinant and inverse, transformation of normals
+ *   section 2.3  the library functions amtam, avtam, avtav, astam, amsm, amsv, smamt,
+ *                svamt, aminv, amt, amdet, avtamav
+ *   section 3.1  the coords3D / vectors3D structures
+ *   section 3.2  volumes and normals
+ *   section 3.5  derivative routine, P1 stiffness and mass matrices, sparse() assembly
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Memory: every array argument is DEVICE memory owned by the caller, unless stated.
+ *    Opaque handles (pf_csr, pf_plan, pf_server) are owned by the library and freed by
+ *    their *_destroy call.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls enqueue their kernels on it and return; outputs are valid once the stream has
+ *    been synchronised.  Calls that must read a size back to the host say so.
+ *  - Errors: every call returns a pf_status; pf_last_error() gives a message for the last
+ *    failure on the calling thread.  Numerical events (singular pages, FP64-routed pages,
+ *    out-of-range indices found on the device) are not errors: they are reported through
+ *    optional per-page flags and device counters, so no call synchronises for them.
+ *  - Pages: a batch of `count` matrices of `rows` x `cols` is described by pf_pages with
+ *    element strides.  The paper's (MATLAB) layout is column-major inside a page with pages
+ *    contiguous: s_row = 1, s_col = rows, s_page = rows*cols.  The structure-of-arrays
+ *    layout (component-major) is s_page = 1, s_row = count, s_col = rows*count.  s_page = 0
+ *    broadcasts one page to every index (the copy map of section 2.2, used by amsm, amsv,
+ *    smamt, svamt).  Orders are 1..4 in each dimension.
+ *  - Indices: element and face connectivity is 0-based int32, row-major (element e's
+ *    nodes at elems[e*nlb .. e*nlb+nlb-1]); coordinates are float64, row-major nn x dim.
+ *  - Device counters (nullable int64_t[4] in device memory, zeroed by the caller; calls
+ *    add to them): [0] pages/elements routed to FP64, [1] singular pages/elements,
+ *    [2] out-of-range indices met, [3] reserved.
+ *  - Per-page flags (nullable uint8 array, one per page/element): bit 0 singular
+ *    (determinant exactly zero in the final precision), bit 1 routed to FP64, bit 2 bad
+ *    index.
+ */
+#ifndef PAGEFEM_H
+#define PAGEFEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PF_OK = 0,
+    PF_EINVAL = 1,   /* invalid argument (null pointer, negative size, bad stride)      */
+    PF_EDTYPE = 2,   /* unsupported precision                                           */
+    PF_EORDER = 3,   /* unsupported matrix order or shape                               */
+    PF_ENOMEM = 4,   /* device or host allocation failed                                */
+    PF_EHIP = 5,     /* HIP runtime error (message has the HIP error string)            */
+    PF_EINDEX = 6,   /* out-of-range connectivity index found while building a structure */
+    PF_ELIMIT = 7,   /* a documented size limit was exceeded                             */
+    PF_EBUDGET = 8,  /* a request can never fit the configured memory budget             */
+    PF_ESTATE = 9    /* handle used in the wrong state                                   */
+} pf_status;
+
+typedef enum { PF_F32 = 0, PF_F64 = 1 } pf_dtype;
+
+typedef struct pf_pages {
+    int32_t rows, cols;            /* page shape, 1..4 each                             */
+    int64_t count;                 /* number of pages (>= 0)                            */
+    int64_t s_row, s_col, s_page;  /* strides in elements; s_page == 0 broadcasts       */
+} pf_pages;
+
+/* FP64 routing of the FP32 path: a page/element is recomputed in FP64 when its FP32
+ * determinant (compensated) satisfies |det| < tau_abs, or its det-condition
+ * sum_j |a_0j C_0j| / |det| (expansion along the first row) exceeds tau_cond, or det is
+ * not finite.  enable = 0 turns routing off.  A NULL pf_fallback* means
+ * {tau_abs = 0, tau_cond = 1e6, enable = 1}.  Ignored on the FP64 path.               */
+typedef struct pf_fallback {
+    double tau_abs;
+    double tau_cond;
+    int32_t enable;
+} pf_fallback;
+
+const char* pf_last_error(void);
+int pf_version(void);
+
+/* ------------------------------------------------------------------------------------
+ * Page operations (section 2.2, page-wise maps; section 2.3, library functions)
+ * ---------------------------------------------------------------------------------- */
+
+/* Page-wise determinant det_W (section 2.2; amdet).  A: n x n pages, n = 1..4.
+ * det: `count` values of `dtype`, contiguous.  flags, d_counters nullable. */
+pf_status pf_page_det(pf_dtype dtype, const pf_pages* A, const void* a, void* det,
+                      const pf_fallback* fb, uint8_t* flags, int64_t* d_counters, void* stream);
+
+/* Page-wise inverse on det_W^{-1}(W*) (section 2.2; aminv, which also returns the
+ * determinants).  X: output pages (n x n).  det (nullable): determinants as in
+ * pf_page_det.  A page with zero determinant gets the IEEE result of adj(A)/0 (inf/nan)
+ * and flag bit 0; it is counted in d_counters[1]. */
+pf_status pf_page_inv(pf_dtype dtype, const pf_pages* A, const void* a, const pf_pages* X, void* x,
+                      void* det, const pf_fallback* fb, uint8_t* flags, int64_t* d_counters,
+                      void* stream);
+
+/* Page-wise transpose (section 2.2; amt).  A: r x c pages, T: c x r pages. Bit-exact. */
+pf_status pf_page_transpose(pf_dtype dtype, const pf_pages* A, const void* a, const pf_pages* T,
+                            void* t, void* stream);
+
+/* Page-wise product C_k = op(A_k) op(B_k) (section 2.2, page-wise matrix multiplication;
+ * section 2.3 amtam, avtam, avtav, amsm, amsv, smamt, svamt are instances).  op(X) = X or
+ * X^T per the trans flag.  op(A): m x k, op(B): k x n, C: m x n, all dims 1..4; a
+ * broadcast operand (s_page = 0) is one matrix used for every page.  C.count pages are
+ * computed; non-broadcast A/B must have count equal to C.count. */
+pf_status pf_page_mtimes(pf_dtype dtype, const pf_pages* A, const void* a, int transA,
+                         const pf_pages* B, const void* b, int transB, const pf_pages* C, void* c,
+                         void* stream);
+
+/* Page-wise matrix-vector product y_k = op(A_k) x_k (section 2.3 amsv / avtam pattern);
+ * x, y are vectors given as n x 1 pages.  Same rules as pf_page_mtimes. */
+pf_status pf_page_mv(pf_dtype dtype, const pf_pages* A, const void* a, int transA,
+                     const pf_pages* X, const void* x, const pf_pages* Y, void* y, void* stream);
+
+/* Page-wise scalar multiplication C_k = s_k A_k (section 2.2, Id (x) pi; astam).
+ * s: count scalars, contiguous, or one scalar broadcast when s_stride = 0. */
+pf_status pf_page_scale(pf_dtype dtype, const void* s, int64_t s_stride, const pf_pages* A,
+                        const void* a, const pf_pages* C, void* c, void* stream);
+
+/* Page-wise bilinear form q_k = u_k^T A_k v_k (section 2.2, page-wise bilinear form
+ * evaluation; avtamav).  u, v: n x 1 pages; q: count values, contiguous. */
+pf_status pf_page_bilinear(pf_dtype dtype, const pf_pages* U, const void* u, const pf_pages* A,
+                           const void* a, const pf_pages* V, const void* v, void* q, void* stream);
+
+/* ------------------------------------------------------------------------------------
+ * P1 elements (section 3.5, derivative routine and P1 stiffness / mass; section 3.2,
+ * volumes and normals).  dim = 2 (triangles, nlb = 3) or 3 (tetrahedra, nlb = 4).
+ * prec = PF_F64: FP64 arithmetic and outputs.  prec = PF_F32: FP32 arithmetic (Jacobian
+ * edges subtracted in FP64, then rounded), compensated determinant, FP64 recomputation of
+ * routed elements, FP32 outputs.  The Jacobian uses the first node as origin,
+ * J = [p_2 - p_1, ..., p_{d+1} - p_1] (the transpose of the routine's tjac).
+ * ---------------------------------------------------------------------------------- */
+
+/* Per-element geometry.  Outputs (each nullable, type = prec):
+ *   det[ne]            signed det J
+ *   vol[ne]            |det J| / dim!                                 (section 3.2)
+ *   grads[ne][dim*nlb] dphi = J^{-T} D, column-major dim x nlb; column j = grad phi_j
+ *   normals[ne][dim*nlb] normals3D = vectors3D^{-T} normalsRef = -grads  (section 3.2)
+ *   facet[ne][nlb]     measure of the facet opposite node j = dim |T| |grad phi_j|    */
+pf_status pf_elem_geometry(int dim, pf_dtype prec, int64_t nn, const double* coords, int64_t ne,
+                           const int32_t* elems, void* det, void* vol, void* grads, void* normals,
+                           void* facet, const pf_fallback* fb, uint8_t* flags,
+                           int64_t* d_counters, void* stream);
+
+/* Element stiffness and mass matrices (the listings' K3D and M3D outputs), column-major
+ * nlb x nlb per element: K_e = cK_e |T| dphi^T dphi, M_e = cM_e |T| (1 + delta_ab) /
+ * ((d+1)(d+2)) (the exact P1 mass for an element-wise constant coefficient).  cK, cM:
+ * per-element coefficients of type prec, nullable (= 1).  K3D, M3D nullable. */
+pf_status pf_elem_stiffness_mass(int dim, pf_dtype prec, int64_t nn, const double* coords,
+                                 int64_t ne, const int32_t* elems, const void* cK, const void* cM,
+                                 void* K3D, void* M3D, const pf_fallback* fb, uint8_t* flags,
+                                 int64_t* d_counters, void* stream);
+
+/* Boundary facets (section 3.2 normals; facesB / areasB of the surface integral).
+ * dim = 3: faces[nf][3] triangles (a,b,c), n = (b-a) x (c-a), measure = |n| / 2.
+ * dim = 2: faces[nf][2] edges (a,b), n = (b_y - a_y, a_x - b_x), measure = |n|.
+ * unit[nf][dim] = n / |n| (nullable), measure[nf] (nullable), type prec. */
+pf_status pf_boundary_normals(int dim, pf_dtype prec, int64_t nn, const double* coords, int64_t nf,
+                              const int32_t* faces, void* unit, void* measure, void* stream);
+
+/* ------------------------------------------------------------------------------------
+ * Assembly: sparse(X3D(:), Y3D(:), K3D(:), nn, nn) of the P1 listings (section 3.5).
+ * The CSR pattern holds every pair of nodes that share an element (entries that sum to
+ * zero are kept), columns ascending in each row.  K and M are symmetric, so the CSR
+ * arrays equal the compressed-column arrays of the global matrices.
+ * ---------------------------------------------------------------------------------- */
+typedef struct pf_csr pf_csr;
+
+/* Create an empty structure handle (host call, no device work). */
+pf_status pf_csr_create(pf_csr** out);
+
+/* Build (or rebuild) the CSR structure of a P1 mesh: node-to-element adjacency and the
+ * row pattern.  Device buffers are kept in the handle and grown when needed.  This call
+ * synchronises `stream` once (it reads nnz and the error word back to the host).
+ * Limits: 4*ne < 2^31, nnz < 2^31, at most 64 elements per node and 64 nonzeros per row
+ * (PF_ELIMIT otherwise).  Out-of-range node ids give PF_EINDEX. */
+pf_status pf_csr_symbolic(pf_csr* csr, int dim, int64_t nn, int64_t ne, const int32_t* elems,
+                          void* stream);
+
+/* Read the structure: sizes on the host, device pointers owned by the handle. */
+pf_status pf_csr_info(const pf_csr* csr, int64_t* nn, int64_t* nnz, const int32_t** row_ptr,
+                      const int32_t** col_idx);
+
+/* Numeric assembly of the global K (valsK[nnz]) and M (valsM[nnz], nullable) on the
+ * structure built from the same `elems`.  Each value is the sum of its element
+ * contributions in ascending element order (deterministic: the same inputs give the same
+ * bits).  prec as for the element calls; cK, cM nullable (= 1). */
+pf_status pf_assemble(const pf_csr* csr, pf_dtype prec, const double* coords, const int32_t* elems,
+                      const void* cK, const void* cM, void* valsK, void* valsM,
+                      const pf_fallback* fb, int64_t* d_counters, void* stream);
+
+void pf_csr_destroy(pf_csr* csr);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAGEFEM_H */

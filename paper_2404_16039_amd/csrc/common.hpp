@@ -1,0 +1,165 @@
+// common.hpp -- shared host and device helpers of libpagefem (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/pagefem.h"
+
+namespace pf {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------------------------
+// host: error reporting
+// ------------------------------------------------------------------------------------
+void set_error(const std::string& msg);
+pf_status fail(pf_status st, const std::string& msg);
+
+#define PF_HIP_TRY(expr)                                                                  \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return ::pf::fail(PF_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+inline pf_status launch_check(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(PF_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    return PF_OK;
+}
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------------------------------
+// device: error-free transformations and compensated small determinants
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// a*d - b*c with Kahan's FMA scheme: the rounding error of b*c is recovered exactly by an
+// FMA and added back, so the result is within 2 ulp of the exact value (Jeannerod,
+// Louvet, Muller, Math. Comp. 2013), whatever the cancellation.
+template <typename T>
+__device__ __forceinline__ T det2(T a, T b, T c, T d) {
+    T w = b * c;
+    T e = fmaT(-b, c, w);   // w - b*c, exact
+    T f = fmaT(a, d, -w);   // a*d - w, one rounding
+    return f + e;
+}
+
+// Knuth's TwoSum: s + err = a + b exactly
+template <typename T>
+__device__ __forceinline__ T two_sum(T a, T b, T& err) {
+    T s = a + b;
+    T bb = s - a;
+    err = (a - (s - bb)) + (b - bb);
+    return s;
+}
+
+// Compensated dot product of length N (Ogita, Rump, Oishi 2005, Dot2): as accurate as if
+// computed in twice the working precision and rounded once.  Also returns sum |x_i y_i|.
+template <typename T, int N>
+__device__ __forceinline__ T dot_comp(const T* x, const T* y, T& abs_sum) {
+    T p = x[0] * y[0];
+    T s = fmaT(x[0], y[0], -p);
+    abs_sum = fabs(p);
+#pragma unroll
+    for (int i = 1; i < N; ++i) {
+        T h = x[i] * y[i];
+        T q = fmaT(x[i], y[i], -h);
+        T err;
+        p = two_sum(p, h, err);
+        s += q + err;
+        abs_sum += fabs(h);
+    }
+    return p + s;
+}
+
+// double-word number hi + lo (unevaluated sum), |lo| <= ulp(hi)/2 after normalisation
+template <typename T>
+struct DW {
+    T hi, lo;
+};
+
+template <typename T>
+__device__ __forceinline__ DW<T> two_prod(T a, T b) {
+    const T p = a * b;
+    return DW<T>{p, fmaT(a, b, -p)};
+}
+
+// a*d - b*c as a double-word value; the error is O(u^2 (|ad| + |bc|)), so the value is
+// effectively exact for every later rounding to working precision
+template <typename T>
+__device__ __forceinline__ DW<T> dw_det2(T a, T b, T c, T d) {
+    const DW<T> p = two_prod(a, d), q = two_prod(b, c);
+    T e;
+    const T s = two_sum(p.hi, -q.hi, e);
+    const T lo = e + (p.lo - q.lo);
+    T e2;
+    const T hi = two_sum(s, lo, e2);
+    return DW<T>{hi, e2};
+}
+
+// sum_i x_i * y_i with double-word y_i, compensated (Dot2-style): the result carries an
+// error of about u |result| + O(u^2) sum |x_i y_i|.  abs_sum = sum |x_i y_i.hi|.
+template <typename T, int N>
+__device__ __forceinline__ DW<T> dot_dw(const T* x, const DW<T>* y, T& abs_sum) {
+    DW<T> p = two_prod(x[0], y[0].hi);
+    T s = p.hi;
+    T err = fmaT(x[0], y[0].lo, p.lo);
+    abs_sum = fabs(p.hi);
+#pragma unroll
+    for (int i = 1; i < N; ++i) {
+        p = two_prod(x[i], y[i].hi);
+        T e;
+        s = two_sum(s, p.hi, e);
+        err += e + fmaT(x[i], y[i].lo, p.lo);
+        abs_sum += fabs(p.hi);
+    }
+    T e2;
+    const T hi = two_sum(s, err, e2);
+    return DW<T>{hi, e2};
+}
+
+template <typename T>
+__device__ __forceinline__ bool finiteT(T v) {
+    return __builtin_isfinite(v);
+}
+
+// counters layout (see pagefem.h): [0] routed, [1] singular, [2] bad index
+__device__ __forceinline__ void count_add(int64_t* d_counters, int which, int64_t v) {
+    if (d_counters && v) atomicAdd(reinterpret_cast<unsigned long long*>(d_counters + which),
+                                   static_cast<unsigned long long>(v));
+}
+
+// wave-level sum of an integer flag, one atomic per wave
+__device__ __forceinline__ void count_wave(int64_t* d_counters, int which, bool pred) {
+    if (!d_counters) return;
+    unsigned long long m = __ballot(pred);
+    if (m && (__lane_id() == __ffsll(static_cast<long long>(m)) - 1))
+        atomicAdd(reinterpret_cast<unsigned long long*>(d_counters + which),
+                  static_cast<unsigned long long>(__popcll(m)));
+}
+
+constexpr uint8_t FLAG_SINGULAR = 1;
+constexpr uint8_t FLAG_ROUTED = 2;
+constexpr uint8_t FLAG_BADINDEX = 4;
+
+struct Fallback {
+    double tau_abs;
+    double tau_cond;
+    int enable;
+};
+
+inline Fallback make_fallback(const pf_fallback* fb) {
+    if (!fb) return Fallback{0.0, 1e6, 1};
+    return Fallback{fb->tau_abs, fb->tau_cond, fb->enable};
+}
+
+}  // namespace pf

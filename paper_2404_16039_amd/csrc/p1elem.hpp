@@ -1,0 +1,117 @@
+// p1elem.hpp -- per-element P1 geometry in registers (section 3.5 derivative routine with
+// one integration point; section 3.2 volumes and normals).
+//
+// With edges e_k = p_{k+1} - p_1 (the columns of J), the inverse transpose of J has the
+// cofactor vectors as columns: c_1 = e_2 x e_3, c_2 = e_3 x e_1, c_3 = e_1 x e_2 (3-D), or
+// the rotated edges (2-D), divided by det J = e_1 . c_1.  The barycentric gradients
+// (the routine's dphi = tjac^{-1} dshape with the P1 reference derivatives) are therefore
+// grad phi_j = c_j / det for j >= 1 and grad phi_0 = -(c_1 + ... + c_d) / det, and the P1
+// stiffness entry |T| grad phi_a . grad phi_b equals (c_a . c_b) / (d! |det|).  Every
+// cofactor component is a 2x2 determinant evaluated with Kahan's FMA scheme (c_1 as an
+// exact double-word value), and det is a compensated dot product with c_1, so the FP32
+// path loses no accuracy to cancellation.
+#pragma once
+
+#include "smallmat.hpp"
+
+namespace pf {
+
+template <int DIM, typename C>
+struct P1Geom {
+    C c[DIM + 1][DIM];  // c[j] = det * grad phi_j
+    C det;              // signed det J (first node origin)
+    C absterms;         // sum_j |e_1j c_1j|, numerator of the det-condition
+};
+
+template <int DIM, typename C>
+__device__ __forceinline__ void p1_geom(const double (&e)[DIM][DIM], P1Geom<DIM, C>& g) {
+    C u[DIM][DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) u[k][i] = static_cast<C>(e[k][i]);
+    if constexpr (DIM == 3) {
+        // c_1 = e_2 x e_3 as double-word components: det = e_1 . c_1 within about one ulp
+        DW<C> c1[3];
+        c1[0] = dw_det2(u[1][1], u[1][2], u[2][1], u[2][2]);
+        c1[1] = dw_det2(u[1][2], u[1][0], u[2][2], u[2][0]);
+        c1[2] = dw_det2(u[1][0], u[1][1], u[2][0], u[2][1]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) g.c[1][i] = c1[i].hi + c1[i].lo;
+#pragma unroll
+        for (int j = 2; j <= 3; ++j) {
+            const C* x = u[j % 3];  // c_2 = e_3 x e_1, c_3 = e_1 x e_2 (Kahan, within 2 ulp)
+            const C* y = u[(j + 1) % 3];
+            g.c[j][0] = det2(x[1], x[2], y[1], y[2]);
+            g.c[j][1] = det2(x[2], x[0], y[2], y[0]);
+            g.c[j][2] = det2(x[0], x[1], y[0], y[1]);
+        }
+        const DW<C> d = dot_dw<C, 3>(u[0], c1, g.absterms);
+        g.det = d.hi + d.lo;
+    } else {
+        g.c[1][0] = u[1][1];
+        g.c[1][1] = -u[1][0];
+        g.c[2][0] = -u[0][1];
+        g.c[2][1] = u[0][0];
+        const DW<C> d = dw_det2(u[0][0], u[0][1], u[1][0], u[1][1]);
+        g.det = d.hi + d.lo;
+        g.absterms = fabs(u[0][0] * u[1][1]) + fabs(u[0][1] * u[1][0]);
+    }
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+        C s = g.c[1][i];
+#pragma unroll
+        for (int j = 2; j <= DIM; ++j) s += g.c[j][i];
+        g.c[0][i] = -s;
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ constexpr double fact_dim() {
+    return DIM == 2 ? 2.0 : 6.0;
+}
+
+// gather the element's node coordinates and form the FP64 edge vectors; returns false on
+// an out-of-range node id
+template <int DIM>
+__device__ __forceinline__ bool p1_edges(const double* __restrict__ coords, int64_t nn, const int (&nd)[DIM + 1],
+                                         double (&e)[DIM][DIM]) {
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j <= DIM; ++j) ok = ok && (nd[j] >= 0) && (nd[j] < nn);
+    if (!ok) return false;
+    double p0[DIM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) p0[i] = coords[static_cast<int64_t>(nd[0]) * DIM + i];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) e[k][i] = coords[static_cast<int64_t>(nd[k + 1]) * DIM + i] - p0[i];
+    return true;
+}
+
+template <int DIM>
+__device__ __forceinline__ void load_nodes(const int32_t* __restrict__ elems, int64_t e, int (&nd)[DIM + 1]) {
+    if constexpr (DIM == 3) {
+        if ((reinterpret_cast<uintptr_t>(elems) & 15) == 0) {
+            const int4 v = *reinterpret_cast<const int4*>(elems + e * 4);
+            nd[0] = v.x;
+            nd[1] = v.y;
+            nd[2] = v.z;
+            nd[3] = v.w;
+        } else {
+            const int32_t* p = elems + e * 4;
+            nd[0] = p[0];
+            nd[1] = p[1];
+            nd[2] = p[2];
+            nd[3] = p[3];
+        }
+    } else {
+        const int32_t* p = elems + e * 3;
+        nd[0] = p[0];
+        nd[1] = p[1];
+        nd[2] = p[2];
+    }
+}
+
+}  // namespace pf

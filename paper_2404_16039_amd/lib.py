@@ -1,0 +1,271 @@
+"""Thin Python binding of libpagefem.so (ctypes).
+
+Argument marshalling only: every function forwards torch tensors' device pointers, sizes
+and the current HIP stream to the C entry point of the same name (without the ``pf_``
+prefix) declared in ``include/pagefem.h``.  PyTorch supplies device memory and streams;
+all computation happens in the library's HIP kernels.  There is no CPU fallback: if the
+library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpagefem.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2404_16039_amd.build`")
+
+_lib = C.CDLL(LIB_PATH)
+
+F32, F64 = 0, 1
+STATUS = {0: "PF_OK", 1: "PF_EINVAL", 2: "PF_EDTYPE", 3: "PF_EORDER", 4: "PF_ENOMEM", 5: "PF_EHIP",
+          6: "PF_EINDEX", 7: "PF_ELIMIT", 8: "PF_EBUDGET", 9: "PF_ESTATE"}
+
+
+class PagefemError(RuntimeError):
+    def __init__(self, name, code, msg):
+        super().__init__(f"{name}: {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Pages(C.Structure):
+    """pf_pages: page shape, count and element strides (s_page = 0 broadcasts)."""
+    _fields_ = [("rows", C.c_int32), ("cols", C.c_int32), ("count", C.c_int64),
+                ("s_row", C.c_int64), ("s_col", C.c_int64), ("s_page", C.c_int64)]
+
+
+class Fallback(C.Structure):
+    """pf_fallback: FP64 routing thresholds of the FP32 path."""
+    _fields_ = [("tau_abs", C.c_double), ("tau_cond", C.c_double), ("enable", C.c_int32)]
+
+
+def pages(count, rows, cols):
+    """Descriptor of the paper's layout: column-major pages stored back to back."""
+    return Pages(rows, cols, count, 1, rows, rows * cols)
+
+
+def pages_soa(count, rows, cols):
+    """Descriptor of the structure-of-arrays layout: component (r, c) of all pages contiguous."""
+    return Pages(rows, cols, count, count, rows * count, 1)
+
+
+def pages_bcast(rows, cols, count=1):
+    """One column-major page broadcast to every index."""
+    return Pages(rows, cols, count, 1, rows, 0)
+
+
+def fallback(tau_abs=0.0, tau_cond=1e6, enable=True):
+    return Fallback(float(tau_abs), float(tau_cond), 1 if enable else 0)
+
+
+P = C.c_void_p
+I32 = C.c_int
+I64 = C.c_int64
+PP = C.POINTER(Pages)
+FP = C.POINTER(Fallback)
+
+_sig = {
+    "pf_last_error": ([], C.c_char_p),
+    "pf_version": ([], C.c_int),
+    "pf_page_det": ([I32, PP, P, P, FP, P, P, P], C.c_int),
+    "pf_page_inv": ([I32, PP, P, PP, P, P, FP, P, P, P], C.c_int),
+    "pf_page_transpose": ([I32, PP, P, PP, P, P], C.c_int),
+    "pf_page_mtimes": ([I32, PP, P, I32, PP, P, I32, PP, P, P], C.c_int),
+    "pf_page_mv": ([I32, PP, P, I32, PP, P, PP, P, P], C.c_int),
+    "pf_page_scale": ([I32, P, I64, PP, P, PP, P, P], C.c_int),
+    "pf_page_bilinear": ([I32, PP, P, PP, P, PP, P, P, P], C.c_int),
+    "pf_elem_geometry": ([I32, I32, I64, P, I64, P, P, P, P, P, P, FP, P, P, P], C.c_int),
+    "pf_elem_stiffness_mass": ([I32, I32, I64, P, I64, P, P, P, P, P, FP, P, P, P], C.c_int),
+    "pf_boundary_normals": ([I32, I32, I64, P, I64, P, P, P, P], C.c_int),
+    "pf_csr_create": ([C.POINTER(P)], C.c_int),
+    "pf_csr_symbolic": ([P, I32, I64, I64, P, P], C.c_int),
+    "pf_csr_info": ([P, C.POINTER(I64), C.POINTER(I64), C.POINTER(P), C.POINTER(P)], C.c_int),
+    "pf_assemble": ([P, I32, P, P, P, P, P, P, FP, P, P], C.c_int),
+    "pf_csr_destroy": ([P], None),
+}
+for _name, (_args, _res) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+def exported_symbols():
+    return sorted(_sig)
+
+
+def last_error() -> str:
+    return _lib.pf_last_error().decode()
+
+
+def version() -> int:
+    return _lib.pf_version()
+
+
+def _chk(rc, name):
+    if rc != 0:
+        raise PagefemError(name, rc, last_error())
+
+
+def _p(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return P(t)
+    if not t.is_cuda:
+        raise ValueError("pagefem tensors must live in device memory")
+    return P(t.data_ptr())
+
+
+def _s(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return P(s.cuda_stream)
+
+
+def _dt(t):
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise ValueError(f"unsupported dtype {t.dtype}")
+
+
+def _ref(x, typ):
+    return None if x is None else C.byref(x)
+
+
+# ----------------------------------------------------------------------------- page ops
+def page_det(A: Pages, a, det, fb=None, flags=None, counters=None, stream=None):
+    _chk(_lib.pf_page_det(_dt(a), C.byref(A), _p(a), _p(det), _ref(fb, Fallback), _p(flags), _p(counters),
+                          _s(stream)), "pf_page_det")
+
+
+def page_inv(A: Pages, a, X: Pages, x, det=None, fb=None, flags=None, counters=None, stream=None):
+    _chk(_lib.pf_page_inv(_dt(a), C.byref(A), _p(a), C.byref(X), _p(x), _p(det), _ref(fb, Fallback), _p(flags),
+                          _p(counters), _s(stream)), "pf_page_inv")
+
+
+def page_transpose(A: Pages, a, T: Pages, t, stream=None):
+    _chk(_lib.pf_page_transpose(_dt(a), C.byref(A), _p(a), C.byref(T), _p(t), _s(stream)), "pf_page_transpose")
+
+
+def page_mtimes(A: Pages, a, transA, B: Pages, b, transB, Cd: Pages, c, stream=None):
+    _chk(_lib.pf_page_mtimes(_dt(a), C.byref(A), _p(a), int(transA), C.byref(B), _p(b), int(transB), C.byref(Cd),
+                             _p(c), _s(stream)), "pf_page_mtimes")
+
+
+def page_mv(A: Pages, a, transA, X: Pages, x, Y: Pages, y, stream=None):
+    _chk(_lib.pf_page_mv(_dt(a), C.byref(A), _p(a), int(transA), C.byref(X), _p(x), C.byref(Y), _p(y), _s(stream)),
+         "pf_page_mv")
+
+
+def page_scale(s, s_stride, A: Pages, a, Cd: Pages, c, stream=None):
+    _chk(_lib.pf_page_scale(_dt(a), _p(s), int(s_stride), C.byref(A), _p(a), C.byref(Cd), _p(c), _s(stream)),
+         "pf_page_scale")
+
+
+def page_bilinear(U: Pages, u, A: Pages, a, V: Pages, v, q, stream=None):
+    _chk(_lib.pf_page_bilinear(_dt(a), C.byref(U), _p(u), C.byref(A), _p(a), C.byref(V), _p(v), _p(q), _s(stream)),
+         "pf_page_bilinear")
+
+
+# ----------------------------------------------------------------------------- elements
+def _mesh(coords, elems):
+    if coords.dtype != torch.float64 or elems.dtype != torch.int32:
+        raise ValueError("coords must be float64 and elems int32")
+    if not (coords.is_contiguous() and elems.is_contiguous()):
+        raise ValueError("coords and elems must be contiguous")
+    return coords.shape[0], coords.shape[1], elems.shape[0]
+
+
+def elem_geometry(prec, coords, elems, det=None, vol=None, grads=None, normals=None, facet=None, fb=None,
+                  flags=None, counters=None, stream=None):
+    nn, dim, ne = _mesh(coords, elems)
+    _chk(_lib.pf_elem_geometry(dim, prec, nn, _p(coords), ne, _p(elems), _p(det), _p(vol), _p(grads), _p(normals),
+                               _p(facet), _ref(fb, Fallback), _p(flags), _p(counters), _s(stream)),
+         "pf_elem_geometry")
+
+
+def elem_stiffness_mass(prec, coords, elems, cK=None, cM=None, K3D=None, M3D=None, fb=None, flags=None,
+                        counters=None, stream=None):
+    nn, dim, ne = _mesh(coords, elems)
+    _chk(_lib.pf_elem_stiffness_mass(dim, prec, nn, _p(coords), ne, _p(elems), _p(cK), _p(cM), _p(K3D), _p(M3D),
+                                     _ref(fb, Fallback), _p(flags), _p(counters), _s(stream)),
+         "pf_elem_stiffness_mass")
+
+
+def boundary_normals(prec, coords, faces, unit=None, measure=None, stream=None):
+    nn, dim = coords.shape
+    if coords.dtype != torch.float64 or faces.dtype != torch.int32:
+        raise ValueError("coords must be float64 and faces int32")
+    _chk(_lib.pf_boundary_normals(dim, prec, nn, _p(coords), faces.shape[0], _p(faces), _p(unit), _p(measure),
+                                  _s(stream)), "pf_boundary_normals")
+
+
+# ----------------------------------------------------------------------------- assembly
+class Csr:
+    """Owner of a pf_csr handle (CSR structure of one P1 mesh)."""
+
+    def __init__(self):
+        h = P()
+        _chk(_lib.pf_csr_create(C.byref(h)), "pf_csr_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def symbolic(self, dim, nn, elems, stream=None):
+        if elems.dtype != torch.int32 or not elems.is_contiguous():
+            raise ValueError("elems must be contiguous int32")
+        _chk(_lib.pf_csr_symbolic(self._h, int(dim), int(nn), elems.shape[0], _p(elems), _s(stream)),
+             "pf_csr_symbolic")
+        return self
+
+    def info(self):
+        nn, nnz, rp, ci = I64(), I64(), P(), P()
+        _chk(_lib.pf_csr_info(self._h, C.byref(nn), C.byref(nnz), C.byref(rp), C.byref(ci)), "pf_csr_info")
+        return nn.value, nnz.value, rp.value, ci.value
+
+    def structure(self, stream=None):
+        """Copies of (row_ptr, col_idx) as int32 device tensors."""
+        nn, nnz, rp, ci = self.info()
+        row_ptr = torch.empty(nn + 1, dtype=torch.int32, device="cuda")
+        col_idx = torch.empty(max(nnz, 1), dtype=torch.int32, device="cuda")[:nnz]
+        _memcpy_d2d(row_ptr.data_ptr(), rp, 4 * (nn + 1), stream)
+        if nnz:
+            _memcpy_d2d(col_idx.data_ptr(), ci, 4 * nnz, stream)
+        return row_ptr, col_idx
+
+    def assemble(self, prec, coords, elems, valsK, valsM=None, cK=None, cM=None, fb=None, counters=None,
+                 stream=None):
+        _chk(_lib.pf_assemble(self._h, prec, _p(coords), _p(elems), _p(cK), _p(cM), _p(valsK), _p(valsM),
+                              _ref(fb, Fallback), _p(counters), _s(stream)), "pf_assemble")
+
+    def close(self):
+        if self._h:
+            _lib.pf_csr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_hip = None
+
+
+def _memcpy_d2d(dst, src, nbytes, stream=None):
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpyAsync.argtypes = [P, P, C.c_size_t, C.c_int, P]
+        _hip.hipMemcpyAsync.restype = C.c_int
+    rc = _hip.hipMemcpyAsync(P(dst), P(src), nbytes, 3, _s(stream))  # hipMemcpyDeviceToDevice
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpyAsync failed ({rc})")

@@ -1,0 +1,222 @@
+"""Parity of the CSR assembly (the sparse() call of the section 3.5 listings) against the
+oracle: structure bit-exact, values within tolerance of the sum of |contributions|, at the
+small configurations in full and at the 128^3 configuration on sampled rows."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import TOL, counters, cube, dev, host, prec_of, say, square, within
+from paper_2404_16039_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2404_16039_amd import lib as L
+    return L
+
+
+def _assemble(L, coords, elems, dtype, cK=None, cM=None, fb=None, csr=None):
+    dim = coords.shape[1]
+    nn = coords.shape[0]
+    tc, te = dev(coords), dev(elems)
+    csr = csr or L.Csr()
+    csr.symbolic(dim, nn, te)
+    _, nnz, _, _ = csr.info()
+    vk = torch.empty(nnz, dtype=dtype, device="cuda")
+    vm = torch.empty(nnz, dtype=dtype, device="cuda")
+    ctr = counters()
+    tK = None if cK is None else dev(cK, dtype)
+    tM = None if cM is None else dev(cM, dtype)
+    csr.assemble(prec_of(dtype), tc, te, vk, vm, cK=tK, cM=tM, fb=fb, counters=ctr)
+    rp, ci = csr.structure()
+    return {"row_ptr": host(rp).astype(np.int64), "col_idx": host(ci), "valK": host(vk), "valM": host(vm),
+            "ctr": host(ctr), "csr": csr, "nnz": nnz, "tK": vk, "tM": vm}
+
+
+def _full_oracle(coords, elems, cK=None, cM=None):
+    el = oracle.p1_elements(coords, elems)
+    Ke, Me, Ka = el["Ke"], el["Me"], el["Kabs"]
+    if cK is not None:
+        Ke = Ke * cK[:, None]
+        Ka = Ka * np.abs(cK[:, None])
+    if cM is not None:
+        Me = Me * cM[:, None]
+    return oracle.assemble(elems, coords.shape[0], Ke, Me, Ka)
+
+
+def _compare_full(got, ref, dtype):
+    assert got["nnz"] == ref["nnz"]
+    assert np.array_equal(got["row_ptr"], ref["row_ptr"])
+    assert np.array_equal(got["col_idx"], ref["col_idx"])
+    within(got["valK"], ref["valK"], ref["scaleK"], TOL[dtype], "K values")
+    within(got["valM"], ref["valM"], ref["scaleM"], TOL[dtype], "M values")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_cfg1_square_32(lib, dtype):
+    """2048 triangles, 1089 nodes: the 1089 x 1089 CSR K and M, every entry."""
+    say("assemble square 32", dtype)
+    coords, elems, _ = square(32)
+    got = _assemble(lib, coords, elems, dtype)
+    assert got["nnz"] == gen.square_counts(32)["nnz"] == 7361
+    _compare_full(got, _full_oracle(coords, elems), dtype)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("n", [1, 2, 7])
+def test_cube_small_full(lib, dtype, n):
+    say("assemble cube", n, dtype)
+    coords, elems, _ = cube(n)
+    g = np.random.default_rng(n)
+    cK = g.uniform(0.5, 2.0, len(elems))
+    cM = g.uniform(0.5, 2.0, len(elems))
+    if dtype == torch.float32:
+        cK = cK.astype(np.float32).astype(np.float64)
+        cM = cM.astype(np.float32).astype(np.float64)
+    got = _assemble(lib, coords, elems, dtype, cK, cM)
+    assert got["nnz"] == gen.kuhn_counts(n)["nnz"]
+    _compare_full(got, _full_oracle(coords, elems, cK, cM), dtype)
+
+
+def test_deterministic_and_handle_reuse(lib):
+    say("determinism")
+    coords, elems, _ = cube(9)
+    a = _assemble(lib, coords, elems, torch.float32)
+    b = _assemble(lib, coords, elems, torch.float32, csr=a["csr"])  # rebuilt in the same handle
+    assert torch.equal(a["tK"], b["tK"]) and torch.equal(a["tM"], b["tM"])
+    # a smaller mesh in the same (larger) handle, then the larger one again
+    c2, e2, _ = cube(3)
+    small = _assemble(lib, c2, e2, torch.float64, csr=a["csr"])
+    _compare_full(small, _full_oracle(c2, e2), torch.float64)
+    c = _assemble(lib, coords, elems, torch.float32, csr=a["csr"])
+    assert torch.equal(a["tK"], c["tK"])
+
+
+def test_node_permutation_invariance(lib):
+    """Random node numbering gives the same matrices, up to the permutation, bit for bit."""
+    say("permutation")
+    coords, elems, faces = cube(6)
+    c2, e2, _, perm = gen.permute_nodes(coords, elems, faces)
+    a = _assemble(lib, coords, elems, torch.float32)
+    b = _assemble(lib, c2, e2, torch.float32)
+    nn = coords.shape[0]
+    for i in range(0, nn, 7):
+        sa = slice(a["row_ptr"][i], a["row_ptr"][i + 1])
+        pi = perm[i]
+        sb = slice(b["row_ptr"][pi], b["row_ptr"][pi + 1])
+        cols_a = perm[a["col_idx"][sa]]
+        order = np.argsort(cols_a)
+        assert np.array_equal(cols_a[order], b["col_idx"][sb])
+        assert np.array_equal(a["valK"][sa][order], b["valK"][sb])
+        assert np.array_equal(a["valM"][sa][order], b["valM"][sb])
+
+
+def test_edge_cases(lib):
+    say("edge cases")
+    # one element
+    coords = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float)
+    elems = np.array([[0, 1, 2, 3]], np.int32)
+    got = _assemble(lib, coords, elems, torch.float64)
+    _compare_full(got, _full_oracle(coords, elems), torch.float64)
+    # isolated nodes and no elements
+    csr = lib.Csr()
+    csr.symbolic(3, 10, torch.zeros((0, 4), dtype=torch.int32, device="cuda"))
+    assert csr.info()[1] == 0
+    rp, _ = csr.structure()
+    assert not host(rp).any()
+    # out-of-range node id
+    bad = dev(np.array([[0, 1, 2, 99]], np.int32))
+    with pytest.raises(lib.PagefemError) as ei:
+        lib.Csr().symbolic(3, 4, bad)
+    assert ei.value.code == 6
+    # a node in more than 64 elements (a fan of 70 triangles) is a documented limit
+    k = 70
+    ang = np.linspace(0, 2 * np.pi, k, endpoint=False)
+    fan_c = np.concatenate([[[0.0, 0.0]], np.stack([np.cos(ang), np.sin(ang)], 1)])
+    fan_e = np.array([[0, 1 + i, 1 + (i + 1) % k] for i in range(k)], np.int32)
+    with pytest.raises(lib.PagefemError) as ei:
+        lib.Csr().symbolic(2, k + 1, dev(fan_e))
+    assert ei.value.code == 7
+    del fan_c
+
+
+def _sampled_rows_check(got, coords, elems, rows, dtype):
+    ref = oracle.assemble_rows(coords, elems, rows)
+    rp, ci = got["row_ptr"], got["col_idx"]
+    worst = 0.0
+    for r, (cols, vk, vm, sk, sm) in zip(rows, ref):
+        s = slice(rp[r], rp[r + 1])
+        assert np.array_equal(ci[s], cols), f"row {r} pattern"
+        worst = max(worst, within(got["valK"][s], vk, sk, TOL[dtype], f"K row {r}"))
+        within(got["valM"][s], vm, sm, TOL[dtype], f"M row {r}")
+    return worst
+
+
+def _structure_properties(got, nn, expect_nnz):
+    rp, ci = got["row_ptr"], got["col_idx"]
+    assert got["nnz"] == expect_nnz and rp[0] == 0 and rp[-1] == expect_nnz
+    ln = np.diff(rp)
+    assert np.all(ln >= 1)
+    row_of = np.repeat(np.arange(nn), ln)
+    step = np.diff(ci.astype(np.int64))
+    same = row_of[1:] == row_of[:-1]
+    assert np.all(step[same] > 0)  # strictly ascending columns in each row
+    assert np.all((ci >= 0) & (ci < nn))
+    return row_of
+
+
+def test_cfg3_full_size_fp32(lib):
+    """128^3 cubes x 6 tets (12,582,912 tets, 2,146,689 nodes), jitter 0.15 h, FP32 values,
+    FP64 fallback below 1e-3 h^3: structure properties everywhere, oracle rows sampled."""
+    n = 128
+    h = 1.0 / n
+    say("cfg3 full size")
+    coords, elems, _ = cube(n)
+    fb = lib.fallback(1e-3 * h ** 3, 1e6, True)
+    got = _assemble(lib, coords, elems, torch.float32, fb=fb)
+    cnt = gen.kuhn_counts(n)
+    row_of = _structure_properties(got, coords.shape[0], cnt["nnz"])
+    assert got["ctr"][0] == 0 and got["ctr"][2] == 0  # no element is routed, no bad index
+    g = np.random.default_rng(11)
+    rows = np.unique(np.concatenate([g.choice(coords.shape[0], 600, replace=False), [0, coords.shape[0] - 1]]))
+    worst = _sampled_rows_check(got, coords, elems, rows.astype(np.int32), torch.float32)
+    print("worst K error / scale:", worst)
+    # K 1 = 0 and 1^T M 1 = |Omega| over all rows
+    vk = got["valK"].astype(np.float64)
+    rs = np.bincount(row_of, weights=vk, minlength=coords.shape[0])
+    ra = np.bincount(row_of, weights=np.abs(vk), minlength=coords.shape[0])
+    assert np.all(np.abs(rs) <= 1e-5 * ra)
+    assert abs(got["valM"].astype(np.float64).sum() - 1.0) < 1e-5
+
+
+def test_cfg3_sliver_variant(lib):
+    """The 128^3 mesh plus 4,096 isolated slivers (det in [1e-6, 1e-3] h^3): exactly the
+    slivers are routed to FP64, and their rows match the oracle."""
+    n = 128
+    h = 1.0 / n
+    say("cfg3 slivers")
+    coords, elems, _ = cube(n)
+    c2, e2, t = gen.append_slivers(coords, elems, 4096, h)
+    fb = lib.fallback(1e-3 * h ** 3, 1e6, True)
+    got = _assemble(lib, c2, e2, torch.float32, fb=fb)
+    assert got["ctr"][0] == 4096
+    nn0 = coords.shape[0]
+    rows = np.concatenate([np.arange(nn0, nn0 + 400), [5000, 100000]]).astype(np.int32)
+    _sampled_rows_check(got, c2, e2, rows, torch.float32)
+    # the element-level flags agree: the routed set is exactly the appended slivers
+    flags = torch.zeros(e2.shape[0], dtype=torch.uint8, device="cuda")
+    lib.elem_geometry(0, dev(c2), dev(e2), fb=fb, flags=flags)
+    f = host(flags)
+    assert not (f[:elems.shape[0]] & 2).any() and (f[elems.shape[0]:] & 2).all()
+
+
+def test_cfg3_fp64(lib):
+    say("cfg3 fp64")
+    n = 128
+    coords, elems, _ = cube(n)
+    got = _assemble(lib, coords, elems, torch.float64)
+    rows = np.random.default_rng(12).choice(coords.shape[0], 300, replace=False).astype(np.int32)
+    _sampled_rows_check(got, coords, elems, rows, torch.float64)

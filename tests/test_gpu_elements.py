@@ -1,0 +1,164 @@
+"""Parity of the P1 element kernels (section 3.5 derivative routine, stiffness and mass;
+section 3.2 volumes and normals) and of the boundary facets against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import TOL, counters, cube, dev, host, prec_of, say, square, within
+from paper_2404_16039_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2404_16039_amd import lib as L
+    return L
+
+
+def _run_elements(L, coords, elems, dtype, cK=None, cM=None, fb=None):
+    ne, nlb = elems.shape
+    dim = coords.shape[1]
+    tc, te = dev(coords), dev(elems)
+    out = {k: torch.empty(s, dtype=dtype, device="cuda") for k, s in
+           [("det", ne), ("vol", ne), ("grads", ne * dim * nlb), ("normals", ne * dim * nlb), ("facet", ne * nlb),
+            ("K3D", ne * nlb * nlb), ("M3D", ne * nlb * nlb)]}
+    flags = torch.zeros(ne, dtype=torch.uint8, device="cuda")
+    ctr = counters()
+    p = prec_of(dtype)
+    L.elem_geometry(p, tc, te, det=out["det"], vol=out["vol"], grads=out["grads"], normals=out["normals"],
+                    facet=out["facet"], fb=fb, flags=flags, counters=ctr)
+    tK = None if cK is None else dev(cK, dtype)
+    tM = None if cM is None else dev(cM, dtype)
+    L.elem_stiffness_mass(p, tc, te, cK=tK, cM=tM, K3D=out["K3D"], M3D=out["M3D"], fb=fb, counters=ctr)
+    res = {k: host(v).reshape(ne, -1) for k, v in out.items()}
+    res["flags"] = host(flags)
+    res["ctr"] = host(ctr)
+    return res
+
+
+def _check_against_oracle(res, coords, elems, dtype, cK=None, cM=None):
+    tol = TOL[dtype]
+    el = oracle.p1_elements(coords, elems)
+    dim = coords.shape[1]
+    tj = oracle.jacobians(coords, elems)
+    _, perm = oracle.page_det(tj, dim)
+    within(res["det"][:, 0], el["det"], perm, tol, "det")
+    within(res["vol"][:, 0], el["vol"], el["vol"], tol, "vol")
+    gscale = np.abs(el["grads"]).max(axis=1, keepdims=True) * np.ones_like(el["grads"])
+    within(res["grads"], el["grads"], gscale, tol, "grads")
+    within(res["normals"], -el["grads"], gscale, tol, "normals")
+    within(res["facet"], el["facet"], el["facet"], tol, "facet")
+    ck = np.ones(len(elems)) if cK is None else cK
+    cm = np.ones(len(elems)) if cM is None else cM
+    within(res["K3D"], el["Ke"] * ck[:, None], el["Kabs"] * np.abs(ck[:, None]), tol, "K3D")
+    within(res["M3D"], el["Me"] * cm[:, None], np.abs(el["Me"] * cm[:, None]), tol, "M3D")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_square_mesh_cfg1(lib, dtype):
+    """32 x 32 squares, two triangles each, jitter 0.2 h (2048 triangles, 1089 nodes)."""
+    say("elements square 32", dtype)
+    coords, elems, _ = square(32)
+    res = _run_elements(lib, coords, elems, dtype)
+    _check_against_oracle(res, coords, elems, dtype)
+    assert res["ctr"][0] == 0 and res["ctr"][1] == 0 and not res["flags"].any()
+    tol_sum = 1e-12 if dtype == torch.float64 else 1e-5
+    assert abs(res["vol"].astype(np.float64).sum() - 1.0) < tol_sum
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_cube_mesh_with_coefficients(lib, dtype):
+    say("elements cube 6", dtype)
+    coords, elems, _ = cube(6)
+    g = np.random.default_rng(3)
+    cK = g.uniform(0.5, 2.0, len(elems))
+    cM = g.uniform(0.5, 2.0, len(elems))
+    if dtype == torch.float32:
+        cK = cK.astype(np.float32).astype(np.float64)
+        cM = cM.astype(np.float32).astype(np.float64)
+    res = _run_elements(lib, coords, elems, dtype, cK, cM)
+    _check_against_oracle(res, coords, elems, dtype, cK, cM)
+
+
+def test_worked_example_tet(lib):
+    """The example tetrahedron of section 3.2: |T| = 25/64 and its printed normals."""
+    say("worked example")
+    nodes = np.array([[7, 3, -1], [7, -2, 4], [10, 3, 4], [4, 3, 4]], float) / 4
+    elems = np.array([[0, 1, 2, 3]], np.int32)
+    for dtype in (torch.float64, torch.float32):
+        res = _run_elements(lib, nodes, elems, dtype)
+        assert abs(res["vol"][0, 0] - 25 / 64) <= TOL[dtype] * 25 / 64
+        N = np.array([[0, 0, -2 / 3, 2 / 3], [0, 4 / 5, -2 / 5, -2 / 5], [4 / 5, 0, -2 / 5, -2 / 5]])
+        within(res["normals"][0].reshape(4, 3).T, N, np.ones_like(N), TOL[dtype], "worked normals")
+
+
+def test_slivers_routed_to_fp64(lib):
+    """FP32 path: elements with det below 1e-3 h^3 are recomputed in FP64."""
+    say("slivers")
+    n = 8
+    h = 1.0 / n
+    coords, elems, _ = cube(n)
+    c2, e2, t = gen.append_slivers(coords, elems, 512, h)
+    fb = lib.fallback(1e-3 * h ** 3, 1e6, True)
+    res = _run_elements(lib, c2, e2, torch.float32, fb=fb)
+    routed = (res["flags"] & 2).astype(bool)
+    ne0 = len(elems)
+    assert not routed[:ne0].any() and routed[ne0:].all()
+    assert res["ctr"][0] == 2 * 512  # geometry and stiffness/mass calls both count
+    el = oracle.p1_elements(c2, e2)
+    s = slice(ne0, None)
+    within(res["K3D"][s], el["Ke"][s], el["Kabs"][s], 1e-5, "sliver K3D")
+    within(res["vol"][s, 0], el["vol"][s], el["vol"][s], 1e-6, "sliver vol")
+    # without routing the FP32 slivers lose accuracy on their volumes; routing is what fixes it
+    res2 = _run_elements(lib, c2, e2, torch.float32, fb=lib.fallback(enable=False))
+    assert not (res2["flags"] & 2).any()
+
+
+def test_bad_index_flagged(lib):
+    say("bad index")
+    coords, elems, _ = cube(2)
+    e = elems.copy()
+    e[5, 2] = coords.shape[0]  # out of range
+    e[7, 0] = -1
+    res = _run_elements(lib, coords, e, torch.float64)
+    bad = (res["flags"] & 4).astype(bool)
+    assert bad[5] and bad[7] and bad.sum() == 2
+    assert res["ctr"][2] == 4  # two bad elements, counted by both calls
+    good = ~bad
+    el = oracle.p1_elements(coords, elems)
+    within(res["vol"][good, 0], el["vol"][good], el["vol"][good], 1e-12, "vol of good elements")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_boundary_normals_cfg3(lib, dtype):
+    """196,608 outward boundary triangles of the 128^3 Kuhn cube."""
+    say("boundary 128", dtype)
+    coords, _, faces = cube(128)
+    unit = torch.empty(faces.shape[0] * 3, dtype=dtype, device="cuda")
+    meas = torch.empty(faces.shape[0], dtype=dtype, device="cuda")
+    lib.boundary_normals(prec_of(dtype), dev(coords), dev(faces), unit=unit, measure=meas)
+    u_or, m_or, _ = oracle.boundary(coords, faces)
+    within(host(unit).reshape(-1, 3), u_or, np.ones_like(u_or), TOL[dtype], "unit normals")
+    within(host(meas), m_or, m_or, TOL[dtype], "areas")
+    assert abs(host(meas).astype(np.float64).sum() - 6.0) < (1e-10 if dtype == torch.float64 else 1e-4)
+
+
+def test_boundary_edges_2d(lib):
+    say("boundary 2d")
+    coords, _, bed = square(32)
+    unit = torch.empty(bed.shape[0] * 2, dtype=torch.float64, device="cuda")
+    meas = torch.empty(bed.shape[0], dtype=torch.float64, device="cuda")
+    lib.boundary_normals(1, dev(coords), dev(bed), unit=unit, measure=meas)
+    u_or, m_or, _ = oracle.boundary(coords, bed)
+    within(host(unit).reshape(-1, 2), u_or, np.ones_like(u_or), 1e-12, "2d unit normals")
+    within(host(meas), m_or, m_or, 1e-12, "edge lengths")
+
+
+def test_empty_mesh(lib):
+    say("empty mesh")
+    coords = torch.zeros((4, 3), dtype=torch.float64, device="cuda")
+    elems = torch.zeros((0, 4), dtype=torch.int32, device="cuda")
+    lib.elem_geometry(0, coords, elems)
+    lib.elem_stiffness_mass(1, coords, elems)

@@ -1,0 +1,318 @@
+"""Parity of the page operations (section 2.2 / 2.3) against the FP64 oracle, through the
+C ABI, on several tiles plus a ragged tail, in every supported layout, and at the full
+1e7-page batch size on sampled pages."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import TOL, counters, dev, host, say, within
+from paper_2404_16039_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+COUNT = 3 * 256 + 17  # three full tiles and a ragged tail
+DTYPES = [torch.float64, torch.float32]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2404_16039_amd import lib as L
+    return L
+
+
+def _pages(count, n, sub, dtype, shift=3.0):
+    a = gen.page_batch(count, n, sub=sub, shift=shift)
+    if dtype == torch.float32:
+        a = a.astype(np.float32).astype(np.float64)  # the FP32 input, promoted exactly
+    return a
+
+
+def _device_layout(L, a, n, dtype, layout):
+    """Put column-major flat pages a[count, n*n] on the device in the given layout."""
+    count = a.shape[0]
+    if layout == "pages":
+        return L.pages(count, n, n), dev(a, dtype)
+    if layout == "soa":
+        return L.pages_soa(count, n, n), dev(np.ascontiguousarray(a.T), dtype)
+    pad = np.zeros((count, n * n + 3))
+    pad[:, :n * n] = a
+    return L.Pages(n, n, count, 1, n, n * n + 3), dev(pad, dtype)
+
+
+def _from_layout(t, n, layout, count):
+    x = host(t)
+    if layout == "pages":
+        return x.reshape(count, n * n)
+    if layout == "soa":
+        return x.reshape(n * n, count).T
+    return x.reshape(count, n * n + 3)[:, :n * n]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+@pytest.mark.parametrize("layout", ["pages", "soa", "strided"])
+def test_det_inv_parity(lib, dtype, n, layout):
+    say("det/inv", dtype, n, layout)
+    a = _pages(COUNT, n, 21, dtype)
+    A, ta = _device_layout(lib, a, n, dtype, layout)
+    det = torch.empty(COUNT, dtype=dtype, device="cuda")
+    flags = torch.zeros(COUNT, dtype=torch.uint8, device="cuda")
+    ctr = counters()
+    lib.page_det(A, ta, det, flags=flags, counters=ctr)
+    d_or, pa = oracle.page_det(a, n)
+    within(host(det), d_or, pa, TOL[dtype], "det")
+    X, tx = _device_layout(lib, np.zeros_like(a), n, dtype, layout)
+    det2 = torch.empty(COUNT, dtype=dtype, device="cuda")
+    lib.page_inv(A, ta, X, tx, det=det2, flags=flags, counters=ctr)
+    inv_or, sing, sc = oracle.page_inv(a, n)
+    assert not sing.any()
+    within(_from_layout(tx, n, layout, COUNT), inv_or, sc, TOL[dtype], "inv")
+    assert torch.equal(det, det2)
+    assert int(host(ctr)[1]) == 0
+
+
+def _inv_exact(m):
+    from fractions import Fraction as Fr
+    n = len(m)
+
+    def det(x):
+        if len(x) == 1:
+            return x[0][0]
+        return sum((-1) ** j * x[0][j] * det([r[:j] + r[j + 1:] for r in x[1:]]) for j in range(len(x)))
+    M = [[Fr(float(v)) for v in row] for row in m]
+    d = det(M)
+    out = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            minor = [r[:j] + r[j + 1:] for k, r in enumerate(M) if k != i] if n > 1 else [[Fr(1)]]
+            out[j, i] = float((-1) ** (i + j) * det(minor) / d)
+    return out, float(d)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_inverse_componentwise_exact_rational(lib, dtype, n):
+    """Each inverse entry and det within tol of the exact rational result, componentwise."""
+    say("componentwise inverse", dtype, n)
+    cnt = 300
+    a = _pages(cnt, n, 51, dtype)
+    x = torch.empty(cnt * n * n, dtype=dtype, device="cuda")
+    det = torch.empty(cnt, dtype=dtype, device="cuda")
+    lib.page_inv(lib.pages(cnt, n, n), dev(a, dtype), lib.pages(cnt, n, n), x, det=det)
+    xs = host(x).reshape(cnt, n, n).transpose(0, 2, 1)  # row-major
+    ds = host(det)
+    for k in range(cnt):
+        ex, dex = _inv_exact(a[k].reshape(n, n).T)
+        within(xs[k], ex, np.abs(ex), TOL[dtype], f"inverse page {k}")
+        within(ds[k], dex, abs(dex), TOL[dtype], f"det page {k}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("n", [2, 3, 4])
+def test_singular_pages_flagged(lib, dtype, n):
+    say("singular", dtype, n)
+    g = np.random.default_rng(31)
+    R = g.integers(-4, 5, size=(COUNT, n, n)).astype(np.float64)
+    sing_idx = np.arange(0, COUNT, 7)
+    R[sing_idx, :, n - 1] = R[sing_idx, :, 0]  # repeated column: exactly singular, exact arithmetic
+    a = np.transpose(R, (0, 2, 1)).reshape(COUNT, n * n)
+    _, s_or, _ = oracle.page_inv(a, n)
+    d_or, _ = oracle.page_det(a, n)
+    A, ta = lib.pages(COUNT, n, n), dev(a, dtype)
+    x = torch.empty_like(ta)
+    det = torch.empty(COUNT, dtype=dtype, device="cuda")
+    flags = torch.zeros(COUNT, dtype=torch.uint8, device="cuda")
+    ctr = counters()
+    lib.page_inv(A, ta, lib.pages(COUNT, n, n), x, det=det, flags=flags, counters=ctr)
+    f = host(flags)
+    expect = (d_or == 0)
+    assert np.array_equal((f & 1).astype(bool), expect)
+    assert np.array_equal(host(det), d_or)  # integer pages: exact
+    assert int(host(ctr)[1]) == int(expect.sum())
+    xs = host(x).reshape(COUNT, n * n)
+    assert np.all(~np.isfinite(xs[expect]).all(axis=1))
+    inv_or, _, sc = oracle.page_inv(a[~expect], n)
+    within(xs[~expect], inv_or, sc, TOL[dtype], "inv of regular integer pages")
+
+
+def test_fp32_routing_near_singular(lib):
+    say("fp32 routing")
+    n = 3
+    g = np.random.default_rng(41)
+    a = gen.page_batch(COUNT, n, sub=41).astype(np.float32).astype(np.float64)
+    near = np.arange(3, COUNT, 11)
+    k = g.integers(1, 8, size=near.size)
+    for idx, kk in zip(near, k):
+        m = np.eye(3)
+        m[0, 0], m[0, 1], m[1, 0], m[1, 1] = 1.0, 1.0, 1.0, 1.0 + kk * 2.0 ** -23
+        m[2, :] = g.standard_normal(3)
+        m[2, 2] = 3.0
+        a[idx] = m.T.reshape(-1)  # column-major
+    a = a.astype(np.float32).astype(np.float64)
+    fb = lib.fallback(0.0, 1e6, True)
+    A, ta = lib.pages(COUNT, n, n), dev(a, torch.float32)
+    x = torch.empty_like(ta)
+    det = torch.empty(COUNT, dtype=torch.float32, device="cuda")
+    flags = torch.zeros(COUNT, dtype=torch.uint8, device="cuda")
+    ctr = counters()
+    lib.page_inv(A, ta, lib.pages(COUNT, n, n), x, det=det, fb=fb, flags=flags, counters=ctr)
+    routed = (host(flags) & 2).astype(bool)
+    r_or, cond = oracle.route_predicate(a, 3, 0.0, 1e6)
+    clear = np.abs(np.log(cond / 1e6)) > 1e-4  # decisions away from the threshold must agree
+    assert np.array_equal(routed[clear], r_or[clear])
+    assert routed[near].all()
+    assert int(host(ctr)[0]) == int(routed.sum())
+    inv_or, _, sc = oracle.page_inv(a, n)
+    within(host(x).reshape(COUNT, 9), inv_or, sc, TOL[torch.float32], "inv with routing")
+    d_or, pa = oracle.page_det(a, n)
+    within(host(det), d_or, pa, TOL[torch.float32], "det with routing")
+    within(host(det)[routed], d_or[routed], np.abs(d_or[routed]), 1e-6, "routed det, relative")
+    # routing switched off: the same pages stay in FP32 and are flagged as not routed
+    flags.zero_()
+    lib.page_inv(A, ta, lib.pages(COUNT, n, n), x, det=det, fb=lib.fallback(enable=False), flags=flags)
+    assert not (host(flags) & 2).any()
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_transpose_bit_exact(lib, dtype):
+    for (r, c) in [(3, 3), (2, 4), (4, 3), (1, 4), (4, 4)]:
+        say("transpose", dtype, r, c)
+        g = np.random.default_rng(r * 10 + c)
+        a = g.standard_normal((COUNT, r * c))
+        if dtype == torch.float32:
+            a = a.astype(np.float32).astype(np.float64)
+        t = torch.empty(COUNT * r * c, dtype=dtype, device="cuda")
+        lib.page_transpose(lib.pages(COUNT, r, c), dev(a, dtype), lib.pages(COUNT, c, r), t)
+        assert np.array_equal(host(t).reshape(COUNT, -1), oracle.page_transpose(a, r, c))
+        # structure-of-arrays in, pages out
+        t2 = torch.empty_like(t)
+        lib.page_transpose(lib.pages_soa(COUNT, r, c), dev(a.T, dtype), lib.pages(COUNT, c, r), t2)
+        assert torch.equal(t, t2)
+
+
+SHAPES = [(2, 2, 2), (3, 3, 3), (4, 4, 4), (3, 3, 1), (2, 2, 1), (4, 4, 1), (1, 3, 3), (3, 4, 3), (3, 3, 4),
+          (1, 4, 1), (4, 1, 4), (2, 3, 4)]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("shape", SHAPES)
+def test_mtimes_parity(lib, dtype, shape):
+    m, k, n = shape
+    g = np.random.default_rng(m * 100 + k * 10 + n)
+    for ta_ in (0, 1):
+        for tb_ in (0, 1):
+            for bc in ("none", "A", "B"):
+                say("mtimes", dtype, shape, ta_, tb_, bc)
+                ar, ac = (k, m) if ta_ else (m, k)
+                br, bcn = (n, k) if tb_ else (k, n)
+                na = 1 if bc == "A" else COUNT
+                nb = 1 if bc == "B" else COUNT
+                a = g.standard_normal((na, ar * ac))
+                b = g.standard_normal((nb, br * bcn))
+                if dtype == torch.float32:
+                    a = a.astype(np.float32).astype(np.float64)
+                    b = b.astype(np.float32).astype(np.float64)
+                Ad = lib.pages_bcast(ar, ac) if bc == "A" else lib.pages(COUNT, ar, ac)
+                Bd = lib.pages_bcast(br, bcn) if bc == "B" else lib.pages(COUNT, br, bcn)
+                c = torch.empty(COUNT * m * n, dtype=dtype, device="cuda")
+                lib.page_mtimes(Ad, dev(a, dtype), ta_, Bd, dev(b, dtype), tb_, lib.pages(COUNT, m, n), c)
+                ref, absc = oracle.page_mtimes(a, b, m, k, n, transA=bool(ta_), transB=bool(tb_), count=COUNT)
+                within(host(c).reshape(COUNT, -1), ref, absc, TOL[dtype], f"mtimes {shape} {ta_}{tb_} {bc}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_mv_scale_bilinear(lib, dtype):
+    say("mv/scale/bilinear", dtype)
+    g = np.random.default_rng(7)
+    n = 3
+    a = gen.page_batch(COUNT, n, sub=8)
+    x = g.standard_normal((COUNT, n))
+    u = g.standard_normal((COUNT, n))
+    s = g.standard_normal(COUNT)
+    if dtype == torch.float32:
+        a, x, u, s = (v.astype(np.float32).astype(np.float64) for v in (a, x, u, s))
+    y = torch.empty(COUNT * n, dtype=dtype, device="cuda")
+    for tr in (0, 1):
+        lib.page_mv(lib.pages(COUNT, n, n), dev(a, dtype), tr, lib.pages(COUNT, n, 1), dev(x, dtype),
+                    lib.pages(COUNT, n, 1), y)
+        ref, absc = oracle.page_mtimes(a, x, n, n, 1, transA=bool(tr))
+        within(host(y).reshape(COUNT, n), ref, absc, TOL[dtype], "mv")
+    # SoA operands
+    lib.page_mv(lib.pages_soa(COUNT, n, n), dev(a.T, dtype), 0, lib.pages_soa(COUNT, n, 1), dev(x.T, dtype),
+                lib.pages_soa(COUNT, n, 1), y)
+    ref, absc = oracle.page_mtimes(a, x, n, n, 1)
+    within(host(y).reshape(n, COUNT).T, ref, absc, TOL[dtype], "mv soa")
+    c = torch.empty(COUNT * n * n, dtype=dtype, device="cuda")
+    lib.page_scale(dev(s, dtype), 1, lib.pages(COUNT, n, n), dev(a, dtype), lib.pages(COUNT, n, n), c)
+    assert np.array_equal(host(c).reshape(COUNT, -1), (oracle.page_scale(s, a, n, n)).astype(
+        np.float32 if dtype == torch.float32 else np.float64).astype(np.float64))
+    q = torch.empty(COUNT, dtype=dtype, device="cuda")
+    lib.page_bilinear(lib.pages(COUNT, n, 1), dev(u, dtype), lib.pages(COUNT, n, n), dev(a, dtype),
+                      lib.pages(COUNT, n, 1), dev(x, dtype), q)
+    qo = oracle.page_bilinear(u, a, x, n)
+    scale = np.einsum("ki,kij,kj->k", np.abs(u), np.abs(a.reshape(COUNT, n, n).transpose(0, 2, 1)), np.abs(x))
+    within(host(q), qo, scale, TOL[dtype], "bilinear")
+
+
+def test_empty_batch(lib):
+    say("empty batch")
+    t = torch.empty(0, dtype=torch.float64, device="cuda")
+    lib.page_det(lib.pages(0, 3, 3), t, t)
+    lib.page_inv(lib.pages(0, 3, 3), t, lib.pages(0, 3, 3), t)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("layout", ["pages", "soa"])
+def test_full_size_1e7_sampled(lib, dtype, layout):
+    """cfg2 scale: 1e7 random 3x3 pages, N(0,1) + 3 I, a second batch and 3-vectors."""
+    count, n = 10_000_000, 3
+    say("1e7 pages", dtype, layout)
+    a = gen.page_batch(count, n, stream=gen.STREAM_PAGES_A)
+    b = gen.page_batch(count, n, stream=gen.STREAM_PAGES_B)
+    x = gen.vector_batch(count, n)
+    if dtype == torch.float32:
+        a, b, x = (v.astype(np.float32) for v in (a, b, x))
+    A, ta = _device_layout(lib, a, n, dtype, layout)
+    B, tb = _device_layout(lib, b, n, dtype, layout)
+    if layout == "pages":
+        Xd, tx, Yd = lib.pages(count, n, 1), dev(x, dtype), lib.pages(count, n, 1)
+    else:
+        Xd, tx, Yd = lib.pages_soa(count, n, 1), dev(x.T, dtype), lib.pages_soa(count, n, 1)
+    del b
+    det = torch.empty(count, dtype=dtype, device="cuda")
+    inv = torch.empty_like(ta)
+    tr = torch.empty_like(ta)
+    y = torch.empty(count * n, dtype=dtype, device="cuda")
+    c = torch.empty_like(ta)
+    ctr = counters()
+    lib.page_det(A, ta, det, counters=ctr)
+    lib.page_inv(A, ta, A, inv, counters=ctr)
+    lib.page_transpose(A, ta, A, tr)
+    lib.page_mv(A, ta, 0, Xd, tx, Yd, y)
+    lib.page_mtimes(A, ta, 0, B, tb, 0, A, c)
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(5).choice(count, 20000, replace=False))
+    idx = np.concatenate([idx, [0, count - 1]])
+    it = torch.from_numpy(idx).cuda()
+
+    def pick(t, P):
+        if layout == "pages":
+            return host(t.view(count, P)[it])
+        return host(t.view(P, count)[:, it]).T
+
+    a_s = a[idx].astype(np.float64)
+    b_s = gen.page_batch(count, n, stream=gen.STREAM_PAGES_B)[idx]
+    if dtype == torch.float32:
+        b_s = b_s.astype(np.float32).astype(np.float64)
+    x_s = x[idx].astype(np.float64)
+    d_or, pa = oracle.page_det(a_s, n)
+    within(host(det[it]), d_or, pa, TOL[dtype], "det 1e7")
+    inv_or, _, sc = oracle.page_inv(a_s, n)
+    within(pick(inv, 9), inv_or, sc, TOL[dtype], "inv 1e7")
+    assert np.array_equal(pick(tr, 9), oracle.page_transpose(a_s, 3, 3))
+    ref, absc = oracle.page_mtimes(a_s, x_s, n, n, 1)
+    within(pick(y, 3), ref, absc, TOL[dtype], "mv 1e7")
+    ref, absc = oracle.page_mtimes(a_s, b_s, n, n, n)
+    within(pick(c, 9), ref, absc, TOL[dtype], "mtimes 1e7")
+    assert int(host(ctr)[1]) == 0
