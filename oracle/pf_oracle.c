@@ -245,7 +245,8 @@ static int p1_mass_rule(int dim, double lam[4][4], double* w) {
  *   vol[e]   |det| / dim!
  *   grads    dim x nlb per element: dphi = tjac^{-1} dshape (column j = grad phi_j)
  *   Ke, Me   nlb x nlb per element: Ke = w |det| dphi^T dphi, Me = sum_q w_q |det| phi phi^T
- *   Kabs     nlb x nlb per element: w |det| sum_i |dphi(i,a) dphi(i,b)|, the error scale of Ke
+ *   Kabs     nlb x nlb per element: w |det| |dphi(:,a)| |dphi(:,b)|, the error scale of Ke
+ *            (Cauchy-Schwarz bound of the integrand grad phi_a . grad phi_b)
  *   facet    nlb per element: measure of the facet opposite node j = dim |T| |grad phi_j|
  * Any output pointer may be NULL.  Returns the number of elements whose Jacobian is singular. */
 int64_t or_p1_elements(int dim, int64_t nn, const double* coords, int64_t ne, const int32_t* elems,
@@ -291,15 +292,19 @@ int64_t or_p1_elements(int dim, int64_t nn, const double* coords, int64_t ne, co
         if (vol) vol[e] = T;
         if (grads)
             for (int q = 0; q < dim * nlb; q++) grads[e * dim * nlb + q] = dphi[q];
+        double gnorm[4];
+        for (int j = 0; j < nlb; j++) {
+            double g2 = 0.0;
+            for (int i = 0; i < dim; i++) g2 += AT(dphi, dim, i, j) * AT(dphi, dim, i, j);
+            gnorm[j] = sqrt(g2);
+        }
         for (int a = 0; a < nlb; a++)
             for (int b = 0; b < nlb; b++) {
-                double acc = 0.0, aacc = 0.0;
-                for (int i = 0; i < dim; i++) {
-                    acc += AT(dphi, dim, i, a) * AT(dphi, dim, i, b);
-                    aacc += fabs(AT(dphi, dim, i, a) * AT(dphi, dim, i, b));
-                }
+                double acc = 0.0;
+                for (int i = 0; i < dim; i++) acc += AT(dphi, dim, i, a) * AT(dphi, dim, i, b);
                 if (Ke) Ke[e * nlb * nlb + a + b * nlb] = w1 * adet * acc;
-                if (Kabs) Kabs[e * nlb * nlb + a + b * nlb] = w1 * adet * aacc;
+                /* error scale of the integrand: |grad phi_a . grad phi_b| <= |grad phi_a| |grad phi_b| */
+                if (Kabs) Kabs[e * nlb * nlb + a + b * nlb] = w1 * adet * gnorm[a] * gnorm[b];
                 if (Me) {
                     double m = 0.0;
                     for (int q = 0; q < nq; q++) m += wq[q] * adet * lam[q][a] * lam[q][b];
