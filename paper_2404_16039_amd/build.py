@@ -13,8 +13,11 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpagefem.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-# gfx950 only; packed FP32 instructions are disabled (hipcc feature flag, device side)
-FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall",
+# gfx950 only; packed FP32 instructions are disabled (hipcc feature flag, device side).
+# No implicit FMA contraction: the error-free transformations (two-sum, two-product,
+# double-word minors) need every product and sum rounded exactly as written; every FMA
+# the kernels want is spelled out.
+FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-fno-gpu-rdc"]
 
