@@ -188,10 +188,14 @@ pf_status pf_csr_symbolic(pf_csr* csr, int dim, int64_t nn, int64_t ne, const in
 pf_status pf_csr_info(const pf_csr* csr, int64_t* nn, int64_t* nnz, const int32_t** row_ptr,
                       const int32_t** col_idx);
 
-/* Numeric assembly of the global K (valsK[nnz]) and M (valsM[nnz], nullable) on the
- * structure built from the same `elems`.  Each value is the sum of its element
+/* Numeric assembly of the global K (valsK[nnz]) and M (valsM[nnz], nullable) of the mesh
+ * whose structure `csr` holds (the handle keeps the connectivity it was built from;
+ * `elems` is accepted for symmetry with the element calls and may be NULL).  coords may
+ * change between calls (same topology).  Each value is the sum of its element
  * contributions in ascending element order (deterministic: the same inputs give the same
- * bits).  prec as for the element calls; cK, cM nullable (= 1). */
+ * bits).  Every element row is computed with that row's node as the origin of the edge
+ * vectors.  prec as for the element calls; cK, cM per-element coefficients, nullable
+ * (= 1).  d_counters[0] counts FP64-routed elements once each. */
 pf_status pf_assemble(const pf_csr* csr, pf_dtype prec, const double* coords, const int32_t* elems,
                       const void* cK, const void* cM, void* valsK, void* valsM,
                       const pf_fallback* fb, int64_t* d_counters, void* stream);

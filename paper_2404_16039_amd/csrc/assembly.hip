@@ -2,21 +2,21 @@
 // sparse(X3D(:), Y3D(:), K3D(:), nn, nn) call of the section 3.5 listings, without ever
 // materialising the 16 (row, col, value) triples per element.
 //
-// Symbolic phase (integer-exact, cached in a pf_csr handle):
-//   1. count the elements around every node (node -> element adjacency, a transpose of
-//      `elems` by counting sort), scan the counts, scatter (element, local index) pairs;
-//   2. per node (one lane per row): sort its adjacency list ascending by element id, and
-//      merge the element node lists into the sorted set of distinct neighbours (LDS lists
-//      interleaved across lanes, so every lane's dynamic index hits its own bank);
-//   3. scan the row lengths into row_ptr, write col_idx.
-// Numeric phase (one lane per row, deterministic):
-//   each lane walks its node's sorted adjacency, recomputes each element's P1 geometry in
-//   registers (FP32 with compensated cofactors, FP64 for routed elements), and adds row a
-//   of K_e and M_e into the row's slots, found by binary search in the row's column list.
-//   A workgroup owns a contiguous block of rows, hence a contiguous window of the CSR
-//   arrays: columns are staged into LDS and the accumulated values leave LDS with fully
-//   coalesced stores.  Every slot is summed in ascending element order, so the result is
-//   bitwise reproducible and independent of scheduling.
+// Symbolic phase (integer-exact, kept in a pf_csr handle):
+//   1. node -> element adjacency by counting sort: per-tile LDS hash aggregation of the
+//      (element, local node) entries, one global atomic per (tile, node), a scan, and a
+//      scatter into reserved ranges;
+//   2. row lengths: per node, the number of distinct nodes of its elements (per-lane LDS
+//      hash tables, interleaved across lanes so dynamic indices stay conflict-free);
+//   3. scan into row_ptr; then per node: sort the adjacency by element id, write the
+//      sorted distinct neighbours (col_idx), and pack for every adjacency entry the row
+//      positions ("slots") of the element's other nodes.
+// Numeric phase (deterministic; see k_numeric): a block owns a contiguous range of rows,
+// hence a contiguous window of the CSR arrays.  Node coordinates are staged in LDS as the
+// FP64 difference vector of every window slot (column node minus row node, rounded once),
+// each adjacency entry recomputes its element's row of K_e and M_e from three of those
+// vectors, and every slot sums its contributions in ascending element order before one
+// coalesced store.  The result is bitwise reproducible and independent of scheduling.
 #include "p1elem.hpp"
 
 #include <algorithm>
@@ -26,15 +26,18 @@
 struct pf_csr {
     int dim = 0, nlb = 0;
     int64_t nn = 0, ne = 0, nnz = 0;
-    int max_window = 0;       // largest CSR window of one numeric workgroup
+    int wmax_big = 0, emax_big = 0;      // largest window / adjacency range of a 32-row block
+    int wmax_small = 0, emax_small = 0;  // ... of an 8-row block
     int32_t* adj_ptr = nullptr;
     int32_t* adj = nullptr;   // (element << 2) | local index, sorted per node
+    uint32_t* pk = nullptr;   // per adjacency entry: local index and slots of the other nodes
     int32_t* row_ptr = nullptr;
     int32_t* col_idx = nullptr;
     int32_t* cnt = nullptr;   // per-node counts / cursors / row lengths
     int64_t* bsum = nullptr;  // scan workspace
-    int64_t* info = nullptr;  // [0] error bits, [1] adjacency total, [2] nnz, [3] max window
-    int64_t cap_adj_ptr = 0, cap_row_ptr = 0, cap_cnt = 0, cap_adj = 0, cap_nnz = 0, cap_bsum = 0, cap_info = 0;
+    int64_t* info = nullptr;  // [0] error bits, [1] adjacency total, [2] nnz, [3..6] block stats
+    int64_t cap_adj_ptr = 0, cap_row_ptr = 0, cap_cnt = 0, cap_adj = 0, cap_pk = 0, cap_nnz = 0, cap_bsum = 0,
+            cap_info = 0;
     bool built = false;
 };
 
@@ -43,11 +46,7 @@ namespace pf {
 constexpr int SBS = 256;         // threads per block in the flat symbolic kernels
 constexpr int SCAN_ITEMS = 8;    // items per thread in the scan
 constexpr int SCAN_TILE = SBS * SCAN_ITEMS;
-constexpr int RBS = 128;         // rows per block in the row kernels
-constexpr int MAXADJ = 64;       // elements per node
-constexpr int MAXROW = 64;       // nonzeros per row
-constexpr int NBS = 128;         // rows per block in the numeric kernel
-constexpr size_t LDS_BYTES = 65536;  // largest window staged in LDS (else the global path)
+constexpr size_t LDS_BYTES = 65536;  // dynamic LDS budget of one numeric block
 
 constexpr int64_t ERR_INDEX = 1, ERR_ADJ = 2, ERR_ROW = 4;
 
@@ -133,50 +132,136 @@ __global__ __launch_bounds__(SBS) void k_scan_apply(const int32_t* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------- adjacency
-__global__ __launch_bounds__(SBS) void k_count(const int32_t* __restrict__ elems, int64_t m, int64_t nn,
-                                               int32_t* __restrict__ cnt, int64_t* __restrict__ info) {
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * SBS + threadIdx.x; t < m;
-         t += static_cast<int64_t>(gridDim.x) * SBS) {
-        const int32_t node = elems[t];
-        if (node < 0 || node >= nn)
-            atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_INDEX));
-        else
-            atomicAdd(cnt + node, 1);
+// Node -> element adjacency by counting sort.  Each block aggregates a tile of AG_TILE
+// (element, local node) entries in an LDS hash table keyed by node id, so a node that
+// appears several times in the tile (neighbouring elements share nodes) costs one global
+// atomic per tile instead of one per entry.
+constexpr int AG_BS = 256;
+constexpr int AG_ITEMS = 16;
+constexpr int AG_TILE = AG_BS * AG_ITEMS;
+constexpr int AG_HASH = 2 * AG_TILE;  // load factor <= 1/2, probing always ends
+
+__device__ __forceinline__ int ag_hash(int32_t node) {
+    return static_cast<int>((static_cast<uint32_t>(node) * 2654435761u) >> (32 - 13)) & (AG_HASH - 1);
+}
+
+// insert `node` (or find it) in the block's table; returns its slot
+__device__ __forceinline__ int ag_insert(int32_t* keys, int32_t node) {
+    int h = ag_hash(node);
+    while (true) {
+        const int32_t k = atomicCAS(keys + h, -1, node);
+        if (k == -1 || k == node) return h;
+        h = (h + 1) & (AG_HASH - 1);
     }
 }
 
-__global__ __launch_bounds__(SBS) void k_scatter(const int32_t* __restrict__ elems, int64_t m, int nlb, int64_t nn,
-                                                 const int32_t* __restrict__ adj_ptr, int32_t* __restrict__ cursor,
-                                                 int32_t* __restrict__ adj) {
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * SBS + threadIdx.x; t < m;
-         t += static_cast<int64_t>(gridDim.x) * SBS) {
-        const int32_t node = elems[t];
-        if (node < 0 || node >= nn) continue;
-        const int64_t e = t / nlb;
-        const int a = static_cast<int>(t - e * nlb);
-        const int32_t pos = adj_ptr[node] + atomicAdd(cursor + node, 1);
-        adj[pos] = static_cast<int32_t>((e << 2) | a);
+__global__ __launch_bounds__(AG_BS) void k_count(const int32_t* __restrict__ elems, int64_t m, int64_t nn,
+                                                 int32_t* __restrict__ cnt, int64_t* __restrict__ info) {
+    __shared__ int32_t keys[AG_HASH];
+    __shared__ int32_t vals[AG_HASH];
+    for (int h = threadIdx.x; h < AG_HASH; h += AG_BS) {
+        keys[h] = -1;
+        vals[h] = 0;
+    }
+    __syncthreads();
+    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * AG_TILE;
+    bool bad = false;
+#pragma unroll
+    for (int q = 0; q < AG_ITEMS; ++q) {
+        const int64_t t = t0 + q * AG_BS + threadIdx.x;
+        if (t < m) {
+            const int32_t node = elems[t];
+            if (node < 0 || node >= nn) bad = true;
+            else atomicAdd(vals + ag_insert(keys, node), 1);
+        }
+    }
+    if (bad) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_INDEX));
+    __syncthreads();
+    for (int h = threadIdx.x; h < AG_HASH; h += AG_BS)
+        if (keys[h] >= 0) atomicAdd(cnt + keys[h], vals[h]);
+}
+
+// Scatter (element << 2 | local index) into each node's list.  One global atomic per
+// (tile, node) reserves the tile's range; entries take positions inside it through LDS
+// atomics.  The order inside a list is fixed later (k_cols sorts every list).
+__global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ elems, int64_t m, int nlb, int64_t nn,
+                                                   const int32_t* __restrict__ adj_ptr, int32_t* __restrict__ cursor,
+                                                   int32_t* __restrict__ adj) {
+    __shared__ int32_t keys[AG_HASH];
+    __shared__ int32_t vals[AG_HASH];
+    for (int h = threadIdx.x; h < AG_HASH; h += AG_BS) {
+        keys[h] = -1;
+        vals[h] = 0;
+    }
+    __syncthreads();
+    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * AG_TILE;
+    int slot[AG_ITEMS];
+#pragma unroll
+    for (int q = 0; q < AG_ITEMS; ++q) {
+        const int64_t t = t0 + q * AG_BS + threadIdx.x;
+        slot[q] = -1;
+        if (t < m) {
+            const int32_t node = elems[t];
+            if (node >= 0 && node < nn) {
+                slot[q] = ag_insert(keys, node);
+                atomicAdd(vals + slot[q], 1);
+            }
+        }
+    }
+    __syncthreads();
+    for (int h = threadIdx.x; h < AG_HASH; h += AG_BS) {
+        const int32_t node = keys[h];
+        if (node >= 0) vals[h] = adj_ptr[node] + atomicAdd(cursor + node, vals[h]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < AG_ITEMS; ++q) {
+        if (slot[q] >= 0) {
+            const int64_t t = t0 + q * AG_BS + threadIdx.x;
+            const int64_t e = t / nlb;
+            const int a = static_cast<int>(t - e * nlb);
+            adj[atomicAdd(vals + slot[q], 1)] = static_cast<int32_t>((e << 2) | a);
+        }
     }
 }
 
-// insert `v` into the interleaved sorted list lst[0..n) (stride RBS); returns false when full
-__device__ __forceinline__ bool insert_unique(int32_t* lst, int& n, int32_t v, int cap) {
-    int p = 0;
-    while (p < n && lst[p * RBS] < v) ++p;
-    if (p < n && lst[p * RBS] == v) return true;
-    if (n >= cap) return false;
-    for (int q = n; q > p; --q) lst[q * RBS] = lst[(q - 1) * RBS];
-    lst[p * RBS] = v;
-    ++n;
-    return true;
+// ---------------------------------------------------------------------------- row pattern
+constexpr int RBS = 64;        // rows (= lanes) per block in the row kernels
+constexpr int MAXADJ = 64;     // elements per node
+constexpr int MAXROW = 64;     // nonzeros per row
+constexpr int RHASH = 128;     // per-lane hash table of the distinct neighbours
+
+// gather the node lists of up to 4 adjacency entries at once (independent loads in flight)
+template <int NLB>
+__device__ __forceinline__ void gather4(const int32_t* __restrict__ elems, const int32_t* __restrict__ keys, int j,
+                                        int L, int (&nd)[4][4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (j + q < L) {
+            const int64_t e = keys[j + q] >> 2;
+            if constexpr (NLB == 4) {
+                int n4[4];
+                load_nodes<3>(elems, e, n4);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) nd[q][k] = n4[k];
+            } else {
+                int n3[3];
+                load_nodes<2>(elems, e, n3);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) nd[q][k] = n3[k];
+            }
+        }
+    }
 }
 
-// sort each node's adjacency and count its distinct neighbours (row length)
-__global__ __launch_bounds__(RBS) void k_rows(int64_t nn, int nlb, const int32_t* __restrict__ elems,
-                                              const int32_t* __restrict__ adj_ptr, int32_t* __restrict__ adj,
+// number of distinct neighbours of every node (row lengths), through a per-lane open-
+// addressing table in LDS (interleaved across lanes, so each lane's probes hit its bank)
+template <int NLB>
+__global__ __launch_bounds__(RBS) void k_rows(int64_t nn, const int32_t* __restrict__ elems,
+                                              const int32_t* __restrict__ adj_ptr, const int32_t* __restrict__ adj,
                                               int32_t* __restrict__ rowlen, int64_t* __restrict__ info) {
-    __shared__ int32_t lds[MAXADJ * RBS];
-    int32_t* lst = lds + threadIdx.x;
+    __shared__ int32_t lds[RHASH * RBS];
+    int32_t* tab = lds + threadIdx.x;
     const int64_t i = static_cast<int64_t>(blockIdx.x) * RBS + threadIdx.x;
     if (i >= nn) return;
     const int32_t b = adj_ptr[i];
@@ -186,7 +271,57 @@ __global__ __launch_bounds__(RBS) void k_rows(int64_t nn, int nlb, const int32_t
         rowlen[i] = 0;
         return;
     }
-    for (int j = 0; j < L; ++j) {  // insertion sort (lists are short)
+#pragma unroll 8
+    for (int h = 0; h < RHASH; ++h) tab[h * RBS] = -1;
+    int n = 0;
+    for (int j = 0; j < L; j += 4) {
+        int nd[4][4];
+        gather4<NLB>(elems, adj + b, j, L, nd);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (j + q >= L) break;
+#pragma unroll
+            for (int k = 0; k < NLB; ++k) {
+                const int32_t v = nd[q][k];
+                int h = static_cast<int>((static_cast<uint32_t>(v) * 2654435761u) >> 25);
+                while (true) {
+                    const int32_t cur = tab[h * RBS];
+                    if (cur == v) break;
+                    if (cur == -1) {
+                        tab[h * RBS] = v;
+                        ++n;
+                        break;
+                    }
+                    h = (h + 1) & (RHASH - 1);
+                }
+            }
+        }
+        if (n > MAXROW) break;
+    }
+    if (n > MAXROW) {
+        atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
+        n = 0;
+    }
+    rowlen[i] = n;
+}
+
+// Per node: sort its adjacency ascending by element (deterministic summation order), build
+// the sorted distinct neighbour list (col_idx), and pack for every adjacency entry its local
+// index a and the row positions ("slots") of the element's other nodes, in local order:
+// bits 0-1 a, bits 2+8k .. 9+8k slot of the k-th other node.
+template <int NLB>
+__global__ __launch_bounds__(RBS) void k_cols(int64_t nn, const int32_t* __restrict__ elems,
+                                              const int32_t* __restrict__ adj_ptr, int32_t* __restrict__ adj,
+                                              const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_idx,
+                                              uint32_t* __restrict__ pk) {
+    __shared__ int32_t lds[MAXROW * RBS];
+    int32_t* lst = lds + threadIdx.x;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * RBS + threadIdx.x;
+    if (i >= nn) return;
+    const int32_t b = adj_ptr[i];
+    const int L = adj_ptr[i + 1] - b;
+    // 1. insertion sort of the adjacency keys (L <= MAXADJ, checked by k_rows)
+    for (int j = 0; j < L; ++j) {
         const int32_t v = adj[b + j];
         int p = j;
         while (p > 0 && lst[(p - 1) * RBS] > v) {
@@ -196,175 +331,233 @@ __global__ __launch_bounds__(RBS) void k_rows(int64_t nn, int nlb, const int32_t
         lst[p * RBS] = v;
     }
     for (int j = 0; j < L; ++j) adj[b + j] = lst[j * RBS];
+    // 2. sorted distinct neighbours (at most MAXROW, checked by k_rows)
     int n = 0;
-    bool ok = true;
-    for (int j = 0; j < L && ok; ++j) {
-        const int64_t e = adj[b + j] >> 2;
-        for (int q = 0; q < nlb && ok; ++q) ok = insert_unique(lst, n, elems[e * nlb + q], MAXROW);
-    }
-    if (!ok) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
-    rowlen[i] = ok ? n : 0;
-}
-
-__global__ __launch_bounds__(RBS) void k_cols(int64_t nn, int nlb, const int32_t* __restrict__ elems,
-                                              const int32_t* __restrict__ adj_ptr, const int32_t* __restrict__ adj,
-                                              const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_idx) {
-    __shared__ int32_t lds[MAXROW * RBS];
-    int32_t* lst = lds + threadIdx.x;
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * RBS + threadIdx.x;
-    if (i >= nn) return;
-    const int32_t b = adj_ptr[i];
-    const int L = adj_ptr[i + 1] - b;
-    int n = 0;
-    for (int j = 0; j < L; ++j) {
-        const int64_t e = adj[b + j] >> 2;
-        for (int q = 0; q < nlb; ++q) insert_unique(lst, n, elems[e * nlb + q], MAXROW);
+    for (int j = 0; j < L; j += 4) {
+        int nd[4][4];
+        gather4<NLB>(elems, adj + b, j, L, nd);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (j + q >= L) break;
+#pragma unroll
+            for (int k = 0; k < NLB; ++k) {
+                const int32_t v = nd[q][k];
+                int p = 0;
+                while (p < n && lst[p * RBS] < v) ++p;
+                if (p < n && lst[p * RBS] == v) continue;
+                for (int r = n; r > p; --r) lst[r * RBS] = lst[(r - 1) * RBS];
+                lst[p * RBS] = v;
+                ++n;
+            }
+        }
     }
     const int32_t o = row_ptr[i];
     for (int j = 0; j < n; ++j) col_idx[o + j] = lst[j * RBS];
-}
-
-__global__ void k_window_max(int64_t nn, const int32_t* __restrict__ row_ptr, int64_t nblk, int64_t* __restrict__ info) {
-    const int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (b >= nblk) return;
-    const int64_t r0 = b * NBS;
-    const int64_t r1 = (r0 + NBS < nn) ? r0 + NBS : nn;
-    const int64_t w = row_ptr[r1] - row_ptr[r0];
-    atomicMax(reinterpret_cast<unsigned long long*>(info + 3), static_cast<unsigned long long>(w));
+    // 3. packed slots of every entry
+    for (int j = 0; j < L; j += 4) {
+        int nd[4][4];
+        gather4<NLB>(elems, adj + b, j, L, nd);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (j + q >= L) break;
+            const int a = adj[b + j + q] & 3;
+            uint32_t word = static_cast<uint32_t>(a);
+            int k2 = 0;
+#pragma unroll
+            for (int k = 0; k < NLB; ++k) {
+                if (k == a) continue;
+                const int32_t v = nd[q][k];
+                int lo = 0, hi = n;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (lst[mid * RBS] < v) lo = mid + 1;
+                    else hi = mid;
+                }
+                word |= static_cast<uint32_t>(lo) << (2 + 8 * k2);
+                ++k2;
+            }
+            pk[b + j + q] = word;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------- numeric
-__device__ __forceinline__ int find_col(const int32_t* __restrict__ cols, int len, int32_t v) {
-    int lo = 0, hi = len;  // first position with cols[p] >= v
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (cols[mid] < v) lo = mid + 1;
-        else hi = mid;
-    }
-    return (lo < len && cols[lo] == v) ? lo : -1;
+constexpr int NR_BIG = 32;   // rows per block of the numeric kernel
+constexpr int NR_SMALL = 8;  // ... when the big blocks' windows do not fit in LDS
+constexpr int NBT = 256;     // threads per block of the numeric kernel
+
+// largest CSR window and adjacency range of one numeric block of `nr` rows, into info[slot],
+// info[slot + 1]
+__global__ void k_block_stats(int64_t nn, int nr, const int32_t* __restrict__ row_ptr,
+                              const int32_t* __restrict__ adj_ptr, int64_t nblk, int64_t* __restrict__ info, int slot) {
+    const int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= nblk) return;
+    const int64_t r0 = b * nr;
+    const int64_t r1 = (r0 + nr < nn) ? r0 + nr : nn;
+    atomicMax(reinterpret_cast<unsigned long long*>(info + slot),
+              static_cast<unsigned long long>(row_ptr[r1] - row_ptr[r0]));
+    atomicMax(reinterpret_cast<unsigned long long*>(info + slot + 1),
+              static_cast<unsigned long long>(adj_ptr[r1] - adj_ptr[r0]));
 }
 
-// Row a of K_e and M_e (coefficients and FP64 routing included), computed in precision C.
+template <int DIM, typename T>
+constexpr size_t numeric_lds_bytes(int nr, int wmax, int emax) {
+    return static_cast<size_t>(DIM * wmax + (DIM + 2) * emax) * sizeof(T) + static_cast<size_t>(emax) * 4 +
+           static_cast<size_t>(2 * (nr + 1)) * 4 + static_cast<size_t>(wmax);
+}
+
+// Row of K_e and M_e for the element's node that is the origin of the edge vectors (local
+// vertex 0 of the geometry): k[b] = cK |T| grad phi_0 . grad phi_b, mo = cM |T| / ((d+1)(d+2)).
 template <int DIM, typename C>
-__device__ __forceinline__ void elem_row(const P1Geom<DIM, C>& g, int a, C ck, C cm, C (&krow)[DIM + 1], C& moff) {
+__device__ __forceinline__ void origin_row(const P1Geom<DIM, C>& g, C ck, C cm, C (&k)[DIM + 1], C& mo) {
     const C adet = fabs(g.det);
     const C kf = ck / (static_cast<C>(fact_dim<DIM>()) * adet);
-    C ca[DIM];
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) {
-        C v = g.c[0][i];
-#pragma unroll
-        for (int j = 1; j <= DIM; ++j) v = (a == j) ? g.c[j][i] : v;
-        ca[i] = v;
-    }
 #pragma unroll
     for (int b = 0; b <= DIM; ++b) {
-        C s = ca[0] * g.c[b][0];
+        C s = g.c[0][0] * g.c[b][0];
 #pragma unroll
-        for (int i = 1; i < DIM; ++i) s = fmaT(ca[i], g.c[b][i], s);
-        krow[b] = kf * s;
+        for (int q = 1; q < DIM; ++q) s = fmaT(g.c[0][q], g.c[b][q], s);
+        k[b] = kf * s;
     }
-    moff = cm * (adet / static_cast<C>(fact_dim<DIM>())) / static_cast<C>((DIM + 1) * (DIM + 2));
+    mo = cm * (adet / static_cast<C>(fact_dim<DIM>())) / static_cast<C>((DIM + 1) * (DIM + 2));
 }
 
-template <int DIM, typename T, bool LDS>
-__global__ __launch_bounds__(NBS) void k_numeric(int64_t nn, const double* __restrict__ coords,
-                                                 const int32_t* __restrict__ elems, const int32_t* __restrict__ adj_ptr,
-                                                 const int32_t* __restrict__ adj, const int32_t* __restrict__ row_ptr,
-                                                 const int32_t* __restrict__ col_idx, const T* __restrict__ cK,
+__device__ __forceinline__ int upper_pos(const int32_t* v, int n, int32_t x) {
+    // last index r in [0, n) with v[r] <= x (v ascending, v[0] <= x)
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (v[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Numeric assembly, NR rows per block:
+//   phase 0  every CSR slot of the block's window gets the edge vector from its row's node to
+//            its column's node (FP64 difference, rounded to T) in LDS;
+//   phase 1  every adjacency entry (row node = element vertex a) computes, from three edge
+//            vectors read from LDS, its element's row a of K_e and M_e (routed elements are
+//            recomputed from the FP64 coordinates), into an LDS stage;
+//   phase 2  every slot sums its row's stage in ascending element order and stores once.
+template <int DIM, typename T, bool COEF, int NR>
+__global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __restrict__ coords,
+                                                 const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                                                 const int32_t* __restrict__ adj_ptr, const int32_t* __restrict__ adj,
+                                                 const uint32_t* __restrict__ pk, const T* __restrict__ cK,
                                                  const T* __restrict__ cM, T* __restrict__ valsK, T* __restrict__ valsM,
-                                                 Fallback fb, int64_t* d_counters) {
+                                                 Fallback fb, int64_t* d_counters, int wmax, int emax) {
     constexpr int NLB = DIM + 1;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * NBS;
-    const int64_t r1 = (r0 + NBS < nn) ? r0 + NBS : nn;
-    const int32_t w0 = row_ptr[r0];
-    const int W = row_ptr[r1] - w0;
-    T* accK;
-    T* accM;
-    const int32_t* cols;
-    if constexpr (LDS) {
-        accK = reinterpret_cast<T*>(smem);
-        accM = accK + W;
-        int32_t* c = reinterpret_cast<int32_t*>(accM + W);
-        for (int w = threadIdx.x; w < W; w += NBS) {
-            c[w] = col_idx[w0 + w];
-            accK[w] = T(0);
-            accM[w] = T(0);
-        }
-        cols = c;
-        __syncthreads();
-    } else {
-        accK = valsK + w0;
-        accM = valsM ? valsM + w0 : nullptr;
-        cols = col_idx + w0;
-        for (int w = threadIdx.x; w < W; w += NBS) {
-            accK[w] = T(0);
-            if (accM) accM[w] = T(0);
-        }
-        __syncthreads();
+    T* f = reinterpret_cast<T*>(smem);                          // [DIM][wmax]
+    T* kc = f + DIM * wmax;                                     // [emax][NLB]
+    T* mo = kc + NLB * emax;                                    // [emax]
+    uint32_t* pkl = reinterpret_cast<uint32_t*>(mo + emax);     // [emax]
+    int32_t* rp = reinterpret_cast<int32_t*>(pkl + emax);       // [NR + 1]
+    int32_t* ap = rp + (NR + 1);                                // [NR + 1]
+    uint8_t* rloc = reinterpret_cast<uint8_t*>(ap + (NR + 1));  // [wmax]
+
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * NR;
+    const int nr = static_cast<int>((r0 + NR < nn) ? NR : nn - r0);
+    if (threadIdx.x <= nr) {
+        rp[threadIdx.x] = row_ptr[r0 + threadIdx.x];
+        ap[threadIdx.x] = adj_ptr[r0 + threadIdx.x];
     }
-    const int64_t i = r0 + threadIdx.x;
-    int64_t bad = 0;
-    if (i < r1) {
-        const int s0 = row_ptr[i] - w0;
-        const int len = row_ptr[i + 1] - row_ptr[i];
-        const int32_t* rc = cols + s0;
-        const int diag = find_col(rc, len, static_cast<int32_t>(i));
-        const int32_t t1 = adj_ptr[i + 1];
-        for (int32_t t = adj_ptr[i]; t < t1; ++t) {
-            const int32_t v = adj[t];
-            const int64_t e = v >> 2;
-            const int a = v & 3;
-            int nd[NLB];
-            load_nodes<DIM>(elems, e, nd);
+    __syncthreads();
+    const int32_t w0 = rp[0], e0 = ap[0];
+    const int W = rp[nr] - w0, NE = ap[nr] - e0;
+
+    // phase 0: edge vector per slot
+    for (int w = threadIdx.x; w < W; w += NBT) {
+        const int r = upper_pos(rp, nr, w0 + w);
+        const int64_t i = r0 + r;
+        const int32_t col = col_idx[w0 + w];
+        rloc[w] = static_cast<uint8_t>(r | ((col == i) ? 128 : 0));
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+            f[k * wmax + w] = static_cast<T>(coords[static_cast<int64_t>(col) * DIM + k] - coords[i * DIM + k]);
+    }
+    __syncthreads();
+
+    // phase 1: row a of every adjacent element
+    int64_t routed = 0;
+    for (int t = threadIdx.x; t < NE; t += NBT) {
+        const int r = upper_pos(ap, nr, e0 + t);
+        const int s0 = rp[r] - w0;
+        const uint32_t p = pk[e0 + t];
+        pkl[t] = p;
+        T ck = T(1), cm = T(1);
+        if constexpr (COEF) {
+            const int64_t e = adj[e0 + t] >> 2;
+            if (cK) ck = cK[e];
+            if (cM) cm = cM[e];
+        }
+        T u[DIM][DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const int s = s0 + static_cast<int>((p >> (2 + 8 * k)) & 255);
+#pragma unroll
+            for (int q = 0; q < DIM; ++q) u[k][q] = f[q * wmax + s];
+        }
+        T krow[NLB], m;
+        P1Geom<DIM, T> g;
+        p1_geom_edges<DIM, T>(u, g);
+        bool route = false;
+        if constexpr (sizeof(T) == 4) route = should_route(g.det, g.absterms, fb);
+        if (route) {
+            // FP64 recomputation from the coordinates of the row's node and the three others
+            const int64_t i = r0 + r;
             double ev[DIM][DIM];
-            if (!p1_edges<DIM>(coords, nn, nd, ev) || diag < 0) {
-                ++bad;
-                continue;
-            }
-            T krow[NLB], moff;
-            const T ck = cK ? cK[e] : T(1);
-            const T cm = cM ? cM[e] : T(1);
-            if constexpr (sizeof(T) == 4) {
-                P1Geom<DIM, float> g;
-                p1_geom<DIM, float>(ev, g);
-                if (should_route(g.det, g.absterms, fb)) {
-                    P1Geom<DIM, double> gd;
-                    p1_geom<DIM, double>(ev, gd);
-                    double kr[NLB], mo;
-                    elem_row<DIM, double>(gd, a, ck, cm, kr, mo);
 #pragma unroll
-                    for (int b = 0; b < NLB; ++b) krow[b] = static_cast<T>(kr[b]);
-                    moff = static_cast<T>(mo);
-                    if (a == 0) count_add(d_counters, 0, 1);
-                } else {
-                    elem_row<DIM, float>(g, a, ck, cm, krow, moff);
-                }
-            } else {
-                P1Geom<DIM, double> g;
-                p1_geom<DIM, double>(ev, g);
-                elem_row<DIM, double>(g, a, ck, cm, krow, moff);
-            }
+            for (int k = 0; k < DIM; ++k) {
+                const int64_t col = col_idx[w0 + s0 + static_cast<int>((p >> (2 + 8 * k)) & 255)];
 #pragma unroll
-            for (int b = 0; b < NLB; ++b) {
-                const int slot = (b == a) ? diag : find_col(rc, len, nd[b]);
-                if (slot < 0) {
-                    ++bad;
-                    continue;
-                }
-                accK[s0 + slot] += krow[b];
-                if (LDS || accM) accM[s0 + slot] += (b == a) ? moff + moff : moff;
+                for (int q = 0; q < DIM; ++q) ev[k][q] = coords[col * DIM + q] - coords[i * DIM + q];
             }
+            P1Geom<DIM, double> gd;
+            p1_geom<DIM, double>(ev, gd);
+            double kd[NLB], md;
+            origin_row<DIM, double>(gd, ck, cm, kd, md);
+#pragma unroll
+            for (int b = 0; b < NLB; ++b) krow[b] = static_cast<T>(kd[b]);
+            m = static_cast<T>(md);
+            if ((p & 3) == 0) ++routed;  // count each element once, at its first node's row
+        } else {
+            origin_row<DIM, T>(g, ck, cm, krow, m);
         }
+#pragma unroll
+        for (int b = 0; b < NLB; ++b) kc[t * NLB + b] = krow[b];
+        mo[t] = m;
     }
-    if (bad) count_add(d_counters, 2, bad);
-    if constexpr (LDS) {
-        __syncthreads();
-        for (int w = threadIdx.x; w < W; w += NBS) {
-            valsK[w0 + w] = accK[w];
-            if (valsM) valsM[w0 + w] = accM[w];
+    if (routed) count_add(d_counters, 0, routed);
+    __syncthreads();
+
+    // phase 2: one slot per thread, ascending element order, coalesced stores
+    for (int w = threadIdx.x; w < W; w += NBT) {
+        const int code = rloc[w];
+        const int r = code & 127;
+        const int s = w - (rp[r] - w0);
+        const int t0 = ap[r] - e0, t1 = ap[r + 1] - e0;
+        T sk = T(0), sm = T(0);
+        if (code & 128) {
+            for (int t = t0; t < t1; ++t) {
+                sk += kc[t * NLB];
+                sm += mo[t] + mo[t];
+            }
+        } else {
+            for (int t = t0; t < t1; ++t) {
+                const uint32_t p = pkl[t];
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) {
+                    if (static_cast<int>((p >> (2 + 8 * k)) & 255) == s) {
+                        sk += kc[t * NLB + 1 + k];
+                        sm += mo[t];
+                    }
+                }
+            }
         }
+        valsK[w0 + w] = sk;
+        if (valsM) valsM[w0 + w] = sm;
     }
 }
 
@@ -401,6 +594,34 @@ pf_status scan(const int32_t* in, int64_t n, int32_t* out, int64_t* bsum, int64_
     return launch_check("scan");
 }
 
+template <int DIM, typename T, bool COEF, int NRB>
+pf_status launch_numeric(const pf_csr* c, const double* coords, const void* cK, const void* cM, void* valsK,
+                         void* valsM, Fallback f, int64_t* ctr, int wmax, int emax, hipStream_t s) {
+    const size_t shm = numeric_lds_bytes<DIM, T>(NRB, wmax, emax);
+    const unsigned g = static_cast<unsigned>(ceil_div(c->nn, NRB));
+    hipLaunchKernelGGL((k_numeric<DIM, T, COEF, NRB>), dim3(g), dim3(NBT), shm, s, c->nn, coords, c->row_ptr,
+                       c->col_idx, c->adj_ptr, c->adj, c->pk, static_cast<const T*>(cK), static_cast<const T*>(cM),
+                       static_cast<T*>(valsK), static_cast<T*>(valsM), f, ctr, wmax, emax);
+    return launch_check("pf_assemble");
+}
+
+template <int DIM, typename T>
+pf_status numeric_dispatch(const pf_csr* c, const double* coords, const void* cK, const void* cM, void* valsK,
+                           void* valsM, Fallback f, int64_t* ctr, hipStream_t s) {
+    const bool coef = cK || cM;
+    if (numeric_lds_bytes<DIM, T>(NR_BIG, c->wmax_big, c->emax_big) <= LDS_BYTES) {
+        return coef ? launch_numeric<DIM, T, true, NR_BIG>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_big,
+                                                           c->emax_big, s)
+                    : launch_numeric<DIM, T, false, NR_BIG>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_big,
+                                                            c->emax_big, s);
+    }
+    // 8 rows of at most MAXROW nonzeros and MAXADJ elements always fit
+    return coef ? launch_numeric<DIM, T, true, NR_SMALL>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_small,
+                                                         c->emax_small, s)
+                : launch_numeric<DIM, T, false, NR_SMALL>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_small,
+                                                          c->emax_small, s);
+}
+
 }  // namespace
 }  // namespace pf
 
@@ -419,6 +640,7 @@ void pf_csr_destroy(pf_csr* c) {
     if (!c) return;
     (void)hipFree(c->adj_ptr);
     (void)hipFree(c->adj);
+    (void)hipFree(c->pk);
     (void)hipFree(c->row_ptr);
     (void)hipFree(c->col_idx);
     (void)hipFree(c->cnt);
@@ -443,27 +665,34 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     if ((st = grow(c->row_ptr, c->cap_row_ptr, nn + 1))) return st;
     if ((st = grow(c->cnt, c->cap_cnt, nn + 1))) return st;
     if ((st = grow(c->adj, c->cap_adj, m))) return st;
+    if ((st = grow(c->pk, c->cap_pk, m))) return st;
     const int64_t nb = std::max<int64_t>(ceil_div(nn + 1, SCAN_TILE), 1);
     if ((st = grow(c->bsum, c->cap_bsum, nb))) return st;
-    if ((st = grow(c->info, c->cap_info, 4))) return st;
-    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, c->info, int64_t(4), int64_t(0));
+    if ((st = grow(c->info, c->cap_info, 8))) return st;
+    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, c->info, int64_t(8), int64_t(0));
     if (nn > 0) hipLaunchKernelGGL(k_fill_i32, dim3(flat_grid(nn)), dim3(SBS), 0, s, c->cnt, nn, 0);
-    if (m > 0) hipLaunchKernelGGL(k_count, dim3(flat_grid(m)), dim3(SBS), 0, s, elems, m, nn, c->cnt, c->info);
+    const unsigned gtile = static_cast<unsigned>(std::max<int64_t>(ceil_div(m, AG_TILE), 1));
+    if (m > 0) hipLaunchKernelGGL(k_count, dim3(gtile), dim3(AG_BS), 0, s, elems, m, nn, c->cnt, c->info);
     if ((st = scan(c->cnt, nn, c->adj_ptr, c->bsum, c->info + 1, s))) return st;
     if (nn > 0) hipLaunchKernelGGL(k_fill_i32, dim3(flat_grid(nn)), dim3(SBS), 0, s, c->cnt, nn, 0);
     if (m > 0)
-        hipLaunchKernelGGL(k_scatter, dim3(flat_grid(m)), dim3(SBS), 0, s, elems, m, nlb, nn, c->adj_ptr, c->cnt,
-                           c->adj);
-    if (nn > 0)
-        hipLaunchKernelGGL(k_rows, dim3(static_cast<unsigned>(ceil_div(nn, RBS))), dim3(RBS), 0, s, nn, nlb, elems,
-                           c->adj_ptr, c->adj, c->cnt, c->info);
+        hipLaunchKernelGGL(k_scatter, dim3(gtile), dim3(AG_BS), 0, s, elems, m, nlb, nn, c->adj_ptr, c->cnt, c->adj);
+    const unsigned grows = static_cast<unsigned>(ceil_div(nn, RBS));
+    if (nn > 0) {
+        if (nlb == 4)
+            hipLaunchKernelGGL(k_rows<4>, dim3(grows), dim3(RBS), 0, s, nn, elems, c->adj_ptr, c->adj, c->cnt, c->info);
+        else
+            hipLaunchKernelGGL(k_rows<3>, dim3(grows), dim3(RBS), 0, s, nn, elems, c->adj_ptr, c->adj, c->cnt, c->info);
+    }
     if ((st = scan(c->cnt, nn, c->row_ptr, c->bsum, c->info + 2, s))) return st;
-    const int64_t nblk = ceil_div(nn, NBS);
-    if (nblk > 0)
-        hipLaunchKernelGGL(k_window_max, dim3(static_cast<unsigned>(ceil_div(nblk, 256))), dim3(256), 0, s, nn,
-                           c->row_ptr, nblk, c->info);
+    for (int which = 0; which < 2 && nn > 0; ++which) {
+        const int nr = which == 0 ? NR_BIG : NR_SMALL;
+        const int64_t nblk = ceil_div(nn, nr);
+        hipLaunchKernelGGL(k_block_stats, dim3(static_cast<unsigned>(ceil_div(nblk, 256))), dim3(256), 0, s, nn, nr,
+                           c->row_ptr, c->adj_ptr, nblk, c->info, 3 + 2 * which);
+    }
     if ((st = launch_check("pf_csr_symbolic"))) return st;
-    int64_t info[4];
+    int64_t info[8];
     PF_HIP_TRY(hipMemcpyAsync(info, c->info, sizeof(info), hipMemcpyDeviceToHost, s));
     PF_HIP_TRY(hipStreamSynchronize(s));
     if (info[0] & ERR_INDEX) return fail(PF_EINDEX, "pf_csr_symbolic: node index out of range in elems");
@@ -472,16 +701,24 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     if (info[2] >= INT32_MAX) return fail(PF_ELIMIT, "pf_csr_symbolic: nnz must be < 2^31");
     const int64_t nnz = info[2];
     if ((st = grow(c->col_idx, c->cap_nnz, nnz))) return st;
-    if (nn > 0)
-        hipLaunchKernelGGL(k_cols, dim3(static_cast<unsigned>(ceil_div(nn, RBS))), dim3(RBS), 0, s, nn, nlb, elems,
-                           c->adj_ptr, c->adj, c->row_ptr, c->col_idx);
+    if (nn > 0) {
+        if (nlb == 4)
+            hipLaunchKernelGGL(k_cols<4>, dim3(grows), dim3(RBS), 0, s, nn, elems, c->adj_ptr, c->adj, c->row_ptr,
+                               c->col_idx, c->pk);
+        else
+            hipLaunchKernelGGL(k_cols<3>, dim3(grows), dim3(RBS), 0, s, nn, elems, c->adj_ptr, c->adj, c->row_ptr,
+                               c->col_idx, c->pk);
+    }
     if ((st = launch_check("pf_csr_symbolic cols"))) return st;
     c->dim = dim;
     c->nlb = nlb;
     c->nn = nn;
     c->ne = ne;
     c->nnz = nnz;
-    c->max_window = static_cast<int>(info[3]);
+    c->wmax_big = static_cast<int>(info[3]);
+    c->emax_big = static_cast<int>(info[4]);
+    c->wmax_small = static_cast<int>(info[5]);
+    c->emax_small = static_cast<int>(info[6]);
     c->built = true;
     return PF_OK;
 }
@@ -502,28 +739,16 @@ pf_status pf_assemble(const pf_csr* c, pf_dtype prec, const double* coords, cons
     if (!c) return fail(PF_EINVAL, "pf_assemble: null handle");
     if (!c->built) return fail(PF_ESTATE, "pf_assemble: structure not built");
     if (c->nn == 0 || c->nnz == 0) return PF_OK;
-    if (!coords || !elems || !valsK) return fail(PF_EINVAL, "pf_assemble: null coords, elems or valsK");
+    if (!coords || !valsK) return fail(PF_EINVAL, "pf_assemble: null coords or valsK");
+    (void)elems;  // the structure carries the connectivity it was built from
     if (prec != PF_F32 && prec != PF_F64) return fail(PF_EDTYPE, "pf_assemble: prec must be PF_F32 or PF_F64");
     hipStream_t s = as_stream(stream);
     Fallback f = make_fallback(fb);
-    const size_t tsz = prec == PF_F64 ? 8 : 4;
-    const size_t need = static_cast<size_t>(c->max_window) * (4 + 2 * tsz);
-    const bool lds = need <= LDS_BYTES;
-    const size_t shm = lds ? need : 0;
-    const unsigned g = static_cast<unsigned>(ceil_div(c->nn, NBS));
-#define PF_NUM(DIM, T, L)                                                                                       \
-    hipLaunchKernelGGL((k_numeric<DIM, T, L>), dim3(g), dim3(NBS), shm, s, c->nn, coords, elems, c->adj_ptr,     \
-                       c->adj, c->row_ptr, c->col_idx, static_cast<const T*>(cK), static_cast<const T*>(cM),     \
-                       static_cast<T*>(valsK), static_cast<T*>(valsM), f, d_counters)
-    if (prec == PF_F32) {
-        if (c->dim == 3) { if (lds) PF_NUM(3, float, true); else PF_NUM(3, float, false); }
-        else { if (lds) PF_NUM(2, float, true); else PF_NUM(2, float, false); }
-    } else {
-        if (c->dim == 3) { if (lds) PF_NUM(3, double, true); else PF_NUM(3, double, false); }
-        else { if (lds) PF_NUM(2, double, true); else PF_NUM(2, double, false); }
-    }
-#undef PF_NUM
-    return launch_check("pf_assemble");
+    if (prec == PF_F32)
+        return c->dim == 3 ? numeric_dispatch<3, float>(c, coords, cK, cM, valsK, valsM, f, d_counters, s)
+                           : numeric_dispatch<2, float>(c, coords, cK, cM, valsK, valsM, f, d_counters, s);
+    return c->dim == 3 ? numeric_dispatch<3, double>(c, coords, cK, cM, valsK, valsM, f, d_counters, s)
+                       : numeric_dispatch<2, double>(c, coords, cK, cM, valsK, valsM, f, d_counters, s);
 }
 
 }  // extern "C"

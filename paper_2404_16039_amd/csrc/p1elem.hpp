@@ -23,13 +23,9 @@ struct P1Geom {
     C absterms;         // sum_j |e_1j c_1j|, numerator of the det-condition
 };
 
+// Geometry from edge vectors already in precision C (u[k] = p_{k+1} - p_origin).
 template <int DIM, typename C>
-__device__ __forceinline__ void p1_geom(const double (&e)[DIM][DIM], P1Geom<DIM, C>& g) {
-    C u[DIM][DIM];
-#pragma unroll
-    for (int k = 0; k < DIM; ++k)
-#pragma unroll
-        for (int i = 0; i < DIM; ++i) u[k][i] = static_cast<C>(e[k][i]);
+__device__ __forceinline__ void p1_geom_edges(const C (&u)[DIM][DIM], P1Geom<DIM, C>& g) {
     if constexpr (DIM == 3) {
         // c_1 = e_2 x e_3 as double-word components: det = e_1 . c_1 within about one ulp
         DW<C> c1[3];
@@ -64,6 +60,17 @@ __device__ __forceinline__ void p1_geom(const double (&e)[DIM][DIM], P1Geom<DIM,
         for (int j = 2; j <= DIM; ++j) s += g.c[j][i];
         g.c[0][i] = -s;
     }
+}
+
+// Geometry from FP64 edge vectors, rounded once to precision C.
+template <int DIM, typename C>
+__device__ __forceinline__ void p1_geom(const double (&e)[DIM][DIM], P1Geom<DIM, C>& g) {
+    C u[DIM][DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k)
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) u[k][i] = static_cast<C>(e[k][i]);
+    p1_geom_edges<DIM, C>(u, g);
 }
 
 template <int DIM>
