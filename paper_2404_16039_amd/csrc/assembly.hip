@@ -6,17 +6,17 @@
 //   1. node -> element adjacency by counting sort: per-tile LDS hash aggregation of the
 //      (element, local node) entries, one global atomic per (tile, node), a scan, and a
 //      scatter into reserved ranges;
-//   2. row lengths: per node, the number of distinct nodes of its elements (per-lane LDS
-//      hash tables, interleaved across lanes so dynamic indices stay conflict-free);
-//   3. scan into row_ptr; then per node: sort the adjacency by element id, write the
-//      sorted distinct neighbours (col_idx), and pack for every adjacency entry the row
-//      positions ("slots") of the element's other nodes.
+//   2. row lengths: per block of rows, the distinct (row, node) pairs of its elements in a
+//      block-wide LDS hash table;
+//   3. scan into row_ptr; then per block again: rank each row's distinct nodes (col_idx,
+//      ascending) and pack for every adjacency entry the row positions ("slots") of the
+//      element's other nodes.
 // Numeric phase (deterministic; see k_numeric): a block owns a contiguous range of rows,
 // hence a contiguous window of the CSR arrays.  Node coordinates are staged in LDS as the
 // FP64 difference vector of every window slot (column node minus row node, rounded once),
 // each adjacency entry recomputes its element's row of K_e and M_e from three of those
-// vectors, and every slot sums its contributions in ascending element order before one
-// coalesced store.  The result is bitwise reproducible and independent of scheduling.
+// vectors, and the contributions are summed exactly (rounded onto a fixed grid first), so
+// the result is bitwise reproducible whatever the order of the atomic adds.
 #include "p1elem.hpp"
 
 #include <algorithm>
@@ -183,7 +183,8 @@ __global__ __launch_bounds__(AG_BS) void k_count(const int32_t* __restrict__ ele
 
 // Scatter (element << 2 | local index) into each node's list.  One global atomic per
 // (tile, node) reserves the tile's range; entries take positions inside it through LDS
-// atomics.  The order inside a list is fixed later (k_cols sorts every list).
+// atomics.  The order inside a list is not fixed: nothing downstream depends on it (the
+// numeric phase sums exactly, so its result does not depend on the entry order).
 __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ elems, int64_t m, int nlb, int64_t nn,
                                                    const int32_t* __restrict__ adj_ptr, int32_t* __restrict__ cursor,
                                                    int32_t* __restrict__ adj) {
@@ -226,184 +227,228 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
 }
 
 // ---------------------------------------------------------------------------- row pattern
-constexpr int RBS = 64;        // rows (= lanes) per block in the row kernels
-constexpr int MAXADJ = 64;     // elements per node
-constexpr int MAXROW = 64;     // nonzeros per row
-constexpr int RHASH = 128;     // per-lane hash table of the distinct neighbours
+// Row patterns are built block-cooperatively: a block of RR rows inserts the (row, node)
+// pairs of all its adjacency entries into one LDS hash table; the first inserter of a pair
+// appends the node to its row's list.  Lists are then ranked (sorted) in parallel and the
+// ranks give both col_idx and, for every adjacency entry, the row positions ("slots") of the
+// element's other nodes.  Every loop is thread-strided over entries or list items, so the
+// work stays uniform across lanes.
+constexpr int RR = 32;           // rows per block in the row-pattern kernels
+constexpr int RT = 256;          // threads per block
+constexpr int MAXADJ = 64;       // elements per node
+constexpr int MAXROW = 64;       // nonzeros per row
+constexpr int RTAB = 2 * RR * MAXROW;  // (row, node) table: load <= 1/2 for valid meshes
+constexpr unsigned long long RKEY_EMPTY = ~0ull;
+constexpr unsigned long long RKEY_ID = (1ull << 36) - 1;  // bits 0-30 node, 31-35 row
 
-// gather the node lists of up to 4 adjacency entries at once (independent loads in flight)
-template <int NLB>
-__device__ __forceinline__ void gather4(const int32_t* __restrict__ elems, const int32_t* __restrict__ keys, int j,
-                                        int L, int (&nd)[4][4]) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        if (j + q < L) {
-            const int64_t e = keys[j + q] >> 2;
-            if constexpr (NLB == 4) {
-                int n4[4];
-                load_nodes<3>(elems, e, n4);
-#pragma unroll
-                for (int k = 0; k < 4; ++k) nd[q][k] = n4[k];
-            } else {
-                int n3[3];
-                load_nodes<2>(elems, e, n3);
-#pragma unroll
-                for (int k = 0; k < 3; ++k) nd[q][k] = n3[k];
-            }
-        }
-    }
+__device__ __forceinline__ int rtab_hash(int r, int32_t v) {
+    const uint32_t x = static_cast<uint32_t>(v) * 2654435761u ^ static_cast<uint32_t>(r) * 0x9E3779B9u;
+    return static_cast<int>(x >> 19) & (RTAB - 1);
 }
 
-// number of distinct neighbours of every node (row lengths), through a per-lane open-
-// addressing table in LDS (interleaved across lanes, so each lane's probes hit its bank)
-template <int NLB>
-__global__ __launch_bounds__(RBS) void k_rows(int64_t nn, const int32_t* __restrict__ elems,
-                                              const int32_t* __restrict__ adj_ptr, const int32_t* __restrict__ adj,
-                                              int32_t* __restrict__ rowlen, int64_t* __restrict__ info) {
-    __shared__ int32_t lds[RHASH * RBS];
-    int32_t* tab = lds + threadIdx.x;
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * RBS + threadIdx.x;
-    if (i >= nn) return;
-    const int32_t b = adj_ptr[i];
-    const int L = adj_ptr[i + 1] - b;
-    if (L > MAXADJ) {
-        atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ADJ));
-        rowlen[i] = 0;
-        return;
+// find or insert (r, v); returns the slot (or -1 when the table is full) and whether this
+// call inserted it
+__device__ __forceinline__ int rtab_insert(unsigned long long* tab, int r, int32_t v, bool& fresh) {
+    const unsigned long long id = (static_cast<unsigned long long>(r) << 31) | static_cast<uint32_t>(v);
+    int h = rtab_hash(r, v);
+    fresh = false;
+    for (int probe = 0; probe < RTAB; ++probe) {
+        unsigned long long cur = tab[h];
+        if (cur == RKEY_EMPTY) {
+            cur = atomicCAS(tab + h, RKEY_EMPTY, id);
+            if (cur == RKEY_EMPTY) {
+                fresh = true;
+                return h;
+            }
+        }
+        if ((cur & RKEY_ID) == id) return h;
+        h = (h + 1) & (RTAB - 1);
     }
-#pragma unroll 8
-    for (int h = 0; h < RHASH; ++h) tab[h * RBS] = -1;
-    int n = 0;
-    for (int j = 0; j < L; j += 4) {
-        int nd[4][4];
-        gather4<NLB>(elems, adj + b, j, L, nd);
+    return -1;
+}
+
+__device__ __forceinline__ int rtab_find(const unsigned long long* tab, int r, int32_t v) {
+    const unsigned long long id = (static_cast<unsigned long long>(r) << 31) | static_cast<uint32_t>(v);
+    int h = rtab_hash(r, v);
+    for (int probe = 0; probe < RTAB; ++probe) {
+        const unsigned long long cur = tab[h];
+        if ((cur & RKEY_ID) == id) return h;
+        if (cur == RKEY_EMPTY) return -1;
+        h = (h + 1) & (RTAB - 1);
+    }
+    return -1;
+}
+
+__device__ __forceinline__ int upper_pos(const int32_t* v, int n, int32_t x) {
+    // last index r in [0, n) with v[r] <= x (v ascending, v[0] <= x)
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (v[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// FULL = false: row lengths only.  FULL = true: col_idx and the packed slots pk (bits 0-1
+// local index a, bits 2+8k .. 9+8k slot of the k-th other node of the element, in local
+// order).
+template <int NLB, bool FULL>
+__global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __restrict__ elems,
+                                                const int32_t* __restrict__ adj_ptr, const int32_t* __restrict__ adj,
+                                                int32_t* __restrict__ rowlen, const int32_t* __restrict__ row_ptr,
+                                                int32_t* __restrict__ col_idx, uint32_t* __restrict__ pk,
+                                                int64_t* __restrict__ info) {
+    __shared__ unsigned long long tab[RTAB];
+    __shared__ int32_t seg[FULL ? RR * MAXROW : 1];
+    __shared__ uint8_t rank_of[FULL ? RR * MAXROW : 1];
+    __shared__ int32_t cnt[RR];
+    __shared__ int32_t ap[RR + 1];
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RR;
+    const int nr = static_cast<int>((r0 + RR < nn) ? RR : nn - r0);
+    for (int h = threadIdx.x; h < RTAB; h += RT) tab[h] = RKEY_EMPTY;
+    if (threadIdx.x < RR) cnt[threadIdx.x] = 0;
+    if (threadIdx.x <= nr) ap[threadIdx.x] = adj_ptr[r0 + threadIdx.x];
+    __syncthreads();
+    const int32_t e0 = ap[0];
+    const int NE = ap[nr] - e0;
+    bool bad = false;
+    if (threadIdx.x < nr && ap[threadIdx.x + 1] - ap[threadIdx.x] > MAXADJ) bad = true;
+    for (int t = threadIdx.x; t < NE; t += RT) {
+        const int r = upper_pos(ap, nr, e0 + t);
+        int nd[4];
+        const int64_t e = adj[e0 + t] >> 2;
+        if constexpr (NLB == 4) load_nodes<3>(elems, e, nd);
+        else load_nodes<2>(elems, e, *reinterpret_cast<int(*)[3]>(nd));
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (j + q >= L) break;
-#pragma unroll
-            for (int k = 0; k < NLB; ++k) {
-                const int32_t v = nd[q][k];
-                int h = static_cast<int>((static_cast<uint32_t>(v) * 2654435761u) >> 25);
-                while (true) {
-                    const int32_t cur = tab[h * RBS];
-                    if (cur == v) break;
-                    if (cur == -1) {
-                        tab[h * RBS] = v;
-                        ++n;
-                        break;
+        for (int k = 0; k < NLB; ++k) {
+            bool fresh;
+            const int h = rtab_insert(tab, r, nd[k], fresh);
+            if (h < 0) {
+                bad = true;
+            } else if (fresh) {
+                const int p = atomicAdd(cnt + r, 1);
+                if (p < MAXROW) {
+                    if constexpr (FULL) {
+                        seg[r * MAXROW + p] = nd[k];
+                        atomicOr(tab + h, static_cast<unsigned long long>(p) << 36);
                     }
-                    h = (h + 1) & (RHASH - 1);
+                } else {
+                    bad = true;
                 }
             }
         }
-        if (n > MAXROW) break;
     }
-    if (n > MAXROW) {
-        atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
-        n = 0;
-    }
-    rowlen[i] = n;
-}
-
-// Per node: sort its adjacency ascending by element (deterministic summation order), build
-// the sorted distinct neighbour list (col_idx), and pack for every adjacency entry its local
-// index a and the row positions ("slots") of the element's other nodes, in local order:
-// bits 0-1 a, bits 2+8k .. 9+8k slot of the k-th other node.
-template <int NLB>
-__global__ __launch_bounds__(RBS) void k_cols(int64_t nn, const int32_t* __restrict__ elems,
-                                              const int32_t* __restrict__ adj_ptr, int32_t* __restrict__ adj,
-                                              const int32_t* __restrict__ row_ptr, int32_t* __restrict__ col_idx,
-                                              uint32_t* __restrict__ pk) {
-    __shared__ int32_t lds[MAXROW * RBS];
-    int32_t* lst = lds + threadIdx.x;
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * RBS + threadIdx.x;
-    if (i >= nn) return;
-    const int32_t b = adj_ptr[i];
-    const int L = adj_ptr[i + 1] - b;
-    // 1. insertion sort of the adjacency keys (L <= MAXADJ, checked by k_rows)
-    for (int j = 0; j < L; ++j) {
-        const int32_t v = adj[b + j];
-        int p = j;
-        while (p > 0 && lst[(p - 1) * RBS] > v) {
-            lst[p * RBS] = lst[(p - 1) * RBS];
-            --p;
+    if (bad) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
+    __syncthreads();
+    if constexpr (!FULL) {
+        if (threadIdx.x < nr) rowlen[r0 + threadIdx.x] = cnt[threadIdx.x] <= MAXROW ? cnt[threadIdx.x] : 0;
+    } else {
+        // rank every row list (ascending node id) and write col_idx
+        for (int q = threadIdx.x; q < nr * MAXROW; q += RT) {
+            const int r = q / MAXROW, p = q - r * MAXROW;
+            const int n = cnt[r];
+            if (p >= n) continue;
+            const int32_t v = seg[q];
+            int rank = 0;
+            for (int j = 0; j < n; ++j) rank += seg[r * MAXROW + j] < v;
+            rank_of[q] = static_cast<uint8_t>(rank);
+            col_idx[row_ptr[r0 + r] + rank] = v;
         }
-        lst[p * RBS] = v;
-    }
-    for (int j = 0; j < L; ++j) adj[b + j] = lst[j * RBS];
-    // 2. sorted distinct neighbours (at most MAXROW, checked by k_rows)
-    int n = 0;
-    for (int j = 0; j < L; j += 4) {
-        int nd[4][4];
-        gather4<NLB>(elems, adj + b, j, L, nd);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (j + q >= L) break;
-#pragma unroll
-            for (int k = 0; k < NLB; ++k) {
-                const int32_t v = nd[q][k];
-                int p = 0;
-                while (p < n && lst[p * RBS] < v) ++p;
-                if (p < n && lst[p * RBS] == v) continue;
-                for (int r = n; r > p; --r) lst[r * RBS] = lst[(r - 1) * RBS];
-                lst[p * RBS] = v;
-                ++n;
-            }
-        }
-    }
-    const int32_t o = row_ptr[i];
-    for (int j = 0; j < n; ++j) col_idx[o + j] = lst[j * RBS];
-    // 3. packed slots of every entry
-    for (int j = 0; j < L; j += 4) {
-        int nd[4][4];
-        gather4<NLB>(elems, adj + b, j, L, nd);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (j + q >= L) break;
-            const int a = adj[b + j + q] & 3;
+        __syncthreads();
+        for (int t = threadIdx.x; t < NE; t += RT) {
+            const int r = upper_pos(ap, nr, e0 + t);
+            const int32_t key = adj[e0 + t];
+            const int a = key & 3;
+            int nd[4];
+            if constexpr (NLB == 4) load_nodes<3>(elems, key >> 2, nd);
+            else load_nodes<2>(elems, key >> 2, *reinterpret_cast<int(*)[3]>(nd));
             uint32_t word = static_cast<uint32_t>(a);
             int k2 = 0;
 #pragma unroll
             for (int k = 0; k < NLB; ++k) {
                 if (k == a) continue;
-                const int32_t v = nd[q][k];
-                int lo = 0, hi = n;
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (lst[mid * RBS] < v) lo = mid + 1;
-                    else hi = mid;
-                }
-                word |= static_cast<uint32_t>(lo) << (2 + 8 * k2);
+                const int h = rtab_find(tab, r, nd[k]);
+                const int p = static_cast<int>((tab[h] >> 36) & 63);
+                word |= static_cast<uint32_t>(rank_of[r * MAXROW + p]) << (2 + 8 * k2);
                 ++k2;
             }
-            pk[b + j + q] = word;
+            pk[e0 + t] = word;
         }
     }
 }
 
 // ---------------------------------------------------------------------------- numeric
 constexpr int NR_BIG = 32;   // rows per block of the numeric kernel
-constexpr int NR_SMALL = 8;  // ... when the big blocks' windows do not fit in LDS
+constexpr int NR_SMALL = 8;  // ... when a big block's window or entries do not fit
 constexpr int NBT = 256;     // threads per block of the numeric kernel
+constexpr int NITEMS = 4;    // adjacency entries per thread (held in registers)
 
 // largest CSR window and adjacency range of one numeric block of `nr` rows, into info[slot],
 // info[slot + 1]
 __global__ void k_block_stats(int64_t nn, int nr, const int32_t* __restrict__ row_ptr,
                               const int32_t* __restrict__ adj_ptr, int64_t nblk, int64_t* __restrict__ info, int slot) {
     const int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (b >= nblk) return;
-    const int64_t r0 = b * nr;
-    const int64_t r1 = (r0 + nr < nn) ? r0 + nr : nn;
-    atomicMax(reinterpret_cast<unsigned long long*>(info + slot),
-              static_cast<unsigned long long>(row_ptr[r1] - row_ptr[r0]));
-    atomicMax(reinterpret_cast<unsigned long long*>(info + slot + 1),
-              static_cast<unsigned long long>(adj_ptr[r1] - adj_ptr[r0]));
+    int w = 0, e = 0;
+    if (b < nblk) {
+        const int64_t r0 = b * nr;
+        const int64_t r1 = (r0 + nr < nn) ? r0 + nr : nn;
+        w = row_ptr[r1] - row_ptr[r0];
+        e = adj_ptr[r1] - adj_ptr[r0];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        w = max(w, __shfl_xor(w, d, 64));
+        e = max(e, __shfl_xor(e, d, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(reinterpret_cast<unsigned long long*>(info + slot), static_cast<unsigned long long>(w));
+        atomicMax(reinterpret_cast<unsigned long long*>(info + slot + 1), static_cast<unsigned long long>(e));
+    }
 }
 
-template <int DIM, typename T>
-constexpr size_t numeric_lds_bytes(int nr, int wmax, int emax) {
-    return static_cast<size_t>(DIM * wmax + (DIM + 2) * emax) * sizeof(T) + static_cast<size_t>(emax) * 4 +
-           static_cast<size_t>(2 * (nr + 1)) * 4 + static_cast<size_t>(wmax);
+// Exact, order-independent accumulation: every contribution is first rounded onto a fixed
+// grid (a power of two chosen from the block's largest contribution), after which sums of
+// up to MAXADJ grid values are exact in the accumulator type, so atomic adds in any order
+// give the same bits.  FP32 contributions: grid 2^-47 of the block maximum, FP64
+// accumulator (53-bit significand).  FP64 contributions: grid 2^-56, int64 accumulator.
+template <typename T>
+struct Exact;
+template <>
+struct Exact<float> {
+    using acc = double;
+    static constexpr int bits = 47;
+    __device__ static acc quant(float x, double s) { return rint(static_cast<double>(x) * s); }
+    __device__ static float back(acc a, double inv) { return static_cast<float>(a * inv); }
+};
+template <>
+struct Exact<double> {
+    using acc = unsigned long long;
+    static constexpr int bits = 56;
+    __device__ static acc quant(double x, double s) {
+        return static_cast<unsigned long long>(static_cast<long long>(rint(x * s)));
+    }
+    __device__ static double back(acc a, double inv) { return static_cast<double>(static_cast<long long>(a)) * inv; }
+};
+
+template <typename T>
+__device__ __forceinline__ double grid_scale(unsigned long long maxbits, double& inv) {
+    double m;
+    if constexpr (sizeof(T) == 4) m = static_cast<double>(__uint_as_float(static_cast<uint32_t>(maxbits)));
+    else m = __longlong_as_double(static_cast<long long>(maxbits));
+    if (!(m > 0.0) || !__builtin_isfinite(m)) {
+        inv = 1.0;
+        return 1.0;
+    }
+    const int e = ilogb(m) + 1;  // m < 2^e
+    inv = ldexp(1.0, e - Exact<T>::bits);
+    return ldexp(1.0, Exact<T>::bits - e);
+}
+
+template <typename T>
+__device__ __forceinline__ unsigned long long abs_bits(T x) {
+    if constexpr (sizeof(T) == 4) return __float_as_uint(fabsf(x));
+    else return static_cast<unsigned long long>(__double_as_longlong(fabs(x)));
 }
 
 // Row of K_e and M_e for the element's node that is the origin of the edge vectors (local
@@ -422,40 +467,40 @@ __device__ __forceinline__ void origin_row(const P1Geom<DIM, C>& g, C ck, C cm, 
     mo = cm * (adet / static_cast<C>(fact_dim<DIM>())) / static_cast<C>((DIM + 1) * (DIM + 2));
 }
 
-__device__ __forceinline__ int upper_pos(const int32_t* v, int n, int32_t x) {
-    // last index r in [0, n) with v[r] <= x (v ascending, v[0] <= x)
-    int lo = 0, hi = n;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (v[mid] <= x) lo = mid;
-        else hi = mid;
-    }
-    return lo;
+template <int DIM, typename T>
+constexpr size_t numeric_lds_bytes(int nr, int wmax) {
+    return static_cast<size_t>(wmax) * (DIM * sizeof(T) + 2 * sizeof(typename Exact<T>::acc) + 1) +
+           static_cast<size_t>(3 * (nr + 1)) * 4 + 16;
 }
 
 // Numeric assembly, NR rows per block:
 //   phase 0  every CSR slot of the block's window gets the edge vector from its row's node to
-//            its column's node (FP64 difference, rounded to T) in LDS;
+//            its column's node (FP64 difference, rounded once to T) in LDS;
 //   phase 1  every adjacency entry (row node = element vertex a) computes, from three edge
 //            vectors read from LDS, its element's row a of K_e and M_e (routed elements are
-//            recomputed from the FP64 coordinates), into an LDS stage;
-//   phase 2  every slot sums its row's stage in ascending element order and stores once.
+//            recomputed from the FP64 coordinates) and keeps it in registers; the block's
+//            largest contribution fixes the grid, and the rounded contributions are added
+//            into LDS accumulators with atomics (exact, so the order does not matter);
+//   phase 2  every slot converts its sum and stores it once (coalesced).
 template <int DIM, typename T, bool COEF, int NR>
 __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __restrict__ coords,
                                                  const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
                                                  const int32_t* __restrict__ adj_ptr, const int32_t* __restrict__ adj,
                                                  const uint32_t* __restrict__ pk, const T* __restrict__ cK,
                                                  const T* __restrict__ cM, T* __restrict__ valsK, T* __restrict__ valsM,
-                                                 Fallback fb, int64_t* d_counters, int wmax, int emax) {
+                                                 Fallback fb, int64_t* d_counters, int wmax) {
     constexpr int NLB = DIM + 1;
+    using A = typename Exact<T>::acc;
     extern __shared__ __align__(16) unsigned char smem[];
-    T* f = reinterpret_cast<T*>(smem);                          // [DIM][wmax]
-    T* kc = f + DIM * wmax;                                     // [emax][NLB]
-    T* mo = kc + NLB * emax;                                    // [emax]
-    uint32_t* pkl = reinterpret_cast<uint32_t*>(mo + emax);     // [emax]
-    int32_t* rp = reinterpret_cast<int32_t*>(pkl + emax);       // [NR + 1]
-    int32_t* ap = rp + (NR + 1);                                // [NR + 1]
-    uint8_t* rloc = reinterpret_cast<uint8_t*>(ap + (NR + 1));  // [wmax]
+    // 8-byte arrays first, so every 64-bit LDS access (the atomics included) is aligned
+    A* accK = reinterpret_cast<A*>(smem);                                   // [wmax]
+    A* accM = accK + wmax;                                                   // [wmax]
+    unsigned long long* maxb = reinterpret_cast<unsigned long long*>(accM + wmax);  // [2]
+    T* f = reinterpret_cast<T*>(maxb + 2);                                   // [DIM][wmax]
+    int32_t* rp = reinterpret_cast<int32_t*>(f + DIM * wmax);                // [NR + 1]
+    int32_t* ap = rp + (NR + 1);                                             // [NR + 1]
+    int32_t* dslot = ap + (NR + 1);                                          // [NR + 1]
+    uint8_t* rowof = reinterpret_cast<uint8_t*>(dslot + (NR + 1));          // [wmax]
 
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * NR;
     const int nr = static_cast<int>((r0 + NR < nn) ? NR : nn - r0);
@@ -463,29 +508,40 @@ __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __res
         rp[threadIdx.x] = row_ptr[r0 + threadIdx.x];
         ap[threadIdx.x] = adj_ptr[r0 + threadIdx.x];
     }
+    if (threadIdx.x < 2) maxb[threadIdx.x] = 0;
     __syncthreads();
     const int32_t w0 = rp[0], e0 = ap[0];
     const int W = rp[nr] - w0, NE = ap[nr] - e0;
 
-    // phase 0: edge vector per slot
+    // phase 0: edge vector per slot, accumulators cleared
     for (int w = threadIdx.x; w < W; w += NBT) {
         const int r = upper_pos(rp, nr, w0 + w);
         const int64_t i = r0 + r;
         const int32_t col = col_idx[w0 + w];
-        rloc[w] = static_cast<uint8_t>(r | ((col == i) ? 128 : 0));
+        rowof[w] = static_cast<uint8_t>(r);
+        if (col == i) dslot[r] = w;
+        accK[w] = A(0);
+        accM[w] = A(0);
 #pragma unroll
         for (int k = 0; k < DIM; ++k)
             f[k * wmax + w] = static_cast<T>(coords[static_cast<int64_t>(col) * DIM + k] - coords[i * DIM + k]);
     }
     __syncthreads();
 
-    // phase 1: row a of every adjacent element
+    // phase 1a: rows of the adjacent elements, in registers
+    T kr[NITEMS][NLB], mr[NITEMS];
+    uint32_t pw[NITEMS];
+    int rr[NITEMS];
+    unsigned long long mk = 0, mm = 0;
     int64_t routed = 0;
-    for (int t = threadIdx.x; t < NE; t += NBT) {
+#pragma unroll
+    for (int q = 0; q < NITEMS; ++q) {
+        const int t = threadIdx.x + q * NBT;
+        rr[q] = -1;
+        if (t >= NE) continue;
         const int r = upper_pos(ap, nr, e0 + t);
         const int s0 = rp[r] - w0;
         const uint32_t p = pk[e0 + t];
-        pkl[t] = p;
         T ck = T(1), cm = T(1);
         if constexpr (COEF) {
             const int64_t e = adj[e0 + t] >> 2;
@@ -497,9 +553,8 @@ __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __res
         for (int k = 0; k < DIM; ++k) {
             const int s = s0 + static_cast<int>((p >> (2 + 8 * k)) & 255);
 #pragma unroll
-            for (int q = 0; q < DIM; ++q) u[k][q] = f[q * wmax + s];
+            for (int c = 0; c < DIM; ++c) u[k][c] = f[c * wmax + s];
         }
-        T krow[NLB], m;
         P1Geom<DIM, T> g;
         p1_geom_edges<DIM, T>(u, g);
         bool route = false;
@@ -512,52 +567,63 @@ __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __res
             for (int k = 0; k < DIM; ++k) {
                 const int64_t col = col_idx[w0 + s0 + static_cast<int>((p >> (2 + 8 * k)) & 255)];
 #pragma unroll
-                for (int q = 0; q < DIM; ++q) ev[k][q] = coords[col * DIM + q] - coords[i * DIM + q];
+                for (int c = 0; c < DIM; ++c) ev[k][c] = coords[col * DIM + c] - coords[i * DIM + c];
             }
             P1Geom<DIM, double> gd;
             p1_geom<DIM, double>(ev, gd);
             double kd[NLB], md;
             origin_row<DIM, double>(gd, ck, cm, kd, md);
 #pragma unroll
-            for (int b = 0; b < NLB; ++b) krow[b] = static_cast<T>(kd[b]);
-            m = static_cast<T>(md);
+            for (int b = 0; b < NLB; ++b) kr[q][b] = static_cast<T>(kd[b]);
+            mr[q] = static_cast<T>(md);
             if ((p & 3) == 0) ++routed;  // count each element once, at its first node's row
         } else {
-            origin_row<DIM, T>(g, ck, cm, krow, m);
+            origin_row<DIM, T>(g, ck, cm, kr[q], mr[q]);
         }
+        pw[q] = p;
+        rr[q] = r;
 #pragma unroll
-        for (int b = 0; b < NLB; ++b) kc[t * NLB + b] = krow[b];
-        mo[t] = m;
+        for (int b = 0; b < NLB; ++b) mk = max(mk, abs_bits(kr[q][b]));
+        mm = max(mm, abs_bits(mr[q] + mr[q]));
     }
     if (routed) count_add(d_counters, 0, routed);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        mk = max(mk, static_cast<unsigned long long>(__shfl_xor(static_cast<long long>(mk), d, 64)));
+        mm = max(mm, static_cast<unsigned long long>(__shfl_xor(static_cast<long long>(mm), d, 64)));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(maxb, mk);
+        atomicMax(maxb + 1, mm);
+    }
     __syncthreads();
 
-    // phase 2: one slot per thread, ascending element order, coalesced stores
-    for (int w = threadIdx.x; w < W; w += NBT) {
-        const int code = rloc[w];
-        const int r = code & 127;
-        const int s = w - (rp[r] - w0);
-        const int t0 = ap[r] - e0, t1 = ap[r + 1] - e0;
-        T sk = T(0), sm = T(0);
-        if (code & 128) {
-            for (int t = t0; t < t1; ++t) {
-                sk += kc[t * NLB];
-                sm += mo[t] + mo[t];
-            }
-        } else {
-            for (int t = t0; t < t1; ++t) {
-                const uint32_t p = pkl[t];
+    // phase 1b: exact accumulation
+    double invK, invM;
+    const double sK = grid_scale<T>(maxb[0], invK);
+    const double sM = grid_scale<T>(maxb[1], invM);
 #pragma unroll
-                for (int k = 0; k < DIM; ++k) {
-                    if (static_cast<int>((p >> (2 + 8 * k)) & 255) == s) {
-                        sk += kc[t * NLB + 1 + k];
-                        sm += mo[t];
-                    }
-                }
-            }
+    for (int q = 0; q < NITEMS; ++q) {
+        const int r = rr[q];
+        if (r < 0) continue;
+        const int s0 = rp[r] - w0;
+        const int sd = dslot[r];
+        atomicAdd(accK + sd, Exact<T>::quant(kr[q][0], sK));
+        atomicAdd(accM + sd, Exact<T>::quant(mr[q] + mr[q], sM));
+        const A qm = Exact<T>::quant(mr[q], sM);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const int s = s0 + static_cast<int>((pw[q] >> (2 + 8 * k)) & 255);
+            atomicAdd(accK + s, Exact<T>::quant(kr[q][1 + k], sK));
+            atomicAdd(accM + s, qm);
         }
-        valsK[w0 + w] = sk;
-        if (valsM) valsM[w0 + w] = sm;
+    }
+    __syncthreads();
+
+    // phase 2: one slot per thread, coalesced stores
+    for (int w = threadIdx.x; w < W; w += NBT) {
+        valsK[w0 + w] = Exact<T>::back(accK[w], invK);
+        if (valsM) valsM[w0 + w] = Exact<T>::back(accM[w], invM);
     }
 }
 
@@ -596,12 +662,12 @@ pf_status scan(const int32_t* in, int64_t n, int32_t* out, int64_t* bsum, int64_
 
 template <int DIM, typename T, bool COEF, int NRB>
 pf_status launch_numeric(const pf_csr* c, const double* coords, const void* cK, const void* cM, void* valsK,
-                         void* valsM, Fallback f, int64_t* ctr, int wmax, int emax, hipStream_t s) {
-    const size_t shm = numeric_lds_bytes<DIM, T>(NRB, wmax, emax);
+                         void* valsM, Fallback f, int64_t* ctr, int wmax, hipStream_t s) {
+    const size_t shm = numeric_lds_bytes<DIM, T>(NRB, wmax);
     const unsigned g = static_cast<unsigned>(ceil_div(c->nn, NRB));
     hipLaunchKernelGGL((k_numeric<DIM, T, COEF, NRB>), dim3(g), dim3(NBT), shm, s, c->nn, coords, c->row_ptr,
                        c->col_idx, c->adj_ptr, c->adj, c->pk, static_cast<const T*>(cK), static_cast<const T*>(cM),
-                       static_cast<T*>(valsK), static_cast<T*>(valsM), f, ctr, wmax, emax);
+                       static_cast<T*>(valsK), static_cast<T*>(valsM), f, ctr, wmax);
     return launch_check("pf_assemble");
 }
 
@@ -609,17 +675,13 @@ template <int DIM, typename T>
 pf_status numeric_dispatch(const pf_csr* c, const double* coords, const void* cK, const void* cM, void* valsK,
                            void* valsM, Fallback f, int64_t* ctr, hipStream_t s) {
     const bool coef = cK || cM;
-    if (numeric_lds_bytes<DIM, T>(NR_BIG, c->wmax_big, c->emax_big) <= LDS_BYTES) {
-        return coef ? launch_numeric<DIM, T, true, NR_BIG>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_big,
-                                                           c->emax_big, s)
-                    : launch_numeric<DIM, T, false, NR_BIG>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_big,
-                                                            c->emax_big, s);
+    if (numeric_lds_bytes<DIM, T>(NR_BIG, c->wmax_big) <= LDS_BYTES && c->emax_big <= NITEMS * NBT) {
+        return coef ? launch_numeric<DIM, T, true, NR_BIG>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_big, s)
+                    : launch_numeric<DIM, T, false, NR_BIG>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_big, s);
     }
     // 8 rows of at most MAXROW nonzeros and MAXADJ elements always fit
-    return coef ? launch_numeric<DIM, T, true, NR_SMALL>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_small,
-                                                         c->emax_small, s)
-                : launch_numeric<DIM, T, false, NR_SMALL>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_small,
-                                                          c->emax_small, s);
+    return coef ? launch_numeric<DIM, T, true, NR_SMALL>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_small, s)
+                : launch_numeric<DIM, T, false, NR_SMALL>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_small, s);
 }
 
 }  // namespace
@@ -677,12 +739,14 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     if (nn > 0) hipLaunchKernelGGL(k_fill_i32, dim3(flat_grid(nn)), dim3(SBS), 0, s, c->cnt, nn, 0);
     if (m > 0)
         hipLaunchKernelGGL(k_scatter, dim3(gtile), dim3(AG_BS), 0, s, elems, m, nlb, nn, c->adj_ptr, c->cnt, c->adj);
-    const unsigned grows = static_cast<unsigned>(ceil_div(nn, RBS));
+    const unsigned grows = static_cast<unsigned>(ceil_div(nn, RR));
     if (nn > 0) {
         if (nlb == 4)
-            hipLaunchKernelGGL(k_rows<4>, dim3(grows), dim3(RBS), 0, s, nn, elems, c->adj_ptr, c->adj, c->cnt, c->info);
+            hipLaunchKernelGGL((k_pattern<4, false>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_ptr, c->adj, c->cnt,
+                               nullptr, nullptr, nullptr, c->info);
         else
-            hipLaunchKernelGGL(k_rows<3>, dim3(grows), dim3(RBS), 0, s, nn, elems, c->adj_ptr, c->adj, c->cnt, c->info);
+            hipLaunchKernelGGL((k_pattern<3, false>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_ptr, c->adj, c->cnt,
+                               nullptr, nullptr, nullptr, c->info);
     }
     if ((st = scan(c->cnt, nn, c->row_ptr, c->bsum, c->info + 2, s))) return st;
     for (int which = 0; which < 2 && nn > 0; ++which) {
@@ -696,18 +760,19 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     PF_HIP_TRY(hipMemcpyAsync(info, c->info, sizeof(info), hipMemcpyDeviceToHost, s));
     PF_HIP_TRY(hipStreamSynchronize(s));
     if (info[0] & ERR_INDEX) return fail(PF_EINDEX, "pf_csr_symbolic: node index out of range in elems");
-    if (info[0] & ERR_ADJ) return fail(PF_ELIMIT, "pf_csr_symbolic: a node belongs to more than 64 elements");
-    if (info[0] & ERR_ROW) return fail(PF_ELIMIT, "pf_csr_symbolic: a row has more than 64 nonzeros");
+    if (info[0] & ERR_ROW)
+        return fail(PF_ELIMIT, "pf_csr_symbolic: a node belongs to more than 64 elements or a row has more than 64 "
+                               "nonzeros");
     if (info[2] >= INT32_MAX) return fail(PF_ELIMIT, "pf_csr_symbolic: nnz must be < 2^31");
     const int64_t nnz = info[2];
     if ((st = grow(c->col_idx, c->cap_nnz, nnz))) return st;
     if (nn > 0) {
         if (nlb == 4)
-            hipLaunchKernelGGL(k_cols<4>, dim3(grows), dim3(RBS), 0, s, nn, elems, c->adj_ptr, c->adj, c->row_ptr,
-                               c->col_idx, c->pk);
+            hipLaunchKernelGGL((k_pattern<4, true>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_ptr, c->adj, nullptr,
+                               c->row_ptr, c->col_idx, c->pk, c->info);
         else
-            hipLaunchKernelGGL(k_cols<3>, dim3(grows), dim3(RBS), 0, s, nn, elems, c->adj_ptr, c->adj, c->row_ptr,
-                               c->col_idx, c->pk);
+            hipLaunchKernelGGL((k_pattern<3, true>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_ptr, c->adj, nullptr,
+                               c->row_ptr, c->col_idx, c->pk, c->info);
     }
     if ((st = launch_check("pf_csr_symbolic cols"))) return st;
     c->dim = dim;
