@@ -408,16 +408,25 @@ __global__ void k_block_stats(int64_t nn, int nr, const int32_t* __restrict__ ro
 }
 
 // Exact, order-independent accumulation: every contribution is first rounded onto a fixed
-// grid (a power of two chosen from the block's largest contribution), after which sums of
-// up to MAXADJ grid values are exact in the accumulator type, so atomic adds in any order
-// give the same bits.  FP32 contributions: grid 2^-47 of the block maximum, FP64
-// accumulator (53-bit significand).  FP64 contributions: grid 2^-56, int64 accumulator.
+// grid, a power of two chosen per CSR slot from the slot's largest contribution (found
+// with an LDS atomic max before any add), after which sums of up to MAXADJ grid values are
+// exact in the accumulator type, so atomic adds in any order give the same bits.  The
+// rounding error of a slot is at most 2^-bits times its largest contribution.
+//   FP32 contributions: grid 2^-47 of the slot maximum, FP64 accumulator (53 bits).
+//   FP64 contributions: grid 2^-56, two's-complement int64 accumulator.
 template <typename T>
 struct Exact;
 template <>
 struct Exact<float> {
     using acc = double;
     static constexpr int bits = 47;
+    __device__ static unsigned long long mag(float x) { return __float_as_uint(fabsf(x)); }
+    // 2^(bits - E) with max < 2^E, E from the FP32 exponent field of the slot maximum
+    __device__ static double scale(unsigned long long mbits, double& inv) {
+        const int E = static_cast<int>((mbits >> 23) & 255) - 126;
+        inv = __longlong_as_double(static_cast<long long>(E - bits + 1023) << 52);
+        return __longlong_as_double(static_cast<long long>(bits - E + 1023) << 52);
+    }
     __device__ static acc quant(float x, double s) { return rint(static_cast<double>(x) * s); }
     __device__ static float back(acc a, double inv) { return static_cast<float>(a * inv); }
 };
@@ -425,31 +434,20 @@ template <>
 struct Exact<double> {
     using acc = unsigned long long;
     static constexpr int bits = 56;
+    __device__ static unsigned long long mag(double x) {
+        return static_cast<unsigned long long>(__double_as_longlong(fabs(x)));
+    }
+    __device__ static double scale(unsigned long long mbits, double& inv) {
+        int E = static_cast<int>((mbits >> 52) & 2047) - 1022;
+        E = E < -960 ? -960 : (E > 960 ? 960 : E);  // keep both powers of two normal
+        inv = __longlong_as_double(static_cast<long long>(E - bits + 1023) << 52);
+        return __longlong_as_double(static_cast<long long>(bits - E + 1023) << 52);
+    }
     __device__ static acc quant(double x, double s) {
         return static_cast<unsigned long long>(static_cast<long long>(rint(x * s)));
     }
     __device__ static double back(acc a, double inv) { return static_cast<double>(static_cast<long long>(a)) * inv; }
 };
-
-template <typename T>
-__device__ __forceinline__ double grid_scale(unsigned long long maxbits, double& inv) {
-    double m;
-    if constexpr (sizeof(T) == 4) m = static_cast<double>(__uint_as_float(static_cast<uint32_t>(maxbits)));
-    else m = __longlong_as_double(static_cast<long long>(maxbits));
-    if (!(m > 0.0) || !__builtin_isfinite(m)) {
-        inv = 1.0;
-        return 1.0;
-    }
-    const int e = ilogb(m) + 1;  // m < 2^e
-    inv = ldexp(1.0, e - Exact<T>::bits);
-    return ldexp(1.0, Exact<T>::bits - e);
-}
-
-template <typename T>
-__device__ __forceinline__ unsigned long long abs_bits(T x) {
-    if constexpr (sizeof(T) == 4) return __float_as_uint(fabsf(x));
-    else return static_cast<unsigned long long>(__double_as_longlong(fabs(x)));
-}
 
 // Row of K_e and M_e for the element's node that is the origin of the edge vectors (local
 // vertex 0 of the geometry): k[b] = cK |T| grad phi_0 . grad phi_b, mo = cM |T| / ((d+1)(d+2)).
@@ -469,8 +467,8 @@ __device__ __forceinline__ void origin_row(const P1Geom<DIM, C>& g, C ck, C cm, 
 
 template <int DIM, typename T>
 constexpr size_t numeric_lds_bytes(int nr, int wmax) {
-    return static_cast<size_t>(wmax) * (DIM * sizeof(T) + 2 * sizeof(typename Exact<T>::acc) + 1) +
-           static_cast<size_t>(3 * (nr + 1)) * 4 + 16;
+    return static_cast<size_t>(wmax) * (DIM * sizeof(T) + 2 * sizeof(typename Exact<T>::acc) + 16 + 1) +
+           static_cast<size_t>(3 * (nr + 1)) * 4;
 }
 
 // Numeric assembly, NR rows per block:
@@ -478,9 +476,9 @@ constexpr size_t numeric_lds_bytes(int nr, int wmax) {
 //            its column's node (FP64 difference, rounded once to T) in LDS;
 //   phase 1  every adjacency entry (row node = element vertex a) computes, from three edge
 //            vectors read from LDS, its element's row a of K_e and M_e (routed elements are
-//            recomputed from the FP64 coordinates) and keeps it in registers; the block's
-//            largest contribution fixes the grid, and the rounded contributions are added
-//            into LDS accumulators with atomics (exact, so the order does not matter);
+//            recomputed from the FP64 coordinates) and keeps it in registers; each slot's
+//            largest contribution fixes that slot's grid, and the rounded contributions
+//            are added into LDS accumulators with atomics (exact: order does not matter);
 //   phase 2  every slot converts its sum and stores it once (coalesced).
 template <int DIM, typename T, bool COEF, int NR>
 __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __restrict__ coords,
@@ -495,8 +493,9 @@ __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __res
     // 8-byte arrays first, so every 64-bit LDS access (the atomics included) is aligned
     A* accK = reinterpret_cast<A*>(smem);                                   // [wmax]
     A* accM = accK + wmax;                                                   // [wmax]
-    unsigned long long* maxb = reinterpret_cast<unsigned long long*>(accM + wmax);  // [2]
-    T* f = reinterpret_cast<T*>(maxb + 2);                                   // [DIM][wmax]
+    unsigned long long* mxK = reinterpret_cast<unsigned long long*>(accM + wmax);  // [wmax]
+    unsigned long long* mxM = mxK + wmax;                                    // [wmax]
+    T* f = reinterpret_cast<T*>(mxM + wmax);                                 // [DIM][wmax]
     int32_t* rp = reinterpret_cast<int32_t*>(f + DIM * wmax);                // [NR + 1]
     int32_t* ap = rp + (NR + 1);                                             // [NR + 1]
     int32_t* dslot = ap + (NR + 1);                                          // [NR + 1]
@@ -508,7 +507,6 @@ __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __res
         rp[threadIdx.x] = row_ptr[r0 + threadIdx.x];
         ap[threadIdx.x] = adj_ptr[r0 + threadIdx.x];
     }
-    if (threadIdx.x < 2) maxb[threadIdx.x] = 0;
     __syncthreads();
     const int32_t w0 = rp[0], e0 = ap[0];
     const int W = rp[nr] - w0, NE = ap[nr] - e0;
@@ -522,17 +520,18 @@ __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __res
         if (col == i) dslot[r] = w;
         accK[w] = A(0);
         accM[w] = A(0);
+        mxK[w] = 0;
+        mxM[w] = 0;
 #pragma unroll
         for (int k = 0; k < DIM; ++k)
             f[k * wmax + w] = static_cast<T>(coords[static_cast<int64_t>(col) * DIM + k] - coords[i * DIM + k]);
     }
     __syncthreads();
 
-    // phase 1a: rows of the adjacent elements, in registers
+    // phase 1a: rows of the adjacent elements, in registers; per-slot maxima
     T kr[NITEMS][NLB], mr[NITEMS];
     uint32_t pw[NITEMS];
     int rr[NITEMS];
-    unsigned long long mk = 0, mm = 0;
     int64_t routed = 0;
 #pragma unroll
     for (int q = 0; q < NITEMS; ++q) {
@@ -582,46 +581,44 @@ __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __res
         }
         pw[q] = p;
         rr[q] = r;
+        const int sd = dslot[r];
+        atomicMax(mxK + sd, Exact<T>::mag(kr[q][0]));
+        atomicMax(mxM + sd, Exact<T>::mag(mr[q] + mr[q]));
+        const unsigned long long mm = Exact<T>::mag(mr[q]);
 #pragma unroll
-        for (int b = 0; b < NLB; ++b) mk = max(mk, abs_bits(kr[q][b]));
-        mm = max(mm, abs_bits(mr[q] + mr[q]));
+        for (int k = 0; k < DIM; ++k) {
+            const int s = s0 + static_cast<int>((p >> (2 + 8 * k)) & 255);
+            atomicMax(mxK + s, Exact<T>::mag(kr[q][1 + k]));
+            atomicMax(mxM + s, mm);
+        }
     }
     if (routed) count_add(d_counters, 0, routed);
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        mk = max(mk, static_cast<unsigned long long>(__shfl_xor(static_cast<long long>(mk), d, 64)));
-        mm = max(mm, static_cast<unsigned long long>(__shfl_xor(static_cast<long long>(mm), d, 64)));
-    }
-    if ((threadIdx.x & 63) == 0) {
-        atomicMax(maxb, mk);
-        atomicMax(maxb + 1, mm);
-    }
     __syncthreads();
 
-    // phase 1b: exact accumulation
-    double invK, invM;
-    const double sK = grid_scale<T>(maxb[0], invK);
-    const double sM = grid_scale<T>(maxb[1], invM);
+    // phase 1b: exact accumulation on each slot's grid
 #pragma unroll
     for (int q = 0; q < NITEMS; ++q) {
         const int r = rr[q];
         if (r < 0) continue;
         const int s0 = rp[r] - w0;
         const int sd = dslot[r];
-        atomicAdd(accK + sd, Exact<T>::quant(kr[q][0], sK));
-        atomicAdd(accM + sd, Exact<T>::quant(mr[q] + mr[q], sM));
-        const A qm = Exact<T>::quant(mr[q], sM);
+        double inv;
+        atomicAdd(accK + sd, Exact<T>::quant(kr[q][0], Exact<T>::scale(mxK[sd], inv)));
+        atomicAdd(accM + sd, Exact<T>::quant(mr[q] + mr[q], Exact<T>::scale(mxM[sd], inv)));
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             const int s = s0 + static_cast<int>((pw[q] >> (2 + 8 * k)) & 255);
-            atomicAdd(accK + s, Exact<T>::quant(kr[q][1 + k], sK));
-            atomicAdd(accM + s, qm);
+            atomicAdd(accK + s, Exact<T>::quant(kr[q][1 + k], Exact<T>::scale(mxK[s], inv)));
+            atomicAdd(accM + s, Exact<T>::quant(mr[q], Exact<T>::scale(mxM[s], inv)));
         }
     }
     __syncthreads();
 
     // phase 2: one slot per thread, coalesced stores
     for (int w = threadIdx.x; w < W; w += NBT) {
+        double invK, invM;
+        Exact<T>::scale(mxK[w], invK);
+        Exact<T>::scale(mxM[w], invM);
         valsK[w0 + w] = Exact<T>::back(accK[w], invK);
         if (valsM) valsM[w0 + w] = Exact<T>::back(accM[w], invM);
     }
