@@ -28,6 +28,7 @@ struct pf_csr {
     int64_t nn = 0, ne = 0, nnz = 0;
     int wmax_big = 0, emax_big = 0;      // largest window / adjacency range of a 32-row block
     int wmax_small = 0, emax_small = 0;  // ... of an 8-row block
+    int max_adj = 0;                     // largest number of elements around one node
     int32_t* adj_ptr = nullptr;
     int32_t* adj = nullptr;   // (element << 2) | local index, sorted per node
     uint32_t* pk = nullptr;   // per adjacency entry: local index and slots of the other nodes
@@ -304,18 +305,29 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
     __shared__ uint8_t rank_of[FULL ? RR * MAXROW : 1];
     __shared__ int32_t cnt[RR];
     __shared__ int32_t ap[RR + 1];
+    __shared__ int32_t maxl;
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RR;
     const int nr = static_cast<int>((r0 + RR < nn) ? RR : nn - r0);
     for (int h = threadIdx.x; h < RTAB; h += RT) tab[h] = RKEY_EMPTY;
     if (threadIdx.x < RR) cnt[threadIdx.x] = 0;
     if (threadIdx.x <= nr) ap[threadIdx.x] = adj_ptr[r0 + threadIdx.x];
+    if (threadIdx.x == 0) maxl = 0;
     __syncthreads();
     const int32_t e0 = ap[0];
     const int NE = ap[nr] - e0;
     bool bad = false;
-    if (threadIdx.x < nr && ap[threadIdx.x + 1] - ap[threadIdx.x] > MAXADJ) bad = true;
-    for (int t = threadIdx.x; t < NE; t += RT) {
-        const int r = upper_pos(ap, nr, e0 + t);
+    if (threadIdx.x < nr) {
+        const int L = ap[threadIdx.x + 1] - ap[threadIdx.x];
+        if (L > MAXADJ) bad = true;
+        atomicMax(&maxl, L);
+    }
+    __syncthreads();
+    // entry j of row r goes to item r + nr * j: the lanes of one instruction work on
+    // different rows, so they insert different (row, node) keys
+    for (int idx = threadIdx.x; idx < nr * maxl; idx += RT) {
+        const int r = idx % nr, j = idx / nr;
+        if (j >= ap[r + 1] - ap[r]) continue;
+        const int t = ap[r] + j - e0;
         int nd[4];
         const int64_t e = adj[e0 + t] >> 2;
         if constexpr (NLB == 4) load_nodes<3>(elems, e, nd);
@@ -357,7 +369,7 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
         }
         __syncthreads();
         for (int t = threadIdx.x; t < NE; t += RT) {
-            const int r = upper_pos(ap, nr, e0 + t);
+            const int r = upper_pos(ap, nr, e0 + t);  // different keys per lane here: no contention
             const int32_t key = adj[e0 + t];
             const int a = key & 3;
             int nd[4];
@@ -383,27 +395,48 @@ constexpr int NR_BIG = 32;   // rows per block of the numeric kernel
 constexpr int NR_SMALL = 8;  // ... when a big block's window or entries do not fit
 constexpr int NBT = 256;     // threads per block of the numeric kernel
 constexpr int NITEMS = 4;    // adjacency entries per thread (held in registers)
+static_assert(MAXADJ <= NITEMS * NBT / NR_SMALL, "the small numeric blocks must cover any admissible row");
 
-// largest CSR window and adjacency range of one numeric block of `nr` rows, into info[slot],
-// info[slot + 1]
-__global__ void k_block_stats(int64_t nn, int nr, const int32_t* __restrict__ row_ptr,
-                              const int32_t* __restrict__ adj_ptr, int64_t nblk, int64_t* __restrict__ info, int slot) {
-    const int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    int w = 0, e = 0;
-    if (b < nblk) {
+// largest CSR window and adjacency range of one numeric block of `nr` rows, and the largest
+// adjacency count of a row, into info[slot], info[slot + 1], info[7].  Grid-strided, then
+// reduced in the wave and in the block: one global atomic per block.
+__global__ __launch_bounds__(256) void k_block_stats(int64_t nn, int nr, const int32_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ adj_ptr, int64_t nblk,
+                                                     int64_t* __restrict__ info, int slot) {
+    __shared__ int red[3][4];
+    int w = 0, e = 0, l = 0;
+    for (int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; b < nblk;
+         b += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int64_t r0 = b * nr;
         const int64_t r1 = (r0 + nr < nn) ? r0 + nr : nn;
-        w = row_ptr[r1] - row_ptr[r0];
-        e = adj_ptr[r1] - adj_ptr[r0];
+        w = max(w, row_ptr[r1] - row_ptr[r0]);
+        e = max(e, adj_ptr[r1] - adj_ptr[r0]);
+        for (int64_t i = r0; i < r1; ++i) l = max(l, adj_ptr[i + 1] - adj_ptr[i]);
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         w = max(w, __shfl_xor(w, d, 64));
         e = max(e, __shfl_xor(e, d, 64));
+        l = max(l, __shfl_xor(l, d, 64));
     }
     if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = w;
+        red[1][threadIdx.x >> 6] = e;
+        red[2][threadIdx.x >> 6] = l;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < 4; ++q) {
+            w = max(w, red[0][q]);
+            e = max(e, red[1][q]);
+            l = max(l, red[2][q]);
+        }
+        w = max(w, red[0][0]);
+        e = max(e, red[1][0]);
+        l = max(l, red[2][0]);
         atomicMax(reinterpret_cast<unsigned long long*>(info + slot), static_cast<unsigned long long>(w));
         atomicMax(reinterpret_cast<unsigned long long*>(info + slot + 1), static_cast<unsigned long long>(e));
+        atomicMax(reinterpret_cast<unsigned long long*>(info + 7), static_cast<unsigned long long>(l));
     }
 }
 
@@ -535,10 +568,14 @@ __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __res
     int64_t routed = 0;
 #pragma unroll
     for (int q = 0; q < NITEMS; ++q) {
-        const int t = threadIdx.x + q * NBT;
+        // entry j of row r is item r + nr * j: the lanes of one instruction work on different
+        // rows, so their LDS atomics hit different slots (the host guarantees that
+        // NITEMS * NBT / NR covers the longest adjacency list)
+        const int idx = threadIdx.x + q * NBT;
+        const int r = idx % nr, j = idx / nr;
         rr[q] = -1;
-        if (t >= NE) continue;
-        const int r = upper_pos(ap, nr, e0 + t);
+        if (j >= ap[r + 1] - ap[r]) continue;
+        const int t = ap[r] + j - e0;
         const int s0 = rp[r] - w0;
         const uint32_t p = pk[e0 + t];
         T ck = T(1), cm = T(1);
@@ -672,11 +709,11 @@ template <int DIM, typename T>
 pf_status numeric_dispatch(const pf_csr* c, const double* coords, const void* cK, const void* cM, void* valsK,
                            void* valsM, Fallback f, int64_t* ctr, hipStream_t s) {
     const bool coef = cK || cM;
-    if (numeric_lds_bytes<DIM, T>(NR_BIG, c->wmax_big) <= LDS_BYTES && c->emax_big <= NITEMS * NBT) {
+    if (numeric_lds_bytes<DIM, T>(NR_BIG, c->wmax_big) <= LDS_BYTES && c->max_adj <= NITEMS * NBT / NR_BIG) {
         return coef ? launch_numeric<DIM, T, true, NR_BIG>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_big, s)
                     : launch_numeric<DIM, T, false, NR_BIG>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_big, s);
     }
-    // 8 rows of at most MAXROW nonzeros and MAXADJ elements always fit
+    // 8 rows of at most MAXROW nonzeros and MAXADJ (<= NITEMS * NBT / NR_SMALL) elements always fit
     return coef ? launch_numeric<DIM, T, true, NR_SMALL>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_small, s)
                 : launch_numeric<DIM, T, false, NR_SMALL>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_small, s);
 }
@@ -749,8 +786,9 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     for (int which = 0; which < 2 && nn > 0; ++which) {
         const int nr = which == 0 ? NR_BIG : NR_SMALL;
         const int64_t nblk = ceil_div(nn, nr);
-        hipLaunchKernelGGL(k_block_stats, dim3(static_cast<unsigned>(ceil_div(nblk, 256))), dim3(256), 0, s, nn, nr,
-                           c->row_ptr, c->adj_ptr, nblk, c->info, 3 + 2 * which);
+        const unsigned g = static_cast<unsigned>(std::min<int64_t>(ceil_div(nblk, 256), 128));
+        hipLaunchKernelGGL(k_block_stats, dim3(g), dim3(256), 0, s, nn, nr, c->row_ptr, c->adj_ptr, nblk, c->info,
+                           3 + 2 * which);
     }
     if ((st = launch_check("pf_csr_symbolic"))) return st;
     int64_t info[8];
@@ -781,6 +819,7 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     c->emax_big = static_cast<int>(info[4]);
     c->wmax_small = static_cast<int>(info[5]);
     c->emax_small = static_cast<int>(info[6]);
+    c->max_adj = static_cast<int>(info[7]);
     c->built = true;
     return PF_OK;
 }
