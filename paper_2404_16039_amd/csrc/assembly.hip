@@ -138,13 +138,14 @@ __global__ __launch_bounds__(SBS) void k_scan_apply(const int32_t* __restrict__ 
 // appears several times in the tile (neighbouring elements share nodes) costs one global
 // atomic per tile instead of one per entry.
 constexpr int AG_BS = 256;
-constexpr int AG_ITEMS = 16;
+constexpr int AG_ITEMS = 4;
 constexpr int AG_TILE = AG_BS * AG_ITEMS;
 constexpr int AG_HASH = 2 * AG_TILE;  // load factor <= 1/2, probing always ends
 
 __device__ __forceinline__ int ag_hash(int32_t node) {
-    return static_cast<int>((static_cast<uint32_t>(node) * 2654435761u) >> (32 - 13)) & (AG_HASH - 1);
+    return static_cast<int>((static_cast<uint32_t>(node) * 2654435761u) >> (32 - 11)) & (AG_HASH - 1);
 }
+static_assert(AG_HASH == 2048, "ag_hash yields 11 bits");
 
 // insert `node` (or find it) in the block's table; returns its slot
 __device__ __forceinline__ int ag_insert(int32_t* keys, int32_t node) {
@@ -228,54 +229,51 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
 }
 
 // ---------------------------------------------------------------------------- row pattern
-// Row patterns are built block-cooperatively: a block of RR rows inserts the (row, node)
-// pairs of all its adjacency entries into one LDS hash table; the first inserter of a pair
-// appends the node to its row's list.  Lists are then ranked (sorted) in parallel and the
+// Row patterns are built block-cooperatively: a block of RR rows inserts the nodes of all
+// its adjacency entries into per-row open-addressing tables in LDS; the first inserter of a
+// node appends it to its row's list.  Lists are then ranked (sorted) in parallel and the
 // ranks give both col_idx and, for every adjacency entry, the row positions ("slots") of the
-// element's other nodes.  Every loop is thread-strided over entries or list items, so the
-// work stays uniform across lanes.
+// element's other nodes.  Entries are dealt to lanes row-interleaved (entry j of row r is
+// item r + nr j), so the lanes of one instruction insert into different rows' tables.
 constexpr int RR = 32;           // rows per block in the row-pattern kernels
 constexpr int RT = 256;          // threads per block
 constexpr int MAXADJ = 64;       // elements per node
 constexpr int MAXROW = 64;       // nonzeros per row
-constexpr int RTAB = 2 * RR * MAXROW;  // (row, node) table: load <= 1/2 for valid meshes
-constexpr unsigned long long RKEY_EMPTY = ~0ull;
-constexpr unsigned long long RKEY_ID = (1ull << 36) - 1;  // bits 0-30 node, 31-35 row
+constexpr int RSUB = 2 * MAXROW; // slots of one row's table: load <= 1/2 for admissible rows
+constexpr int RBATCH = 4;        // entries gathered together per thread (independent loads)
 
-__device__ __forceinline__ int rtab_hash(int r, int32_t v) {
-    const uint32_t x = static_cast<uint32_t>(v) * 2654435761u ^ static_cast<uint32_t>(r) * 0x9E3779B9u;
-    return static_cast<int>(x >> 19) & (RTAB - 1);
+__device__ __forceinline__ int rsub_hash(int32_t v) {
+    return static_cast<int>((static_cast<uint32_t>(v) * 2654435761u) >> 25);  // 7 bits
 }
+static_assert(RSUB == 128, "rsub_hash yields 7 bits");
 
-// find or insert (r, v); returns the slot (or -1 when the table is full) and whether this
-// call inserted it
-__device__ __forceinline__ int rtab_insert(unsigned long long* tab, int r, int32_t v, bool& fresh) {
-    const unsigned long long id = (static_cast<unsigned long long>(r) << 31) | static_cast<uint32_t>(v);
-    int h = rtab_hash(r, v);
+// find or insert v in a row table; returns the slot (or -1 when the table is full) and
+// whether this call inserted it
+__device__ __forceinline__ int rsub_insert(int32_t* tab, int32_t v, bool& fresh) {
+    int h = rsub_hash(v);
     fresh = false;
-    for (int probe = 0; probe < RTAB; ++probe) {
-        unsigned long long cur = tab[h];
-        if (cur == RKEY_EMPTY) {
-            cur = atomicCAS(tab + h, RKEY_EMPTY, id);
-            if (cur == RKEY_EMPTY) {
+    for (int probe = 0; probe < RSUB; ++probe) {
+        int32_t cur = tab[h];
+        if (cur == -1) {
+            cur = atomicCAS(tab + h, -1, v);
+            if (cur == -1) {
                 fresh = true;
                 return h;
             }
         }
-        if ((cur & RKEY_ID) == id) return h;
-        h = (h + 1) & (RTAB - 1);
+        if (cur == v) return h;
+        h = (h + 1) & (RSUB - 1);
     }
     return -1;
 }
 
-__device__ __forceinline__ int rtab_find(const unsigned long long* tab, int r, int32_t v) {
-    const unsigned long long id = (static_cast<unsigned long long>(r) << 31) | static_cast<uint32_t>(v);
-    int h = rtab_hash(r, v);
-    for (int probe = 0; probe < RTAB; ++probe) {
-        const unsigned long long cur = tab[h];
-        if ((cur & RKEY_ID) == id) return h;
-        if (cur == RKEY_EMPTY) return -1;
-        h = (h + 1) & (RTAB - 1);
+__device__ __forceinline__ int rsub_find(const int32_t* tab, int32_t v) {
+    int h = rsub_hash(v);
+    for (int probe = 0; probe < RSUB; ++probe) {
+        const int32_t cur = tab[h];
+        if (cur == v) return h;
+        if (cur == -1) return -1;
+        h = (h + 1) & (RSUB - 1);
     }
     return -1;
 }
@@ -291,6 +289,20 @@ __device__ __forceinline__ int upper_pos(const int32_t* v, int n, int32_t x) {
     return lo;
 }
 
+template <int NLB>
+__device__ __forceinline__ void elem_nodes(const int32_t* __restrict__ elems, int64_t e, int (&nd)[4]) {
+    if constexpr (NLB == 4) {
+        load_nodes<3>(elems, e, nd);
+    } else {
+        int n3[3];
+        load_nodes<2>(elems, e, n3);
+        nd[0] = n3[0];
+        nd[1] = n3[1];
+        nd[2] = n3[2];
+        nd[3] = -1;
+    }
+}
+
 // FULL = false: row lengths only.  FULL = true: col_idx and the packed slots pk (bits 0-1
 // local index a, bits 2+8k .. 9+8k slot of the k-th other node of the element, in local
 // order).
@@ -300,21 +312,21 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
                                                 int32_t* __restrict__ rowlen, const int32_t* __restrict__ row_ptr,
                                                 int32_t* __restrict__ col_idx, uint32_t* __restrict__ pk,
                                                 int64_t* __restrict__ info) {
-    __shared__ unsigned long long tab[RTAB];
-    __shared__ int32_t seg[FULL ? RR * MAXROW : 1];
-    __shared__ uint8_t rank_of[FULL ? RR * MAXROW : 1];
+    __shared__ int32_t tab[RR * RSUB];                  // node ids, -1 empty
+    __shared__ uint8_t pos_of[FULL ? RR * RSUB : 1];     // list position of each table slot
+    __shared__ int32_t seg[FULL ? RR * MAXROW : 1];      // each row's nodes, insertion order
+    __shared__ uint8_t rank_of[FULL ? RR * MAXROW : 1];  // rank of each list item
     __shared__ int32_t cnt[RR];
     __shared__ int32_t ap[RR + 1];
     __shared__ int32_t maxl;
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RR;
     const int nr = static_cast<int>((r0 + RR < nn) ? RR : nn - r0);
-    for (int h = threadIdx.x; h < RTAB; h += RT) tab[h] = RKEY_EMPTY;
+    for (int h = threadIdx.x; h < RR * RSUB; h += RT) tab[h] = -1;
     if (threadIdx.x < RR) cnt[threadIdx.x] = 0;
     if (threadIdx.x <= nr) ap[threadIdx.x] = adj_ptr[r0 + threadIdx.x];
     if (threadIdx.x == 0) maxl = 0;
     __syncthreads();
     const int32_t e0 = ap[0];
-    const int NE = ap[nr] - e0;
     bool bad = false;
     if (threadIdx.x < nr) {
         const int L = ap[threadIdx.x + 1] - ap[threadIdx.x];
@@ -322,31 +334,41 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
         atomicMax(&maxl, L);
     }
     __syncthreads();
-    // entry j of row r goes to item r + nr * j: the lanes of one instruction work on
-    // different rows, so they insert different (row, node) keys
-    for (int idx = threadIdx.x; idx < nr * maxl; idx += RT) {
-        const int r = idx % nr, j = idx / nr;
-        if (j >= ap[r + 1] - ap[r]) continue;
-        const int t = ap[r] + j - e0;
-        int nd[4];
-        const int64_t e = adj[e0 + t] >> 2;
-        if constexpr (NLB == 4) load_nodes<3>(elems, e, nd);
-        else load_nodes<2>(elems, e, *reinterpret_cast<int(*)[3]>(nd));
+    const int items = nr * maxl;
+    for (int base = threadIdx.x; base < items; base += RT * RBATCH) {
+        int nd[RBATCH][4];
+        int rq[RBATCH];
 #pragma unroll
-        for (int k = 0; k < NLB; ++k) {
-            bool fresh;
-            const int h = rtab_insert(tab, r, nd[k], fresh);
-            if (h < 0) {
-                bad = true;
-            } else if (fresh) {
-                const int p = atomicAdd(cnt + r, 1);
-                if (p < MAXROW) {
-                    if constexpr (FULL) {
-                        seg[r * MAXROW + p] = nd[k];
-                        atomicOr(tab + h, static_cast<unsigned long long>(p) << 36);
-                    }
-                } else {
+        for (int b = 0; b < RBATCH; ++b) {
+            const int idx = base + b * RT;
+            rq[b] = -1;
+            if (idx >= items) continue;
+            const int r = idx % nr, j = idx / nr;
+            if (j >= ap[r + 1] - ap[r]) continue;
+            rq[b] = r;
+            elem_nodes<NLB>(elems, adj[ap[r] + j] >> 2, nd[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < RBATCH; ++b) {
+            const int r = rq[b];
+            if (r < 0) continue;
+            int32_t* rt = tab + r * RSUB;
+#pragma unroll
+            for (int k = 0; k < NLB; ++k) {
+                bool fresh;
+                const int h = rsub_insert(rt, nd[b][k], fresh);
+                if (h < 0) {
                     bad = true;
+                } else if (fresh) {
+                    const int p = atomicAdd(cnt + r, 1);
+                    if (p < MAXROW) {
+                        if constexpr (FULL) {
+                            seg[r * MAXROW + p] = nd[b][k];
+                            pos_of[r * RSUB + h] = static_cast<uint8_t>(p);
+                        }
+                    } else {
+                        bad = true;
+                    }
                 }
             }
         }
@@ -368,20 +390,20 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
             col_idx[row_ptr[r0 + r] + rank] = v;
         }
         __syncthreads();
+        const int NE = ap[nr] - e0;
         for (int t = threadIdx.x; t < NE; t += RT) {
-            const int r = upper_pos(ap, nr, e0 + t);  // different keys per lane here: no contention
+            const int r = upper_pos(ap, nr, e0 + t);
             const int32_t key = adj[e0 + t];
             const int a = key & 3;
             int nd[4];
-            if constexpr (NLB == 4) load_nodes<3>(elems, key >> 2, nd);
-            else load_nodes<2>(elems, key >> 2, *reinterpret_cast<int(*)[3]>(nd));
+            elem_nodes<NLB>(elems, key >> 2, nd);
             uint32_t word = static_cast<uint32_t>(a);
             int k2 = 0;
 #pragma unroll
             for (int k = 0; k < NLB; ++k) {
                 if (k == a) continue;
-                const int h = rtab_find(tab, r, nd[k]);
-                const int p = static_cast<int>((tab[h] >> 36) & 63);
+                const int h = rsub_find(tab + r * RSUB, nd[k]);
+                const int p = h >= 0 ? pos_of[r * RSUB + h] : 0;  // always found when no error was raised
                 word |= static_cast<uint32_t>(rank_of[r * MAXROW + p]) << (2 + 8 * k2);
                 ++k2;
             }
