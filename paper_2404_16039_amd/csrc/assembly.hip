@@ -317,6 +317,7 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
     __shared__ int32_t seg[FULL ? RR * MAXROW : 1];      // each row's nodes, insertion order
     __shared__ uint8_t rank_of[FULL ? RR * MAXROW : 1];  // rank of each list item
     __shared__ int32_t cnt[RR];
+    __shared__ int32_t cpre[FULL ? RR + 1 : 1];
     __shared__ int32_t ap[RR + 1];
     __shared__ int32_t maxl;
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RR;
@@ -378,15 +379,25 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
     if constexpr (!FULL) {
         if (threadIdx.x < nr) rowlen[r0 + threadIdx.x] = cnt[threadIdx.x] <= MAXROW ? cnt[threadIdx.x] : 0;
     } else {
-        // rank every row list (ascending node id) and write col_idx
-        for (int q = threadIdx.x; q < nr * MAXROW; q += RT) {
-            const int r = q / MAXROW, p = q - r * MAXROW;
+        // rank every row list (ascending node id) and write col_idx; only existing
+        // (row, position) items are dealt out
+        if (threadIdx.x == 0) {
+            int acc = 0;
+            for (int r = 0; r < nr; ++r) {
+                cpre[r] = acc;
+                acc += cnt[r] <= MAXROW ? cnt[r] : MAXROW;
+            }
+            cpre[nr] = acc;
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < cpre[nr]; q += RT) {
+            const int r = upper_pos(cpre, nr, q);
+            const int p = q - cpre[r];
             const int n = cnt[r];
-            if (p >= n) continue;
-            const int32_t v = seg[q];
+            const int32_t v = seg[r * MAXROW + p];
             int rank = 0;
             for (int j = 0; j < n; ++j) rank += seg[r * MAXROW + j] < v;
-            rank_of[q] = static_cast<uint8_t>(rank);
+            rank_of[r * MAXROW + p] = static_cast<uint8_t>(rank);
             col_idx[row_ptr[r0 + r] + rank] = v;
         }
         __syncthreads();
@@ -469,39 +480,40 @@ __global__ __launch_bounds__(256) void k_block_stats(int64_t nn, int nr, const i
 // rounding error of a slot is at most 2^-bits times its largest contribution.
 //   FP32 contributions: grid 2^-47 of the slot maximum, FP64 accumulator (53 bits).
 //   FP64 contributions: grid 2^-56, two's-complement int64 accumulator.
+// Only the maximum's exponent matters, so maxima are kept as the high 32 bits of |x|.
 template <typename T>
 struct Exact;
 template <>
 struct Exact<float> {
     using acc = double;
     static constexpr int bits = 47;
-    __device__ static unsigned long long mag(float x) { return __float_as_uint(fabsf(x)); }
-    // 2^(bits - E) with max < 2^E, E from the FP32 exponent field of the slot maximum
-    __device__ static double scale(unsigned long long mbits, double& inv) {
-        const int E = static_cast<int>((mbits >> 23) & 255) - 126;
-        inv = __longlong_as_double(static_cast<long long>(E - bits + 1023) << 52);
-        return __longlong_as_double(static_cast<long long>(bits - E + 1023) << 52);
-    }
-    __device__ static acc quant(float x, double s) { return rint(static_cast<double>(x) * s); }
-    __device__ static float back(acc a, double inv) { return static_cast<float>(a * inv); }
+    __device__ static uint32_t mag(float x) { return __float_as_uint(fabsf(x)); }
+    // shift = bits - E with max < 2^E
+    __device__ static int shift(uint32_t m) { return bits - (static_cast<int>((m >> 23) & 255) - 126); }
+    __device__ static acc quant(float x, int sh) { return rint(ldexp(static_cast<double>(x), sh)); }
+    __device__ static float back(acc a, int sh) { return static_cast<float>(ldexp(a, -sh)); }
 };
 template <>
 struct Exact<double> {
     using acc = unsigned long long;
     static constexpr int bits = 56;
-    __device__ static unsigned long long mag(double x) {
-        return static_cast<unsigned long long>(__double_as_longlong(fabs(x)));
+    __device__ static uint32_t mag(double x) {
+        return static_cast<uint32_t>(static_cast<unsigned long long>(__double_as_longlong(fabs(x))) >> 32);
     }
-    __device__ static double scale(unsigned long long mbits, double& inv) {
-        int E = static_cast<int>((mbits >> 52) & 2047) - 1022;
-        E = E < -960 ? -960 : (E > 960 ? 960 : E);  // keep both powers of two normal
-        inv = __longlong_as_double(static_cast<long long>(E - bits + 1023) << 52);
-        return __longlong_as_double(static_cast<long long>(bits - E + 1023) << 52);
+    __device__ static int shift(uint32_t m) {
+        int E = static_cast<int>((m >> 20) & 2047) - 1022;
+        E = E < -960 ? -960 : (E > 960 ? 960 : E);  // keep 2^shift and 2^-shift normal
+        return bits - E;
     }
-    __device__ static acc quant(double x, double s) {
-        return static_cast<unsigned long long>(static_cast<long long>(rint(x * s)));
+    __device__ static acc quant(double x, int sh) {
+        return static_cast<unsigned long long>(static_cast<long long>(rint(ldexp(x, sh))));
     }
-    __device__ static double back(acc a, double inv) { return static_cast<double>(static_cast<long long>(a)) * inv; }
+    __device__ static double back(acc a, int sh) { return ldexp(static_cast<double>(static_cast<long long>(a)), -sh); }
+};
+
+template <typename T>
+struct alignas(16) Vec4 {  // 16-byte LDS reads; the layout keeps Vec4 arrays 16-byte aligned
+    T x, y, z, w;
 };
 
 // Row of K_e and M_e for the element's node that is the origin of the edge vectors (local
@@ -517,13 +529,33 @@ __device__ __forceinline__ void origin_row(const P1Geom<DIM, C>& g, C ck, C cm, 
         for (int q = 1; q < DIM; ++q) s = fmaT(g.c[0][q], g.c[b][q], s);
         k[b] = kf * s;
     }
-    mo = cm * (adet / static_cast<C>(fact_dim<DIM>())) / static_cast<C>((DIM + 1) * (DIM + 2));
+    mo = cm * adet * static_cast<C>(1.0 / (fact_dim<DIM>() * (DIM + 1) * (DIM + 2)));
+}
+
+// FP32 routing test with thresholds already rounded to FP32
+__device__ __forceinline__ bool route32(float det, float absterms, float tau_abs, float tau_cond, int enable) {
+    const float ad = fabsf(det);
+    return enable && (!__builtin_isfinite(det) || !__builtin_isfinite(absterms) || ad < tau_abs ||
+                      absterms > tau_cond * ad);
+}
+
+// item index -> (row, position) for row-interleaved dealing; full blocks divide by a
+// compile-time constant
+template <int NR>
+__device__ __forceinline__ void split_item(int idx, int nr, int& r, int& j) {
+    if (nr == NR) {
+        r = idx % NR;
+        j = idx / NR;
+    } else {
+        r = idx % nr;
+        j = idx / nr;
+    }
 }
 
 template <int DIM, typename T>
 constexpr size_t numeric_lds_bytes(int nr, int wmax) {
-    return static_cast<size_t>(wmax) * (DIM * sizeof(T) + 2 * sizeof(typename Exact<T>::acc) + 16 + 1) +
-           static_cast<size_t>(3 * (nr + 1)) * 4;
+    return static_cast<size_t>(wmax) * (2 * sizeof(typename Exact<T>::acc) + sizeof(Vec4<T>) + 8) +
+           static_cast<size_t>(3 * (nr + 1) + 1) * 4;
 }
 
 // Numeric assembly, NR rows per block:
@@ -535,6 +567,8 @@ constexpr size_t numeric_lds_bytes(int nr, int wmax) {
 //            largest contribution fixes that slot's grid, and the rounded contributions
 //            are added into LDS accumulators with atomics (exact: order does not matter);
 //   phase 2  every slot converts its sum and stores it once (coalesced).
+// Entries and slots are dealt row-interleaved (item r + nr j), so the lanes of one
+// instruction work on different rows and their LDS atomics hit different addresses.
 template <int DIM, typename T, bool COEF, int NR>
 __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __restrict__ coords,
                                                  const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
@@ -545,16 +579,16 @@ __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __res
     constexpr int NLB = DIM + 1;
     using A = typename Exact<T>::acc;
     extern __shared__ __align__(16) unsigned char smem[];
-    // 8-byte arrays first, so every 64-bit LDS access (the atomics included) is aligned
-    A* accK = reinterpret_cast<A*>(smem);                                   // [wmax]
-    A* accM = accK + wmax;                                                   // [wmax]
-    unsigned long long* mxK = reinterpret_cast<unsigned long long*>(accM + wmax);  // [wmax]
-    unsigned long long* mxM = mxK + wmax;                                    // [wmax]
-    T* f = reinterpret_cast<T*>(mxM + wmax);                                 // [DIM][wmax]
-    int32_t* rp = reinterpret_cast<int32_t*>(f + DIM * wmax);                // [NR + 1]
-    int32_t* ap = rp + (NR + 1);                                             // [NR + 1]
-    int32_t* dslot = ap + (NR + 1);                                          // [NR + 1]
-    uint8_t* rowof = reinterpret_cast<uint8_t*>(dslot + (NR + 1));          // [wmax]
+    // widest types first, so every LDS access is naturally aligned
+    A* accK = reinterpret_cast<A*>(smem);                       // [wmax]
+    A* accM = accK + wmax;                                       // [wmax]
+    Vec4<T>* f = reinterpret_cast<Vec4<T>*>(accM + wmax);        // [wmax] edge vector per slot
+    int32_t* shK = reinterpret_cast<int32_t*>(f + wmax);         // [wmax] max bits, then shift
+    int32_t* shM = shK + wmax;                                   // [wmax]
+    int32_t* rp = shM + wmax;                                    // [NR + 1]
+    int32_t* ap = rp + (NR + 1);                                 // [NR + 1]
+    int32_t* dslot = ap + (NR + 1);                              // [NR + 1]
+    int32_t* maxlen = dslot + (NR + 1);                          // [1]
 
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * NR;
     const int nr = static_cast<int>((r0 + NR < nn) ? NR : nn - r0);
@@ -562,61 +596,69 @@ __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __res
         rp[threadIdx.x] = row_ptr[r0 + threadIdx.x];
         ap[threadIdx.x] = adj_ptr[r0 + threadIdx.x];
     }
+    if (threadIdx.x == 0) *maxlen = 0;
     __syncthreads();
+    if (threadIdx.x < nr) atomicMax(maxlen, rp[threadIdx.x + 1] - rp[threadIdx.x]);
     const int32_t w0 = rp[0], e0 = ap[0];
-    const int W = rp[nr] - w0, NE = ap[nr] - e0;
+    const int W = rp[nr] - w0;
+    __syncthreads();
 
-    // phase 0: edge vector per slot, accumulators cleared
-    for (int w = threadIdx.x; w < W; w += NBT) {
-        const int r = upper_pos(rp, nr, w0 + w);
+    // phase 0: edge vector per slot (row-interleaved, no search), accumulators cleared
+    for (int idx = threadIdx.x; idx < nr * *maxlen; idx += NBT) {
+        int r, k;
+        split_item<NR>(idx, nr, r, k);
+        if (k >= rp[r + 1] - rp[r]) continue;
+        const int w = rp[r] - w0 + k;
         const int64_t i = r0 + r;
-        const int32_t col = col_idx[w0 + w];
-        rowof[w] = static_cast<uint8_t>(r);
+        const int64_t col = col_idx[w0 + w];
         if (col == i) dslot[r] = w;
         accK[w] = A(0);
         accM[w] = A(0);
-        mxK[w] = 0;
-        mxM[w] = 0;
-#pragma unroll
-        for (int k = 0; k < DIM; ++k)
-            f[k * wmax + w] = static_cast<T>(coords[static_cast<int64_t>(col) * DIM + k] - coords[i * DIM + k]);
+        shK[w] = 0;
+        shM[w] = 0;
+        Vec4<T> v;
+        v.x = static_cast<T>(coords[col * DIM] - coords[i * DIM]);
+        v.y = static_cast<T>(coords[col * DIM + 1] - coords[i * DIM + 1]);
+        v.z = DIM == 3 ? static_cast<T>(coords[col * DIM + (DIM - 1)] - coords[i * DIM + (DIM - 1)]) : T(0);
+        v.w = T(0);
+        f[w] = v;
     }
     __syncthreads();
 
     // phase 1a: rows of the adjacent elements, in registers; per-slot maxima
+    const float tau_abs = static_cast<float>(fb.tau_abs), tau_cond = static_cast<float>(fb.tau_cond);
     T kr[NITEMS][NLB], mr[NITEMS];
     uint32_t pw[NITEMS];
     int rr[NITEMS];
     int64_t routed = 0;
 #pragma unroll
     for (int q = 0; q < NITEMS; ++q) {
-        // entry j of row r is item r + nr * j: the lanes of one instruction work on different
-        // rows, so their LDS atomics hit different slots (the host guarantees that
-        // NITEMS * NBT / NR covers the longest adjacency list)
-        const int idx = threadIdx.x + q * NBT;
-        const int r = idx % nr, j = idx / nr;
+        // the host guarantees that NITEMS * NBT / NR covers the longest adjacency list
+        int r, j;
+        split_item<NR>(threadIdx.x + q * NBT, nr, r, j);
         rr[q] = -1;
         if (j >= ap[r + 1] - ap[r]) continue;
-        const int t = ap[r] + j - e0;
+        const int t = ap[r] + j;
         const int s0 = rp[r] - w0;
-        const uint32_t p = pk[e0 + t];
+        const uint32_t p = pk[t];
         T ck = T(1), cm = T(1);
         if constexpr (COEF) {
-            const int64_t e = adj[e0 + t] >> 2;
+            const int64_t e = adj[t] >> 2;
             if (cK) ck = cK[e];
             if (cM) cm = cM[e];
         }
         T u[DIM][DIM];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
-            const int s = s0 + static_cast<int>((p >> (2 + 8 * k)) & 255);
-#pragma unroll
-            for (int c = 0; c < DIM; ++c) u[k][c] = f[c * wmax + s];
+            const Vec4<T> v = f[s0 + static_cast<int>((p >> (2 + 8 * k)) & 255)];
+            u[k][0] = v.x;
+            u[k][1] = v.y;
+            if constexpr (DIM == 3) u[k][2] = v.z;
         }
         P1Geom<DIM, T> g;
         p1_geom_edges<DIM, T>(u, g);
         bool route = false;
-        if constexpr (sizeof(T) == 4) route = should_route(g.det, g.absterms, fb);
+        if constexpr (sizeof(T) == 4) route = route32(g.det, g.absterms, tau_abs, tau_cond, fb.enable);
         if (route) {
             // FP64 recomputation from the coordinates of the row's node and the three others
             const int64_t i = r0 + r;
@@ -641,17 +683,23 @@ __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __res
         pw[q] = p;
         rr[q] = r;
         const int sd = dslot[r];
-        atomicMax(mxK + sd, Exact<T>::mag(kr[q][0]));
-        atomicMax(mxM + sd, Exact<T>::mag(mr[q] + mr[q]));
-        const unsigned long long mm = Exact<T>::mag(mr[q]);
+        atomicMax(reinterpret_cast<uint32_t*>(shK + sd), Exact<T>::mag(kr[q][0]));
+        atomicMax(reinterpret_cast<uint32_t*>(shM + sd), Exact<T>::mag(mr[q] + mr[q]));
+        const uint32_t mm = Exact<T>::mag(mr[q]);
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             const int s = s0 + static_cast<int>((p >> (2 + 8 * k)) & 255);
-            atomicMax(mxK + s, Exact<T>::mag(kr[q][1 + k]));
-            atomicMax(mxM + s, mm);
+            atomicMax(reinterpret_cast<uint32_t*>(shK + s), Exact<T>::mag(kr[q][1 + k]));
+            atomicMax(reinterpret_cast<uint32_t*>(shM + s), mm);
         }
     }
     if (routed) count_add(d_counters, 0, routed);
+    __syncthreads();
+    // per-slot grid: maximum bits -> shift
+    for (int w = threadIdx.x; w < W; w += NBT) {
+        shK[w] = Exact<T>::shift(static_cast<uint32_t>(shK[w]));
+        shM[w] = Exact<T>::shift(static_cast<uint32_t>(shM[w]));
+    }
     __syncthreads();
 
     // phase 1b: exact accumulation on each slot's grid
@@ -661,25 +709,21 @@ __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __res
         if (r < 0) continue;
         const int s0 = rp[r] - w0;
         const int sd = dslot[r];
-        double inv;
-        atomicAdd(accK + sd, Exact<T>::quant(kr[q][0], Exact<T>::scale(mxK[sd], inv)));
-        atomicAdd(accM + sd, Exact<T>::quant(mr[q] + mr[q], Exact<T>::scale(mxM[sd], inv)));
+        atomicAdd(accK + sd, Exact<T>::quant(kr[q][0], shK[sd]));
+        atomicAdd(accM + sd, Exact<T>::quant(mr[q] + mr[q], shM[sd]));
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             const int s = s0 + static_cast<int>((pw[q] >> (2 + 8 * k)) & 255);
-            atomicAdd(accK + s, Exact<T>::quant(kr[q][1 + k], Exact<T>::scale(mxK[s], inv)));
-            atomicAdd(accM + s, Exact<T>::quant(mr[q], Exact<T>::scale(mxM[s], inv)));
+            atomicAdd(accK + s, Exact<T>::quant(kr[q][1 + k], shK[s]));
+            atomicAdd(accM + s, Exact<T>::quant(mr[q], shM[s]));
         }
     }
     __syncthreads();
 
     // phase 2: one slot per thread, coalesced stores
     for (int w = threadIdx.x; w < W; w += NBT) {
-        double invK, invM;
-        Exact<T>::scale(mxK[w], invK);
-        Exact<T>::scale(mxM[w], invM);
-        valsK[w0 + w] = Exact<T>::back(accK[w], invK);
-        if (valsM) valsM[w0 + w] = Exact<T>::back(accM[w], invM);
+        valsK[w0 + w] = Exact<T>::back(accK[w], shK[w]);
+        if (valsM) valsM[w0 + w] = Exact<T>::back(accM[w], shM[w]);
     }
 }
 
