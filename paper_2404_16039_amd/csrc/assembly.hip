@@ -424,10 +424,10 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
 }
 
 // ---------------------------------------------------------------------------- numeric
-constexpr int NR_BIG = 32;   // rows per block of the numeric kernel
-constexpr int NR_SMALL = 8;  // ... when a big block's window or entries do not fit
+constexpr int NR_BIG = 16;   // rows per block of the numeric kernel
+constexpr int NR_SMALL = 4;  // ... when a big block's window or entries do not fit
 constexpr int NBT = 256;     // threads per block of the numeric kernel
-constexpr int NITEMS = 4;    // adjacency entries per thread (held in registers)
+constexpr int NITEMS = 2;    // adjacency entries per thread (held in registers)
 static_assert(MAXADJ <= NITEMS * NBT / NR_SMALL, "the small numeric blocks must cover any admissible row");
 
 // largest CSR window and adjacency range of one numeric block of `nr` rows, and the largest
@@ -532,6 +532,50 @@ __device__ __forceinline__ void origin_row(const P1Geom<DIM, C>& g, C ck, C cm, 
     mo = cm * adet * static_cast<C>(1.0 / (fact_dim<DIM>() * (DIM + 1) * (DIM + 2)));
 }
 
+// Row of K_e and M_e from FP64 edge vectors, plain FP64 arithmetic (used for the elements the
+// FP32 path routes: FP64 carries 29 more bits than the FP32 result needs, so no compensation
+// is required, and the path stays light on registers).
+template <int DIM>
+__device__ __forceinline__ void origin_row_f64(const double (&u)[DIM][DIM], double ck, double cm,
+                                               double (&k)[DIM + 1], double& mo) {
+    double c[DIM + 1][DIM];
+    double det;
+    if constexpr (DIM == 3) {
+#pragma unroll
+        for (int j = 1; j <= 3; ++j) {
+            const double* x = u[j % 3];
+            const double* y = u[(j + 1) % 3];
+            c[j][0] = fmaT(x[1], y[2], -x[2] * y[1]);
+            c[j][1] = fmaT(x[2], y[0], -x[0] * y[2]);
+            c[j][2] = fmaT(x[0], y[1], -x[1] * y[0]);
+        }
+        det = fmaT(u[0][0], c[1][0], fmaT(u[0][1], c[1][1], u[0][2] * c[1][2]));
+    } else {
+        c[1][0] = u[1][1];
+        c[1][1] = -u[1][0];
+        c[2][0] = -u[0][1];
+        c[2][1] = u[0][0];
+        det = fmaT(u[0][0], u[1][1], -u[0][1] * u[1][0]);
+    }
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+        double s = c[1][i];
+#pragma unroll
+        for (int j = 2; j <= DIM; ++j) s += c[j][i];
+        c[0][i] = -s;
+    }
+    const double adet = fabs(det);
+    const double kf = ck / (fact_dim<DIM>() * adet);
+#pragma unroll
+    for (int b = 0; b <= DIM; ++b) {
+        double s = c[0][0] * c[b][0];
+#pragma unroll
+        for (int q = 1; q < DIM; ++q) s = fmaT(c[0][q], c[b][q], s);
+        k[b] = kf * s;
+    }
+    mo = cm * adet * (1.0 / (fact_dim<DIM>() * (DIM + 1) * (DIM + 2)));
+}
+
 // FP32 routing test with thresholds already rounded to FP32
 __device__ __forceinline__ bool route32(float det, float absterms, float tau_abs, float tau_cond, int enable) {
     const float ad = fabsf(det);
@@ -599,8 +643,23 @@ __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __res
     if (threadIdx.x == 0) *maxlen = 0;
     __syncthreads();
     if (threadIdx.x < nr) atomicMax(maxlen, rp[threadIdx.x + 1] - rp[threadIdx.x]);
-    const int32_t w0 = rp[0], e0 = ap[0];
+    const int32_t w0 = rp[0];
     const int W = rp[nr] - w0;
+    // packed entries of this thread's items, loaded before phase 0 so their latency overlaps it
+    uint32_t pw[NITEMS];
+    int rr[NITEMS], tt[NITEMS];
+#pragma unroll
+    for (int q = 0; q < NITEMS; ++q) {
+        // the host guarantees that NITEMS * NBT / NR covers the longest adjacency list
+        int r, j;
+        split_item<NR>(threadIdx.x + q * NBT, nr, r, j);
+        rr[q] = -1;
+        if (j < ap[r + 1] - ap[r]) {
+            rr[q] = r;
+            tt[q] = ap[r] + j;
+            pw[q] = pk[tt[q]];
+        }
+    }
     __syncthreads();
 
     // phase 0: edge vector per slot (row-interleaved, no search), accumulators cleared
@@ -628,19 +687,14 @@ __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __res
     // phase 1a: rows of the adjacent elements, in registers; per-slot maxima
     const float tau_abs = static_cast<float>(fb.tau_abs), tau_cond = static_cast<float>(fb.tau_cond);
     T kr[NITEMS][NLB], mr[NITEMS];
-    uint32_t pw[NITEMS];
-    int rr[NITEMS];
     int64_t routed = 0;
 #pragma unroll
     for (int q = 0; q < NITEMS; ++q) {
-        // the host guarantees that NITEMS * NBT / NR covers the longest adjacency list
-        int r, j;
-        split_item<NR>(threadIdx.x + q * NBT, nr, r, j);
-        rr[q] = -1;
-        if (j >= ap[r + 1] - ap[r]) continue;
-        const int t = ap[r] + j;
+        const int r = rr[q];
+        if (r < 0) continue;
+        const int t = tt[q];
         const int s0 = rp[r] - w0;
-        const uint32_t p = pk[t];
+        const uint32_t p = pw[q];
         T ck = T(1), cm = T(1);
         if constexpr (COEF) {
             const int64_t e = adj[t] >> 2;
@@ -669,10 +723,8 @@ __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __res
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) ev[k][c] = coords[col * DIM + c] - coords[i * DIM + c];
             }
-            P1Geom<DIM, double> gd;
-            p1_geom<DIM, double>(ev, gd);
             double kd[NLB], md;
-            origin_row<DIM, double>(gd, ck, cm, kd, md);
+            origin_row_f64<DIM>(ev, ck, cm, kd, md);
 #pragma unroll
             for (int b = 0; b < NLB; ++b) kr[q][b] = static_cast<T>(kd[b]);
             mr[q] = static_cast<T>(md);
@@ -680,8 +732,6 @@ __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __res
         } else {
             origin_row<DIM, T>(g, ck, cm, kr[q], mr[q]);
         }
-        pw[q] = p;
-        rr[q] = r;
         const int sd = dslot[r];
         atomicMax(reinterpret_cast<uint32_t*>(shK + sd), Exact<T>::mag(kr[q][0]));
         atomicMax(reinterpret_cast<uint32_t*>(shM + sd), Exact<T>::mag(mr[q] + mr[q]));
