@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "numeric_assembly_cfg3_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "numeric_assembly_cube128_traffic.json")
 KERNEL_SOURCES = ["assembly.hip", "p1elem.hpp", "smallmat.hpp", "common.hpp"]
 
 
