@@ -10,6 +10,14 @@ Workload (one step = the whole hot path over one mesh, inputs resident in HBM):
        deterministic row-wise sums into the CSR values)
     3. boundary triangle normals and areas (196,608 faces)
 Prints one JSON line (see the design doc for the fields).
+
+Other workloads (one JSON line each, same contract):
+  --workload pages   page operations on 1e7 random 3x3 pages (N(0,1) + 3 I), FP64 and FP32,
+                     paper layout and structure-of-arrays: det, inv + det, transpose,
+                     mat-vec, mat-mat
+  --workload batch   64 groups of pages of orders 2..4, sizes 10^U(3,6) (about 9.3 million
+                     pages), FP32 inverse + product per group in one persistent launch
+                     replayed from a HIP graph, against one launch per group and operation
 """
 from __future__ import annotations
 
@@ -43,10 +51,206 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=128, help="cubes per side of the mesh (default 128)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=96, help="cubes per side of the CPU oracle sample")
+    ap.add_argument("--cpu-n", type=int, default=128, help="cubes per side of the CPU oracle sample")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
+    ap.add_argument("--workload", choices=["assembly", "pages", "batch"], default="assembly")
+    ap.add_argument("--tuner-cache", default=None, help="JSON schedule cache of the batch workload")
     return ap.parse_args()
+
+
+def _events(n):
+    import torch
+    return [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+
+
+def _timed(fn, steps, warmup, stream):
+    """Per-call times (ms) of fn() from HIP events on `stream`, after `warmup` calls."""
+    import numpy as np
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = _events(steps)
+    for e0, e1 in ev:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+
+
+def _calib_copy(mib):
+    import torch
+    if mib:
+        src = torch.empty((mib << 20) // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+
+def run_pages(args):
+    """1e7 random 3x3 pages: every page operation, FP64 and FP32, both layouts."""
+    import numpy as np
+    import torch
+
+    from paper_2404_16039_amd import gen
+    from paper_2404_16039_amd import lib as L
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    count, n = 10_000_000, 3
+    _calib_copy(args.copy_calib_mib)
+    a64 = gen.page_batch(count, n)
+    b64 = gen.page_batch(count, n, stream=gen.STREAM_PAGES_B)
+    x64 = gen.vector_batch(count, n)
+    rows = []
+    fb = L.fallback(0.0, 1e6, True)
+    ctr = torch.zeros(4, dtype=torch.int64, device="cuda")
+    for dtype, prec, es in ((torch.float64, L.F64, 8), (torch.float32, L.F32, 4)):
+        for layout in ("pages", "soa"):
+            if layout == "pages":
+                ta = torch.from_numpy(a64).to(dtype).cuda()
+                tb = torch.from_numpy(b64).to(dtype).cuda()
+                D = L.pages(count, n, n)
+                V = L.pages(count, n, 1)
+                tx = torch.from_numpy(x64).to(dtype).cuda()
+            else:
+                ta = torch.from_numpy(np.ascontiguousarray(a64.T)).to(dtype).cuda()
+                tb = torch.from_numpy(np.ascontiguousarray(b64.T)).to(dtype).cuda()
+                D = L.pages_soa(count, n, n)
+                V = L.pages_soa(count, n, 1)
+                tx = torch.from_numpy(np.ascontiguousarray(x64.T)).to(dtype).cuda()
+            out = torch.empty_like(ta)
+            det = torch.empty(count, dtype=dtype, device="cuda")
+            y = torch.empty_like(tx)
+            ops = {
+                "det": (lambda: L.page_det(D, ta, det, fb=fb, counters=ctr), 9 * es + es),
+                "inv+det": (lambda: L.page_inv(D, ta, D, out, det=det, fb=fb, counters=ctr), 18 * es + es),
+                "transpose": (lambda: L.page_transpose(D, ta, D, out), 18 * es),
+                "mv": (lambda: L.page_mv(D, ta, 0, V, tx, V, y), 15 * es),
+                "mtimes": (lambda: L.page_mtimes(D, ta, 0, D, tb, 0, D, out), 27 * es),
+            }
+            for name, (fn, bpp) in ops.items():
+                t = _timed(fn, args.steps, args.warmup, stream)
+                med = float(np.median(t))
+                gbs = bpp * count / (med * 1e-3) / 1e9
+                rows.append({"op": name, "dtype": "f64" if es == 8 else "f32", "layout": layout,
+                             "ms_median": round(med, 4), "ms_p10": round(float(np.percentile(t, 10)), 4),
+                             "ms_p90": round(float(np.percentile(t, 90)), 4), "bytes_per_page": bpp,
+                             "gbps": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)})
+            del ta, tb, tx, out, det, y
+            torch.cuda.empty_cache()
+    head = next(r for r in rows if r["op"] == "inv+det" and r["dtype"] == "f32" and r["layout"] == "pages")
+    out = {
+        "metric": "3x3 page inverses (with det) per second, FP32, paper layout",
+        "value": count / (head["ms_median"] * 1e-3), "unit": "pages/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_median"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "1e7 random 3x3 pages, N(0,1) + 3 I; FP64 and FP32; paper layout and SoA",
+                   "pages": count},
+        "roofline": {"kernel": "k_page_inv<float,3,true> (pf_page_inv)", "bound": "hbm",
+                     "achieved": head["gbps"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": head["frac"],
+                     "traffic": None, "algorithmic_bytes_per_launch": head["bytes_per_page"] * count},
+        "ops": rows,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        a32 = a64.astype(np.float32).astype(np.float64)
+        t1 = time.perf_counter()
+        done = 0
+        while time.perf_counter() - t1 < 10.0:  # whole passes over the 1e7 pages, >= 10 s in total
+            oracle.page_inv(a32, n)
+            oracle.page_det(a32, n)
+            done += count
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": done / dt, "unit": "pages/s", "cores": 1, "kind": "oracle",
+                               "sample": "FP64 oracle Gauss-Jordan inverse + Leibniz det of all 1e7 FP32 pages, "
+                                         "%d pass(es), single thread, %.1f s" % (done // count, dt)}
+    print(json.dumps(out))
+
+
+def run_batch(args):
+    """64-group uneven mixed batch: inverse + product per group, one persistent launch."""
+    import tempfile
+
+    import numpy as np
+    import torch
+
+    from paper_2404_16039_amd import gen
+    from paper_2404_16039_amd import lib as L
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    spec = gen.mixed_groups(64)
+    total = sum(c for _, c in spec)
+    groups, host_a = [], []
+    for gi, (n, count) in enumerate(spec):
+        a = gen.page_batch(count, n, sub=gi).astype(np.float32)
+        b = gen.page_batch(count, n, stream=gen.STREAM_PAGES_B, sub=gi).astype(np.float32)
+        ta, tb = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+        groups.append({"order": n, "ops": L.OP_INV | L.OP_MTIMES, "a": ta, "b": tb, "x": torch.empty_like(ta),
+                       "c": torch.empty_like(ta), "det": torch.empty(count, device="cuda")})
+        host_a.append((n, a, b))
+    # algorithmic bytes: A and B read, inv(A), A*B and det(A) written once, FP32
+    alg = sum(4 * (4 * n * n + 1) * c for n, c in spec)
+    fb = L.fallback(0.0, 1e6, True)
+    ctr = torch.zeros(4, dtype=torch.int64, device="cuda")
+    plan = L.Plan(L.F32, 64, fb).set_groups(groups)
+    _calib_copy(args.copy_calib_mib)
+
+    plan.tune(None, L.TUNE_DEFAULT)
+    t_def = _timed(lambda: plan.run(counters=ctr), args.steps, args.warmup, stream)
+    cache = args.tuner_cache or os.path.join(tempfile.gettempdir(), "pagefem_tuner_cache.json")
+    t0 = time.perf_counter()
+    sched = plan.tune(cache, L.TUNE_CACHED, stream=stream).as_dict()
+    tune_s = time.perf_counter() - t0
+    t_tuned = _timed(lambda: plan.run(counters=ctr), args.steps, args.warmup, stream)
+    ntiles, grid, lds = plan.info()
+
+    def plain():
+        for g in groups:
+            n, count = g["order"], g["a"].shape[0]
+            P = L.pages(count, n, n)
+            L.page_inv(P, g["a"], P, g["x"], det=g["det"], fb=fb, counters=ctr)
+            L.page_mtimes(P, g["a"], 0, P, g["b"], 0, P, g["c"])
+    t_plain = _timed(plain, args.steps, args.warmup, stream)
+    med = float(np.median(t_tuned))
+    gbs = alg / (med * 1e-3) / 1e9
+    out = {
+        "metric": "matrices/s (mixed-order inverse + product, one persistent graph-replayed launch)",
+        "value": total / (med * 1e-3), "unit": "matrices/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": med, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "64 groups, orders uniform in {2,3,4}, sizes round(10^U(3,6)), A, B = N(0,1) + 3 I, "
+                               "FP32 inv(A) with det and A*B per group", "matrices": total,
+                   "per_order": {str(n): sum(c for m, c in spec if m == n) for n in (2, 3, 4)}},
+        "ms_tuned": {"median": med, "p10": float(np.percentile(t_tuned, 10)), "p90": float(np.percentile(t_tuned, 90))},
+        "ms_default_schedule": float(np.median(t_def)),
+        "ms_one_launch_per_group_and_op": float(np.median(t_plain)),
+        "schedule": sched, "tune_seconds": round(tune_s, 3), "tiles": ntiles, "grid": grid, "lds_bytes": lds,
+        "roofline": {"kernel": "k_plan<float,%d> (pf_plan_run)" % sched["waves"], "bound": "hbm", "achieved": gbs,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": alg},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        t1 = time.perf_counter()
+        done = 0
+        while time.perf_counter() - t1 < 10.0:  # whole passes over every group, >= 10 s in total
+            for n, a, b in host_a:
+                a64, b64 = a.astype(np.float64).reshape(-1, n * n), b.astype(np.float64).reshape(-1, n * n)
+                oracle.page_inv(a64, n)
+                oracle.page_det(a64, n)
+                oracle.page_mtimes(a64, b64, n, n, n)
+                done += a.shape[0]
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": done / dt, "unit": "matrices/s", "cores": 1, "kind": "oracle",
+                               "sample": "FP64 oracle inverse + det + product of every matrix of the batch, "
+                                         "%d pass(es), single thread, %.1f s" % (done // total, dt)}
+    plan.close()
+    print(json.dumps(out))
 
 
 def main():
@@ -55,6 +259,11 @@ def main():
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the path shards by rows or elements, see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "pages":
+        return run_pages(args)
+    if args.workload == "batch":
+        return run_batch(args)
 
     import numpy as np
     import torch

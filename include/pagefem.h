@@ -73,7 +73,7 @@ typedef struct pf_pages {
 /* FP64 routing of the FP32 path: a page/element is recomputed in FP64 when its FP32
  * determinant (compensated) satisfies |det| < tau_abs, or its det-condition
  * sum_j |a_0j C_0j| / |det| (expansion along the first row) exceeds tau_cond, or det is
- * not finite.  enable = 0 turns routing off.  A NULL pf_fallback* means
+ * zero (infinite det-condition) or not finite.  enable = 0 turns routing off.  A NULL pf_fallback* means
  * {tau_abs = 0, tau_cond = 1e6, enable = 1}.  Ignored on the FP64 path.               */
 typedef struct pf_fallback {
     double tau_abs;
@@ -201,6 +201,89 @@ pf_status pf_assemble(const pf_csr* csr, pf_dtype prec, const double* coords, co
                       const pf_fallback* fb, int64_t* d_counters, void* stream);
 
 void pf_csr_destroy(pf_csr* csr);
+
+/* ----------------------------------------------------------------------------------
+ * Mixed-order batch plans: one persistent launch applies the page-wise inverse (with
+ * determinant) and the page-wise product of section 2.2 (aminv and amsm/amtam-style
+ * products of section 2.3) to many groups of square pages of different orders at once.
+ *
+ * A plan holds a work list (one descriptor per group, tiles of each group numbered
+ * consecutively) in pinned host memory and a copy of it in device memory.  pf_plan_run
+ * replays a HIP graph of two nodes: the host-to-device copy of the work list, then one
+ * persistent kernel whose workgroups (compute units x occupancy) walk the tiles in
+ * round-robin order.  Group pointers and counts may change between runs without a new
+ * graph (pf_plan_set_groups); a new schedule with another wave count re-captures it.
+ *
+ * Pages of every group use the paper's layout (column-major n x n pages stored back to
+ * back, element (r, c) of page k at k*n*n + r + c*n); pointers need the natural alignment
+ * of the element type only.  FP32 plans compute the inverse with compensated cofactors
+ * and route pages by the fallback predicate to FP64, exactly as pf_page_inv; products
+ * are FMA chains in ascending inner index (bitwise the same for every schedule).
+ * ---------------------------------------------------------------------------------- */
+typedef struct pf_plan pf_plan;
+
+enum { PF_OP_INV = 1, PF_OP_MTIMES = 2 };
+
+typedef struct {
+    int32_t order;    /* n, 1..4                                                          */
+    int32_t ops;      /* PF_OP_INV and/or PF_OP_MTIMES                                    */
+    int64_t count;    /* pages in the group (0 allowed)                                   */
+    const void* a;    /* count pages A                                                    */
+    const void* b;    /* count pages B (PF_OP_MTIMES), else ignored                       */
+    void* x;          /* out: inv(A) (PF_OP_INV), else ignored                            */
+    void* c;          /* out: A*B (PF_OP_MTIMES), else ignored                            */
+    void* det;        /* out: det(A) (PF_OP_INV, nullable)                                */
+} pf_group;
+
+/* Schedule of one order: lanes per matrix (1, n or n*n), LDS staging of the tile (1) or
+ * direct per-lane loads (0), and chunks per tile (1..16; a chunk is one page per lane for
+ * lanes = 1, else floor(64/lanes) pages per wave). */
+typedef struct {
+    int32_t lanes, staged, tile;
+} pf_order_schedule;
+
+typedef struct {
+    int32_t waves;               /* waves per workgroup: 1, 2, 4 or 8 */
+    pf_order_schedule order[5];  /* indexed by the order, entry 0 unused */
+} pf_schedule;
+
+enum { PF_TUNE_CACHED = 0, PF_TUNE_FORCE = 1, PF_TUNE_DEFAULT = 2 };
+
+/* Create a plan for up to max_groups groups of pages of type dtype (host call; allocates
+ * the pinned and device work lists).  fb: routing of FP32 pages (NULL = tau_abs 0,
+ * tau_cond 1e6, enabled).  The schedule starts as the default one. */
+pf_status pf_plan_create(pf_dtype dtype, int32_t max_groups, const pf_fallback* fb, pf_plan** out);
+
+/* Replace the plan's groups (ngroups <= max_groups).  Validates orders, ops, counts and
+ * pointers (PF_EINVAL / PF_EORDER), waits for the plan's previous run to finish, then
+ * rewrites the host work list; the next run copies it to the device. */
+pf_status pf_plan_set_groups(pf_plan* plan, const pf_group* groups, int32_t ngroups);
+
+/* Read / set the schedule.  PF_EINVAL for values outside the documented sets or a tile
+ * staging buffer beyond the device's LDS per workgroup. */
+pf_status pf_plan_get_schedule(const pf_plan* plan, pf_schedule* out);
+pf_status pf_plan_set_schedule(pf_plan* plan, const pf_schedule* sched);
+
+/* Choose the schedule for the current groups.  mode PF_TUNE_DEFAULT: the default schedule.
+ * PF_TUNE_CACHED: look the groups' shape up in the JSON file `cache_path` (device
+ * architecture, precision, total pages per order as a power-of-two bucket); on a miss,
+ * tune and add the result to the file.  PF_TUNE_FORCE: tune and overwrite the entry.
+ * Tuning times candidate schedules with HIP events on `stream` (it runs the plan, so it
+ * writes the groups' outputs) and keeps the tuned schedule only if it beats the default
+ * on the whole batch.  cache_path may be NULL (no file).  Synchronises `stream`. */
+pf_status pf_plan_tune(pf_plan* plan, const char* cache_path, int32_t mode, void* stream);
+
+/* Run the plan on `stream` by replaying its graph (captured on first use).  d_counters
+ * (nullable, as for the page calls) receives routed and singular page counts. */
+pf_status pf_plan_run(pf_plan* plan, int64_t* d_counters, void* stream);
+
+/* The same work as pf_plan_run with ordinary launches (a copy, then the kernel). */
+pf_status pf_plan_launch(pf_plan* plan, int64_t* d_counters, void* stream);
+
+/* Launch geometry of the current schedule: tiles, workgroups, LDS bytes per workgroup. */
+pf_status pf_plan_info(const pf_plan* plan, int64_t* ntiles, int32_t* grid, int32_t* lds_bytes);
+
+void pf_plan_destroy(pf_plan* plan);
 
 #ifdef __cplusplus
 }

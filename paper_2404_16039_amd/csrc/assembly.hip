@@ -579,7 +579,7 @@ __device__ __forceinline__ void origin_row_f64(const double (&u)[DIM][DIM], doub
 // FP32 routing test with thresholds already rounded to FP32
 __device__ __forceinline__ bool route32(float det, float absterms, float tau_abs, float tau_cond, int enable) {
     const float ad = fabsf(det);
-    return enable && (!__builtin_isfinite(det) || !__builtin_isfinite(absterms) || ad < tau_abs ||
+    return enable && (!__builtin_isfinite(det) || !__builtin_isfinite(absterms) || ad == 0.0f || ad < tau_abs ||
                       absterms > tau_cond * ad);
 }
 

@@ -130,13 +130,14 @@ __device__ __forceinline__ void adjugate(const T* a, T* adj) {
 #undef A_
 
 // Routing decision of the FP32 path (see pf_fallback): route when |det| < tau_abs, the
-// det-condition exceeds tau_cond, or det is not finite.
+// det-condition exceeds tau_cond, or det is zero or not finite (the det-condition of a zero
+// determinant is infinite, also when every term of the expansion is zero).
 template <typename T>
 __device__ __forceinline__ bool should_route(T det, T absterms, const Fallback& fb) {
     if (!fb.enable) return false;
     T ad = fabs(det);
     if (!finiteT(det) || !finiteT(absterms)) return true;
-    if (static_cast<double>(ad) < fb.tau_abs) return true;
+    if (ad == T(0) || static_cast<double>(ad) < fb.tau_abs) return true;
     // absterms / |det| > tau_cond  <=>  absterms > tau_cond * |det| (no division)
     return static_cast<double>(absterms) > fb.tau_cond * static_cast<double>(ad);
 }

@@ -58,6 +58,27 @@ def pages_bcast(rows, cols, count=1):
     return Pages(rows, cols, count, 1, rows, 0)
 
 
+class Group(C.Structure):
+    _fields_ = [("order", C.c_int32), ("ops", C.c_int32), ("count", C.c_int64), ("a", C.c_void_p),
+                ("b", C.c_void_p), ("x", C.c_void_p), ("c", C.c_void_p), ("det", C.c_void_p)]
+
+
+class OrderSchedule(C.Structure):
+    _fields_ = [("lanes", C.c_int32), ("staged", C.c_int32), ("tile", C.c_int32)]
+
+
+class Schedule(C.Structure):
+    _fields_ = [("waves", C.c_int32), ("order", OrderSchedule * 5)]
+
+    def as_dict(self):
+        return {"waves": self.waves,
+                "order": {n: (self.order[n].lanes, self.order[n].staged, self.order[n].tile) for n in range(1, 5)}}
+
+
+OP_INV, OP_MTIMES = 1, 2
+TUNE_CACHED, TUNE_FORCE, TUNE_DEFAULT = 0, 1, 2
+
+
 def fallback(tau_abs=0.0, tau_cond=1e6, enable=True):
     return Fallback(float(tau_abs), float(tau_cond), 1 if enable else 0)
 
@@ -86,6 +107,15 @@ _sig = {
     "pf_csr_info": ([P, C.POINTER(I64), C.POINTER(I64), C.POINTER(P), C.POINTER(P)], C.c_int),
     "pf_assemble": ([P, I32, P, P, P, P, P, P, FP, P, P], C.c_int),
     "pf_csr_destroy": ([P], None),
+    "pf_plan_create": ([I32, I32, FP, C.POINTER(P)], C.c_int),
+    "pf_plan_set_groups": ([P, C.POINTER(Group), I32], C.c_int),
+    "pf_plan_get_schedule": ([P, C.POINTER(Schedule)], C.c_int),
+    "pf_plan_set_schedule": ([P, C.POINTER(Schedule)], C.c_int),
+    "pf_plan_tune": ([P, C.c_char_p, I32, P], C.c_int),
+    "pf_plan_run": ([P, P, P], C.c_int),
+    "pf_plan_launch": ([P, P, P], C.c_int),
+    "pf_plan_info": ([P, C.POINTER(I64), C.POINTER(I32), C.POINTER(I32)], C.c_int),
+    "pf_plan_destroy": ([P], None),
 }
 for _name, (_args, _res) in _sig.items():
     _f = getattr(_lib, _name)
@@ -248,6 +278,74 @@ class Csr:
     def close(self):
         if self._h:
             _lib.pf_csr_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------- batch plans
+class Plan:
+    """Owner of a pf_plan handle: inverse and product of many groups of pages in one
+    persistent launch replayed from a HIP graph.  `groups` are dicts with keys order, ops,
+    a, b, x, c, det (tensors, b/x/c/det optional) or pf_group structures."""
+
+    def __init__(self, dtype, max_groups, fb=None):
+        h = P()
+        _chk(_lib.pf_plan_create(dtype, int(max_groups), _ref(fb, Fallback), C.byref(h)), "pf_plan_create")
+        self._h = h
+        self._keep = None
+
+    def set_groups(self, groups):
+        arr = (Group * max(len(groups), 1))()
+        keep = []
+        for i, g in enumerate(groups):
+            if isinstance(g, Group):
+                arr[i] = g
+                continue
+            a = g["a"]
+            keep.append(g)
+            arr[i] = Group(int(g["order"]), int(g["ops"]), int(g.get("count", a.numel() // g["order"] ** 2)),
+                           _p(a), _p(g.get("b")), _p(g.get("x")), _p(g.get("c")), _p(g.get("det")))
+        _chk(_lib.pf_plan_set_groups(self._h, arr, len(groups)), "pf_plan_set_groups")
+        self._keep = keep  # the tensors stay alive while the plan may run on them
+        return self
+
+    def schedule(self):
+        s = Schedule()
+        _chk(_lib.pf_plan_get_schedule(self._h, C.byref(s)), "pf_plan_get_schedule")
+        return s
+
+    def set_schedule(self, waves, per_order):
+        """per_order: {order: (lanes, staged, tile)}; orders not given keep (1, 1, 1)."""
+        s = Schedule()
+        s.waves = int(waves)
+        for n in range(5):
+            s.order[n] = OrderSchedule(*per_order.get(n, (1, 1, 1)))
+        _chk(_lib.pf_plan_set_schedule(self._h, C.byref(s)), "pf_plan_set_schedule")
+
+    def tune(self, cache_path=None, mode=TUNE_CACHED, stream=None):
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _chk(_lib.pf_plan_tune(self._h, path, int(mode), _s(stream)), "pf_plan_tune")
+        return self.schedule()
+
+    def run(self, counters=None, stream=None):
+        _chk(_lib.pf_plan_run(self._h, _p(counters), _s(stream)), "pf_plan_run")
+
+    def launch(self, counters=None, stream=None):
+        _chk(_lib.pf_plan_launch(self._h, _p(counters), _s(stream)), "pf_plan_launch")
+
+    def info(self):
+        nt, grid, lds = I64(), I32(), I32()
+        _chk(_lib.pf_plan_info(self._h, C.byref(nt), C.byref(grid), C.byref(lds)), "pf_plan_info")
+        return nt.value, grid.value, lds.value
+
+    def close(self):
+        if self._h:
+            _lib.pf_plan_destroy(self._h)
             self._h = None
 
     def __del__(self):

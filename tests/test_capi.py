@@ -78,3 +78,19 @@ def test_csr_handle_states_without_gpu():
     assert L.pf_csr_symbolic(h, 3, 1 << 31, 1, C.c_void_p(16), None) == 7
     L.pf_csr_destroy(h)
     L.pf_csr_destroy(None)
+
+
+def test_plan_host_validation_without_gpu():
+    from paper_2404_16039_amd import lib
+    L = lib._lib
+    h = C.c_void_p()
+    assert L.pf_plan_create(7, 4, None, C.byref(h)) == 2
+    assert L.pf_plan_create(lib.F32, 0, None, C.byref(h)) == 1
+    assert L.pf_plan_create(lib.F32, 4, None, None) == 1
+    assert L.pf_plan_set_groups(None, None, 0) == 1
+    assert L.pf_plan_run(None, None, None) == 1
+    assert L.pf_plan_launch(None, None, None) == 1
+    assert L.pf_plan_tune(None, None, 0, None) == 1
+    assert L.pf_plan_get_schedule(None, None) == 1
+    assert L.pf_plan_info(None, None, None, None) == 1
+    L.pf_plan_destroy(None)
