@@ -34,14 +34,33 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "numeric_assembly_cube128_traffic.json")
 KERNEL_SOURCES = ["assembly.hip", "p1elem.hpp", "smallmat.hpp", "common.hpp"]
+BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_plan_64groups_traffic.json")
+BATCH_SOURCES = ["batch.hip", "smallmat.hpp", "common.hpp"]
 
 
-def kernel_hash() -> str:
+def kernel_hash(files=KERNEL_SOURCES) -> str:
+    """Hash of the kernel sources with comments and blank space removed (a counter file
+    stays valid across comment-only edits)."""
+    import re
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2404_16039_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2404_16039_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        h.update("".join(src.split()).encode())
     return h.hexdigest()[:16]
+
+
+def traffic_of(path, files, **match):
+    """HBM bytes per launch from a committed counter file, if it matches these sources."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tr = json.load(f)
+    if tr.get("kernel_hash") != kernel_hash(files) or any(tr.get(k) != v for k, v in match.items()):
+        return None
+    return tr.get("hbm_bytes_per_launch")
 
 
 def parse():
@@ -231,7 +250,8 @@ def run_batch(args):
         "ms_one_launch_per_group_and_op": float(np.median(t_plain)),
         "schedule": sched, "tune_seconds": round(tune_s, 3), "tiles": ntiles, "grid": grid, "lds_bytes": lds,
         "roofline": {"kernel": "k_plan<float,%d> (pf_plan_run)" % sched["waves"], "bound": "hbm", "achieved": gbs,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "traffic": None,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                     "traffic": traffic_of(BATCH_TRAFFIC_FILE, BATCH_SOURCES, matrices=total),
                      "algorithmic_bytes_per_launch": alg},
     }
     if not args.no_cpu_baseline:
@@ -344,12 +364,7 @@ def main():
               "boundary_ms": round(float(bnd.mean()), 4)}
     dominant = max(phases, key=phases.get)
 
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as f:
-            tr = json.load(f)
-        if tr.get("kernel_hash") == kernel_hash() and tr.get("n") == n:
-            traffic = tr.get("hbm_bytes_per_launch")
+    traffic = traffic_of(TRAFFIC_FILE, KERNEL_SOURCES, n=n)
 
     out = {
         "metric": "P1 tet elements assembled/sec (stiffness + mass, CSR) + achieved HBM GB/s",

@@ -5,12 +5,14 @@
  * The operations follow "On a vectorized basic linear algebra package for prototyping
  * codes in MATLAB" (Moskovka, Rahman, Valdman, Vatne, arXiv 2404.16039):
  *   section 2.2  page-wise multiplication, transpose, scalar multiplication, bilinear form
- *                evaluation, page-wise determinant and inverse, transformation of normals
- *   section 2.3  the library functions amtam, avtam, avtav, astam, amsm, amsv, smamt,
+ *                evaluation
+ *   section 2.3  page-wise determinant and inverse, transformation of normals
+ *   section 2.4  the library functions amtam, avtam, avtav, astam, amsm, amsv, smamt,
  *                svamt, aminv, amt, amdet, avtamav
  *   section 3.1  the coords3D / vectors3D structures
  *   section 3.2  volumes and normals
- *   section 3.5  derivative routine, P1 stiffness and mass matrices, sparse() assembly
+ *   section 3.5  surface integrals (boundary faces, their normals and areas)
+ *   section 3.6  derivative routine, P1 stiffness and mass matrices, sparse() assembly
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -85,15 +87,16 @@ const char* pf_last_error(void);
 int pf_version(void);
 
 /* ------------------------------------------------------------------------------------
- * Page operations (section 2.2, page-wise maps; section 2.3, library functions)
+ * Page operations (section 2.2, page-wise maps; section 2.3, determinants
+ * and inverses; section 2.4, library functions)
  * ---------------------------------------------------------------------------------- */
 
-/* Page-wise determinant det_W (section 2.2; amdet).  A: n x n pages, n = 1..4.
+/* Page-wise determinant det_W (section 2.3; amdet).  A: n x n pages, n = 1..4.
  * det: `count` values of `dtype`, contiguous.  flags, d_counters nullable. */
 pf_status pf_page_det(pf_dtype dtype, const pf_pages* A, const void* a, void* det,
                       const pf_fallback* fb, uint8_t* flags, int64_t* d_counters, void* stream);
 
-/* Page-wise inverse on det_W^{-1}(W*) (section 2.2; aminv, which also returns the
+/* Page-wise inverse on det_W^{-1}(W*) (section 2.3; aminv, which also returns the
  * determinants).  X: output pages (n x n).  det (nullable): determinants as in
  * pf_page_det.  A page with zero determinant gets the IEEE result of adj(A)/0 (inf/nan)
  * and flag bit 0; it is counted in d_counters[1]. */
@@ -106,7 +109,7 @@ pf_status pf_page_transpose(pf_dtype dtype, const pf_pages* A, const void* a, co
                             void* t, void* stream);
 
 /* Page-wise product C_k = op(A_k) op(B_k) (section 2.2, page-wise matrix multiplication;
- * section 2.3 amtam, avtam, avtav, amsm, amsv, smamt, svamt are instances).  op(X) = X or
+ * section 2.4 amtam, avtam, avtav, amsm, amsv, smamt, svamt are instances).  op(X) = X or
  * X^T per the trans flag.  op(A): m x k, op(B): k x n, C: m x n, all dims 1..4; a
  * broadcast operand (s_page = 0) is one matrix used for every page.  C.count pages are
  * computed; non-broadcast A/B must have count equal to C.count. */
@@ -114,7 +117,7 @@ pf_status pf_page_mtimes(pf_dtype dtype, const pf_pages* A, const void* a, int t
                          const pf_pages* B, const void* b, int transB, const pf_pages* C, void* c,
                          void* stream);
 
-/* Page-wise matrix-vector product y_k = op(A_k) x_k (section 2.3 amsv / avtam pattern);
+/* Page-wise matrix-vector product y_k = op(A_k) x_k (section 2.4 amsv / avtam pattern);
  * x, y are vectors given as n x 1 pages.  Same rules as pf_page_mtimes. */
 pf_status pf_page_mv(pf_dtype dtype, const pf_pages* A, const void* a, int transA,
                      const pf_pages* X, const void* x, const pf_pages* Y, void* y, void* stream);
@@ -130,7 +133,7 @@ pf_status pf_page_bilinear(pf_dtype dtype, const pf_pages* U, const void* u, con
                            const void* a, const pf_pages* V, const void* v, void* q, void* stream);
 
 /* ------------------------------------------------------------------------------------
- * P1 elements (section 3.5, derivative routine and P1 stiffness / mass; section 3.2,
+ * P1 elements (section 3.6, derivative routine and P1 stiffness / mass; section 3.2,
  * volumes and normals).  dim = 2 (triangles, nlb = 3) or 3 (tetrahedra, nlb = 4).
  * prec = PF_F64: FP64 arithmetic and outputs.  prec = PF_F32: FP32 arithmetic (Jacobian
  * edges subtracted in FP64, then rounded), compensated determinant, FP64 recomputation of
@@ -158,7 +161,8 @@ pf_status pf_elem_stiffness_mass(int dim, pf_dtype prec, int64_t nn, const doubl
                                  void* K3D, void* M3D, const pf_fallback* fb, uint8_t* flags,
                                  int64_t* d_counters, void* stream);
 
-/* Boundary facets (section 3.2 normals; facesB / areasB of the surface integral).
+/* Boundary facets (section 3.2 normals; facesB / areasB of the surface integrals of
+ * section 3.5).
  * dim = 3: faces[nf][3] triangles (a,b,c), n = (b-a) x (c-a), measure = |n| / 2.
  * dim = 2: faces[nf][2] edges (a,b), n = (b_y - a_y, a_x - b_x), measure = |n|.
  * unit[nf][dim] = n / |n| (nullable), measure[nf] (nullable), type prec. */
@@ -166,7 +170,7 @@ pf_status pf_boundary_normals(int dim, pf_dtype prec, int64_t nn, const double* 
                               const int32_t* faces, void* unit, void* measure, void* stream);
 
 /* ------------------------------------------------------------------------------------
- * Assembly: sparse(X3D(:), Y3D(:), K3D(:), nn, nn) of the P1 listings (section 3.5).
+ * Assembly: sparse(X3D(:), Y3D(:), K3D(:), nn, nn) of the P1 listings (section 3.6).
  * The CSR pattern holds every pair of nodes that share an element (entries that sum to
  * zero are kept), columns ascending in each row.  K and M are symmetric, so the CSR
  * arrays equal the compressed-column arrays of the global matrices.
@@ -204,8 +208,9 @@ void pf_csr_destroy(pf_csr* csr);
 
 /* ----------------------------------------------------------------------------------
  * Mixed-order batch plans: one persistent launch applies the page-wise inverse (with
- * determinant) and the page-wise product of section 2.2 (aminv and amsm/amtam-style
- * products of section 2.3) to many groups of square pages of different orders at once.
+ * determinant, section 2.3) and the page-wise product of section 2.2 (aminv and the
+ * amsm/amtam-style products of section 2.4) to many groups of square pages of different
+ * orders at once.
  *
  * A plan holds a work list (one descriptor per group, tiles of each group numbered
  * consecutively) in pinned host memory and a copy of it in device memory.  pf_plan_run

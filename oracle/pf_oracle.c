@@ -9,16 +9,16 @@
  *
  * Everything is computed from the plain mathematical definitions, one page / one element
  * at a time, in double precision, with no blocking, fusion or reordering:
- *   - determinant: Leibniz sum over all permutations (section 2.2, page-wise determinant)
- *   - inverse: Gauss-Jordan elimination with partial pivoting (section 2.2, page-wise
+ *   - determinant: Leibniz sum over all permutations (section 2.3, page-wise determinant)
+ *   - inverse: Gauss-Jordan elimination with partial pivoting (section 2.3, page-wise
  *     inverse on the set of pages with non-zero determinant)
  *   - transpose / products: index definitions (section 2.2, page-wise transpose and
- *     page-wise matrix multiplication; section 2.3 library functions)
+ *     page-wise matrix multiplication; section 2.4 library functions)
  *   - P1 elements: Jacobian from the reference shape-function derivatives, its inverse,
- *     global gradients, stiffness and mass by quadrature (section 3.5, the derivative
+ *     global gradients, stiffness and mass by quadrature (section 3.6, the derivative
  *     routine and the P1 stiffness / P2 mass listings specialised to P1, c = 1)
  *   - assembly: (row, col, value) triples in element-major order, stable sort by
- *     (row, col), sum of each run (section 3.5, the sparse() call of the listings)
+ *     (row, col), sum of each run (section 3.6, the sparse() call of the listings)
  *   - boundary faces: cross product normals and areas (section 3.2)
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math, no FMA contraction).
@@ -107,7 +107,7 @@ static int gauss_jordan(const double* a, int n, double* inv) {
 }
 
 /* ------------------------------------------------------------------------------------ */
-/* page operations (section 2.2 / 2.3)                                                  */
+/* page operations (sections 2.2-2.4)                                                  */
 /* ------------------------------------------------------------------------------------ */
 
 /* det[k] = det of page k (n x n), perm_abs[k] = perm(|A_k|) (nullable) */
@@ -211,7 +211,7 @@ int or_page_bilinear(int n, int64_t count, const double* u, const double* a, con
 }
 
 /* ------------------------------------------------------------------------------------ */
-/* P1 elements (section 3.5): one quadrature point for the gradients (constant on a P1  */
+/* P1 elements (section 3.6): one quadrature point for the gradients (constant on a P1  */
 /* element), a degree-2 exact rule for the mass matrix, coefficients c_K = c_M = 1.     */
 /* ------------------------------------------------------------------------------------ */
 

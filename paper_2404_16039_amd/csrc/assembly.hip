@@ -1,5 +1,5 @@
 // assembly.hip -- COO -> CSR assembly of the P1 stiffness and mass matrices, i.e. the
-// sparse(X3D(:), Y3D(:), K3D(:), nn, nn) call of the section 3.5 listings, without ever
+// sparse(X3D(:), Y3D(:), K3D(:), nn, nn) call of the section 3.6 listings, without ever
 // materialising the 16 (row, col, value) triples per element.
 //
 // Symbolic phase (integer-exact, kept in a pf_csr handle):

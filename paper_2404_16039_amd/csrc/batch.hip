@@ -1,5 +1,5 @@
-// batch.hip -- mixed-order batch plans: the page-wise inverse (with determinant) and the
-// page-wise product of section 2.2 over many groups of pages of orders 1..4, in ONE
+// batch.hip -- mixed-order batch plans: the page-wise inverse with determinant (section
+// 2.3) and the page-wise product (section 2.2) over many groups of pages of orders 1..4, in ONE
 // persistent launch replayed from a HIP graph.
 //
 // Work list.  Each group is cut into tiles of `tile` chunks; a chunk is one page per lane

@@ -1,4 +1,4 @@
-// elements.hip -- per-element P1 geometry, stiffness and mass matrices (section 3.5), and
+// elements.hip -- per-element P1 geometry, stiffness and mass matrices (section 3.6), and
 // boundary facet normals and measures (section 3.2).  One element (or facet) per lane.
 #include "p1elem.hpp"
 

@@ -1,4 +1,4 @@
-// p1elem.hpp -- per-element P1 geometry in registers (section 3.5 derivative routine with
+// p1elem.hpp -- per-element P1 geometry in registers (section 3.6 derivative routine with
 // one integration point; section 3.2 volumes and normals).
 //
 // With edges e_k = p_{k+1} - p_1 (the columns of J), the inverse transpose of J has the

@@ -1,5 +1,6 @@
 // page_ops.hip -- page-wise det, inverse, transpose, products, scaling and bilinear forms
-// over batches of 1x1..4x4 matrices (section 2.2 page-wise maps, section 2.3 library).
+// over batches of 1x1..4x4 matrices (section 2.2 page-wise maps, section 2.3 determinants
+// and inverses, section 2.4 library).
 //
 // One page per lane.  Pages in the paper's contiguous layout (column-major pages stored
 // one after another) are staged through LDS by the whole workgroup with 16-byte vector

@@ -1,7 +1,7 @@
 // smallmat.hpp -- register-resident determinants, cofactors and inverses of 1x1..4x4
 // column-major pages (element (r, c) at a[r + c*N]).
 //
-// Determinant and inverse follow section 2.2 of the paper (page-wise determinant; inverse
+// Determinant and inverse follow section 2.3 of the paper (page-wise determinant; inverse
 // on the pages with non-zero determinant) through the adjugate, inv = adj / det.  Accuracy
 // in the working precision (FP32 or FP64) does not depend on cancellation:
 //   - 2x2 minors are evaluated as double-word values (error-free products and sums), or

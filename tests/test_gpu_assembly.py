@@ -1,4 +1,4 @@
-"""Parity of the CSR assembly (the sparse() call of the section 3.5 listings) against the
+"""Parity of the CSR assembly (the sparse() call of the section 3.6 listings) against the
 oracle: structure bit-exact, values within tolerance of the sum of |contributions|, at the
 small configurations in full and at the 128^3 configuration on sampled rows."""
 import numpy as np

@@ -1,5 +1,5 @@
-"""Parity of the mixed-order batch plans (page-wise inverse with determinant and page-wise
-product of section 2.2, many groups of orders 1..4 in one persistent launch) against the
+"""Parity of the mixed-order batch plans (page-wise inverse with determinant of section
+2.3 and page-wise product of section 2.2, many groups of orders 1..4 in one persistent launch) against the
 oracle, under every schedule, through the graph replay path, and at the 64-group
 uneven-batch size (about 9.3 million pages) on sampled pages."""
 import json

@@ -1,4 +1,4 @@
-"""Parity of the P1 element kernels (section 3.5 derivative routine, stiffness and mass;
+"""Parity of the P1 element kernels (section 3.6 derivative routine, stiffness and mass;
 section 3.2 volumes and normals) and of the boundary facets against the FP64 oracle."""
 import numpy as np
 import pytest

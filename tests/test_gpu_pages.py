@@ -1,4 +1,4 @@
-"""Parity of the page operations (section 2.2 / 2.3) against the FP64 oracle, through the
+"""Parity of the page operations (sections 2.2-2.4) against the FP64 oracle, through the
 C ABI, on several tiles plus a ragged tail, in every supported layout, and at the full
 1e7-page batch size on sampled pages."""
 import numpy as np
