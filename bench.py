@@ -18,6 +18,10 @@ Other workloads (one JSON line each, same contract):
   --workload batch   64 groups of pages of orders 2..4, sizes 10^U(3,6) (about 9.3 million
                      pages), FP32 inverse + product per group in one persistent launch
                      replayed from a HIP graph, against one launch per group and operation
+  --workload serve   a Poisson stream of assembly jobs (200 jobs/s, 2-D FP64 / 3-D FP32,
+                     1e3..2e6 elements) through the serving loop: p50/p99 latency and
+                     throughput, fused + resident structures vs one launch per job without
+                     them, and a 10x overload run
 """
 from __future__ import annotations
 
@@ -73,7 +77,9 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=128, help="cubes per side of the CPU oracle sample")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
-    ap.add_argument("--workload", choices=["assembly", "pages", "batch"], default="assembly")
+    ap.add_argument("--workload", choices=["assembly", "pages", "batch", "serve"], default="assembly")
+    ap.add_argument("--jobs", type=int, default=1000, help="jobs of the serving trace")
+    ap.add_argument("--rate", type=float, default=200.0, help="arrival rate of the serving trace (jobs/s)")
     ap.add_argument("--tuner-cache", default=None, help="JSON schedule cache of the batch workload")
     return ap.parse_args()
 
@@ -273,6 +279,100 @@ def run_batch(args):
     print(json.dumps(out))
 
 
+def run_serve(args):
+    """Poisson stream of assembly jobs through the serving loop."""
+    import numpy as np
+    import torch
+
+    from paper_2404_16039_amd import gen
+    from paper_2404_16039_amd import lib as L
+
+    torch.cuda.set_device(0)
+    trace = gen.serving_trace(args.jobs, rate=args.rate)
+    elems_of, meshes = {}, []
+    t_gen = time.perf_counter()
+    for j in trace:  # meshes in host memory before the clock starts (coordinates pinned)
+        if j["dim"] == 2:
+            c, e, _ = gen.square_mesh(j["n"], seed_sub=j["id"], stream=gen.STREAM_SERVE)
+        else:
+            c, e, _ = gen.cube_mesh(j["n"], seed_sub=j["id"], stream=gen.STREAM_SERVE, with_faces=False)
+        key = (j["dim"] << 32) | j["n"]
+        e = elems_of.setdefault(key, e)
+        meshes.append((torch.from_numpy(c).pin_memory(), e, key))
+    t_gen = time.perf_counter() - t_gen
+    total_el = sum(m[1].shape[0] for m in meshes)
+    n_out = min(64, len(trace))  # these jobs also copy their values back (pinned outputs)
+    outs = []
+    for j in trace[:n_out]:
+        cnt = gen.square_counts(j["n"]) if j["dim"] == 2 else gen.kuhn_counts(j["n"])
+        dt = torch.float64 if j["dim"] == 2 else torch.float32
+        outs.append((torch.empty(cnt["nnz"], dtype=dt).pin_memory(), torch.empty(cnt["nnz"], dtype=dt).pin_memory()))
+    budget = 64 << 30
+
+    def replay(flags, speed):
+        srv = L.Server(budget, 256, flags)
+        t0 = srv.now() + 0.05
+        tickets = []
+        for k, j in enumerate(trace):
+            at = t0 + j["t"] / speed
+            while srv.now() < at:
+                pass
+            c, e, key = meshes[k]
+            prec = L.F64 if j["dim"] == 2 else L.F32
+            vk, vm = outs[k] if k < n_out else (None, None)
+            tickets.append(srv.submit(j["dim"], prec, c, e, topology=key, arrival=at, valsK=vk, valsM=vm))
+        srv.drain()
+        st = srv.stats()
+        res = [srv.poll(t) for t in tickets]
+        srv.close()
+        bad = [r for r in res if r["status"] != 0]
+        if bad:
+            raise RuntimeError(f"{len(bad)} serving jobs failed, first status {bad[0]['status']}")
+        copy = [r["copied"] - r["finished"] for r in res[:n_out]]
+        return {"jobs": st["completed"], "elements": st["elements"],
+                "latency_ms": {"p50": st["latency_p50"] * 1e3, "p99": st["latency_p99"] * 1e3,
+                               "mean": st["latency_mean"] * 1e3, "max": st["latency_max"] * 1e3},
+                "jobs_per_s": st["jobs_per_s"], "elements_per_s": st["elements_per_s"],
+                "copy_back_ms_median": float(np.median(copy)) * 1e3 if copy else None,
+                "ticks": st["ticks"], "launches": st["launches"], "max_batch": st["max_batch"],
+                "structure_hits": st["cache_hits"], "structure_misses": st["cache_misses"],
+                "hbm_high_water_bytes": st["hbm_high_water"], "span_s": st["last_finish"] - st["first_arrival"]}
+
+    served = replay(0, 1.0)
+    plain = replay(L.SERVER_NOFUSE | L.SERVER_NOCACHE, 1.0)
+    overload = replay(0, 10.0)
+    out = {
+        "metric": "P1 elements assembled/s under a Poisson stream of assembly jobs (+ p50/p99 job latency)",
+        "value": served["elements_per_s"], "unit": "elements/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": served["span_s"] * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (2-D jobs) / f32 (3-D jobs)", "data": "synthetic",
+        "config": {"workload": "%d jobs, Poisson arrivals %.0f jobs/s, dim 2 (FP64) or 3 (FP32 + FP64 fallback) "
+                               "with p = 1/2, 10^U(3, log10 2e6) elements, jittered structured meshes, "
+                               "64 GiB budget, 256 slots" % (len(trace), args.rate),
+                   "elements": total_el, "mesh_generation_s": round(t_gen, 1)},
+        "served": served, "one_launch_per_job_no_resident_structures": plain, "overload_10x": overload,
+        "roofline": None,
+        "roofline_note": "latency-bound job stream; the kernels' rooflines are those of the assembly workload",
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        t1 = time.perf_counter()
+        done = 0
+        for k, j in enumerate(trace):
+            c, e, _ = meshes[k]
+            cn = c.numpy()
+            el = oracle.p1_elements(cn, e)
+            oracle.assemble(e, cn.shape[0], el["Ke"], el["Me"], el["Kabs"])
+            done += e.shape[0]
+            if time.perf_counter() - t1 > 10.0:
+                break
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": done / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+                               "sample": "FP64 oracle element matrices + sparse assembly of the first %d jobs of the "
+                                         "trace (%d elements), single thread, %.1f s" % (k + 1, done, dt)}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -284,6 +384,8 @@ def main():
         return run_pages(args)
     if args.workload == "batch":
         return run_batch(args)
+    if args.workload == "serve":
+        return run_serve(args)
 
     import numpy as np
     import torch

@@ -290,6 +290,87 @@ pf_status pf_plan_info(const pf_plan* plan, int64_t* ntiles, int32_t* grid, int3
 
 void pf_plan_destroy(pf_plan* plan);
 
+/* ----------------------------------------------------------------------------------
+ * Serving loop: assembly jobs (the section 3.6 K and M of one P1 mesh each) submitted
+ * from host memory are admitted by a device-memory budget and a slot limit, and every
+ * scheduler tick runs the numeric phase of all jobs admitted in that tick as one
+ * launch per (dimension, precision) class.  Meshes with the same non-zero topology key
+ * share their connectivity and CSR structure, which stay resident (least recently used
+ * structures are evicted when the budget needs room).
+ *
+ * A server owns one scheduler thread and one HIP stream on the device that is current
+ * when it is created.  Per job: host-to-device copy of the coordinates (and of the
+ * connectivity plus the symbolic phase when the topology is not resident), the numeric
+ * phase, then the device-to-host copy of the values when output buffers are given.
+ * Times are seconds on the server clock (pf_server_now, steady clock, 0 at creation).
+ * Latency = end of the numeric phase - arrival; the copy back is reported apart.
+ * Job values are bitwise those of pf_csr_symbolic + pf_assemble on the same mesh, alone
+ * or in any batch.  Coefficients are 1 (no cK/cM).
+ * ---------------------------------------------------------------------------------- */
+typedef struct pf_server pf_server;
+
+enum { PF_SERVER_NOFUSE = 1, PF_SERVER_NOCACHE = 2 };
+
+typedef struct {
+    int32_t dim;             /* 2 (triangles) or 3 (tetrahedra)                               */
+    int32_t prec;            /* pf_dtype of the arithmetic and of the values                  */
+    int64_t nn, ne;          /* nodes, elements (both > 0)                                     */
+    const double* coords;    /* HOST nn x dim, row-major (pinned memory: asynchronous copy)    */
+    const int32_t* elems;    /* HOST ne x (dim+1), 0-based                                     */
+    uint64_t topology;       /* non-zero: jobs with equal keys have identical elems            */
+    double arrival;          /* arrival time on the server clock; < 0: the time of submission   */
+    pf_fallback fb;          /* routing of FP32 jobs                                           */
+    void* valsK;             /* HOST output, nullable: nnz values of K in CSR order            */
+    void* valsM;             /* HOST output, nullable: nnz values of M                         */
+    int64_t vals_cap;        /* capacity of valsK / valsM in values (PF_ELIMIT if nnz exceeds) */
+} pf_job;
+
+typedef struct {
+    int32_t status;          /* pf_status of the job (valid once done)                       */
+    int32_t done;            /* 1 once the job has finished (values copied back)              */
+    int64_t nnz;             /* nonzeros of the job's CSR structure                           */
+    int64_t routed;          /* elements recomputed in FP64                                   */
+    double arrival, admitted, finished, copied;  /* server clock                             */
+} pf_job_result;
+
+typedef struct {
+    int64_t submitted, completed, failed;
+    int64_t elements;                  /* elements of the completed jobs                     */
+    int64_t ticks, launches, max_batch;
+    int64_t cache_hits, cache_misses, evictions;
+    double latency_p50, latency_p99, latency_mean, latency_max;  /* seconds               */
+    double first_arrival, last_finish; /* server clock                                        */
+    double jobs_per_s, elements_per_s; /* completed work over [first_arrival, last_finish]    */
+    int64_t hbm_in_use, hbm_high_water;  /* accounted device bytes                            */
+} pf_stats;
+
+/* Create a server with a device-memory budget (bytes of job inputs, outputs and resident
+ * structures, estimated before the structure is built and exact afterwards) and at most
+ * max_slots jobs in flight.  flags: PF_SERVER_NOFUSE (one numeric launch per job),
+ * PF_SERVER_NOCACHE (no resident structures: every job builds and frees its own). */
+pf_status pf_server_create(size_t hbm_budget, int32_t max_slots, int32_t flags, pf_server** out);
+
+/* Seconds since the server was created (steady clock). */
+double pf_server_now(const pf_server* srv);
+
+/* Queue a job (host call; the host arrays must stay valid until the job is done).
+ * PF_EINVAL / PF_EORDER / PF_EDTYPE for invalid jobs, PF_EBUDGET if the job alone can
+ * never fit the budget.  Jobs are admitted in submission order. */
+pf_status pf_server_submit(pf_server* srv, const pf_job* job, uint64_t* ticket);
+
+/* State of a job; PF_EINVAL for an unknown ticket.  wait blocks until it is done. */
+pf_status pf_server_poll(pf_server* srv, uint64_t ticket, pf_job_result* out);
+pf_status pf_server_wait(pf_server* srv, uint64_t ticket, pf_job_result* out);
+
+/* Block until every submitted job is done. */
+pf_status pf_server_drain(pf_server* srv);
+
+/* Counters and latency percentiles over the completed jobs. */
+pf_status pf_server_stats(pf_server* srv, pf_stats* out);
+
+/* Finish every submitted job, stop the scheduler thread and free all device memory. */
+void pf_server_destroy(pf_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

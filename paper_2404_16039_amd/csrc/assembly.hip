@@ -18,6 +18,7 @@
 // vectors, and the contributions are summed exactly (rounded onto a fixed grid first), so
 // the result is bitwise reproducible whatever the order of the atomic adds.
 #include "p1elem.hpp"
+#include "internal.hpp"
 
 #include <algorithm>
 #include <new>
@@ -613,13 +614,14 @@ constexpr size_t numeric_lds_bytes(int nr, int wmax) {
 //   phase 2  every slot converts its sum and stores it once (coalesced).
 // Entries and slots are dealt row-interleaved (item r + nr j), so the lanes of one
 // instruction work on different rows and their LDS atomics hit different addresses.
+// One block of NR rows starting at row r0 (the body of the numeric kernels).
 template <int DIM, typename T, bool COEF, int NR>
-__global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __restrict__ coords,
-                                                 const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
-                                                 const int32_t* __restrict__ adj_ptr, const int32_t* __restrict__ adj,
-                                                 const uint32_t* __restrict__ pk, const T* __restrict__ cK,
-                                                 const T* __restrict__ cM, T* __restrict__ valsK, T* __restrict__ valsM,
-                                                 Fallback fb, int64_t* d_counters, int wmax) {
+__device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const double* __restrict__ coords,
+                                              const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                                              const int32_t* __restrict__ adj_ptr, const int32_t* __restrict__ adj,
+                                              const uint32_t* __restrict__ pk, const T* __restrict__ cK,
+                                              const T* __restrict__ cM, T* __restrict__ valsK, T* __restrict__ valsM,
+                                              const Fallback& fb, int64_t* d_counters, int wmax) {
     constexpr int NLB = DIM + 1;
     using A = typename Exact<T>::acc;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -634,7 +636,6 @@ __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __res
     int32_t* dslot = ap + (NR + 1);                              // [NR + 1]
     int32_t* maxlen = dslot + (NR + 1);                          // [1]
 
-    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * NR;
     const int nr = static_cast<int>((r0 + NR < nn) ? NR : nn - r0);
     if (threadIdx.x <= nr) {
         rp[threadIdx.x] = row_ptr[r0 + threadIdx.x];
@@ -777,6 +778,36 @@ __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __res
     }
 }
 
+template <int DIM, typename T, bool COEF, int NR>
+__global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __restrict__ coords,
+                                                 const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                                                 const int32_t* __restrict__ adj_ptr, const int32_t* __restrict__ adj,
+                                                 const uint32_t* __restrict__ pk, const T* __restrict__ cK,
+                                                 const T* __restrict__ cM, T* __restrict__ valsK, T* __restrict__ valsM,
+                                                 Fallback fb, int64_t* d_counters, int wmax) {
+    numeric_block<DIM, T, COEF, NR>(static_cast<int64_t>(blockIdx.x) * NR, nn, coords, row_ptr, col_idx, adj_ptr, adj,
+                                    pk, cK, cM, valsK, valsM, fb, d_counters, wmax);
+}
+
+// The numeric phase of several meshes in one launch: block b belongs to the job whose
+// block range holds b (binary search over the jobs' first blocks); every job keeps its own
+// structure, coordinates, outputs, routing thresholds and counters, and its rows are
+// computed exactly as by k_numeric, so a job's values do not depend on its batch.
+template <int DIM, typename T, int NR>
+__global__ __launch_bounds__(NBT) void k_numeric_jobs(const NumericJob* __restrict__ jobs, int njobs, int wmax) {
+    int lo = 0, hi = njobs - 1;
+    const int64_t b = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].block0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const NumericJob& j = jobs[lo];
+    numeric_block<DIM, T, false, NR>((b - j.block0) * NR, j.nn, j.coords, j.row_ptr, j.col_idx, j.adj_ptr, j.adj, j.pk,
+                                     nullptr, nullptr, static_cast<T*>(j.valsK), static_cast<T*>(j.valsM), j.fb,
+                                     j.counters, wmax);
+}
+
 // ---------------------------------------------------------------------------- host
 namespace {
 
@@ -835,6 +866,76 @@ pf_status numeric_dispatch(const pf_csr* c, const double* coords, const void* cK
 }
 
 }  // namespace
+
+// rows per block of a job's numeric phase: 16 when its largest window fits the LDS budget
+// and its longest adjacency list fits the item budget, else 4 (as pf_assemble chooses)
+template <int DIM, typename T>
+int numeric_rows(const pf_csr* c) {
+    return (numeric_lds_bytes<DIM, T>(NR_BIG, c->wmax_big) <= LDS_BYTES && c->max_adj <= NITEMS * NBT / NR_BIG)
+               ? NR_BIG
+               : NR_SMALL;
+}
+
+int numeric_class(const pf_csr* c, pf_dtype prec) {
+    if (c->dim == 3) return prec == PF_F32 ? numeric_rows<3, float>(c) : numeric_rows<3, double>(c);
+    return prec == PF_F32 ? numeric_rows<2, float>(c) : numeric_rows<2, double>(c);
+}
+
+int64_t numeric_blocks(const pf_csr* c, pf_dtype prec) { return ceil_div(c->nn, numeric_class(c, prec)); }
+
+void numeric_describe(const pf_csr* c, const double* coords, void* valsK, void* valsM, const pf_fallback* fb,
+                      int64_t* counters, int64_t block0, NumericJob* out) {
+    out->nn = c->nn;
+    out->coords = coords;
+    out->row_ptr = c->row_ptr;
+    out->col_idx = c->col_idx;
+    out->adj_ptr = c->adj_ptr;
+    out->adj = c->adj;
+    out->pk = c->pk;
+    out->valsK = valsK;
+    out->valsM = valsM;
+    out->counters = counters;
+    out->fb = make_fallback(fb);
+    out->block0 = block0;
+}
+
+int numeric_wmax(const pf_csr* c, int nr) { return nr == NR_BIG ? c->wmax_big : c->wmax_small; }
+
+template <int DIM, typename T, int NR>
+pf_status launch_jobs(const NumericJob* d_jobs, int njobs, int64_t nblocks, int wmax, hipStream_t s) {
+    const size_t shm = numeric_lds_bytes<DIM, T>(NR, wmax);
+    hipLaunchKernelGGL((k_numeric_jobs<DIM, T, NR>), dim3(static_cast<unsigned>(nblocks)), dim3(NBT), shm, s, d_jobs,
+                       njobs, wmax);
+    return launch_check("numeric batch");
+}
+
+pf_status numeric_launch_many(int dim, pf_dtype prec, int nr, const NumericJob* d_jobs, int njobs, int64_t nblocks,
+                              int wmax, hipStream_t s) {
+    if (njobs <= 0 || nblocks <= 0) return PF_OK;
+    if (nblocks >= (int64_t(1) << 31)) return fail(PF_ELIMIT, "numeric batch: too many row blocks");
+    if (dim == 3) {
+        if (prec == PF_F32)
+            return nr == NR_BIG ? launch_jobs<3, float, NR_BIG>(d_jobs, njobs, nblocks, wmax, s)
+                                : launch_jobs<3, float, NR_SMALL>(d_jobs, njobs, nblocks, wmax, s);
+        return nr == NR_BIG ? launch_jobs<3, double, NR_BIG>(d_jobs, njobs, nblocks, wmax, s)
+                            : launch_jobs<3, double, NR_SMALL>(d_jobs, njobs, nblocks, wmax, s);
+    }
+    if (prec == PF_F32)
+        return nr == NR_BIG ? launch_jobs<2, float, NR_BIG>(d_jobs, njobs, nblocks, wmax, s)
+                            : launch_jobs<2, float, NR_SMALL>(d_jobs, njobs, nblocks, wmax, s);
+    return nr == NR_BIG ? launch_jobs<2, double, NR_BIG>(d_jobs, njobs, nblocks, wmax, s)
+                        : launch_jobs<2, double, NR_SMALL>(d_jobs, njobs, nblocks, wmax, s);
+}
+
+size_t csr_bytes(const pf_csr* c) {
+    return static_cast<size_t>(c->cap_adj_ptr + c->cap_row_ptr + c->cap_cnt + c->cap_adj + c->cap_nnz) * 4 +
+           static_cast<size_t>(c->cap_pk) * 4 + static_cast<size_t>(c->cap_bsum + c->cap_info) * 8;
+}
+
+int64_t csr_nnz(const pf_csr* c) { return c->built ? c->nnz : -1; }
+int64_t csr_nn(const pf_csr* c) { return c->nn; }
+int csr_dim(const pf_csr* c) { return c->dim; }
+
 }  // namespace pf
 
 using namespace pf;

@@ -1,0 +1,40 @@
+// internal.hpp -- declarations shared between the library's own translation units (not
+// part of the C ABI): the multi-mesh numeric assembly used by the serving loop.
+#pragma once
+
+#include "common.hpp"
+
+namespace pf {
+
+// Device descriptor of one mesh in a multi-mesh numeric launch (k_numeric_jobs).
+struct NumericJob {
+    int64_t nn;
+    const double* coords;
+    const int32_t* row_ptr;
+    const int32_t* col_idx;
+    const int32_t* adj_ptr;
+    const int32_t* adj;
+    const uint32_t* pk;
+    void* valsK;
+    void* valsM;
+    int64_t* counters;
+    Fallback fb;
+    int64_t block0;  // first block of this job in the launch
+};
+
+// rows per block (16 or 4) that pf_assemble would use for this structure and precision
+int numeric_class(const pf_csr* c, pf_dtype prec);
+int64_t numeric_blocks(const pf_csr* c, pf_dtype prec);
+int numeric_wmax(const pf_csr* c, int nr);
+void numeric_describe(const pf_csr* c, const double* coords, void* valsK, void* valsM, const pf_fallback* fb,
+                      int64_t* counters, int64_t block0, NumericJob* out);
+// one launch over njobs descriptors (device array) of the same dim, precision and rows per
+// block; wmax = the largest window of those jobs, nblocks = the total block count
+pf_status numeric_launch_many(int dim, pf_dtype prec, int nr, const NumericJob* d_jobs, int njobs, int64_t nblocks,
+                              int wmax, hipStream_t s);
+size_t csr_bytes(const pf_csr* c);
+int64_t csr_nnz(const pf_csr* c);
+int64_t csr_nn(const pf_csr* c);
+int csr_dim(const pf_csr* c);
+
+}  // namespace pf

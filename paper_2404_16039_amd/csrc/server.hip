@@ -1,0 +1,607 @@
+// server.hip -- serving loop for assembly jobs: admission by a device-memory budget and a
+// slot limit, resident connectivity and CSR structures keyed by topology, and one fused
+// numeric launch per (dimension, precision, rows-per-block) class in every scheduler tick.
+//
+// The scheduler thread owns every HIP call of the server (one compute stream plus one
+// stream for structure builds, which synchronise).  Public calls only touch host state
+// under the server mutex.  Job lifecycle:
+//   pending --admit--> in flight (inputs copied, numeric launched, copy-back queued)
+//           --numeric event--> finished (latency taken) --copy event--> done (memory freed)
+#include "internal.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+using namespace pf;
+
+namespace {
+
+constexpr int RING = 4;  // job-table staging buffers in flight
+
+struct Topo {
+    uint64_t key = 0;
+    int dim = 0;
+    int64_t nn = 0, ne = 0;
+    int32_t* d_elems = nullptr;
+    pf_csr* csr = nullptr;
+    size_t bytes = 0;  // accounted device bytes (estimate until built)
+    int refs = 0;
+    uint64_t last_use = 0;
+    bool built = false;
+    bool cached = false;
+};
+
+struct TickEvents {
+    hipEvent_t num = nullptr, copy = nullptr;
+    ~TickEvents() {
+        if (num) (void)hipEventDestroy(num);
+        if (copy) (void)hipEventDestroy(copy);
+    }
+};
+
+struct SJob {
+    uint64_t ticket = 0;
+    pf_job spec{};
+    pf_job_result res{};
+    Topo* topo = nullptr;
+    double* d_coords = nullptr;
+    void* d_valsK = nullptr;
+    void* d_valsM = nullptr;
+    int64_t* d_ctr = nullptr;
+    int slot = -1;  // row of the pinned counter block
+    size_t bytes = 0;
+    int stage = 0;  // 0 pending, 1 in flight, 2 numeric done, 3 done
+    std::shared_ptr<TickEvents> ev;
+};
+
+size_t elem_bytes(int32_t prec) { return prec == PF_F32 ? 4 : 8; }
+
+// upper bound of the nonzeros before the structure is built
+int64_t nnz_bound(const pf_job& j) {
+    const int64_t nlb = j.dim + 1;
+    return std::min<int64_t>(j.ne * nlb * nlb, j.nn * 64);
+}
+
+size_t topo_estimate(const pf_job& j) {
+    const int64_t nlb = j.dim + 1;
+    return static_cast<size_t>(j.ne * nlb * 4)                                     // elems
+           + static_cast<size_t>(12 * (j.nn + 1) + 8 * j.ne * nlb + 4 * nnz_bound(j))  // structure
+           + 4096;
+}
+
+size_t job_estimate(const pf_job& j, int64_t nnz) {
+    return static_cast<size_t>(j.nn * j.dim * 8) + 2 * static_cast<size_t>(nnz) * elem_bytes(j.prec) + 64;
+}
+
+}  // namespace
+
+struct pf_server {
+    size_t budget = 0;
+    int max_slots = 0;
+    int flags = 0;
+    int device = 0;
+    std::chrono::steady_clock::time_point t0;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<SJob*> pending;
+    std::vector<SJob*> active;
+    std::unordered_map<uint64_t, std::unique_ptr<SJob>> jobs;
+    std::map<uint64_t, Topo*> cache;
+    uint64_t next_ticket = 1, use_clock = 0;
+    int64_t unfinished = 0;  // submitted and not done (pending, being admitted, or in flight)
+    bool stop = false;
+
+    size_t used = 0, high = 0;
+    pf_stats st{};
+    std::vector<double> lat;
+
+    hipStream_t s = nullptr, sbuild = nullptr;
+    NumericJob* h_tab[RING] = {};
+    NumericJob* d_tab[RING] = {};
+    hipEvent_t tab_ev[RING] = {};
+    bool tab_used[RING] = {};
+    int ring = 0;
+    int64_t* h_ctr = nullptr;  // pinned, 4 per slot
+    std::vector<int> free_slots;
+    std::thread th;
+
+    double now() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+namespace {
+
+void account(pf_server* S, long long delta) {
+    S->used = static_cast<size_t>(static_cast<long long>(S->used) + delta);
+    S->high = std::max(S->high, S->used);
+}
+
+void destroy_topo(pf_server* S, Topo* t) {
+    if (t->csr) pf_csr_destroy(t->csr);
+    if (t->d_elems) (void)hipFree(t->d_elems);
+    account(S, -static_cast<long long>(t->bytes));
+    delete t;
+}
+
+// evict resident structures nobody uses, least recently used first, until `need` fits
+void make_room(pf_server* S, size_t need) {
+    while (S->used + need > S->budget) {
+        Topo* victim = nullptr;
+        for (auto& kv : S->cache)
+            if (kv.second->refs == 0 && (!victim || kv.second->last_use < victim->last_use)) victim = kv.second;
+        if (!victim) return;
+        S->cache.erase(victim->key);
+        destroy_topo(S, victim);
+        ++S->st.evictions;
+    }
+}
+
+// structure of a job: resident (cache hit), or new (estimate accounted; built later).
+// `cacheable` says whether a new structure may enter the cache under the job's key.
+Topo* topo_for(pf_server* S, SJob* j, size_t& extra, bool& cacheable) {
+    extra = 0;
+    cacheable = j->spec.topology != 0 && !(S->flags & PF_SERVER_NOCACHE);
+    if (cacheable) {
+        auto it = S->cache.find(j->spec.topology);
+        if (it != S->cache.end()) {
+            if (it->second->dim == j->spec.dim && it->second->nn == j->spec.nn && it->second->ne == j->spec.ne)
+                return it->second;
+            cacheable = false;  // the key names another mesh: this job gets a private structure
+        }
+    }
+    extra = topo_estimate(j->spec);
+    return nullptr;
+}
+
+pf_status build_topo(pf_server* S, SJob* j, Topo* t) {
+    const pf_job& q = j->spec;
+    const size_t eb = static_cast<size_t>(q.ne * (q.dim + 1)) * 4;
+    PF_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&t->d_elems), eb));
+    PF_HIP_TRY(hipMemcpyAsync(t->d_elems, q.elems, eb, hipMemcpyHostToDevice, S->sbuild));
+    pf_status st = pf_csr_create(&t->csr);
+    if (st != PF_OK) return st;
+    st = pf_csr_symbolic(t->csr, q.dim, q.nn, q.ne, t->d_elems, S->sbuild);  // synchronises sbuild
+    if (st != PF_OK) return st;
+    const size_t exact = eb + csr_bytes(t->csr);
+    std::lock_guard<std::mutex> lk(S->mu);
+    account(S, static_cast<long long>(exact) - static_cast<long long>(t->bytes));
+    t->bytes = exact;
+    t->built = true;
+    return PF_OK;
+}
+
+void finish(pf_server* S, SJob* j, pf_status status) {
+    // caller holds the lock
+    j->res.status = status;
+    j->res.done = 1;
+    j->stage = 3;
+    --S->unfinished;
+    if (status == PF_OK) {
+        ++S->st.completed;
+        S->st.elements += j->spec.ne;
+        S->lat.push_back(j->res.finished - j->res.arrival);
+        if (S->st.completed == 1 || j->res.arrival < S->st.first_arrival) S->st.first_arrival = j->res.arrival;
+        S->st.last_finish = std::max(S->st.last_finish, j->res.finished);
+    } else {
+        ++S->st.failed;
+    }
+}
+
+// release a job's device memory (stream-ordered) and its structure reference
+void release(pf_server* S, SJob* j) {
+    if (j->d_coords) (void)hipFreeAsync(j->d_coords, S->s);
+    if (j->d_valsK) (void)hipFreeAsync(j->d_valsK, S->s);
+    if (j->d_valsM) (void)hipFreeAsync(j->d_valsM, S->s);
+    if (j->d_ctr) (void)hipFreeAsync(j->d_ctr, S->s);
+    j->d_coords = nullptr;
+    j->d_valsK = j->d_valsM = nullptr;
+    j->d_ctr = nullptr;
+    account(S, -static_cast<long long>(j->bytes));
+    j->bytes = 0;
+    if (j->slot >= 0) S->free_slots.push_back(j->slot);
+    j->slot = -1;
+    if (Topo* t = j->topo) {
+        --t->refs;
+        if (!t->cached && t->refs == 0) destroy_topo(S, t);
+        j->topo = nullptr;
+    }
+}
+
+// Stage 1 of a tick, under the lock: move admissible pending jobs into `batch`.
+void admit(pf_server* S, std::vector<SJob*>& batch) {
+    const double t = S->now();
+    while (!S->pending.empty() && static_cast<int>(S->active.size() + batch.size()) < S->max_slots) {
+        SJob* j = S->pending.front();
+        if (j->res.arrival > t) break;  // not arrived yet (a pre-submitted trace)
+        size_t extra = 0;
+        bool cacheable = false;
+        Topo* hit = topo_for(S, j, extra, cacheable);
+        const int64_t nnz = (hit && hit->built) ? csr_nnz(hit->csr) : nnz_bound(j->spec);
+        const size_t need = job_estimate(j->spec, nnz) + extra;
+        if (S->used + need > S->budget) make_room(S, need);
+        if (S->used + need > S->budget) break;  // head of the queue waits for memory
+        S->pending.pop_front();
+        if (hit) {
+            j->topo = hit;
+            ++S->st.cache_hits;
+        } else {
+            Topo* t = new Topo();
+            t->key = j->spec.topology;
+            t->dim = j->spec.dim;
+            t->nn = j->spec.nn;
+            t->ne = j->spec.ne;
+            t->bytes = extra;
+            t->cached = cacheable;
+            account(S, static_cast<long long>(extra));
+            if (t->cached) S->cache[t->key] = t;
+            j->topo = t;
+            ++S->st.cache_misses;
+        }
+        j->topo->refs++;
+        j->topo->last_use = ++S->use_clock;
+        j->bytes = job_estimate(j->spec, nnz);
+        account(S, static_cast<long long>(j->bytes));
+        j->slot = S->free_slots.back();
+        S->free_slots.pop_back();
+        j->res.admitted = t;
+        j->stage = 1;
+        batch.push_back(j);
+    }
+}
+
+// Stage 2 of a tick, without the lock: structures, inputs, fused numeric launches, copies.
+// Returns the jobs that failed (with their status) so the caller can finish them.
+struct TickCounts {
+    int64_t launches = 0, launched = 0;
+};
+
+void run_tick(pf_server* S, std::vector<SJob*>& batch, std::vector<std::pair<SJob*, pf_status>>& failed,
+              TickCounts& tc) {
+    std::vector<SJob*> ok;
+    for (SJob* j : batch) {
+        const pf_job& q = j->spec;
+        pf_status st = PF_OK;
+        Topo* t = j->topo;
+        if (!t->built) {
+            st = build_topo(S, j, t);
+            if (st != PF_OK) {
+                std::lock_guard<std::mutex> lk(S->mu);
+                if (t->cached) {  // a failed build never serves another job
+                    S->cache.erase(t->key);
+                    t->cached = false;
+                }
+            }
+        }
+        if (st == PF_OK) {
+            const int64_t nnz = csr_nnz(t->csr);
+            if ((q.valsK || q.valsM) && nnz > q.vals_cap) st = fail(PF_ELIMIT, "pf_server: vals_cap below nnz");
+            if (st == PF_OK) {
+                const size_t es = elem_bytes(q.prec);
+                const size_t exact = job_estimate(q, nnz);
+                {
+                    std::lock_guard<std::mutex> lk(S->mu);
+                    account(S, static_cast<long long>(exact) - static_cast<long long>(j->bytes));
+                    j->bytes = exact;
+                    j->res.nnz = nnz;
+                }
+                hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&j->d_coords), q.nn * q.dim * 8, S->s);
+                if (e == hipSuccess) e = hipMallocAsync(&j->d_valsK, std::max<size_t>(nnz * es, 16), S->s);
+                if (e == hipSuccess) e = hipMallocAsync(&j->d_valsM, std::max<size_t>(nnz * es, 16), S->s);
+                if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&j->d_ctr), 32, S->s);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(j->d_coords, q.coords, q.nn * q.dim * 8, hipMemcpyHostToDevice, S->s);
+                if (e == hipSuccess) e = hipMemsetAsync(j->d_ctr, 0, 32, S->s);
+                if (e != hipSuccess)
+                    st = fail(e == hipErrorOutOfMemory ? PF_ENOMEM : PF_EHIP,
+                              std::string("pf_server: job inputs: ") + hipGetErrorString(e));
+            }
+        }
+        if (st == PF_OK) ok.push_back(j);
+        else failed.emplace_back(j, st);
+    }
+    if (ok.empty()) return;
+    auto ev = std::make_shared<TickEvents>();
+    (void)hipEventCreateWithFlags(&ev->num, hipEventDisableTiming);
+    (void)hipEventCreateWithFlags(&ev->copy, hipEventDisableTiming);
+    std::vector<SJob*> launched;
+    if (S->flags & PF_SERVER_NOFUSE) {
+        for (SJob* j : ok) {
+            pf_status st = pf_assemble(j->topo->csr, static_cast<pf_dtype>(j->spec.prec), j->d_coords, nullptr,
+                                       nullptr, nullptr, j->d_valsK, j->d_valsM, &j->spec.fb, j->d_ctr, S->s);
+            if (st == PF_OK) {
+                launched.push_back(j);
+                ++tc.launches;
+            } else {
+                failed.emplace_back(j, st);
+            }
+        }
+    } else {
+        // group by class, fill the ring's staging table, one copy, one launch per class
+        const int r = S->ring;
+        S->ring = (S->ring + 1) % RING;
+        if (S->tab_used[r]) (void)hipEventSynchronize(S->tab_ev[r]);
+        std::map<std::tuple<int, int, int>, std::vector<SJob*>> cls;
+        for (SJob* j : ok) {
+            const pf_dtype pr = static_cast<pf_dtype>(j->spec.prec);
+            if (csr_nn(j->topo->csr) == 0) {
+                launched.push_back(j);
+                continue;
+            }
+            cls[{j->spec.dim, static_cast<int>(pr), numeric_class(j->topo->csr, pr)}].push_back(j);
+        }
+        int n = 0;
+        struct Launch {
+            int dim, prec, nr, first, count, wmax;
+            int64_t blocks;
+        };
+        std::vector<Launch> ls;
+        for (auto& kv : cls) {
+            Launch L{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), n, 0, 0, 0};
+            for (SJob* j : kv.second) {
+                const pf_dtype pr = static_cast<pf_dtype>(j->spec.prec);
+                numeric_describe(j->topo->csr, j->d_coords, j->d_valsK, j->d_valsM, &j->spec.fb, j->d_ctr, L.blocks,
+                                 &S->h_tab[r][n]);
+                L.blocks += numeric_blocks(j->topo->csr, pr);
+                L.wmax = std::max(L.wmax, numeric_wmax(j->topo->csr, L.nr));
+                ++n;
+                ++L.count;
+            }
+            ls.push_back(L);
+        }
+        hipError_t e = hipMemcpyAsync(S->d_tab[r], S->h_tab[r], sizeof(NumericJob) * n, hipMemcpyHostToDevice, S->s);
+        (void)hipEventRecord(S->tab_ev[r], S->s);
+        S->tab_used[r] = true;
+        for (const Launch& L : ls) {
+            pf_status st = e == hipSuccess ? numeric_launch_many(L.dim, static_cast<pf_dtype>(L.prec), L.nr,
+                                                                 S->d_tab[r] + L.first, L.count, L.blocks, L.wmax, S->s)
+                                           : fail(PF_EHIP, std::string("pf_server: job table: ") + hipGetErrorString(e));
+            for (auto& kv : cls)
+                if (std::get<0>(kv.first) == L.dim && std::get<1>(kv.first) == L.prec && std::get<2>(kv.first) == L.nr)
+                    for (SJob* j : kv.second) {
+                        if (st == PF_OK) launched.push_back(j);
+                        else failed.emplace_back(j, st);
+                    }
+            ++tc.launches;
+        }
+    }
+    (void)hipEventRecord(ev->num, S->s);
+    for (SJob* j : launched) {
+        const pf_job& q = j->spec;
+        const size_t bytes = static_cast<size_t>(j->res.nnz) * elem_bytes(q.prec);
+        if (q.valsK && bytes) (void)hipMemcpyAsync(q.valsK, j->d_valsK, bytes, hipMemcpyDeviceToHost, S->s);
+        if (q.valsM && bytes) (void)hipMemcpyAsync(q.valsM, j->d_valsM, bytes, hipMemcpyDeviceToHost, S->s);
+        (void)hipMemcpyAsync(S->h_ctr + 4 * j->slot, j->d_ctr, 32, hipMemcpyDeviceToHost, S->s);
+        j->ev = ev;
+    }
+    (void)hipEventRecord(ev->copy, S->s);
+    tc.launched = static_cast<int64_t>(launched.size());
+}
+
+void loop(pf_server* S) {
+    (void)hipSetDevice(S->device);
+    std::vector<SJob*> batch;
+    std::vector<std::pair<SJob*, pf_status>> failed;
+    for (;;) {
+        batch.clear();
+        failed.clear();
+        bool progress = false;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            if (S->stop && S->unfinished == 0) break;
+            if (S->pending.empty() && S->active.empty()) {
+                S->cv_work.wait_for(lk, std::chrono::milliseconds(2));
+                continue;
+            }
+            admit(S, batch);
+        }
+        if (!batch.empty()) {
+            TickCounts tc;
+            run_tick(S, batch, failed, tc);
+            progress = true;
+            std::lock_guard<std::mutex> lk(S->mu);
+            for (SJob* j : batch) S->active.push_back(j);
+            ++S->st.ticks;
+            S->st.launches += tc.launches;
+            S->st.max_batch = std::max(S->st.max_batch, tc.launched);
+        }
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            for (auto& f : failed) {
+                SJob* j = f.first;
+                S->active.erase(std::remove(S->active.begin(), S->active.end(), j), S->active.end());
+                j->res.finished = j->res.copied = S->now();
+                release(S, j);
+                finish(S, j, f.second);
+                progress = true;
+            }
+            const double t = S->now();
+            for (size_t i = 0; i < S->active.size();) {
+                SJob* j = S->active[i];
+                if (j->stage == 1 && j->ev && hipEventQuery(j->ev->num) == hipSuccess) {
+                    j->res.finished = t;
+                    j->stage = 2;
+                    progress = true;
+                }
+                if (j->stage == 2 && hipEventQuery(j->ev->copy) == hipSuccess) {
+                    j->res.copied = S->now();
+                    j->res.routed = S->h_ctr[4 * j->slot];
+                    release(S, j);
+                    finish(S, j, PF_OK);
+                    j->ev.reset();
+                    S->active[i] = S->active.back();
+                    S->active.pop_back();
+                    progress = true;
+                    continue;
+                }
+                ++i;
+            }
+            if (progress) S->cv_done.notify_all();
+        }
+        if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+}
+
+pf_status check_job(const pf_job* q) {
+    if (!q) return fail(PF_EINVAL, "pf_server_submit: job is NULL");
+    if (q->dim != 2 && q->dim != 3) return fail(PF_EORDER, "pf_server_submit: dim must be 2 or 3");
+    if (q->prec != PF_F32 && q->prec != PF_F64) return fail(PF_EDTYPE, "pf_server_submit: prec");
+    if (q->nn <= 0 || q->ne <= 0 || !q->coords || !q->elems)
+        return fail(PF_EINVAL, "pf_server_submit: empty mesh or NULL host arrays");
+    if (q->vals_cap < 0) return fail(PF_EINVAL, "pf_server_submit: negative vals_cap");
+    if (q->nn >= INT32_MAX || q->ne * (q->dim + 1) >= INT32_MAX)
+        return fail(PF_ELIMIT, "pf_server_submit: mesh too large for 32-bit indices");
+    return PF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pf_status pf_server_create(size_t hbm_budget, int32_t max_slots, int32_t flags, pf_server** out) {
+    if (!out) return fail(PF_EINVAL, "pf_server_create: out is NULL");
+    *out = nullptr;
+    if (max_slots < 1 || max_slots > 65536) return fail(PF_EINVAL, "pf_server_create: max_slots must be 1..65536");
+    if (hbm_budget == 0) return fail(PF_EINVAL, "pf_server_create: zero budget");
+    if (flags & ~(PF_SERVER_NOFUSE | PF_SERVER_NOCACHE)) return fail(PF_EINVAL, "pf_server_create: flags");
+    pf_server* S = new (std::nothrow) pf_server();
+    if (!S) return fail(PF_ENOMEM, "pf_server_create: host allocation");
+    S->budget = hbm_budget;
+    S->max_slots = max_slots;
+    S->flags = flags;
+    S->t0 = std::chrono::steady_clock::now();
+    hipError_t e = hipGetDevice(&S->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->sbuild, hipStreamNonBlocking);
+    for (int r = 0; r < RING && e == hipSuccess; ++r) {
+        e = hipHostMalloc(reinterpret_cast<void**>(&S->h_tab[r]), sizeof(NumericJob) * max_slots, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&S->d_tab[r]), sizeof(NumericJob) * max_slots);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&S->tab_ev[r], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&S->h_ctr), 32 * static_cast<size_t>(max_slots),
+                                           hipHostMallocDefault);
+    if (e != hipSuccess) {
+        pf_server_destroy(S);
+        return fail(PF_EHIP, std::string("pf_server_create: ") + hipGetErrorString(e));
+    }
+    for (int i = max_slots - 1; i >= 0; --i) S->free_slots.push_back(i);
+    try {
+        S->th = std::thread(loop, S);
+    } catch (...) {
+        pf_server_destroy(S);
+        return fail(PF_ENOMEM, "pf_server_create: cannot start the scheduler thread");
+    }
+    *out = S;
+    return PF_OK;
+}
+
+double pf_server_now(const pf_server* S) { return S ? S->now() : 0.0; }
+
+pf_status pf_server_submit(pf_server* S, const pf_job* q, uint64_t* ticket) {
+    if (!S) return fail(PF_EINVAL, "pf_server_submit: server is NULL");
+    pf_status st = check_job(q);
+    if (st != PF_OK) return st;
+    const size_t need = job_estimate(*q, nnz_bound(*q)) + topo_estimate(*q);
+    if (need > S->budget) return fail(PF_EBUDGET, "pf_server_submit: the job can never fit the memory budget");
+    auto j = std::make_unique<SJob>();
+    j->spec = *q;
+    j->res.arrival = q->arrival < 0 ? S->now() : q->arrival;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->stop) return fail(PF_ESTATE, "pf_server_submit: server is shutting down");
+    j->ticket = S->next_ticket++;
+    if (ticket) *ticket = j->ticket;
+    S->pending.push_back(j.get());
+    S->jobs[j->ticket] = std::move(j);
+    ++S->st.submitted;
+    ++S->unfinished;
+    S->cv_work.notify_one();
+    return PF_OK;
+}
+
+pf_status pf_server_poll(pf_server* S, uint64_t ticket, pf_job_result* out) {
+    if (!S) return fail(PF_EINVAL, "pf_server_poll: server is NULL");
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->jobs.find(ticket);
+    if (it == S->jobs.end()) return fail(PF_EINVAL, "pf_server_poll: unknown ticket");
+    if (out) *out = it->second->res;
+    return PF_OK;
+}
+
+pf_status pf_server_wait(pf_server* S, uint64_t ticket, pf_job_result* out) {
+    if (!S) return fail(PF_EINVAL, "pf_server_wait: server is NULL");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->jobs.find(ticket);
+    if (it == S->jobs.end()) return fail(PF_EINVAL, "pf_server_wait: unknown ticket");
+    SJob* j = it->second.get();
+    S->cv_done.wait(lk, [&] { return j->res.done != 0; });
+    if (out) *out = j->res;
+    return PF_OK;
+}
+
+pf_status pf_server_drain(pf_server* S) {
+    if (!S) return fail(PF_EINVAL, "pf_server_drain: server is NULL");
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->cv_done.wait(lk, [&] { return S->unfinished == 0; });
+    return PF_OK;
+}
+
+pf_status pf_server_stats(pf_server* S, pf_stats* out) {
+    if (!S || !out) return fail(PF_EINVAL, "pf_server_stats: NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    *out = S->st;
+    std::vector<double> l = S->lat;
+    std::sort(l.begin(), l.end());
+    auto pct = [&](double p) {
+        if (l.empty()) return 0.0;
+        const size_t k = std::min(l.size() - 1, static_cast<size_t>(p * (l.size() - 1) + 0.5));
+        return l[k];
+    };
+    out->latency_p50 = pct(0.50);
+    out->latency_p99 = pct(0.99);
+    out->latency_max = l.empty() ? 0.0 : l.back();
+    double sum = 0;
+    for (double x : l) sum += x;
+    out->latency_mean = l.empty() ? 0.0 : sum / l.size();
+    const double span = out->last_finish - out->first_arrival;
+    out->jobs_per_s = span > 0 ? out->completed / span : 0.0;
+    out->elements_per_s = span > 0 ? out->elements / span : 0.0;
+    out->hbm_in_use = static_cast<int64_t>(S->used);
+    out->hbm_high_water = static_cast<int64_t>(S->high);
+    return PF_OK;
+}
+
+void pf_server_destroy(pf_server* S) {
+    if (!S) return;
+    if (S->th.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->stop = true;
+        }
+        S->cv_work.notify_all();
+        S->th.join();
+    }
+    if (S->s) (void)hipStreamSynchronize(S->s);
+    for (auto& kv : S->cache) destroy_topo(S, kv.second);
+    S->cache.clear();
+    for (int r = 0; r < RING; ++r) {
+        if (S->h_tab[r]) (void)hipHostFree(S->h_tab[r]);
+        if (S->d_tab[r]) (void)hipFree(S->d_tab[r]);
+        if (S->tab_ev[r]) (void)hipEventDestroy(S->tab_ev[r]);
+    }
+    if (S->h_ctr) (void)hipHostFree(S->h_ctr);
+    if (S->sbuild) (void)hipStreamDestroy(S->sbuild);
+    if (S->s) (void)hipStreamDestroy(S->s);
+    delete S;
+}
+
+}  // extern "C"

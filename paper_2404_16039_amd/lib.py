@@ -75,6 +75,35 @@ class Schedule(C.Structure):
                 "order": {n: (self.order[n].lanes, self.order[n].staged, self.order[n].tile) for n in range(1, 5)}}
 
 
+class Job(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("prec", C.c_int32), ("nn", C.c_int64), ("ne", C.c_int64),
+                ("coords", C.c_void_p), ("elems", C.c_void_p), ("topology", C.c_uint64), ("arrival", C.c_double),
+                ("fb", Fallback), ("valsK", C.c_void_p), ("valsM", C.c_void_p), ("vals_cap", C.c_int64)]
+
+
+class JobResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("done", C.c_int32), ("nnz", C.c_int64), ("routed", C.c_int64),
+                ("arrival", C.c_double), ("admitted", C.c_double), ("finished", C.c_double),
+                ("copied", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64), ("elements", C.c_int64),
+                ("ticks", C.c_int64), ("launches", C.c_int64), ("max_batch", C.c_int64),
+                ("cache_hits", C.c_int64), ("cache_misses", C.c_int64), ("evictions", C.c_int64),
+                ("latency_p50", C.c_double), ("latency_p99", C.c_double), ("latency_mean", C.c_double),
+                ("latency_max", C.c_double), ("first_arrival", C.c_double), ("last_finish", C.c_double),
+                ("jobs_per_s", C.c_double), ("elements_per_s", C.c_double), ("hbm_in_use", C.c_int64),
+                ("hbm_high_water", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+SERVER_NOFUSE, SERVER_NOCACHE = 1, 2
 OP_INV, OP_MTIMES = 1, 2
 TUNE_CACHED, TUNE_FORCE, TUNE_DEFAULT = 0, 1, 2
 
@@ -116,6 +145,14 @@ _sig = {
     "pf_plan_launch": ([P, P, P], C.c_int),
     "pf_plan_info": ([P, C.POINTER(I64), C.POINTER(I32), C.POINTER(I32)], C.c_int),
     "pf_plan_destroy": ([P], None),
+    "pf_server_create": ([C.c_size_t, I32, I32, C.POINTER(P)], C.c_int),
+    "pf_server_now": ([P], C.c_double),
+    "pf_server_submit": ([P, C.POINTER(Job), C.POINTER(C.c_uint64)], C.c_int),
+    "pf_server_poll": ([P, C.c_uint64, C.POINTER(JobResult)], C.c_int),
+    "pf_server_wait": ([P, C.c_uint64, C.POINTER(JobResult)], C.c_int),
+    "pf_server_drain": ([P], C.c_int),
+    "pf_server_stats": ([P, C.POINTER(Stats)], C.c_int),
+    "pf_server_destroy": ([P], None),
 }
 for _name, (_args, _res) in _sig.items():
     _f = getattr(_lib, _name)
@@ -347,6 +384,82 @@ class Plan:
         if self._h:
             _lib.pf_plan_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------- serving
+def _host_ptr(x):
+    """Address of a host array: a CPU torch tensor (pinned for asynchronous copies) or a
+    C-contiguous numpy array."""
+    if x is None:
+        return None
+    if isinstance(x, torch.Tensor):
+        if x.is_cuda or not x.is_contiguous():
+            raise ValueError("server job arrays must be contiguous host tensors")
+        return x.data_ptr()
+    if not x.flags["C_CONTIGUOUS"]:
+        raise ValueError("server job arrays must be C-contiguous")
+    return x.ctypes.data
+
+
+class Server:
+    """Owner of a pf_server handle: assembly jobs from host memory, admitted by a device
+    memory budget, batched per scheduler tick, with resident structures per topology."""
+
+    def __init__(self, hbm_budget, max_slots=256, flags=0):
+        h = P()
+        _chk(_lib.pf_server_create(int(hbm_budget), int(max_slots), int(flags), C.byref(h)), "pf_server_create")
+        self._h = h
+        self._keep = {}
+
+    def now(self):
+        return _lib.pf_server_now(self._h)
+
+    def submit(self, dim, prec, coords, elems, topology=0, arrival=-1.0, fb=None, valsK=None, valsM=None):
+        nn, ne = coords.shape[0], elems.shape[0]
+        cap = 0
+        for v in (valsK, valsM):
+            if v is not None:
+                cap = v.shape[0] if cap == 0 else min(cap, v.shape[0])
+        job = Job(int(dim), int(prec), nn, ne, _host_ptr(coords), _host_ptr(elems), int(topology), float(arrival),
+                  fb if fb is not None else fallback(), _host_ptr(valsK), _host_ptr(valsM), cap)
+        t = C.c_uint64()
+        _chk(_lib.pf_server_submit(self._h, C.byref(job), C.byref(t)), "pf_server_submit")
+        self._keep[t.value] = (coords, elems, valsK, valsM)  # alive until the job is done
+        return t.value
+
+    def poll(self, ticket):
+        r = JobResult()
+        _chk(_lib.pf_server_poll(self._h, ticket, C.byref(r)), "pf_server_poll")
+        if r.done:
+            self._keep.pop(ticket, None)
+        return r.as_dict()
+
+    def wait(self, ticket):
+        r = JobResult()
+        _chk(_lib.pf_server_wait(self._h, ticket, C.byref(r)), "pf_server_wait")
+        self._keep.pop(ticket, None)
+        return r.as_dict()
+
+    def drain(self):
+        _chk(_lib.pf_server_drain(self._h), "pf_server_drain")
+        self._keep.clear()
+
+    def stats(self):
+        s = Stats()
+        _chk(_lib.pf_server_stats(self._h, C.byref(s)), "pf_server_stats")
+        return s.as_dict()
+
+    def close(self):
+        if self._h:
+            _lib.pf_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
 
     def __del__(self):
         try:

@@ -94,3 +94,18 @@ def test_plan_host_validation_without_gpu():
     assert L.pf_plan_get_schedule(None, None) == 1
     assert L.pf_plan_info(None, None, None, None) == 1
     L.pf_plan_destroy(None)
+
+
+def test_server_host_validation_without_gpu():
+    from paper_2404_16039_amd import lib
+    L = lib._lib
+    h = C.c_void_p()
+    assert L.pf_server_create(0, 4, 0, C.byref(h)) == 1
+    assert L.pf_server_create(1 << 30, 0, 0, C.byref(h)) == 1
+    assert L.pf_server_create(1 << 30, 4, 8, C.byref(h)) == 1
+    assert L.pf_server_create(1 << 30, 4, 0, None) == 1
+    assert L.pf_server_submit(None, None, None) == 1
+    assert L.pf_server_poll(None, 1, None) == 1
+    assert L.pf_server_drain(None) == 1
+    assert L.pf_server_stats(None, None) == 1
+    L.pf_server_destroy(None)

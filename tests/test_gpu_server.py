@@ -1,0 +1,206 @@
+"""The serving loop (row a14): jobs admitted by a device-memory budget, fused numeric
+launches per scheduler tick, resident structures per topology.  A job's values are bitwise
+those of the same mesh assembled alone, and match the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import TOL, host, say, within
+from paper_2404_16039_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2404_16039_amd import lib as L
+    return L
+
+
+def _mesh(dim, n, sub):
+    if dim == 2:
+        c, e, _ = gen.square_mesh(n, seed_sub=sub, stream=gen.STREAM_SERVE)
+    else:
+        c, e, _ = gen.cube_mesh(n, seed_sub=sub, stream=gen.STREAM_SERVE, with_faces=False)
+    return c, e
+
+
+def _alone(L, dim, prec, coords, elems, fb=None):
+    """The same mesh through pf_csr_symbolic + pf_assemble on its own."""
+    dt = torch.float32 if prec == L.F32 else torch.float64
+    csr = L.Csr().symbolic(dim, coords.shape[0], torch.from_numpy(elems).cuda())
+    _, nnz, _, _ = csr.info()
+    vk = torch.empty(nnz, dtype=dt, device="cuda")
+    vm = torch.empty(nnz, dtype=dt, device="cuda")
+    csr.assemble(prec, torch.from_numpy(coords).cuda(), None, vk, vm, fb=fb)
+    rp, ci = csr.structure()
+    out = host(vk), host(vm), host(rp), host(ci)
+    csr.close()
+    return out
+
+
+def _outputs(nnz_cap, prec):
+    dt = torch.float32 if prec == 0 else torch.float64
+    return (torch.full((nnz_cap,), float("nan"), dtype=dt).pin_memory(),
+            torch.full((nnz_cap,), float("nan"), dtype=dt).pin_memory())
+
+
+SPEC = [(2, 1, 12), (3, 0, 5), (3, 0, 4), (2, 1, 20), (3, 1, 3), (2, 0, 7), (3, 0, 9), (2, 1, 1)]
+
+
+@pytest.mark.parametrize("flags", [0, 1 | 2])
+def test_jobs_match_alone_bitwise(lib, flags):
+    """Fused (flags 0) and one-launch-per-job without resident structures (flags 3)."""
+    say("server identity", flags)
+    srv = lib.Server(1 << 30, 16, flags)
+    start = srv.now() + 0.05  # every job arrives at the same instant: one tick, fused launches
+    tickets = []
+    for k, (dim, prec, n) in enumerate(SPEC):
+        c, e = _mesh(dim, n, k)
+        cap = (gen.square_counts(n) if dim == 2 else gen.kuhn_counts(n))["nnz"]
+        vk, vm = _outputs(cap, prec)
+        t = srv.submit(dim, prec, torch.from_numpy(c).pin_memory(), torch.from_numpy(e).pin_memory(),
+                       topology=1000 + k, arrival=start, valsK=vk, valsM=vm)
+        tickets.append((t, dim, prec, c, e, vk, vm, cap))
+    srv.drain()
+    for t, dim, prec, c, e, vk, vm, cap in tickets:
+        r = srv.poll(t)
+        assert r["done"] == 1 and r["status"] == 0 and r["nnz"] == cap
+        ak, am, _, _ = _alone(lib, dim, prec, c, e)
+        assert np.array_equal(vk.numpy(), ak) and np.array_equal(vm.numpy(), am), f"job {t} differs from alone"
+        assert r["arrival"] <= r["admitted"] <= r["finished"] <= r["copied"]
+    s = srv.stats()
+    assert s["completed"] == len(SPEC) and s["failed"] == 0
+    if flags == 0:
+        assert s["max_batch"] == len(SPEC) and s["launches"] <= 4  # one launch per (dim, prec, rows) class
+    else:
+        assert s["launches"] == len(SPEC)
+    assert s["hbm_in_use"] >= 0 and s["hbm_high_water"] <= 1 << 30
+    srv.close()
+
+
+def test_values_match_oracle(lib):
+    say("server oracle")
+    srv = lib.Server(1 << 28, 4)
+    for dim, prec, n in [(2, lib.F64, 9), (3, lib.F32, 4)]:
+        c, e = _mesh(dim, n, 7)
+        cap = (gen.square_counts(n) if dim == 2 else gen.kuhn_counts(n))["nnz"]
+        vk, vm = _outputs(cap, prec)
+        t = srv.submit(dim, prec, torch.from_numpy(c).pin_memory(), torch.from_numpy(e).pin_memory(),
+                       valsK=vk, valsM=vm)
+        r = srv.wait(t)
+        assert r["status"] == 0
+        el = oracle.p1_elements(c, e)
+        ref = oracle.assemble(e, c.shape[0], el["Ke"], el["Me"], el["Kabs"])
+        tol = TOL[torch.float64 if prec == lib.F64 else torch.float32]
+        within(vk.numpy(), ref["valK"], ref["scaleK"], tol, "server K")
+        within(vm.numpy(), ref["valM"], ref["scaleM"], tol, "server M")
+    srv.close()
+
+
+def test_budget_queueing_and_rejection(lib):
+    """A budget that holds about two jobs: all ten finish, in turn, under the budget; a job
+    that can never fit is refused at submission."""
+    say("server budget")
+    c, e = _mesh(3, 8, 1)
+    budget = 3 * 1024 * 1024
+    srv = lib.Server(budget, 64)
+    with pytest.raises(lib.PagefemError) as ei:
+        big_c, big_e = _mesh(3, 20, 2)
+        srv.submit(3, lib.F32, big_c, big_e)
+    assert ei.value.code == 8
+    tc, te = torch.from_numpy(c).pin_memory(), torch.from_numpy(e).pin_memory()
+    ts = [srv.submit(3, lib.F32, tc, te) for _ in range(10)]
+    srv.drain()
+    for t in ts:
+        r = srv.poll(t)
+        assert r["done"] == 1 and r["status"] == 0
+    s = srv.stats()
+    assert s["completed"] == 10 and s["hbm_high_water"] <= budget and s["hbm_in_use"] == 0
+    assert s["max_batch"] < 10  # the budget split the jobs over several ticks
+    srv.close()
+
+
+def test_resident_structures(lib):
+    """Jobs of one topology share its structure (one miss, then hits) and still get their
+    own values; a small budget evicts idle structures."""
+    say("server cache")
+    srv = lib.Server(1 << 28, 8)
+    outs = []
+    for k in range(4):
+        c, e = _mesh(3, 6, 50 + k)  # same connectivity, different jitter
+        cap = gen.kuhn_counts(6)["nnz"]
+        vk, vm = _outputs(cap, 0)
+        t = srv.submit(3, lib.F32, torch.from_numpy(c).pin_memory(), torch.from_numpy(e).pin_memory(),
+                       topology=77, valsK=vk, valsM=vm)
+        srv.wait(t)
+        outs.append((c, e, vk, vm))
+    s = srv.stats()
+    assert s["cache_misses"] == 1 and s["cache_hits"] == 3
+    for c, e, vk, vm in outs:
+        ak, am, _, _ = _alone(lib, 3, lib.F32, c, e)
+        assert np.array_equal(vk.numpy(), ak) and np.array_equal(vm.numpy(), am)
+    assert not np.array_equal(outs[0][2].numpy(), outs[1][2].numpy())
+    srv.close()
+    # eviction: two topologies that do not fit together
+    c1, e1 = _mesh(3, 10, 1)
+    c2, e2 = _mesh(3, 11, 2)
+    budget = 2 * 1024 * 1024  # one resident structure plus one job, not two structures
+    srv = lib.Server(budget, 8)
+    for k in range(3):
+        srv.wait(srv.submit(3, lib.F32, c1, e1, topology=1))
+        srv.wait(srv.submit(3, lib.F32, c2, e2, topology=2))
+    s = srv.stats()
+    assert s["completed"] == 6 and s["evictions"] >= 1 and s["hbm_high_water"] <= budget
+    srv.close()
+
+
+def test_job_errors_do_not_stop_the_server(lib):
+    say("server errors")
+    srv = lib.Server(1 << 28, 4)
+    c, e = _mesh(2, 6, 3)
+    with pytest.raises(lib.PagefemError) as ei:
+        srv.submit(4, lib.F32, c, e)
+    assert ei.value.code == 3
+    small = torch.empty(10, dtype=torch.float64).pin_memory()
+    t = srv.submit(2, lib.F64, c, e, valsK=small)  # vals_cap below nnz
+    r = srv.wait(t)
+    assert r["done"] == 1 and r["status"] == 7
+    bad = e.copy()
+    bad[3, 1] = 10 ** 6  # out-of-range node id
+    r = srv.wait(srv.submit(2, lib.F64, c, bad))
+    assert r["status"] == 6
+    r = srv.wait(srv.submit(2, lib.F64, c, e))
+    assert r["status"] == 0
+    with pytest.raises(lib.PagefemError):
+        srv.poll(12345)
+    s = srv.stats()
+    assert s["failed"] == 2 and s["completed"] == 1
+    srv.close()
+
+
+def test_poisson_trace(lib):
+    """A short Poisson trace (200 jobs/s, small meshes) submitted at its arrival times."""
+    import time
+    trace = gen.serving_trace(60, rate=200.0, hi=3e4)
+    say("server trace", len(trace))
+    srv = lib.Server(1 << 30, 64)
+    meshes = {}
+    for j in trace:
+        c, e = _mesh(j["dim"], j["n"], j["id"])
+        meshes[j["id"]] = (torch.from_numpy(c).pin_memory(), torch.from_numpy(e).pin_memory())
+    t0 = srv.now() + 0.01
+    ts = []
+    for j in trace:
+        while srv.now() < t0 + j["t"]:
+            time.sleep(0.0002)
+        c, e = meshes[j["id"]]
+        prec = lib.F64 if j["dim"] == 2 else lib.F32
+        ts.append(srv.submit(j["dim"], prec, c, e, topology=(j["dim"] << 32) | j["n"], arrival=t0 + j["t"]))
+    srv.drain()
+    s = srv.stats()
+    assert s["completed"] == len(trace) and s["failed"] == 0
+    assert 0 < s["latency_p50"] <= s["latency_p99"] <= s["latency_max"]
+    assert s["jobs_per_s"] > 0 and s["elements"] == sum(m[1].shape[0] for m in meshes.values())
+    srv.close()
