@@ -6,11 +6,11 @@
 //   1. node -> element adjacency by counting sort: per-tile LDS hash aggregation of the
 //      (element, local node) entries, one global atomic per (tile, node), a scan, and a
 //      scatter into reserved ranges;
-//   2. row lengths: per block of rows, the distinct (row, node) pairs of its elements in a
-//      block-wide LDS hash table;
-//   3. scan into row_ptr; then per block again: rank each row's distinct nodes (col_idx,
-//      ascending) and pack for every adjacency entry the row positions ("slots") of the
-//      element's other nodes.
+//   2. row patterns, one pass per block of rows: the distinct (row, node) pairs of its
+//      elements in per-row LDS hash tables, each row's nodes ranked (ascending) into a
+//      padded buffer, the row lengths, and for every adjacency entry the row positions
+//      ("slots") of the element's other nodes;
+//   3. scan of the row lengths into row_ptr, then the padded rows are moved into col_idx.
 // Numeric phase (deterministic; see k_numeric): a block owns a contiguous range of rows,
 // hence a contiguous window of the CSR arrays.  Node coordinates are staged in LDS as the
 // FP64 difference vector of every window slot (column node minus row node, rounded once),
@@ -36,10 +36,11 @@ struct pf_csr {
     int32_t* row_ptr = nullptr;
     int32_t* col_idx = nullptr;
     int32_t* cnt = nullptr;   // per-node counts / cursors / row lengths
+    int32_t* colpad = nullptr;  // sorted columns of every row, MAXROW per row (symbolic scratch)
     int64_t* bsum = nullptr;  // scan workspace
     int64_t* info = nullptr;  // [0] error bits, [1] adjacency total, [2] nnz, [3..6] block stats
     int64_t cap_adj_ptr = 0, cap_row_ptr = 0, cap_cnt = 0, cap_adj = 0, cap_pk = 0, cap_nnz = 0, cap_bsum = 0,
-            cap_info = 0;
+            cap_info = 0, cap_colpad = 0;
     bool built = false;
 };
 
@@ -50,7 +51,7 @@ constexpr int SCAN_ITEMS = 8;    // items per thread in the scan
 constexpr int SCAN_TILE = SBS * SCAN_ITEMS;
 constexpr size_t LDS_BYTES = 65536;  // dynamic LDS budget of one numeric block
 
-constexpr int64_t ERR_INDEX = 1, ERR_ADJ = 2, ERR_ROW = 4;
+constexpr int64_t ERR_INDEX = 1, ERR_ROW = 4;
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
@@ -240,13 +241,14 @@ constexpr int RR = 32;           // rows per block in the row-pattern kernels
 constexpr int RT = 256;          // threads per block
 constexpr int MAXADJ = 64;       // elements per node
 constexpr int MAXROW = 64;       // nonzeros per row
-constexpr int RSUB = 2 * MAXROW; // slots of one row's table: load <= 1/2 for admissible rows
+constexpr int RSUB = MAXROW;     // slots of one row's table: every admissible row fits
 constexpr int RBATCH = 4;        // entries gathered together per thread (independent loads)
+static_assert(RR <= 64, "the row-count prefix runs in one wave");
 
 __device__ __forceinline__ int rsub_hash(int32_t v) {
-    return static_cast<int>((static_cast<uint32_t>(v) * 2654435761u) >> 25);  // 7 bits
+    return static_cast<int>((static_cast<uint32_t>(v) * 2654435761u) >> 26);  // 6 bits
 }
-static_assert(RSUB == 128, "rsub_hash yields 7 bits");
+static_assert(RSUB == 64, "rsub_hash yields 6 bits");
 
 // find or insert v in a row table; returns the slot (or -1 when the table is full) and
 // whether this call inserted it
@@ -304,21 +306,24 @@ __device__ __forceinline__ void elem_nodes(const int32_t* __restrict__ elems, in
     }
 }
 
-// FULL = false: row lengths only.  FULL = true: col_idx and the packed slots pk (bits 0-1
-// local index a, bits 2+8k .. 9+8k slot of the k-th other node of the element, in local
-// order).
-template <int NLB, bool FULL>
+// One pass per block of RR rows: insert, rank, and write (a) each row's length, (b) its
+// sorted columns into a padded buffer colpad[row * MAXROW ...] (moved to col_idx once the
+// row lengths are scanned), (c) the packed slots pk of every adjacency entry (bits 0-1 local
+// index a, bits 2+8k .. 9+8k row position of the k-th other node of the element, in local
+// order).  The table slot of every inserted node is kept per entry in LDS, so pk needs no
+// second gather of the element and no second table lookup.
+template <int NLB>
 __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __restrict__ elems,
                                                 const int32_t* __restrict__ adj_ptr, const int32_t* __restrict__ adj,
-                                                int32_t* __restrict__ rowlen, const int32_t* __restrict__ row_ptr,
-                                                int32_t* __restrict__ col_idx, uint32_t* __restrict__ pk,
-                                                int64_t* __restrict__ info) {
-    __shared__ int32_t tab[RR * RSUB];                  // node ids, -1 empty
-    __shared__ uint8_t pos_of[FULL ? RR * RSUB : 1];     // list position of each table slot
-    __shared__ int32_t seg[FULL ? RR * MAXROW : 1];      // each row's nodes, insertion order
-    __shared__ uint8_t rank_of[FULL ? RR * MAXROW : 1];  // rank of each list item
+                                                int32_t* __restrict__ rowlen, int32_t* __restrict__ colpad,
+                                                uint32_t* __restrict__ pk, int64_t* __restrict__ info) {
+    __shared__ int32_t tab[RR * RSUB];       // node ids, -1 empty
+    __shared__ uint8_t pos_of[RR * RSUB];     // list position of each table slot
+    __shared__ int32_t seg[RR * MAXROW];      // each row's nodes, insertion order
+    __shared__ uint8_t rank_of[RR * MAXROW];  // rank of each list item
+    __shared__ uint32_t eslot[RR * MAXADJ];   // per entry: a | table slot of node k << (2 + 6k)
     __shared__ int32_t cnt[RR];
-    __shared__ int32_t cpre[FULL ? RR + 1 : 1];
+    __shared__ int32_t cpre[RR + 1];
     __shared__ int32_t ap[RR + 1];
     __shared__ int32_t maxl;
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RR;
@@ -336,10 +341,10 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
         atomicMax(&maxl, L);
     }
     __syncthreads();
-    const int items = nr * maxl;
+    const int items = nr * min(maxl, MAXADJ);
     for (int base = threadIdx.x; base < items; base += RT * RBATCH) {
         int nd[RBATCH][4];
-        int rq[RBATCH];
+        int rq[RBATCH], tq[RBATCH];
 #pragma unroll
         for (int b = 0; b < RBATCH; ++b) {
             const int idx = base + b * RT;
@@ -348,79 +353,100 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
             const int r = idx % nr, j = idx / nr;
             if (j >= ap[r + 1] - ap[r]) continue;
             rq[b] = r;
-            elem_nodes<NLB>(elems, adj[ap[r] + j] >> 2, nd[b]);
+            tq[b] = ap[r] + j;
+            elem_nodes<NLB>(elems, adj[tq[b]] >> 2, nd[b]);
         }
 #pragma unroll
         for (int b = 0; b < RBATCH; ++b) {
             const int r = rq[b];
             if (r < 0) continue;
             int32_t* rt = tab + r * RSUB;
+            uint32_t word = static_cast<uint32_t>(adj[tq[b]] & 3);
 #pragma unroll
             for (int k = 0; k < NLB; ++k) {
                 bool fresh;
                 const int h = rsub_insert(rt, nd[b][k], fresh);
                 if (h < 0) {
                     bad = true;
-                } else if (fresh) {
+                    continue;
+                }
+                word |= static_cast<uint32_t>(h) << (2 + 6 * k);
+                if (fresh) {
                     const int p = atomicAdd(cnt + r, 1);
                     if (p < MAXROW) {
-                        if constexpr (FULL) {
-                            seg[r * MAXROW + p] = nd[b][k];
-                            pos_of[r * RSUB + h] = static_cast<uint8_t>(p);
-                        }
+                        seg[r * MAXROW + p] = nd[b][k];
+                        pos_of[r * RSUB + h] = static_cast<uint8_t>(p);
                     } else {
                         bad = true;
                     }
                 }
             }
+            if (tq[b] - e0 < RR * MAXADJ) eslot[tq[b] - e0] = word;  // else a row is over the limit (error)
         }
     }
     if (bad) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
     __syncthreads();
-    if constexpr (!FULL) {
-        if (threadIdx.x < nr) rowlen[r0 + threadIdx.x] = cnt[threadIdx.x] <= MAXROW ? cnt[threadIdx.x] : 0;
-    } else {
-        // rank every row list (ascending node id) and write col_idx; only existing
-        // (row, position) items are dealt out
-        if (threadIdx.x == 0) {
-            int acc = 0;
-            for (int r = 0; r < nr; ++r) {
-                cpre[r] = acc;
-                acc += cnt[r] <= MAXROW ? cnt[r] : MAXROW;
-            }
-            cpre[nr] = acc;
-        }
-        __syncthreads();
-        for (int q = threadIdx.x; q < cpre[nr]; q += RT) {
-            const int r = upper_pos(cpre, nr, q);
-            const int p = q - cpre[r];
-            const int n = cnt[r];
-            const int32_t v = seg[r * MAXROW + p];
-            int rank = 0;
-            for (int j = 0; j < n; ++j) rank += seg[r * MAXROW + j] < v;
-            rank_of[r * MAXROW + p] = static_cast<uint8_t>(rank);
-            col_idx[row_ptr[r0 + r] + rank] = v;
-        }
-        __syncthreads();
-        const int NE = ap[nr] - e0;
-        for (int t = threadIdx.x; t < NE; t += RT) {
-            const int r = upper_pos(ap, nr, e0 + t);
-            const int32_t key = adj[e0 + t];
-            const int a = key & 3;
-            int nd[4];
-            elem_nodes<NLB>(elems, key >> 2, nd);
-            uint32_t word = static_cast<uint32_t>(a);
-            int k2 = 0;
+    // rank every row list (ascending node id): padded columns and row lengths
+    if (threadIdx.x < 64) {  // exclusive prefix of the (capped) row counts in wave 0
+        const int lane = threadIdx.x;
+        const int v = lane < nr ? min(cnt[lane], MAXROW) : 0;
+        int x = v;
 #pragma unroll
-            for (int k = 0; k < NLB; ++k) {
-                if (k == a) continue;
-                const int h = rsub_find(tab + r * RSUB, nd[k]);
-                const int p = h >= 0 ? pos_of[r * RSUB + h] : 0;  // always found when no error was raised
-                word |= static_cast<uint32_t>(rank_of[r * MAXROW + p]) << (2 + 8 * k2);
-                ++k2;
-            }
-            pk[e0 + t] = word;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(x, d, 64);
+            if (lane >= d) x += y;
         }
+        if (lane < nr) cpre[lane] = x - v;
+        if (lane == nr - 1) cpre[nr] = x;
+    }
+    if (threadIdx.x < nr) rowlen[r0 + threadIdx.x] = cnt[threadIdx.x] <= MAXROW ? cnt[threadIdx.x] : 0;
+    __syncthreads();
+    for (int q = threadIdx.x; q < cpre[nr]; q += RT) {
+        const int r = upper_pos(cpre, nr, q);
+        const int p = q - cpre[r];
+        const int n = min(cnt[r], MAXROW);
+        const int32_t v = seg[r * MAXROW + p];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) rank += seg[r * MAXROW + j] < v;
+        rank_of[r * MAXROW + p] = static_cast<uint8_t>(rank);
+        colpad[(r0 + r) * MAXROW + rank] = v;
+    }
+    __syncthreads();
+    // packed slots of every adjacency entry from its kept table slots
+    const int NE = min(ap[nr] - e0, RR * MAXADJ);
+    for (int t = threadIdx.x; t < NE; t += RT) {
+        const int r = upper_pos(ap, nr, e0 + t);
+        const uint32_t w = eslot[t];
+        const int a = static_cast<int>(w & 3);
+        uint32_t word = static_cast<uint32_t>(a);
+        int k2 = 0;
+#pragma unroll
+        for (int k = 0; k < NLB; ++k) {
+            if (k == a) continue;
+            const int h = static_cast<int>((w >> (2 + 6 * k)) & (RSUB - 1));
+            const int p = min(static_cast<int>(pos_of[r * RSUB + h]), MAXROW - 1);  // < cnt unless the row failed
+            word |= static_cast<uint32_t>(rank_of[r * MAXROW + p]) << (2 + 8 * k2);
+            ++k2;
+        }
+        pk[e0 + t] = word;
+    }
+}
+
+// col_idx from the padded columns: a block moves the CSR window of RR rows with
+// coalesced writes
+constexpr int CR = 128;  // rows per compaction block
+__global__ __launch_bounds__(RT) void k_compact(int64_t nn, const int32_t* __restrict__ row_ptr,
+                                                const int32_t* __restrict__ colpad, int32_t* __restrict__ col_idx) {
+    __shared__ int32_t rp[CR + 1];
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * CR;
+    const int nr = static_cast<int>((r0 + CR < nn) ? CR : nn - r0);
+    if (threadIdx.x <= nr) rp[threadIdx.x] = row_ptr[r0 + threadIdx.x];
+    __syncthreads();
+    const int32_t w0 = rp[0];
+    const int W = rp[nr] - w0;
+    for (int w = threadIdx.x; w < W; w += RT) {
+        const int r = upper_pos(rp, nr, w0 + w);
+        col_idx[w0 + w] = colpad[(r0 + r) * MAXROW + (w0 + w - rp[r])];
     }
 }
 
@@ -928,7 +954,7 @@ pf_status numeric_launch_many(int dim, pf_dtype prec, int nr, const NumericJob* 
 }
 
 size_t csr_bytes(const pf_csr* c) {
-    return static_cast<size_t>(c->cap_adj_ptr + c->cap_row_ptr + c->cap_cnt + c->cap_adj + c->cap_nnz) * 4 +
+    return static_cast<size_t>(c->cap_adj_ptr + c->cap_row_ptr + c->cap_cnt + c->cap_adj + c->cap_nnz + c->cap_colpad) * 4 +
            static_cast<size_t>(c->cap_pk) * 4 + static_cast<size_t>(c->cap_bsum + c->cap_info) * 8;
 }
 
@@ -957,6 +983,7 @@ void pf_csr_destroy(pf_csr* c) {
     (void)hipFree(c->row_ptr);
     (void)hipFree(c->col_idx);
     (void)hipFree(c->cnt);
+    (void)hipFree(c->colpad);
     (void)hipFree(c->bsum);
     (void)hipFree(c->info);
     delete c;
@@ -991,13 +1018,14 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     if (m > 0)
         hipLaunchKernelGGL(k_scatter, dim3(gtile), dim3(AG_BS), 0, s, elems, m, nlb, nn, c->adj_ptr, c->cnt, c->adj);
     const unsigned grows = static_cast<unsigned>(ceil_div(nn, RR));
+    if ((st = grow(c->colpad, c->cap_colpad, nn * MAXROW))) return st;
     if (nn > 0) {
         if (nlb == 4)
-            hipLaunchKernelGGL((k_pattern<4, false>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_ptr, c->adj, c->cnt,
-                               nullptr, nullptr, nullptr, c->info);
+            hipLaunchKernelGGL((k_pattern<4>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_ptr, c->adj, c->cnt,
+                               c->colpad, c->pk, c->info);
         else
-            hipLaunchKernelGGL((k_pattern<3, false>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_ptr, c->adj, c->cnt,
-                               nullptr, nullptr, nullptr, c->info);
+            hipLaunchKernelGGL((k_pattern<3>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_ptr, c->adj, c->cnt,
+                               c->colpad, c->pk, c->info);
     }
     if ((st = scan(c->cnt, nn, c->row_ptr, c->bsum, c->info + 2, s))) return st;
     for (int which = 0; which < 2 && nn > 0; ++which) {
@@ -1018,14 +1046,9 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     if (info[2] >= INT32_MAX) return fail(PF_ELIMIT, "pf_csr_symbolic: nnz must be < 2^31");
     const int64_t nnz = info[2];
     if ((st = grow(c->col_idx, c->cap_nnz, nnz))) return st;
-    if (nn > 0) {
-        if (nlb == 4)
-            hipLaunchKernelGGL((k_pattern<4, true>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_ptr, c->adj, nullptr,
-                               c->row_ptr, c->col_idx, c->pk, c->info);
-        else
-            hipLaunchKernelGGL((k_pattern<3, true>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_ptr, c->adj, nullptr,
-                               c->row_ptr, c->col_idx, c->pk, c->info);
-    }
+    if (nn > 0)
+        hipLaunchKernelGGL(k_compact, dim3(static_cast<unsigned>(ceil_div(nn, CR))), dim3(RT), 0, s, nn, c->row_ptr,
+                           c->colpad, c->col_idx);
     if ((st = launch_check("pf_csr_symbolic cols"))) return st;
     c->dim = dim;
     c->nlb = nlb;

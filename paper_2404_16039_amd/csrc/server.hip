@@ -75,6 +75,7 @@ size_t topo_estimate(const pf_job& j) {
     const int64_t nlb = j.dim + 1;
     return static_cast<size_t>(j.ne * nlb * 4)                                     // elems
            + static_cast<size_t>(12 * (j.nn + 1) + 8 * j.ne * nlb + 4 * nnz_bound(j))  // structure
+           + static_cast<size_t>(256 * j.nn)                                         // padded rows (scratch)
            + 4096;
 }
 

@@ -146,7 +146,7 @@ def test_resident_structures(lib):
     # eviction: two topologies that do not fit together
     c1, e1 = _mesh(3, 10, 1)
     c2, e2 = _mesh(3, 11, 2)
-    budget = 2 * 1024 * 1024  # one resident structure plus one job, not two structures
+    budget = 5 * 512 * 1024  # one resident structure plus one job, not two structures
     srv = lib.Server(budget, 8)
     for k in range(3):
         srv.wait(srv.submit(3, lib.F32, c1, e1, topology=1))
