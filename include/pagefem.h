@@ -358,6 +358,10 @@ double pf_server_now(const pf_server* srv);
  * never fit the budget.  Jobs are admitted in submission order. */
 pf_status pf_server_submit(pf_server* srv, const pf_job* job, uint64_t* ticket);
 
+/* Device bytes a job is admitted with when its structure is not resident: inputs, values
+ * and a new structure, estimated from its sizes (an upper bound of what it holds). */
+pf_status pf_server_footprint(const pf_job* job, size_t* bytes);
+
 /* State of a job; PF_EINVAL for an unknown ticket.  wait blocks until it is done. */
 pf_status pf_server_poll(pf_server* srv, uint64_t ticket, pf_job_result* out);
 pf_status pf_server_wait(pf_server* srv, uint64_t ticket, pf_job_result* out);

@@ -3,9 +3,9 @@
 // materialising the 16 (row, col, value) triples per element.
 //
 // Symbolic phase (integer-exact, kept in a pf_csr handle):
-//   1. node -> element adjacency by counting sort: per-tile LDS hash aggregation of the
-//      (element, local node) entries, one global atomic per (tile, node), a scan, and a
-//      scatter into reserved ranges;
+//   1. node -> element adjacency in a padded layout (MAXADJ entries per node): per-tile LDS
+//      hash aggregation of the (element, local node) entries, one global atomic per
+//      (tile, node) reserving positions in the node's row, LDS atomics inside the tile;
 //   2. row patterns, one pass per block of rows: the distinct (row, node) pairs of its
 //      elements in per-row LDS hash tables, each row's nodes ranked (ascending) into a
 //      padded buffer, the row lengths, and for every adjacency entry the row positions
@@ -27,19 +27,19 @@
 struct pf_csr {
     int dim = 0, nlb = 0;
     int64_t nn = 0, ne = 0, nnz = 0;
-    int wmax_big = 0, emax_big = 0;      // largest window / adjacency range of a 32-row block
-    int wmax_small = 0, emax_small = 0;  // ... of an 8-row block
-    int max_adj = 0;                     // largest number of elements around one node
-    int32_t* adj_ptr = nullptr;
-    int32_t* adj = nullptr;   // (element << 2) | local index, sorted per node
-    uint32_t* pk = nullptr;   // per adjacency entry: local index and slots of the other nodes
+    int wmax_big = 0;    // largest CSR window of a numeric block of NR_BIG rows
+    int wmax_small = 0;  // ... of NR_SMALL rows
+    int max_adj = 0;     // largest number of elements around one node
+    int32_t* adj_len = nullptr;  // elements around each node
+    int32_t* adj = nullptr;   // node i's entries (element << 2 | local index) at i * MAXADJ ...
+    uint32_t* pk = nullptr;   // per adjacency entry (same layout): local index, slots of the other nodes
     int32_t* row_ptr = nullptr;
     int32_t* col_idx = nullptr;
     int32_t* cnt = nullptr;   // per-node counts / cursors / row lengths
     int32_t* colpad = nullptr;  // sorted columns of every row, MAXROW per row (symbolic scratch)
     int64_t* bsum = nullptr;  // scan workspace
     int64_t* info = nullptr;  // [0] error bits, [1] adjacency total, [2] nnz, [3..6] block stats
-    int64_t cap_adj_ptr = 0, cap_row_ptr = 0, cap_cnt = 0, cap_adj = 0, cap_pk = 0, cap_nnz = 0, cap_bsum = 0,
+    int64_t cap_adj_len = 0, cap_row_ptr = 0, cap_cnt = 0, cap_adj = 0, cap_pk = 0, cap_nnz = 0, cap_bsum = 0,
             cap_info = 0, cap_colpad = 0;
     bool built = false;
 };
@@ -52,6 +52,8 @@ constexpr int SCAN_TILE = SBS * SCAN_ITEMS;
 constexpr size_t LDS_BYTES = 65536;  // dynamic LDS budget of one numeric block
 
 constexpr int64_t ERR_INDEX = 1, ERR_ROW = 4;
+constexpr int MAXADJ = 64;  // elements per node (adjacency rows are padded to this length)
+constexpr int MAXROW = 64;  // nonzeros per row
 
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
@@ -159,39 +161,15 @@ __device__ __forceinline__ int ag_insert(int32_t* keys, int32_t node) {
     }
 }
 
-__global__ __launch_bounds__(AG_BS) void k_count(const int32_t* __restrict__ elems, int64_t m, int64_t nn,
-                                                 int32_t* __restrict__ cnt, int64_t* __restrict__ info) {
-    __shared__ int32_t keys[AG_HASH];
-    __shared__ int32_t vals[AG_HASH];
-    for (int h = threadIdx.x; h < AG_HASH; h += AG_BS) {
-        keys[h] = -1;
-        vals[h] = 0;
-    }
-    __syncthreads();
-    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * AG_TILE;
-    bool bad = false;
-#pragma unroll
-    for (int q = 0; q < AG_ITEMS; ++q) {
-        const int64_t t = t0 + q * AG_BS + threadIdx.x;
-        if (t < m) {
-            const int32_t node = elems[t];
-            if (node < 0 || node >= nn) bad = true;
-            else atomicAdd(vals + ag_insert(keys, node), 1);
-        }
-    }
-    if (bad) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_INDEX));
-    __syncthreads();
-    for (int h = threadIdx.x; h < AG_HASH; h += AG_BS)
-        if (keys[h] >= 0) atomicAdd(cnt + keys[h], vals[h]);
-}
-
-// Scatter (element << 2 | local index) into each node's list.  One global atomic per
-// (tile, node) reserves the tile's range; entries take positions inside it through LDS
-// atomics.  The order inside a list is not fixed: nothing downstream depends on it (the
-// numeric phase sums exactly, so its result does not depend on the entry order).
+// Scatter (element << 2 | local index) into each node's padded row (MAXADJ entries).  One
+// global atomic per (tile, node) on the node's length reserves the tile's positions; entries
+// take positions inside them through LDS atomics.  The order inside a row is not fixed:
+// nothing downstream depends on it (the numeric phase sums exactly, so its result does not
+// depend on the entry order).  Out-of-range node ids and rows beyond MAXADJ set error bits
+// and are not stored.
 __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ elems, int64_t m, int nlb, int64_t nn,
-                                                   const int32_t* __restrict__ adj_ptr, int32_t* __restrict__ cursor,
-                                                   int32_t* __restrict__ adj) {
+                                                   int32_t* __restrict__ adj_len, int32_t* __restrict__ adj,
+                                                   int64_t* __restrict__ info) {
     __shared__ int32_t keys[AG_HASH];
     __shared__ int32_t vals[AG_HASH];
     for (int h = threadIdx.x; h < AG_HASH; h += AG_BS) {
@@ -201,6 +179,7 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
     __syncthreads();
     const int64_t t0 = static_cast<int64_t>(blockIdx.x) * AG_TILE;
     int slot[AG_ITEMS];
+    bool bad = false;
 #pragma unroll
     for (int q = 0; q < AG_ITEMS; ++q) {
         const int64_t t = t0 + q * AG_BS + threadIdx.x;
@@ -210,14 +189,23 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
             if (node >= 0 && node < nn) {
                 slot[q] = ag_insert(keys, node);
                 atomicAdd(vals + slot[q], 1);
+            } else {
+                bad = true;
             }
         }
     }
+    if (bad) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_INDEX));
     __syncthreads();
+    bool over = false;
     for (int h = threadIdx.x; h < AG_HASH; h += AG_BS) {
         const int32_t node = keys[h];
-        if (node >= 0) vals[h] = adj_ptr[node] + atomicAdd(cursor + node, vals[h]);
+        if (node >= 0) {
+            const int old = atomicAdd(adj_len + node, vals[h]);
+            if (old + vals[h] > MAXADJ) over = true;
+            vals[h] = old;  // the tile's first position in the node's row
+        }
     }
+    if (over) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < AG_ITEMS; ++q) {
@@ -225,7 +213,9 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
             const int64_t t = t0 + q * AG_BS + threadIdx.x;
             const int64_t e = t / nlb;
             const int a = static_cast<int>(t - e * nlb);
-            adj[atomicAdd(vals + slot[q], 1)] = static_cast<int32_t>((e << 2) | a);
+            const int64_t node = keys[slot[q]];
+            const int off = atomicAdd(vals + slot[q], 1);
+            if (off < MAXADJ) adj[node * MAXADJ + off] = static_cast<int32_t>((e << 2) | a);
         }
     }
 }
@@ -239,8 +229,6 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
 // item r + nr j), so the lanes of one instruction insert into different rows' tables.
 constexpr int RR = 32;           // rows per block in the row-pattern kernels
 constexpr int RT = 256;          // threads per block
-constexpr int MAXADJ = 64;       // elements per node
-constexpr int MAXROW = 64;       // nonzeros per row
 constexpr int RSUB = MAXROW;     // slots of one row's table: every admissible row fits
 constexpr int RBATCH = 4;        // entries gathered together per thread (independent loads)
 static_assert(RR <= 64, "the row-count prefix runs in one wave");
@@ -314,7 +302,7 @@ __device__ __forceinline__ void elem_nodes(const int32_t* __restrict__ elems, in
 // second gather of the element and no second table lookup.
 template <int NLB>
 __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __restrict__ elems,
-                                                const int32_t* __restrict__ adj_ptr, const int32_t* __restrict__ adj,
+                                                const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
                                                 int32_t* __restrict__ rowlen, int32_t* __restrict__ colpad,
                                                 uint32_t* __restrict__ pk, int64_t* __restrict__ info) {
     __shared__ int32_t tab[RR * RSUB];       // node ids, -1 empty
@@ -324,44 +312,45 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
     __shared__ uint32_t eslot[RR * MAXADJ];   // per entry: a | table slot of node k << (2 + 6k)
     __shared__ int32_t cnt[RR];
     __shared__ int32_t cpre[RR + 1];
-    __shared__ int32_t ap[RR + 1];
+    __shared__ int32_t alen[RR];
     __shared__ int32_t maxl;
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RR;
     const int nr = static_cast<int>((r0 + RR < nn) ? RR : nn - r0);
+    const int64_t e0 = r0 * MAXADJ;  // the block's adjacency rows start here (padded layout)
     for (int h = threadIdx.x; h < RR * RSUB; h += RT) tab[h] = -1;
     if (threadIdx.x < RR) cnt[threadIdx.x] = 0;
-    if (threadIdx.x <= nr) ap[threadIdx.x] = adj_ptr[r0 + threadIdx.x];
     if (threadIdx.x == 0) maxl = 0;
     __syncthreads();
-    const int32_t e0 = ap[0];
-    bool bad = false;
     if (threadIdx.x < nr) {
-        const int L = ap[threadIdx.x + 1] - ap[threadIdx.x];
-        if (L > MAXADJ) bad = true;
+        const int L = min(adj_len[r0 + threadIdx.x], MAXADJ);  // longer rows raised an error already
+        alen[threadIdx.x] = L;
         atomicMax(&maxl, L);
     }
+    bool bad = false;
     __syncthreads();
-    const int items = nr * min(maxl, MAXADJ);
+    const int items = nr * maxl;
     for (int base = threadIdx.x; base < items; base += RT * RBATCH) {
         int nd[RBATCH][4];
-        int rq[RBATCH], tq[RBATCH];
+        int rq[RBATCH], tq[RBATCH];  // row, and block-local entry index r * MAXADJ + j
+        int32_t aq[RBATCH];
 #pragma unroll
         for (int b = 0; b < RBATCH; ++b) {
             const int idx = base + b * RT;
             rq[b] = -1;
             if (idx >= items) continue;
             const int r = idx % nr, j = idx / nr;
-            if (j >= ap[r + 1] - ap[r]) continue;
+            if (j >= alen[r]) continue;
             rq[b] = r;
-            tq[b] = ap[r] + j;
-            elem_nodes<NLB>(elems, adj[tq[b]] >> 2, nd[b]);
+            tq[b] = r * MAXADJ + j;
+            aq[b] = adj[e0 + tq[b]];
+            elem_nodes<NLB>(elems, aq[b] >> 2, nd[b]);
         }
 #pragma unroll
         for (int b = 0; b < RBATCH; ++b) {
             const int r = rq[b];
             if (r < 0) continue;
             int32_t* rt = tab + r * RSUB;
-            uint32_t word = static_cast<uint32_t>(adj[tq[b]] & 3);
+            uint32_t word = static_cast<uint32_t>(aq[b] & 3);
 #pragma unroll
             for (int k = 0; k < NLB; ++k) {
                 bool fresh;
@@ -381,7 +370,7 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
                     }
                 }
             }
-            if (tq[b] - e0 < RR * MAXADJ) eslot[tq[b] - e0] = word;  // else a row is over the limit (error)
+            eslot[tq[b]] = word;
         }
     }
     if (bad) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
@@ -412,10 +401,11 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
         colpad[(r0 + r) * MAXROW + rank] = v;
     }
     __syncthreads();
-    // packed slots of every adjacency entry from its kept table slots
-    const int NE = min(ap[nr] - e0, RR * MAXADJ);
-    for (int t = threadIdx.x; t < NE; t += RT) {
-        const int r = upper_pos(ap, nr, e0 + t);
+    // packed slots of every adjacency entry from its kept table slots (row-interleaved)
+    for (int idx = threadIdx.x; idx < items; idx += RT) {
+        const int r = idx % nr, j = idx / nr;
+        if (j >= alen[r]) continue;
+        const int t = r * MAXADJ + j;
         const uint32_t w = eslot[t];
         const int a = static_cast<int>(w & 3);
         uint32_t word = static_cast<uint32_t>(a);
@@ -457,45 +447,39 @@ constexpr int NBT = 256;     // threads per block of the numeric kernel
 constexpr int NITEMS = 2;    // adjacency entries per thread (held in registers)
 static_assert(MAXADJ <= NITEMS * NBT / NR_SMALL, "the small numeric blocks must cover any admissible row");
 
-// largest CSR window and adjacency range of one numeric block of `nr` rows, and the largest
-// adjacency count of a row, into info[slot], info[slot + 1], info[7].  Grid-strided, then
-// reduced in the wave and in the block: one global atomic per block.
+// largest CSR window of one numeric block of `nr` rows into info[slot], and the largest
+// number of elements around a node into info[7].  Grid-strided, then reduced in the wave and
+// in the block: one global atomic per block.
 __global__ __launch_bounds__(256) void k_block_stats(int64_t nn, int nr, const int32_t* __restrict__ row_ptr,
-                                                     const int32_t* __restrict__ adj_ptr, int64_t nblk,
+                                                     const int32_t* __restrict__ adj_len, int64_t nblk,
                                                      int64_t* __restrict__ info, int slot) {
-    __shared__ int red[3][4];
-    int w = 0, e = 0, l = 0;
+    __shared__ int red[2][4];
+    int w = 0, l = 0;
     for (int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; b < nblk;
          b += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         const int64_t r0 = b * nr;
         const int64_t r1 = (r0 + nr < nn) ? r0 + nr : nn;
         w = max(w, row_ptr[r1] - row_ptr[r0]);
-        e = max(e, adj_ptr[r1] - adj_ptr[r0]);
-        for (int64_t i = r0; i < r1; ++i) l = max(l, adj_ptr[i + 1] - adj_ptr[i]);
+        for (int64_t i = r0; i < r1; ++i) l = max(l, adj_len[i]);
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         w = max(w, __shfl_xor(w, d, 64));
-        e = max(e, __shfl_xor(e, d, 64));
         l = max(l, __shfl_xor(l, d, 64));
     }
     if ((threadIdx.x & 63) == 0) {
         red[0][threadIdx.x >> 6] = w;
-        red[1][threadIdx.x >> 6] = e;
-        red[2][threadIdx.x >> 6] = l;
+        red[1][threadIdx.x >> 6] = l;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int q = 1; q < 4; ++q) {
             w = max(w, red[0][q]);
-            e = max(e, red[1][q]);
-            l = max(l, red[2][q]);
+            l = max(l, red[1][q]);
         }
         w = max(w, red[0][0]);
-        e = max(e, red[1][0]);
-        l = max(l, red[2][0]);
+        l = max(l, red[1][0]);
         atomicMax(reinterpret_cast<unsigned long long*>(info + slot), static_cast<unsigned long long>(w));
-        atomicMax(reinterpret_cast<unsigned long long*>(info + slot + 1), static_cast<unsigned long long>(e));
         atomicMax(reinterpret_cast<unsigned long long*>(info + 7), static_cast<unsigned long long>(l));
     }
 }
@@ -644,7 +628,7 @@ constexpr size_t numeric_lds_bytes(int nr, int wmax) {
 template <int DIM, typename T, bool COEF, int NR>
 __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const double* __restrict__ coords,
                                               const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
-                                              const int32_t* __restrict__ adj_ptr, const int32_t* __restrict__ adj,
+                                              const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
                                               const uint32_t* __restrict__ pk, const T* __restrict__ cK,
                                               const T* __restrict__ cM, T* __restrict__ valsK, T* __restrict__ valsM,
                                               const Fallback& fb, int64_t* d_counters, int wmax) {
@@ -658,15 +642,13 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
     int32_t* shK = reinterpret_cast<int32_t*>(f + wmax);         // [wmax] max bits, then shift
     int32_t* shM = shK + wmax;                                   // [wmax]
     int32_t* rp = shM + wmax;                                    // [NR + 1]
-    int32_t* ap = rp + (NR + 1);                                 // [NR + 1]
-    int32_t* dslot = ap + (NR + 1);                              // [NR + 1]
+    int32_t* alen = rp + (NR + 1);                               // [NR + 1] elements around each row node
+    int32_t* dslot = alen + (NR + 1);                            // [NR + 1]
     int32_t* maxlen = dslot + (NR + 1);                          // [1]
 
     const int nr = static_cast<int>((r0 + NR < nn) ? NR : nn - r0);
-    if (threadIdx.x <= nr) {
-        rp[threadIdx.x] = row_ptr[r0 + threadIdx.x];
-        ap[threadIdx.x] = adj_ptr[r0 + threadIdx.x];
-    }
+    if (threadIdx.x <= nr) rp[threadIdx.x] = row_ptr[r0 + threadIdx.x];
+    if (threadIdx.x < nr) alen[threadIdx.x] = adj_len[r0 + threadIdx.x];
     if (threadIdx.x == 0) *maxlen = 0;
     __syncthreads();
     if (threadIdx.x < nr) atomicMax(maxlen, rp[threadIdx.x + 1] - rp[threadIdx.x]);
@@ -674,16 +656,17 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
     const int W = rp[nr] - w0;
     // packed entries of this thread's items, loaded before phase 0 so their latency overlaps it
     uint32_t pw[NITEMS];
-    int rr[NITEMS], tt[NITEMS];
+    int rr[NITEMS];
+    int64_t tt[NITEMS];
 #pragma unroll
     for (int q = 0; q < NITEMS; ++q) {
         // the host guarantees that NITEMS * NBT / NR covers the longest adjacency list
         int r, j;
         split_item<NR>(threadIdx.x + q * NBT, nr, r, j);
         rr[q] = -1;
-        if (j < ap[r + 1] - ap[r]) {
+        if (j < alen[r]) {
             rr[q] = r;
-            tt[q] = ap[r] + j;
+            tt[q] = (r0 + r) * MAXADJ + j;  // padded adjacency rows
             pw[q] = pk[tt[q]];
         }
     }
@@ -719,7 +702,7 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
     for (int q = 0; q < NITEMS; ++q) {
         const int r = rr[q];
         if (r < 0) continue;
-        const int t = tt[q];
+        const int64_t t = tt[q];
         const int s0 = rp[r] - w0;
         const uint32_t p = pw[q];
         T ck = T(1), cm = T(1);
@@ -807,11 +790,11 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
 template <int DIM, typename T, bool COEF, int NR>
 __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __restrict__ coords,
                                                  const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
-                                                 const int32_t* __restrict__ adj_ptr, const int32_t* __restrict__ adj,
+                                                 const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
                                                  const uint32_t* __restrict__ pk, const T* __restrict__ cK,
                                                  const T* __restrict__ cM, T* __restrict__ valsK, T* __restrict__ valsM,
                                                  Fallback fb, int64_t* d_counters, int wmax) {
-    numeric_block<DIM, T, COEF, NR>(static_cast<int64_t>(blockIdx.x) * NR, nn, coords, row_ptr, col_idx, adj_ptr, adj,
+    numeric_block<DIM, T, COEF, NR>(static_cast<int64_t>(blockIdx.x) * NR, nn, coords, row_ptr, col_idx, adj_len, adj,
                                     pk, cK, cM, valsK, valsM, fb, d_counters, wmax);
 }
 
@@ -829,7 +812,7 @@ __global__ __launch_bounds__(NBT) void k_numeric_jobs(const NumericJob* __restri
         else hi = mid - 1;
     }
     const NumericJob& j = jobs[lo];
-    numeric_block<DIM, T, false, NR>((b - j.block0) * NR, j.nn, j.coords, j.row_ptr, j.col_idx, j.adj_ptr, j.adj, j.pk,
+    numeric_block<DIM, T, false, NR>((b - j.block0) * NR, j.nn, j.coords, j.row_ptr, j.col_idx, j.adj_len, j.adj, j.pk,
                                      nullptr, nullptr, static_cast<T*>(j.valsK), static_cast<T*>(j.valsM), j.fb,
                                      j.counters, wmax);
 }
@@ -873,7 +856,7 @@ pf_status launch_numeric(const pf_csr* c, const double* coords, const void* cK, 
     const size_t shm = numeric_lds_bytes<DIM, T>(NRB, wmax);
     const unsigned g = static_cast<unsigned>(ceil_div(c->nn, NRB));
     hipLaunchKernelGGL((k_numeric<DIM, T, COEF, NRB>), dim3(g), dim3(NBT), shm, s, c->nn, coords, c->row_ptr,
-                       c->col_idx, c->adj_ptr, c->adj, c->pk, static_cast<const T*>(cK), static_cast<const T*>(cM),
+                       c->col_idx, c->adj_len, c->adj, c->pk, static_cast<const T*>(cK), static_cast<const T*>(cM),
                        static_cast<T*>(valsK), static_cast<T*>(valsM), f, ctr, wmax);
     return launch_check("pf_assemble");
 }
@@ -915,7 +898,7 @@ void numeric_describe(const pf_csr* c, const double* coords, void* valsK, void* 
     out->coords = coords;
     out->row_ptr = c->row_ptr;
     out->col_idx = c->col_idx;
-    out->adj_ptr = c->adj_ptr;
+    out->adj_len = c->adj_len;
     out->adj = c->adj;
     out->pk = c->pk;
     out->valsK = valsK;
@@ -954,7 +937,7 @@ pf_status numeric_launch_many(int dim, pf_dtype prec, int nr, const NumericJob* 
 }
 
 size_t csr_bytes(const pf_csr* c) {
-    return static_cast<size_t>(c->cap_adj_ptr + c->cap_row_ptr + c->cap_cnt + c->cap_adj + c->cap_nnz + c->cap_colpad) * 4 +
+    return static_cast<size_t>(c->cap_adj_len + c->cap_row_ptr + c->cap_cnt + c->cap_adj + c->cap_nnz + c->cap_colpad) * 4 +
            static_cast<size_t>(c->cap_pk) * 4 + static_cast<size_t>(c->cap_bsum + c->cap_info) * 8;
 }
 
@@ -977,7 +960,7 @@ pf_status pf_csr_create(pf_csr** out) {
 
 void pf_csr_destroy(pf_csr* c) {
     if (!c) return;
-    (void)hipFree(c->adj_ptr);
+    (void)hipFree(c->adj_len);
     (void)hipFree(c->adj);
     (void)hipFree(c->pk);
     (void)hipFree(c->row_ptr);
@@ -1001,30 +984,27 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     c->built = false;
     const int64_t m = ne * nlb;
     pf_status st;
-    if ((st = grow(c->adj_ptr, c->cap_adj_ptr, nn + 1))) return st;
+    if ((st = grow(c->adj_len, c->cap_adj_len, nn + 1))) return st;
     if ((st = grow(c->row_ptr, c->cap_row_ptr, nn + 1))) return st;
     if ((st = grow(c->cnt, c->cap_cnt, nn + 1))) return st;
-    if ((st = grow(c->adj, c->cap_adj, m))) return st;
-    if ((st = grow(c->pk, c->cap_pk, m))) return st;
+    if ((st = grow(c->adj, c->cap_adj, nn * MAXADJ))) return st;
+    if ((st = grow(c->pk, c->cap_pk, nn * MAXADJ))) return st;
     const int64_t nb = std::max<int64_t>(ceil_div(nn + 1, SCAN_TILE), 1);
     if ((st = grow(c->bsum, c->cap_bsum, nb))) return st;
     if ((st = grow(c->info, c->cap_info, 8))) return st;
     hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, c->info, int64_t(8), int64_t(0));
-    if (nn > 0) hipLaunchKernelGGL(k_fill_i32, dim3(flat_grid(nn)), dim3(SBS), 0, s, c->cnt, nn, 0);
+    if (nn > 0) hipLaunchKernelGGL(k_fill_i32, dim3(flat_grid(nn)), dim3(SBS), 0, s, c->adj_len, nn, 0);
     const unsigned gtile = static_cast<unsigned>(std::max<int64_t>(ceil_div(m, AG_TILE), 1));
-    if (m > 0) hipLaunchKernelGGL(k_count, dim3(gtile), dim3(AG_BS), 0, s, elems, m, nn, c->cnt, c->info);
-    if ((st = scan(c->cnt, nn, c->adj_ptr, c->bsum, c->info + 1, s))) return st;
-    if (nn > 0) hipLaunchKernelGGL(k_fill_i32, dim3(flat_grid(nn)), dim3(SBS), 0, s, c->cnt, nn, 0);
     if (m > 0)
-        hipLaunchKernelGGL(k_scatter, dim3(gtile), dim3(AG_BS), 0, s, elems, m, nlb, nn, c->adj_ptr, c->cnt, c->adj);
+        hipLaunchKernelGGL(k_scatter, dim3(gtile), dim3(AG_BS), 0, s, elems, m, nlb, nn, c->adj_len, c->adj, c->info);
     const unsigned grows = static_cast<unsigned>(ceil_div(nn, RR));
     if ((st = grow(c->colpad, c->cap_colpad, nn * MAXROW))) return st;
     if (nn > 0) {
         if (nlb == 4)
-            hipLaunchKernelGGL((k_pattern<4>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_ptr, c->adj, c->cnt,
+            hipLaunchKernelGGL((k_pattern<4>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
                                c->colpad, c->pk, c->info);
         else
-            hipLaunchKernelGGL((k_pattern<3>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_ptr, c->adj, c->cnt,
+            hipLaunchKernelGGL((k_pattern<3>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
                                c->colpad, c->pk, c->info);
     }
     if ((st = scan(c->cnt, nn, c->row_ptr, c->bsum, c->info + 2, s))) return st;
@@ -1032,7 +1012,7 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
         const int nr = which == 0 ? NR_BIG : NR_SMALL;
         const int64_t nblk = ceil_div(nn, nr);
         const unsigned g = static_cast<unsigned>(std::min<int64_t>(ceil_div(nblk, 256), 128));
-        hipLaunchKernelGGL(k_block_stats, dim3(g), dim3(256), 0, s, nn, nr, c->row_ptr, c->adj_ptr, nblk, c->info,
+        hipLaunchKernelGGL(k_block_stats, dim3(g), dim3(256), 0, s, nn, nr, c->row_ptr, c->adj_len, nblk, c->info,
                            3 + 2 * which);
     }
     if ((st = launch_check("pf_csr_symbolic"))) return st;
@@ -1056,9 +1036,7 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     c->ne = ne;
     c->nnz = nnz;
     c->wmax_big = static_cast<int>(info[3]);
-    c->emax_big = static_cast<int>(info[4]);
     c->wmax_small = static_cast<int>(info[5]);
-    c->emax_small = static_cast<int>(info[6]);
     c->max_adj = static_cast<int>(info[7]);
     c->built = true;
     return PF_OK;

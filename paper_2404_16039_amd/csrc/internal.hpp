@@ -12,7 +12,7 @@ struct NumericJob {
     const double* coords;
     const int32_t* row_ptr;
     const int32_t* col_idx;
-    const int32_t* adj_ptr;
+    const int32_t* adj_len;
     const int32_t* adj;
     const uint32_t* pk;
     void* valsK;

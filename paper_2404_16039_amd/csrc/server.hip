@@ -74,7 +74,7 @@ int64_t nnz_bound(const pf_job& j) {
 size_t topo_estimate(const pf_job& j) {
     const int64_t nlb = j.dim + 1;
     return static_cast<size_t>(j.ne * nlb * 4)                                     // elems
-           + static_cast<size_t>(12 * (j.nn + 1) + 8 * j.ne * nlb + 4 * nnz_bound(j))  // structure
+           + static_cast<size_t>(12 * (j.nn + 1) + 512 * j.nn + 4 * nnz_bound(j))  // structure (padded adjacency)
            + static_cast<size_t>(256 * j.nn)                                         // padded rows (scratch)
            + 4096;
 }
@@ -512,7 +512,8 @@ pf_status pf_server_submit(pf_server* S, const pf_job* q, uint64_t* ticket) {
     if (!S) return fail(PF_EINVAL, "pf_server_submit: server is NULL");
     pf_status st = check_job(q);
     if (st != PF_OK) return st;
-    const size_t need = job_estimate(*q, nnz_bound(*q)) + topo_estimate(*q);
+    size_t need = 0;
+    pf_server_footprint(q, &need);
     if (need > S->budget) return fail(PF_EBUDGET, "pf_server_submit: the job can never fit the memory budget");
     auto j = std::make_unique<SJob>();
     j->spec = *q;
@@ -526,6 +527,14 @@ pf_status pf_server_submit(pf_server* S, const pf_job* q, uint64_t* ticket) {
     ++S->st.submitted;
     ++S->unfinished;
     S->cv_work.notify_one();
+    return PF_OK;
+}
+
+pf_status pf_server_footprint(const pf_job* q, size_t* bytes) {
+    pf_status st = check_job(q);
+    if (st != PF_OK) return st;
+    if (!bytes) return fail(PF_EINVAL, "pf_server_footprint: bytes is NULL");
+    *bytes = job_estimate(*q, nnz_bound(*q)) + topo_estimate(*q);
     return PF_OK;
 }
 

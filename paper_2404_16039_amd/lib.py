@@ -148,6 +148,7 @@ _sig = {
     "pf_server_create": ([C.c_size_t, I32, I32, C.POINTER(P)], C.c_int),
     "pf_server_now": ([P], C.c_double),
     "pf_server_submit": ([P, C.POINTER(Job), C.POINTER(C.c_uint64)], C.c_int),
+    "pf_server_footprint": ([C.POINTER(Job), C.POINTER(C.c_size_t)], C.c_int),
     "pf_server_poll": ([P, C.c_uint64, C.POINTER(JobResult)], C.c_int),
     "pf_server_wait": ([P, C.c_uint64, C.POINTER(JobResult)], C.c_int),
     "pf_server_drain": ([P], C.c_int),
@@ -405,6 +406,14 @@ def _host_ptr(x):
     if not x.flags["C_CONTIGUOUS"]:
         raise ValueError("server job arrays must be C-contiguous")
     return x.ctypes.data
+
+
+def server_footprint(dim, prec, nn, ne):
+    """Device bytes a job of this size is admitted with when its structure is not resident."""
+    job = Job(int(dim), int(prec), int(nn), int(ne), 16, 16, 0, -1.0, fallback(), None, None, 0)
+    b = C.c_size_t()
+    _chk(_lib.pf_server_footprint(C.byref(job), C.byref(b)), "pf_server_footprint")
+    return b.value
 
 
 class Server:

@@ -109,3 +109,14 @@ def test_server_host_validation_without_gpu():
     assert L.pf_server_drain(None) == 1
     assert L.pf_server_stats(None, None) == 1
     L.pf_server_destroy(None)
+
+
+def test_server_footprint_without_gpu():
+    from paper_2404_16039_amd import lib
+    small = lib.server_footprint(3, lib.F32, 729, 3072)
+    big = lib.server_footprint(3, lib.F32, 9261, 48000)
+    assert 0 < small < big
+    assert lib.server_footprint(2, lib.F64, 100, 162) > lib.server_footprint(2, lib.F32, 100, 162)
+    import pytest
+    with pytest.raises(lib.PagefemError):
+        lib.server_footprint(5, lib.F32, 10, 10)

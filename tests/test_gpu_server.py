@@ -104,7 +104,7 @@ def test_budget_queueing_and_rejection(lib):
     that can never fit is refused at submission."""
     say("server budget")
     c, e = _mesh(3, 8, 1)
-    budget = 3 * 1024 * 1024
+    budget = int(2.5 * lib.server_footprint(3, lib.F32, c.shape[0], e.shape[0]))
     srv = lib.Server(budget, 64)
     with pytest.raises(lib.PagefemError) as ei:
         big_c, big_e = _mesh(3, 20, 2)
@@ -146,7 +146,8 @@ def test_resident_structures(lib):
     # eviction: two topologies that do not fit together
     c1, e1 = _mesh(3, 10, 1)
     c2, e2 = _mesh(3, 11, 2)
-    budget = 5 * 512 * 1024  # one resident structure plus one job, not two structures
+    # room for one new job, not for a resident structure next to it
+    budget = lib.server_footprint(3, lib.F32, c2.shape[0], e2.shape[0]) + 65536
     srv = lib.Server(budget, 8)
     for k in range(3):
         srv.wait(srv.submit(3, lib.F32, c1, e1, topology=1))
