@@ -141,15 +141,22 @@ __global__ __launch_bounds__(SBS) void k_scan_apply(const int32_t* __restrict__ 
 // (element, local node) entries in an LDS hash table keyed by node id, so a node that
 // appears several times in the tile (neighbouring elements share nodes) costs one global
 // atomic per tile instead of one per entry.
-constexpr int AG_BS = 256;
-constexpr int AG_ITEMS = 4;
+#ifndef PF_SCATTER_BS
+#define PF_SCATTER_BS 128
+#endif
+#ifndef PF_SCATTER_ITEMS
+#define PF_SCATTER_ITEMS 4
+#endif
+constexpr int AG_BS = PF_SCATTER_BS;
+constexpr int AG_ITEMS = PF_SCATTER_ITEMS;
 constexpr int AG_TILE = AG_BS * AG_ITEMS;
 constexpr int AG_HASH = 2 * AG_TILE;  // load factor <= 1/2, probing always ends
+constexpr int AG_BITS = AG_HASH == 1024 ? 10 : AG_HASH == 2048 ? 11 : AG_HASH == 4096 ? 12 : AG_HASH == 8192 ? 13 : 0;
+static_assert(AG_BITS > 0, "the scatter table holds 1024..8192 slots");
 
 __device__ __forceinline__ int ag_hash(int32_t node) {
-    return static_cast<int>((static_cast<uint32_t>(node) * 2654435761u) >> (32 - 11)) & (AG_HASH - 1);
+    return static_cast<int>((static_cast<uint32_t>(node) * 2654435761u) >> (32 - AG_BITS));
 }
-static_assert(AG_HASH == 2048, "ag_hash yields 11 bits");
 
 // insert `node` (or find it) in the block's table; returns its slot
 __device__ __forceinline__ int ag_insert(int32_t* keys, int32_t node) {
@@ -227,11 +234,18 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
 // ranks give both col_idx and, for every adjacency entry, the row positions ("slots") of the
 // element's other nodes.  Entries are dealt to lanes row-interleaved (entry j of row r is
 // item r + nr j), so the lanes of one instruction insert into different rows' tables.
-constexpr int RR = 32;           // rows per block in the row-pattern kernels
-constexpr int RT = 256;          // threads per block
+#ifndef PF_PATTERN_RR
+#define PF_PATTERN_RR 8
+#endif
+#ifndef PF_PATTERN_RT
+#define PF_PATTERN_RT 128
+#endif
+constexpr int RR = PF_PATTERN_RR;  // rows per block in the row-pattern kernels
+constexpr int RT = PF_PATTERN_RT;  // threads per block
 constexpr int RSUB = MAXROW;     // slots of one row's table: every admissible row fits
 constexpr int RBATCH = 4;        // entries gathered together per thread (independent loads)
 static_assert(RR <= 64, "the row-count prefix runs in one wave");
+static_assert(RT >= RR && RT >= 64, "one thread per row and a full first wave");
 
 __device__ __forceinline__ int rsub_hash(int32_t v) {
     return static_cast<int>((static_cast<uint32_t>(v) * 2654435761u) >> 26);  // 6 bits
@@ -396,7 +410,13 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
         const int n = min(cnt[r], MAXROW);
         const int32_t v = seg[r * MAXROW + p];
         int rank = 0;
-        for (int j = 0; j < n; ++j) rank += seg[r * MAXROW + j] < v;
+        const int32_t* sr = seg + r * MAXROW;
+        int j = 0;
+        for (; j + 4 <= n; j += 4) {  // four independent LDS reads per step
+            const int32_t a0 = sr[j], a1 = sr[j + 1], a2 = sr[j + 2], a3 = sr[j + 3];
+            rank += (a0 < v) + (a1 < v) + (a2 < v) + (a3 < v);
+        }
+        for (; j < n; ++j) rank += sr[j] < v;
         rank_of[r * MAXROW + p] = static_cast<uint8_t>(rank);
         colpad[(r0 + r) * MAXROW + rank] = v;
     }
@@ -430,7 +450,7 @@ __global__ __launch_bounds__(RT) void k_compact(int64_t nn, const int32_t* __res
     __shared__ int32_t rp[CR + 1];
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * CR;
     const int nr = static_cast<int>((r0 + CR < nn) ? CR : nn - r0);
-    if (threadIdx.x <= nr) rp[threadIdx.x] = row_ptr[r0 + threadIdx.x];
+    for (int i = threadIdx.x; i <= nr; i += RT) rp[i] = row_ptr[r0 + i];
     __syncthreads();
     const int32_t w0 = rp[0];
     const int W = rp[nr] - w0;
