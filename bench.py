@@ -78,6 +78,9 @@ def parse():
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     ap.add_argument("--workload", choices=["assembly", "pages", "batch", "serve"], default="assembly")
+    ap.add_argument("--coef", choices=["one", "quad"], default="one",
+                    help="assembly coefficients: c = 1, or c = exp(x1+x2+x3) at the 4 points of the degree-2 rule "
+                         "(the paper's section 3.6 benchmark)")
     ap.add_argument("--jobs", type=int, default=1000, help="jobs of the serving trace")
     ap.add_argument("--rate", type=float, default=200.0, help="arrival rate of the serving trace (jobs/s)")
     ap.add_argument("--tuner-cache", default=None, help="JSON schedule cache of the batch workload")
@@ -413,6 +416,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    quad = args.coef == "quad"
+    if quad:  # coefficient values at the integration points: inputs resident in HBM before the clock
+        xq = L.quad_points(tc, te, 2)
+        cq = torch.exp(xq.sum(dim=2)).to(torch.float32).contiguous()
+        del xq
     csr = L.Csr()
     csr.symbolic(3, nn, te)
     _, nnz, _, _ = csr.info()
@@ -428,7 +436,10 @@ def main():
         csr.symbolic(3, nn, te, stream=stream)
         if ev:
             ev[1].record(stream)
-        csr.assemble(L.F32, tc, te, valsK, valsM, fb=fb, counters=ctr, stream=stream)
+        if quad:
+            csr.assemble_quad(L.F32, tc, 2, valsK, valsM, cKq=cq, cMq=cq, fb=fb, counters=ctr, stream=stream)
+        else:
+            csr.assemble(L.F32, tc, te, valsK, valsM, fb=fb, counters=ctr, stream=stream)
         if ev:
             ev[2].record(stream)
         L.boundary_normals(L.F32, tc, tf, unit=unit, measure=area, stream=stream)
@@ -455,8 +466,9 @@ def main():
     ms_step = wall * 1e3 / args.steps
     value = ne / (wall / args.steps)
     # algorithmic bytes of the numeric assembly kernel: elems (16 B/tet), FP64 coordinates
-    # (24 B/node), FP32 K and M values (8 B/nonzero)
-    alg_num = 16 * ne + 24 * nn + 8 * nnz
+    # (24 B/node), FP32 K and M values (8 B/nonzero); with quadrature also the FP32
+    # coefficients at 4 points for K and for M (32 B/tet)
+    alg_num = 16 * ne + 24 * nn + 8 * nnz + (32 * ne if quad else 0)
     # whole step: numeric + the structure written once (row_ptr, col_idx) + boundary faces
     # (12 B of indices and 16 B of FP32 outputs per face; their coordinates are counted above)
     alg_step = alg_num + 4 * (nn + 1) + 4 * nnz + nf * (12 + 16)
@@ -466,7 +478,11 @@ def main():
               "boundary_ms": round(float(bnd.mean()), 4)}
     dominant = max(phases, key=phases.get)
 
-    traffic = traffic_of(TRAFFIC_FILE, KERNEL_SOURCES, n=n)
+    traffic = None if quad else traffic_of(TRAFFIC_FILE, KERNEL_SOURCES, n=n)
+    # the paper's level-7 cube (2,146,689 nodes, 12,582,912 tets), K + M with c = exp(x1+x2+x3)
+    # at quadrature points: 66.6 s + 20.4 s in MATLAB (hardware not stated)
+    paper_tets_per_s = 12582912 / (66.6 + 20.4)
+    vs = value / paper_tets_per_s if (quad and n == 128) else None
 
     out = {
         "metric": "P1 tet elements assembled/sec (stiffness + mass, CSR) + achieved HBM GB/s",
@@ -478,12 +494,13 @@ def main():
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
-        "vs_baseline": None,
+        "vs_baseline": vs,
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "3-D P1 tets, FP32 bulk with FP64 fallback: unit cube, %d^3 cubes x 6 Kuhn tets, "
-                               "jitter 0.15 h; K + M CSR assembly (symbolic + numeric) and boundary normals/areas"
-                               % n,
+                               "jitter 0.15 h; K + M CSR assembly (symbolic + numeric) and boundary normals/areas%s"
+                               % (n, "; c_K = c_M = exp(x1+x2+x3) at the 4 points of the degree-2 rule" if quad else
+                                  ""),
                    "tets": ne, "nodes": nn, "nnz": int(nnz), "boundary_faces": nf,
                    "fallback": "det < 1e-3 h^3 or det-condition > 1e6 -> FP64", "coords": "f64"},
         "hbm_gbps_step": alg_step / (ms_step * 1e-3) / 1e9,
@@ -491,7 +508,9 @@ def main():
         "numeric_tets_per_s": ne / (num_ms * 1e-3),
         "routed_per_step": routed,
         "bad_index": bad,
-        "roofline": {"kernel": "k_numeric<3,float> (pf_assemble)", "bound": "hbm", "achieved": achieved,
+        "roofline": {"kernel": "k_numeric<3,float%s> (%s)" % (",QN=4" if quad else "",
+                                                               "pf_assemble_quad" if quad else "pf_assemble"),
+                     "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": alg_num, "dominant_phase": dominant},
         "paper_context": {"what": "MATLAB page-function library, 3-D P1 K and M at 2,146,689 nodes (level 7), "
@@ -504,12 +523,20 @@ def main():
         cn = args.cpu_n
         c2, e2, _ = gen.cube_mesh(cn, jitter=0.15, with_faces=False)
         t1 = time.perf_counter()
-        el = oracle.p1_elements(c2, e2)
+        if quad:  # coefficients at the integration points are inputs, as on the GPU side
+            xq2 = oracle.quad_points(c2, e2, 2)
+            cq2 = np.exp(xq2.sum(axis=2))
+            t1 = time.perf_counter()
+            el = oracle.p1_elements_q(c2, e2, 2, cq2, cq2)
+        else:
+            el = oracle.p1_elements(c2, e2)
         oracle.assemble(e2, c2.shape[0], el["Ke"], el["Me"], el["Kabs"])
         dt = time.perf_counter() - t1
         out["cpu_baseline"] = {"value": e2.shape[0] / dt, "unit": "tets/s", "cores": 1, "kind": "oracle",
-                               "sample": "FP64 oracle (element matrices + stable-sort sparse assembly of K and M, "
-                                         "single thread) on the %d^3 Kuhn mesh, %d tets, %.1f s" % (cn, e2.shape[0], dt)}
+                               "sample": "FP64 oracle (element matrices%s + stable-sort sparse assembly of K and M, "
+                                         "single thread) on the %d^3 Kuhn mesh, %d tets, %.1f s"
+                                         % (" with coefficients at the integration points" if quad else "", cn,
+                                            e2.shape[0], dt)}
     print(json.dumps(out))
     csr.close()
 

@@ -161,6 +161,17 @@ pf_status pf_elem_stiffness_mass(int dim, pf_dtype prec, int64_t nn, const doubl
                                  void* K3D, void* M3D, const pf_fallback* fb, uint8_t* flags,
                                  int64_t* d_counters, void* stream);
 
+/* Integration points of every element for coefficients given at integration points (the
+ * coeffs_in_ip step of the section 3.6 listings).  order 1: the centroid (1 point); order
+ * 2: the degree-2 exact rule, in 2-D the 3 edge midpoints (point q on the edge between local
+ * nodes q and q+1 mod 3), in 3-D the 4 points with barycentric coordinate A = (5+3 sqrt 5)/20
+ * at local node q and B = (5 - sqrt 5)/20 at the others; equal weights summing to 1/dim!.
+ * xq[ne][nq][dim] (FP64): the caller evaluates its coefficient functions there and passes
+ * the values to pf_assemble_quad.  Bad node ids give NaN points.  PF_EINVAL for another
+ * order. */
+pf_status pf_quad_points(int dim, int order, int64_t nn, const double* coords, int64_t ne,
+                         const int32_t* elems, double* xq, void* stream);
+
 /* Boundary facets (section 3.2 normals; facesB / areasB of the surface integrals of
  * section 3.5).
  * dim = 3: faces[nf][3] triangles (a,b,c), n = (b-a) x (c-a), measure = |n| / 2.
@@ -203,6 +214,15 @@ pf_status pf_csr_info(const pf_csr* csr, int64_t* nn, int64_t* nnz, const int32_
 pf_status pf_assemble(const pf_csr* csr, pf_dtype prec, const double* coords, const int32_t* elems,
                       const void* cK, const void* cM, void* valsK, void* valsM,
                       const pf_fallback* fb, int64_t* d_counters, void* stream);
+
+/* Numeric assembly with coefficients given at the integration points of a rule of `order`
+ * (1 or 2, the rules of pf_quad_points), as the loop over integration points of the
+ * section 3.6 listings: K_e = sum_q w_q cK_q |det J| dphi^T dphi, M_e = sum_q w_q cM_q
+ * |det J| phi(x_q) phi(x_q)^T.  cKq, cMq: ne x nq values of type prec in element-major
+ * order (nullable = 1).  Everything else as pf_assemble. */
+pf_status pf_assemble_quad(const pf_csr* csr, pf_dtype prec, const double* coords, int order,
+                           const void* cKq, const void* cMq, void* valsK, void* valsM,
+                           const pf_fallback* fb, int64_t* d_counters, void* stream);
 
 void pf_csr_destroy(pf_csr* csr);
 

@@ -50,6 +50,10 @@ def _load():
         lib.or_p1_elements.argtypes = [INT, I64, P, I64, P, P, P, P, P, P, P, P]
         lib.or_p1_elements.restype = I64
         lib.or_create_coords3d.argtypes = [INT, INT, I64, P, I64, P, P, P]
+        lib.or_quad_count.argtypes = [INT, INT]
+        lib.or_quad_points.argtypes = [INT, INT, I64, P, I64, P, P]
+        lib.or_p1_elements_q.argtypes = [INT, INT, I64, P, I64, P, P, P, P, P, P, P]
+        lib.or_p1_elements_q.restype = I64
         lib.or_route_predicate.argtypes = [INT, P, I64, D, D, P, P]
         lib.or_assemble.argtypes = [INT, I64, I64, P, P, P, P, P, P, P, P, P, P, I64]
         lib.or_assemble.restype = I64
@@ -57,7 +61,7 @@ def _load():
         lib.or_boundary.argtypes = [INT, I64, P, I64, P, P, P, P]
         for f in ("or_page_det", "or_page_inv", "or_page_transpose", "or_page_mtimes", "or_page_scale",
                   "or_page_bilinear", "or_create_coords3d", "or_route_predicate", "or_assemble_rows",
-                  "or_boundary"):
+                  "or_boundary", "or_quad_count", "or_quad_points"):
             getattr(lib, f).restype = INT
         _lib = lib
     return _lib
@@ -161,6 +165,42 @@ def p1_elements(coords, elems):
     _check(rc, "p1_elements")
     return {"det": det, "vol": vol, "grads": grads, "Ke": Ke, "Me": Me, "Kabs": Ka, "facet": fac,
             "nsingular": int(rc)}
+
+
+def quad_count(dim, order):
+    """Number of integration points of the order-1 / order-2 rule."""
+    n = _load().or_quad_count(int(dim), int(order))
+    _check(0 if n > 0 else n, "quad_count")
+    return n
+
+
+def quad_points(coords, elems, order):
+    """Physical integration points of every element: (ne, nq, dim)."""
+    coords = _f64(coords)
+    elems = _i32(elems)
+    nn, dim = coords.shape
+    ne = elems.shape[0]
+    nq = quad_count(dim, order)
+    xq = np.empty((ne, nq, dim))
+    _check(_load().or_quad_points(dim, int(order), nn, _p(coords), ne, _p(elems), _p(xq)), "quad_points")
+    return xq
+
+
+def p1_elements_q(coords, elems, order, cKq=None, cMq=None):
+    """Ke, Me (and error scales Kabs, Mabs) with coefficients at the integration points
+    (cKq, cMq: (ne, nq) or None for 1)."""
+    coords = _f64(coords)
+    elems = _i32(elems)
+    nn, dim = coords.shape
+    ne, nlb = elems.shape
+    nq = quad_count(dim, order)
+    ck = None if cKq is None else _f64(np.asarray(cKq).reshape(ne, nq))
+    cm = None if cMq is None else _f64(np.asarray(cMq).reshape(ne, nq))
+    Ke, Me, Ka, Ma = (np.empty((ne, nlb * nlb)) for _ in range(4))
+    rc = _load().or_p1_elements_q(dim, int(order), nn, _p(coords), ne, _p(elems), _p(ck), _p(cm), _p(Ke), _p(Me),
+                                  _p(Ka), _p(Ma))
+    _check(rc, "p1_elements_q")
+    return {"Ke": Ke, "Me": Me, "Kabs": Ka, "Mabs": Ma, "nsingular": int(rc)}
 
 
 def create_coords3d(coords, elems):

@@ -321,6 +321,111 @@ int64_t or_p1_elements(int dim, int64_t nn, const double* coords, int64_t ne, co
     return nsing;
 }
 
+/* Integration rules on the reference simplex (the integration points and weights of the
+ * section 3.6 listings; weights sum to the reference measure 1/dim!), in barycentric
+ * coordinates lam[q][j] of local node j:
+ *   order 1: the centroid, weight 1/dim!;
+ *   order 2: the degree-2 exact rules of p1_mass_rule.                                  */
+static int quad_rule(int dim, int order, double lam[4][4], double* w) {
+    if (order == 2) return p1_mass_rule(dim, lam, w);
+    int nlb = dim + 1;
+    for (int j = 0; j < nlb; j++) lam[0][j] = 1.0 / nlb;
+    w[0] = (dim == 2) ? 0.5 : 1.0 / 6.0;
+    return 1;
+}
+
+int or_quad_count(int dim, int order) {
+    double lam[4][4], w[4];
+    if ((dim != 2 && dim != 3) || (order != 1 && order != 2)) return -1;
+    return quad_rule(dim, order, lam, w);
+}
+
+/* Physical integration points x_q = sum_j lam[q][j] p_j of every element: ne x nq x dim */
+int or_quad_points(int dim, int order, int64_t nn, const double* coords, int64_t ne, const int32_t* elems,
+                   double* xq) {
+    double lam[4][4], w[4];
+    if ((dim != 2 && dim != 3) || (order != 1 && order != 2)) return -1;
+    int nq = quad_rule(dim, order, lam, w), nlb = dim + 1;
+    for (int64_t e = 0; e < ne; e++)
+        for (int q = 0; q < nq; q++)
+            for (int i = 0; i < dim; i++) {
+                double x = 0.0;
+                for (int j = 0; j < nlb; j++) {
+                    int64_t node = elems[e * nlb + j];
+                    if (node < 0 || node >= nn) return -2;
+                    x += lam[q][j] * coords[node * dim + i];
+                }
+                xq[(e * nq + q) * dim + i] = x;
+            }
+    return 0;
+}
+
+/* Element matrices with coefficients given at the integration points, as the loop over
+ * integration points of the stiffness / mass listings of section 3.6 computes them:
+ *   Ke = sum_q w_q cK_q |det| dphi^T dphi,  Me = sum_q w_q cM_q |det| phi(x_q) phi(x_q)^T,
+ * with error scales Kabs = sum_q w_q |cK_q| |det| |dphi_a| |dphi_b| and
+ * Mabs = sum_q w_q |cM_q| |det| phi_a phi_b.  cKq, cMq: ne x nq values (NULL = 1).
+ * The Jacobian, its inverse and the gradients follow or_p1_elements step by step. */
+int64_t or_p1_elements_q(int dim, int order, int64_t nn, const double* coords, int64_t ne, const int32_t* elems,
+                         const double* cKq, const double* cMq, double* Ke, double* Me, double* Kabs, double* Mabs) {
+    if ((dim != 2 && dim != 3) || (order != 1 && order != 2)) return -1;
+    int nlb = dim + 1;
+    double ds[3 * 4];
+    p1_dshape(dim, ds);
+    double lam[4][4], wq[4];
+    int nq = quad_rule(dim, order, lam, wq);
+    int64_t nsing = 0;
+    for (int64_t e = 0; e < ne; e++) {
+        double c3[3 * 4];
+        for (int j = 0; j < nlb; j++) {
+            int64_t node = elems[e * nlb + j];
+            if (node < 0 || node >= nn) return -2;
+            for (int i = 0; i < dim; i++) AT(c3, dim, i, j) = coords[node * dim + i];
+        }
+        double tjac[9];
+        for (int r = 0; r < dim; r++)
+            for (int c = 0; c < dim; c++) {
+                double acc = 0.0;
+                for (int j = 0; j < nlb; j++) acc += AT(ds, dim, r, j) * AT(c3, dim, c, j);
+                AT(tjac, dim, r, c) = acc;
+            }
+        double adet = fabs(leibniz(tjac, dim, NULL));
+        double tinv[9];
+        nsing += gauss_jordan(tjac, dim, tinv);
+        double dphi[12];
+        for (int r = 0; r < dim; r++)
+            for (int j = 0; j < nlb; j++) {
+                double acc = 0.0;
+                for (int p = 0; p < dim; p++) acc += AT(tinv, dim, r, p) * AT(ds, dim, p, j);
+                AT(dphi, dim, r, j) = acc;
+            }
+        double gnorm[4];
+        for (int j = 0; j < nlb; j++) {
+            double g2 = 0.0;
+            for (int i = 0; i < dim; i++) g2 += AT(dphi, dim, i, j) * AT(dphi, dim, i, j);
+            gnorm[j] = sqrt(g2);
+        }
+        for (int a = 0; a < nlb; a++)
+            for (int b = 0; b < nlb; b++) {
+                double gg = 0.0;
+                for (int i = 0; i < dim; i++) gg += AT(dphi, dim, i, a) * AT(dphi, dim, i, b);
+                double k = 0.0, ka = 0.0, m = 0.0, ma = 0.0;
+                for (int q = 0; q < nq; q++) {
+                    double ck = cKq ? cKq[e * nq + q] : 1.0, cm = cMq ? cMq[e * nq + q] : 1.0;
+                    k += wq[q] * ck * adet * gg;
+                    ka += wq[q] * fabs(ck) * adet * gnorm[a] * gnorm[b];
+                    m += wq[q] * cm * adet * lam[q][a] * lam[q][b];
+                    ma += wq[q] * fabs(cm) * adet * lam[q][a] * lam[q][b];
+                }
+                if (Ke) Ke[e * nlb * nlb + a + b * nlb] = k;
+                if (Kabs) Kabs[e * nlb * nlb + a + b * nlb] = ka;
+                if (Me) Me[e * nlb * nlb + a + b * nlb] = m;
+                if (Mabs) Mabs[e * nlb * nlb + a + b * nlb] = ma;
+            }
+    }
+    return nsing;
+}
+
 /* coords3D and vectors3D of the coordinate-structure listing (section 3.1):
  * coords3D dim x nlb x ne, vectors3D dim x (nlb-1) x ne with column j = node j - last node */
 int or_create_coords3d(int dim, int nlb, int64_t nn, const double* coords, int64_t ne,

@@ -19,6 +19,7 @@
 // the result is bitwise reproducible whatever the order of the atomic adds.
 #include "p1elem.hpp"
 #include "internal.hpp"
+#include "quadrature.hpp"
 
 #include <algorithm>
 #include <new>
@@ -568,7 +569,7 @@ __device__ __forceinline__ void origin_row(const P1Geom<DIM, C>& g, C ck, C cm, 
 // is required, and the path stays light on registers).
 template <int DIM>
 __device__ __forceinline__ void origin_row_f64(const double (&u)[DIM][DIM], double ck, double cm,
-                                               double (&k)[DIM + 1], double& mo) {
+                                               double (&k)[DIM + 1], double& mo, double& adet_out) {
     double c[DIM + 1][DIM];
     double det;
     if constexpr (DIM == 3) {
@@ -596,6 +597,7 @@ __device__ __forceinline__ void origin_row_f64(const double (&u)[DIM][DIM], doub
         c[0][i] = -s;
     }
     const double adet = fabs(det);
+    adet_out = adet;
     const double kf = ck / (fact_dim<DIM>() * adet);
 #pragma unroll
     for (int b = 0; b <= DIM; ++b) {
@@ -644,8 +646,10 @@ constexpr size_t numeric_lds_bytes(int nr, int wmax) {
 //   phase 2  every slot converts its sum and stores it once (coalesced).
 // Entries and slots are dealt row-interleaved (item r + nr j), so the lanes of one
 // instruction work on different rows and their LDS atomics hit different addresses.
-// One block of NR rows starting at row r0 (the body of the numeric kernels).
-template <int DIM, typename T, bool COEF, int NR>
+// One block of NR rows starting at row r0 (the body of the numeric kernels).  QN > 0:
+// cK and cM hold QN values per element at the integration points of the QuadRule<DIM, QN>
+// (the stiffness takes their weighted mean, the mass row is integrated point by point).
+template <int DIM, typename T, bool COEF, int NR, int QN = 0>
 __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const double* __restrict__ coords,
                                               const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
                                               const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
@@ -716,7 +720,8 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
 
     // phase 1a: rows of the adjacent elements, in registers; per-slot maxima
     const float tau_abs = static_cast<float>(fb.tau_abs), tau_cond = static_cast<float>(fb.tau_cond);
-    T kr[NITEMS][NLB], mr[NITEMS];
+    constexpr int MQ = QN > 0 ? DIM + 1 : 1;  // mass values per row: one per node with a rule, else one
+    T kr[NITEMS][NLB], mr[NITEMS][MQ];
     int64_t routed = 0;
 #pragma unroll
     for (int q = 0; q < NITEMS; ++q) {
@@ -726,10 +731,21 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
         const int s0 = rp[r] - w0;
         const uint32_t p = pw[q];
         T ck = T(1), cm = T(1);
-        if constexpr (COEF) {
+        T cmq[QN > 0 ? QN : 1];
+        if constexpr (COEF && QN == 0) {
             const int64_t e = adj[t] >> 2;
             if (cK) ck = cK[e];
             if (cM) cm = cM[e];
+        }
+        if constexpr (QN > 0) {
+            const int64_t e = adj[t] >> 2;
+            T sk = T(0);
+#pragma unroll
+            for (int iq = 0; iq < QN; ++iq) {
+                sk += cK ? cK[e * QN + iq] : T(1);
+                cmq[iq] = cM ? cM[e * QN + iq] : T(1);
+            }
+            ck = sk * static_cast<T>(1.0 / QN);  // equal weights: the weighted mean of the stiffness coefficient
         }
         T u[DIM][DIM];
 #pragma unroll
@@ -743,6 +759,8 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
         p1_geom_edges<DIM, T>(u, g);
         bool route = false;
         if constexpr (sizeof(T) == 4) route = route32(g.det, g.absterms, tau_abs, tau_cond, fb.enable);
+        T adet_t = fabs(g.det);
+        double adet_d = 0.0;
         if (route) {
             // FP64 recomputation from the coordinates of the row's node and the three others
             const int64_t i = r0 + r;
@@ -754,23 +772,44 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
                 for (int c = 0; c < DIM; ++c) ev[k][c] = coords[col * DIM + c] - coords[i * DIM + c];
             }
             double kd[NLB], md;
-            origin_row_f64<DIM>(ev, ck, cm, kd, md);
+            origin_row_f64<DIM>(ev, ck, cm, kd, md, adet_d);
 #pragma unroll
             for (int b = 0; b < NLB; ++b) kr[q][b] = static_cast<T>(kd[b]);
-            mr[q] = static_cast<T>(md);
+            mr[q][0] = static_cast<T>(md);
             if ((p & 3) == 0) ++routed;  // count each element once, at its first node's row
         } else {
-            origin_row<DIM, T>(g, ck, cm, kr[q], mr[q]);
+            origin_row<DIM, T>(g, ck, cm, kr[q], mr[q][0]);
+        }
+        if constexpr (QN > 0) {
+            // mass row by the rule: |det| sum_q w cM_q lam_a(q) lam_b(q), b = the row's node,
+            // then the other nodes in local order
+            const int a = static_cast<int>(p & 3);
+            T ms[NLB];
+#pragma unroll
+            for (int b = 0; b < NLB; ++b) ms[b] = T(0);
+#pragma unroll
+            for (int iq = 0; iq < QN; ++iq) {
+                const T wl = static_cast<T>(quad_weight<DIM, QN>() * QuadRule<DIM, QN>::lam(iq, a)) * cmq[iq];
+#pragma unroll
+                for (int b = 0; b < NLB; ++b) {
+                    const int lb = b == 0 ? a : (b - 1 < a ? b - 1 : b);
+                    ms[b] = fmaT(wl, static_cast<T>(QuadRule<DIM, QN>::lam(iq, lb)), ms[b]);
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < NLB; ++b)
+                mr[q][b] = route ? static_cast<T>(adet_d * static_cast<double>(ms[b])) : adet_t * ms[b];
         }
         const int sd = dslot[r];
         atomicMax(reinterpret_cast<uint32_t*>(shK + sd), Exact<T>::mag(kr[q][0]));
-        atomicMax(reinterpret_cast<uint32_t*>(shM + sd), Exact<T>::mag(mr[q] + mr[q]));
-        const uint32_t mm = Exact<T>::mag(mr[q]);
+        if constexpr (QN > 0) atomicMax(reinterpret_cast<uint32_t*>(shM + sd), Exact<T>::mag(mr[q][0]));
+        else atomicMax(reinterpret_cast<uint32_t*>(shM + sd), Exact<T>::mag(mr[q][0] + mr[q][0]));
+        const uint32_t mm = Exact<T>::mag(mr[q][0]);
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             const int s = s0 + static_cast<int>((p >> (2 + 8 * k)) & 255);
             atomicMax(reinterpret_cast<uint32_t*>(shK + s), Exact<T>::mag(kr[q][1 + k]));
-            atomicMax(reinterpret_cast<uint32_t*>(shM + s), mm);
+            atomicMax(reinterpret_cast<uint32_t*>(shM + s), QN > 0 ? Exact<T>::mag(mr[q][QN > 0 ? 1 + k : 0]) : mm);
         }
     }
     if (routed) count_add(d_counters, 0, routed);
@@ -790,12 +829,13 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
         const int s0 = rp[r] - w0;
         const int sd = dslot[r];
         atomicAdd(accK + sd, Exact<T>::quant(kr[q][0], shK[sd]));
-        atomicAdd(accM + sd, Exact<T>::quant(mr[q] + mr[q], shM[sd]));
+        if constexpr (QN > 0) atomicAdd(accM + sd, Exact<T>::quant(mr[q][0], shM[sd]));
+        else atomicAdd(accM + sd, Exact<T>::quant(mr[q][0] + mr[q][0], shM[sd]));
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             const int s = s0 + static_cast<int>((pw[q] >> (2 + 8 * k)) & 255);
             atomicAdd(accK + s, Exact<T>::quant(kr[q][1 + k], shK[s]));
-            atomicAdd(accM + s, Exact<T>::quant(mr[q], shM[s]));
+            atomicAdd(accM + s, Exact<T>::quant(mr[q][QN > 0 ? 1 + k : 0], shM[s]));
         }
     }
     __syncthreads();
@@ -807,14 +847,14 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
     }
 }
 
-template <int DIM, typename T, bool COEF, int NR>
+template <int DIM, typename T, bool COEF, int NR, int QN = 0>
 __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __restrict__ coords,
                                                  const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
                                                  const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
                                                  const uint32_t* __restrict__ pk, const T* __restrict__ cK,
                                                  const T* __restrict__ cM, T* __restrict__ valsK, T* __restrict__ valsM,
                                                  Fallback fb, int64_t* d_counters, int wmax) {
-    numeric_block<DIM, T, COEF, NR>(static_cast<int64_t>(blockIdx.x) * NR, nn, coords, row_ptr, col_idx, adj_len, adj,
+    numeric_block<DIM, T, COEF, NR, QN>(static_cast<int64_t>(blockIdx.x) * NR, nn, coords, row_ptr, col_idx, adj_len, adj,
                                     pk, cK, cM, valsK, valsM, fb, d_counters, wmax);
 }
 
@@ -870,28 +910,42 @@ pf_status scan(const int32_t* in, int64_t n, int32_t* out, int64_t* bsum, int64_
     return launch_check("scan");
 }
 
-template <int DIM, typename T, bool COEF, int NRB>
+template <int DIM, typename T, bool COEF, int NRB, int QN = 0>
 pf_status launch_numeric(const pf_csr* c, const double* coords, const void* cK, const void* cM, void* valsK,
                          void* valsM, Fallback f, int64_t* ctr, int wmax, hipStream_t s) {
     const size_t shm = numeric_lds_bytes<DIM, T>(NRB, wmax);
     const unsigned g = static_cast<unsigned>(ceil_div(c->nn, NRB));
-    hipLaunchKernelGGL((k_numeric<DIM, T, COEF, NRB>), dim3(g), dim3(NBT), shm, s, c->nn, coords, c->row_ptr,
+    hipLaunchKernelGGL((k_numeric<DIM, T, COEF, NRB, QN>), dim3(g), dim3(NBT), shm, s, c->nn, coords, c->row_ptr,
                        c->col_idx, c->adj_len, c->adj, c->pk, static_cast<const T*>(cK), static_cast<const T*>(cM),
                        static_cast<T*>(valsK), static_cast<T*>(valsM), f, ctr, wmax);
     return launch_check("pf_assemble");
 }
 
 template <int DIM, typename T>
+bool numeric_big(const pf_csr* c) {
+    return numeric_lds_bytes<DIM, T>(NR_BIG, c->wmax_big) <= LDS_BYTES && c->max_adj <= NITEMS * NBT / NR_BIG;
+}
+
+template <int DIM, typename T>
 pf_status numeric_dispatch(const pf_csr* c, const double* coords, const void* cK, const void* cM, void* valsK,
                            void* valsM, Fallback f, int64_t* ctr, hipStream_t s) {
     const bool coef = cK || cM;
-    if (numeric_lds_bytes<DIM, T>(NR_BIG, c->wmax_big) <= LDS_BYTES && c->max_adj <= NITEMS * NBT / NR_BIG) {
+    if (numeric_big<DIM, T>(c)) {
         return coef ? launch_numeric<DIM, T, true, NR_BIG>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_big, s)
                     : launch_numeric<DIM, T, false, NR_BIG>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_big, s);
     }
-    // 8 rows of at most MAXROW nonzeros and MAXADJ (<= NITEMS * NBT / NR_SMALL) elements always fit
+    // 4 rows of at most MAXROW nonzeros and MAXADJ (<= NITEMS * NBT / NR_SMALL) elements always fit
     return coef ? launch_numeric<DIM, T, true, NR_SMALL>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_small, s)
                 : launch_numeric<DIM, T, false, NR_SMALL>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_small, s);
+}
+
+// coefficients at the QN integration points of every element
+template <int DIM, typename T, int QN>
+pf_status numeric_dispatch_quad(const pf_csr* c, const double* coords, const void* cKq, const void* cMq, void* valsK,
+                                void* valsM, Fallback f, int64_t* ctr, hipStream_t s) {
+    if (numeric_big<DIM, T>(c))
+        return launch_numeric<DIM, T, false, NR_BIG, QN>(c, coords, cKq, cMq, valsK, valsM, f, ctr, c->wmax_big, s);
+    return launch_numeric<DIM, T, false, NR_SMALL, QN>(c, coords, cKq, cMq, valsK, valsM, f, ctr, c->wmax_small, s);
 }
 
 }  // namespace
@@ -900,9 +954,7 @@ pf_status numeric_dispatch(const pf_csr* c, const double* coords, const void* cK
 // and its longest adjacency list fits the item budget, else 4 (as pf_assemble chooses)
 template <int DIM, typename T>
 int numeric_rows(const pf_csr* c) {
-    return (numeric_lds_bytes<DIM, T>(NR_BIG, c->wmax_big) <= LDS_BYTES && c->max_adj <= NITEMS * NBT / NR_BIG)
-               ? NR_BIG
-               : NR_SMALL;
+    return numeric_big<DIM, T>(c) ? NR_BIG : NR_SMALL;
 }
 
 int numeric_class(const pf_csr* c, pf_dtype prec) {
@@ -1060,6 +1112,32 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     c->max_adj = static_cast<int>(info[7]);
     c->built = true;
     return PF_OK;
+}
+
+pf_status pf_assemble_quad(const pf_csr* c, pf_dtype prec, const double* coords, int order, const void* cKq,
+                           const void* cMq, void* valsK, void* valsM, const pf_fallback* fb, int64_t* d_counters,
+                           void* stream) {
+    if (!c) return fail(PF_EINVAL, "pf_assemble_quad: null handle");
+    if (!c->built) return fail(PF_ESTATE, "pf_assemble_quad: structure not built");
+    const int qn = quad_count(c->dim, order);
+    if (!qn) return fail(PF_EINVAL, "pf_assemble_quad: order must be 1 or 2");
+    if (c->nn == 0 || c->nnz == 0) return PF_OK;
+    if (!coords || !valsK) return fail(PF_EINVAL, "pf_assemble_quad: null coords or valsK");
+    if (prec != PF_F32 && prec != PF_F64) return fail(PF_EDTYPE, "pf_assemble_quad: prec must be PF_F32 or PF_F64");
+    hipStream_t s = as_stream(stream);
+    Fallback f = make_fallback(fb);
+    if (c->dim == 3) {
+        if (prec == PF_F32)
+            return qn == 1 ? numeric_dispatch_quad<3, float, 1>(c, coords, cKq, cMq, valsK, valsM, f, d_counters, s)
+                           : numeric_dispatch_quad<3, float, 4>(c, coords, cKq, cMq, valsK, valsM, f, d_counters, s);
+        return qn == 1 ? numeric_dispatch_quad<3, double, 1>(c, coords, cKq, cMq, valsK, valsM, f, d_counters, s)
+                       : numeric_dispatch_quad<3, double, 4>(c, coords, cKq, cMq, valsK, valsM, f, d_counters, s);
+    }
+    if (prec == PF_F32)
+        return qn == 1 ? numeric_dispatch_quad<2, float, 1>(c, coords, cKq, cMq, valsK, valsM, f, d_counters, s)
+                       : numeric_dispatch_quad<2, float, 3>(c, coords, cKq, cMq, valsK, valsM, f, d_counters, s);
+    return qn == 1 ? numeric_dispatch_quad<2, double, 1>(c, coords, cKq, cMq, valsK, valsM, f, d_counters, s)
+                   : numeric_dispatch_quad<2, double, 3>(c, coords, cKq, cMq, valsK, valsM, f, d_counters, s);
 }
 
 pf_status pf_csr_info(const pf_csr* c, int64_t* nn, int64_t* nnz, const int32_t** row_ptr, const int32_t** col_idx) {

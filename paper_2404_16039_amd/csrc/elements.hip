@@ -1,6 +1,7 @@
 // elements.hip -- per-element P1 geometry, stiffness and mass matrices (section 3.6), and
 // boundary facet normals and measures (section 3.2).  One element (or facet) per lane.
 #include "p1elem.hpp"
+#include "quadrature.hpp"
 
 namespace pf {
 
@@ -172,6 +173,34 @@ __global__ __launch_bounds__(EBS) void k_boundary(int64_t nn, const double* __re
     }
 }
 
+// Physical integration points x_q = sum_j lam(q, j) p_j of every element (FP64, products
+// and sums in node order without contraction), stored element-major: xq[(e*QN + q)*DIM + i].
+template <int DIM, int QN>
+__global__ __launch_bounds__(EBS) void k_quad_points(int64_t nn, const double* __restrict__ coords, int64_t ne,
+                                                     const int32_t* __restrict__ elems, double* __restrict__ xq) {
+    constexpr int NLB = DIM + 1;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * EBS + threadIdx.x;
+    if (e >= ne) return;
+    double p[NLB][DIM];
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < NLB; ++j) {
+        const int64_t node = elems[e * NLB + j];
+        ok = ok && node >= 0 && node < nn;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) p[j][i] = ok ? coords[node * DIM + i] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < QN; ++q)
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) {
+            double x = 0.0;
+#pragma unroll
+            for (int j = 0; j < NLB; ++j) x += QuadRule<DIM, QN>::lam(q, j) * p[j][i];
+            xq[(e * QN + q) * DIM + i] = ok ? x : NAN;
+        }
+}
+
 namespace {
 
 pf_status check_mesh(int dim, int64_t nn, const double* coords, int64_t ne, const int32_t* elems, const char* who) {
@@ -230,6 +259,26 @@ pf_status pf_elem_stiffness_mass(int dim, pf_dtype prec, int64_t nn, const doubl
     ElemOut o{nullptr, nullptr, nullptr, nullptr, nullptr, K3D, M3D};
     return elem_dispatch(dim, prec, nn, coords, ne, elems, cK, cM, o, fb, flags, d_counters, stream,
                          "pf_elem_stiffness_mass");
+}
+
+pf_status pf_quad_points(int dim, int order, int64_t nn, const double* coords, int64_t ne, const int32_t* elems,
+                         double* xq, void* stream) {
+    pf_status st = check_mesh(dim, nn, coords, ne, elems, "pf_quad_points");
+    if (st) return st;
+    const int qn = quad_count(dim, order);
+    if (!qn) return fail(PF_EINVAL, "pf_quad_points: order must be 1 or 2");
+    if (ne == 0) return PF_OK;
+    if (!xq) return fail(PF_EINVAL, "pf_quad_points: null xq");
+    hipStream_t s = as_stream(stream);
+    const unsigned g = static_cast<unsigned>(ceil_div(ne, EBS));
+    if (dim == 2) {
+        if (qn == 1) hipLaunchKernelGGL((k_quad_points<2, 1>), dim3(g), dim3(EBS), 0, s, nn, coords, ne, elems, xq);
+        else hipLaunchKernelGGL((k_quad_points<2, 3>), dim3(g), dim3(EBS), 0, s, nn, coords, ne, elems, xq);
+    } else {
+        if (qn == 1) hipLaunchKernelGGL((k_quad_points<3, 1>), dim3(g), dim3(EBS), 0, s, nn, coords, ne, elems, xq);
+        else hipLaunchKernelGGL((k_quad_points<3, 4>), dim3(g), dim3(EBS), 0, s, nn, coords, ne, elems, xq);
+    }
+    return launch_check("pf_quad_points");
 }
 
 pf_status pf_boundary_normals(int dim, pf_dtype prec, int64_t nn, const double* coords, int64_t nf,

@@ -131,6 +131,8 @@ _sig = {
     "pf_elem_geometry": ([I32, I32, I64, P, I64, P, P, P, P, P, P, FP, P, P, P], C.c_int),
     "pf_elem_stiffness_mass": ([I32, I32, I64, P, I64, P, P, P, P, P, FP, P, P, P], C.c_int),
     "pf_boundary_normals": ([I32, I32, I64, P, I64, P, P, P, P], C.c_int),
+    "pf_quad_points": ([I32, I32, I64, P, I64, P, P, P], C.c_int),
+    "pf_assemble_quad": ([P, I32, P, I32, P, P, P, P, FP, P, P], C.c_int),
     "pf_csr_create": ([C.POINTER(P)], C.c_int),
     "pf_csr_symbolic": ([P, I32, I64, I64, P, P], C.c_int),
     "pf_csr_info": ([P, C.POINTER(I64), C.POINTER(I64), C.POINTER(P), C.POINTER(P)], C.c_int),
@@ -273,6 +275,22 @@ def boundary_normals(prec, coords, faces, unit=None, measure=None, stream=None):
                                   _s(stream)), "pf_boundary_normals")
 
 
+def quad_count(dim, order):
+    if dim not in (2, 3) or order not in (1, 2):
+        raise ValueError("dim must be 2 or 3 and order 1 or 2")
+    return 1 if order == 1 else dim + 1
+
+
+def quad_points(coords, elems, order, xq=None, stream=None):
+    """Integration points (ne, nq, dim) FP64 of the order-1 / order-2 rule of every element."""
+    nn, dim = coords.shape
+    ne = elems.shape[0]
+    if xq is None:
+        xq = torch.empty((ne, quad_count(dim, order), dim), dtype=torch.float64, device=coords.device)
+    _chk(_lib.pf_quad_points(dim, int(order), nn, _p(coords), ne, _p(elems), _p(xq), _s(stream)), "pf_quad_points")
+    return xq
+
+
 # ----------------------------------------------------------------------------- assembly
 class Csr:
     """Owner of a pf_csr handle (CSR structure of one P1 mesh)."""
@@ -312,6 +330,12 @@ class Csr:
                  stream=None):
         _chk(_lib.pf_assemble(self._h, prec, _p(coords), _p(elems), _p(cK), _p(cM), _p(valsK), _p(valsM),
                               _ref(fb, Fallback), _p(counters), _s(stream)), "pf_assemble")
+
+    def assemble_quad(self, prec, coords, order, valsK, valsM=None, cKq=None, cMq=None, fb=None, counters=None,
+                      stream=None):
+        """Assembly with coefficients at the integration points (ne x nq, type prec)."""
+        _chk(_lib.pf_assemble_quad(self._h, prec, _p(coords), int(order), _p(cKq), _p(cMq), _p(valsK), _p(valsM),
+                                   _ref(fb, Fallback), _p(counters), _s(stream)), "pf_assemble_quad")
 
     def close(self):
         if self._h:

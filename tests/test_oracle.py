@@ -505,3 +505,88 @@ def test_det_condition_hand_worked():
     assert np.all(c1 >= 1.0 - 1e-12) and np.allclose(c1, c2, rtol=1e-13)
     _, cd = oracle.route_predicate(_colmajor(np.diag([2.0, -3.0, 0.5]))[None, :], 3, 0.0, 1e30)
     assert cd[0] == 1.0
+
+
+# ------------------------------------------------------------------ quadrature coefficients
+def _golden_energies():
+    out = {"closed": {}, "p1_3d": [], "p1_2d": []}
+    for line in open(os.path.join(GOLD, "energies.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        if f[0] == "closed":
+            out["closed"][(f[1], f[2])] = float(f[3])
+        else:
+            out[f[0]].append((int(f[1]), int(f[2]), float(f[3]), float(f[4])))
+    return out
+
+
+def _energy_errors(coords, elems, order):
+    """e_K, e_M of the section 3.6 benchmark from the oracle's quadrature-coefficient
+    element matrices assembled with sparse() semantics."""
+    dim = coords.shape[1]
+    pi = np.pi
+    xq = oracle.quad_points(coords, elems, order)
+    cq = np.exp(xq.sum(axis=2))
+    q = oracle.p1_elements_q(coords, elems, order, cq, cq)
+    A = oracle.assemble(elems, coords.shape[0], q["Ke"], q["Me"], q["Kabs"])
+    if dim == 2:
+        v = np.sin(pi * coords[:, 0]) * np.sin(pi * coords[:, 1])
+    else:
+        v = np.cos(pi * coords[:, 0]) * np.cos(pi * coords[:, 1]) * np.cos(pi * coords[:, 2])
+    rows = np.repeat(np.arange(coords.shape[0]), np.diff(A["row_ptr"]))
+    vKv = np.sum(v[rows] * A["valK"] * v[A["col_idx"]])
+    vMv = np.sum(v[rows] * A["valM"] * v[A["col_idx"]])
+    g = _golden_energies()["closed"]
+    key = "2d" if dim == 2 else "3d"
+    return abs(vKv - g[(key, "IK")]), abs(vMv - g[(key, "IM")])
+
+
+def test_energy_closed_forms_match_printed_values():
+    """The closed forms, evaluated, reproduce the printed digits (this fixes the reading of
+    the test functions with the factor pi)."""
+    g = _golden_energies()["closed"]
+    pi, e = np.pi, np.e
+    assert abs(4 * pi**4 * (e - 1)**2 * (1 + 2 * pi**2) / (1 + 4 * pi**2)**2 - g[("2d", "IK")]) < 1e-9
+    assert abs(4 * pi**4 * (e - 1)**2 / (1 + 4 * pi**2)**2 - g[("2d", "IM")]) < 1e-9
+    assert abs(6 * pi**4 * (e - 1)**3 * (1 + 2 * pi**2)**2 / (1 + 4 * pi**2)**3 - g[("3d", "IK")]) < 1e-9
+    assert abs((e - 1)**3 * (1 + 2 * pi**2)**3 / (1 + 4 * pi**2)**3 - g[("3d", "IM")]) < 1e-9
+
+
+def test_quadrature_coefficients_constant_reduce_to_plain():
+    coords, elems, _ = gen.cube_mesh(3, jitter=0.15)
+    plain = oracle.p1_elements(coords, elems)
+    for order in (1, 2):
+        nq = oracle.quad_count(3, order)
+        q = oracle.p1_elements_q(coords, elems, order, 2.5 * np.ones((elems.shape[0], nq)), None)
+        assert np.allclose(q["Ke"], 2.5 * plain["Ke"], rtol=1e-13, atol=0)
+        if order == 2:  # the degree-2 rule integrates the P1 mass matrix exactly
+            assert np.allclose(q["Me"], plain["Me"], rtol=1e-13, atol=1e-300)
+    # the one-point rule puts the element measure on the centroid: M_e = |T| / (d+1)^2
+    q1 = oracle.p1_elements_q(coords, elems, 1)
+    assert np.allclose(q1["Me"], plain["vol"][:, None] / 16.0, rtol=1e-13)
+    # integration points are the barycentric combinations of the vertices
+    xq = oracle.quad_points(coords, elems, 1)
+    assert np.allclose(xq[:, 0, :], coords[elems].mean(axis=1), rtol=0, atol=1e-15)
+
+
+def test_energy_errors_converge_at_second_order_2d():
+    errs = [_energy_errors(*gen.square_mesh(n, jitter=0.0)[:2], 2) for n in (16, 32, 64)]
+    for (k0, m0), (k1, m1) in zip(errs, errs[1:]):
+        assert 3.7 < k0 / k1 < 4.3 and 3.7 < m0 / m1 < 4.3
+
+
+def test_energy_errors_match_printed_3d_table():
+    """Kuhn cube meshes with the node counts of the printed levels 3-5: e_K and e_M within
+    25% of the printed values, and second-order convergence."""
+    rows = _golden_energies()["p1_3d"][:3]
+    errs = []
+    for level, nodes, eK, eM in rows:
+        n = round(nodes ** (1 / 3)) - 1
+        coords, elems, _ = gen.cube_mesh(n, jitter=0.0, with_faces=False)
+        assert coords.shape[0] == nodes
+        k, m = _energy_errors(coords, elems, 2)
+        assert 0.8 < k / eK < 1.25 and 0.8 < m / eM < 1.25, (level, k, eK, m, eM)
+        errs.append((k, m))
+    for (k0, m0), (k1, m1) in zip(errs, errs[1:]):
+        assert 3.6 < k0 / k1 < 4.4 and 3.6 < m0 / m1 < 4.4
