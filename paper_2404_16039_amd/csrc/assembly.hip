@@ -510,20 +510,30 @@ __global__ __launch_bounds__(256) void k_block_stats(int64_t nn, int nr, const i
 // with an LDS atomic max before any add), after which sums of up to MAXADJ grid values are
 // exact in the accumulator type, so atomic adds in any order give the same bits.  The
 // rounding error of a slot is at most 2^-bits times its largest contribution.
-//   FP32 contributions: grid 2^-47 of the slot maximum, FP64 accumulator (53 bits).
+//   FP32 contributions: grid 2^-24 of the slot maximum's power of two (|x| < 2^E quantizes
+//   to an integer below 2^24, exact in FP32 and int32), two's-complement int32 accumulator:
+//   at most 64 contributions per slot keep every partial sum below 2^30.  The grid error of
+//   a slot is at most (contributions) x 2^-25 of its largest contribution's power of two,
+//   i.e. below 2^-18 relative even with 64 contributions, under the FP32 tolerance; the
+//   final conversion rounds once.
 //   FP64 contributions: grid 2^-56, two's-complement int64 accumulator.
 // Only the maximum's exponent matters, so maxima are kept as the high 32 bits of |x|.
 template <typename T>
 struct Exact;
 template <>
 struct Exact<float> {
-    using acc = double;
-    static constexpr int bits = 47;
+    using acc = unsigned int;  // two's-complement int32 sums (LDS integer atomics wrap)
+    static constexpr int bits = 24;
     __device__ static uint32_t mag(float x) { return __float_as_uint(fabsf(x)); }
-    // shift = bits - E with max < 2^E
-    __device__ static int shift(uint32_t m) { return bits - (static_cast<int>((m >> 23) & 255) - 126); }
-    __device__ static acc quant(float x, int sh) { return rint(ldexp(static_cast<double>(x), sh)); }
-    __device__ static float back(acc a, int sh) { return static_cast<float>(ldexp(a, -sh)); }
+    // shift = bits - E with max < 2^E (clamped so that 2^shift stays a normal float)
+    __device__ static int shift(uint32_t m) {
+        int sh = bits - (static_cast<int>((m >> 23) & 255) - 126);
+        return sh > 126 ? 126 : sh;
+    }
+    __device__ static acc quant(float x, int sh) {
+        return static_cast<acc>(static_cast<int>(rintf(ldexpf(x, sh))));
+    }
+    __device__ static float back(acc a, int sh) { return ldexpf(static_cast<float>(static_cast<int>(a)), -sh); }
 };
 template <>
 struct Exact<double> {
@@ -659,11 +669,11 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
     constexpr int NLB = DIM + 1;
     using A = typename Exact<T>::acc;
     extern __shared__ __align__(16) unsigned char smem[];
-    // widest types first, so every LDS access is naturally aligned
-    A* accK = reinterpret_cast<A*>(smem);                       // [wmax]
+    // 16-byte vectors first, then the accumulators, so every LDS access is naturally aligned
+    Vec4<T>* f = reinterpret_cast<Vec4<T>*>(smem);               // [wmax] edge vector per slot
+    A* accK = reinterpret_cast<A*>(f + wmax);                    // [wmax]
     A* accM = accK + wmax;                                       // [wmax]
-    Vec4<T>* f = reinterpret_cast<Vec4<T>*>(accM + wmax);        // [wmax] edge vector per slot
-    int32_t* shK = reinterpret_cast<int32_t*>(f + wmax);         // [wmax] max bits, then shift
+    int32_t* shK = reinterpret_cast<int32_t*>(accM + wmax);      // [wmax] max bits, then shift
     int32_t* shM = shK + wmax;                                   // [wmax]
     int32_t* rp = shM + wmax;                                    // [NR + 1]
     int32_t* alen = rp + (NR + 1);                               // [NR + 1] elements around each row node
