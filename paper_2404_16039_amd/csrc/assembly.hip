@@ -29,6 +29,7 @@ struct pf_csr {
     int dim = 0, nlb = 0;
     int64_t nn = 0, ne = 0, nnz = 0;
     int wmax_big = 0;    // largest CSR window of a numeric block of NR_BIG rows
+    int wmax_mid = 0;    // ... of NR_MID rows
     int wmax_small = 0;  // ... of NR_SMALL rows
     int max_adj = 0;     // largest number of elements around one node
     int32_t* adj_len = nullptr;  // elements around each node
@@ -462,10 +463,17 @@ __global__ __launch_bounds__(RT) void k_compact(int64_t nn, const int32_t* __res
 }
 
 // ---------------------------------------------------------------------------- numeric
-constexpr int NR_BIG = 16;   // rows per block of the numeric kernel
-constexpr int NR_SMALL = 4;  // ... when a big block's window or entries do not fit
+#ifndef PF_NUMERIC_ROWS
+#define PF_NUMERIC_ROWS 32
+#endif
+#ifndef PF_NUMERIC_ITEMS
+#define PF_NUMERIC_ITEMS 3
+#endif
+constexpr int NR_BIG = PF_NUMERIC_ROWS;   // rows per block of the numeric kernel
+constexpr int NR_MID = PF_NUMERIC_ROWS / 2;  // ... when a node has more elements than a big block covers
+constexpr int NR_SMALL = 4;  // ... when neither fits
 constexpr int NBT = 256;     // threads per block of the numeric kernel
-constexpr int NITEMS = 2;    // adjacency entries per thread (held in registers)
+constexpr int NITEMS = PF_NUMERIC_ITEMS;    // adjacency entries per thread (held in registers)
 static_assert(MAXADJ <= NITEMS * NBT / NR_SMALL, "the small numeric blocks must cover any admissible row");
 
 // largest CSR window of one numeric block of `nr` rows into info[slot], and the largest
@@ -931,42 +939,54 @@ pf_status launch_numeric(const pf_csr* c, const double* coords, const void* cK, 
     return launch_check("pf_assemble");
 }
 
+// rows per block: the largest of NR_BIG, NR_MID, NR_SMALL whose window fits the LDS budget
+// and whose item budget covers the longest adjacency row
 template <int DIM, typename T>
-bool numeric_big(const pf_csr* c) {
-    return numeric_lds_bytes<DIM, T>(NR_BIG, c->wmax_big) <= LDS_BYTES && c->max_adj <= NITEMS * NBT / NR_BIG;
+int numeric_rows(const pf_csr* c) {
+    if (numeric_lds_bytes<DIM, T>(NR_BIG, c->wmax_big) <= LDS_BYTES && c->max_adj <= NITEMS * NBT / NR_BIG)
+        return NR_BIG;
+    if (numeric_lds_bytes<DIM, T>(NR_MID, c->wmax_mid) <= LDS_BYTES && c->max_adj <= NITEMS * NBT / NR_MID)
+        return NR_MID;
+    return NR_SMALL;  // 4 rows of at most MAXROW nonzeros and MAXADJ elements always fit
 }
 
 template <int DIM, typename T>
 pf_status numeric_dispatch(const pf_csr* c, const double* coords, const void* cK, const void* cM, void* valsK,
                            void* valsM, Fallback f, int64_t* ctr, hipStream_t s) {
     const bool coef = cK || cM;
-    if (numeric_big<DIM, T>(c)) {
-        return coef ? launch_numeric<DIM, T, true, NR_BIG>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_big, s)
-                    : launch_numeric<DIM, T, false, NR_BIG>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_big, s);
+    switch (numeric_rows<DIM, T>(c)) {
+        case NR_BIG:
+            return coef ? launch_numeric<DIM, T, true, NR_BIG>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_big, s)
+                        : launch_numeric<DIM, T, false, NR_BIG>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_big, s);
+        case NR_MID:
+            return coef ? launch_numeric<DIM, T, true, NR_MID>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_mid, s)
+                        : launch_numeric<DIM, T, false, NR_MID>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_mid, s);
+        default:
+            return coef ? launch_numeric<DIM, T, true, NR_SMALL>(c, coords, cK, cM, valsK, valsM, f, ctr,
+                                                                  c->wmax_small, s)
+                        : launch_numeric<DIM, T, false, NR_SMALL>(c, coords, cK, cM, valsK, valsM, f, ctr,
+                                                                   c->wmax_small, s);
     }
-    // 4 rows of at most MAXROW nonzeros and MAXADJ (<= NITEMS * NBT / NR_SMALL) elements always fit
-    return coef ? launch_numeric<DIM, T, true, NR_SMALL>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_small, s)
-                : launch_numeric<DIM, T, false, NR_SMALL>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_small, s);
 }
 
 // coefficients at the QN integration points of every element
 template <int DIM, typename T, int QN>
 pf_status numeric_dispatch_quad(const pf_csr* c, const double* coords, const void* cKq, const void* cMq, void* valsK,
                                 void* valsM, Fallback f, int64_t* ctr, hipStream_t s) {
-    if (numeric_big<DIM, T>(c))
-        return launch_numeric<DIM, T, false, NR_BIG, QN>(c, coords, cKq, cMq, valsK, valsM, f, ctr, c->wmax_big, s);
-    return launch_numeric<DIM, T, false, NR_SMALL, QN>(c, coords, cKq, cMq, valsK, valsM, f, ctr, c->wmax_small, s);
+    switch (numeric_rows<DIM, T>(c)) {
+        case NR_BIG:
+            return launch_numeric<DIM, T, false, NR_BIG, QN>(c, coords, cKq, cMq, valsK, valsM, f, ctr, c->wmax_big, s);
+        case NR_MID:
+            return launch_numeric<DIM, T, false, NR_MID, QN>(c, coords, cKq, cMq, valsK, valsM, f, ctr, c->wmax_mid, s);
+        default:
+            return launch_numeric<DIM, T, false, NR_SMALL, QN>(c, coords, cKq, cMq, valsK, valsM, f, ctr,
+                                                               c->wmax_small, s);
+    }
 }
 
 }  // namespace
 
-// rows per block of a job's numeric phase: 16 when its largest window fits the LDS budget
-// and its longest adjacency list fits the item budget, else 4 (as pf_assemble chooses)
-template <int DIM, typename T>
-int numeric_rows(const pf_csr* c) {
-    return numeric_big<DIM, T>(c) ? NR_BIG : NR_SMALL;
-}
-
+// rows per block of a job's numeric phase (as pf_assemble chooses)
 int numeric_class(const pf_csr* c, pf_dtype prec) {
     if (c->dim == 3) return prec == PF_F32 ? numeric_rows<3, float>(c) : numeric_rows<3, double>(c);
     return prec == PF_F32 ? numeric_rows<2, float>(c) : numeric_rows<2, double>(c);
@@ -990,7 +1010,9 @@ void numeric_describe(const pf_csr* c, const double* coords, void* valsK, void* 
     out->block0 = block0;
 }
 
-int numeric_wmax(const pf_csr* c, int nr) { return nr == NR_BIG ? c->wmax_big : c->wmax_small; }
+int numeric_wmax(const pf_csr* c, int nr) {
+    return nr == NR_BIG ? c->wmax_big : (nr == NR_MID ? c->wmax_mid : c->wmax_small);
+}
 
 template <int DIM, typename T, int NR>
 pf_status launch_jobs(const NumericJob* d_jobs, int njobs, int64_t nblocks, int wmax, hipStream_t s) {
@@ -1004,18 +1026,18 @@ pf_status numeric_launch_many(int dim, pf_dtype prec, int nr, const NumericJob* 
                               int wmax, hipStream_t s) {
     if (njobs <= 0 || nblocks <= 0) return PF_OK;
     if (nblocks >= (int64_t(1) << 31)) return fail(PF_ELIMIT, "numeric batch: too many row blocks");
+    auto pick = [&](auto big, auto mid, auto small) {
+        return nr == NR_BIG ? big(d_jobs, njobs, nblocks, wmax, s)
+                            : (nr == NR_MID ? mid(d_jobs, njobs, nblocks, wmax, s) : small(d_jobs, njobs, nblocks, wmax, s));
+    };
     if (dim == 3) {
         if (prec == PF_F32)
-            return nr == NR_BIG ? launch_jobs<3, float, NR_BIG>(d_jobs, njobs, nblocks, wmax, s)
-                                : launch_jobs<3, float, NR_SMALL>(d_jobs, njobs, nblocks, wmax, s);
-        return nr == NR_BIG ? launch_jobs<3, double, NR_BIG>(d_jobs, njobs, nblocks, wmax, s)
-                            : launch_jobs<3, double, NR_SMALL>(d_jobs, njobs, nblocks, wmax, s);
+            return pick(launch_jobs<3, float, NR_BIG>, launch_jobs<3, float, NR_MID>, launch_jobs<3, float, NR_SMALL>);
+        return pick(launch_jobs<3, double, NR_BIG>, launch_jobs<3, double, NR_MID>, launch_jobs<3, double, NR_SMALL>);
     }
     if (prec == PF_F32)
-        return nr == NR_BIG ? launch_jobs<2, float, NR_BIG>(d_jobs, njobs, nblocks, wmax, s)
-                            : launch_jobs<2, float, NR_SMALL>(d_jobs, njobs, nblocks, wmax, s);
-    return nr == NR_BIG ? launch_jobs<2, double, NR_BIG>(d_jobs, njobs, nblocks, wmax, s)
-                        : launch_jobs<2, double, NR_SMALL>(d_jobs, njobs, nblocks, wmax, s);
+        return pick(launch_jobs<2, float, NR_BIG>, launch_jobs<2, float, NR_MID>, launch_jobs<2, float, NR_SMALL>);
+    return pick(launch_jobs<2, double, NR_BIG>, launch_jobs<2, double, NR_MID>, launch_jobs<2, double, NR_SMALL>);
 }
 
 size_t csr_bytes(const pf_csr* c) {
@@ -1090,12 +1112,12 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
                                c->colpad, c->pk, c->info);
     }
     if ((st = scan(c->cnt, nn, c->row_ptr, c->bsum, c->info + 2, s))) return st;
-    for (int which = 0; which < 2 && nn > 0; ++which) {
-        const int nr = which == 0 ? NR_BIG : NR_SMALL;
+    for (int which = 0; which < 3 && nn > 0; ++which) {
+        const int nr = which == 0 ? NR_BIG : (which == 1 ? NR_MID : NR_SMALL);
         const int64_t nblk = ceil_div(nn, nr);
         const unsigned g = static_cast<unsigned>(std::min<int64_t>(ceil_div(nblk, 256), 128));
         hipLaunchKernelGGL(k_block_stats, dim3(g), dim3(256), 0, s, nn, nr, c->row_ptr, c->adj_len, nblk, c->info,
-                           3 + 2 * which);
+                           3 + which);
     }
     if ((st = launch_check("pf_csr_symbolic"))) return st;
     int64_t info[8];
@@ -1118,6 +1140,7 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     c->ne = ne;
     c->nnz = nnz;
     c->wmax_big = static_cast<int>(info[3]);
+    c->wmax_mid = static_cast<int>(info[4]);
     c->wmax_small = static_cast<int>(info[5]);
     c->max_adj = static_cast<int>(info[7]);
     c->built = true;
