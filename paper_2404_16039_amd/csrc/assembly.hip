@@ -160,31 +160,40 @@ __device__ __forceinline__ int ag_hash(int32_t node) {
     return static_cast<int>((static_cast<uint32_t>(node) * 2654435761u) >> (32 - AG_BITS));
 }
 
-// insert `node` (or find it) in the block's table; returns its slot
-__device__ __forceinline__ int ag_insert(int32_t* keys, int32_t node) {
+// insert `node` (or find it) in the block's table; returns its slot, fresh = this call
+// inserted it
+__device__ __forceinline__ int ag_insert(int32_t* keys, int32_t node, bool& fresh) {
     int h = ag_hash(node);
     while (true) {
         const int32_t k = atomicCAS(keys + h, -1, node);
-        if (k == -1 || k == node) return h;
+        if (k == -1 || k == node) {
+            fresh = k == -1;
+            return h;
+        }
         h = (h + 1) & (AG_HASH - 1);
     }
 }
 
 // Scatter (element << 2 | local index) into each node's padded row (MAXADJ entries).  One
 // global atomic per (tile, node) on the node's length reserves the tile's positions; entries
-// take positions inside them through LDS atomics.  The order inside a row is not fixed:
-// nothing downstream depends on it (the numeric phase sums exactly, so its result does not
-// depend on the entry order).  Out-of-range node ids and rows beyond MAXADJ set error bits
-// and are not stored.
+// take positions inside them through LDS atomics.  The first inserter of a node lists its
+// table slot, so the block issues the global atomics of all its distinct nodes at once (one
+// round trip) instead of sweeping the table.  The order inside a row is not fixed: nothing
+// downstream depends on it (the numeric phase sums exactly, so its result does not depend
+// on the entry order).  Out-of-range node ids and rows beyond MAXADJ set error bits and are
+// not stored.
 __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ elems, int64_t m, int nlb, int64_t nn,
                                                    int32_t* __restrict__ adj_len, int32_t* __restrict__ adj,
                                                    int64_t* __restrict__ info) {
     __shared__ int32_t keys[AG_HASH];
     __shared__ int32_t vals[AG_HASH];
+    __shared__ int32_t uniq[AG_TILE];  // table slots of the tile's distinct nodes
+    __shared__ int32_t nuniq;
     for (int h = threadIdx.x; h < AG_HASH; h += AG_BS) {
         keys[h] = -1;
         vals[h] = 0;
     }
+    if (threadIdx.x == 0) nuniq = 0;
     __syncthreads();
     const int64_t t0 = static_cast<int64_t>(blockIdx.x) * AG_TILE;
     int slot[AG_ITEMS];
@@ -196,7 +205,9 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
         if (t < m) {
             const int32_t node = elems[t];
             if (node >= 0 && node < nn) {
-                slot[q] = ag_insert(keys, node);
+                bool fresh;
+                slot[q] = ag_insert(keys, node, fresh);
+                if (fresh) uniq[atomicAdd(&nuniq, 1)] = slot[q];
                 atomicAdd(vals + slot[q], 1);
             } else {
                 bad = true;
@@ -205,13 +216,25 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
     }
     if (bad) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_INDEX));
     __syncthreads();
+    const int nu = nuniq;
+    int old[AG_ITEMS];
+#pragma unroll
+    for (int q = 0; q < AG_ITEMS; ++q) {  // independent atomics, all in flight together
+        const int u = threadIdx.x + q * AG_BS;
+        old[q] = 0;
+        if (u < nu) {
+            const int h = uniq[u];
+            old[q] = atomicAdd(adj_len + keys[h], vals[h]);
+        }
+    }
     bool over = false;
-    for (int h = threadIdx.x; h < AG_HASH; h += AG_BS) {
-        const int32_t node = keys[h];
-        if (node >= 0) {
-            const int old = atomicAdd(adj_len + node, vals[h]);
-            if (old + vals[h] > MAXADJ) over = true;
-            vals[h] = old;  // the tile's first position in the node's row
+#pragma unroll
+    for (int q = 0; q < AG_ITEMS; ++q) {
+        const int u = threadIdx.x + q * AG_BS;
+        if (u < nu) {
+            const int h = uniq[u];
+            if (old[q] + vals[h] > MAXADJ) over = true;
+            vals[h] = old[q];  // the tile's first position in the node's row
         }
     }
     if (over) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
@@ -220,7 +243,7 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
     for (int q = 0; q < AG_ITEMS; ++q) {
         if (slot[q] >= 0) {
             const int64_t t = t0 + q * AG_BS + threadIdx.x;
-            const int64_t e = t / nlb;
+            const int64_t e = nlb == 4 ? (t >> 2) : static_cast<int64_t>(static_cast<uint64_t>(t) / 3u);
             const int a = static_cast<int>(t - e * nlb);
             const int64_t node = keys[slot[q]];
             const int off = atomicAdd(vals + slot[q], 1);
@@ -255,33 +278,20 @@ __device__ __forceinline__ int rsub_hash(int32_t v) {
 static_assert(RSUB == 64, "rsub_hash yields 6 bits");
 
 // find or insert v in a row table; returns the slot (or -1 when the table is full) and
-// whether this call inserted it
+// whether this call inserted it.  One compare-and-swap per probe: it returns the slot's
+// node whether or not it stored v.
 __device__ __forceinline__ int rsub_insert(int32_t* tab, int32_t v, bool& fresh) {
     int h = rsub_hash(v);
-    fresh = false;
+#pragma unroll 1
     for (int probe = 0; probe < RSUB; ++probe) {
-        int32_t cur = tab[h];
-        if (cur == -1) {
-            cur = atomicCAS(tab + h, -1, v);
-            if (cur == -1) {
-                fresh = true;
-                return h;
-            }
+        const int32_t cur = atomicCAS(tab + h, -1, v);
+        if (cur == -1 || cur == v) {
+            fresh = cur == -1;
+            return h;
         }
-        if (cur == v) return h;
         h = (h + 1) & (RSUB - 1);
     }
-    return -1;
-}
-
-__device__ __forceinline__ int rsub_find(const int32_t* tab, int32_t v) {
-    int h = rsub_hash(v);
-    for (int probe = 0; probe < RSUB; ++probe) {
-        const int32_t cur = tab[h];
-        if (cur == v) return h;
-        if (cur == -1) return -1;
-        h = (h + 1) & (RSUB - 1);
-    }
+    fresh = false;
     return -1;
 }
 
@@ -314,18 +324,21 @@ __device__ __forceinline__ void elem_nodes(const int32_t* __restrict__ elems, in
 // sorted columns into a padded buffer colpad[row * MAXROW ...] (moved to col_idx once the
 // row lengths are scanned), (c) the packed slots pk of every adjacency entry (bits 0-1 local
 // index a, bits 2+8k .. 9+8k row position of the k-th other node of the element, in local
-// order).  The table slot of every inserted node is kept per entry in LDS, so pk needs no
-// second gather of the element and no second table lookup.
+// order).  A row with elements holds its own node (the diagonal), which is entered once
+// before the entries, so each entry inserts only the element's other nodes.  The table slot
+// of every inserted node is kept per entry in LDS, so pk needs no second gather of the
+// element and no second table lookup.
 template <int NLB>
 __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __restrict__ elems,
                                                 const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
                                                 int32_t* __restrict__ rowlen, int32_t* __restrict__ colpad,
                                                 uint32_t* __restrict__ pk, int64_t* __restrict__ info) {
+    constexpr int NO = NLB - 1;               // other nodes of an element
     __shared__ int32_t tab[RR * RSUB];       // node ids, -1 empty
     __shared__ uint8_t pos_of[RR * RSUB];     // list position of each table slot
     __shared__ int32_t seg[RR * MAXROW];      // each row's nodes, insertion order
     __shared__ uint8_t rank_of[RR * MAXROW];  // rank of each list item
-    __shared__ uint32_t eslot[RR * MAXADJ];   // per entry: a | table slot of node k << (2 + 6k)
+    __shared__ uint32_t eslot[RR * MAXADJ];   // per entry: a | table slot of other node k << (2 + 6k)
     __shared__ int32_t cnt[RR];
     __shared__ int32_t cpre[RR + 1];
     __shared__ int32_t alen[RR];
@@ -334,13 +347,22 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
     const int nr = static_cast<int>((r0 + RR < nn) ? RR : nn - r0);
     const int64_t e0 = r0 * MAXADJ;  // the block's adjacency rows start here (padded layout)
     for (int h = threadIdx.x; h < RR * RSUB; h += RT) tab[h] = -1;
-    if (threadIdx.x < RR) cnt[threadIdx.x] = 0;
     if (threadIdx.x == 0) maxl = 0;
     __syncthreads();
-    if (threadIdx.x < nr) {
-        const int L = min(adj_len[r0 + threadIdx.x], MAXADJ);  // longer rows raised an error already
-        alen[threadIdx.x] = L;
-        atomicMax(&maxl, L);
+    if (threadIdx.x < RR) {
+        const int r = threadIdx.x;
+        const int L = r < nr ? min(adj_len[r0 + r], MAXADJ) : 0;  // longer rows raised an error already
+        alen[r] = L;
+        cnt[r] = 0;
+        if (L > 0) {  // the diagonal
+            const int32_t self = static_cast<int32_t>(r0 + r);
+            const int h = rsub_hash(self);
+            tab[r * RSUB + h] = self;
+            pos_of[r * RSUB + h] = 0;
+            seg[r * MAXROW] = self;
+            cnt[r] = 1;
+            atomicMax(&maxl, L);
+        }
     }
     bool bad = false;
     __syncthreads();
@@ -354,7 +376,14 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
             const int idx = base + b * RT;
             rq[b] = -1;
             if (idx >= items) continue;
-            const int r = idx % nr, j = idx / nr;
+            int r, j;
+            if (nr == RR) {
+                r = idx % RR;
+                j = idx / RR;
+            } else {
+                r = idx % nr;
+                j = idx / nr;
+            }
             if (j >= alen[r]) continue;
             rq[b] = r;
             tq[b] = r * MAXADJ + j;
@@ -366,11 +395,15 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
             const int r = rq[b];
             if (r < 0) continue;
             int32_t* rt = tab + r * RSUB;
-            uint32_t word = static_cast<uint32_t>(aq[b] & 3);
+            const int a = aq[b] & 3;
+            int32_t o[NO];
 #pragma unroll
-            for (int k = 0; k < NLB; ++k) {
+            for (int k = 0; k < NO; ++k) o[k] = k < a ? nd[b][k] : nd[b][k + 1];
+            uint32_t word = static_cast<uint32_t>(a);
+#pragma unroll
+            for (int k = 0; k < NO; ++k) {
                 bool fresh;
-                const int h = rsub_insert(rt, nd[b][k], fresh);
+                const int h = rsub_insert(rt, o[k], fresh);
                 if (h < 0) {
                     bad = true;
                     continue;
@@ -379,7 +412,7 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
                 if (fresh) {
                     const int p = atomicAdd(cnt + r, 1);
                     if (p < MAXROW) {
-                        seg[r * MAXROW + p] = nd[b][k];
+                        seg[r * MAXROW + p] = o[k];
                         pos_of[r * RSUB + h] = static_cast<uint8_t>(p);
                     } else {
                         bad = true;
@@ -425,20 +458,23 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
     __syncthreads();
     // packed slots of every adjacency entry from its kept table slots (row-interleaved)
     for (int idx = threadIdx.x; idx < items; idx += RT) {
-        const int r = idx % nr, j = idx / nr;
+        int r, j;
+        if (nr == RR) {
+            r = idx % RR;
+            j = idx / RR;
+        } else {
+            r = idx % nr;
+            j = idx / nr;
+        }
         if (j >= alen[r]) continue;
         const int t = r * MAXADJ + j;
         const uint32_t w = eslot[t];
-        const int a = static_cast<int>(w & 3);
-        uint32_t word = static_cast<uint32_t>(a);
-        int k2 = 0;
+        uint32_t word = w & 3;
 #pragma unroll
-        for (int k = 0; k < NLB; ++k) {
-            if (k == a) continue;
+        for (int k = 0; k < NO; ++k) {
             const int h = static_cast<int>((w >> (2 + 6 * k)) & (RSUB - 1));
             const int p = min(static_cast<int>(pos_of[r * RSUB + h]), MAXROW - 1);  // < cnt unless the row failed
-            word |= static_cast<uint32_t>(rank_of[r * MAXROW + p]) << (2 + 8 * k2);
-            ++k2;
+            word |= static_cast<uint32_t>(rank_of[r * MAXROW + p]) << (2 + 8 * k);
         }
         pk[e0 + t] = word;
     }
@@ -571,7 +607,9 @@ struct alignas(16) Vec4 {  // 16-byte LDS reads; the layout keeps Vec4 arrays 16
 template <int DIM, typename C>
 __device__ __forceinline__ void origin_row(const P1Geom<DIM, C>& g, C ck, C cm, C (&k)[DIM + 1], C& mo) {
     const C adet = fabs(g.det);
-    const C kf = ck / (static_cast<C>(fact_dim<DIM>()) * adet);
+    C kf;
+    if constexpr (sizeof(C) == 4) kf = ck * __builtin_amdgcn_rcpf(static_cast<C>(fact_dim<DIM>()) * adet);  // 1 ulp
+    else kf = ck / (static_cast<C>(fact_dim<DIM>()) * adet);
 #pragma unroll
     for (int b = 0; b <= DIM; ++b) {
         C s = g.c[0][0] * g.c[b][0];
@@ -627,11 +665,13 @@ __device__ __forceinline__ void origin_row_f64(const double (&u)[DIM][DIM], doub
     mo = cm * adet * (1.0 / (fact_dim<DIM>() * (DIM + 1) * (DIM + 2)));
 }
 
-// FP32 routing test with thresholds already rounded to FP32
+// FP32 routing test with thresholds already rounded to FP32: route unless 0 < |det| < inf,
+// |det| >= tau_abs and absterms <= tau_cond |det| (a NaN fails every comparison, so NaN
+// det or absterms route; an infinite absterms with finite det fails the last test)
 __device__ __forceinline__ bool route32(float det, float absterms, float tau_abs, float tau_cond, int enable) {
     const float ad = fabsf(det);
-    return enable && (!__builtin_isfinite(det) || !__builtin_isfinite(absterms) || ad == 0.0f || ad < tau_abs ||
-                      absterms > tau_cond * ad);
+    const bool keep = ad > 0.0f && ad < __builtin_huge_valf() && ad >= tau_abs && absterms <= tau_cond * ad;
+    return enable && !keep;
 }
 
 // item index -> (row, position) for row-interleaved dealing; full blocks divide by a

@@ -6,10 +6,13 @@
 // the rotated edges (2-D), divided by det J = e_1 . c_1.  The barycentric gradients
 // (the routine's dphi = tjac^{-1} dshape with the P1 reference derivatives) are therefore
 // grad phi_j = c_j / det for j >= 1 and grad phi_0 = -(c_1 + ... + c_d) / det, and the P1
-// stiffness entry |T| grad phi_a . grad phi_b equals (c_a . c_b) / (d! |det|).  Every
-// cofactor component is a 2x2 determinant evaluated with Kahan's FMA scheme (c_1 as an
-// exact double-word value), and det is a compensated dot product with c_1, so the FP32
-// path loses no accuracy to cancellation.
+// stiffness entry |T| grad phi_a . grad phi_b equals (c_a . c_b) / (d! |det|).
+// Precision: the determinant is compensated -- c_1 by Kahan's FMA scheme (each component
+// within 2 ulp), then det = e_1 . c_1 as a Dot2 sum (FMA-split products, compensated sum) --
+// so its arithmetic error is at most (1 + 2 kappa) u |det| with kappa the det-condition
+// sum_j |e_1j c_1j| / |det| that the routing predicate tests.  The other cofactors take one
+// FMA per component: their error stays within a few u |e_k||e_l|, the size of what the
+// rounding of the edge vectors themselves (from FP64 coordinates) already puts there.
 #pragma once
 
 #include "smallmat.hpp"
@@ -27,30 +30,25 @@ struct P1Geom {
 template <int DIM, typename C>
 __device__ __forceinline__ void p1_geom_edges(const C (&u)[DIM][DIM], P1Geom<DIM, C>& g) {
     if constexpr (DIM == 3) {
-        // c_1 = e_2 x e_3 as double-word components: det = e_1 . c_1 within about one ulp
-        DW<C> c1[3];
-        c1[0] = dw_det2(u[1][1], u[1][2], u[2][1], u[2][2]);
-        c1[1] = dw_det2(u[1][2], u[1][0], u[2][2], u[2][0]);
-        c1[2] = dw_det2(u[1][0], u[1][1], u[2][0], u[2][1]);
-#pragma unroll
-        for (int i = 0; i < 3; ++i) g.c[1][i] = c1[i].hi + c1[i].lo;
+        // c_1 = e_2 x e_3 (Kahan), det = e_1 . c_1 compensated
+        g.c[1][0] = det2(u[1][1], u[1][2], u[2][1], u[2][2]);
+        g.c[1][1] = det2(u[1][2], u[1][0], u[2][2], u[2][0]);
+        g.c[1][2] = det2(u[1][0], u[1][1], u[2][0], u[2][1]);
+        g.det = dot_comp<C, 3>(u[0], g.c[1], g.absterms);
 #pragma unroll
         for (int j = 2; j <= 3; ++j) {
-            const C* x = u[j % 3];  // c_2 = e_3 x e_1, c_3 = e_1 x e_2 (Kahan, within 2 ulp)
+            const C* x = u[j % 3];  // c_2 = e_3 x e_1, c_3 = e_1 x e_2, one FMA per component
             const C* y = u[(j + 1) % 3];
-            g.c[j][0] = det2(x[1], x[2], y[1], y[2]);
-            g.c[j][1] = det2(x[2], x[0], y[2], y[0]);
-            g.c[j][2] = det2(x[0], x[1], y[0], y[1]);
+            g.c[j][0] = fmaT(x[1], y[2], -(x[2] * y[1]));
+            g.c[j][1] = fmaT(x[2], y[0], -(x[0] * y[2]));
+            g.c[j][2] = fmaT(x[0], y[1], -(x[1] * y[0]));
         }
-        const DW<C> d = dot_dw<C, 3>(u[0], c1, g.absterms);
-        g.det = d.hi + d.lo;
     } else {
         g.c[1][0] = u[1][1];
         g.c[1][1] = -u[1][0];
         g.c[2][0] = -u[0][1];
         g.c[2][1] = u[0][0];
-        const DW<C> d = dw_det2(u[0][0], u[0][1], u[1][0], u[1][1]);
-        g.det = d.hi + d.lo;
+        g.det = det2(u[0][0], u[0][1], u[1][0], u[1][1]);
         g.absterms = fabs(u[0][0] * u[1][1]) + fabs(u[0][1] * u[1][0]);
     }
 #pragma unroll
