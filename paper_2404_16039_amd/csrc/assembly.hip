@@ -306,20 +306,6 @@ __device__ __forceinline__ int upper_pos(const int32_t* v, int n, int32_t x) {
     return lo;
 }
 
-template <int NLB>
-__device__ __forceinline__ void elem_nodes(const int32_t* __restrict__ elems, int64_t e, int (&nd)[4]) {
-    if constexpr (NLB == 4) {
-        load_nodes<3>(elems, e, nd);
-    } else {
-        int n3[3];
-        load_nodes<2>(elems, e, n3);
-        nd[0] = n3[0];
-        nd[1] = n3[1];
-        nd[2] = n3[2];
-        nd[3] = -1;
-    }
-}
-
 // One pass per block of RR rows: insert, rank, and write (a) each row's length, (b) its
 // sorted columns into a padded buffer colpad[row * MAXROW ...] (moved to col_idx once the
 // row lengths are scanned), (c) the packed slots pk of every adjacency entry (bits 0-1 local
@@ -366,29 +352,40 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
     }
     bool bad = false;
     __syncthreads();
-    const int items = nr * maxl;
+    // entry j of row r is item r + RR j; rows past the end of the matrix are empty
+    static_assert((RR & (RR - 1)) == 0, "RR is a power of two");
+    const int items = RR * maxl;
     for (int base = threadIdx.x; base < items; base += RT * RBATCH) {
         int nd[RBATCH][4];
         int rq[RBATCH], tq[RBATCH];  // row, and block-local entry index r * MAXADJ + j
         int32_t aq[RBATCH];
+        // loads without branches (an empty item reads entry 0 and element 0, and is dropped),
+        // so all of them are in flight together
 #pragma unroll
         for (int b = 0; b < RBATCH; ++b) {
             const int idx = base + b * RT;
-            rq[b] = -1;
-            if (idx >= items) continue;
-            int r, j;
-            if (nr == RR) {
-                r = idx % RR;
-                j = idx / RR;
-            } else {
-                r = idx % nr;
-                j = idx / nr;
-            }
-            if (j >= alen[r]) continue;
-            rq[b] = r;
-            tq[b] = r * MAXADJ + j;
+            const int r = idx % RR, j = idx / RR;
+            const bool ok = idx < items && j < alen[r];
+            rq[b] = ok ? r : -1;
+            tq[b] = ok ? r * MAXADJ + j : 0;
             aq[b] = adj[e0 + tq[b]];
-            elem_nodes<NLB>(elems, aq[b] >> 2, nd[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < RBATCH; ++b) aq[b] = rq[b] >= 0 ? aq[b] : 0;
+        if (NLB == 4 && (reinterpret_cast<uintptr_t>(elems) & 15) == 0) {
+#pragma unroll
+            for (int b = 0; b < RBATCH; ++b) {
+                const int4 v = *reinterpret_cast<const int4*>(elems + static_cast<int64_t>(aq[b] >> 2) * 4);
+                nd[b][0] = v.x;
+                nd[b][1] = v.y;
+                nd[b][2] = v.z;
+                nd[b][3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int b = 0; b < RBATCH; ++b)
+#pragma unroll
+                for (int k = 0; k < NLB; ++k) nd[b][k] = elems[static_cast<int64_t>(aq[b] >> 2) * NLB + k];
         }
 #pragma unroll
         for (int b = 0; b < RBATCH; ++b) {
@@ -458,14 +455,7 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
     __syncthreads();
     // packed slots of every adjacency entry from its kept table slots (row-interleaved)
     for (int idx = threadIdx.x; idx < items; idx += RT) {
-        int r, j;
-        if (nr == RR) {
-            r = idx % RR;
-            j = idx / RR;
-        } else {
-            r = idx % nr;
-            j = idx / nr;
-        }
+        const int r = idx % RR, j = idx / RR;
         if (j >= alen[r]) continue;
         const int t = r * MAXADJ + j;
         const uint32_t w = eslot[t];
@@ -674,19 +664,6 @@ __device__ __forceinline__ bool route32(float det, float absterms, float tau_abs
     return enable && !keep;
 }
 
-// item index -> (row, position) for row-interleaved dealing; full blocks divide by a
-// compile-time constant
-template <int NR>
-__device__ __forceinline__ void split_item(int idx, int nr, int& r, int& j) {
-    if (nr == NR) {
-        r = idx % NR;
-        j = idx / NR;
-    } else {
-        r = idx % nr;
-        j = idx / nr;
-    }
-}
-
 template <int DIM, typename T>
 constexpr size_t numeric_lds_bytes(int nr, int wmax) {
     return static_cast<size_t>(wmax) * (2 * sizeof(typename Exact<T>::acc) + sizeof(Vec4<T>) + 8) +
@@ -702,7 +679,7 @@ constexpr size_t numeric_lds_bytes(int nr, int wmax) {
 //            largest contribution fixes that slot's grid, and the rounded contributions
 //            are added into LDS accumulators with atomics (exact: order does not matter);
 //   phase 2  every slot converts its sum and stores it once (coalesced).
-// Entries and slots are dealt row-interleaved (item r + nr j), so the lanes of one
+// Entries and slots are dealt row-interleaved (item r + NR j), so the lanes of one
 // instruction work on different rows and their LDS atomics hit different addresses.
 // One block of NR rows starting at row r0 (the body of the numeric kernels).  QN > 0:
 // cK and cM hold QN values per element at the integration points of the QuadRule<DIM, QN>
@@ -728,36 +705,43 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
     int32_t* dslot = alen + (NR + 1);                            // [NR + 1]
     int32_t* maxlen = dslot + (NR + 1);                          // [1]
 
+    // Items are dealt by NR (row r = item % NR, a power of two); rows past the end of the
+    // matrix in the last block are empty (no elements, no slots).
+    static_assert((NR & (NR - 1)) == 0, "NR is a power of two");
     const int nr = static_cast<int>((r0 + NR < nn) ? NR : nn - r0);
-    if (threadIdx.x <= nr) rp[threadIdx.x] = row_ptr[r0 + threadIdx.x];
-    if (threadIdx.x < nr) alen[threadIdx.x] = adj_len[r0 + threadIdx.x];
+    {
+        const int t = static_cast<int>(threadIdx.x);
+        const int32_t rpv = row_ptr[r0 + (t <= nr ? t : nr)];  // both loads unconditional
+        const int32_t alv = adj_len[r0 + (t < nr ? t : nr - 1)];
+        if (t <= NR) rp[t] = rpv;
+        if (t < NR) alen[t] = t < nr ? alv : 0;
+    }
     if (threadIdx.x == 0) *maxlen = 0;
     __syncthreads();
     if (threadIdx.x < nr) atomicMax(maxlen, rp[threadIdx.x + 1] - rp[threadIdx.x]);
     const int32_t w0 = rp[0];
     const int W = rp[nr] - w0;
-    // packed entries of this thread's items, loaded before phase 0 so their latency overlaps it
+    // packed entries of this thread's items, loaded before phase 0 so their latency overlaps
+    // it; the loads take no branch (an empty item reads the block's first entry and drops
+    // it), so all of them are in flight together
     uint32_t pw[NITEMS];
     int rr[NITEMS];
     int64_t tt[NITEMS];
 #pragma unroll
     for (int q = 0; q < NITEMS; ++q) {
         // the host guarantees that NITEMS * NBT / NR covers the longest adjacency list
-        int r, j;
-        split_item<NR>(threadIdx.x + q * NBT, nr, r, j);
-        rr[q] = -1;
-        if (j < alen[r]) {
-            rr[q] = r;
-            tt[q] = (r0 + r) * MAXADJ + j;  // padded adjacency rows
-            pw[q] = pk[tt[q]];
-        }
+        const int idx = threadIdx.x + q * NBT;
+        const int r = idx % NR, j = idx / NR;
+        const bool ok = j < alen[r];
+        rr[q] = ok ? r : -1;
+        tt[q] = ok ? (r0 + r) * MAXADJ + j : r0 * MAXADJ;  // padded adjacency rows
+        pw[q] = pk[tt[q]];
     }
     __syncthreads();
 
     // phase 0: edge vector per slot (row-interleaved, no search), accumulators cleared
-    for (int idx = threadIdx.x; idx < nr * *maxlen; idx += NBT) {
-        int r, k;
-        split_item<NR>(idx, nr, r, k);
+    for (int idx = threadIdx.x; idx < NR * *maxlen; idx += NBT) {
+        const int r = idx % NR, k = idx / NR;
         if (k >= rp[r + 1] - rp[r]) continue;
         const int w = rp[r] - w0 + k;
         const int64_t i = r0 + r;
