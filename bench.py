@@ -36,7 +36,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "numeric_assembly_cube128_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assembly_cube128_traffic.json")
 KERNEL_SOURCES = ["assembly.hip", "p1elem.hpp", "smallmat.hpp", "common.hpp"]
 BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_plan_64groups_traffic.json")
 BATCH_SOURCES = ["batch.hip", "smallmat.hpp", "common.hpp"]
@@ -56,14 +56,17 @@ def kernel_hash(files=KERNEL_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_of(path, files, **match):
-    """HBM bytes per launch from a committed counter file, if it matches these sources."""
+def traffic_of(path, files, kernel=None, **match):
+    """HBM bytes per launch from a committed counter file, if it matches these sources
+    (files holding several kernels list them under "kernels")."""
     if not os.path.exists(path):
         return None
     with open(path) as f:
         tr = json.load(f)
     if tr.get("kernel_hash") != kernel_hash(files) or any(tr.get(k) != v for k, v in match.items()):
         return None
+    if kernel is not None:
+        return tr.get("kernels", {}).get(kernel)
     return tr.get("hbm_bytes_per_launch")
 
 
@@ -451,12 +454,14 @@ def main():
     torch.cuda.synchronize()
     ctr.zero_()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    csr.set_timing(True)  # HIP events between the symbolic kernels, on the same stream
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
         step(evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    stage_ms, stage_calls = csr.stage_times()
     sym = np.array([e[0].elapsed_time(e[1]) for e in evs])
     num = np.array([e[1].elapsed_time(e[2]) for e in evs])
     bnd = np.array([e[2].elapsed_time(e[3]) for e in evs])
@@ -473,12 +478,28 @@ def main():
     # (12 B of indices and 16 B of FP32 outputs per face; their coordinates are counted above)
     alg_step = alg_num + 4 * (nn + 1) + 4 * nnz + nf * (12 + 16)
     num_ms = float(num.mean())
-    achieved = alg_num / (num_ms * 1e-3) / 1e9
     phases = {"symbolic_ms": round(float(sym.mean()), 4), "numeric_ms": round(num_ms, 4),
               "boundary_ms": round(float(bnd.mean()), 4)}
-    dominant = max(phases, key=phases.get)
+    # per-kernel launch durations (HIP events on the launch stream) and algorithmic bytes
+    # per launch; the symbolic stages are timed inside pf_csr_symbolic (pf_csr_stage_times)
+    kname = "k_numeric<3,float%s>" % (",QN=4" if quad else "")
+    kernels = {
+        "k_scatter": (stage_ms["adjacency"] / stage_calls, 16 * ne + 16 * ne + 4 * nn),
+        "k_pattern<4>": (stage_ms["pattern"] / stage_calls, 16 * ne + 16 * ne + 16 * ne + 4 * nnz + 4 * nn),
+        "scan + block stats": (stage_ms["scan"] / stage_calls, 16 * nn),
+        "k_compact": (stage_ms["compact"] / stage_calls, 8 * nnz + 4 * nn),
+        kname: (num_ms, alg_num),
+    }
 
-    traffic = None if quad else traffic_of(TRAFFIC_FILE, KERNEL_SOURCES, n=n)
+    def roofline(name):
+        ms, alg = kernels[name]
+        gbs = alg / (ms * 1e-3) / 1e9
+        tr = None if quad else traffic_of(TRAFFIC_FILE, KERNEL_SOURCES, kernel=name.split(" ")[0], n=n)
+        return {"kernel": name, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS, "traffic": tr, "algorithmic_bytes_per_launch": alg,
+                "launch_us": round(ms * 1e3, 1)}
+
+    dominant = max(kernels, key=lambda k: kernels[k][0])
     # the paper's level-7 cube (2,146,689 nodes, 12,582,912 tets), K + M with c = exp(x1+x2+x3)
     # at quadrature points: 66.6 s + 20.4 s in MATLAB (hardware not stated)
     paper_tets_per_s = 12582912 / (66.6 + 20.4)
@@ -508,11 +529,9 @@ def main():
         "numeric_tets_per_s": ne / (num_ms * 1e-3),
         "routed_per_step": routed,
         "bad_index": bad,
-        "roofline": {"kernel": "k_numeric<3,float%s> (%s)" % (",QN=4" if quad else "",
-                                                               "pf_assemble_quad" if quad else "pf_assemble"),
-                     "bound": "hbm", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": alg_num, "dominant_phase": dominant},
+        "kernels_us": {k: round(v[0] * 1e3, 1) for k, v in kernels.items()},
+        "roofline": roofline(dominant),
+        "roofline_numeric": roofline(kname),
         "paper_context": {"what": "MATLAB page-function library, 3-D P1 K and M at 2,146,689 nodes (level 7), "
                                   "hardware not stated, c = exp(x1+x2+x3) with quadrature",
                           "K_s": 66.6, "M_s": 20.4},

@@ -203,12 +203,24 @@ pf_status pf_csr_symbolic(pf_csr* csr, int dim, int64_t nn, int64_t ne, const in
 pf_status pf_csr_info(const pf_csr* csr, int64_t* nn, int64_t* nnz, const int32_t** row_ptr,
                       const int32_t** col_idx);
 
+/* Per-stage device time of pf_csr_symbolic, a profiling aid.  pf_csr_set_timing(csr, 1)
+ * clears the sums and makes every later pf_csr_symbolic call on the handle record HIP
+ * events on its stream between its stages (0 stops recording).  pf_csr_stage_times waits
+ * for the events of the last call and writes ms[PF_CSR_STAGES], the summed milliseconds
+ * of each stage since timing was switched on, and *calls, the number of calls summed
+ * (nullable).  Stages: adjacency (counting scatter), row pattern, scan (row_ptr and block
+ * statistics), compaction of the columns. */
+#define PF_CSR_STAGES 4
+pf_status pf_csr_set_timing(pf_csr* csr, int on);
+pf_status pf_csr_stage_times(pf_csr* csr, double* ms, int64_t* calls);
+
 /* Numeric assembly of the global K (valsK[nnz]) and M (valsM[nnz], nullable) of the mesh
  * whose structure `csr` holds (the handle keeps the connectivity it was built from;
  * `elems` is accepted for symmetry with the element calls and may be NULL).  coords may
  * change between calls (same topology).  Each value is the sum of its element
- * contributions in ascending element order (deterministic: the same inputs give the same
- * bits).  Every element row is computed with that row's node as the origin of the edge
+ * contributions, each first rounded onto a grid fixed by the value's largest contribution
+ * (2^-24 of its power of two for FP32, 2^-56 for FP64), so the sum is exact and does not
+ * depend on the order of the additions: the same inputs give the same bits.  Every element row is computed with that row's node as the origin of the edge
  * vectors.  prec as for the element calls; cK, cM per-element coefficients, nullable
  * (= 1).  d_counters[0] counts FP64-routed elements once each. */
 pf_status pf_assemble(const pf_csr* csr, pf_dtype prec, const double* coords, const int32_t* elems,

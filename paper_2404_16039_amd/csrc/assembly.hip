@@ -44,6 +44,12 @@ struct pf_csr {
     int64_t cap_adj_len = 0, cap_row_ptr = 0, cap_cnt = 0, cap_adj = 0, cap_pk = 0, cap_nnz = 0, cap_bsum = 0,
             cap_info = 0, cap_colpad = 0;
     bool built = false;
+    // per-stage timing of pf_csr_symbolic (events e0..e5: start, after the adjacency, after
+    // the pattern, after the scan; around the compaction)
+    bool timing = false, pending = false;
+    hipEvent_t ev[6] = {};
+    double stage_ms[PF_CSR_STAGES] = {};
+    int64_t stage_calls = 0;
 };
 
 namespace pf {
@@ -312,8 +318,9 @@ __device__ __forceinline__ int upper_pos(const int32_t* v, int n, int32_t x) {
 // index a, bits 2+8k .. 9+8k row position of the k-th other node of the element, in local
 // order).  A row with elements holds its own node (the diagonal), which is entered once
 // before the entries, so each entry inserts only the element's other nodes.  The table slot
-// of every inserted node is kept per entry in LDS, so pk needs no second gather of the
-// element and no second table lookup.
+// of every inserted node is kept per entry in LDS and ranking labels each used table slot
+// with its column position, so pk needs no second gather of the element and no second
+// table lookup.
 template <int NLB>
 __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __restrict__ elems,
                                                 const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
@@ -321,10 +328,10 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
                                                 uint32_t* __restrict__ pk, int64_t* __restrict__ info) {
     constexpr int NO = NLB - 1;               // other nodes of an element
     __shared__ int32_t tab[RR * RSUB];       // node ids, -1 empty
-    __shared__ uint8_t pos_of[RR * RSUB];     // list position of each table slot
     __shared__ int32_t seg[RR * MAXROW];      // each row's nodes, insertion order
-    __shared__ uint8_t rank_of[RR * MAXROW];  // rank of each list item
-    __shared__ uint32_t eslot[RR * MAXADJ];   // per entry: a | table slot of other node k << (2 + 6k)
+    __shared__ uint8_t seg_h[RR * MAXROW];    // table slot of each list item
+    __shared__ uint8_t slot_rank[RR * RSUB];  // rank (column position) of each used table slot
+    __shared__ uint32_t eslot[RR * MAXADJ];   // per item: a | table slot of other node k << (2 + 6k)
     __shared__ int32_t cnt[RR];
     __shared__ int32_t cpre[RR + 1];
     __shared__ int32_t alen[RR];
@@ -344,7 +351,7 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
             const int32_t self = static_cast<int32_t>(r0 + r);
             const int h = rsub_hash(self);
             tab[r * RSUB + h] = self;
-            pos_of[r * RSUB + h] = 0;
+            seg_h[r * MAXROW] = static_cast<uint8_t>(h);
             seg[r * MAXROW] = self;
             cnt[r] = 1;
             atomicMax(&maxl, L);
@@ -410,13 +417,13 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
                     const int p = atomicAdd(cnt + r, 1);
                     if (p < MAXROW) {
                         seg[r * MAXROW + p] = o[k];
-                        pos_of[r * RSUB + h] = static_cast<uint8_t>(p);
+                        seg_h[r * MAXROW + p] = static_cast<uint8_t>(h);
                     } else {
                         bad = true;
                     }
                 }
             }
-            eslot[tq[b]] = word;
+            eslot[base + b * RT] = word;  // by item: consecutive lanes, consecutive words
         }
     }
     if (bad) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
@@ -449,7 +456,7 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
             rank += (a0 < v) + (a1 < v) + (a2 < v) + (a3 < v);
         }
         for (; j < n; ++j) rank += sr[j] < v;
-        rank_of[r * MAXROW + p] = static_cast<uint8_t>(rank);
+        slot_rank[r * RSUB + seg_h[r * MAXROW + p]] = static_cast<uint8_t>(rank);
         colpad[(r0 + r) * MAXROW + rank] = v;
     }
     __syncthreads();
@@ -458,13 +465,12 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
         const int r = idx % RR, j = idx / RR;
         if (j >= alen[r]) continue;
         const int t = r * MAXADJ + j;
-        const uint32_t w = eslot[t];
+        const uint32_t w = eslot[idx];
         uint32_t word = w & 3;
 #pragma unroll
         for (int k = 0; k < NO; ++k) {
             const int h = static_cast<int>((w >> (2 + 6 * k)) & (RSUB - 1));
-            const int p = min(static_cast<int>(pos_of[r * RSUB + h]), MAXROW - 1);  // < cnt unless the row failed
-            word |= static_cast<uint32_t>(rank_of[r * MAXROW + p]) << (2 + 8 * k);
+            word |= static_cast<uint32_t>(slot_rank[r * RSUB + h]) << (2 + 8 * k);
         }
         pk[e0 + t] = word;
     }
@@ -502,40 +508,35 @@ constexpr int NBT = 256;     // threads per block of the numeric kernel
 constexpr int NITEMS = PF_NUMERIC_ITEMS;    // adjacency entries per thread (held in registers)
 static_assert(MAXADJ <= NITEMS * NBT / NR_SMALL, "the small numeric blocks must cover any admissible row");
 
-// largest CSR window of one numeric block of `nr` rows into info[slot], and the largest
-// number of elements around a node into info[7].  Grid-strided, then reduced in the wave and
-// in the block: one global atomic per block.
-__global__ __launch_bounds__(256) void k_block_stats(int64_t nn, int nr, const int32_t* __restrict__ row_ptr,
-                                                     const int32_t* __restrict__ adj_len, int64_t nblk,
-                                                     int64_t* __restrict__ info, int slot) {
-    __shared__ int red[2][4];
-    int w = 0, l = 0;
-    for (int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; b < nblk;
-         b += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const int64_t r0 = b * nr;
-        const int64_t r1 = (r0 + nr < nn) ? r0 + nr : nn;
-        w = max(w, row_ptr[r1] - row_ptr[r0]);
-        for (int64_t i = r0; i < r1; ++i) l = max(l, adj_len[i]);
+// largest CSR window of one numeric block of NR_BIG, NR_MID and NR_SMALL rows into info[3],
+// info[4] and info[5], and the largest number of elements around a node into info[7]: one
+// thread per row (coalesced), the row that starts a block of a class measures its window.
+// Grid-strided, then reduced in the wave and in the block: one global atomic per value and
+// block.
+__global__ __launch_bounds__(256) void k_block_stats(int64_t nn, const int32_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ adj_len, int64_t* __restrict__ info) {
+    __shared__ int red[4][4];
+    int m[4] = {0, 0, 0, 0};
+    constexpr int NRS[3] = {NR_BIG, NR_MID, NR_SMALL};
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < nn;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        m[3] = max(m[3], adj_len[i]);
+        const int32_t p = row_ptr[i];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if (i % NRS[c] == 0) m[c] = max(m[c], row_ptr[(i + NRS[c] < nn) ? i + NRS[c] : nn] - p);
     }
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        w = max(w, __shfl_xor(w, d, 64));
-        l = max(l, __shfl_xor(l, d, 64));
-    }
-    if ((threadIdx.x & 63) == 0) {
-        red[0][threadIdx.x >> 6] = w;
-        red[1][threadIdx.x >> 6] = l;
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) m[c] = max(m[c], __shfl_xor(m[c], d, 64));
+        if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = m[c];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int q = 1; q < 4; ++q) {
-            w = max(w, red[0][q]);
-            l = max(l, red[1][q]);
-        }
-        w = max(w, red[0][0]);
-        l = max(l, red[1][0]);
-        atomicMax(reinterpret_cast<unsigned long long*>(info + slot), static_cast<unsigned long long>(w));
-        atomicMax(reinterpret_cast<unsigned long long*>(info + 7), static_cast<unsigned long long>(l));
+    if (threadIdx.x < 4) {
+        const int c = threadIdx.x;
+        const int v = max(max(red[c][0], red[c][1]), max(red[c][2], red[c][3]));
+        atomicMax(reinterpret_cast<unsigned long long*>(info + (c < 3 ? 3 + c : 7)), static_cast<unsigned long long>(v));
     }
 }
 
@@ -1088,6 +1089,8 @@ pf_status pf_csr_create(pf_csr** out) {
 
 void pf_csr_destroy(pf_csr* c) {
     if (!c) return;
+    for (hipEvent_t& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
     (void)hipFree(c->adj_len);
     (void)hipFree(c->adj);
     (void)hipFree(c->pk);
@@ -1098,6 +1101,49 @@ void pf_csr_destroy(pf_csr* c) {
     (void)hipFree(c->bsum);
     (void)hipFree(c->info);
     delete c;
+}
+
+namespace {
+// add the stage times of the last timed call to the sums
+pf_status collect_stage_times(pf_csr* c) {
+    if (!c->pending) return PF_OK;
+    c->pending = false;
+    PF_HIP_TRY(hipEventSynchronize(c->ev[5]));
+    const int from[PF_CSR_STAGES] = {0, 1, 2, 4}, to[PF_CSR_STAGES] = {1, 2, 3, 5};
+    for (int k = 0; k < PF_CSR_STAGES; ++k) {
+        float ms = 0.0f;
+        PF_HIP_TRY(hipEventElapsedTime(&ms, c->ev[from[k]], c->ev[to[k]]));
+        c->stage_ms[k] += ms;
+    }
+    ++c->stage_calls;
+    return PF_OK;
+}
+
+pf_status mark(pf_csr* c, int k, hipStream_t s) {
+    if (c->timing) PF_HIP_TRY(hipEventRecord(c->ev[k], s));
+    return PF_OK;
+}
+}  // namespace
+
+pf_status pf_csr_set_timing(pf_csr* c, int on) {
+    if (!c) return fail(PF_EINVAL, "pf_csr_set_timing: null handle");
+    if (on)
+        for (hipEvent_t& e : c->ev)
+            if (!e) PF_HIP_TRY(hipEventCreate(&e));
+    c->timing = on != 0;
+    c->pending = false;
+    for (double& v : c->stage_ms) v = 0.0;
+    c->stage_calls = 0;
+    return PF_OK;
+}
+
+pf_status pf_csr_stage_times(pf_csr* c, double* ms, int64_t* calls) {
+    if (!c || !ms) return fail(PF_EINVAL, "pf_csr_stage_times: null argument");
+    pf_status st;
+    if ((st = collect_stage_times(c))) return st;
+    for (int k = 0; k < PF_CSR_STAGES; ++k) ms[k] = c->stage_ms[k];
+    if (calls) *calls = c->stage_calls;
+    return PF_OK;
 }
 
 pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int32_t* elems, void* stream) {
@@ -1112,6 +1158,7 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     c->built = false;
     const int64_t m = ne * nlb;
     pf_status st;
+    if ((st = collect_stage_times(c))) return st;  // the previous call's events are reused below
     if ((st = grow(c->adj_len, c->cap_adj_len, nn + 1))) return st;
     if ((st = grow(c->row_ptr, c->cap_row_ptr, nn + 1))) return st;
     if ((st = grow(c->cnt, c->cap_cnt, nn + 1))) return st;
@@ -1120,6 +1167,7 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     const int64_t nb = std::max<int64_t>(ceil_div(nn + 1, SCAN_TILE), 1);
     if ((st = grow(c->bsum, c->cap_bsum, nb))) return st;
     if ((st = grow(c->info, c->cap_info, 8))) return st;
+    if ((st = mark(c, 0, s))) return st;
     hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, c->info, int64_t(8), int64_t(0));
     if (nn > 0) hipLaunchKernelGGL(k_fill_i32, dim3(flat_grid(nn)), dim3(SBS), 0, s, c->adj_len, nn, 0);
     const unsigned gtile = static_cast<unsigned>(std::max<int64_t>(ceil_div(m, AG_TILE), 1));
@@ -1127,6 +1175,7 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
         hipLaunchKernelGGL(k_scatter, dim3(gtile), dim3(AG_BS), 0, s, elems, m, nlb, nn, c->adj_len, c->adj, c->info);
     const unsigned grows = static_cast<unsigned>(ceil_div(nn, RR));
     if ((st = grow(c->colpad, c->cap_colpad, nn * MAXROW))) return st;
+    if ((st = mark(c, 1, s))) return st;
     if (nn > 0) {
         if (nlb == 4)
             hipLaunchKernelGGL((k_pattern<4>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
@@ -1135,14 +1184,13 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
             hipLaunchKernelGGL((k_pattern<3>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
                                c->colpad, c->pk, c->info);
     }
+    if ((st = mark(c, 2, s))) return st;
     if ((st = scan(c->cnt, nn, c->row_ptr, c->bsum, c->info + 2, s))) return st;
-    for (int which = 0; which < 3 && nn > 0; ++which) {
-        const int nr = which == 0 ? NR_BIG : (which == 1 ? NR_MID : NR_SMALL);
-        const int64_t nblk = ceil_div(nn, nr);
-        const unsigned g = static_cast<unsigned>(std::min<int64_t>(ceil_div(nblk, 256), 128));
-        hipLaunchKernelGGL(k_block_stats, dim3(g), dim3(256), 0, s, nn, nr, c->row_ptr, c->adj_len, nblk, c->info,
-                           3 + which);
+    if (nn > 0) {
+        const unsigned g = static_cast<unsigned>(std::min<int64_t>(ceil_div(nn, 256), 2048));
+        hipLaunchKernelGGL(k_block_stats, dim3(g), dim3(256), 0, s, nn, c->row_ptr, c->adj_len, c->info);
     }
+    if ((st = mark(c, 3, s))) return st;
     if ((st = launch_check("pf_csr_symbolic"))) return st;
     int64_t info[8];
     PF_HIP_TRY(hipMemcpyAsync(info, c->info, sizeof(info), hipMemcpyDeviceToHost, s));
@@ -1154,10 +1202,13 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     if (info[2] >= INT32_MAX) return fail(PF_ELIMIT, "pf_csr_symbolic: nnz must be < 2^31");
     const int64_t nnz = info[2];
     if ((st = grow(c->col_idx, c->cap_nnz, nnz))) return st;
+    if ((st = mark(c, 4, s))) return st;
     if (nn > 0)
         hipLaunchKernelGGL(k_compact, dim3(static_cast<unsigned>(ceil_div(nn, CR))), dim3(RT), 0, s, nn, c->row_ptr,
                            c->colpad, c->col_idx);
+    if ((st = mark(c, 5, s))) return st;
     if ((st = launch_check("pf_csr_symbolic cols"))) return st;
+    c->pending = c->timing;
     c->dim = dim;
     c->nlb = nlb;
     c->nn = nn;

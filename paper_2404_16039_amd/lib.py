@@ -136,6 +136,8 @@ _sig = {
     "pf_csr_create": ([C.POINTER(P)], C.c_int),
     "pf_csr_symbolic": ([P, I32, I64, I64, P, P], C.c_int),
     "pf_csr_info": ([P, C.POINTER(I64), C.POINTER(I64), C.POINTER(P), C.POINTER(P)], C.c_int),
+    "pf_csr_set_timing": ([P, C.c_int], C.c_int),
+    "pf_csr_stage_times": ([P, C.POINTER(C.c_double), C.POINTER(I64)], C.c_int),
     "pf_assemble": ([P, I32, P, P, P, P, P, P, FP, P, P], C.c_int),
     "pf_csr_destroy": ([P], None),
     "pf_plan_create": ([I32, I32, FP, C.POINTER(P)], C.c_int),
@@ -315,6 +317,19 @@ class Csr:
         nn, nnz, rp, ci = I64(), I64(), P(), P()
         _chk(_lib.pf_csr_info(self._h, C.byref(nn), C.byref(nnz), C.byref(rp), C.byref(ci)), "pf_csr_info")
         return nn.value, nnz.value, rp.value, ci.value
+
+    CSR_STAGES = ("adjacency", "pattern", "scan", "compact")
+
+    def set_timing(self, on=True):
+        """Record per-stage events in every later symbolic call (and clear the sums)."""
+        _chk(_lib.pf_csr_set_timing(self._h, 1 if on else 0), "pf_csr_set_timing")
+
+    def stage_times(self):
+        """({stage: summed ms}, calls) since timing was switched on."""
+        ms = (C.c_double * len(self.CSR_STAGES))()
+        calls = I64()
+        _chk(_lib.pf_csr_stage_times(self._h, ms, C.byref(calls)), "pf_csr_stage_times")
+        return dict(zip(self.CSR_STAGES, list(ms))), calls.value
 
     def structure(self, stream=None):
         """Copies of (row_ptr, col_idx) as int32 device tensors."""

@@ -76,6 +76,16 @@ def test_csr_handle_states_without_gpu():
     assert L.pf_csr_symbolic(h, 5, 1, 1, C.c_void_p(16), None) == 3
     assert L.pf_csr_symbolic(h, 3, -1, 1, C.c_void_p(16), None) == 1
     assert L.pf_csr_symbolic(h, 3, 1 << 31, 1, C.c_void_p(16), None) == 7
+    # stage timing: null arguments, and timing off needs no device
+    ms = (C.c_double * 4)(1, 1, 1, 1)
+    calls = C.c_int64(-1)
+    assert L.pf_csr_set_timing(None, 1) == 1
+    assert L.pf_csr_stage_times(None, ms, None) == 1
+    assert L.pf_csr_stage_times(h, None, None) == 1
+    assert L.pf_csr_set_timing(h, 0) == 0
+    assert L.pf_csr_stage_times(h, ms, C.byref(calls)) == 0 and calls.value == 0 and list(ms) == [0.0] * 4
+    stages = re.search(r"#define PF_CSR_STAGES (\d+)", open(os.path.join(ROOT, "include", "pagefem.h")).read())
+    assert int(stages.group(1)) == len(lib.Csr.CSR_STAGES) == 4
     L.pf_csr_destroy(h)
     L.pf_csr_destroy(None)
 

@@ -95,6 +95,29 @@ def test_deterministic_and_handle_reuse(lib):
     assert torch.equal(a["tK"], c["tK"])
 
 
+def test_stage_timing(lib):
+    """Per-stage timing of the symbolic phase: positive sums over the timed calls, and the
+    structure built with timing on is the same."""
+    say("stage timing")
+    coords, elems, _ = cube(6)
+    te = dev(elems)
+    ref = lib.Csr().symbolic(3, coords.shape[0], te)
+    csr = lib.Csr()
+    csr.set_timing(True)
+    for _ in range(3):
+        csr.symbolic(3, coords.shape[0], te)
+    ms, calls = csr.stage_times()
+    assert calls == 3 and set(ms) == set(lib.Csr.CSR_STAGES)
+    assert all(v > 0 for v in ms.values()), ms
+    for a, b in zip(ref.structure(), csr.structure()):
+        assert torch.equal(a, b)
+    csr.set_timing(False)
+    csr.symbolic(3, coords.shape[0], te)
+    assert csr.stage_times() == ({k: 0.0 for k in lib.Csr.CSR_STAGES}, 0)
+    ref.close()
+    csr.close()
+
+
 def test_node_permutation_invariance(lib):
     """Random node numbering gives the same matrices, up to the permutation, bit for bit."""
     say("permutation")
