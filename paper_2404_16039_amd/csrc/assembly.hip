@@ -509,22 +509,32 @@ constexpr int NITEMS = PF_NUMERIC_ITEMS;    // adjacency entries per thread (hel
 static_assert(MAXADJ <= NITEMS * NBT / NR_SMALL, "the small numeric blocks must cover any admissible row");
 
 // largest CSR window of one numeric block of NR_BIG, NR_MID and NR_SMALL rows into info[3],
-// info[4] and info[5], and the largest number of elements around a node into info[7]: one
-// thread per row (coalesced), the row that starts a block of a class measures its window.
-// Grid-strided, then reduced in the wave and in the block: one global atomic per value and
-// block.
+// info[4] and info[5], and the largest number of elements around a node into info[7].  One
+// thread per block of NR_SMALL rows (two row_ptr reads and its rows' lengths); the windows
+// of NR_MID and NR_BIG rows are sums over 4 and 8 neighbouring lanes.  Reduced in the wave
+// and in the block: one global atomic per value and block.
+static_assert(NR_SMALL == 4 && NR_MID == 4 * NR_SMALL && NR_BIG == 8 * NR_SMALL, "lane sums assume 4/16/32 rows");
 __global__ __launch_bounds__(256) void k_block_stats(int64_t nn, const int32_t* __restrict__ row_ptr,
                                                      const int32_t* __restrict__ adj_len, int64_t* __restrict__ info) {
     __shared__ int red[4][4];
     int m[4] = {0, 0, 0, 0};
-    constexpr int NRS[3] = {NR_BIG, NR_MID, NR_SMALL};
-    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < nn;
-         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        m[3] = max(m[3], adj_len[i]);
-        const int32_t p = row_ptr[i];
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            if (i % NRS[c] == 0) m[c] = max(m[c], row_ptr[(i + NRS[c] < nn) ? i + NRS[c] : nn] - p);
+    const int64_t nsb = (nn + NR_SMALL - 1) / NR_SMALL;  // blocks of 4 rows
+    // grid-strided by a multiple of 8 lanes, so 8 neighbouring lanes always hold one big block
+    for (int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; b - threadIdx.x < nsb;
+         b += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t i0 = b * NR_SMALL;
+        int w = 0;
+        if (i0 < nn) {
+            const int64_t i1 = i0 + NR_SMALL < nn ? i0 + NR_SMALL : nn;
+            w = row_ptr[i1] - row_ptr[i0];
+            for (int64_t i = i0; i < i1; ++i) m[3] = max(m[3], adj_len[i]);
+        }
+        int w16 = w + __shfl_xor(w, 1, 64);
+        w16 += __shfl_xor(w16, 2, 64);
+        const int w32 = w16 + __shfl_xor(w16, 4, 64);
+        m[2] = max(m[2], w);
+        m[1] = max(m[1], w16);
+        m[0] = max(m[0], w32);
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -1187,7 +1197,8 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     if ((st = mark(c, 2, s))) return st;
     if ((st = scan(c->cnt, nn, c->row_ptr, c->bsum, c->info + 2, s))) return st;
     if (nn > 0) {
-        const unsigned g = static_cast<unsigned>(std::min<int64_t>(ceil_div(nn, 256), 2048));
+        // few blocks: every block ends with global atomics on the same four words
+        const unsigned g = static_cast<unsigned>(std::min<int64_t>(ceil_div(ceil_div(nn, NR_SMALL), 256), 256));
         hipLaunchKernelGGL(k_block_stats, dim3(g), dim3(256), 0, s, nn, c->row_ptr, c->adj_len, c->info);
     }
     if ((st = mark(c, 3, s))) return st;
