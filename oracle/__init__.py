@@ -54,6 +54,7 @@ def _load():
         lib.or_quad_points.argtypes = [INT, INT, I64, P, I64, P, P]
         lib.or_p1_elements_q.argtypes = [INT, INT, I64, P, I64, P, P, P, P, P, P, P]
         lib.or_p1_elements_q.restype = I64
+        lib.or_rhs_p1.argtypes = [INT, INT, I64, P, I64, P, P, P, P, P]
         lib.or_route_predicate.argtypes = [INT, P, I64, D, D, P, P]
         lib.or_assemble.argtypes = [INT, I64, I64, P, P, P, P, P, P, P, P, P, P, I64]
         lib.or_assemble.restype = I64
@@ -201,6 +202,51 @@ def p1_elements_q(coords, elems, order, cKq=None, cMq=None):
                                   _p(Ka), _p(Ma))
     _check(rc, "p1_elements_q")
     return {"Ke": Ke, "Me": Me, "Kabs": Ka, "Mabs": Ma, "nsingular": int(rc)}
+
+
+def rhs_p1(coords, elems, order, fq):
+    """Load vector of the right-hand side listing: local vectors b2D (ne, nlb), the
+    accumarray sum b (nn), and its error scale babs (nn).  fq: (ne, nq) values of f at the
+    integration points of the rule of `order`."""
+    coords = _f64(coords)
+    elems = _i32(elems)
+    nn, dim = coords.shape
+    ne, nlb = elems.shape
+    nq = quad_count(dim, order)
+    f = _f64(np.asarray(fq).reshape(ne, nq))
+    b2D = np.empty((ne, nlb))
+    b = np.empty(nn)
+    babs = np.empty(nn)
+    _check(_load().or_rhs_p1(dim, int(order), nn, _p(coords), ne, _p(elems), _p(f), _p(b2D), _p(b), _p(babs)),
+           "rhs_p1")
+    return {"b2D": b2D, "b": b, "babs": babs}
+
+
+def local_energies(coords, elems, order, u, cKq=None, cMq=None, b2D=None):
+    """Local energy contributions of the section 3.6 energy functional, as the page
+    bilinear form (section 2.2) of the element matrices with the nodal values u_k of each
+    element: J1k = 1/2 u_k^T K_k u_k, J2k = 1/2 u_k^T M_k u_k, J3k = -b_k^T u_k (K_k, M_k with
+    coefficients at the integration points of the rule of `order`; b_k the local load
+    vector b2D, or None for J3k = 0).  Returns J1k, J2k, J3k and their error scales."""
+    coords = _f64(coords)
+    elems = _i32(elems)
+    ne, nlb = elems.shape
+    u = _f64(u)
+    el = p1_elements_q(coords, elems, order, cKq, cMq)
+    ue = u[elems]                        # (ne, nlb): u restricted to each element
+    ua = np.abs(ue)
+    J1 = 0.5 * page_bilinear(ue, el["Ke"], ue, nlb)
+    J2 = 0.5 * page_bilinear(ue, el["Me"], ue, nlb)
+    J1abs = 0.5 * page_bilinear(ua, el["Kabs"], ua, nlb)
+    J2abs = 0.5 * page_bilinear(ua, el["Mabs"], ua, nlb)
+    if b2D is None:
+        J3 = np.zeros(ne)
+        J3abs = np.zeros(ne)
+    else:
+        b2 = _f64(np.asarray(b2D).reshape(ne, nlb))
+        J3 = -(b2 * ue).sum(axis=1)
+        J3abs = (np.abs(b2) * ua).sum(axis=1)
+    return {"J1k": J1, "J2k": J2, "J3k": J3, "J1abs": J1abs, "J2abs": J2abs, "J3abs": J3abs}
 
 
 def create_coords3d(coords, elems):

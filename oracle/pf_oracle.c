@@ -647,3 +647,48 @@ int or_boundary(int dim, int64_t nn, const double* coords, int64_t nf, const int
     }
     return 0;
 }
+
+/* Load vector of the right-hand side listing (section 3.6): on every element the local
+ * vector b2D[e*nlb + j] = sum_q w_q |det J_e| f_eq phi_j(x_q) over the integration points
+ * of the rule of `order` (phi_j(x_q) = lam[q][j]), then the accumarray step b[i] = sum of
+ * b2D[e*nlb + j] over all (e, j) with elems[e*nlb + j] == i, taken in element order.
+ * babs[i] = the same sum of absolute values (the error scale of b[i]).  f: ne x nq values
+ * (element-major).  b2D, b, babs may be NULL.  Returns 0, or -1 / -2 on a bad rule or node. */
+int or_rhs_p1(int dim, int order, int64_t nn, const double* coords, int64_t ne, const int32_t* elems,
+              const double* fq, double* b2D, double* b, double* babs) {
+    if ((dim != 2 && dim != 3) || (order != 1 && order != 2)) return -1;
+    int nlb = dim + 1;
+    double ds[3 * 4];
+    p1_dshape(dim, ds);
+    double lam[4][4], wq[4];
+    int nq = quad_rule(dim, order, lam, wq);
+    if (b)
+        for (int64_t i = 0; i < nn; i++) b[i] = 0.0;
+    if (babs)
+        for (int64_t i = 0; i < nn; i++) babs[i] = 0.0;
+    for (int64_t e = 0; e < ne; e++) {
+        double c3[3 * 4];
+        for (int j = 0; j < nlb; j++) {
+            int64_t node = elems[e * nlb + j];
+            if (node < 0 || node >= nn) return -2;
+            for (int i = 0; i < dim; i++) AT(c3, dim, i, j) = coords[node * dim + i];
+        }
+        double tjac[9];
+        for (int r = 0; r < dim; r++)
+            for (int c = 0; c < dim; c++) {
+                double acc = 0.0;
+                for (int j = 0; j < nlb; j++) acc += AT(ds, dim, r, j) * AT(c3, dim, c, j);
+                AT(tjac, dim, r, c) = acc;
+            }
+        double adet = fabs(leibniz(tjac, dim, NULL));
+        for (int j = 0; j < nlb; j++) {
+            double v = 0.0;
+            for (int q = 0; q < nq; q++) v += wq[q] * adet * fq[e * nq + q] * lam[q][j];
+            if (b2D) b2D[e * nlb + j] = v;
+            int64_t node = elems[e * nlb + j];
+            if (b) b[node] += v;
+            if (babs) babs[node] += fabs(v);
+        }
+    }
+    return 0;
+}

@@ -101,6 +101,40 @@ def square_mesh(n: int, jitter: float = 0.2, seed_sub: int | None = None, stream
 _PERMS = list(itertools.permutations((0, 1, 2)))  # lexicographic
 
 
+def lshape_mesh(n: int):
+    """L-shaped domain of the section 3.6 boundary value problem: the unit square without
+    the quarter-open square (0.25, 1) x (0.25, 1), i.e. the union of (0, 0.25)^2,
+    (0, 0.25) x (0.25, 1) and (0.25, 1) x (0, 0.25).  A (4n x 4n) grid of squares of side
+    h = 1 / (4n) keeps the 7 n^2 squares inside the domain, each cut into two triangles as
+    in square_mesh; nodes are renumbered consecutively (x fastest).  No jitter.
+
+    Returns (coords[nn,2] f64, elems[ne,3] i32)."""
+    n = int(n)
+    if n < 1:
+        raise ValueError("n must be >= 1")
+    m = 4 * n
+    h = 1.0 / m
+    i, j = np.meshgrid(np.arange(m), np.arange(m), indexing="xy")
+    i = i.ravel()
+    j = j.ravel()
+    keep = (i < n) | (j < n)  # squares left of x = 0.25 or below y = 0.25
+    i = i[keep]
+    j = j[keep]
+    g = m + 1
+    v00 = i + g * j
+    v10 = v00 + 1
+    v01 = v00 + g
+    v11 = v01 + 1
+    elems = np.empty((2 * i.size, 3), dtype=np.int64)
+    elems[0::2] = np.stack([v00, v10, v11], axis=1)
+    elems[1::2] = np.stack([v00, v11, v01], axis=1)
+    used = np.unique(elems)
+    new_id = np.full(g * g, -1, dtype=np.int64)
+    new_id[used] = np.arange(used.size)
+    coords = np.stack([(used % g) * h, (used // g) * h], axis=1).astype(np.float64)
+    return coords, new_id[elems].astype(np.int32)
+
+
 def _perm_sign(p):
     s = 1
     p = list(p)

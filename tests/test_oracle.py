@@ -590,3 +590,155 @@ def test_energy_errors_match_printed_3d_table():
         errs.append((k, m))
     for (k0, m0), (k1, m1) in zip(errs, errs[1:]):
         assert 3.6 < k0 / k1 < 4.4 and 3.6 < m0 / m1 < 4.4
+
+
+# ----------------------------------------------------------------------------- load vector
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("order", [1, 2])
+def test_rhs_constant_f_closed_form(dim, order):
+    """f = 1: every local entry is |T| / (d + 1) (the integral of a barycentric function),
+    and the global vector sums to the domain measure."""
+    n = 3
+    coords, elems, _ = gen.square_mesh(n, jitter=0.0) if dim == 2 else gen.cube_mesh(n, jitter=0.0)
+    h = 1.0 / n
+    nq = oracle.quad_count(dim, order)
+    r = oracle.rhs_p1(coords, elems, order, np.ones((elems.shape[0], nq)))
+    vol = h * h / 2 if dim == 2 else h ** 3 / 6
+    assert np.allclose(r["b2D"], vol / (dim + 1), rtol=1e-14, atol=0)
+    assert abs(r["b"].sum() - 1.0) < 1e-13
+    assert np.allclose(r["b"], r["babs"])
+    # corner node of the square / cube: 1 (2-D: two triangles at node 0? one) element(s)
+    cnt = np.bincount(elems.ravel(), minlength=coords.shape[0])
+    assert np.allclose(r["b"], cnt * vol / (dim + 1), rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_rhs_linear_f_closed_forms(dim):
+    """f linear: the degree-2 rule integrates f phi_j exactly, so b2D_j = |T| (f_j + sum_k f_k)
+    / ((d+1)(d+2)) from the nodal values alone; the centroid rule gives |T| f(centroid) / (d+1)."""
+    coords, elems, _ = gen.square_mesh(4, jitter=0.2) if dim == 2 else gen.cube_mesh(3, jitter=0.15)
+    g = np.array([0.7, -1.3, 2.1][:dim])
+    fnode = coords @ g + 0.4
+    fe = fnode[elems]                      # (ne, nlb)
+    vol = oracle.p1_elements(coords, elems)["vol"]
+    xq2 = oracle.quad_points(coords, elems, 2)
+    r2 = oracle.rhs_p1(coords, elems, 2, xq2 @ g + 0.4)
+    want2 = vol[:, None] * (fe + fe.sum(axis=1, keepdims=True)) / ((dim + 1) * (dim + 2))
+    assert np.allclose(r2["b2D"], want2, rtol=1e-12, atol=1e-18)
+    xq1 = oracle.quad_points(coords, elems, 1)
+    r1 = oracle.rhs_p1(coords, elems, 1, xq1 @ g + 0.4)
+    want1 = vol[:, None] * fe.mean(axis=1, keepdims=True) / (dim + 1) * np.ones((1, dim + 1))
+    assert np.allclose(r1["b2D"], want1, rtol=1e-12, atol=1e-18)
+    # accumarray: b[i] gathers exactly the entries of node i (brute force)
+    b = np.zeros(coords.shape[0])
+    for e in range(elems.shape[0]):
+        for j in range(dim + 1):
+            b[elems[e, j]] += r2["b2D"][e, j]
+    assert np.array_equal(b, r2["b"])
+
+
+# ----------------------------------------------------------------------------- local energies
+@pytest.mark.parametrize("dim", [2, 3])
+def test_local_energies_linear_u_closed_forms(dim):
+    """u = g.x + c with unit coefficients: J1k = |g|^2 |T| / 2, J2k = |T| (sum u_j^2 +
+    (sum u_j)^2) / (2 (d+1)(d+2)) (degree-2 rule, exact), J3k = -|T| mean(u_e) for f = 1; the
+    sums over elements equal the global forms 1/2 u^T K u, 1/2 u^T M u, -b^T u of the
+    assembled K, M and b."""
+    coords, elems, _ = gen.square_mesh(5, jitter=0.2) if dim == 2 else gen.cube_mesh(3, jitter=0.15)
+    g = np.array([1.1, -0.6, 0.9][:dim])
+    u = coords @ g - 0.3
+    ne, nq = elems.shape[0], oracle.quad_count(dim, 2)
+    rhs = oracle.rhs_p1(coords, elems, 2, np.ones((ne, nq)))
+    J = oracle.local_energies(coords, elems, 2, u, b2D=rhs["b2D"])
+    vol = oracle.p1_elements(coords, elems)["vol"]
+    ue = u[elems]
+    assert np.allclose(J["J1k"], 0.5 * (g @ g) * vol, rtol=1e-12, atol=0)
+    want2 = vol * ((ue ** 2).sum(axis=1) + ue.sum(axis=1) ** 2) / (2 * (dim + 1) * (dim + 2))
+    assert np.allclose(J["J2k"], want2, rtol=1e-12, atol=0)
+    assert np.allclose(J["J3k"], -vol * ue.mean(axis=1), rtol=1e-12, atol=1e-18)
+    assert abs(J["J1k"].sum() - 0.5 * (g @ g)) < 1e-12  # |Omega| = 1
+    el = oracle.p1_elements_q(coords, elems, 2)
+    A = oracle.assemble(elems, coords.shape[0], el["Ke"], el["Me"], el["Kabs"])
+    rp, ci, vK, vM = A["row_ptr"], A["col_idx"], A["valK"], A["valM"]
+    Ku = np.zeros_like(u)
+    Mu = np.zeros_like(u)
+    for i in range(coords.shape[0]):
+        s = slice(rp[i], rp[i + 1])
+        Ku[i] = vK[s] @ u[ci[s]]
+        Mu[i] = vM[s] @ u[ci[s]]
+    assert abs(J["J1k"].sum() - 0.5 * u @ Ku) < 1e-12
+    assert abs(J["J2k"].sum() - 0.5 * u @ Mu) < 1e-13
+    assert abs(J["J3k"].sum() + rhs["b"] @ u) < 1e-13
+
+
+def _bvp_fields():
+    pi = math.pi
+    u = lambda x: np.cos(4 * pi * x[..., 0]) * np.cos(4 * pi * x[..., 1])
+    cK = lambda x: 1 + x[..., 0] ** 2 - x[..., 1]
+    cM = lambda x: 1 - x[..., 0] + x[..., 1] ** 2
+
+    def f(x):
+        x1, x2 = x[..., 0], x[..., 1]
+        return (8 * pi * x1 * np.sin(4 * pi * x1) * np.cos(4 * pi * x2) + np.cos(4 * pi * x1) *
+                (-4 * pi * np.sin(4 * pi * x2) + (1 - x1 + 32 * pi ** 2 * (1 + x1 ** 2 - x2) + x2 ** 2) *
+                 np.cos(4 * pi * x2)))
+    return u, cK, cM, f
+
+
+def _printed_bvp():
+    pr = {}
+    with open(os.path.join(GOLD, "energies_bvp.txt")) as fh:
+        for line in fh:
+            p = line.split()
+            if p and p[0] == "printed":
+                pr[p[1]] = float(p[2])
+    return pr
+
+
+def test_bvp_energy_closed_forms():
+    """The printed closed forms of J1, J3 and (with the 12288 reading) J2 give the printed
+    decimals, and a direct adaptive integration over the three rectangles of the L-shaped
+    domain gives the same values (a check of the reading of u, c_K, c_M and f)."""
+    from scipy import integrate
+    gold = _golden("energies_bvp.txt")
+    pi = math.pi
+    den = float(gold["closed_denominator"][1])
+    closed = {"J1": 289 * pi ** 2 / 192, "J2": (578 * pi ** 2 + 21) / (den * pi ** 2),
+              "J3": -(578 * (32 * pi ** 4 + pi ** 2) + 21) / (6144 * pi ** 2)}
+    pr = _printed_bvp()
+    for k in ("J1", "J2", "J3"):
+        assert abs(closed[k] - pr[k]) <= 0.6 * 10.0 ** (math.floor(math.log10(abs(pr[k]))) - 9), k
+    assert abs(sum(closed.values()) - pr["J"]) < 1e-8
+    u, cK, cM, f = _bvp_fields()
+
+    def grad2(x):
+        gx = -4 * pi * np.sin(4 * pi * x[..., 0]) * np.cos(4 * pi * x[..., 1])
+        gy = -4 * pi * np.cos(4 * pi * x[..., 0]) * np.sin(4 * pi * x[..., 1])
+        return gx ** 2 + gy ** 2
+    rects = [(0, 0.25, 0, 0.25), (0, 0.25, 0.25, 1), (0.25, 1, 0, 0.25)]
+
+    def integ(fn):
+        return sum(integrate.dblquad(lambda y, x: fn(np.array([x, y])), a, b, c, d, epsabs=1e-12,
+                                     epsrel=1e-12)[0] for a, b, c, d in rects)
+    assert abs(integ(lambda x: 0.5 * cK(x) * grad2(x)) - closed["J1"]) < 1e-9
+    assert abs(integ(lambda x: 0.5 * cM(x) * u(x) ** 2) - closed["J2"]) < 1e-11
+    assert abs(integ(lambda x: -f(x) * u(x)) - closed["J3"]) < 1e-9
+
+
+def test_bvp_energies_converge_to_closed_forms():
+    """The oracle's discrete energy parts of the nodal interpolant of u (coefficients and f
+    at the integration points of the degree-2 rule) on refined L-shaped meshes converge to
+    the printed values at second order."""
+    u, cK, cM, f = _bvp_fields()
+    pr = _printed_bvp()
+    errs = []
+    for n in (4, 8, 16):
+        coords, elems = gen.lshape_mesh(n)
+        xq = oracle.quad_points(coords, elems, 2)
+        rhs = oracle.rhs_p1(coords, elems, 2, f(xq))
+        J = oracle.local_energies(coords, elems, 2, u(coords), cKq=cK(xq), cMq=cM(xq), b2D=rhs["b2D"])
+        errs.append([abs(J[k + "k"].sum() - pr[k]) for k in ("J1", "J2", "J3")])
+    errs = np.array(errs)
+    ratios = errs[:-1] / errs[1:]
+    assert np.all(ratios > 3.3) and np.all(ratios < 4.8), (errs, ratios)
+    assert np.all(errs[-1] < [0.06, 1e-3, 0.25]), errs[-1]  # h = 1/64: within 0.5%, 1.5%, 0.7%
