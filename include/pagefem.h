@@ -236,6 +236,37 @@ pf_status pf_assemble_quad(const pf_csr* csr, pf_dtype prec, const double* coord
                            const void* cKq, const void* cMq, void* valsK, void* valsM,
                            const pf_fallback* fb, int64_t* d_counters, void* stream);
 
+/* Load vector (section 3.6, right-hand side listing) of the mesh whose structure `csr`
+ * holds; elems: the connectivity it was built from (ne x (dim+1), device).  For every
+ * element, b2D[e*nlb + j] = |det J_e| sum_q w_q f_eq phi_j(x_q) over the points of the rule
+ * of `order` (1 or 2, those of pf_quad_points; fq: ne x nq values of type prec,
+ * element-major), in prec (FP32 recomputes the determinant of routed elements in FP64, as
+ * pf_elem_stiffness_mass).  b (nn values, nullable): the accumarray step, b[i] = the sum of
+ * the entries of the elements around node i, read through the handle's node-element
+ * adjacency and summed exactly on a grid fixed by the largest entry (2^-24 of its power of
+ * two for FP32, 2^-56 for FP64): deterministic.  b2D (device, ne x nlb, type prec) is
+ * required.  d_counters: [0] routed elements, [2] elements with a bad node index (their
+ * entries are NaN). */
+pf_status pf_rhs(const pf_csr* csr, pf_dtype prec, const double* coords, const int32_t* elems,
+                 int order, const void* fq, void* b2D, void* b, const pf_fallback* fb,
+                 int64_t* d_counters, void* stream);
+
+/* Local energy parts (section 3.6, element-wise contributions to the energy functional) of
+ * the P1 function with nodal values u (nn values of type prec, device) on the mesh of `csr`
+ * (elems as for pf_rhs): J[e] = 1/2 u_e^T K_e u_e, J[ne + e] = 1/2 u_e^T M_e u_e,
+ * J[2 ne + e] = -b2D_e^T u_e, with K_e and M_e the element matrices of pf_assemble_quad for
+ * the rule of `order` (cKq, cMq: ne x nq, nullable = 1) and b2D the local load vectors of
+ * pf_rhs (nullable: the third part is 0).  The bilinear forms are evaluated as
+ * 1/2 mean(cK) |det| |grad u_e|^2 / d! and 1/2 |det| sum_q w_q cM_q u_e(x_q)^2, which equal
+ * them.  J (device, 3 ne values of type prec) is nullable; totals (device, 3 doubles,
+ * nullable) receives the sums of the stored J values over all elements, in FP64 and in a
+ * fixed order (deterministic).  Uses a workspace of the handle (grown when needed, so the
+ * handle is not const).  d_counters as pf_rhs. */
+pf_status pf_energies(pf_csr* csr, pf_dtype prec, const double* coords, const int32_t* elems,
+                      int order, const void* cKq, const void* cMq, const void* u, const void* b2D,
+                      void* J, double* totals, const pf_fallback* fb, int64_t* d_counters,
+                      void* stream);
+
 void pf_csr_destroy(pf_csr* csr);
 
 /* ----------------------------------------------------------------------------------

@@ -20,6 +20,7 @@
 #include "p1elem.hpp"
 #include "internal.hpp"
 #include "quadrature.hpp"
+#include "exact.hpp"
 
 #include <algorithm>
 #include <new>
@@ -41,8 +42,9 @@ struct pf_csr {
     int32_t* colpad = nullptr;  // sorted columns of every row, MAXROW per row (symbolic scratch)
     int64_t* bsum = nullptr;  // scan workspace
     int64_t* info = nullptr;  // [0] error bits, [1] adjacency total, [2] nnz, [3..6] block stats
+    void* work = nullptr;     // workspace of the energy reductions (pf_energies)
     int64_t cap_adj_len = 0, cap_row_ptr = 0, cap_cnt = 0, cap_adj = 0, cap_pk = 0, cap_nnz = 0, cap_bsum = 0,
-            cap_info = 0, cap_colpad = 0;
+            cap_info = 0, cap_colpad = 0, cap_work = 0;
     bool built = false;
     // per-stage timing of pf_csr_symbolic (events e0..e5: start, after the adjacency, after
     // the pattern, after the scan; around the compaction)
@@ -507,6 +509,7 @@ constexpr int NR_SMALL = 4;  // ... when neither fits
 constexpr int NBT = 256;     // threads per block of the numeric kernel
 constexpr int NITEMS = PF_NUMERIC_ITEMS;    // adjacency entries per thread (held in registers)
 static_assert(MAXADJ <= NITEMS * NBT / NR_SMALL, "the small numeric blocks must cover any admissible row");
+static_assert(MAXADJ == CSR_MAXADJ, "one padded adjacency layout");
 
 // largest CSR window of one numeric block of NR_BIG, NR_MID and NR_SMALL rows into info[3],
 // info[4] and info[5], and the largest number of elements around a node into info[7].  One
@@ -549,54 +552,6 @@ __global__ __launch_bounds__(256) void k_block_stats(int64_t nn, const int32_t* 
         atomicMax(reinterpret_cast<unsigned long long*>(info + (c < 3 ? 3 + c : 7)), static_cast<unsigned long long>(v));
     }
 }
-
-// Exact, order-independent accumulation: every contribution is first rounded onto a fixed
-// grid, a power of two chosen per CSR slot from the slot's largest contribution (found
-// with an LDS atomic max before any add), after which sums of up to MAXADJ grid values are
-// exact in the accumulator type, so atomic adds in any order give the same bits.  The
-// rounding error of a slot is at most 2^-bits times its largest contribution.
-//   FP32 contributions: grid 2^-24 of the slot maximum's power of two (|x| < 2^E quantizes
-//   to an integer below 2^24, exact in FP32 and int32), two's-complement int32 accumulator:
-//   at most 64 contributions per slot keep every partial sum below 2^30.  The grid error of
-//   a slot is at most (contributions) x 2^-25 of its largest contribution's power of two,
-//   i.e. below 2^-18 relative even with 64 contributions, under the FP32 tolerance; the
-//   final conversion rounds once.
-//   FP64 contributions: grid 2^-56, two's-complement int64 accumulator.
-// Only the maximum's exponent matters, so maxima are kept as the high 32 bits of |x|.
-template <typename T>
-struct Exact;
-template <>
-struct Exact<float> {
-    using acc = unsigned int;  // two's-complement int32 sums (LDS integer atomics wrap)
-    static constexpr int bits = 24;
-    __device__ static uint32_t mag(float x) { return __float_as_uint(fabsf(x)); }
-    // shift = bits - E with max < 2^E (clamped so that 2^shift stays a normal float)
-    __device__ static int shift(uint32_t m) {
-        int sh = bits - (static_cast<int>((m >> 23) & 255) - 126);
-        return sh > 126 ? 126 : sh;
-    }
-    __device__ static acc quant(float x, int sh) {
-        return static_cast<acc>(static_cast<int>(rintf(ldexpf(x, sh))));
-    }
-    __device__ static float back(acc a, int sh) { return ldexpf(static_cast<float>(static_cast<int>(a)), -sh); }
-};
-template <>
-struct Exact<double> {
-    using acc = unsigned long long;
-    static constexpr int bits = 56;
-    __device__ static uint32_t mag(double x) {
-        return static_cast<uint32_t>(static_cast<unsigned long long>(__double_as_longlong(fabs(x))) >> 32);
-    }
-    __device__ static int shift(uint32_t m) {
-        int E = static_cast<int>((m >> 20) & 2047) - 1022;
-        E = E < -960 ? -960 : (E > 960 ? 960 : E);  // keep 2^shift and 2^-shift normal
-        return bits - E;
-    }
-    __device__ static acc quant(double x, int sh) {
-        return static_cast<unsigned long long>(static_cast<long long>(rint(ldexp(x, sh))));
-    }
-    __device__ static double back(acc a, int sh) { return ldexp(static_cast<double>(static_cast<long long>(a)), -sh); }
-};
 
 template <typename T>
 struct alignas(16) Vec4 {  // 16-byte LDS reads; the layout keeps Vec4 arrays 16-byte aligned
@@ -1077,12 +1032,23 @@ pf_status numeric_launch_many(int dim, pf_dtype prec, int nr, const NumericJob* 
 
 size_t csr_bytes(const pf_csr* c) {
     return static_cast<size_t>(c->cap_adj_len + c->cap_row_ptr + c->cap_cnt + c->cap_adj + c->cap_nnz + c->cap_colpad) * 4 +
-           static_cast<size_t>(c->cap_pk) * 4 + static_cast<size_t>(c->cap_bsum + c->cap_info) * 8;
+           static_cast<size_t>(c->cap_pk) * 4 + static_cast<size_t>(c->cap_bsum + c->cap_info + c->cap_work) * 8;
 }
 
 int64_t csr_nnz(const pf_csr* c) { return c->built ? c->nnz : -1; }
 int64_t csr_nn(const pf_csr* c) { return c->nn; }
 int csr_dim(const pf_csr* c) { return c->dim; }
+int64_t csr_ne(const pf_csr* c) { return c->ne; }
+bool csr_built(const pf_csr* c) { return c->built; }
+const int32_t* csr_adj(const pf_csr* c) { return c->adj; }
+const int32_t* csr_adj_len(const pf_csr* c) { return c->adj_len; }
+
+pf_status csr_workspace(pf_csr* c, int64_t words, double** out) {
+    pf_status st;
+    if ((st = grow(reinterpret_cast<double*&>(c->work), c->cap_work, words))) return st;
+    *out = static_cast<double*>(c->work);
+    return PF_OK;
+}
 
 }  // namespace pf
 
@@ -1110,6 +1076,7 @@ void pf_csr_destroy(pf_csr* c) {
     (void)hipFree(c->colpad);
     (void)hipFree(c->bsum);
     (void)hipFree(c->info);
+    (void)hipFree(c->work);
     delete c;
 }
 

@@ -1,0 +1,352 @@
+// energy.hip -- load vector and local energy parts of P1 elements (section 3.6: the
+// right-hand side listing with its accumarray step, and the element-wise contributions to
+// the gradient, reactive and linear parts of the energy functional).
+//
+// Load vector: one element per lane computes its local vector b2D (|det J| times the rule
+// applied to f phi_j); one node per lane then sums the entries of the elements around it,
+// read through the structure handle's node -> element adjacency, exactly on a grid fixed by
+// the node's largest entry (two passes over its entries), so b does not depend on the order
+// of the adjacency lists.
+//
+// Energies: one element per lane; with c_j = det * grad phi_j (the cofactor columns of the
+// Jacobian),
+//   1/2 u^T K_e u = 1/2 cK_mean |sum_j u_j c_j|^2 / (d! |det|),  sum_j u_j c_j = sum_{j>=1} (u_j - u_0) c_j,
+//   1/2 u^T M_e u = 1/2 |det| sum_q w_q cM_q u(x_q)^2,          u(x_q) = sum_j lam_qj u_j,
+// which are the page bilinear forms with the element matrices of the quadrature assembly
+// (stiffness with the weighted mean of the coefficient, mass integrated point by point), in
+// a form that takes differences of u before any product.  The three sums over elements are
+// FP64 block sums in a fixed order, then one block adds the block sums in order.
+#include "p1elem.hpp"
+#include "quadrature.hpp"
+#include "exact.hpp"
+#include "internal.hpp"
+
+#include <string>
+
+namespace pf {
+
+constexpr int RBS = 256;  // threads per block
+constexpr int ETOT_BLOCKS = 2048;  // blocks of the energy kernel at most (one partial each)
+
+template <int DIM>
+__device__ __forceinline__ bool gather_edges(const double* __restrict__ coords, int64_t nn,
+                                             const int32_t* __restrict__ elems, int64_t e, int (&nd)[DIM + 1],
+                                             double (&ev)[DIM][DIM]) {
+    load_nodes<DIM>(elems, e, nd);
+    return p1_edges<DIM>(coords, nn, nd, ev);
+}
+
+// |det J| of one element in precision C, with the FP32 routing to FP64 of pf_fallback
+template <int DIM, typename T>
+__device__ __forceinline__ double abs_det(const double (&ev)[DIM][DIM], const Fallback& fb, bool& routed) {
+    routed = false;
+    if constexpr (sizeof(T) == 4) {
+        P1Geom<DIM, float> g;
+        p1_geom<DIM, float>(ev, g);
+        routed = should_route(g.det, g.absterms, fb);
+        if (!routed) return fabsf(g.det);
+    }
+    P1Geom<DIM, double> gd;
+    p1_geom<DIM, double>(ev, gd);
+    return fabs(gd.det);
+}
+
+// ------------------------------------------------------------------------- load vector
+// b2D[e*nlb + j] = |det| sum_q w_q f_q lam_qj; the rule sum in T, |det| in T (FP64 when routed)
+template <int DIM, typename T, int QN>
+__global__ __launch_bounds__(RBS) void k_rhs_elem(int64_t nn, const double* __restrict__ coords, int64_t ne,
+                                                  const int32_t* __restrict__ elems, const T* __restrict__ fq,
+                                                  T* __restrict__ b2D, Fallback fb, int64_t* d_counters) {
+    constexpr int NLB = DIM + 1;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * RBS + threadIdx.x;
+    bool routed = false, bad = false;
+    if (e < ne) {
+        int nd[NLB];
+        double ev[DIM][DIM];
+        bad = !gather_edges<DIM>(coords, nn, elems, e, nd, ev);
+        T s[NLB];
+#pragma unroll
+        for (int j = 0; j < NLB; ++j) s[j] = T(0);
+#pragma unroll
+        for (int q = 0; q < QN; ++q) {
+            const T wf = static_cast<T>(quad_weight<DIM, QN>()) * fq[e * QN + q];
+#pragma unroll
+            for (int j = 0; j < NLB; ++j) s[j] = fmaT(wf, static_cast<T>(QuadRule<DIM, QN>::lam(q, j)), s[j]);
+        }
+        if (bad) {
+#pragma unroll
+            for (int j = 0; j < NLB; ++j) b2D[e * NLB + j] = static_cast<T>(NAN);
+        } else {
+            const double ad = abs_det<DIM, T>(ev, fb, routed);
+#pragma unroll
+            for (int j = 0; j < NLB; ++j)
+                b2D[e * NLB + j] = routed ? static_cast<T>(ad * static_cast<double>(s[j])) : static_cast<T>(ad) * s[j];
+        }
+    }
+    count_wave(d_counters, 0, routed);
+    count_wave(d_counters, 2, bad);
+}
+
+// b[i] = sum of the entries of the elements around node i, exact on the grid of the node's
+// largest entry: the first pass finds that maximum, the second adds the rounded entries in
+// the integer accumulator (order-independent), one conversion back at the end
+template <typename T>
+__global__ __launch_bounds__(RBS) void k_rhs_nodes(int64_t nn, int nlb, const int32_t* __restrict__ adj_len,
+                                                   const int32_t* __restrict__ adj, const T* __restrict__ b2D,
+                                                   T* __restrict__ b) {
+    using A = typename Exact<T>::acc;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * RBS + threadIdx.x;
+    if (i >= nn) return;
+    const int L = min(adj_len[i], CSR_MAXADJ);
+    const int32_t* row = adj + i * CSR_MAXADJ;
+    uint32_t mx = 0;
+    for (int j = 0; j < L; ++j) {
+        const int32_t w = row[j];
+        mx = max(mx, Exact<T>::mag(b2D[static_cast<int64_t>(w >> 2) * nlb + (w & 3)]));
+    }
+    const int sh = Exact<T>::shift(mx);
+    A acc = A(0);
+    for (int j = 0; j < L; ++j) {
+        const int32_t w = row[j];
+        acc += Exact<T>::quant(b2D[static_cast<int64_t>(w >> 2) * nlb + (w & 3)], sh);
+    }
+    b[i] = Exact<T>::back(acc, sh);
+}
+
+// ----------------------------------------------------------------------------- energies
+// The three parts of one element from its cofactor columns (precision C) and nodal values.
+template <int DIM, int QN, typename C>
+__device__ __forceinline__ void energy_parts(const P1Geom<DIM, C>& g, const C (&uj)[DIM + 1], C ckm,
+                                             const C (&cmq)[QN], C (&J)[2]) {
+    C gu[DIM];
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+        C s = (uj[1] - uj[0]) * g.c[1][i];
+#pragma unroll
+        for (int j = 2; j <= DIM; ++j) s = fmaT(uj[j] - uj[0], g.c[j][i], s);
+        gu[i] = s;
+    }
+    C g2 = gu[0] * gu[0];
+#pragma unroll
+    for (int i = 1; i < DIM; ++i) g2 = fmaT(gu[i], gu[i], g2);
+    const C adet = fabs(g.det);
+    J[0] = C(0.5) * ckm * g2 / (static_cast<C>(fact_dim<DIM>()) * adet);
+    C m = C(0);
+#pragma unroll
+    for (int q = 0; q < QN; ++q) {
+        C uq = static_cast<C>(QuadRule<DIM, QN>::lam(q, 0)) * uj[0];
+#pragma unroll
+        for (int j = 1; j <= DIM; ++j) uq = fmaT(static_cast<C>(QuadRule<DIM, QN>::lam(q, j)), uj[j], uq);
+        m = fmaT(cmq[q] * uq, uq, m);
+    }
+    J[1] = C(0.5) * adet * static_cast<C>(quad_weight<DIM, QN>()) * m;
+}
+
+// one element per lane (grid-strided over a fixed grid); J[c * ne + e] in T (nullable);
+// per-block FP64 sums of the three parts into part[3 * blockIdx.x + c]
+template <int DIM, typename T, int QN>
+__global__ __launch_bounds__(RBS) void k_energies(int64_t nn, const double* __restrict__ coords, int64_t ne,
+                                                  const int32_t* __restrict__ elems, const T* __restrict__ cKq,
+                                                  const T* __restrict__ cMq, const T* __restrict__ u,
+                                                  const T* __restrict__ b2D, T* __restrict__ J,
+                                                  double* __restrict__ part, Fallback fb, int64_t* d_counters) {
+    constexpr int NLB = DIM + 1;
+    __shared__ double red[3][RBS / 64];
+    double sum[3] = {0.0, 0.0, 0.0};
+    int64_t nrouted = 0, nbad = 0;
+    for (int64_t e = static_cast<int64_t>(blockIdx.x) * RBS + threadIdx.x; e < ne;
+         e += static_cast<int64_t>(gridDim.x) * RBS) {
+        int nd[NLB];
+        double ev[DIM][DIM];
+        const bool ok = gather_edges<DIM>(coords, nn, elems, e, nd, ev);
+        double Je[3];
+        if (!ok) {
+            ++nbad;
+            Je[0] = Je[1] = Je[2] = NAN;
+        } else {
+            T uj[NLB], ck = T(0), cmq[QN];
+#pragma unroll
+            for (int j = 0; j < NLB; ++j) uj[j] = u[nd[j]];
+#pragma unroll
+            for (int q = 0; q < QN; ++q) {
+                ck += cKq ? cKq[e * QN + q] : T(1);
+                cmq[q] = cMq ? cMq[e * QN + q] : T(1);
+            }
+            ck *= static_cast<T>(1.0 / QN);  // equal weights: the weighted mean
+            T j3 = T(0);
+            if (b2D)
+#pragma unroll
+                for (int j = 0; j < NLB; ++j) j3 = fmaT(-b2D[e * NLB + j], uj[j], j3);
+            Je[2] = static_cast<double>(j3);
+            bool routed = false;
+            if constexpr (sizeof(T) == 4) {
+                P1Geom<DIM, float> g;
+                p1_geom<DIM, float>(ev, g);
+                routed = should_route(g.det, g.absterms, fb);
+                if (!routed) {
+                    float Jf[2];
+                    energy_parts<DIM, QN, float>(g, uj, ck, cmq, Jf);
+                    Je[0] = Jf[0];
+                    Je[1] = Jf[1];
+                }
+            }
+            if (sizeof(T) == 8 || routed) {
+                P1Geom<DIM, double> gd;
+                p1_geom<DIM, double>(ev, gd);
+                double ud[NLB], cmd[QN], Jd[2];
+#pragma unroll
+                for (int j = 0; j < NLB; ++j) ud[j] = uj[j];
+#pragma unroll
+                for (int q = 0; q < QN; ++q) cmd[q] = cmq[q];
+                energy_parts<DIM, QN, double>(gd, ud, static_cast<double>(ck), cmd, Jd);
+                Je[0] = Jd[0];
+                Je[1] = Jd[1];
+            }
+            nrouted += routed;
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T v = static_cast<T>(Je[c]);
+            if (J) J[c * ne + e] = v;
+            sum[c] += static_cast<double>(v);  // the totals add the stored values
+        }
+    }
+    if (nrouted) count_add(d_counters, 0, nrouted);
+    if (nbad) count_add(d_counters, 2, nbad);
+    // fixed-order block reduction: wave tree (xor shuffles), then the waves in order
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) sum[c] += __shfl_xor(sum[c], d, 64);
+        if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = sum[c];
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double s = 0.0;
+        for (int w = 0; w < RBS / 64; ++w) s += red[threadIdx.x][w];
+        part[3 * blockIdx.x + threadIdx.x] = s;
+    }
+}
+
+// totals[c] = sum over the block sums in block order (one wave per part, fixed tree)
+__global__ __launch_bounds__(192) void k_energy_totals(const double* __restrict__ part, int nblocks,
+                                                       double* __restrict__ totals) {
+    const int c = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double s = 0.0;
+    for (int b = lane; b < nblocks; b += 64) s += part[3 * b + c];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+    if (lane == 0) totals[c] = s;
+}
+
+namespace {
+
+pf_status check_csr_mesh(const pf_csr* csr, const double* coords, const int32_t* elems, const char* who) {
+    if (!csr) return fail(PF_EINVAL, std::string(who) + ": null handle");
+    if (!csr_built(csr)) return fail(PF_ESTATE, std::string(who) + ": structure not built");
+    if (csr_ne(csr) > 0 && (!coords || !elems)) return fail(PF_EINVAL, std::string(who) + ": null coords or elems");
+    return PF_OK;
+}
+
+template <int DIM, typename T>
+void launch_rhs_elem(int qn, int64_t nn, const double* coords, int64_t ne, const int32_t* elems, const void* fq,
+                     void* b2D, Fallback f, int64_t* ctr, hipStream_t s) {
+    const unsigned g = static_cast<unsigned>(ceil_div(ne, RBS));
+    constexpr int Q2 = DIM == 2 ? 3 : 4;
+    if (qn == 1)
+        hipLaunchKernelGGL((k_rhs_elem<DIM, T, 1>), dim3(g), dim3(RBS), 0, s, nn, coords, ne, elems,
+                           static_cast<const T*>(fq), static_cast<T*>(b2D), f, ctr);
+    else
+        hipLaunchKernelGGL((k_rhs_elem<DIM, T, Q2>), dim3(g), dim3(RBS), 0, s, nn, coords, ne, elems,
+                           static_cast<const T*>(fq), static_cast<T*>(b2D), f, ctr);
+}
+
+template <int DIM, typename T>
+void launch_energies(int qn, int grid, int64_t nn, const double* coords, int64_t ne, const int32_t* elems,
+                     const void* cKq, const void* cMq, const void* u, const void* b2D, void* J, double* part,
+                     Fallback f, int64_t* ctr, hipStream_t s) {
+    constexpr int Q2 = DIM == 2 ? 3 : 4;
+    if (qn == 1)
+        hipLaunchKernelGGL((k_energies<DIM, T, 1>), dim3(grid), dim3(RBS), 0, s, nn, coords, ne, elems,
+                           static_cast<const T*>(cKq), static_cast<const T*>(cMq), static_cast<const T*>(u),
+                           static_cast<const T*>(b2D), static_cast<T*>(J), part, f, ctr);
+    else
+        hipLaunchKernelGGL((k_energies<DIM, T, Q2>), dim3(grid), dim3(RBS), 0, s, nn, coords, ne, elems,
+                           static_cast<const T*>(cKq), static_cast<const T*>(cMq), static_cast<const T*>(u),
+                           static_cast<const T*>(b2D), static_cast<T*>(J), part, f, ctr);
+}
+
+}  // namespace
+}  // namespace pf
+
+using namespace pf;
+
+pf_status pf_rhs(const pf_csr* csr, pf_dtype prec, const double* coords, const int32_t* elems, int order,
+                 const void* fq, void* b2D, void* b, const pf_fallback* fb, int64_t* d_counters, void* stream) {
+    pf_status st = check_csr_mesh(csr, coords, elems, "pf_rhs");
+    if (st) return st;
+    const int dim = csr_dim(csr);
+    const int qn = quad_count(dim, order);
+    if (!qn) return fail(PF_EINVAL, "pf_rhs: order must be 1 or 2");
+    if (prec != PF_F32 && prec != PF_F64) return fail(PF_EDTYPE, "pf_rhs: prec must be PF_F32 or PF_F64");
+    const int64_t nn = csr_nn(csr), ne = csr_ne(csr);
+    if (ne > 0 && (!fq || !b2D)) return fail(PF_EINVAL, "pf_rhs: null fq or b2D");
+    hipStream_t s = as_stream(stream);
+    const Fallback f = make_fallback(fb);
+    if (ne > 0) {
+        if (dim == 3) {
+            if (prec == PF_F32) launch_rhs_elem<3, float>(qn, nn, coords, ne, elems, fq, b2D, f, d_counters, s);
+            else launch_rhs_elem<3, double>(qn, nn, coords, ne, elems, fq, b2D, f, d_counters, s);
+        } else {
+            if (prec == PF_F32) launch_rhs_elem<2, float>(qn, nn, coords, ne, elems, fq, b2D, f, d_counters, s);
+            else launch_rhs_elem<2, double>(qn, nn, coords, ne, elems, fq, b2D, f, d_counters, s);
+        }
+        if ((st = launch_check("pf_rhs elements"))) return st;
+    }
+    if (b && nn > 0) {
+        const unsigned g = static_cast<unsigned>(ceil_div(nn, RBS));
+        if (prec == PF_F32)
+            hipLaunchKernelGGL(k_rhs_nodes<float>, dim3(g), dim3(RBS), 0, s, nn, dim + 1, csr_adj_len(csr),
+                               csr_adj(csr), static_cast<const float*>(b2D), static_cast<float*>(b));
+        else
+            hipLaunchKernelGGL(k_rhs_nodes<double>, dim3(g), dim3(RBS), 0, s, nn, dim + 1, csr_adj_len(csr),
+                               csr_adj(csr), static_cast<const double*>(b2D), static_cast<double*>(b));
+        if ((st = launch_check("pf_rhs nodes"))) return st;
+    }
+    return PF_OK;
+}
+
+pf_status pf_energies(pf_csr* csr, pf_dtype prec, const double* coords, const int32_t* elems, int order,
+                      const void* cKq, const void* cMq, const void* u, const void* b2D, void* J, double* totals,
+                      const pf_fallback* fb, int64_t* d_counters, void* stream) {
+    pf_status st = check_csr_mesh(csr, coords, elems, "pf_energies");
+    if (st) return st;
+    const int dim = csr_dim(csr);
+    const int qn = quad_count(dim, order);
+    if (!qn) return fail(PF_EINVAL, "pf_energies: order must be 1 or 2");
+    if (prec != PF_F32 && prec != PF_F64) return fail(PF_EDTYPE, "pf_energies: prec must be PF_F32 or PF_F64");
+    const int64_t nn = csr_nn(csr), ne = csr_ne(csr);
+    if (ne > 0 && !u) return fail(PF_EINVAL, "pf_energies: null u");
+    hipStream_t s = as_stream(stream);
+    const Fallback f = make_fallback(fb);
+    const int grid = static_cast<int>(std::max<int64_t>(std::min<int64_t>(ceil_div(ne, RBS), ETOT_BLOCKS), 1));
+    double* part = nullptr;
+    if ((st = csr_workspace(csr, 3 * static_cast<int64_t>(grid), &part))) return st;
+    if (dim == 3) {
+        if (prec == PF_F32)
+            launch_energies<3, float>(qn, grid, nn, coords, ne, elems, cKq, cMq, u, b2D, J, part, f, d_counters, s);
+        else
+            launch_energies<3, double>(qn, grid, nn, coords, ne, elems, cKq, cMq, u, b2D, J, part, f, d_counters, s);
+    } else {
+        if (prec == PF_F32)
+            launch_energies<2, float>(qn, grid, nn, coords, ne, elems, cKq, cMq, u, b2D, J, part, f, d_counters, s);
+        else
+            launch_energies<2, double>(qn, grid, nn, coords, ne, elems, cKq, cMq, u, b2D, J, part, f, d_counters, s);
+    }
+    if ((st = launch_check("pf_energies"))) return st;
+    if (totals) {
+        hipLaunchKernelGGL(k_energy_totals, dim3(1), dim3(192), 0, s, part, grid, totals);
+        if ((st = launch_check("pf_energies totals"))) return st;
+    }
+    return PF_OK;
+}

@@ -1,5 +1,6 @@
 // internal.hpp -- declarations shared between the library's own translation units (not
-// part of the C ABI): the multi-mesh numeric assembly used by the serving loop.
+// part of the C ABI): the multi-mesh numeric assembly used by the serving loop, and the
+// structure handle's adjacency and workspace for the load vector and energy kernels.
 #pragma once
 
 #include "common.hpp"
@@ -36,5 +37,14 @@ size_t csr_bytes(const pf_csr* c);
 int64_t csr_nnz(const pf_csr* c);
 int64_t csr_nn(const pf_csr* c);
 int csr_dim(const pf_csr* c);
+int64_t csr_ne(const pf_csr* c);
+bool csr_built(const pf_csr* c);
+// node -> element adjacency of the structure: entries (element << 2 | local index) of node i
+// at adj[i * CSR_MAXADJ ...], adj_len[i] of them
+constexpr int CSR_MAXADJ = 64;
+const int32_t* csr_adj(const pf_csr* c);
+const int32_t* csr_adj_len(const pf_csr* c);
+// a device workspace of at least `words` doubles owned by the handle (grown when needed)
+pf_status csr_workspace(pf_csr* c, int64_t words, double** out);
 
 }  // namespace pf

@@ -133,6 +133,8 @@ _sig = {
     "pf_boundary_normals": ([I32, I32, I64, P, I64, P, P, P, P], C.c_int),
     "pf_quad_points": ([I32, I32, I64, P, I64, P, P, P], C.c_int),
     "pf_assemble_quad": ([P, I32, P, I32, P, P, P, P, FP, P, P], C.c_int),
+    "pf_rhs": ([P, I32, P, P, I32, P, P, P, FP, P, P], C.c_int),
+    "pf_energies": ([P, I32, P, P, I32, P, P, P, P, P, P, FP, P, P], C.c_int),
     "pf_csr_create": ([C.POINTER(P)], C.c_int),
     "pf_csr_symbolic": ([P, I32, I64, I64, P, P], C.c_int),
     "pf_csr_info": ([P, C.POINTER(I64), C.POINTER(I64), C.POINTER(P), C.POINTER(P)], C.c_int),
@@ -351,6 +353,17 @@ class Csr:
         """Assembly with coefficients at the integration points (ne x nq, type prec)."""
         _chk(_lib.pf_assemble_quad(self._h, prec, _p(coords), int(order), _p(cKq), _p(cMq), _p(valsK), _p(valsM),
                                    _ref(fb, Fallback), _p(counters), _s(stream)), "pf_assemble_quad")
+
+    def rhs(self, prec, coords, elems, order, fq, b2D, b=None, fb=None, counters=None, stream=None):
+        """Load vector: local vectors into b2D (ne x nlb) and, if b is given, their node sums."""
+        _chk(_lib.pf_rhs(self._h, prec, _p(coords), _p(elems), int(order), _p(fq), _p(b2D), _p(b),
+                         _ref(fb, Fallback), _p(counters), _s(stream)), "pf_rhs")
+
+    def energies(self, prec, coords, elems, order, u, cKq=None, cMq=None, b2D=None, J=None, totals=None, fb=None,
+                 counters=None, stream=None):
+        """Local energy parts into J (3 x ne) and/or their FP64 sums into totals (3 doubles)."""
+        _chk(_lib.pf_energies(self._h, prec, _p(coords), _p(elems), int(order), _p(cKq), _p(cMq), _p(u), _p(b2D),
+                              _p(J), _p(totals), _ref(fb, Fallback), _p(counters), _s(stream)), "pf_energies")
 
     def close(self):
         if self._h:

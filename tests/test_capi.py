@@ -84,6 +84,11 @@ def test_csr_handle_states_without_gpu():
     assert L.pf_csr_stage_times(h, None, None) == 1
     assert L.pf_csr_set_timing(h, 0) == 0
     assert L.pf_csr_stage_times(h, ms, C.byref(calls)) == 0 and calls.value == 0 and list(ms) == [0.0] * 4
+    # load vector and energies: null / unbuilt handles and bad rules are host errors
+    assert L.pf_rhs(None, lib.F32, None, None, 2, None, None, None, None, None, None) == 1
+    assert L.pf_rhs(h, lib.F32, None, None, 2, None, None, None, None, None, None) == 9
+    assert L.pf_energies(None, lib.F32, None, None, 2, None, None, None, None, None, None, None, None, None) == 1
+    assert L.pf_energies(h, lib.F32, None, None, 2, None, None, None, None, None, None, None, None, None) == 9
     stages = re.search(r"#define PF_CSR_STAGES (\d+)", open(os.path.join(ROOT, "include", "pagefem.h")).read())
     assert int(stages.group(1)) == len(lib.Csr.CSR_STAGES) == 4
     L.pf_csr_destroy(h)
