@@ -18,6 +18,8 @@ Other workloads (one JSON line each, same contract):
   --workload batch   64 groups of pages of orders 2..4, sizes 10^U(3,6) (about 9.3 million
                      pages), FP32 inverse + product per group in one persistent launch
                      replayed from a HIP graph, against one launch per group and operation
+  --workload energy  load vector (local vectors + node sums) and local energy parts on the
+                     128^3 cube mesh, FP32, fields at the 4 points of the degree-2 rule
   --workload serve   a Poisson stream of assembly jobs (200 jobs/s, 2-D FP64 / 3-D FP32,
                      1e3..2e6 elements) through the serving loop: p50/p99 latency and
                      throughput, fused + resident structures vs one launch per job without
@@ -37,8 +39,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "assembly_cube128_traffic.json")
-KERNEL_SOURCES = ["assembly.hip", "p1elem.hpp", "smallmat.hpp", "common.hpp"]
+KERNEL_SOURCES = ["assembly.hip", "p1elem.hpp", "smallmat.hpp", "common.hpp", "exact.hpp", "quadrature.hpp"]
 BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_plan_64groups_traffic.json")
+ENERGY_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "energy_cube128_traffic.json")
+ENERGY_SOURCES = ["energy.hip", "p1elem.hpp", "smallmat.hpp", "common.hpp", "exact.hpp", "quadrature.hpp"]
 BATCH_SOURCES = ["batch.hip", "smallmat.hpp", "common.hpp"]
 
 
@@ -80,7 +84,7 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=128, help="cubes per side of the CPU oracle sample")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
-    ap.add_argument("--workload", choices=["assembly", "pages", "batch", "serve"], default="assembly")
+    ap.add_argument("--workload", choices=["assembly", "pages", "batch", "serve", "energy"], default="assembly")
     ap.add_argument("--coef", choices=["one", "quad"], default="one",
                     help="assembly coefficients: c = 1, or c = exp(x1+x2+x3) at the 4 points of the degree-2 rule "
                          "(the paper's section 3.6 benchmark)")
@@ -285,6 +289,109 @@ def run_batch(args):
     print(json.dumps(out))
 
 
+def run_energy(args):
+    """Load vector and local energy parts on the 3-D cube mesh (FP32, degree-2 rule)."""
+    import numpy as np
+    import torch
+
+    from paper_2404_16039_amd import gen
+    from paper_2404_16039_amd import lib as L
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    n = args.n
+    coords, elems, _ = gen.cube_mesh(n, jitter=0.15, with_faces=False)
+    nn, ne = coords.shape[0], elems.shape[0]
+    tc, te = torch.from_numpy(coords).cuda(), torch.from_numpy(elems).cuda()
+    # fields at the 4 integration points of every element, resident before the clock
+    xq = L.quad_points(tc, te, 2)
+    s = xq.sum(dim=2)
+    fq = (torch.sin(3.0 * s) + 0.5 * xq[..., 0]).to(torch.float32).contiguous()
+    cKq = torch.exp(s).to(torch.float32).contiguous()
+    cMq = (1.0 + xq[..., 2] ** 2).to(torch.float32).contiguous()
+    u = (torch.cos(2.0 * tc[:, 0]) + tc[:, 1] ** 2 - 0.3 * tc[:, 2]).to(torch.float32).contiguous()
+    del xq, s
+    csr = L.Csr().symbolic(3, nn, te)
+    b2D = torch.empty(ne * 4, dtype=torch.float32, device="cuda")
+    b = torch.empty(nn, dtype=torch.float32, device="cuda")
+    J = torch.empty(3 * ne, dtype=torch.float32, device="cuda")
+    tot = torch.zeros(3, dtype=torch.float64, device="cuda")
+    fb = L.fallback(1e-3 / n ** 3, 1e6, True)
+    _calib_copy(args.copy_calib_mib)
+
+    def step():
+        csr.rhs(L.F32, tc, te, 2, fq, b2D, b, fb=fb, stream=stream)
+        csr.energies(L.F32, tc, te, 2, u, cKq=cKq, cMq=cMq, b2D=b2D, J=J, totals=tot, fb=fb, stream=stream)
+
+    # per-kernel durations: the element part of the load vector alone, the whole load
+    # vector (the node sums are the difference), the energies (element kernel + totals)
+    t_elem = _timed(lambda: csr.rhs(L.F32, tc, te, 2, fq, b2D, None, fb=fb, stream=stream), args.steps,
+                    args.warmup, stream)
+    t_rhs = _timed(lambda: csr.rhs(L.F32, tc, te, 2, fq, b2D, b, fb=fb, stream=stream), args.steps, args.warmup,
+                   stream)
+    t_en = _timed(lambda: csr.energies(L.F32, tc, te, 2, u, cKq=cKq, cMq=cMq, b2D=b2D, J=J, totals=tot, fb=fb,
+                                       stream=stream), args.steps, args.warmup, stream)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    ms = {"k_rhs_elem<3,float,4>": float(np.mean(t_elem)),
+          "k_rhs_nodes<float>": max(float(np.mean(t_rhs) - np.mean(t_elem)), 1e-6),
+          "k_energies<3,float,4> + totals": float(np.mean(t_en))}
+    # algorithmic bytes per launch: element node ids 16 B/tet, FP64 coordinates 24 B/node,
+    # FP32 values at 4 points 16 B/tet each (f; c_K; c_M), local vectors 16 B/tet, node sums
+    # 4 B/node, the adjacency words 16 B/tet and lengths 4 B/node, nodal u 4 B/node, J 12 B/tet
+    alg = {"k_rhs_elem<3,float,4>": 48 * ne + 24 * nn,
+           "k_rhs_nodes<float>": 32 * ne + 8 * nn,
+           "k_energies<3,float,4> + totals": 76 * ne + 28 * nn}
+    dom = max(ms, key=ms.get)
+
+    def roof(k):
+        gbs = alg[k] / (ms[k] * 1e-3) / 1e9
+        return {"kernel": k, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS,
+                "traffic": traffic_of(ENERGY_TRAFFIC_FILE, ENERGY_SOURCES, kernel=k.split(" ")[0], n=n),
+                "algorithmic_bytes_per_launch": alg[k], "launch_us": round(ms[k] * 1e3, 1)}
+
+    th = tot.cpu().numpy()
+    out = {
+        "metric": "P1 tet elements/s (load vector with node sums + local energy parts)",
+        "value": ne / (wall / args.steps), "unit": "tets/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "3-D P1 tets: unit cube, %d^3 cubes x 6 Kuhn tets, jitter 0.15 h; f, c_K, c_M at the "
+                               "4 points of the degree-2 rule, FP32; b2D + b (pf_rhs) and J1k, J2k, J3k + totals "
+                               "(pf_energies)" % n, "tets": ne, "nodes": nn},
+        "kernels_us": {k: round(v * 1e3, 1) for k, v in ms.items()},
+        "totals": [float(x) for x in th],
+        "roofline": roof(dom),
+        "rooflines": {k: roof(k) for k in ms},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        cn = args.cpu_n
+        c2, e2, _ = gen.cube_mesh(cn, jitter=0.15, with_faces=False)
+        xq2 = oracle.quad_points(c2, e2, 2)
+        s2 = xq2.sum(axis=2)
+        f2, ck2, cm2 = np.sin(3.0 * s2) + 0.5 * xq2[..., 0], np.exp(s2), 1.0 + xq2[..., 2] ** 2
+        u2 = np.cos(2.0 * c2[:, 0]) + c2[:, 1] ** 2 - 0.3 * c2[:, 2]
+        t1 = time.perf_counter()
+        r = oracle.rhs_p1(c2, e2, 2, f2)
+        oracle.local_energies(c2, e2, 2, u2, cKq=ck2, cMq=cm2, b2D=r["b2D"])
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": e2.shape[0] / dt, "unit": "tets/s", "cores": 1, "kind": "oracle",
+                               "sample": "FP64 oracle load vector (local vectors + accumarray) and local energies "
+                                         "(element matrices + page bilinear forms), single thread, %d^3 Kuhn mesh, "
+                                         "%d tets, %.1f s" % (cn, e2.shape[0], dt)}
+    csr.close()
+    print(json.dumps(out))
+
+
 def run_serve(args):
     """Poisson stream of assembly jobs through the serving loop."""
     import numpy as np
@@ -392,6 +499,8 @@ def main():
         return run_batch(args)
     if args.workload == "serve":
         return run_serve(args)
+    if args.workload == "energy":
+        return run_energy(args)
 
     import numpy as np
     import torch

@@ -3,10 +3,9 @@
 // the gradient, reactive and linear parts of the energy functional).
 //
 // Load vector: one element per lane computes its local vector b2D (|det J| times the rule
-// applied to f phi_j); one node per lane then sums the entries of the elements around it,
+// applied to f phi_j); half a wave per node then sums the entries of the elements around it,
 // read through the structure handle's node -> element adjacency, exactly on a grid fixed by
-// the node's largest entry (two passes over its entries), so b does not depend on the order
-// of the adjacency lists.
+// the node's largest entry, so b does not depend on the order of the adjacency lists.
 //
 // Energies: one element per lane; with c_j = det * grad phi_j (the cofactor columns of the
 // Jacobian),
@@ -88,29 +87,53 @@ __global__ __launch_bounds__(RBS) void k_rhs_elem(int64_t nn, const double* __re
 }
 
 // b[i] = sum of the entries of the elements around node i, exact on the grid of the node's
-// largest entry: the first pass finds that maximum, the second adds the rounded entries in
-// the integer accumulator (order-independent), one conversion back at the end
+// largest entry.  Half a wave per node: lane l reads adjacency entries l and l + 32 of the
+// row (contiguous words) and gathers their local-vector values; the row maximum and then
+// the integer sum of the rounded values are reduced across the 32 lanes with shuffles
+// (integer adds: exact, so the result does not depend on the entry order).  Each half wave
+// takes RHS_ROWS nodes at once, issuing all of their loads before the first reduction.
+constexpr int RHS_ROWS = 4;
 template <typename T>
 __global__ __launch_bounds__(RBS) void k_rhs_nodes(int64_t nn, int nlb, const int32_t* __restrict__ adj_len,
                                                    const int32_t* __restrict__ adj, const T* __restrict__ b2D,
                                                    T* __restrict__ b) {
     using A = typename Exact<T>::acc;
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * RBS + threadIdx.x;
-    if (i >= nn) return;
-    const int L = min(adj_len[i], CSR_MAXADJ);
-    const int32_t* row = adj + i * CSR_MAXADJ;
-    uint32_t mx = 0;
-    for (int j = 0; j < L; ++j) {
-        const int32_t w = row[j];
-        mx = max(mx, Exact<T>::mag(b2D[static_cast<int64_t>(w >> 2) * nlb + (w & 3)]));
+    static_assert(CSR_MAXADJ == 64, "two entries per lane of a half wave");
+    const int64_t h = (static_cast<int64_t>(blockIdx.x) * RBS + threadIdx.x) >> 5;  // half wave
+    const int l = threadIdx.x & 31;
+    int64_t i[RHS_ROWS];
+    int L[RHS_ROWS];
+    int32_t w0[RHS_ROWS];
+    T v0[RHS_ROWS], v1[RHS_ROWS];
+#pragma unroll
+    for (int k = 0; k < RHS_ROWS; ++k) {  // every lane takes part in the shuffles
+        i[k] = h * RHS_ROWS + k;
+        L[k] = i[k] < nn ? min(adj_len[i[k]], CSR_MAXADJ) : 0;
     }
-    const int sh = Exact<T>::shift(mx);
-    A acc = A(0);
-    for (int j = 0; j < L; ++j) {
-        const int32_t w = row[j];
-        acc += Exact<T>::quant(b2D[static_cast<int64_t>(w >> 2) * nlb + (w & 3)], sh);
+#pragma unroll
+    for (int k = 0; k < RHS_ROWS; ++k)  // the rows' first 128 bytes: one line each
+        w0[k] = l < L[k] ? adj[i[k] * CSR_MAXADJ + l] : 0;
+#pragma unroll
+    for (int k = 0; k < RHS_ROWS; ++k) {
+        v0[k] = l < L[k] ? b2D[static_cast<int64_t>(w0[k] >> 2) * nlb + (w0[k] & 3)] : T(0);
+        v1[k] = T(0);
+        if (l + 32 < L[k]) {  // only nodes with more than 32 elements read the second half
+            const int32_t w1 = adj[i[k] * CSR_MAXADJ + l + 32];
+            v1[k] = b2D[static_cast<int64_t>(w1 >> 2) * nlb + (w1 & 3)];
+        }
     }
-    b[i] = Exact<T>::back(acc, sh);
+#pragma unroll
+    for (int k = 0; k < RHS_ROWS; ++k) {
+        uint32_t mx = max(Exact<T>::mag(v0[k]), Exact<T>::mag(v1[k]));
+#pragma unroll
+        for (int d = 16; d >= 1; d >>= 1)
+            mx = max(mx, static_cast<uint32_t>(__shfl_xor(static_cast<int>(mx), d, 32)));
+        const int sh = Exact<T>::shift(mx);
+        A acc = Exact<T>::quant(v0[k], sh) + Exact<T>::quant(v1[k], sh);
+#pragma unroll
+        for (int d = 16; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 32);
+        if (i[k] < nn && l == 0) b[i[k]] = Exact<T>::back(acc, sh);
+    }
 }
 
 // ----------------------------------------------------------------------------- energies
@@ -304,7 +327,7 @@ pf_status pf_rhs(const pf_csr* csr, pf_dtype prec, const double* coords, const i
         if ((st = launch_check("pf_rhs elements"))) return st;
     }
     if (b && nn > 0) {
-        const unsigned g = static_cast<unsigned>(ceil_div(nn, RBS));
+        const unsigned g = static_cast<unsigned>(ceil_div(ceil_div(nn, RHS_ROWS) * 32, RBS));  // half waves
         if (prec == PF_F32)
             hipLaunchKernelGGL(k_rhs_nodes<float>, dim3(g), dim3(RBS), 0, s, nn, dim + 1, csr_adj_len(csr),
                                csr_adj(csr), static_cast<const float*>(b2D), static_cast<float*>(b));
