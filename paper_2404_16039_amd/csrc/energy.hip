@@ -92,7 +92,7 @@ __global__ __launch_bounds__(RBS) void k_rhs_elem(int64_t nn, const double* __re
 // the integer sum of the rounded values are reduced across the 32 lanes with shuffles
 // (integer adds: exact, so the result does not depend on the entry order).  Each half wave
 // takes RHS_ROWS nodes at once, issuing all of their loads before the first reduction.
-constexpr int RHS_ROWS = 4;
+constexpr int RHS_ROWS = 8;
 template <typename T>
 __global__ __launch_bounds__(RBS) void k_rhs_nodes(int64_t nn, int nlb, const int32_t* __restrict__ adj_len,
                                                    const int32_t* __restrict__ adj, const T* __restrict__ b2D,
