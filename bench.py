@@ -9,7 +9,8 @@ Workload (one step = the whole hot path over one mesh, inputs resident in HBM):
     2. numeric assembly of K and M (per-element geometry, stiffness and mass in registers,
        deterministic row-wise sums into the CSR values)
     3. boundary triangle normals and areas (196,608 faces)
-Prints one JSON line (see the design doc for the fields).
+Prints one JSON line: the metric and its value, the step time, per-phase and per-kernel
+times, the roofline of the dominant kernel and the CPU oracle's rate on the same work.
 
 Other workloads (one JSON line each, same contract):
   --workload pages   page operations on 1e7 random 3x3 pages (N(0,1) + 3 I), FP64 and FP32,
@@ -490,7 +491,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(the path shards by rows or elements, see DESIGN.md)", file=sys.stderr)
+              f"(the assembly would shard by rows: each GPU owns a node range and the elements around it)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "pages":
