@@ -55,6 +55,11 @@ def _load():
         lib.or_p1_elements_q.argtypes = [INT, INT, I64, P, I64, P, P, P, P, P, P, P]
         lib.or_p1_elements_q.restype = I64
         lib.or_rhs_p1.argtypes = [INT, INT, I64, P, I64, P, P, P, P, P]
+        lib.or_faces.argtypes = [INT, I64, P, I64, P, P, P, I64]
+        lib.or_faces.restype = I64
+        lib.or_simplex_points.argtypes = [INT, INT, I64, P, I64, P, INT, P, P]
+        lib.or_gi.argtypes = [I64, INT, INT, P, P, P, P]
+        lib.or_gi.restype = D
         lib.or_route_predicate.argtypes = [INT, P, I64, D, D, P, P]
         lib.or_assemble.argtypes = [INT, I64, I64, P, P, P, P, P, P, P, P, P, P, I64]
         lib.or_assemble.restype = I64
@@ -247,6 +252,68 @@ def local_energies(coords, elems, order, u, cKq=None, cMq=None, b2D=None):
         J3 = -(b2 * ue).sum(axis=1)
         J3abs = (np.abs(b2) * ua).sum(axis=1)
     return {"J1k": J1, "J2k": J2, "J3k": J3, "J1abs": J1abs, "J2abs": J2abs, "J3abs": J3abs}
+
+
+def faces(coords, elems):
+    """All faces by sorting the nlb faces of every element (keys = ascending node ids, ties
+    by element): (faces (nf, dim) oriented outward of their first element, fel (nf, 2) with
+    e2 = -1 on the boundary), in ascending key order."""
+    coords = _f64(coords)
+    elems = _i32(elems)
+    nn, dim = coords.shape
+    ne, nlb = elems.shape
+    cap = max(ne * nlb, 1)
+    f = np.empty((cap, dim), dtype=np.int32)
+    fe = np.empty((cap, 2), dtype=np.int32)
+    nf = _load().or_faces(dim, nn, _p(coords), ne, _p(elems), _p(f), _p(fe), cap)
+    _check(0 if nf >= 0 else int(nf), "faces")
+    return f[:nf].copy(), fe[:nf].copy()
+
+
+def simplex_points(coords, cells, lam):
+    """Points of a rule with barycentric coordinates lam (nq, nv) on every cell: (nc, nq, dim)."""
+    coords = _f64(coords)
+    cells = _i32(cells)
+    lam = _f64(lam)
+    nn, dim = coords.shape
+    nc, nv = cells.shape
+    nq = lam.shape[0]
+    X = np.empty((nc, nq, dim))
+    _check(_load().or_simplex_points(dim, nv, nn, _p(coords), nc, _p(cells), nq, _p(lam), _p(X)), "simplex_points")
+    return X
+
+
+def gi(fip, w, sizes, normals=None):
+    """The GI function: fip (nc, nq) or (nc, nq, d), w (nq) summing to 1, sizes (nc)."""
+    fip = _f64(fip)
+    nc, nq = fip.shape[0], fip.shape[1]
+    d = fip.shape[2] if fip.ndim == 3 else 1
+    nrm = None if normals is None else _f64(np.asarray(normals).reshape(nc, d))
+    return float(_load().or_gi(nc, nq, d, _p(fip), _p(_f64(w)), _p(_f64(sizes)), _p(nrm)))
+
+
+def stroud_rule(d, m):
+    """Conical product (collapsed-coordinate) rule on the reference d-simplex (d = 2, 3;
+    Stroud, Approximate Calculation of Multiple Integrals, 1971): m Gauss-Jacobi points per
+    direction, exact for degree 2m - 1.  Returns (lam (m^d, d+1) barycentric, w summing to 1)."""
+    from scipy.special import roots_jacobi
+    ax = []
+    for k in range(d):  # direction k carries the Jacobian factor (1 - u_k)^(d - 1 - k)
+        a = d - 1 - k
+        x, wx = roots_jacobi(m, a, 0)
+        ax.append(((1 + x) / 2, wx / 2 ** (a + 1)))
+    pts, wts = [], []
+    for idx in np.ndindex(*([m] * d)):
+        u = [ax[k][0][idx[k]] for k in range(d)]
+        w = np.prod([ax[k][1][idx[k]] for k in range(d)])
+        xi, rest = [], 1.0
+        for k in range(d):
+            xi.append(u[k] * rest)
+            rest *= 1 - u[k]
+        pts.append([1 - sum(xi)] + xi)
+        wts.append(w)
+    w = np.array(wts)
+    return np.array(pts), w / w.sum()
 
 
 def create_coords3d(coords, elems):

@@ -692,3 +692,123 @@ int or_rhs_p1(int dim, int order, int64_t nn, const double* coords, int64_t ne, 
     }
     return 0;
 }
+
+/* All faces of a simplicial mesh (section 3.2, normals of all faces or of boundary faces
+ * only): every element contributes its nlb faces (the face opposite local node k), each
+ * keyed by its node ids in ascending order; the keys are sorted (ties by element id) and
+ * equal keys merged.  Outputs, faces in ascending key order:
+ *   faces[f*nv ...]  the face's nodes ordered so that its normal points out of its first
+ *                    element e1 (the smaller element id): for a positively oriented
+ *                    element (det J > 0, first-node origin) the face opposite node k is
+ *                    taken in the order that makes (b-a)x(c-a) (3-D) or (b_y-a_y, a_x-b_x)
+ *                    (2-D) outward, reversed when det J < 0;
+ *   fel[f*2 ...]     (e1, e2), e2 = -1 on the boundary.
+ * Returns the number of faces, or -1 / -2 / -3 (bad dim, bad node, a face in more than two
+ * elements); cap is the capacity of the outputs (at least nlb * ne faces). */
+typedef struct {
+    int32_t key[3];
+    int64_t e;
+    int k;
+} or_face_t;
+
+static int face_cmp(const void* pa, const void* pb) {
+    const or_face_t* a = (const or_face_t*)pa;
+    const or_face_t* b = (const or_face_t*)pb;
+    for (int i = 0; i < 3; i++)
+        if (a->key[i] != b->key[i]) return a->key[i] < b->key[i] ? -1 : 1;
+    return (a->e > b->e) - (a->e < b->e);
+}
+
+/* local node order of the face opposite node k, outward for a positively oriented element */
+static const int FACE3[4][3] = {{1, 2, 3}, {0, 3, 2}, {0, 1, 3}, {0, 2, 1}};
+static const int FACE2[3][2] = {{1, 2}, {2, 0}, {0, 1}};
+
+int64_t or_faces(int dim, int64_t nn, const double* coords, int64_t ne, const int32_t* elems, int32_t* faces,
+                 int32_t* fel, int64_t cap) {
+    if (dim != 2 && dim != 3) return -1;
+    int nlb = dim + 1, nv = dim;
+    int64_t m = ne * nlb;
+    or_face_t* all = (or_face_t*)malloc(sizeof(or_face_t) * (size_t)(m > 0 ? m : 1));
+    if (!all) return -4;
+    for (int64_t e = 0; e < ne; e++)
+        for (int k = 0; k < nlb; k++) {
+            or_face_t* f = &all[e * nlb + k];
+            int t = 0;
+            for (int j = 0; j < nlb; j++) {
+                if (j == k) continue;
+                int32_t v = elems[e * nlb + j];
+                if (v < 0 || v >= nn) { free(all); return -2; }
+                f->key[t++] = v;
+            }
+            for (int a = 0; a < nv; a++)       /* insertion sort of the key */
+                for (int b = a + 1; b < nv; b++)
+                    if (f->key[b] < f->key[a]) { int32_t x = f->key[a]; f->key[a] = f->key[b]; f->key[b] = x; }
+            if (nv == 2) f->key[2] = -1;
+            f->e = e;
+            f->k = k;
+        }
+    qsort(all, (size_t)m, sizeof(or_face_t), face_cmp);
+    int64_t nf = 0;
+    for (int64_t i = 0; i < m;) {
+        int64_t j = i + 1;
+        while (j < m && all[j].key[0] == all[i].key[0] && all[j].key[1] == all[i].key[1] &&
+               all[j].key[2] == all[i].key[2])
+            j++;
+        if (j - i > 2) { free(all); return -3; }
+        if (nf >= cap) { free(all); return -5; }
+        const or_face_t* f = &all[i];
+        /* sign of det J of e1 (first-node origin), Leibniz */
+        double J[9];
+        int64_t e = f->e;
+        for (int r = 0; r < dim; r++)
+            for (int c = 0; c < dim; c++)
+                J[r + c * dim] = coords[(int64_t)elems[e * nlb + c + 1] * dim + r] - coords[(int64_t)elems[e * nlb] * dim + r];
+        double det = leibniz(J, dim, NULL);
+        for (int t = 0; t < nv; t++) {
+            int loc = (dim == 3) ? FACE3[f->k][det < 0 ? nv - 1 - t : t] : FACE2[f->k][det < 0 ? nv - 1 - t : t];
+            faces[nf * nv + t] = elems[e * nlb + loc];
+        }
+        fel[nf * 2] = (int32_t)e;
+        fel[nf * 2 + 1] = (j - i == 2) ? (int32_t)all[i + 1].e : -1;
+        nf++;
+        i = j;
+    }
+    free(all);
+    return nf;
+}
+
+/* Points of an integration rule on every cell (section 3.5/3.6, X_ip = amsm(coords3D, ip)):
+ * X[(c*nq + q)*dim + i] = sum_j lam[q*nv + j] * coords[cells[c*nv + j]*dim + i]. */
+int or_simplex_points(int dim, int nv, int64_t nn, const double* coords, int64_t nc, const int32_t* cells, int nq,
+                      const double* lam, double* X) {
+    for (int64_t c = 0; c < nc; c++)
+        for (int q = 0; q < nq; q++)
+            for (int i = 0; i < dim; i++) {
+                double x = 0.0;
+                for (int j = 0; j < nv; j++) {
+                    int64_t v = cells[c * nv + j];
+                    if (v < 0 || v >= nn) return -2;
+                    x += lam[q * nv + j] * coords[v * dim + i];
+                }
+                X[(c * nq + q) * dim + i] = x;
+            }
+    return 0;
+}
+
+/* The GI function (section 3.5): value = sum_c sizes[c] * f_c with f_c = sum_q w_q fip[c, q]
+ * for a scalar (d = 1), or f_c = sum_i n_ci sum_q w_q fip[c, q, i] for a vector field with
+ * normals n (nc x d).  fip: nc x nq x d, component fastest.  Plain sum in cell order. */
+double or_gi(int64_t nc, int nq, int d, const double* fip, const double* w, const double* sizes,
+             const double* normals) {
+    double value = 0.0;
+    for (int64_t c = 0; c < nc; c++) {
+        double fc = 0.0;
+        for (int i = 0; i < d; i++) {
+            double s = 0.0;
+            for (int q = 0; q < nq; q++) s += w[q] * fip[(c * nq + q) * d + i];
+            fc += normals ? normals[c * d + i] * s : s;
+        }
+        value += sizes[c] * fc;
+    }
+    return value;
+}

@@ -742,3 +742,92 @@ def test_bvp_energies_converge_to_closed_forms():
     ratios = errs[:-1] / errs[1:]
     assert np.all(ratios > 3.3) and np.all(ratios < 4.8), (errs, ratios)
     assert np.all(errs[-1] < [0.06, 1e-3, 0.25]), errs[-1]  # h = 1/64: within 0.5%, 1.5%, 0.7%
+
+
+# ----------------------------------------------------------------------------- faces, GI
+@pytest.mark.parametrize("d,m", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2), (3, 3)])
+def test_stroud_rule_exact_on_monomials(d, m):
+    """The collapsed-coordinate rule with m points per direction integrates every monomial
+    of the barycentric coordinates of total degree <= 2m - 1 exactly: the mean of
+    prod lam_i^a_i over the simplex is d! prod a_i! / (sum a_i + d)! (Dirichlet integral)."""
+    lam, w = oracle.stroud_rule(d, m)
+    assert lam.shape == (m ** d, d + 1) and abs(w.sum() - 1) < 1e-15 and np.all(w > 0)
+    assert np.allclose(lam.sum(axis=1), 1.0, atol=1e-15) and np.all(lam >= 0)
+    for ex in itertools.product(range(2 * m), repeat=d + 1):
+        if sum(ex) > 2 * m - 1:
+            continue
+        got = (w * np.prod(lam ** np.array(ex), axis=1)).sum()
+        want = math.factorial(d) * math.prod(math.factorial(a) for a in ex) / math.factorial(sum(ex) + d)
+        assert abs(got - want) < 1e-14, (ex, got, want)
+    # one degree more is not exact for every monomial
+    ex = (0,) * d + (2 * m,)
+    got = (w * lam[:, -1] ** (2 * m)).sum()
+    want = math.factorial(d) * math.factorial(2 * m) / math.factorial(2 * m + d)
+    assert abs(got - want) > 1e-10
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_faces_counts_orientation_and_neighbours(n):
+    """All faces of the Kuhn mesh: the closed-form counts (the section 3.2 normals table at
+    n = 128), boundary faces = the generator's boundary triangles, every face in one or two
+    elements found by brute force, boundary normals outward (sum of area n = 0, flux of x =
+    3 |Omega|), interior normals pointing from e1 into e2."""
+    coords, elems, bfaces = gen.cube_mesh(n, jitter=0.15)
+    F, FE = oracle.faces(coords, elems)
+    c = gen.kuhn_counts(n)
+    assert F.shape[0] == c["faces"] and int((FE[:, 1] < 0).sum()) == c["bfaces"]
+    keys = np.sort(F, axis=1)
+    assert np.all(np.diff(keys[:, 0]) >= 0)  # ascending by the smallest node
+    order = np.lexsort(keys.T[::-1])
+    assert np.array_equal(order, np.arange(F.shape[0]))
+    assert {tuple(k) for k in keys[FE[:, 1] < 0]} == {tuple(sorted(map(int, f))) for f in bfaces}
+    sets = [set(map(int, e)) for e in elems]
+    for k, (e1, e2) in zip(keys, FE):
+        owners = [i for i, s in enumerate(sets) if set(map(int, k)) <= s]
+        assert owners == ([e1] if e2 < 0 else [e1, e2])
+    unit, area, raw = oracle.boundary(coords, F[FE[:, 1] < 0])
+    assert np.allclose((unit * area[:, None]).sum(axis=0), 0.0, atol=1e-13)
+    cent = coords[F[FE[:, 1] < 0]].mean(axis=1)
+    assert abs((cent * unit * area[:, None]).sum() - 3.0) < 1e-12
+    inner = FE[:, 1] >= 0
+    _, _, rawi = oracle.boundary(coords, F[inner])
+    c1 = coords[elems[FE[inner, 0]]].mean(axis=1)
+    c2 = coords[elems[FE[inner, 1]]].mean(axis=1)
+    assert np.all(((c2 - c1) * rawi).sum(axis=1) > 0)
+
+
+def test_faces_2d_edges():
+    coords, elems, bedges = gen.square_mesh(4, jitter=0.2)
+    F, FE = oracle.faces(coords, elems)
+    c = gen.square_counts(4)
+    assert F.shape[0] == c["edges"] and int((FE[:, 1] < 0).sum()) == c["bedges"]
+    b = F[FE[:, 1] < 0]
+    assert {tuple(sorted(map(int, f))) for f in b} == {tuple(sorted(map(int, f))) for f in bedges}
+    unit, area, _ = oracle.boundary(coords, b)
+    mid = coords[b].mean(axis=1)
+    assert abs((mid * unit * area[:, None]).sum() - 2.0) < 1e-12  # flux of x = 2 |Omega|
+
+
+def test_gi_divergence_theorem_exact_rules():
+    """GI (section 3.5): for F = (x1^3 (x2^2 + x3^2)/3, x2^5/5, x2^2 x3^3/3), div F =
+    (x1^2 + x2^2)(x2^2 + x3^2); with rules exact for the degrees (4 in the volume, 5 on
+    the faces) the volume integral of div F over the jittered unit-cube mesh and the flux
+    of F through its boundary both equal the closed form 8/15; the mass of rho = x1^2 + x2^2
+    is 2/3 and its first moment in x1 is 1/4 + 1/6 = 5/12."""
+    coords, elems, _ = gen.cube_mesh(3, jitter=0.15)
+    F, FE = oracle.faces(coords, elems)
+    bf = F[FE[:, 1] < 0]
+    lam3, w3 = oracle.stroud_rule(3, 3)
+    lam2, w2 = oracle.stroud_rule(2, 3)
+    X = oracle.simplex_points(coords, elems, lam3)
+    vol = oracle.p1_elements(coords, elems)["vol"]
+    rho = X[..., 0] ** 2 + X[..., 1] ** 2
+    div = rho * (X[..., 1] ** 2 + X[..., 2] ** 2)
+    assert abs(oracle.gi(div, w3, vol) - 8 / 15) < 1e-13
+    assert abs(oracle.gi(rho, w3, vol) - 2 / 3) < 1e-13
+    assert abs(oracle.gi(rho * X[..., 0], w3, vol) - 5 / 12) < 1e-13
+    Y = oracle.simplex_points(coords, bf, lam2)
+    Fv = np.stack([Y[..., 0] ** 3 * (Y[..., 1] ** 2 + Y[..., 2] ** 2) / 3, Y[..., 1] ** 5 / 5,
+                   Y[..., 1] ** 2 * Y[..., 2] ** 3 / 3], axis=2)
+    unit, area, _ = oracle.boundary(coords, bf)
+    assert abs(oracle.gi(Fv, w2, area, unit) - 8 / 15) < 1e-13
