@@ -21,6 +21,8 @@ Other workloads (one JSON line each, same contract):
                      replayed from a HIP graph, against one launch per group and operation
   --workload energy  load vector (local vectors + node sums) and local energy parts on the
                      128^3 cube mesh, FP32, fields at the 4 points of the degree-2 rule
+  --workload faces   all faces of the 128^3 cube mesh with the normals of all of them, and
+                     GI volume / surface integrals of the divergence theorem
   --workload serve   a Poisson stream of assembly jobs (200 jobs/s, 2-D FP64 / 3-D FP32,
                      1e3..2e6 elements) through the serving loop: p50/p99 latency and
                      throughput, fused + resident structures vs one launch per job without
@@ -85,7 +87,8 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=128, help="cubes per side of the CPU oracle sample")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
-    ap.add_argument("--workload", choices=["assembly", "pages", "batch", "serve", "energy"], default="assembly")
+    ap.add_argument("--workload", choices=["assembly", "pages", "batch", "serve", "energy", "faces"],
+                    default="assembly")
     ap.add_argument("--coef", choices=["one", "quad"], default="one",
                     help="assembly coefficients: c = 1, or c = exp(x1+x2+x3) at the 4 points of the degree-2 rule "
                          "(the paper's section 3.6 benchmark)")
@@ -393,6 +396,139 @@ def run_energy(args):
     print(json.dumps(out))
 
 
+def _collapsed_rule(d, m):
+    """Collapsed-coordinate (conical product) rule on the d-simplex, m Gauss-Jacobi points per
+    direction (exact for degree 2m - 1): barycentric points and weights summing to 1."""
+    import numpy as np
+    from scipy.special import roots_jacobi
+    ax = []
+    for k in range(d):
+        a = d - 1 - k
+        x, wx = roots_jacobi(m, a, 0)
+        ax.append(((1 + x) / 2, wx / 2 ** (a + 1)))
+    pts, wts = [], []
+    for idx in np.ndindex(*([m] * d)):
+        xi, rest, w = [], 1.0, 1.0
+        for k in range(d):
+            u = ax[k][0][idx[k]]
+            xi.append(u * rest)
+            rest *= 1 - u
+            w *= ax[k][1][idx[k]]
+        pts.append([1 - sum(xi)] + xi)
+        wts.append(w)
+    w = np.array(wts)
+    return np.array(pts), w / w.sum()
+
+
+def run_faces(args):
+    """All faces with their normals (section 3.2 normals benchmark) and GI volume / surface
+    integrals (section 3.5) on the 3-D cube mesh."""
+    import numpy as np
+    import torch
+
+    from paper_2404_16039_amd import gen
+    from paper_2404_16039_amd import lib as L
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    n = args.n
+    coords, elems, _ = gen.cube_mesh(n, jitter=0.15, with_faces=False)
+    nn, ne = coords.shape[0], elems.shape[0]
+    tc, te = torch.from_numpy(coords).cuda(), torch.from_numpy(elems).cuda()
+    csr = L.Csr().symbolic(3, nn, te)
+    csr.faces(tc, te)
+    f, fe, bf, be = csr.face_lists()
+    nf, nfb = f.shape[0], bf.shape[0]
+    unit = torch.empty(nf * 3, dtype=torch.float32, device="cuda")
+    area = torch.empty(nf, dtype=torch.float32, device="cuda")
+    _calib_copy(args.copy_calib_mib)
+
+    def normals():  # faces of the mesh and the normals of all of them
+        csr.faces(tc, te, stream=stream)
+        fl = csr.face_lists(stream=stream)[0]
+        L.boundary_normals(L.F32, tc, fl, unit=unit, measure=area, stream=stream)
+
+    t_faces = _timed(lambda: csr.faces(tc, te, stream=stream), args.steps, args.warmup, stream)
+    t_norm = _timed(normals, args.steps, args.warmup, stream)
+    # GI: the moment of inertia of rho = x1^2 + x2^2 about the x1 axis, int rho (x2^2 + x3^2),
+    # by a volume integral (degree-5 rule on the tets) and as the flux of
+    # F = (x1^3 (x2^2 + x3^2)/3, x2^5/5, x2^2 x3^3/3) through the boundary (degree-5 rule on
+    # the faces); both 8/15 on the unit cube
+    lam3, w3 = _collapsed_rule(3, 3)
+    lam2, w2 = _collapsed_rule(2, 3)
+    vol = torch.empty(ne, dtype=torch.float64, device="cuda")
+    L.elem_geometry(L.F64, tc, te, vol=vol)
+    bfc = bf.contiguous()
+    bunit = torch.empty(nfb * 3, dtype=torch.float64, device="cuda")
+    barea = torch.empty(nfb, dtype=torch.float64, device="cuda")
+    L.boundary_normals(L.F64, tc, bfc, unit=bunit, measure=barea)
+    value = torch.empty(1, dtype=torch.float64, device="cuda")
+    work = torch.empty(L.GI_WORK, dtype=torch.float64, device="cuda")
+    X = L.simplex_points(tc, te, lam3)
+    div = ((X[..., 0] ** 2 + X[..., 1] ** 2) * (X[..., 1] ** 2 + X[..., 2] ** 2)).contiguous()
+    t_pts = _timed(lambda: L.simplex_points(tc, te, lam3, stream=stream), 5, 1, stream)
+    t_gi = _timed(lambda: L.gi(L.F64, div, w3, vol, value=value, work=work, stream=stream), args.steps, args.warmup,
+                  stream)
+    i_vol = float(value.item())
+    Y = L.simplex_points(tc, bfc, lam2)
+    Fv = torch.stack([Y[..., 0] ** 3 * (Y[..., 1] ** 2 + Y[..., 2] ** 2) / 3, Y[..., 1] ** 5 / 5,
+                      Y[..., 1] ** 2 * Y[..., 2] ** 3 / 3], dim=2).contiguous()
+    L.gi(L.F64, Fv, w2, barea, normals=bunit, value=value, work=work)
+    i_surf = float(value.item())
+    del X, div
+    nq3 = lam3.shape[0]
+    ms = {"faces (k_faces x 2 + scans)": float(np.mean(t_faces)),
+          "faces + all normals": float(np.mean(t_norm)),
+          "k_simplex_points<3,4> (27 points)": float(np.mean(t_pts)),
+          "k_gi<double> (27 points)": float(np.mean(t_gi))}
+    # algorithmic bytes: faces -- the adjacency words and slot words read once per pass
+    # (2 x 32 B/tet), the faces written (5 x 4 B per face) and the boundary list (4 x 4 B);
+    # points -- element node ids 16 B/tet, coordinates 24 B/node, points 24 B each;
+    # GI -- the values 8 B per point and the volume 8 B per tet
+    alg = {"faces (k_faces x 2 + scans)": 64 * ne + 20 * nf + 16 * nfb,
+           "k_simplex_points<3,4> (27 points)": 16 * ne + 24 * nn + 24 * nq3 * ne,
+           "k_gi<double> (27 points)": 8 * nq3 * ne + 8 * ne}
+    dom = max(alg, key=lambda k: ms[k])
+
+    def roof(k):
+        gbs = alg[k] / (ms[k] * 1e-3) / 1e9
+        return {"kernel": k, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": alg[k],
+                "launch_us": round(ms[k] * 1e3, 1)}
+
+    step_ms = ms["faces + all normals"]
+    out = {
+        "metric": "P1 tet elements/s (all faces with their outward normals and areas)",
+        "value": ne / (step_ms * 1e-3), "unit": "tets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": step_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "3-D P1 tets: unit cube, %d^3 cubes x 6 Kuhn tets, jitter 0.15 h; all faces (sorted, "
+                               "oriented outward of their first element, element pairs, boundary list) and the FP32 "
+                               "normals and areas of all of them; GI volume and surface integrals" % n,
+                   "tets": ne, "nodes": nn, "faces": nf, "boundary_faces": nfb},
+        "kernels_us": {k: round(v * 1e3, 1) for k, v in ms.items()},
+        "gi": {"volume_integral": i_vol, "surface_integral": i_surf, "closed_form": 8 / 15},
+        "roofline": roof(dom),
+        "rooflines": {k: roof(k) for k in alg},
+        "paper_context": {"what": "all-face normals of a 12,582,912-tet sphere mesh (25,264,128 faces) in MATLAB, "
+                                  "mesh generation included, hardware not stated", "s": 10.9},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        cn = args.cpu_n
+        c2, e2, _ = gen.cube_mesh(cn, jitter=0.15, with_faces=False)
+        t1 = time.perf_counter()
+        F2, FE2 = oracle.faces(c2, e2)
+        oracle.boundary(c2, F2)
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": e2.shape[0] / dt, "unit": "tets/s", "cores": 1, "kind": "oracle",
+                               "sample": "FP64 oracle: all faces by sorting the element faces, then the normals and "
+                                         "areas of all faces, single thread, %d^3 Kuhn mesh, %d tets, %.1f s"
+                                         % (cn, e2.shape[0], dt)}
+    csr.close()
+    print(json.dumps(out))
+
+
 def run_serve(args):
     """Poisson stream of assembly jobs through the serving loop."""
     import numpy as np
@@ -502,6 +638,8 @@ def main():
         return run_serve(args)
     if args.workload == "energy":
         return run_energy(args)
+    if args.workload == "faces":
+        return run_faces(args)
 
     import numpy as np
     import torch

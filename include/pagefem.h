@@ -236,6 +236,49 @@ pf_status pf_assemble_quad(const pf_csr* csr, pf_dtype prec, const double* coord
                            const void* cKq, const void* cMq, void* valsK, void* valsM,
                            const pf_fallback* fb, int64_t* d_counters, void* stream);
 
+/* All faces of the mesh whose structure `csr` holds (section 3.2: the normals of all faces,
+ * internal ones included, or of the boundary faces only); elems: the connectivity it was
+ * built from.  A face is the set of dim nodes of an element minus one node; faces are
+ * listed in ascending order of their sorted node ids, each once, with its nodes ordered so
+ * that the normal of pf_boundary_normals points out of its first element e1 (the smaller
+ * element id; the orientation follows the sign of e1's det J) and the element pair
+ * (e1, e2), e2 = -1 on the boundary.  The boundary faces, in the same order, also form a
+ * list of their own (the section 3.5 facesB) with their elements.  Built from the
+ * structure's adjacency and row patterns inside the handle; synchronises `stream` once
+ * (the counts size the lists).  PF_EINVAL if a face belongs to more than two elements,
+ * PF_ELIMIT if a node owns more than 256 faces.  A later pf_csr_symbolic invalidates it. */
+pf_status pf_csr_faces(pf_csr* csr, const double* coords, const int32_t* elems, void* stream);
+
+/* The face lists of pf_csr_faces: counts on the host, device pointers owned by the handle:
+ * faces nf x dim, fel nf x 2 (e1, e2), bfaces nfb x dim, bel nfb (the element of each
+ * boundary face).  Any output may be NULL. */
+pf_status pf_csr_faces_info(const pf_csr* csr, int64_t* nf, int64_t* nfb, const int32_t** faces,
+                            const int32_t** fel, const int32_t** bfaces, const int32_t** bel);
+
+/* ----------------------------------------------------------------------------------
+ * Integration over cells (sections 3.5, 3.6): points of a rule and the GI function.
+ * A rule is nq barycentric points lam (host, nq x nv, row-major) with weights w (host, nq)
+ * summing to 1; at most PF_RULE_MAX points.
+ * ---------------------------------------------------------------------------------- */
+#define PF_RULE_MAX 64
+#define PF_GI_WORK 2048
+
+/* Points of a rule on every cell (X_ip = amsm(coords3D, ip)): cells are nc simplices of nv
+ * nodes each (nv = dim + 1 elements, nv = dim boundary faces, ...), int32 row-major;
+ * X (device, FP64) receives nc x nq x dim values, X[(c*nq + q)*dim + i] =
+ * sum_j lam[q*nv + j] coords[cells[c*nv + j]*dim + i]; a cell with a bad node gets NaN. */
+pf_status pf_simplex_points(int dim, int nv, int64_t nn, const double* coords, int64_t nc,
+                            const int32_t* cells, int nq, const double* lam, double* X, void* stream);
+
+/* The GI function (section 3.5): value = sum_c sizes[c] f_c with
+ * f_c = sum_i normals[c*d + i] sum_q w_q fip[(c*nq + q)*d + i] (normals nullable: the plain
+ * sum over the d components, d = 1 for a scalar), i.e. the integral of a scalar function or
+ * the flux of a vector field through oriented cells.  fip, sizes, normals: device, type prec;
+ * value: device, one FP64; work: device scratch of PF_GI_WORK doubles.  Sums in FP64 in a
+ * fixed order (deterministic). */
+pf_status pf_gi(pf_dtype prec, int64_t nc, int nq, int d, const void* fip, const double* w,
+                const void* sizes, const void* normals, double* value, double* work, void* stream);
+
 /* Load vector (section 3.6, right-hand side listing) of the mesh whose structure `csr`
  * holds; elems: the connectivity it was built from (ne x (dim+1), device).  For every
  * element, b2D[e*nlb + j] = |det J_e| sum_q w_q f_eq phi_j(x_q) over the points of the rule

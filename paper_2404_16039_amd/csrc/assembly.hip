@@ -43,6 +43,14 @@ struct pf_csr {
     int64_t* bsum = nullptr;  // scan workspace
     int64_t* info = nullptr;  // [0] error bits, [1] adjacency total, [2] nnz, [3..6] block stats
     void* work = nullptr;     // workspace of the energy reductions (pf_energies)
+    // faces (pf_csr_faces): per-row counts and their scans, the lists, and the totals
+    int32_t *fcount = nullptr, *bcount = nullptr, *fptr = nullptr, *bptr = nullptr;
+    int32_t *faces = nullptr, *fel = nullptr, *bfaces = nullptr, *bel = nullptr;
+    int64_t* finfo = nullptr;  // [0] error bits, [1] faces, [2] boundary faces
+    int64_t nf = 0, nfb = 0;
+    bool faces_built = false;
+    int64_t cap_fcount = 0, cap_bcount = 0, cap_fptr = 0, cap_bptr = 0, cap_faces = 0, cap_fel = 0,
+            cap_bfaces = 0, cap_bel = 0, cap_finfo = 0;
     int64_t cap_adj_len = 0, cap_row_ptr = 0, cap_cnt = 0, cap_adj = 0, cap_pk = 0, cap_nnz = 0, cap_bsum = 0,
             cap_info = 0, cap_colpad = 0, cap_work = 0;
     bool built = false;
@@ -493,6 +501,208 @@ __global__ __launch_bounds__(RT) void k_compact(int64_t nn, const int32_t* __res
     for (int w = threadIdx.x; w < W; w += RT) {
         const int r = upper_pos(rp, nr, w0 + w);
         col_idx[w0 + w] = colpad[(r0 + r) * MAXROW + (w0 + w - rp[r])];
+    }
+}
+
+// ---------------------------------------------------------------------------- faces
+// All faces of the mesh (section 3.2: normals of all faces, or of the boundary faces only),
+// grouped by their smallest node.  Node i owns the faces of its adjacent elements whose
+// other nodes all come after i, i.e. lie after the diagonal in row i of the CSR structure;
+// the packed slot words give those positions without a gather, so inside its row a face is
+// keyed by the column positions of its other nodes, and ascending keys are ascending node
+// ids.  Two passes over blocks of FR rows: pass 0 counts each row's faces and boundary
+// faces (for the scans), pass 1 rebuilds the same tables and writes every face at its
+// place -- nodes ordered outward of its first element (the smaller element id), the pair
+// of elements, and the boundary faces in a list of their own.
+constexpr int FR = 8;              // rows per block
+constexpr int FT = 128;            // threads per block
+constexpr int FSUB = 256;          // slots of one row's face table (at most 3 x 64 candidates)
+constexpr int64_t ERR_FACE = 8;    // a face in more than two elements
+static_assert(FT >= FR && FT >= 64, "one thread per row");
+
+__device__ __forceinline__ int fsub_hash(int32_t k) {
+    return static_cast<int>((static_cast<uint32_t>(k) * 2654435761u) >> 24);  // 8 bits
+}
+static_assert(FSUB == 256, "fsub_hash yields 8 bits");
+
+// find or insert k in a row's face table (one compare-and-swap per probe); -1 when full
+__device__ __forceinline__ int fsub_insert(int32_t* tab, int32_t k, bool& fresh) {
+    int h = fsub_hash(k);
+#pragma unroll 1
+    for (int probe = 0; probe < FSUB; ++probe) {
+        const int32_t cur = atomicCAS(tab + h, -1, k);
+        if (cur == -1 || cur == k) {
+            fresh = cur == -1;
+            return h;
+        }
+        h = (h + 1) & (FSUB - 1);
+    }
+    fresh = false;
+    return -1;
+}
+
+// local node order of the face opposite local node k, outward for a positively oriented
+// element (det J > 0, first-node origin); reversed when det J < 0
+__device__ __forceinline__ int face_local(int nlb, int k, int t) {
+    if (nlb == 4) {
+        constexpr int F3[4][3] = {{1, 2, 3}, {0, 3, 2}, {0, 1, 3}, {0, 2, 1}};
+        return F3[k][t];
+    }
+    constexpr int F2[3][2] = {{1, 2}, {2, 0}, {0, 1}};
+    return F2[k][t];
+}
+
+template <int NLB, int PASS>
+__global__ __launch_bounds__(FT) void k_faces(int64_t nn, const double* __restrict__ coords,
+                                              const int32_t* __restrict__ elems, const int32_t* __restrict__ row_ptr,
+                                              const int32_t* __restrict__ col_idx, const int32_t* __restrict__ adj_len,
+                                              const int32_t* __restrict__ adj, const uint32_t* __restrict__ pk,
+                                              int32_t* __restrict__ fcount, int32_t* __restrict__ bcount,
+                                              const int32_t* __restrict__ fptr, const int32_t* __restrict__ bptr,
+                                              int32_t* __restrict__ faces, int32_t* __restrict__ fel,
+                                              int32_t* __restrict__ bfaces, int32_t* __restrict__ bel,
+                                              int64_t* __restrict__ info) {
+    constexpr int NV = NLB - 1;  // nodes of a face = other nodes of an element
+    __shared__ int32_t key[FR * FSUB];
+    __shared__ int32_t cnt[FR * FSUB];
+    __shared__ uint32_t emin[FR * FSUB], emax[FR * FSUB];  // element << 2 | opposite local node
+    __shared__ int16_t list[FR * FSUB];                     // used slots of each row
+    __shared__ int32_t nlist[FR], dslot[FR], alen[FR];
+    __shared__ int32_t maxl;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * FR;
+    const int nr = static_cast<int>((r0 + FR < nn) ? FR : nn - r0);
+    for (int h = threadIdx.x; h < FR * FSUB; h += FT) {
+        key[h] = -1;
+        cnt[h] = 0;
+        emin[h] = 0xffffffffu;
+        emax[h] = 0u;
+    }
+    if (threadIdx.x == 0) maxl = 0;
+    __syncthreads();
+    if (threadIdx.x < FR) {
+        const int r = threadIdx.x;
+        const int64_t i = r0 + r;
+        const int L = r < nr ? min(adj_len[i], MAXADJ) : 0;
+        alen[r] = L;
+        nlist[r] = 0;
+        int d = 0;
+        if (L > 0) {  // column position of the diagonal: the row's columns are ascending
+            const int32_t b = row_ptr[i], n = row_ptr[i + 1] - b;
+            int lo = 0, hi = n;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (col_idx[b + mid] < i) lo = mid + 1;
+                else hi = mid;
+            }
+            d = lo;
+            atomicMax(&maxl, L);
+        }
+        dslot[r] = d;
+    }
+    __syncthreads();
+    bool bad = false, full = false;
+    // entries dealt r + FR j: the faces each one owns go into its row's table
+    for (int idx = threadIdx.x; idx < FR * maxl; idx += FT) {
+        const int r = idx % FR, j = idx / FR;
+        if (j >= alen[r]) continue;
+        const int64_t t = (r0 + r) * MAXADJ + j;
+        const int32_t w = adj[t];
+        const uint32_t p = pk[t];
+        const uint32_t e = static_cast<uint32_t>(w) >> 2;
+        const int a = w & 3;
+        int s[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) s[k] = static_cast<int>((p >> (2 + 8 * k)) & 255);
+        int32_t* tab = key + r * FSUB;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {  // the face opposite the k-th other node
+            int smin = 1 << 20, smax = -1;
+#pragma unroll
+            for (int k2 = 0; k2 < NV; ++k2) {
+                if (k2 == k) continue;
+                smin = min(smin, s[k2]);
+                smax = max(smax, s[k2]);
+            }
+            if (smin <= dslot[r]) continue;  // a node before the row's own: another row owns it
+            const int32_t kk = NV == 3 ? (smin << 6) | smax : smin;
+            bool fresh;
+            const int h = fsub_insert(tab, kk, fresh);
+            if (h < 0) {
+                full = true;
+                continue;
+            }
+            if (fresh) list[r * FSUB + atomicAdd(&nlist[r], 1)] = static_cast<int16_t>(h);
+            atomicAdd(&cnt[r * FSUB + h], 1);
+            const int opp = k < a ? k : k + 1;  // local index of the opposite node
+            const uint32_t word = (e << 2) | static_cast<uint32_t>(opp);
+            atomicMin(&emin[r * FSUB + h], word);
+            atomicMax(&emax[r * FSUB + h], word);
+        }
+    }
+    __syncthreads();
+    if constexpr (PASS == 0) {
+        if (threadIdx.x < nr) {
+            const int r = threadIdx.x;
+            int nb = 0;
+            for (int u = 0; u < nlist[r]; ++u) {
+                const int c = cnt[r * FSUB + list[r * FSUB + u]];
+                nb += c == 1;
+                bad = bad || c > 2;
+            }
+            fcount[r0 + r] = nlist[r];
+            bcount[r0 + r] = nb;
+        }
+        if (bad || full)
+            atomicOr(reinterpret_cast<unsigned long long*>(info),
+                     static_cast<unsigned long long>((bad ? ERR_FACE : 0) | (full ? ERR_ROW : 0)));
+    } else {
+        // every used slot of every row: its rank by key among the row's faces (and among the
+        // row's boundary faces), then the face itself
+        for (int q = threadIdx.x; q < FR * FSUB; q += FT) {
+            const int r = q / FSUB, u = q % FSUB;
+            if (u >= nlist[r]) continue;
+            const int h = list[r * FSUB + u];
+            const int32_t kk = key[r * FSUB + h];
+            const int c = cnt[r * FSUB + h];
+            int rank = 0, brank = 0;
+            for (int v = 0; v < nlist[r]; ++v) {
+                const int h2 = list[r * FSUB + v];
+                const bool before = key[r * FSUB + h2] < kk;
+                rank += before;
+                brank += before && cnt[r * FSUB + h2] == 1;
+            }
+            const int64_t i = r0 + r;
+            const uint32_t w1 = emin[r * FSUB + h];
+            const int64_t e1 = w1 >> 2;
+            const int opp = static_cast<int>(w1 & 3);
+            int nd[NLB];
+#pragma unroll
+            for (int k = 0; k < NLB; ++k) nd[k] = elems[e1 * NLB + k];
+            // sign of det J of e1 (first-node origin), FP64
+            double ev[NV][NV];
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+#pragma unroll
+                for (int c2 = 0; c2 < NV; ++c2)
+                    ev[k][c2] = coords[static_cast<int64_t>(nd[k + 1]) * NV + c2] - coords[static_cast<int64_t>(nd[0]) * NV + c2];
+            double det;
+            if constexpr (NV == 3)
+                det = ev[0][0] * (ev[1][1] * ev[2][2] - ev[1][2] * ev[2][1]) -
+                      ev[0][1] * (ev[1][0] * ev[2][2] - ev[1][2] * ev[2][0]) +
+                      ev[0][2] * (ev[1][0] * ev[2][1] - ev[1][1] * ev[2][0]);
+            else
+                det = ev[0][0] * ev[1][1] - ev[0][1] * ev[1][0];
+            const int64_t f = fptr[i] + rank;
+#pragma unroll
+            for (int t = 0; t < NV; ++t) {
+                const int v = nd[face_local(NLB, opp, det < 0.0 ? NV - 1 - t : t)];
+                faces[f * NV + t] = v;
+                if (c == 1) bfaces[(bptr[i] + brank) * NV + t] = v;
+            }
+            fel[2 * f] = static_cast<int32_t>(e1);
+            fel[2 * f + 1] = c == 2 ? static_cast<int32_t>(emax[r * FSUB + h] >> 2) : -1;
+            if (c == 1) bel[bptr[i] + brank] = static_cast<int32_t>(e1);
+        }
     }
 }
 
@@ -1032,7 +1242,9 @@ pf_status numeric_launch_many(int dim, pf_dtype prec, int nr, const NumericJob* 
 
 size_t csr_bytes(const pf_csr* c) {
     return static_cast<size_t>(c->cap_adj_len + c->cap_row_ptr + c->cap_cnt + c->cap_adj + c->cap_nnz + c->cap_colpad) * 4 +
-           static_cast<size_t>(c->cap_pk) * 4 + static_cast<size_t>(c->cap_bsum + c->cap_info + c->cap_work) * 8;
+           static_cast<size_t>(c->cap_pk) * 4 + static_cast<size_t>(c->cap_bsum + c->cap_info + c->cap_work) * 8 +
+           static_cast<size_t>(c->cap_fcount + c->cap_bcount + c->cap_fptr + c->cap_bptr + c->cap_faces + c->cap_fel +
+                               c->cap_bfaces + c->cap_bel) * 4 + static_cast<size_t>(c->cap_finfo) * 8;
 }
 
 int64_t csr_nnz(const pf_csr* c) { return c->built ? c->nnz : -1; }
@@ -1077,6 +1289,8 @@ void pf_csr_destroy(pf_csr* c) {
     (void)hipFree(c->bsum);
     (void)hipFree(c->info);
     (void)hipFree(c->work);
+    for (int32_t* q : {c->fcount, c->bcount, c->fptr, c->bptr, c->faces, c->fel, c->bfaces, c->bel}) (void)hipFree(q);
+    (void)hipFree(c->finfo);
     delete c;
 }
 
@@ -1133,6 +1347,7 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     if (ne > 0 && !elems) return fail(PF_EINVAL, "pf_csr_symbolic: null elems");
     hipStream_t s = as_stream(stream);
     c->built = false;
+    c->faces_built = false;
     const int64_t m = ne * nlb;
     pf_status st;
     if ((st = collect_stage_times(c))) return st;  // the previous call's events are reused below
@@ -1224,6 +1439,75 @@ pf_status pf_assemble_quad(const pf_csr* c, pf_dtype prec, const double* coords,
                        : numeric_dispatch_quad<2, float, 3>(c, coords, cKq, cMq, valsK, valsM, f, d_counters, s);
     return qn == 1 ? numeric_dispatch_quad<2, double, 1>(c, coords, cKq, cMq, valsK, valsM, f, d_counters, s)
                    : numeric_dispatch_quad<2, double, 3>(c, coords, cKq, cMq, valsK, valsM, f, d_counters, s);
+}
+
+pf_status pf_csr_faces(pf_csr* c, const double* coords, const int32_t* elems, void* stream) {
+    if (!c) return fail(PF_EINVAL, "pf_csr_faces: null handle");
+    if (!c->built) return fail(PF_ESTATE, "pf_csr_faces: structure not built");
+    if (c->ne > 0 && (!coords || !elems)) return fail(PF_EINVAL, "pf_csr_faces: null coords or elems");
+    hipStream_t s = as_stream(stream);
+    c->faces_built = false;
+    const int64_t nn = c->nn;
+    pf_status st;
+    if ((st = grow(c->fcount, c->cap_fcount, nn + 1))) return st;
+    if ((st = grow(c->bcount, c->cap_bcount, nn + 1))) return st;
+    if ((st = grow(c->fptr, c->cap_fptr, nn + 1))) return st;
+    if ((st = grow(c->bptr, c->cap_bptr, nn + 1))) return st;
+    if ((st = grow(c->finfo, c->cap_finfo, 4))) return st;
+    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, c->finfo, int64_t(4), int64_t(0));
+    const unsigned g = static_cast<unsigned>(std::max<int64_t>(ceil_div(nn, FR), 1));
+    if (nn > 0) {
+        if (c->nlb == 4)
+            hipLaunchKernelGGL((k_faces<4, 0>), dim3(g), dim3(FT), 0, s, nn, coords, elems, c->row_ptr, c->col_idx,
+                               c->adj_len, c->adj, c->pk, c->fcount, c->bcount, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, nullptr, c->finfo);
+        else
+            hipLaunchKernelGGL((k_faces<3, 0>), dim3(g), dim3(FT), 0, s, nn, coords, elems, c->row_ptr, c->col_idx,
+                               c->adj_len, c->adj, c->pk, c->fcount, c->bcount, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, nullptr, c->finfo);
+    }
+    if ((st = scan(c->fcount, nn, c->fptr, c->bsum, c->finfo + 1, s))) return st;
+    if ((st = scan(c->bcount, nn, c->bptr, c->bsum, c->finfo + 2, s))) return st;
+    int64_t info[4];
+    PF_HIP_TRY(hipMemcpyAsync(info, c->finfo, sizeof(info), hipMemcpyDeviceToHost, s));
+    PF_HIP_TRY(hipStreamSynchronize(s));
+    if (info[0] & ERR_FACE)
+        return fail(PF_EINVAL, "pf_csr_faces: a face belongs to more than two elements (not a conforming mesh)");
+    if (info[0] & ERR_ROW) return fail(PF_ELIMIT, "pf_csr_faces: a node owns more than 256 faces");
+    const int64_t nf = info[1], nfb = info[2];
+    const int nv = c->dim;
+    if ((st = grow(c->faces, c->cap_faces, nf * nv))) return st;
+    if ((st = grow(c->fel, c->cap_fel, 2 * nf))) return st;
+    if ((st = grow(c->bfaces, c->cap_bfaces, nfb * nv))) return st;
+    if ((st = grow(c->bel, c->cap_bel, nfb))) return st;
+    if (nn > 0 && nf > 0) {
+        if (c->nlb == 4)
+            hipLaunchKernelGGL((k_faces<4, 1>), dim3(g), dim3(FT), 0, s, nn, coords, elems, c->row_ptr, c->col_idx,
+                               c->adj_len, c->adj, c->pk, nullptr, nullptr, c->fptr, c->bptr, c->faces, c->fel,
+                               c->bfaces, c->bel, c->finfo);
+        else
+            hipLaunchKernelGGL((k_faces<3, 1>), dim3(g), dim3(FT), 0, s, nn, coords, elems, c->row_ptr, c->col_idx,
+                               c->adj_len, c->adj, c->pk, nullptr, nullptr, c->fptr, c->bptr, c->faces, c->fel,
+                               c->bfaces, c->bel, c->finfo);
+    }
+    if ((st = launch_check("pf_csr_faces"))) return st;
+    c->nf = nf;
+    c->nfb = nfb;
+    c->faces_built = true;
+    return PF_OK;
+}
+
+pf_status pf_csr_faces_info(const pf_csr* c, int64_t* nf, int64_t* nfb, const int32_t** faces, const int32_t** fel,
+                            const int32_t** bfaces, const int32_t** bel) {
+    if (!c) return fail(PF_EINVAL, "pf_csr_faces_info: null handle");
+    if (!c->faces_built) return fail(PF_ESTATE, "pf_csr_faces_info: faces not built");
+    if (nf) *nf = c->nf;
+    if (nfb) *nfb = c->nfb;
+    if (faces) *faces = c->faces;
+    if (fel) *fel = c->fel;
+    if (bfaces) *bfaces = c->bfaces;
+    if (bel) *bel = c->bel;
+    return PF_OK;
 }
 
 pf_status pf_csr_info(const pf_csr* c, int64_t* nn, int64_t* nnz, const int32_t** row_ptr, const int32_t** col_idx) {

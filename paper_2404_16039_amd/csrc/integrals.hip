@@ -1,0 +1,131 @@
+// integrals.hip -- integration points of a rule on every cell and the GI function
+// (sections 3.5 and 3.6: X_ip = amsm(coords3D, ip) and GI(fip, w, sizes, normals)).
+//
+// A rule is given by the caller as barycentric points (nq x nv) and weights summing to 1,
+// so any order the caller needs (the paper's Gauss_points for a chosen gqo) runs through
+// the same kernels; both travel as kernel arguments (at most PF_RULE_MAX points).
+// GI reduces in FP64 over a fixed grid: every block sums its cells in a fixed order, one
+// block adds the block sums in block order, so the value is deterministic.
+#include "common.hpp"
+
+#include <string>
+
+namespace pf {
+
+constexpr int IBS = 256;
+
+struct Rule {
+    double lam[PF_RULE_MAX * 4];
+    double w[PF_RULE_MAX];
+};
+
+// X[(c nq + q) dim + i] = sum_j lam_qj coords[cells[c nv + j] dim + i]; NaN for a bad node
+template <int DIM, int NV>
+__global__ __launch_bounds__(IBS) void k_simplex_points(int64_t nn, const double* __restrict__ coords, int64_t nc,
+                                                        const int32_t* __restrict__ cells, int nq, Rule rule,
+                                                        double* __restrict__ X) {
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * IBS + threadIdx.x;
+    if (c >= nc) return;
+    double p[NV][DIM];
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        const int32_t v = cells[c * NV + j];
+        ok = ok && v >= 0 && v < nn;
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) p[j][i] = ok ? coords[static_cast<int64_t>(v) * DIM + i] : 0.0;
+    }
+    for (int q = 0; q < nq; ++q)
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) {
+            double x = rule.lam[q * NV] * p[0][i];
+#pragma unroll
+            for (int j = 1; j < NV; ++j) x = __builtin_fma(rule.lam[q * NV + j], p[j][i], x);
+            X[(c * nq + q) * DIM + i] = ok ? x : static_cast<double>(NAN);
+        }
+}
+
+// block sums of sizes[c] * f_c, f_c = sum_i n_ci sum_q w_q fip[c, q, i] (n = 1 without normals)
+template <typename T>
+__global__ __launch_bounds__(IBS) void k_gi(int64_t nc, int nq, int d, const T* __restrict__ fip, Rule rule,
+                                            const T* __restrict__ sizes, const T* __restrict__ normals,
+                                            double* __restrict__ part) {
+    __shared__ double red[IBS / 64];
+    double sum = 0.0;
+    for (int64_t c = static_cast<int64_t>(blockIdx.x) * IBS + threadIdx.x; c < nc;
+         c += static_cast<int64_t>(gridDim.x) * IBS) {
+        double fc = 0.0;
+        for (int i = 0; i < d; ++i) {
+            double s = 0.0;
+            for (int q = 0; q < nq; ++q) s = __builtin_fma(rule.w[q], static_cast<double>(fip[(c * nq + q) * d + i]), s);
+            fc = normals ? __builtin_fma(static_cast<double>(normals[c * d + i]), s, fc) : fc + s;
+        }
+        sum = __builtin_fma(static_cast<double>(sizes[c]), fc, sum);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < IBS / 64; ++w) s += red[w];
+        part[blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_gi_total(const double* __restrict__ part, int nblocks, double* __restrict__ value) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 64) s += part[b];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (threadIdx.x == 0) *value = s;
+}
+
+}  // namespace pf
+
+using namespace pf;
+
+pf_status pf_simplex_points(int dim, int nv, int64_t nn, const double* coords, int64_t nc, const int32_t* cells,
+                            int nq, const double* lam, double* X, void* stream) {
+    if (dim != 2 && dim != 3) return fail(PF_EORDER, "pf_simplex_points: dim must be 2 or 3");
+    if (nv < 2 || nv > dim + 1) return fail(PF_EINVAL, "pf_simplex_points: nv must be 2..dim+1");
+    if (nq < 1 || nq > PF_RULE_MAX) return fail(PF_EINVAL, "pf_simplex_points: nq must be 1..PF_RULE_MAX");
+    if (nn < 0 || nc < 0) return fail(PF_EINVAL, "pf_simplex_points: negative size");
+    if (nc == 0) return PF_OK;
+    if (!coords || !cells || !lam || !X) return fail(PF_EINVAL, "pf_simplex_points: null argument");
+    Rule rule{};
+    for (int i = 0; i < nq * nv; ++i) rule.lam[i] = lam[i];
+    hipStream_t s = as_stream(stream);
+    const unsigned g = static_cast<unsigned>(ceil_div(nc, IBS));
+    if (dim == 3) {
+        if (nv == 4) hipLaunchKernelGGL((k_simplex_points<3, 4>), dim3(g), dim3(IBS), 0, s, nn, coords, nc, cells, nq, rule, X);
+        else if (nv == 3) hipLaunchKernelGGL((k_simplex_points<3, 3>), dim3(g), dim3(IBS), 0, s, nn, coords, nc, cells, nq, rule, X);
+        else hipLaunchKernelGGL((k_simplex_points<3, 2>), dim3(g), dim3(IBS), 0, s, nn, coords, nc, cells, nq, rule, X);
+    } else {
+        if (nv == 3) hipLaunchKernelGGL((k_simplex_points<2, 3>), dim3(g), dim3(IBS), 0, s, nn, coords, nc, cells, nq, rule, X);
+        else hipLaunchKernelGGL((k_simplex_points<2, 2>), dim3(g), dim3(IBS), 0, s, nn, coords, nc, cells, nq, rule, X);
+    }
+    return launch_check("pf_simplex_points");
+}
+
+pf_status pf_gi(pf_dtype prec, int64_t nc, int nq, int d, const void* fip, const double* w, const void* sizes,
+                const void* normals, double* value, double* work, void* stream) {
+    if (prec != PF_F32 && prec != PF_F64) return fail(PF_EDTYPE, "pf_gi: prec must be PF_F32 or PF_F64");
+    if (nq < 1 || nq > PF_RULE_MAX) return fail(PF_EINVAL, "pf_gi: nq must be 1..PF_RULE_MAX");
+    if (d < 1 || d > 3) return fail(PF_EINVAL, "pf_gi: d must be 1..3");
+    if (nc < 0) return fail(PF_EINVAL, "pf_gi: negative size");
+    if (!w || !value || !work) return fail(PF_EINVAL, "pf_gi: null w, value or work");
+    if (nc > 0 && (!fip || !sizes)) return fail(PF_EINVAL, "pf_gi: null fip or sizes");
+    Rule rule{};
+    for (int q = 0; q < nq; ++q) rule.w[q] = w[q];
+    hipStream_t s = as_stream(stream);
+    const int grid = static_cast<int>(std::max<int64_t>(std::min<int64_t>(ceil_div(nc, IBS), PF_GI_WORK), 1));
+    if (prec == PF_F32)
+        hipLaunchKernelGGL(k_gi<float>, dim3(grid), dim3(IBS), 0, s, nc, nq, d, static_cast<const float*>(fip), rule,
+                           static_cast<const float*>(sizes), static_cast<const float*>(normals), work);
+    else
+        hipLaunchKernelGGL(k_gi<double>, dim3(grid), dim3(IBS), 0, s, nc, nq, d, static_cast<const double*>(fip), rule,
+                           static_cast<const double*>(sizes), static_cast<const double*>(normals), work);
+    hipLaunchKernelGGL(k_gi_total, dim3(1), dim3(64), 0, s, work, grid, value);
+    return launch_check("pf_gi");
+}

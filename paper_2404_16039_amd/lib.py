@@ -133,6 +133,11 @@ _sig = {
     "pf_boundary_normals": ([I32, I32, I64, P, I64, P, P, P, P], C.c_int),
     "pf_quad_points": ([I32, I32, I64, P, I64, P, P, P], C.c_int),
     "pf_assemble_quad": ([P, I32, P, I32, P, P, P, P, FP, P, P], C.c_int),
+    "pf_csr_faces": ([P, P, P, P], C.c_int),
+    "pf_csr_faces_info": ([P, C.POINTER(I64), C.POINTER(I64), C.POINTER(P), C.POINTER(P), C.POINTER(P),
+                           C.POINTER(P)], C.c_int),
+    "pf_simplex_points": ([I32, I32, I64, P, I64, P, I32, P, P, P], C.c_int),
+    "pf_gi": ([I32, I64, I32, I32, P, P, P, P, P, P, P], C.c_int),
     "pf_rhs": ([P, I32, P, P, I32, P, P, P, FP, P, P], C.c_int),
     "pf_energies": ([P, I32, P, P, I32, P, P, P, P, P, P, FP, P, P], C.c_int),
     "pf_csr_create": ([C.POINTER(P)], C.c_int),
@@ -311,6 +316,7 @@ class Csr:
     def symbolic(self, dim, nn, elems, stream=None):
         if elems.dtype != torch.int32 or not elems.is_contiguous():
             raise ValueError("elems must be contiguous int32")
+        self._dim = int(dim)
         _chk(_lib.pf_csr_symbolic(self._h, int(dim), int(nn), elems.shape[0], _p(elems), _s(stream)),
              "pf_csr_symbolic")
         return self
@@ -354,6 +360,26 @@ class Csr:
         _chk(_lib.pf_assemble_quad(self._h, prec, _p(coords), int(order), _p(cKq), _p(cMq), _p(valsK), _p(valsM),
                                    _ref(fb, Fallback), _p(counters), _s(stream)), "pf_assemble_quad")
 
+    def faces(self, coords, elems, stream=None):
+        """Build the face lists (all faces, boundary faces) of the structure's mesh."""
+        _chk(_lib.pf_csr_faces(self._h, _p(coords), _p(elems), _s(stream)), "pf_csr_faces")
+        return self
+
+    def face_lists(self, stream=None):
+        """Copies of (faces, fel, bfaces, bel) as int32 device tensors."""
+        nf, nfb = I64(), I64()
+        f, fe, bf, be = P(), P(), P(), P()
+        _chk(_lib.pf_csr_faces_info(self._h, C.byref(nf), C.byref(nfb), C.byref(f), C.byref(fe), C.byref(bf),
+                                    C.byref(be)), "pf_csr_faces_info")
+        dim = self._dim
+        out = []
+        for ptr, n in ((f, nf.value * dim), (fe, 2 * nf.value), (bf, nfb.value * dim), (be, nfb.value)):
+            t = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")[:n]
+            if n:
+                _memcpy_d2d(t.data_ptr(), ptr.value, 4 * n, stream)
+            out.append(t)
+        return (out[0].view(-1, dim), out[1].view(-1, 2), out[2].view(-1, dim), out[3])
+
     def rhs(self, prec, coords, elems, order, fq, b2D, b=None, fb=None, counters=None, stream=None):
         """Load vector: local vectors into b2D (ne x nlb) and, if b is given, their node sums."""
         _chk(_lib.pf_rhs(self._h, prec, _p(coords), _p(elems), int(order), _p(fq), _p(b2D), _p(b),
@@ -375,6 +401,36 @@ class Csr:
             self.close()
         except Exception:
             pass
+
+
+RULE_MAX = 64
+GI_WORK = 2048
+
+
+def simplex_points(coords, cells, lam, stream=None):
+    """Points of the rule with barycentric points lam (nq x nv) on every cell: (nc, nq, dim) FP64."""
+    import numpy as np
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    nc, nv = cells.shape
+    nq = lam.shape[0]
+    dim = coords.shape[1]
+    X = torch.empty((nc, nq, dim), dtype=torch.float64, device="cuda")
+    _chk(_lib.pf_simplex_points(dim, nv, coords.shape[0], _p(coords), nc, _p(cells), nq,
+                                lam.ctypes.data_as(P), _p(X), _s(stream)), "pf_simplex_points")
+    return X
+
+
+def gi(prec, fip, w, sizes, normals=None, value=None, work=None, stream=None):
+    """The GI function; returns the device FP64 scalar tensor `value`."""
+    import numpy as np
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    nc, nq = fip.shape[0], fip.shape[1]
+    d = fip.shape[2] if fip.dim() == 3 else 1
+    value = value if value is not None else torch.empty(1, dtype=torch.float64, device="cuda")
+    work = work if work is not None else torch.empty(GI_WORK, dtype=torch.float64, device="cuda")
+    _chk(_lib.pf_gi(prec, nc, nq, d, _p(fip), w.ctypes.data_as(P), _p(sizes), _p(normals), _p(value), _p(work),
+                    _s(stream)), "pf_gi")
+    return value
 
 
 # ----------------------------------------------------------------------- batch plans
