@@ -46,6 +46,8 @@ KERNEL_SOURCES = ["assembly.hip", "p1elem.hpp", "smallmat.hpp", "common.hpp", "e
 BATCH_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "batch_plan_64groups_traffic.json")
 ENERGY_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "energy_cube128_traffic.json")
 ENERGY_SOURCES = ["energy.hip", "p1elem.hpp", "smallmat.hpp", "common.hpp", "exact.hpp", "quadrature.hpp"]
+FACES_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "faces_cube128_traffic.json")
+FACES_SOURCES = ["assembly.hip", "integrals.hip", "common.hpp"]
 BATCH_SOURCES = ["batch.hip", "smallmat.hpp", "common.hpp"]
 
 
@@ -492,9 +494,12 @@ def run_faces(args):
 
     def roof(k):
         gbs = alg[k] / (ms[k] * 1e-3) / 1e9
+        tk = {"k_simplex_points<3,4> (27 points)": ["k_simplex_points<3,4>"], "k_gi<double> (27 points)": ["k_gi<double>"],
+              "faces (k_faces x 2 + scans)": ["k_faces<4,0>", "k_faces<4,1>"]}[k]
+        tr = [traffic_of(FACES_TRAFFIC_FILE, FACES_SOURCES, kernel=x, n=n) for x in tk]
         return {"kernel": k, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": gbs / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": alg[k],
-                "launch_us": round(ms[k] * 1e3, 1)}
+                "frac": gbs / HBM_PEAK_GBS, "traffic": None if None in tr else sum(tr),
+                "algorithmic_bytes_per_launch": alg[k], "launch_us": round(ms[k] * 1e3, 1)}
 
     step_ms = ms["faces + all normals"]
     out = {

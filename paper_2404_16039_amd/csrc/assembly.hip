@@ -44,13 +44,15 @@ struct pf_csr {
     int64_t* info = nullptr;  // [0] error bits, [1] adjacency total, [2] nnz, [3..6] block stats
     void* work = nullptr;     // workspace of the energy reductions (pf_energies)
     // faces (pf_csr_faces): per-row counts and their scans, the lists, and the totals
+    int32_t* dpos = nullptr;   // column position of each row's diagonal
+    uint8_t* esign = nullptr;  // orientation of every element (1: det J < 0)
     int32_t *fcount = nullptr, *bcount = nullptr, *fptr = nullptr, *bptr = nullptr;
     int32_t *faces = nullptr, *fel = nullptr, *bfaces = nullptr, *bel = nullptr;
     int64_t* finfo = nullptr;  // [0] error bits, [1] faces, [2] boundary faces
     int64_t nf = 0, nfb = 0;
     bool faces_built = false;
     int64_t cap_fcount = 0, cap_bcount = 0, cap_fptr = 0, cap_bptr = 0, cap_faces = 0, cap_fel = 0,
-            cap_bfaces = 0, cap_bel = 0, cap_finfo = 0;
+            cap_bfaces = 0, cap_bel = 0, cap_finfo = 0, cap_dpos = 0, cap_esign = 0;
     int64_t cap_adj_len = 0, cap_row_ptr = 0, cap_cnt = 0, cap_adj = 0, cap_pk = 0, cap_nnz = 0, cap_bsum = 0,
             cap_info = 0, cap_colpad = 0, cap_work = 0;
     bool built = false;
@@ -335,7 +337,8 @@ template <int NLB>
 __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __restrict__ elems,
                                                 const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
                                                 int32_t* __restrict__ rowlen, int32_t* __restrict__ colpad,
-                                                uint32_t* __restrict__ pk, int64_t* __restrict__ info) {
+                                                uint32_t* __restrict__ pk, int32_t* __restrict__ dpos,
+                                                int64_t* __restrict__ info) {
     constexpr int NO = NLB - 1;               // other nodes of an element
     __shared__ int32_t tab[RR * RSUB];       // node ids, -1 empty
     __shared__ int32_t seg[RR * MAXROW];      // each row's nodes, insertion order
@@ -357,6 +360,7 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
         const int L = r < nr ? min(adj_len[r0 + r], MAXADJ) : 0;  // longer rows raised an error already
         alen[r] = L;
         cnt[r] = 0;
+        if (r < nr && L == 0) dpos[r0 + r] = 0;  // a node of no element has an empty row
         if (L > 0) {  // the diagonal
             const int32_t self = static_cast<int32_t>(r0 + r);
             const int h = rsub_hash(self);
@@ -467,6 +471,7 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
         }
         for (; j < n; ++j) rank += sr[j] < v;
         slot_rank[r * RSUB + seg_h[r * MAXROW + p]] = static_cast<uint8_t>(rank);
+        if (p == 0) dpos[r0 + r] = rank;  // item 0 is the row's own node
         colpad[(r0 + r) * MAXROW + rank] = v;
     }
     __syncthreads();
@@ -516,14 +521,14 @@ __global__ __launch_bounds__(RT) void k_compact(int64_t nn, const int32_t* __res
 // of elements, and the boundary faces in a list of their own.
 constexpr int FR = 8;              // rows per block
 constexpr int FT = 128;            // threads per block
-constexpr int FSUB = 256;          // slots of one row's face table (at most 3 x 64 candidates)
+constexpr int FSUB = 128;          // slots of one row's face table (faces a node owns, at most 128)
 constexpr int64_t ERR_FACE = 8;    // a face in more than two elements
 static_assert(FT >= FR && FT >= 64, "one thread per row");
 
 __device__ __forceinline__ int fsub_hash(int32_t k) {
-    return static_cast<int>((static_cast<uint32_t>(k) * 2654435761u) >> 24);  // 8 bits
+    return static_cast<int>((static_cast<uint32_t>(k) * 2654435761u) >> 25);  // 7 bits
 }
-static_assert(FSUB == 256, "fsub_hash yields 8 bits");
+static_assert(FSUB == 128, "fsub_hash yields 7 bits");
 
 // find or insert k in a row's face table (one compare-and-swap per probe); -1 when full
 __device__ __forceinline__ int fsub_insert(int32_t* tab, int32_t k, bool& fresh) {
@@ -552,11 +557,35 @@ __device__ __forceinline__ int face_local(int nlb, int k, int t) {
     return F2[k][t];
 }
 
+// orientation of every element: esign[e] = 1 when det J < 0 (FP64, first-node origin)
+template <int NLB>
+__global__ __launch_bounds__(SBS) void k_elem_sign(int64_t ne, const double* __restrict__ coords,
+                                                   const int32_t* __restrict__ elems, uint8_t* __restrict__ esign) {
+    constexpr int D = NLB - 1;
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * SBS + threadIdx.x;
+    if (e >= ne) return;
+    double ev[D][D];
+    const int64_t n0 = elems[e * NLB];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const int64_t nk = elems[e * NLB + k + 1];
+#pragma unroll
+        for (int c = 0; c < D; ++c) ev[k][c] = coords[nk * D + c] - coords[n0 * D + c];
+    }
+    double det;
+    if constexpr (D == 3)
+        det = ev[0][0] * (ev[1][1] * ev[2][2] - ev[1][2] * ev[2][1]) - ev[0][1] * (ev[1][0] * ev[2][2] - ev[1][2] * ev[2][0]) +
+              ev[0][2] * (ev[1][0] * ev[2][1] - ev[1][1] * ev[2][0]);
+    else
+        det = ev[0][0] * ev[1][1] - ev[0][1] * ev[1][0];
+    esign[e] = det < 0.0 ? 1 : 0;
+}
+
 template <int NLB, int PASS>
-__global__ __launch_bounds__(FT) void k_faces(int64_t nn, const double* __restrict__ coords,
-                                              const int32_t* __restrict__ elems, const int32_t* __restrict__ row_ptr,
+__global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restrict__ row_ptr,
                                               const int32_t* __restrict__ col_idx, const int32_t* __restrict__ adj_len,
                                               const int32_t* __restrict__ adj, const uint32_t* __restrict__ pk,
+                                              const int32_t* __restrict__ dpos, const uint8_t* __restrict__ esign,
                                               int32_t* __restrict__ fcount, int32_t* __restrict__ bcount,
                                               const int32_t* __restrict__ fptr, const int32_t* __restrict__ bptr,
                                               int32_t* __restrict__ faces, int32_t* __restrict__ fel,
@@ -565,42 +594,32 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const double* __restri
     constexpr int NV = NLB - 1;  // nodes of a face = other nodes of an element
     __shared__ int32_t key[FR * FSUB];
     __shared__ int32_t cnt[FR * FSUB];
-    __shared__ uint32_t emin[FR * FSUB], emax[FR * FSUB];  // element << 2 | opposite local node
-    __shared__ int16_t list[FR * FSUB];                     // used slots of each row
-    __shared__ int32_t nlist[FR], dslot[FR], alen[FR];
+    // element << 32 | slot word of its entry | opposite local node << 26: the smallest and the
+    // largest element of each face, with what it takes to name the face's nodes
+    __shared__ unsigned long long wmin[FR * FSUB], wmax[FR * FSUB];
+    __shared__ int16_t list[FR * FSUB];  // used slots of each row
+    __shared__ int32_t nlist[FR], dslot[FR], alen[FR], lpre[FR + 1];
     __shared__ int32_t maxl;
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * FR;
     const int nr = static_cast<int>((r0 + FR < nn) ? FR : nn - r0);
     for (int h = threadIdx.x; h < FR * FSUB; h += FT) {
         key[h] = -1;
         cnt[h] = 0;
-        emin[h] = 0xffffffffu;
-        emax[h] = 0u;
+        wmin[h] = ~0ull;
+        wmax[h] = 0ull;
     }
     if (threadIdx.x == 0) maxl = 0;
-    __syncthreads();
     if (threadIdx.x < FR) {
         const int r = threadIdx.x;
-        const int64_t i = r0 + r;
-        const int L = r < nr ? min(adj_len[i], MAXADJ) : 0;
+        const int L = r < nr ? min(adj_len[r0 + r], MAXADJ) : 0;
         alen[r] = L;
         nlist[r] = 0;
-        int d = 0;
-        if (L > 0) {  // column position of the diagonal: the row's columns are ascending
-            const int32_t b = row_ptr[i], n = row_ptr[i + 1] - b;
-            int lo = 0, hi = n;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (col_idx[b + mid] < i) lo = mid + 1;
-                else hi = mid;
-            }
-            d = lo;
-            atomicMax(&maxl, L);
-        }
-        dslot[r] = d;
+        dslot[r] = L > 0 ? dpos[r0 + r] : 0;
     }
     __syncthreads();
-    bool bad = false, full = false;
+    if (threadIdx.x < FR) atomicMax(&maxl, alen[threadIdx.x]);
+    __syncthreads();
+    bool full = false;
     // entries dealt r + FR j: the faces each one owns go into its row's table
     for (int idx = threadIdx.x; idx < FR * maxl; idx += FT) {
         const int r = idx % FR, j = idx / FR;
@@ -608,7 +627,7 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const double* __restri
         const int64_t t = (r0 + r) * MAXADJ + j;
         const int32_t w = adj[t];
         const uint32_t p = pk[t];
-        const uint32_t e = static_cast<uint32_t>(w) >> 2;
+        const unsigned long long e = static_cast<uint32_t>(w) >> 2;
         const int a = w & 3;
         int s[NV];
 #pragma unroll
@@ -634,13 +653,14 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const double* __restri
             if (fresh) list[r * FSUB + atomicAdd(&nlist[r], 1)] = static_cast<int16_t>(h);
             atomicAdd(&cnt[r * FSUB + h], 1);
             const int opp = k < a ? k : k + 1;  // local index of the opposite node
-            const uint32_t word = (e << 2) | static_cast<uint32_t>(opp);
-            atomicMin(&emin[r * FSUB + h], word);
-            atomicMax(&emax[r * FSUB + h], word);
+            const unsigned long long word = (e << 32) | (static_cast<unsigned long long>(opp) << 26) | (p & 0x3ffffffu);
+            atomicMin(&wmin[r * FSUB + h], word);
+            atomicMax(&wmax[r * FSUB + h], word);
         }
     }
     __syncthreads();
     if constexpr (PASS == 0) {
+        bool bad = false;
         if (threadIdx.x < nr) {
             const int r = threadIdx.x;
             int nb = 0;
@@ -656,12 +676,19 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const double* __restri
             atomicOr(reinterpret_cast<unsigned long long*>(info),
                      static_cast<unsigned long long>((bad ? ERR_FACE : 0) | (full ? ERR_ROW : 0)));
     } else {
-        // every used slot of every row: its rank by key among the row's faces (and among the
-        // row's boundary faces), then the face itself
-        for (int q = threadIdx.x; q < FR * FSUB; q += FT) {
-            const int r = q / FSUB, u = q % FSUB;
-            if (u >= nlist[r]) continue;
-            const int h = list[r * FSUB + u];
+        if (threadIdx.x == 0) {  // the block's faces, row after row
+            int acc = 0;
+            for (int r = 0; r < FR; ++r) {
+                lpre[r] = acc;
+                acc += nlist[r];
+            }
+            lpre[FR] = acc;
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < lpre[FR]; q += FT) {
+            int r = 0;
+            while (q >= lpre[r + 1]) ++r;
+            const int h = list[r * FSUB + (q - lpre[r])];
             const int32_t kk = key[r * FSUB + h];
             const int c = cnt[r * FSUB + h];
             int rank = 0, brank = 0;
@@ -672,36 +699,27 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const double* __restri
                 brank += before && cnt[r * FSUB + h2] == 1;
             }
             const int64_t i = r0 + r;
-            const uint32_t w1 = emin[r * FSUB + h];
-            const int64_t e1 = w1 >> 2;
-            const int opp = static_cast<int>(w1 & 3);
-            int nd[NLB];
-#pragma unroll
-            for (int k = 0; k < NLB; ++k) nd[k] = elems[e1 * NLB + k];
-            // sign of det J of e1 (first-node origin), FP64
-            double ev[NV][NV];
-#pragma unroll
-            for (int k = 0; k < NV; ++k)
-#pragma unroll
-                for (int c2 = 0; c2 < NV; ++c2)
-                    ev[k][c2] = coords[static_cast<int64_t>(nd[k + 1]) * NV + c2] - coords[static_cast<int64_t>(nd[0]) * NV + c2];
-            double det;
-            if constexpr (NV == 3)
-                det = ev[0][0] * (ev[1][1] * ev[2][2] - ev[1][2] * ev[2][1]) -
-                      ev[0][1] * (ev[1][0] * ev[2][2] - ev[1][2] * ev[2][0]) +
-                      ev[0][2] * (ev[1][0] * ev[2][1] - ev[1][1] * ev[2][0]);
-            else
-                det = ev[0][0] * ev[1][1] - ev[0][1] * ev[1][0];
+            const unsigned long long w1 = wmin[r * FSUB + h];
+            const int64_t e1 = static_cast<int64_t>(w1 >> 32);
+            const int opp = static_cast<int>((w1 >> 26) & 3);
+            const uint32_t p1 = static_cast<uint32_t>(w1 & 0x3ffffffu);
+            const int a1 = static_cast<int>(p1 & 3);  // local index of node i in e1
+            const bool flip = esign[e1] != 0;
+            const int32_t rb = row_ptr[i];
             const int64_t f = fptr[i] + rank;
+            const int64_t fb = c == 1 ? bptr[i] + brank : -1;
 #pragma unroll
             for (int t = 0; t < NV; ++t) {
-                const int v = nd[face_local(NLB, opp, det < 0.0 ? NV - 1 - t : t)];
+                const int L = face_local(NLB, opp, flip ? NV - 1 - t : t);  // local node of e1
+                // node i itself, or the k-th other node of e1 at its column position in row i
+                const int32_t v = L == a1 ? static_cast<int32_t>(i)
+                                          : col_idx[rb + static_cast<int>((p1 >> (2 + 8 * (L < a1 ? L : L - 1))) & 255)];
                 faces[f * NV + t] = v;
-                if (c == 1) bfaces[(bptr[i] + brank) * NV + t] = v;
+                if (fb >= 0) bfaces[fb * NV + t] = v;
             }
             fel[2 * f] = static_cast<int32_t>(e1);
-            fel[2 * f + 1] = c == 2 ? static_cast<int32_t>(emax[r * FSUB + h] >> 2) : -1;
-            if (c == 1) bel[bptr[i] + brank] = static_cast<int32_t>(e1);
+            fel[2 * f + 1] = c == 2 ? static_cast<int32_t>(wmax[r * FSUB + h] >> 32) : -1;
+            if (fb >= 0) bel[fb] = static_cast<int32_t>(e1);
         }
     }
 }
@@ -1244,7 +1262,8 @@ size_t csr_bytes(const pf_csr* c) {
     return static_cast<size_t>(c->cap_adj_len + c->cap_row_ptr + c->cap_cnt + c->cap_adj + c->cap_nnz + c->cap_colpad) * 4 +
            static_cast<size_t>(c->cap_pk) * 4 + static_cast<size_t>(c->cap_bsum + c->cap_info + c->cap_work) * 8 +
            static_cast<size_t>(c->cap_fcount + c->cap_bcount + c->cap_fptr + c->cap_bptr + c->cap_faces + c->cap_fel +
-                               c->cap_bfaces + c->cap_bel) * 4 + static_cast<size_t>(c->cap_finfo) * 8;
+                               c->cap_bfaces + c->cap_bel + c->cap_dpos) * 4 + static_cast<size_t>(c->cap_finfo) * 8 +
+           static_cast<size_t>(c->cap_esign);
 }
 
 int64_t csr_nnz(const pf_csr* c) { return c->built ? c->nnz : -1; }
@@ -1289,7 +1308,9 @@ void pf_csr_destroy(pf_csr* c) {
     (void)hipFree(c->bsum);
     (void)hipFree(c->info);
     (void)hipFree(c->work);
-    for (int32_t* q : {c->fcount, c->bcount, c->fptr, c->bptr, c->faces, c->fel, c->bfaces, c->bel}) (void)hipFree(q);
+    for (int32_t* q : {c->fcount, c->bcount, c->fptr, c->bptr, c->faces, c->fel, c->bfaces, c->bel, c->dpos})
+        (void)hipFree(q);
+    (void)hipFree(c->esign);
     (void)hipFree(c->finfo);
     delete c;
 }
@@ -1367,14 +1388,15 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
         hipLaunchKernelGGL(k_scatter, dim3(gtile), dim3(AG_BS), 0, s, elems, m, nlb, nn, c->adj_len, c->adj, c->info);
     const unsigned grows = static_cast<unsigned>(ceil_div(nn, RR));
     if ((st = grow(c->colpad, c->cap_colpad, nn * MAXROW))) return st;
+    if ((st = grow(c->dpos, c->cap_dpos, nn + 1))) return st;
     if ((st = mark(c, 1, s))) return st;
     if (nn > 0) {
         if (nlb == 4)
             hipLaunchKernelGGL((k_pattern<4>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
-                               c->colpad, c->pk, c->info);
+                               c->colpad, c->pk, c->dpos, c->info);
         else
             hipLaunchKernelGGL((k_pattern<3>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
-                               c->colpad, c->pk, c->info);
+                               c->colpad, c->pk, c->dpos, c->info);
     }
     if ((st = mark(c, 2, s))) return st;
     if ((st = scan(c->cnt, nn, c->row_ptr, c->bsum, c->info + 2, s))) return st;
@@ -1454,17 +1476,23 @@ pf_status pf_csr_faces(pf_csr* c, const double* coords, const int32_t* elems, vo
     if ((st = grow(c->fptr, c->cap_fptr, nn + 1))) return st;
     if ((st = grow(c->bptr, c->cap_bptr, nn + 1))) return st;
     if ((st = grow(c->finfo, c->cap_finfo, 4))) return st;
+    if ((st = grow(c->esign, c->cap_esign, std::max<int64_t>(c->ne, 1)))) return st;
     hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, c->finfo, int64_t(4), int64_t(0));
+    if (c->ne > 0) {
+        const unsigned ge = static_cast<unsigned>(ceil_div(c->ne, SBS));
+        if (c->nlb == 4) hipLaunchKernelGGL((k_elem_sign<4>), dim3(ge), dim3(SBS), 0, s, c->ne, coords, elems, c->esign);
+        else hipLaunchKernelGGL((k_elem_sign<3>), dim3(ge), dim3(SBS), 0, s, c->ne, coords, elems, c->esign);
+    }
     const unsigned g = static_cast<unsigned>(std::max<int64_t>(ceil_div(nn, FR), 1));
     if (nn > 0) {
         if (c->nlb == 4)
-            hipLaunchKernelGGL((k_faces<4, 0>), dim3(g), dim3(FT), 0, s, nn, coords, elems, c->row_ptr, c->col_idx,
-                               c->adj_len, c->adj, c->pk, c->fcount, c->bcount, nullptr, nullptr, nullptr, nullptr,
-                               nullptr, nullptr, c->finfo);
+            hipLaunchKernelGGL((k_faces<4, 0>), dim3(g), dim3(FT), 0, s, nn, c->row_ptr, c->col_idx, c->adj_len,
+                               c->adj, c->pk, c->dpos, c->esign, c->fcount, c->bcount, nullptr, nullptr, nullptr,
+                               nullptr, nullptr, nullptr, c->finfo);
         else
-            hipLaunchKernelGGL((k_faces<3, 0>), dim3(g), dim3(FT), 0, s, nn, coords, elems, c->row_ptr, c->col_idx,
-                               c->adj_len, c->adj, c->pk, c->fcount, c->bcount, nullptr, nullptr, nullptr, nullptr,
-                               nullptr, nullptr, c->finfo);
+            hipLaunchKernelGGL((k_faces<3, 0>), dim3(g), dim3(FT), 0, s, nn, c->row_ptr, c->col_idx, c->adj_len,
+                               c->adj, c->pk, c->dpos, c->esign, c->fcount, c->bcount, nullptr, nullptr, nullptr,
+                               nullptr, nullptr, nullptr, c->finfo);
     }
     if ((st = scan(c->fcount, nn, c->fptr, c->bsum, c->finfo + 1, s))) return st;
     if ((st = scan(c->bcount, nn, c->bptr, c->bsum, c->finfo + 2, s))) return st;
@@ -1473,7 +1501,7 @@ pf_status pf_csr_faces(pf_csr* c, const double* coords, const int32_t* elems, vo
     PF_HIP_TRY(hipStreamSynchronize(s));
     if (info[0] & ERR_FACE)
         return fail(PF_EINVAL, "pf_csr_faces: a face belongs to more than two elements (not a conforming mesh)");
-    if (info[0] & ERR_ROW) return fail(PF_ELIMIT, "pf_csr_faces: a node owns more than 256 faces");
+    if (info[0] & ERR_ROW) return fail(PF_ELIMIT, "pf_csr_faces: a node owns more than 128 faces");
     const int64_t nf = info[1], nfb = info[2];
     const int nv = c->dim;
     if ((st = grow(c->faces, c->cap_faces, nf * nv))) return st;
@@ -1482,13 +1510,13 @@ pf_status pf_csr_faces(pf_csr* c, const double* coords, const int32_t* elems, vo
     if ((st = grow(c->bel, c->cap_bel, nfb))) return st;
     if (nn > 0 && nf > 0) {
         if (c->nlb == 4)
-            hipLaunchKernelGGL((k_faces<4, 1>), dim3(g), dim3(FT), 0, s, nn, coords, elems, c->row_ptr, c->col_idx,
-                               c->adj_len, c->adj, c->pk, nullptr, nullptr, c->fptr, c->bptr, c->faces, c->fel,
-                               c->bfaces, c->bel, c->finfo);
+            hipLaunchKernelGGL((k_faces<4, 1>), dim3(g), dim3(FT), 0, s, nn, c->row_ptr, c->col_idx, c->adj_len,
+                               c->adj, c->pk, c->dpos, c->esign, nullptr, nullptr, c->fptr, c->bptr, c->faces,
+                               c->fel, c->bfaces, c->bel, c->finfo);
         else
-            hipLaunchKernelGGL((k_faces<3, 1>), dim3(g), dim3(FT), 0, s, nn, coords, elems, c->row_ptr, c->col_idx,
-                               c->adj_len, c->adj, c->pk, nullptr, nullptr, c->fptr, c->bptr, c->faces, c->fel,
-                               c->bfaces, c->bel, c->finfo);
+            hipLaunchKernelGGL((k_faces<3, 1>), dim3(g), dim3(FT), 0, s, nn, c->row_ptr, c->col_idx, c->adj_len,
+                               c->adj, c->pk, c->dpos, c->esign, nullptr, nullptr, c->fptr, c->bptr, c->faces,
+                               c->fel, c->bfaces, c->bel, c->finfo);
     }
     if ((st = launch_check("pf_csr_faces"))) return st;
     c->nf = nf;

@@ -4,8 +4,8 @@
 // A rule is given by the caller as barycentric points (nq x nv) and weights summing to 1,
 // so any order the caller needs (the paper's Gauss_points for a chosen gqo) runs through
 // the same kernels; both travel as kernel arguments (at most PF_RULE_MAX points).
-// GI reduces in FP64 over a fixed grid: every block sums its cells in a fixed order, one
-// block adds the block sums in block order, so the value is deterministic.
+// GI reduces in FP64 over a fixed grid: every block sums its share of the values in a fixed
+// order, one block adds the block sums in block order, so the value is deterministic.
 #include "common.hpp"
 
 #include <string>
@@ -19,48 +19,76 @@ struct Rule {
     double w[PF_RULE_MAX];
 };
 
-// X[(c nq + q) dim + i] = sum_j lam_qj coords[cells[c nv + j] dim + i]; NaN for a bad node
+// X[(c nq + q) dim + i] = sum_j lam_qj coords[cells[c nv + j] dim + i]; NaN for a bad node.
+// A block makes PB consecutive (cell, point) pairs: each lane computes pairs into LDS, then
+// the block writes its contiguous run of PB x dim values with consecutive lanes on
+// consecutive words (coalesced); the lanes of one cell read its node coordinates from the
+// same cache lines.
+constexpr int PB = 512;
 template <int DIM, int NV>
 __global__ __launch_bounds__(IBS) void k_simplex_points(int64_t nn, const double* __restrict__ coords, int64_t nc,
                                                         const int32_t* __restrict__ cells, int nq, Rule rule,
                                                         double* __restrict__ X) {
-    const int64_t c = static_cast<int64_t>(blockIdx.x) * IBS + threadIdx.x;
-    if (c >= nc) return;
-    double p[NV][DIM];
-    bool ok = true;
+    __shared__ double buf[PB * DIM];
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * PB;
+    const int64_t total = nc * nq;
+    const int np = static_cast<int>(total - base < PB ? total - base : PB);
+    for (int u = threadIdx.x; u < np; u += IBS) {
+        const int64_t t = base + u;
+        const int64_t c = t / nq;
+        const int q = static_cast<int>(t - c * nq);
+        double x[DIM];
+        bool ok = true;
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        const int32_t v = cells[c * NV + j];
-        ok = ok && v >= 0 && v < nn;
+        for (int j = 0; j < NV; ++j) {
+            const int32_t v = cells[c * NV + j];
+            ok = ok && v >= 0 && v < nn;
+            const double l = rule.lam[q * NV + j];
 #pragma unroll
-        for (int i = 0; i < DIM; ++i) p[j][i] = ok ? coords[static_cast<int64_t>(v) * DIM + i] : 0.0;
-    }
-    for (int q = 0; q < nq; ++q)
-#pragma unroll
-        for (int i = 0; i < DIM; ++i) {
-            double x = rule.lam[q * NV] * p[0][i];
-#pragma unroll
-            for (int j = 1; j < NV; ++j) x = __builtin_fma(rule.lam[q * NV + j], p[j][i], x);
-            X[(c * nq + q) * DIM + i] = ok ? x : static_cast<double>(NAN);
+            for (int i = 0; i < DIM; ++i) {
+                const double p = ok ? coords[static_cast<int64_t>(v) * DIM + i] : 0.0;
+                x[i] = j == 0 ? l * p : __builtin_fma(l, p, x[i]);
+            }
         }
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) buf[u * DIM + i] = ok ? x[i] : static_cast<double>(NAN);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < np * DIM; k += IBS) X[base * DIM + k] = buf[k];
 }
 
-// block sums of sizes[c] * f_c, f_c = sum_i n_ci sum_q w_q fip[c, q, i] (n = 1 without normals)
+// Block sums of sizes[c] * f_c, f_c = sum_i n_ci sum_q w_q fip[c, q, i] (n = 1 without
+// normals), reading fip as one flat array: value k of the grid-strided sweep belongs to cell
+// k / (nq d) at position r = k mod (nq d); each lane advances (cell, r) by fixed steps, so
+// consecutive lanes read consecutive values with no division in the loop.
 template <typename T>
 __global__ __launch_bounds__(IBS) void k_gi(int64_t nc, int nq, int d, const T* __restrict__ fip, Rule rule,
                                             const T* __restrict__ sizes, const T* __restrict__ normals,
                                             double* __restrict__ part) {
+    __shared__ double wr[PF_RULE_MAX * 3];  // weight of position r: w[r / d]
     __shared__ double red[IBS / 64];
+    const int nqd = nq * d;
+    for (int r = threadIdx.x; r < nqd; r += IBS) wr[r] = rule.w[r / d];
+    __syncthreads();
+    const int64_t total = nc * nqd;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * IBS;
+    int64_t k = static_cast<int64_t>(blockIdx.x) * IBS + threadIdx.x;
+    int64_t c = k / nqd;
+    int r = static_cast<int>(k - c * nqd);
+    const int64_t dc = stride / nqd;
+    const int dr = static_cast<int>(stride - dc * nqd);
     double sum = 0.0;
-    for (int64_t c = static_cast<int64_t>(blockIdx.x) * IBS + threadIdx.x; c < nc;
-         c += static_cast<int64_t>(gridDim.x) * IBS) {
-        double fc = 0.0;
-        for (int i = 0; i < d; ++i) {
-            double s = 0.0;
-            for (int q = 0; q < nq; ++q) s = __builtin_fma(rule.w[q], static_cast<double>(fip[(c * nq + q) * d + i]), s);
-            fc = normals ? __builtin_fma(static_cast<double>(normals[c * d + i]), s, fc) : fc + s;
+    for (; k < total; k += stride) {
+        const int i = r % d;
+        double v = wr[r] * static_cast<double>(fip[k]) * static_cast<double>(sizes[c]);
+        if (normals) v *= static_cast<double>(normals[c * d + i]);
+        sum += v;
+        c += dc;
+        r += dr;
+        if (r >= nqd) {
+            r -= nqd;
+            ++c;
         }
-        sum = __builtin_fma(static_cast<double>(sizes[c]), fc, sum);
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, 64);
@@ -96,7 +124,7 @@ pf_status pf_simplex_points(int dim, int nv, int64_t nn, const double* coords, i
     Rule rule{};
     for (int i = 0; i < nq * nv; ++i) rule.lam[i] = lam[i];
     hipStream_t s = as_stream(stream);
-    const unsigned g = static_cast<unsigned>(ceil_div(nc, IBS));
+    const unsigned g = static_cast<unsigned>(ceil_div(nc * nq, PB));
     if (dim == 3) {
         if (nv == 4) hipLaunchKernelGGL((k_simplex_points<3, 4>), dim3(g), dim3(IBS), 0, s, nn, coords, nc, cells, nq, rule, X);
         else if (nv == 3) hipLaunchKernelGGL((k_simplex_points<3, 3>), dim3(g), dim3(IBS), 0, s, nn, coords, nc, cells, nq, rule, X);
@@ -119,7 +147,7 @@ pf_status pf_gi(pf_dtype prec, int64_t nc, int nq, int d, const void* fip, const
     Rule rule{};
     for (int q = 0; q < nq; ++q) rule.w[q] = w[q];
     hipStream_t s = as_stream(stream);
-    const int grid = static_cast<int>(std::max<int64_t>(std::min<int64_t>(ceil_div(nc, IBS), PF_GI_WORK), 1));
+    const int grid = static_cast<int>(std::max<int64_t>(std::min<int64_t>(ceil_div(nc * nq * d, IBS), PF_GI_WORK), 1));
     if (prec == PF_F32)
         hipLaunchKernelGGL(k_gi<float>, dim3(grid), dim3(IBS), 0, s, nc, nq, d, static_cast<const float*>(fip), rule,
                            static_cast<const float*>(sizes), static_cast<const float*>(normals), work);
