@@ -60,6 +60,8 @@ def _load():
         lib.or_simplex_points.argtypes = [INT, INT, I64, P, I64, P, INT, P, P]
         lib.or_gi.argtypes = [I64, INT, INT, P, P, P, P]
         lib.or_gi.restype = D
+        lib.or_p2_elements.argtypes = [INT, I64, P, I64, P, INT, P, P, P, INT, P, P, P, P, P, P, P]
+        lib.or_p2_elements.restype = I64
         lib.or_route_predicate.argtypes = [INT, P, I64, D, D, P, P]
         lib.or_assemble.argtypes = [INT, I64, I64, P, P, P, P, P, P, P, P, P, P, I64]
         lib.or_assemble.restype = I64
@@ -290,6 +292,24 @@ def gi(fip, w, sizes, normals=None):
     d = fip.shape[2] if fip.ndim == 3 else 1
     nrm = None if normals is None else _f64(np.asarray(normals).reshape(nc, d))
     return float(_load().or_gi(nc, nq, d, _p(fip), _p(_f64(w)), _p(_f64(sizes)), _p(nrm)))
+
+
+def p2_elements(coords, elems2, ruleK, ruleM, cK=None, cM=None):
+    """P2 element matrices K3D, M3D (ne, nlb2*nlb2, column-major pages) and their error
+    scales, for rules (lam, w) with weights summing to 1 and coefficients (ne, nq) or None."""
+    coords = _f64(coords)
+    elems2 = _i32(elems2)
+    nn, dim = coords.shape
+    ne, nlb2 = elems2.shape
+    lamK, wK = (_f64(x) for x in ruleK)
+    lamM, wM = (_f64(x) for x in ruleM)
+    ck = None if cK is None else _f64(np.asarray(cK).reshape(ne, lamK.shape[0]))
+    cm = None if cM is None else _f64(np.asarray(cM).reshape(ne, lamM.shape[0]))
+    K, M, Ka, Ma = (np.empty((ne, nlb2 * nlb2)) for _ in range(4))
+    rc = _load().or_p2_elements(dim, nn, _p(coords), ne, _p(elems2), lamK.shape[0], _p(lamK), _p(wK), _p(ck),
+                                lamM.shape[0], _p(lamM), _p(wM), _p(cm), _p(K), _p(M), _p(Ka), _p(Ma))
+    _check(rc, "p2_elements")
+    return {"K3D": K, "M3D": M, "Kabs": Ka, "Mabs": Ma, "nsingular": int(rc)}
 
 
 def stroud_rule(d, m):

@@ -812,3 +812,105 @@ double or_gi(int64_t nc, int nq, int d, const double* fip, const double* w, cons
     }
     return value;
 }
+
+/* P2 element matrices (section 3.6, stiffness_matrixP2 / mass_matrixP2) of straight-sided
+ * triangles (dim 2) and tetrahedra (dim 3).  Local nodes: the nlb1 = dim + 1 vertices, then
+ * the midpoints of the local edges (0,1), (0,2), (1,2) (2-D) or (0,1), (0,2), (0,3), (1,2),
+ * (1,3), (2,3) (3-D).  Basis in barycentric coordinates: vertex i: lam_i (2 lam_i - 1),
+ * edge (i,j): 4 lam_i lam_j; gradients from grad lam = the P1 gradients of or_p1_elements.
+ * With |T| the element measure and rules (lamK, wK), (lamM, wM) whose weights sum to 1:
+ *   K3D[e, a, b] = |T| sum_q wK_q cK[e, q] grad phi_a(x_q) . grad phi_b(x_q),
+ *   M3D[e, a, b] = |T| sum_q wM_q cM[e, q] phi_a(x_q) phi_b(x_q)
+ * (column-major nlb2 x nlb2 pages; cK, cM NULL = 1), and the error scales with |cK|,
+ * |grad phi_a| |grad phi_b| and |cM| |phi_a phi_b|.  Returns the number of singular
+ * Jacobians, or -1 / -2. */
+static void p2_basis(int dim, const double* lam, double* phi) {
+    int nlb1 = dim + 1, t = nlb1;
+    for (int i = 0; i < nlb1; i++) phi[i] = lam[i] * (2.0 * lam[i] - 1.0);
+    for (int i = 0; i < nlb1; i++)
+        for (int j = i + 1; j < nlb1; j++) phi[t++] = 4.0 * lam[i] * lam[j];
+}
+
+static void p2_grads(int dim, const double* lam, const double* glam /* dim x nlb1, col-major */, double* gphi) {
+    int nlb1 = dim + 1, t = nlb1;
+    for (int i = 0; i < nlb1; i++)
+        for (int r = 0; r < dim; r++) gphi[r + i * dim] = (4.0 * lam[i] - 1.0) * glam[r + i * dim];
+    for (int i = 0; i < nlb1; i++)
+        for (int j = i + 1; j < nlb1; j++, t++)
+            for (int r = 0; r < dim; r++) gphi[r + t * dim] = 4.0 * (lam[i] * glam[r + j * dim] + lam[j] * glam[r + i * dim]);
+}
+
+int64_t or_p2_elements(int dim, int64_t nn, const double* coords, int64_t ne, const int32_t* elems, int nqK,
+                       const double* lamK, const double* wK, const double* cK, int nqM, const double* lamM,
+                       const double* wM, const double* cM, double* K3D, double* M3D, double* Kabs, double* Mabs) {
+    if (dim != 2 && dim != 3) return -1;
+    int nlb1 = dim + 1, nlb2 = (dim == 2) ? 6 : 10;
+    double ds[3 * 4];
+    p1_dshape(dim, ds);
+    int64_t nsing = 0;
+    for (int64_t e = 0; e < ne; e++) {
+        double c3[3 * 4];
+        for (int j = 0; j < nlb1; j++) {
+            int64_t node = elems[e * nlb2 + j];
+            if (node < 0 || node >= nn) return -2;
+            for (int i = 0; i < dim; i++) AT(c3, dim, i, j) = coords[node * dim + i];
+        }
+        for (int j = nlb1; j < nlb2; j++)
+            if (elems[e * nlb2 + j] < 0 || elems[e * nlb2 + j] >= nn) return -2;
+        double tjac[9];
+        for (int r = 0; r < dim; r++)
+            for (int c = 0; c < dim; c++) {
+                double acc = 0.0;
+                for (int j = 0; j < nlb1; j++) acc += AT(ds, dim, r, j) * AT(c3, dim, c, j);
+                AT(tjac, dim, r, c) = acc;
+            }
+        double vol = fabs(leibniz(tjac, dim, NULL)) / ((dim == 2) ? 2.0 : 6.0);
+        double tinv[9];
+        nsing += gauss_jordan(tjac, dim, tinv);
+        double glam[3 * 4];
+        for (int r = 0; r < dim; r++)
+            for (int j = 0; j < nlb1; j++) {
+                double acc = 0.0;
+                for (int p = 0; p < dim; p++) acc += AT(tinv, dim, r, p) * AT(ds, dim, p, j);
+                AT(glam, dim, r, j) = acc;
+            }
+        double* Ke = K3D ? K3D + e * nlb2 * nlb2 : NULL;
+        double* Me = M3D ? M3D + e * nlb2 * nlb2 : NULL;
+        double* Ka = Kabs ? Kabs + e * nlb2 * nlb2 : NULL;
+        double* Ma = Mabs ? Mabs + e * nlb2 * nlb2 : NULL;
+        for (int k = 0; k < nlb2 * nlb2; k++) {
+            if (Ke) Ke[k] = 0.0;
+            if (Me) Me[k] = 0.0;
+            if (Ka) Ka[k] = 0.0;
+            if (Ma) Ma[k] = 0.0;
+        }
+        for (int q = 0; q < nqK; q++) {
+            double gphi[3 * 10], gn[10];
+            p2_grads(dim, lamK + q * nlb1, glam, gphi);
+            for (int a = 0; a < nlb2; a++) {
+                double g2 = 0.0;
+                for (int r = 0; r < dim; r++) g2 += gphi[r + a * dim] * gphi[r + a * dim];
+                gn[a] = sqrt(g2);
+            }
+            double c = cK ? cK[e * nqK + q] : 1.0;
+            for (int a = 0; a < nlb2; a++)
+                for (int b = 0; b < nlb2; b++) {
+                    double gg = 0.0;
+                    for (int r = 0; r < dim; r++) gg += gphi[r + a * dim] * gphi[r + b * dim];
+                    if (Ke) Ke[a + b * nlb2] += vol * wK[q] * c * gg;
+                    if (Ka) Ka[a + b * nlb2] += vol * wK[q] * fabs(c) * gn[a] * gn[b];
+                }
+        }
+        for (int q = 0; q < nqM; q++) {
+            double phi[10];
+            p2_basis(dim, lamM + q * nlb1, phi);
+            double c = cM ? cM[e * nqM + q] : 1.0;
+            for (int a = 0; a < nlb2; a++)
+                for (int b = 0; b < nlb2; b++) {
+                    if (Me) Me[a + b * nlb2] += vol * wM[q] * c * phi[a] * phi[b];
+                    if (Ma) Ma[a + b * nlb2] += vol * wM[q] * fabs(c * phi[a] * phi[b]);
+                }
+        }
+    }
+    return nsing;
+}

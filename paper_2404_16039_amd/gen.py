@@ -135,6 +135,30 @@ def lshape_mesh(n: int):
     return coords, new_id[elems].astype(np.int32)
 
 
+P2_EDGES = {2: ((0, 1), (0, 2), (1, 2)), 3: ((0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3))}
+
+
+def p2_mesh(coords: np.ndarray, elems: np.ndarray):
+    """P2 mesh of a P1 mesh: one new node at the midpoint of every edge (numbered after the
+    vertices, edges in ascending (min, max) order), and per element its vertices followed by
+    the mid-edge nodes of its local edges in the order of P2_EDGES.
+
+    Returns (coords2[nn + nedges, dim] f64, elems2[ne, nlb2] i32, nedges)."""
+    nn, dim = coords.shape
+    ne = elems.shape[0]
+    loc = P2_EDGES[dim]
+    a = np.stack([elems[:, i] for i, _ in loc], axis=1).astype(np.int64)
+    b = np.stack([elems[:, j] for _, j in loc], axis=1).astype(np.int64)
+    lo, hi = np.minimum(a, b).ravel(), np.maximum(a, b).ravel()
+    key = lo * nn + hi
+    uniq, inv = np.unique(key, return_inverse=True)
+    ulo, uhi = uniq // nn, uniq % nn
+    mid = 0.5 * (coords[ulo] + coords[uhi])
+    coords2 = np.concatenate([coords, mid], axis=0)
+    elems2 = np.concatenate([elems.astype(np.int64), nn + inv.reshape(ne, len(loc))], axis=1).astype(np.int32)
+    return coords2, elems2, uniq.size
+
+
 def _perm_sign(p):
     s = 1
     p = list(p)

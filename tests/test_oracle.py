@@ -831,3 +831,153 @@ def test_gi_divergence_theorem_exact_rules():
                    Y[..., 1] ** 2 * Y[..., 2] ** 3 / 3], axis=2)
     unit, area, _ = oracle.boundary(coords, bf)
     assert abs(oracle.gi(Fv, w2, area, unit) - 8 / 15) < 1e-13
+
+
+# ----------------------------------------------------------------------------- P2 elements
+def _poly_mul(p, q):
+    out = {}
+    for ea, ca in p.items():
+        for eb, cb in q.items():
+            k = tuple(x + y for x, y in zip(ea, eb))
+            out[k] = out.get(k, 0) + ca * cb
+    return out
+
+
+def _dirichlet_mean(poly, d):
+    """mean over the d-simplex of a polynomial in the barycentric coordinates (exact)"""
+    return sum(c * Fr(math.factorial(d) * math.prod(math.factorial(a) for a in ex), math.factorial(sum(ex) + d))
+               for ex, c in poly.items())
+
+
+def _p2_basis_polys(d):
+    n = d + 1
+
+    def mono(**kw):
+        ex = [0] * n
+        for k, v in kw.items():
+            ex[int(k[1:])] += v
+        return tuple(ex)
+    out = []
+    for i in range(n):  # lam_i (2 lam_i - 1)
+        out.append({mono(**{f"l{i}": 2}): Fr(2), mono(**{f"l{i}": 1}): Fr(-1)})
+    for i in range(n):
+        for j in range(i + 1, n):  # 4 lam_i lam_j
+            ex = [0] * n
+            ex[i] += 1
+            ex[j] += 1
+            out.append({tuple(ex): Fr(4)})
+    return out
+
+
+def _poly_dlam(p, k):
+    out = {}
+    for ex, c in p.items():
+        if ex[k]:
+            e2 = list(ex)
+            e2[k] -= 1
+            out[tuple(e2)] = out.get(tuple(e2), 0) + c * ex[k]
+    return out
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_p2_reference_element_exact(d):
+    """On the reference simplex the P2 mass and stiffness matrices equal their exact values,
+    obtained by expanding the basis products in barycentric coordinates and integrating each
+    monomial by the Dirichlet formula (fractions); the rule has degree 5."""
+    n = d + 1
+    coords = np.vstack([np.zeros(d), np.eye(d)])
+    elems = np.arange(n, dtype=np.int32)[None, :]
+    c2, e2, _ = gen.p2_mesh(coords, elems)
+    rule = oracle.stroud_rule(d, 3)
+    o = oracle.p2_elements(c2, e2, rule, rule)
+    nb = len(_p2_basis_polys(d))
+    K = o["K3D"].reshape(nb, nb).T
+    M = o["M3D"].reshape(nb, nb).T
+    vol = Fr(1, math.factorial(d))
+    phi = _p2_basis_polys(d)
+    # grad lam_0 = -(1, ..., 1), grad lam_i = e_i: Gram matrix of the barycentric gradients
+    G = [[Fr(d) if (k == 0 and l == 0) else (Fr(-1) if (k == 0 or l == 0) else Fr(int(k == l)))
+          for l in range(n)] for k in range(n)]
+    for a in range(nb):
+        for b in range(nb):
+            m = float(vol * _dirichlet_mean(_poly_mul(phi[a], phi[b]), d))
+            assert abs(M[a, b] - m) < 1e-15, (a, b, M[a, b], m)
+            kk = {}
+            for k in range(n):
+                for l in range(n):
+                    if G[k][l]:
+                        t = _poly_mul(_poly_dlam(phi[a], k), _poly_dlam(phi[b], l))
+                        for ex, c in t.items():
+                            kk[ex] = kk.get(ex, 0) + c * G[k][l]
+            kv = float(vol * _dirichlet_mean(kk, d))
+            assert abs(K[a, b] - kv) < 1e-14, (a, b, K[a, b], kv)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_p2_reproduces_quadratics(d):
+    """A quadratic function is its own P2 interpolant: on a jittered mesh the local forms sum
+    to the exact energies, sum v_e^T K_e v_e = int |grad v|^2 and sum v_e^T M_e v_e =
+    int v^2 over the unit square / cube (rules of degree 3 and 5), and every K row sums to 0
+    and every M page to |T|."""
+    coords, elems, _ = gen.square_mesh(3, jitter=0.2) if d == 2 else gen.cube_mesh(2, jitter=0.15)
+    c2, e2, _ = gen.p2_mesh(coords, elems)
+    o = oracle.p2_elements(c2, e2, oracle.stroud_rule(d, 2), oracle.stroud_rule(d, 3))
+    nb = e2.shape[1]
+    x = c2
+
+    def v(x):
+        return x[..., 0] ** 2 + 2 * x[..., 1] * x[..., -1] - x[..., -1] + 0.5
+
+    def grad2(x):
+        g0 = 2 * x[..., 0]
+        if d == 2:  # v = x^2 + 2 y^2 - y + 0.5
+            g1 = 4 * x[..., 1] - 1
+            return g0 ** 2 + g1 ** 2
+        return g0 ** 2 + (2 * x[..., 2]) ** 2 + (2 * x[..., 1] - 1) ** 2
+    ve = v(x)[e2]
+    K = o["K3D"].reshape(-1, nb, nb)
+    M = o["M3D"].reshape(-1, nb, nb)
+    gl, gw = np.polynomial.legendre.leggauss(4)
+    gl, gw = (gl + 1) / 2, gw / 2
+    grid = np.stack(np.meshgrid(*([gl] * d), indexing="ij"), axis=-1).reshape(-1, d)
+    wts = np.prod(np.stack(np.meshgrid(*([gw] * d), indexing="ij"), axis=-1).reshape(-1, d), axis=1)
+    assert abs(np.einsum("ea,eab,eb->", ve, K, ve) - (wts * grad2(grid)).sum()) < 1e-12
+    assert abs(np.einsum("ea,eab,eb->", ve, M, ve) - (wts * v(grid) ** 2).sum()) < 1e-13
+    assert np.abs(K.sum(axis=2)).max() < 1e-12
+    vol = oracle.p1_elements(coords, elems)["vol"]
+    assert np.allclose(M.sum(axis=(1, 2)), vol, rtol=1e-13, atol=0)
+
+
+def test_p2_energies_fourth_order():
+    """The section 3.6 3-D benchmark with P2 elements (c_K = c_M = exp(x1+x2+x3) at the points
+    of degree-5 rules, v = cos(pi x1) cos(pi x2) cos(pi x3) interpolated at the P2 nodes): the
+    errors against the printed I_K, I_M fall at fourth order; e_M stays within 10% of the
+    printed P2 table and e_K within a factor 3 (the table's mesh has the same node counts but
+    is not reproduced exactly)."""
+    ik = im = None
+    with open(os.path.join(GOLD, "energies.txt")) as fh:
+        for line in fh:
+            p = line.split()
+            if p[:3] == ["closed", "3d", "IK"]:
+                ik = float(p[3])
+            if p[:3] == ["closed", "3d", "IM"]:
+                im = float(p[3])
+    printed = {4: (6.84e-3, 5.75e-3), 8: (4.00e-4, 3.88e-4)}
+    errs = {}
+    for n in (4, 8, 16):
+        c, e, _ = gen.cube_mesh(n, jitter=0.0, with_faces=False)
+        c2, e2, _ = gen.p2_mesh(c, e)
+        r = oracle.stroud_rule(3, 3)
+        xq = oracle.simplex_points(c, e, r[0])
+        cq = np.exp(xq.sum(axis=-1))
+        o = oracle.p2_elements(c2, e2, r, r, cq, cq)
+        v = np.cos(np.pi * c2[:, 0]) * np.cos(np.pi * c2[:, 1]) * np.cos(np.pi * c2[:, 2])
+        ve = v[e2]
+        eK = abs(np.einsum("ea,eab,eb->", ve, o["K3D"].reshape(-1, 10, 10), ve) - ik)
+        eM = abs(np.einsum("ea,eab,eb->", ve, o["M3D"].reshape(-1, 10, 10), ve) - im)
+        errs[n] = (eK, eM)
+    for a, b in ((4, 8), (8, 16)):
+        for k in range(2):
+            assert 13.0 < errs[a][k] / errs[b][k] < 19.0, errs
+    for n, (pk, pm) in printed.items():
+        assert pk / 3 < errs[n][0] < 3 * pk and abs(errs[n][1] / pm - 1) < 0.1, (n, errs[n])
