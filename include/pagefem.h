@@ -256,6 +256,25 @@ pf_status pf_csr_faces(pf_csr* csr, const double* coords, const int32_t* elems, 
 pf_status pf_csr_faces_info(const pf_csr* csr, int64_t* nf, int64_t* nfb, const int32_t** faces,
                             const int32_t** fel, const int32_t** bfaces, const int32_t** bel);
 
+/* P2 element matrices (section 3.6, stiffness_matrixP2 / mass_matrixP2) of straight-sided
+ * triangles (dim 2) and tetrahedra (dim 3).  elems2: ne x nlb2 int32 (nlb2 = 6 / 10): the
+ * dim + 1 vertices, then the mid-edge nodes of the local edges (0,1), (0,2), (1,2) (2-D) or
+ * (0,1), (0,2), (0,3), (1,2), (1,3), (2,3) (3-D); the geometry comes from the vertices.
+ * Basis: lam_i (2 lam_i - 1) at vertex i, 4 lam_i lam_j at edge (i,j).  With |T| the element
+ * measure and rules given as barycentric points (host, nq x (dim+1)) and weights summing to 1
+ * (host, nq; at most PF_P2_RULE_MAX points):
+ *   K3D[e*nlb2^2 + a + b*nlb2] = |T| sum_q wK_q cK_q grad phi_a . grad phi_b (rule K),
+ *   M3D[e*nlb2^2 + a + b*nlb2] = |T| sum_q wM_q cM_q phi_a phi_b            (rule M),
+ * column-major pages of type prec; cKq, cMq: ne x nq of type prec (nullable = 1); K3D or M3D
+ * nullable (then its rule is ignored).  FP32 recomputes routed elements in FP64 as
+ * pf_elem_stiffness_mass; d_counters: [0] routed, [2] bad node index (NaN pages). */
+#define PF_P2_RULE_MAX 32
+pf_status pf_p2_elements(int dim, pf_dtype prec, int64_t nn, const double* coords, int64_t ne,
+                         const int32_t* elems2, int nqK, const double* lamK, const double* wK,
+                         const void* cKq, int nqM, const double* lamM, const double* wM,
+                         const void* cMq, void* K3D, void* M3D, const pf_fallback* fb,
+                         int64_t* d_counters, void* stream);
+
 /* ----------------------------------------------------------------------------------
  * Integration over cells (sections 3.5, 3.6): points of a rule and the GI function.
  * A rule is nq barycentric points lam (host, nq x nv, row-major) with weights w (host, nq)

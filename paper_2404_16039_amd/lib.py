@@ -137,6 +137,7 @@ _sig = {
     "pf_csr_faces_info": ([P, C.POINTER(I64), C.POINTER(I64), C.POINTER(P), C.POINTER(P), C.POINTER(P),
                            C.POINTER(P)], C.c_int),
     "pf_simplex_points": ([I32, I32, I64, P, I64, P, I32, P, P, P], C.c_int),
+    "pf_p2_elements": ([I32, I32, I64, P, I64, P, I32, P, P, P, I32, P, P, P, P, P, FP, P, P], C.c_int),
     "pf_gi": ([I32, I64, I32, I32, P, P, P, P, P, P, P], C.c_int),
     "pf_rhs": ([P, I32, P, P, I32, P, P, P, FP, P, P], C.c_int),
     "pf_energies": ([P, I32, P, P, I32, P, P, P, P, P, P, FP, P, P], C.c_int),
@@ -418,6 +419,30 @@ def simplex_points(coords, cells, lam, stream=None):
     _chk(_lib.pf_simplex_points(dim, nv, coords.shape[0], _p(coords), nc, _p(cells), nq,
                                 lam.ctypes.data_as(P), _p(X), _s(stream)), "pf_simplex_points")
     return X
+
+
+P2_RULE_MAX = 32
+
+
+def p2_elements(prec, coords, elems2, ruleK=None, ruleM=None, cKq=None, cMq=None, K3D=None, M3D=None, fb=None,
+                counters=None, stream=None):
+    """P2 element matrices into K3D / M3D (ne x nlb2^2 pages); rules are (lam, w) host arrays."""
+    import numpy as np
+
+    def rule(r):
+        if r is None:
+            return 0, None, None, None
+        lam = np.ascontiguousarray(r[0], dtype=np.float64)
+        w = np.ascontiguousarray(r[1], dtype=np.float64)
+        return lam.shape[0], lam, w, (lam, w)
+    nqK, lK, wK, keepK = rule(ruleK)
+    nqM, lM, wM, keepM = rule(ruleM)
+    nn, dim = coords.shape
+    _chk(_lib.pf_p2_elements(dim, prec, nn, _p(coords), elems2.shape[0], _p(elems2), nqK,
+                             None if lK is None else lK.ctypes.data_as(P), None if wK is None else wK.ctypes.data_as(P),
+                             _p(cKq), nqM, None if lM is None else lM.ctypes.data_as(P),
+                             None if wM is None else wM.ctypes.data_as(P), _p(cMq), _p(K3D), _p(M3D),
+                             _ref(fb, Fallback), _p(counters), _s(stream)), "pf_p2_elements")
 
 
 def gi(prec, fip, w, sizes, normals=None, value=None, work=None, stream=None):
