@@ -23,6 +23,8 @@ Other workloads (one JSON line each, same contract):
                      128^3 cube mesh, FP32, fields at the 4 points of the degree-2 rule
   --workload faces   all faces of the 128^3 cube mesh with the normals of all of them, and
                      GI volume / surface integrals of the divergence theorem
+  --workload p2      P2 element stiffness and mass matrices (10 x 10) on the 64^3 cube mesh
+                     (2,146,689 P2 nodes), coefficients at 27 points
   --workload serve   a Poisson stream of assembly jobs (200 jobs/s, 2-D FP64 / 3-D FP32,
                      1e3..2e6 elements) through the serving loop: p50/p99 latency and
                      throughput, fused + resident structures vs one launch per job without
@@ -48,6 +50,8 @@ ENERGY_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "energy_cube128_traffic.jso
 ENERGY_SOURCES = ["energy.hip", "p1elem.hpp", "smallmat.hpp", "common.hpp", "exact.hpp", "quadrature.hpp"]
 FACES_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "faces_cube128_traffic.json")
 FACES_SOURCES = ["assembly.hip", "integrals.hip", "common.hpp"]
+P2_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "p2_cube64_traffic.json")
+P2_SOURCES = ["p2.hip", "p1elem.hpp", "smallmat.hpp", "common.hpp"]
 BATCH_SOURCES = ["batch.hip", "smallmat.hpp", "common.hpp"]
 
 
@@ -89,7 +93,7 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=128, help="cubes per side of the CPU oracle sample")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
-    ap.add_argument("--workload", choices=["assembly", "pages", "batch", "serve", "energy", "faces"],
+    ap.add_argument("--workload", choices=["assembly", "pages", "batch", "serve", "energy", "faces", "p2"],
                     default="assembly")
     ap.add_argument("--coef", choices=["one", "quad"], default="one",
                     help="assembly coefficients: c = 1, or c = exp(x1+x2+x3) at the 4 points of the degree-2 rule "
@@ -534,6 +538,75 @@ def run_faces(args):
     print(json.dumps(out))
 
 
+def run_p2(args):
+    """P2 element stiffness and mass matrices of the 3-D benchmark (section 3.6)."""
+    import numpy as np
+    import torch
+
+    from paper_2404_16039_amd import gen
+    from paper_2404_16039_amd import lib as L
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    n = args.n if args.n != 128 else 64  # the paper's largest 3-D P2 case: 64^3 cubes, 2,146,689 nodes
+    coords, elems, _ = gen.cube_mesh(n, jitter=0.15, with_faces=False)
+    c2, e2, _ = gen.p2_mesh(coords, elems)
+    ne, nn2 = e2.shape[0], c2.shape[0]
+    tc, te = torch.from_numpy(c2).cuda(), torch.from_numpy(e2).cuda()
+    rule = _collapsed_rule(3, 3)  # 27 points, degree 5
+    nq = rule[0].shape[0]
+    X = L.simplex_points(torch.from_numpy(coords).cuda(), torch.from_numpy(elems).cuda(), rule[0])
+    cq = torch.exp(X.sum(dim=2)).to(torch.float32).contiguous()
+    del X
+    K = torch.empty(ne * 100, dtype=torch.float32, device="cuda")
+    M = torch.empty(ne * 100, dtype=torch.float32, device="cuda")
+    fb = L.fallback(1e-3 / n ** 3, 1e6, True)
+    _calib_copy(args.copy_calib_mib)
+    t_k = _timed(lambda: L.p2_elements(L.F32, tc, te, rule, None, cKq=cq, K3D=K, fb=fb, stream=stream), args.steps,
+                 args.warmup, stream)
+    t_m = _timed(lambda: L.p2_elements(L.F32, tc, te, None, rule, cMq=cq, M3D=M, fb=fb, stream=stream), args.steps,
+                 args.warmup, stream)
+    t_km = _timed(lambda: L.p2_elements(L.F32, tc, te, rule, rule, cKq=cq, cMq=cq, K3D=K, M3D=M, fb=fb,
+                                        stream=stream), args.steps, args.warmup, stream)
+    ms = float(np.mean(t_km))
+    # algorithmic bytes per launch (K and M together): the 10 node ids 40 B/tet, FP64 vertex
+    # coordinates 24 B per vertex node, the coefficient at 27 points for K and for M
+    # (2 x 108 B/tet), the two FP32 10 x 10 pages 800 B/tet
+    alg = 40 * ne + 24 * coords.shape[0] + 2 * 4 * nq * ne + 800 * ne
+    gbs = alg / (ms * 1e-3) / 1e9
+    out = {
+        "metric": "P2 tet elements/s (element stiffness + mass matrices, 10 x 10 each)",
+        "value": ne / (ms * 1e-3), "unit": "tets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "3-D P2 tets: unit cube, %d^3 cubes x 6 Kuhn tets, jitter 0.15 h, mid-edge nodes; "
+                               "K3D and M3D (FP32) with c_K = c_M = exp(x1+x2+x3) at the 27 points of a degree-5 "
+                               "rule" % n, "tets": ne, "nodes_p2": nn2},
+        "kernels_us": {"k_p2_elem<3,float> K": round(float(np.mean(t_k)) * 1e3, 1),
+                       "k_p2_elem<3,float> M": round(float(np.mean(t_m)) * 1e3, 1),
+                       "k_p2_elem<3,float> K+M": round(ms * 1e3, 1)},
+        "roofline": {"kernel": "k_p2_elem<3,float> (K and M)", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                     "traffic": traffic_of(P2_TRAFFIC_FILE, P2_SOURCES, kernel="k_p2_elem<3,float>", n=n),
+                     "algorithmic_bytes_per_launch": alg, "launch_us": round(ms * 1e3, 1)},
+        "paper_context": {"what": "P2 K and M in MATLAB at 2,146,689 nodes (3-D level 6), hardware not stated",
+                          "K_s": 87.6, "M_s": 16.4},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        cn = 48
+        cc, ce, _ = gen.cube_mesh(cn, jitter=0.15, with_faces=False)
+        cc2, ce2, _ = gen.p2_mesh(cc, ce)
+        cqq = np.exp(oracle.simplex_points(cc, ce, rule[0]).sum(axis=-1))
+        t1 = time.perf_counter()
+        oracle.p2_elements(cc2, ce2, rule, rule, cqq, cqq)
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": ce.shape[0] / dt, "unit": "tets/s", "cores": 1, "kind": "oracle",
+                               "sample": "FP64 oracle P2 K3D + M3D (27-point rules, error scales included), single "
+                                         "thread, %d^3 Kuhn mesh, %d tets, %.1f s" % (cn, ce.shape[0], dt)}
+    print(json.dumps(out))
+
+
 def run_serve(args):
     """Poisson stream of assembly jobs through the serving loop."""
     import numpy as np
@@ -645,6 +718,8 @@ def main():
         return run_energy(args)
     if args.workload == "faces":
         return run_faces(args)
+    if args.workload == "p2":
+        return run_p2(args)
 
     import numpy as np
     import torch

@@ -18,7 +18,7 @@
 
 namespace pf {
 
-constexpr int P2BS = 128;
+constexpr int P2BS = 64;  // elements per block (one wave)
 
 struct P2Rules {
     int nqK, nqM;
@@ -72,14 +72,16 @@ __device__ __forceinline__ C p2_kentry(int a, int b, const C (&G)[DIM + 1][DIM +
     return s;
 }
 
+// K and M of one element into the staging pages kp, mp (nullable: not requested); ck, cm:
+// the element's coefficients at the points of each rule (nullable: 1)
 template <int DIM, typename C, typename T>
-__device__ __forceinline__ void p2_write(const P1Geom<DIM, C>& g, int64_t e, const P2Rules& R, const T* cKq,
-                                         const T* cMq, T* K3D, T* M3D) {
+__device__ __forceinline__ void p2_write(const P1Geom<DIM, C>& g, const P2Rules& R, const T* ck, const T* cm, T* kp,
+                                         T* mp) {
     using L = P2Local<DIM>;
     constexpr int N = L::N, NB = L::NB;
     const C adet = fabs(g.det);
     const C vol = adet / static_cast<C>(fact_dim<DIM>());
-    if (K3D) {
+    if (kp) {
         // G_kl = c_k . c_l / det^2
         const C id2 = C(1) / (g.det * g.det);
         C G[N][N];
@@ -100,7 +102,7 @@ __device__ __forceinline__ void p2_write(const P1Geom<DIM, C>& g, int64_t e, con
             for (int l = 0; l < N; ++l) S2[k][l] = C(0);
         }
         for (int q = 0; q < R.nqK; ++q) {
-            const C wc = static_cast<C>(R.wK[q]) * (cKq ? static_cast<C>(cKq[e * R.nqK + q]) : C(1));
+            const C wc = static_cast<C>(R.wK[q]) * (ck ? static_cast<C>(ck[q]) : C(1));
             S0 += wc;
             C lam[N];
 #pragma unroll
@@ -117,7 +119,6 @@ __device__ __forceinline__ void p2_write(const P1Geom<DIM, C>& g, int64_t e, con
         for (int k = 0; k < N; ++k)
 #pragma unroll
             for (int l = 0; l < k; ++l) S2[k][l] = S2[l][k];
-        T* kp = K3D + e * (NB * NB);
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -127,14 +128,14 @@ __device__ __forceinline__ void p2_write(const P1Geom<DIM, C>& g, int64_t e, con
                 kp[b + a * NB] = v;
             }
     }
-    if (M3D) {
+    if (mp) {
         C m[NB][NB];
 #pragma unroll
         for (int a = 0; a < NB; ++a)
 #pragma unroll
             for (int b = 0; b <= a; ++b) m[a][b] = C(0);
         for (int q = 0; q < R.nqM; ++q) {
-            const C wc = static_cast<C>(R.wM[q]) * (cMq ? static_cast<C>(cMq[e * R.nqM + q]) : C(1));
+            const C wc = static_cast<C>(R.wM[q]) * (cm ? static_cast<C>(cm[q]) : C(1));
             C lam[N], phi[NB];
 #pragma unroll
             for (int k = 0; k < N; ++k) lam[k] = static_cast<C>(R.lamM[q * N + k]);
@@ -149,7 +150,6 @@ __device__ __forceinline__ void p2_write(const P1Geom<DIM, C>& g, int64_t e, con
                 for (int b = 0; b <= a; ++b) m[a][b] = fmaT(wa, phi[b], m[a][b]);
             }
         }
-        T* mp = M3D + e * (NB * NB);
 #pragma unroll
         for (int a = 0; a < NB; ++a)
 #pragma unroll
@@ -161,6 +161,10 @@ __device__ __forceinline__ void p2_write(const P1Geom<DIM, C>& g, int64_t e, con
     }
 }
 
+// One element per lane.  The lanes build their pages in LDS (row stride NB*NB + 1 words,
+// so the lanes' writes fall in different banks), then the block copies its elements'
+// contiguous run of pages out with consecutive lanes on consecutive words (coalesced):
+// first the K pages, then the M pages through the same staging area.
 template <int DIM, typename T>
 __global__ __launch_bounds__(P2BS) void k_p2_elem(int64_t nn, const double* __restrict__ coords, int64_t ne,
                                                   const int32_t* __restrict__ elems2, P2Rules R,
@@ -168,40 +172,59 @@ __global__ __launch_bounds__(P2BS) void k_p2_elem(int64_t nn, const double* __re
                                                   T* __restrict__ K3D, T* __restrict__ M3D, Fallback fb,
                                                   int64_t* d_counters) {
     constexpr int NB = P2Local<DIM>::NB;
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * P2BS + threadIdx.x;
+    constexpr int PS = NB * NB + 1;  // staging stride of one page
+    __shared__ T stage[P2BS * PS];
+    const int64_t e0 = static_cast<int64_t>(blockIdx.x) * P2BS;
+    const int64_t e = e0 + threadIdx.x;
+    const int nel = static_cast<int>(ne - e0 < P2BS ? ne - e0 : P2BS);
     bool routed = false, bad = false;
+    double ev[DIM][DIM];
     if (e < ne) {
         int nd[DIM + 1];
 #pragma unroll
         for (int j = 0; j <= DIM; ++j) nd[j] = elems2[e * NB + j];
-        double ev[DIM][DIM];
         bad = !p1_edges<DIM>(coords, nn, nd, ev);
 #pragma unroll
         for (int j = DIM + 1; j < NB; ++j) {
             const int32_t v = elems2[e * NB + j];
             bad = bad || v < 0 || v >= nn;
         }
-        if (bad) {
-            for (int k = 0; k < NB * NB; ++k) {
-                if (K3D) K3D[e * NB * NB + k] = static_cast<T>(NAN);
-                if (M3D) M3D[e * NB * NB + k] = static_cast<T>(NAN);
-            }
-        } else {
-            if constexpr (sizeof(T) == 4) {
-                P1Geom<DIM, float> g;
-                p1_geom<DIM, float>(ev, g);
-                routed = should_route(g.det, g.absterms, fb);
-                if (!routed) p2_write<DIM, float, T>(g, e, R, cKq, cMq, K3D, M3D);
-            }
-            if (sizeof(T) == 8 || routed) {
-                P1Geom<DIM, double> gd;
-                p1_geom<DIM, double>(ev, gd);
-                p2_write<DIM, double, T>(gd, e, R, cKq, cMq, K3D, M3D);
+    }
+    T* page = stage + threadIdx.x * PS;
+    for (int which = 0; which < 2; ++which) {  // 0: K, 1: M
+        T* out = which == 0 ? K3D : M3D;
+        if (!out) continue;
+        const T* cq = which == 0 ? cKq : cMq;
+        const int nq = which == 0 ? R.nqK : R.nqM;
+        const T* cl = cq ? cq + e * nq : nullptr;
+        if (e < ne) {
+            if (bad) {
+                for (int k = 0; k < NB * NB; ++k) page[k] = static_cast<T>(NAN);
+            } else {
+                T* kp = which == 0 ? page : nullptr;
+                T* mp = which == 1 ? page : nullptr;
+                bool r = false;
+                if constexpr (sizeof(T) == 4) {
+                    P1Geom<DIM, float> g;
+                    p1_geom<DIM, float>(ev, g);
+                    r = should_route(g.det, g.absterms, fb);
+                    if (!r) p2_write<DIM, float, T>(g, R, cl, cl, kp, mp);
+                }
+                if (sizeof(T) == 8 || r) {
+                    P1Geom<DIM, double> gd;
+                    p1_geom<DIM, double>(ev, gd);
+                    p2_write<DIM, double, T>(gd, R, cl, cl, kp, mp);
+                }
+                routed = routed || r;
             }
         }
+        __syncthreads();
+        T* dst = out + e0 * (NB * NB);
+        for (int k = threadIdx.x; k < nel * NB * NB; k += P2BS) dst[k] = stage[(k / (NB * NB)) * PS + k % (NB * NB)];
+        __syncthreads();
     }
     count_wave(d_counters, 0, routed);
-    count_wave(d_counters, 2, bad);
+    count_wave(d_counters, 2, bad && e < ne);
 }
 
 }  // namespace pf
