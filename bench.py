@@ -814,8 +814,7 @@ def main():
     kernels = {
         "k_scatter": (stage_ms["adjacency"] / stage_calls, 16 * ne + 16 * ne + 4 * nn),
         "k_pattern<4>": (stage_ms["pattern"] / stage_calls, 16 * ne + 16 * ne + 16 * ne + 4 * nnz + 4 * nn),
-        "scan + block stats": (stage_ms["scan"] / stage_calls, 16 * nn),
-        "k_compact": (stage_ms["compact"] / stage_calls, 8 * nnz + 4 * nn),
+        "k_row_offsets": (stage_ms["row offsets"] / stage_calls, 12 * nn + 8 * nnz),
         kname: (num_ms, alg_num),
     }
 

@@ -192,10 +192,13 @@ typedef struct pf_csr pf_csr;
 pf_status pf_csr_create(pf_csr** out);
 
 /* Build (or rebuild) the CSR structure of a P1 mesh: node-to-element adjacency and the
- * row pattern.  Device buffers are kept in the handle and grown when needed.  This call
- * synchronises `stream` once (it reads nnz and the error word back to the host).
+ * row pattern.  Device buffers are kept in the handle and grown when needed (col_idx is
+ * sized for 64 entries per row, since nnz is known only once the pattern is built).  This
+ * call synchronises `stream` once (it reads nnz and the error word back to the host).
  * Limits: 4*ne < 2^31, nnz < 2^31, at most 64 elements per node and 64 nonzeros per row
- * (PF_ELIMIT otherwise).  Out-of-range node ids give PF_EINDEX. */
+ * (PF_ELIMIT otherwise).  Out-of-range node ids give PF_EINDEX; PF_EINVAL if the row
+ * offsets could not be formed (a bounded wait between the workgroups of the row-offset
+ * scan ran out, which the device's in-order start of workgroups rules out). */
 pf_status pf_csr_symbolic(pf_csr* csr, int dim, int64_t nn, int64_t ne, const int32_t* elems,
                           void* stream);
 
@@ -208,9 +211,9 @@ pf_status pf_csr_info(const pf_csr* csr, int64_t* nn, int64_t* nnz, const int32_
  * events on its stream between its stages (0 stops recording).  pf_csr_stage_times waits
  * for the events of the last call and writes ms[PF_CSR_STAGES], the summed milliseconds
  * of each stage since timing was switched on, and *calls, the number of calls summed
- * (nullable).  Stages: adjacency (counting scatter), row pattern, scan (row_ptr and block
- * statistics), compaction of the columns. */
-#define PF_CSR_STAGES 4
+ * (nullable).  Stages: adjacency (counting scatter), row pattern, row offsets (the scan
+ * of the row lengths with row_ptr, col_idx and the numeric launch statistics). */
+#define PF_CSR_STAGES 3
 pf_status pf_csr_set_timing(pf_csr* csr, int on);
 pf_status pf_csr_stage_times(pf_csr* csr, double* ms, int64_t* calls);
 

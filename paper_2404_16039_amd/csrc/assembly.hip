@@ -39,7 +39,8 @@ struct pf_csr {
     int32_t* row_ptr = nullptr;
     int32_t* col_idx = nullptr;
     int32_t* cnt = nullptr;   // per-node counts / cursors / row lengths
-    int32_t* colpad = nullptr;  // sorted columns of every row, MAXROW per row (symbolic scratch)
+    int32_t* colblk = nullptr;  // sorted columns of every row-pattern block, RR * MAXROW per block
+    uint64_t* look = nullptr;   // published counts / prefixes of the row-offset tiles
     int64_t* bsum = nullptr;  // scan workspace
     int64_t* info = nullptr;  // [0] error bits, [1] adjacency total, [2] nnz, [3..6] block stats
     void* work = nullptr;     // workspace of the energy reductions (pf_energies)
@@ -54,12 +55,12 @@ struct pf_csr {
     int64_t cap_fcount = 0, cap_bcount = 0, cap_fptr = 0, cap_bptr = 0, cap_faces = 0, cap_fel = 0,
             cap_bfaces = 0, cap_bel = 0, cap_finfo = 0, cap_dpos = 0, cap_esign = 0;
     int64_t cap_adj_len = 0, cap_row_ptr = 0, cap_cnt = 0, cap_adj = 0, cap_pk = 0, cap_nnz = 0, cap_bsum = 0,
-            cap_info = 0, cap_colpad = 0, cap_work = 0;
+            cap_info = 0, cap_colblk = 0, cap_look = 0, cap_work = 0;
     bool built = false;
     // per-stage timing of pf_csr_symbolic (events e0..e5: start, after the adjacency, after
     // the pattern, after the scan; around the compaction)
     bool timing = false, pending = false;
-    hipEvent_t ev[6] = {};
+    hipEvent_t ev[PF_CSR_STAGES + 1] = {};
     double stage_ms[PF_CSR_STAGES] = {};
     int64_t stage_calls = 0;
 };
@@ -324,11 +325,12 @@ __device__ __forceinline__ int upper_pos(const int32_t* v, int n, int32_t x) {
     return lo;
 }
 
-// One pass per block of RR rows: insert, rank, and write (a) each row's length, (b) its
-// sorted columns into a padded buffer colpad[row * MAXROW ...] (moved to col_idx once the
-// row lengths are scanned), (c) the packed slots pk of every adjacency entry (bits 0-1 local
-// index a, bits 2+8k .. 9+8k row position of the k-th other node of the element, in local
-// order).  A row with elements holds its own node (the diagonal), which is entered once
+// One pass per block of RR rows: insert, rank, and write (a) each row's length, (b) the
+// block's sorted columns, row after row, at the start of its own region of RR * MAXROW
+// words of colblk (moved to col_idx once the row lengths are scanned; a contiguous run, so
+// both moves are coalesced), (c) the packed slots pk of every adjacency entry (bits 0-1
+// local index a, bits 2+8k .. 9+8k row position of the k-th other node of the element, in
+// local order).  A row with elements holds its own node (the diagonal), which is entered once
 // before the entries, so each entry inserts only the element's other nodes.  The table slot
 // of every inserted node is kept per entry in LDS and ranking labels each used table slot
 // with its column position, so pk needs no second gather of the element and no second
@@ -336,12 +338,13 @@ __device__ __forceinline__ int upper_pos(const int32_t* v, int n, int32_t x) {
 template <int NLB>
 __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __restrict__ elems,
                                                 const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
-                                                int32_t* __restrict__ rowlen, int32_t* __restrict__ colpad,
+                                                int32_t* __restrict__ rowlen, int32_t* __restrict__ colblk,
                                                 uint32_t* __restrict__ pk, int32_t* __restrict__ dpos,
                                                 int64_t* __restrict__ info) {
     constexpr int NO = NLB - 1;               // other nodes of an element
     __shared__ int32_t tab[RR * RSUB];       // node ids, -1 empty
     __shared__ int32_t seg[RR * MAXROW];      // each row's nodes, insertion order
+    __shared__ int32_t srt[RR * MAXROW];      // the block's columns in CSR order
     __shared__ uint8_t seg_h[RR * MAXROW];    // table slot of each list item
     __shared__ uint8_t slot_rank[RR * RSUB];  // rank (column position) of each used table slot
     __shared__ uint32_t eslot[RR * MAXADJ];   // per item: a | table slot of other node k << (2 + 6k)
@@ -472,9 +475,11 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
         for (; j < n; ++j) rank += sr[j] < v;
         slot_rank[r * RSUB + seg_h[r * MAXROW + p]] = static_cast<uint8_t>(rank);
         if (p == 0) dpos[r0 + r] = rank;  // item 0 is the row's own node
-        colpad[(r0 + r) * MAXROW + rank] = v;
+        srt[cpre[r] + rank] = v;
     }
     __syncthreads();
+    int32_t* dst = colblk + static_cast<int64_t>(blockIdx.x) * (RR * MAXROW);
+    for (int q = threadIdx.x; q < cpre[nr]; q += RT) dst[q] = srt[q];
     // packed slots of every adjacency entry from its kept table slots (row-interleaved)
     for (int idx = threadIdx.x; idx < items; idx += RT) {
         const int r = idx % RR, j = idx / RR;
@@ -491,21 +496,187 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
     }
 }
 
-// col_idx from the padded columns: a block moves the CSR window of RR rows with
-// coalesced writes
-constexpr int CR = 128;  // rows per compaction block
-__global__ __launch_bounds__(RT) void k_compact(int64_t nn, const int32_t* __restrict__ row_ptr,
-                                                const int32_t* __restrict__ colpad, int32_t* __restrict__ col_idx) {
-    __shared__ int32_t rp[CR + 1];
-    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * CR;
-    const int nr = static_cast<int>((r0 + CR < nn) ? CR : nn - r0);
-    for (int i = threadIdx.x; i <= nr; i += RT) rp[i] = row_ptr[r0 + i];
+// ---------------------------------------------------------------------------- row offsets
+// row_ptr, col_idx and the numeric launch statistics in one pass over tiles of SCAN_TILE
+// rows (a single-pass scan with decoupled look-back).  Tile t publishes its nonzero count
+// as soon as it has summed its row lengths (status AGG), then sums the published values of
+// the tiles before it, nearest first, 64 at a time, until it meets one holding its
+// inclusive prefix (status INC), and publishes its own.  A tile waits only for tiles of
+// smaller index to publish their counts, which they do before waiting on anyone; every
+// wait is bounded (LB_SPIN polls) and a wait that runs out sets ERR_SCAN.
+constexpr uint64_t LB_AGG = uint64_t(1) << 62, LB_INC = uint64_t(2) << 62, LB_VAL = LB_AGG - 1;
+constexpr int LB_SPIN = 1 << 13;
+constexpr int64_t ERR_SCAN = 16;
+
+__device__ __forceinline__ void lb_publish(uint64_t* look, int64_t t, uint64_t word) {
+    __hip_atomic_store(look + t, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// exclusive prefix of tile t (> 0) over the published counts; run by one full wave
+__device__ int64_t lb_exclusive(const uint64_t* look, int64_t t, bool& timeout) {
+    const int lane = threadIdx.x & 63;
+    int64_t excl = 0;
+    for (int64_t end = t;; end -= 64) {  // tiles end-1-lane, lane 0 the nearest
+        const int64_t j = end - 1 - lane;
+        uint64_t d = LB_INC;  // before tile 0: an inclusive prefix of zero
+        if (j >= 0) {
+            d = __hip_atomic_load(look + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int spin = 0; (d >> 62) == 0; ++spin) {
+                if (spin >= LB_SPIN) {
+                    timeout = true;
+                    d = LB_INC;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+                d = __hip_atomic_load(look + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        const unsigned long long inc = __ballot((d >> 62) == 2);
+        const int first = inc ? __ffsll(static_cast<long long>(inc)) - 1 : 64;  // the nearest inclusive prefix
+        int64_t v = lane <= first ? static_cast<int64_t>(d & LB_VAL) : 0;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        excl += v;
+        if (inc) return excl;
+    }
+}
+
+// Thread i of a tile holds rows 8i .. 8i+7, i.e. exactly one row-pattern block, whose
+// columns lie contiguous in colblk.  Besides the offsets, the tile measures the largest
+// CSR window of the numeric block classes (NR_BIG rows, NR_MID rows as sums over 4 and 2
+// neighbouring lanes, NR_SMALL = 4 rows per half thread) and the largest number of elements
+// around a node, and stores them as tstat[4t .. 4t+3] (no atomics on shared words: those
+// serialise across the whole device); k_row_stats reduces them.
+static_assert(SCAN_ITEMS == RR && SCAN_ITEMS == 8, "a scan thread owns one row-pattern block of 8 rows");
+static_assert(RR * MAXROW >= 128, "a row-pattern block's region holds the 128 words read at once");
+__global__ __launch_bounds__(SBS) void k_row_offsets(int64_t nn, const int32_t* __restrict__ rowlen,
+                                                     const int32_t* __restrict__ adj_len,
+                                                     const int32_t* __restrict__ colblk, int32_t* __restrict__ row_ptr,
+                                                     int32_t* __restrict__ col_idx, uint64_t* __restrict__ look,
+                                                     int32_t* __restrict__ tstat, int64_t* __restrict__ info) {
+    __shared__ int32_t boff[SBS];  // offset of each thread's block inside the tile
+    __shared__ int32_t bcnt[SBS];
+    __shared__ int red[4][SBS / 64];
+    __shared__ int64_t excl_s;
+    const int64_t t = blockIdx.x;
+    const int64_t row0 = t * SCAN_TILE + static_cast<int64_t>(threadIdx.x) * SCAN_ITEMS;
+    int v[SCAN_ITEMS];
+    int sum = 0, amax = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        const bool in = row0 + i < nn;
+        v[i] = in ? rowlen[row0 + i] : 0;
+        amax = max(amax, in ? adj_len[row0 + i] : 0);
+        sum += v[i];
+    }
+    int64_t total;
+    const int64_t pre = block_exclusive_scan(sum, total);  // synchronises the block
+    if (threadIdx.x == 0) lb_publish(look, t, (t == 0 ? LB_INC : LB_AGG) | static_cast<uint64_t>(total));
+    boff[threadIdx.x] = static_cast<int32_t>(pre);
+    bcnt[threadIdx.x] = sum;
+    // launch statistics: 4-, 16- and 32-row windows (tiles and threads start on multiples of 32 and 8 rows)
+    int m[4];
+    const int w4a = v[0] + v[1] + v[2] + v[3], w4b = v[4] + v[5] + v[6] + v[7];
+    m[2] = max(w4a, w4b);
+    m[1] = sum + __shfl_xor(sum, 1, 64);
+    m[0] = m[1] + __shfl_xor(m[1], 2, 64);
+    m[3] = amax;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) m[c] = max(m[c], __shfl_xor(m[c], d, 64));
+        if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = m[c];
+    }
+    if (threadIdx.x < 64) {  // the tile's offset, by wave 0
+        bool timeout = false;
+        int64_t excl = t == 0 ? 0 : lb_exclusive(look, t, timeout);
+        const bool late = __any(timeout);  // wave-uniform
+        excl = late ? 0 : excl;
+        if (threadIdx.x == 0) {
+            if (late) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_SCAN));
+            excl_s = excl;
+            if (t != 0) lb_publish(look, t, LB_INC | static_cast<uint64_t>(excl + total));
+            if (static_cast<int64_t>(t + 1) * SCAN_TILE >= nn) {  // the last tile
+                row_ptr[nn] = static_cast<int32_t>(excl + total);
+                info[2] = excl + total;
+            }
+        }
+    }
     __syncthreads();
-    const int32_t w0 = rp[0];
-    const int W = rp[nr] - w0;
-    for (int w = threadIdx.x; w < W; w += RT) {
-        const int r = upper_pos(rp, nr, w0 + w);
-        col_idx[w0 + w] = colpad[(r0 + r) * MAXROW + (w0 + w - rp[r])];
+    if (threadIdx.x < 4) {
+        const int c = threadIdx.x;
+        int x = red[c][0];
+#pragma unroll
+        for (int w = 1; w < SBS / 64; ++w) x = max(x, red[c][w]);
+        tstat[t * 4 + c] = x;
+    }
+    const int64_t base = excl_s;
+    int64_t o = base + pre;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        if (row0 + i < nn) row_ptr[row0 + i] = static_cast<int32_t>(o);
+        o += v[i];
+    }
+    // columns: each wave moves groups of 4 consecutive row-pattern blocks (wave w takes groups
+    // w, w + 4, ...): the first 128 words of the 4 blocks as 8 loads in flight per lane
+    // (consecutive lanes on consecutive words of a block), then the rest of any longer block
+    const int64_t blk0 = t * SBS;  // the tile's first row-pattern block
+    const int64_t nblk = (nn + RR - 1) / RR;
+    const int nb = static_cast<int>(nblk - blk0 < SBS ? nblk - blk0 : SBS);
+    const int lane = threadIdx.x & 63;
+    int32_t* dst = col_idx + base;
+    for (int g = (threadIdx.x >> 6) * 4; g < nb; g += (SBS / 64) * 4) {
+        int n[4], o[4];
+        const int32_t* src[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int b = min(g + j, nb - 1);
+            n[j] = g + j < nb ? bcnt[b] : 0;
+            o[j] = boff[b];
+            src[j] = colblk + (blk0 + b) * (RR * MAXROW);
+        }
+        int32_t v[4][2];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 2; ++r) v[j][r] = src[j][lane + 64 * r];  // inside the block's region
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+                if (lane + 64 * r < n[j]) dst[o[j] + lane + 64 * r] = v[j][r];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            for (int w = 128 + lane; w < n[j]; w += 64) dst[o[j] + w] = src[j][w];
+    }
+}
+
+// the tiles' statistics into info[3] (NR_BIG windows), info[4] (NR_MID), info[5] (NR_SMALL)
+// and info[7] (elements around a node); one block
+__global__ __launch_bounds__(SBS) void k_row_stats(int64_t tiles, const int32_t* __restrict__ tstat,
+                                                   int64_t* __restrict__ info) {
+    __shared__ int red[4][SBS / 64];
+    int m[4] = {0, 0, 0, 0};
+    for (int64_t t = threadIdx.x; t < tiles; t += SBS) {
+        const int4 v = *reinterpret_cast<const int4*>(tstat + t * 4);
+        m[0] = max(m[0], v.x);
+        m[1] = max(m[1], v.y);
+        m[2] = max(m[2], v.z);
+        m[3] = max(m[3], v.w);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) m[c] = max(m[c], __shfl_xor(m[c], d, 64));
+        if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = m[c];
+    }
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        const int c = threadIdx.x;
+        int x = red[c][0];
+#pragma unroll
+        for (int w = 1; w < SBS / 64; ++w) x = max(x, red[c][w]);
+        info[c < 3 ? 3 + c : 7] = x;
     }
 }
 
@@ -737,49 +908,8 @@ constexpr int NR_SMALL = 4;  // ... when neither fits
 constexpr int NBT = 256;     // threads per block of the numeric kernel
 constexpr int NITEMS = PF_NUMERIC_ITEMS;    // adjacency entries per thread (held in registers)
 static_assert(MAXADJ <= NITEMS * NBT / NR_SMALL, "the small numeric blocks must cover any admissible row");
+static_assert(NR_SMALL == 4 && NR_MID == 16 && NR_BIG == 32, "k_row_offsets measures windows of 4, 16 and 32 rows");
 static_assert(MAXADJ == CSR_MAXADJ, "one padded adjacency layout");
-
-// largest CSR window of one numeric block of NR_BIG, NR_MID and NR_SMALL rows into info[3],
-// info[4] and info[5], and the largest number of elements around a node into info[7].  One
-// thread per block of NR_SMALL rows (two row_ptr reads and its rows' lengths); the windows
-// of NR_MID and NR_BIG rows are sums over 4 and 8 neighbouring lanes.  Reduced in the wave
-// and in the block: one global atomic per value and block.
-static_assert(NR_SMALL == 4 && NR_MID == 4 * NR_SMALL && NR_BIG == 8 * NR_SMALL, "lane sums assume 4/16/32 rows");
-__global__ __launch_bounds__(256) void k_block_stats(int64_t nn, const int32_t* __restrict__ row_ptr,
-                                                     const int32_t* __restrict__ adj_len, int64_t* __restrict__ info) {
-    __shared__ int red[4][4];
-    int m[4] = {0, 0, 0, 0};
-    const int64_t nsb = (nn + NR_SMALL - 1) / NR_SMALL;  // blocks of 4 rows
-    // grid-strided by a multiple of 8 lanes, so 8 neighbouring lanes always hold one big block
-    for (int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; b - threadIdx.x < nsb;
-         b += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const int64_t i0 = b * NR_SMALL;
-        int w = 0;
-        if (i0 < nn) {
-            const int64_t i1 = i0 + NR_SMALL < nn ? i0 + NR_SMALL : nn;
-            w = row_ptr[i1] - row_ptr[i0];
-            for (int64_t i = i0; i < i1; ++i) m[3] = max(m[3], adj_len[i]);
-        }
-        int w16 = w + __shfl_xor(w, 1, 64);
-        w16 += __shfl_xor(w16, 2, 64);
-        const int w32 = w16 + __shfl_xor(w16, 4, 64);
-        m[2] = max(m[2], w);
-        m[1] = max(m[1], w16);
-        m[0] = max(m[0], w32);
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) m[c] = max(m[c], __shfl_xor(m[c], d, 64));
-        if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = m[c];
-    }
-    __syncthreads();
-    if (threadIdx.x < 4) {
-        const int c = threadIdx.x;
-        const int v = max(max(red[c][0], red[c][1]), max(red[c][2], red[c][3]));
-        atomicMax(reinterpret_cast<unsigned long long*>(info + (c < 3 ? 3 + c : 7)), static_cast<unsigned long long>(v));
-    }
-}
 
 template <typename T>
 struct alignas(16) Vec4 {  // 16-byte LDS reads; the layout keeps Vec4 arrays 16-byte aligned
@@ -1259,8 +1389,8 @@ pf_status numeric_launch_many(int dim, pf_dtype prec, int nr, const NumericJob* 
 }
 
 size_t csr_bytes(const pf_csr* c) {
-    return static_cast<size_t>(c->cap_adj_len + c->cap_row_ptr + c->cap_cnt + c->cap_adj + c->cap_nnz + c->cap_colpad) * 4 +
-           static_cast<size_t>(c->cap_pk) * 4 + static_cast<size_t>(c->cap_bsum + c->cap_info + c->cap_work) * 8 +
+    return static_cast<size_t>(c->cap_adj_len + c->cap_row_ptr + c->cap_cnt + c->cap_adj + c->cap_nnz + c->cap_colblk) * 4 +
+           static_cast<size_t>(c->cap_pk) * 4 + static_cast<size_t>(c->cap_bsum + c->cap_info + c->cap_work + c->cap_look) * 8 +
            static_cast<size_t>(c->cap_fcount + c->cap_bcount + c->cap_fptr + c->cap_bptr + c->cap_faces + c->cap_fel +
                                c->cap_bfaces + c->cap_bel + c->cap_dpos) * 4 + static_cast<size_t>(c->cap_finfo) * 8 +
            static_cast<size_t>(c->cap_esign);
@@ -1304,7 +1434,8 @@ void pf_csr_destroy(pf_csr* c) {
     (void)hipFree(c->row_ptr);
     (void)hipFree(c->col_idx);
     (void)hipFree(c->cnt);
-    (void)hipFree(c->colpad);
+    (void)hipFree(c->colblk);
+    (void)hipFree(c->look);
     (void)hipFree(c->bsum);
     (void)hipFree(c->info);
     (void)hipFree(c->work);
@@ -1320,11 +1451,10 @@ namespace {
 pf_status collect_stage_times(pf_csr* c) {
     if (!c->pending) return PF_OK;
     c->pending = false;
-    PF_HIP_TRY(hipEventSynchronize(c->ev[5]));
-    const int from[PF_CSR_STAGES] = {0, 1, 2, 4}, to[PF_CSR_STAGES] = {1, 2, 3, 5};
+    PF_HIP_TRY(hipEventSynchronize(c->ev[PF_CSR_STAGES]));
     for (int k = 0; k < PF_CSR_STAGES; ++k) {
         float ms = 0.0f;
-        PF_HIP_TRY(hipEventElapsedTime(&ms, c->ev[from[k]], c->ev[to[k]]));
+        PF_HIP_TRY(hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]));
         c->stage_ms[k] += ms;
     }
     ++c->stage_calls;
@@ -1386,27 +1516,38 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     const unsigned gtile = static_cast<unsigned>(std::max<int64_t>(ceil_div(m, AG_TILE), 1));
     if (m > 0)
         hipLaunchKernelGGL(k_scatter, dim3(gtile), dim3(AG_BS), 0, s, elems, m, nlb, nn, c->adj_len, c->adj, c->info);
-    const unsigned grows = static_cast<unsigned>(ceil_div(nn, RR));
-    if ((st = grow(c->colpad, c->cap_colpad, nn * MAXROW))) return st;
+    const int64_t grows = ceil_div(nn, RR);
+    const int64_t tiles = ceil_div(nn, SCAN_TILE);
+    // nnz is known only after the pattern: col_idx holds MAXROW columns per row
+    if ((st = grow(c->colblk, c->cap_colblk, std::max<int64_t>(grows * RR * MAXROW, 1)))) return st;
+    if ((st = grow(c->col_idx, c->cap_nnz, std::max<int64_t>(nn * MAXROW, 1)))) return st;
     if ((st = grow(c->dpos, c->cap_dpos, nn + 1))) return st;
+    // tile descriptors, then 4 int32 statistics per tile
+    if ((st = grow(c->look, c->cap_look, 3 * std::max<int64_t>(tiles, 1) + 1))) return st;
     if ((st = mark(c, 1, s))) return st;
     if (nn > 0) {
+        const unsigned g = static_cast<unsigned>(grows);
         if (nlb == 4)
-            hipLaunchKernelGGL((k_pattern<4>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
-                               c->colpad, c->pk, c->dpos, c->info);
+            hipLaunchKernelGGL((k_pattern<4>), dim3(g), dim3(RT), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
+                               c->colblk, c->pk, c->dpos, c->info);
         else
-            hipLaunchKernelGGL((k_pattern<3>), dim3(grows), dim3(RT), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
-                               c->colpad, c->pk, c->dpos, c->info);
+            hipLaunchKernelGGL((k_pattern<3>), dim3(g), dim3(RT), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
+                               c->colblk, c->pk, c->dpos, c->info);
     }
     if ((st = mark(c, 2, s))) return st;
-    if ((st = scan(c->cnt, nn, c->row_ptr, c->bsum, c->info + 2, s))) return st;
     if (nn > 0) {
-        // few blocks: every block ends with global atomics on the same four words
-        const unsigned g = static_cast<unsigned>(std::min<int64_t>(ceil_div(ceil_div(nn, NR_SMALL), 256), 256));
-        hipLaunchKernelGGL(k_block_stats, dim3(g), dim3(256), 0, s, nn, c->row_ptr, c->adj_len, c->info);
+        hipLaunchKernelGGL(k_fill_i64, dim3(flat_grid(tiles)), dim3(SBS), 0, s, reinterpret_cast<int64_t*>(c->look),
+                           tiles, int64_t(0));
+        int32_t* tstat = reinterpret_cast<int32_t*>(c->look + ((tiles + 1) & ~int64_t(1)));  // 16-byte aligned
+        hipLaunchKernelGGL(k_row_offsets, dim3(static_cast<unsigned>(tiles)), dim3(SBS), 0, s, nn, c->cnt, c->adj_len,
+                           c->colblk, c->row_ptr, c->col_idx, c->look, tstat, c->info);
+        hipLaunchKernelGGL(k_row_stats, dim3(1), dim3(SBS), 0, s, tiles, tstat, c->info);
+    } else {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, c->row_ptr, int64_t(1), 0);
     }
     if ((st = mark(c, 3, s))) return st;
     if ((st = launch_check("pf_csr_symbolic"))) return st;
+    c->pending = c->timing;
     int64_t info[8];
     PF_HIP_TRY(hipMemcpyAsync(info, c->info, sizeof(info), hipMemcpyDeviceToHost, s));
     PF_HIP_TRY(hipStreamSynchronize(s));
@@ -1414,16 +1555,9 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     if (info[0] & ERR_ROW)
         return fail(PF_ELIMIT, "pf_csr_symbolic: a node belongs to more than 64 elements or a row has more than 64 "
                                "nonzeros");
+    if (info[0] & ERR_SCAN) return fail(PF_EINVAL, "pf_csr_symbolic: the row offsets could not be formed");
     if (info[2] >= INT32_MAX) return fail(PF_ELIMIT, "pf_csr_symbolic: nnz must be < 2^31");
     const int64_t nnz = info[2];
-    if ((st = grow(c->col_idx, c->cap_nnz, nnz))) return st;
-    if ((st = mark(c, 4, s))) return st;
-    if (nn > 0)
-        hipLaunchKernelGGL(k_compact, dim3(static_cast<unsigned>(ceil_div(nn, CR))), dim3(RT), 0, s, nn, c->row_ptr,
-                           c->colpad, c->col_idx);
-    if ((st = mark(c, 5, s))) return st;
-    if ((st = launch_check("pf_csr_symbolic cols"))) return st;
-    c->pending = c->timing;
     c->dim = dim;
     c->nlb = nlb;
     c->nn = nn;

@@ -74,9 +74,10 @@ int64_t nnz_bound(const pf_job& j) {
 size_t topo_estimate(const pf_job& j) {
     const int64_t nlb = j.dim + 1;
     return static_cast<size_t>(j.ne * nlb * 4)                                     // elems
-           + static_cast<size_t>(12 * (j.nn + 1) + 512 * j.nn + 4 * nnz_bound(j))  // structure (padded adjacency)
-           + static_cast<size_t>(256 * j.nn)                                         // padded rows (scratch)
-           + 4096;
+           + static_cast<size_t>(16 * (j.nn + 1) + 512 * j.nn)  // row arrays, padded adjacency and slot words
+           + static_cast<size_t>(256 * (j.nn + 8))             // col_idx (sized for 64 columns a row)
+           + static_cast<size_t>(256 * (j.nn + 8))             // columns of the row-pattern blocks (scratch)
+           + static_cast<size_t>(j.nn / 256) + 4096;
 }
 
 size_t job_estimate(const pf_job& j, int64_t nnz) {

@@ -327,7 +327,7 @@ class Csr:
         _chk(_lib.pf_csr_info(self._h, C.byref(nn), C.byref(nnz), C.byref(rp), C.byref(ci)), "pf_csr_info")
         return nn.value, nnz.value, rp.value, ci.value
 
-    CSR_STAGES = ("adjacency", "pattern", "scan", "compact")
+    CSR_STAGES = ("adjacency", "pattern", "row offsets")
 
     def set_timing(self, on=True):
         """Record per-stage events in every later symbolic call (and clear the sums)."""
