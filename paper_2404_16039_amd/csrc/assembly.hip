@@ -273,8 +273,10 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
 
 // ---------------------------------------------------------------------------- row pattern
 // Row patterns are built block-cooperatively: a block of RR rows inserts the nodes of all
-// its adjacency entries into per-row open-addressing tables in LDS; the first inserter of a
-// node appends it to its row's list.  Lists are then ranked (sorted) in parallel and the
+// its adjacency entries into per-row open-addressing tables in LDS (linear probing, one
+// compare-and-swap per probe, which returns the slot's node whether or not it stored the
+// new one; the first probes of all of a lane's inserts are issued together); the first
+// inserter of a node appends it to its row's list.  Lists are then ranked (sorted) in parallel and the
 // ranks give both col_idx and, for every adjacency entry, the row positions ("slots") of the
 // element's other nodes.  Entries are dealt to lanes row-interleaved (entry j of row r is
 // item r + nr j), so the lanes of one instruction insert into different rows' tables.
@@ -287,7 +289,7 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
 constexpr int RR = PF_PATTERN_RR;  // rows per block in the row-pattern kernels
 constexpr int RT = PF_PATTERN_RT;  // threads per block
 constexpr int RSUB = MAXROW;     // slots of one row's table: every admissible row fits
-constexpr int RBATCH = 4;        // entries gathered together per thread (independent loads)
+constexpr int RBATCH = 2;        // entries gathered together per thread (independent loads)
 static_assert(RR <= 64, "the row-count prefix runs in one wave");
 static_assert(RT >= RR && RT >= 64, "one thread per row and a full first wave");
 
@@ -295,24 +297,6 @@ __device__ __forceinline__ int rsub_hash(int32_t v) {
     return static_cast<int>((static_cast<uint32_t>(v) * 2654435761u) >> 26);  // 6 bits
 }
 static_assert(RSUB == 64, "rsub_hash yields 6 bits");
-
-// find or insert v in a row table; returns the slot (or -1 when the table is full) and
-// whether this call inserted it.  One compare-and-swap per probe: it returns the slot's
-// node whether or not it stored v.
-__device__ __forceinline__ int rsub_insert(int32_t* tab, int32_t v, bool& fresh) {
-    int h = rsub_hash(v);
-#pragma unroll 1
-    for (int probe = 0; probe < RSUB; ++probe) {
-        const int32_t cur = atomicCAS(tab + h, -1, v);
-        if (cur == -1 || cur == v) {
-            fresh = cur == -1;
-            return h;
-        }
-        h = (h + 1) & (RSUB - 1);
-    }
-    fresh = false;
-    return -1;
-}
 
 __device__ __forceinline__ int upper_pos(const int32_t* v, int n, int32_t x) {
     // last index r in [0, n) with v[r] <= x (v ascending, v[0] <= x)
@@ -343,6 +327,7 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
                                                 int64_t* __restrict__ info) {
     constexpr int NO = NLB - 1;               // other nodes of an element
     __shared__ int32_t tab[RR * RSUB];       // node ids, -1 empty
+    __shared__ int32_t guard[RT];            // never -1: the first probes of empty items
     __shared__ int32_t seg[RR * MAXROW];      // each row's nodes, insertion order
     __shared__ int32_t srt[RR * MAXROW];      // the block's columns in CSR order
     __shared__ uint8_t seg_h[RR * MAXROW];    // table slot of each list item
@@ -356,6 +341,7 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
     const int nr = static_cast<int>((r0 + RR < nn) ? RR : nn - r0);
     const int64_t e0 = r0 * MAXADJ;  // the block's adjacency rows start here (padded layout)
     for (int h = threadIdx.x; h < RR * RSUB; h += RT) tab[h] = -1;
+    guard[threadIdx.x] = -2;
     if (threadIdx.x == 0) maxl = 0;
     __syncthreads();
     if (threadIdx.x < RR) {
@@ -411,29 +397,50 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
 #pragma unroll
                 for (int k = 0; k < NLB; ++k) nd[b][k] = elems[static_cast<int64_t>(aq[b] >> 2) * NLB + k];
         }
+        // the first probe of every insert of the lane, all in flight together; an empty item
+        // probes the lane's own guard word (never -1, so nothing is stored)
+        int32_t ov[RBATCH][NO], cq[RBATCH][NO];
+        int hq[RBATCH][NO];
+#pragma unroll
+        for (int b = 0; b < RBATCH; ++b) {
+            const int a = aq[b] & 3;
+#pragma unroll
+            for (int k = 0; k < NO; ++k) {
+                ov[b][k] = k < a ? nd[b][k] : nd[b][k + 1];
+                hq[b][k] = rsub_hash(ov[b][k]);
+                int32_t* w = rq[b] >= 0 ? tab + rq[b] * RSUB + hq[b][k] : guard + threadIdx.x;
+                cq[b][k] = atomicCAS(w, -1, ov[b][k]);
+            }
+        }
 #pragma unroll
         for (int b = 0; b < RBATCH; ++b) {
             const int r = rq[b];
             if (r < 0) continue;
             int32_t* rt = tab + r * RSUB;
-            const int a = aq[b] & 3;
-            int32_t o[NO];
-#pragma unroll
-            for (int k = 0; k < NO; ++k) o[k] = k < a ? nd[b][k] : nd[b][k + 1];
-            uint32_t word = static_cast<uint32_t>(a);
+            uint32_t word = static_cast<uint32_t>(aq[b] & 3);
 #pragma unroll
             for (int k = 0; k < NO; ++k) {
-                bool fresh;
-                const int h = rsub_insert(rt, o[k], fresh);
+                const int32_t v = ov[b][k];
+                int h = hq[b][k];
+                int32_t cur = cq[b][k];
+#pragma unroll 1
+                for (int probe = 1; cur != -1 && cur != v; ++probe) {  // taken: linear probing
+                    if (probe == RSUB) {
+                        h = -1;
+                        break;
+                    }
+                    h = (h + 1) & (RSUB - 1);
+                    cur = atomicCAS(rt + h, -1, v);
+                }
                 if (h < 0) {
                     bad = true;
                     continue;
                 }
                 word |= static_cast<uint32_t>(h) << (2 + 6 * k);
-                if (fresh) {
+                if (cur == -1) {
                     const int p = atomicAdd(cnt + r, 1);
                     if (p < MAXROW) {
-                        seg[r * MAXROW + p] = o[k];
+                        seg[r * MAXROW + p] = v;
                         seg_h[r * MAXROW + p] = static_cast<uint8_t>(h);
                     } else {
                         bad = true;
