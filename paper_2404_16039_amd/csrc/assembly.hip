@@ -161,9 +161,11 @@ __global__ __launch_bounds__(SBS) void k_scan_apply(const int32_t* __restrict__ 
 // Node -> element adjacency by counting sort.  Each block aggregates a tile of AG_TILE
 // (element, local node) entries in an LDS hash table keyed by node id, so a node that
 // appears several times in the tile (neighbouring elements share nodes) costs one global
-// atomic per tile instead of one per entry.
+// atomic per tile instead of one per entry.  The table uses linear probing with one
+// compare-and-swap per probe; the first probes of all of a lane's entries are issued
+// together.
 #ifndef PF_SCATTER_BS
-#define PF_SCATTER_BS 128
+#define PF_SCATTER_BS 256
 #endif
 #ifndef PF_SCATTER_ITEMS
 #define PF_SCATTER_ITEMS 4
@@ -177,20 +179,6 @@ static_assert(AG_BITS > 0, "the scatter table holds 1024..8192 slots");
 
 __device__ __forceinline__ int ag_hash(int32_t node) {
     return static_cast<int>((static_cast<uint32_t>(node) * 2654435761u) >> (32 - AG_BITS));
-}
-
-// insert `node` (or find it) in the block's table; returns its slot, fresh = this call
-// inserted it
-__device__ __forceinline__ int ag_insert(int32_t* keys, int32_t node, bool& fresh) {
-    int h = ag_hash(node);
-    while (true) {
-        const int32_t k = atomicCAS(keys + h, -1, node);
-        if (k == -1 || k == node) {
-            fresh = k == -1;
-            return h;
-        }
-        h = (h + 1) & (AG_HASH - 1);
-    }
 }
 
 // Scatter (element << 2 | local index) into each node's padded row (MAXADJ entries).  One
@@ -208,30 +196,45 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
     __shared__ int32_t vals[AG_HASH];
     __shared__ int32_t uniq[AG_TILE];  // table slots of the tile's distinct nodes
     __shared__ int32_t nuniq;
+    __shared__ int32_t guard[AG_BS];  // never -1: the first probes of empty entries
     for (int h = threadIdx.x; h < AG_HASH; h += AG_BS) {
         keys[h] = -1;
         vals[h] = 0;
     }
+    guard[threadIdx.x] = -2;
     if (threadIdx.x == 0) nuniq = 0;
     __syncthreads();
     const int64_t t0 = static_cast<int64_t>(blockIdx.x) * AG_TILE;
     int slot[AG_ITEMS];
+    int32_t node[AG_ITEMS], cur[AG_ITEMS];
     bool bad = false;
+#pragma unroll
+    for (int q = 0; q < AG_ITEMS; ++q) {  // all loads in flight together
+        const int64_t t = t0 + q * AG_BS + threadIdx.x;
+        node[q] = elems[t < m ? t : m - 1];
+    }
+    // first probes of all the lane's entries together; an entry outside the tile or with a
+    // bad node id probes the lane's guard word (never -1, so nothing is stored)
 #pragma unroll
     for (int q = 0; q < AG_ITEMS; ++q) {
         const int64_t t = t0 + q * AG_BS + threadIdx.x;
-        slot[q] = -1;
-        if (t < m) {
-            const int32_t node = elems[t];
-            if (node >= 0 && node < nn) {
-                bool fresh;
-                slot[q] = ag_insert(keys, node, fresh);
-                if (fresh) uniq[atomicAdd(&nuniq, 1)] = slot[q];
-                atomicAdd(vals + slot[q], 1);
-            } else {
-                bad = true;
-            }
+        const bool ok = t < m && node[q] >= 0 && node[q] < nn;
+        bad = bad || (t < m && !ok);
+        slot[q] = ok ? ag_hash(node[q]) : -1;
+        cur[q] = atomicCAS(ok ? keys + slot[q] : guard + threadIdx.x, -1, node[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < AG_ITEMS; ++q) {
+        if (slot[q] < 0) continue;
+        int h = slot[q];
+        int32_t c = cur[q];
+        while (c != -1 && c != node[q]) {  // taken: linear probing (the table is at most half full)
+            h = (h + 1) & (AG_HASH - 1);
+            c = atomicCAS(keys + h, -1, node[q]);
         }
+        slot[q] = h;
+        if (c == -1) uniq[atomicAdd(&nuniq, 1)] = h;
+        atomicAdd(vals + h, 1);
     }
     if (bad) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_INDEX));
     __syncthreads();
