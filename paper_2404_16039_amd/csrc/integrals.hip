@@ -20,41 +20,54 @@ struct Rule {
 };
 
 // X[(c nq + q) dim + i] = sum_j lam_qj coords[cells[c nv + j] dim + i]; NaN for a bad node.
-// A block makes PB consecutive (cell, point) pairs: each lane computes pairs into LDS, then
-// the block writes its contiguous run of PB x dim values with consecutive lanes on
-// consecutive words (coalesced); the lanes of one cell read its node coordinates from the
-// same cache lines.
-constexpr int PB = 512;
+// A block takes pc consecutive cells (pc = min(PC_MAX, PB / nq), passed by the host): it
+// stages their node coordinates (a bad node's as NaN, which every point of its cell then
+// carries) and the rule in LDS with one load per value, then thread k makes output word k of
+// the block's contiguous run of pc nq dim values (one coordinate of one point), so the
+// stores are coalesced with no staging of the results.
+#ifndef PF_POINTS_BS
+#define PF_POINTS_BS 512
+#endif
+#ifndef PF_POINTS_PB
+#define PF_POINTS_PB 8192
+#endif
+constexpr int SPT = PF_POINTS_BS;  // threads per block
+constexpr int PB = PF_POINTS_PB;   // points per block at most
+#ifndef PF_POINTS_CELLS
+#define PF_POINTS_CELLS 256
+#endif
+constexpr int PC_MAX = PF_POINTS_CELLS;  // cells per block at most
 template <int DIM, int NV>
-__global__ __launch_bounds__(IBS) void k_simplex_points(int64_t nn, const double* __restrict__ coords, int64_t nc,
-                                                        const int32_t* __restrict__ cells, int nq, Rule rule,
+__global__ __launch_bounds__(SPT) void k_simplex_points(int64_t nn, const double* __restrict__ coords, int64_t nc,
+                                                        const int32_t* __restrict__ cells, int nq, int pc, Rule rule,
                                                         double* __restrict__ X) {
-    __shared__ double buf[PB * DIM];
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * PB;
-    const int64_t total = nc * nq;
-    const int np = static_cast<int>(total - base < PB ? total - base : PB);
-    for (int u = threadIdx.x; u < np; u += IBS) {
-        const int64_t t = base + u;
-        const int64_t c = t / nq;
-        const int q = static_cast<int>(t - c * nq);
-        double x[DIM];
-        bool ok = true;
-#pragma unroll
-        for (int j = 0; j < NV; ++j) {
-            const int32_t v = cells[c * NV + j];
-            ok = ok && v >= 0 && v < nn;
-            const double l = rule.lam[q * NV + j];
-#pragma unroll
-            for (int i = 0; i < DIM; ++i) {
-                const double p = ok ? coords[static_cast<int64_t>(v) * DIM + i] : 0.0;
-                x[i] = j == 0 ? l * p : __builtin_fma(l, p, x[i]);
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < DIM; ++i) buf[u * DIM + i] = ok ? x[i] : static_cast<double>(NAN);
+    __shared__ double xs[PC_MAX * NV * DIM];
+    __shared__ double lam[PF_RULE_MAX * NV];
+    const int64_t c0 = static_cast<int64_t>(blockIdx.x) * pc;
+    const int ncb = static_cast<int>(nc - c0 < pc ? nc - c0 : pc);
+    for (int u = threadIdx.x; u < ncb * NV * DIM; u += SPT) {
+        const int c = u / (NV * DIM), j = (u / DIM) % NV, i = u % DIM;
+        const int32_t v = cells[(c0 + c) * NV + j];
+        xs[u] = v >= 0 && v < nn ? coords[static_cast<int64_t>(v) * DIM + i] : static_cast<double>(NAN);
     }
+    for (int u = threadIdx.x; u < nq * NV; u += SPT) lam[u] = rule.lam[u];
     __syncthreads();
-    for (int k = threadIdx.x; k < np * DIM; k += IBS) X[base * DIM + k] = buf[k];
+    const float rq = 1.0f / static_cast<float>(nq);
+    double* out = X + c0 * nq * DIM;
+    const int nw = ncb * nq * DIM;
+    for (int k = threadIdx.x; k < nw; k += SPT) {
+        const int u = k / DIM, i = k - u * DIM;  // point u of the block, coordinate i
+        int c = static_cast<int>(static_cast<float>(u) * rq);  // u / nq (u < PB: one correction step)
+        c += (c + 1) * nq <= u;
+        c -= c * nq > u;
+        const int q = u - c * nq;
+        const double* xc = xs + c * (NV * DIM) + i;
+        const double* lq = lam + q * NV;
+        double x = lq[0] * xc[0];
+#pragma unroll
+        for (int j = 1; j < NV; ++j) x = __builtin_fma(lq[j], xc[j * DIM], x);
+        out[k] = x;
+    }
 }
 
 // Block sums of sizes[c] * f_c, f_c = sum_i n_ci sum_q w_q fip[c, q, i] (n = 1 without
@@ -124,14 +137,15 @@ pf_status pf_simplex_points(int dim, int nv, int64_t nn, const double* coords, i
     Rule rule{};
     for (int i = 0; i < nq * nv; ++i) rule.lam[i] = lam[i];
     hipStream_t s = as_stream(stream);
-    const unsigned g = static_cast<unsigned>(ceil_div(nc * nq, PB));
+    const int pc = std::max(1, std::min(PC_MAX, PB / nq));  // cells per block: pc nq <= PB points
+    const unsigned g = static_cast<unsigned>(ceil_div(nc, pc));
     if (dim == 3) {
-        if (nv == 4) hipLaunchKernelGGL((k_simplex_points<3, 4>), dim3(g), dim3(IBS), 0, s, nn, coords, nc, cells, nq, rule, X);
-        else if (nv == 3) hipLaunchKernelGGL((k_simplex_points<3, 3>), dim3(g), dim3(IBS), 0, s, nn, coords, nc, cells, nq, rule, X);
-        else hipLaunchKernelGGL((k_simplex_points<3, 2>), dim3(g), dim3(IBS), 0, s, nn, coords, nc, cells, nq, rule, X);
+        if (nv == 4) hipLaunchKernelGGL((k_simplex_points<3, 4>), dim3(g), dim3(SPT), 0, s, nn, coords, nc, cells, nq, pc, rule, X);
+        else if (nv == 3) hipLaunchKernelGGL((k_simplex_points<3, 3>), dim3(g), dim3(SPT), 0, s, nn, coords, nc, cells, nq, pc, rule, X);
+        else hipLaunchKernelGGL((k_simplex_points<3, 2>), dim3(g), dim3(SPT), 0, s, nn, coords, nc, cells, nq, pc, rule, X);
     } else {
-        if (nv == 3) hipLaunchKernelGGL((k_simplex_points<2, 3>), dim3(g), dim3(IBS), 0, s, nn, coords, nc, cells, nq, rule, X);
-        else hipLaunchKernelGGL((k_simplex_points<2, 2>), dim3(g), dim3(IBS), 0, s, nn, coords, nc, cells, nq, rule, X);
+        if (nv == 3) hipLaunchKernelGGL((k_simplex_points<2, 3>), dim3(g), dim3(SPT), 0, s, nn, coords, nc, cells, nq, pc, rule, X);
+        else hipLaunchKernelGGL((k_simplex_points<2, 2>), dim3(g), dim3(SPT), 0, s, nn, coords, nc, cells, nq, pc, rule, X);
     }
     return launch_check("pf_simplex_points");
 }
