@@ -23,8 +23,9 @@ Other workloads (one JSON line each, same contract):
                      128^3 cube mesh, FP32, fields at the 4 points of the degree-2 rule
   --workload faces   all faces of the 128^3 cube mesh with the normals of all of them, and
                      GI volume / surface integrals of the divergence theorem
-  --workload p2      P2 element stiffness and mass matrices (10 x 10) on the 64^3 cube mesh
-                     (2,146,689 P2 nodes), coefficients at 27 points
+  --workload p2      global P2 stiffness and mass matrices on the 64^3 cube mesh (2,146,689
+                     P2 nodes), coefficients at 27 points: the 10 x 10 element pages, the P2
+                     CSR structure and sparse() of the pages
   --workload serve   a Poisson stream of assembly jobs (200 jobs/s, 2-D FP64 / 3-D FP32,
                      1e3..2e6 elements) through the serving loop: p50/p99 latency and
                      throughput, fused + resident structures vs one launch per job without
@@ -51,7 +52,8 @@ ENERGY_SOURCES = ["energy.hip", "p1elem.hpp", "smallmat.hpp", "common.hpp", "exa
 FACES_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "faces_cube128_traffic.json")
 FACES_SOURCES = ["assembly.hip", "integrals.hip", "common.hpp"]
 P2_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "p2_cube64_traffic.json")
-P2_SOURCES = ["p2.hip", "p1elem.hpp", "smallmat.hpp", "common.hpp"]
+P2_SOURCES = ["p2.hip", "sparse.hip", "assembly.hip", "p1elem.hpp", "smallmat.hpp", "common.hpp", "exact.hpp",
+              "internal.hpp"]
 BATCH_SOURCES = ["batch.hip", "smallmat.hpp", "common.hpp"]
 
 
@@ -539,7 +541,8 @@ def run_faces(args):
 
 
 def run_p2(args):
-    """P2 element stiffness and mass matrices of the 3-D benchmark (section 3.6)."""
+    """P2 stiffness and mass matrices of the 3-D benchmark (section 3.6): element pages, the
+    P2 structure and sparse() of the pages, i.e. the global K and M as the P2 listings return."""
     import numpy as np
     import torch
 
@@ -562,48 +565,92 @@ def run_p2(args):
     M = torch.empty(ne * 100, dtype=torch.float32, device="cuda")
     fb = L.fallback(1e-3 / n ** 3, 1e6, True)
     _calib_copy(args.copy_calib_mib)
+    csr = L.Csr().symbolic_p2(3, nn2, te)
+    nnz = csr.info()[1]
+    vK = torch.empty(nnz, dtype=torch.float32, device="cuda")
+    vM = torch.empty(nnz, dtype=torch.float32, device="cuda")
     t_k = _timed(lambda: L.p2_elements(L.F32, tc, te, rule, None, cKq=cq, K3D=K, fb=fb, stream=stream), args.steps,
                  args.warmup, stream)
     t_m = _timed(lambda: L.p2_elements(L.F32, tc, te, None, rule, cMq=cq, M3D=M, fb=fb, stream=stream), args.steps,
                  args.warmup, stream)
     t_km = _timed(lambda: L.p2_elements(L.F32, tc, te, rule, rule, cKq=cq, cMq=cq, K3D=K, M3D=M, fb=fb,
                                         stream=stream), args.steps, args.warmup, stream)
-    ms = float(np.mean(t_km))
-    # algorithmic bytes per launch (K and M together): the 10 node ids 40 B/tet, FP64 vertex
-    # coordinates 24 B per vertex node, the coefficient at 27 points for K and for M
-    # (2 x 108 B/tet), the two FP32 10 x 10 pages 800 B/tet
-    alg = 40 * ne + 24 * coords.shape[0] + 2 * 4 * nq * ne + 800 * ne
-    gbs = alg / (ms * 1e-3) / 1e9
+    t_sp = _timed(lambda: csr.assemble_pages(L.F32, K, M, vK, vM, stream=stream), args.steps, args.warmup, stream)
+
+    def step():  # the whole P2 assembly: pages, structure, sparse()
+        L.p2_elements(L.F32, tc, te, rule, rule, cKq=cq, cMq=cq, K3D=K, M3D=M, fb=fb, stream=stream)
+        csr.symbolic_p2(3, nn2, te, stream=stream)
+        csr.assemble_pages(L.F32, K, M, vK, vM, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    csr.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stage_ms, stage_calls = csr.stage_times()
+    csr.set_timing(False)
+    ms_step = wall * 1e3 / args.steps
+    # algorithmic bytes per launch:
+    #  pages (K and M): the 10 node ids 40 B/tet, FP64 vertex coordinates 24 B per vertex node, the
+    #    coefficient at 27 points for K and for M (2 x 108 B/tet), two FP32 10 x 10 pages 800 B/tet
+    #  scatter: node ids 40 B/tet read, adjacency entries 40 B/tet written, 4 B/node counts
+    #  pattern: adjacency 40 B/tet, node ids once 40 B/tet, position words 80 B/tet, 4 B/nonzero
+    #    (columns), 8 B/node (row lengths, diagonal positions)
+    #  row offsets: 12 B/node, 8 B/nonzero;  sparse(): adjacency + position words 120 B/tet, the
+    #    pages once 800 B/tet, 12 B/node, FP32 K and M 8 B/nonzero
+    nv = coords.shape[0]
+    kernels = {
+        "k_p2_elem<3,float> K+M": (float(np.mean(t_km)), 40 * ne + 24 * nv + 2 * 4 * nq * ne + 800 * ne),
+        "k_scatter<4> (P2)": (stage_ms["adjacency"] / stage_calls, 80 * ne + 4 * nn2),
+        "k_pattern_p2<10>": (stage_ms["pattern"] / stage_calls, 160 * ne + 4 * nnz + 8 * nn2),
+        "k_row_offsets<1024,4>": (stage_ms["row offsets"] / stage_calls, 12 * nn2 + 8 * nnz),
+        "k_assemble_pages<10,P2,float>": (float(np.mean(t_sp)), 920 * ne + 12 * nn2 + 8 * nnz),
+    }
+    dominant = max(kernels, key=lambda k: kernels[k][0])
+
+    def roofline(name):
+        kms, alg = kernels[name]
+        gbs = alg / (kms * 1e-3) / 1e9
+        return {"kernel": name, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS,
+                "traffic": traffic_of(P2_TRAFFIC_FILE, P2_SOURCES, kernel=name.split(" ")[0], n=n),
+                "algorithmic_bytes_per_launch": alg, "launch_us": round(kms * 1e3, 1)}
+
     out = {
-        "metric": "P2 tet elements/s (element stiffness + mass matrices, 10 x 10 each)",
-        "value": ne / (ms * 1e-3), "unit": "tets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "metric": "P2 tet elements/s (global stiffness + mass matrices: element pages, structure, sparse())",
+        "value": ne / (ms_step * 1e-3), "unit": "tets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "3-D P2 tets: unit cube, %d^3 cubes x 6 Kuhn tets, jitter 0.15 h, mid-edge nodes; "
-                               "K3D and M3D (FP32) with c_K = c_M = exp(x1+x2+x3) at the 27 points of a degree-5 "
-                               "rule" % n, "tets": ne, "nodes_p2": nn2},
-        "kernels_us": {"k_p2_elem<3,float> K": round(float(np.mean(t_k)) * 1e3, 1),
-                       "k_p2_elem<3,float> M": round(float(np.mean(t_m)) * 1e3, 1),
-                       "k_p2_elem<3,float> K+M": round(ms * 1e3, 1)},
-        "roofline": {"kernel": "k_p2_elem<3,float> (K and M)", "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                     "traffic": traffic_of(P2_TRAFFIC_FILE, P2_SOURCES, kernel="k_p2_elem<3,float>", n=n),
-                     "algorithmic_bytes_per_launch": alg, "launch_us": round(ms * 1e3, 1)},
+                               "global K and M (FP32, CSR) with c_K = c_M = exp(x1+x2+x3) at the 27 points of a "
+                               "degree-5 rule" % n, "tets": ne, "nodes_p2": nn2, "nnz": nnz},
+        "kernels_us": dict({k: round(v[0] * 1e3, 1) for k, v in kernels.items()},
+                           **{"k_p2_elem<3,float> K": round(float(np.mean(t_k)) * 1e3, 1),
+                              "k_p2_elem<3,float> M": round(float(np.mean(t_m)) * 1e3, 1)}),
+        "roofline": roofline(dominant),
+        "rooflines": {k: roofline(k) for k in kernels},
         "paper_context": {"what": "P2 K and M in MATLAB at 2,146,689 nodes (3-D level 6), hardware not stated",
                           "K_s": 87.6, "M_s": 16.4},
     }
     if not args.no_cpu_baseline:
         import oracle
-        cn = 48
+        cn = 32
         cc, ce, _ = gen.cube_mesh(cn, jitter=0.15, with_faces=False)
         cc2, ce2, _ = gen.p2_mesh(cc, ce)
         cqq = np.exp(oracle.simplex_points(cc, ce, rule[0]).sum(axis=-1))
         t1 = time.perf_counter()
-        oracle.p2_elements(cc2, ce2, rule, rule, cqq, cqq)
+        pg = oracle.p2_elements(cc2, ce2, rule, rule, cqq, cqq)
+        oracle.assemble(ce2, cc2.shape[0], pg["K3D"], pg["M3D"])
         dt = time.perf_counter() - t1
         out["cpu_baseline"] = {"value": ce.shape[0] / dt, "unit": "tets/s", "cores": 1, "kind": "oracle",
-                               "sample": "FP64 oracle P2 K3D + M3D (27-point rules, error scales included), single "
-                                         "thread, %d^3 Kuhn mesh, %d tets, %.1f s" % (cn, ce.shape[0], dt)}
+                               "sample": "FP64 oracle P2 K3D + M3D (27-point rules, error scales included) and "
+                                         "sparse() of both by sorting, single thread, %d^3 Kuhn mesh, %d tets, "
+                                         "%.1f s" % (cn, ce.shape[0], dt)}
+    csr.close()
     print(json.dumps(out))
 
 

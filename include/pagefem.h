@@ -202,6 +202,28 @@ pf_status pf_csr_create(pf_csr** out);
 pf_status pf_csr_symbolic(pf_csr* csr, int dim, int64_t nn, int64_t ne, const int32_t* elems,
                           void* stream);
 
+/* Build the CSR structure of a P2 mesh (section 3.6: the global matrices of the
+ * stiffness_matrixP2 / mass_matrixP2 listings): elems2 ne x nlb2 int32 (nlb2 = 6 for dim 2,
+ * 10 for dim 3) as for pf_p2_elements; every pair of nodes that share an element is an entry.
+ * Rows hold at most 128 nonzeros (a vertex of the Kuhn cube's P2 mesh has 65), nodes at
+ * most 64 elements, ne < 2^27 (PF_ELIMIT otherwise); otherwise as pf_csr_symbolic.  The
+ * handle then serves pf_csr_info, pf_csr_assemble_pages and the stage timing; the P1 calls
+ * (pf_assemble, pf_assemble_quad, pf_csr_faces, pf_rhs, pf_energies) return PF_ESTATE. */
+pf_status pf_csr_symbolic_p2(pf_csr* csr, int dim, int64_t nn, int64_t ne, const int32_t* elems2,
+                             void* stream);
+
+/* sparse(X3D(:), Y3D(:), K3D(:)) of the section 3.6 listings for the structure's mesh (P1 or
+ * P2), with Y3D(a, b, e) = elems(e, a) and X3D its page transpose: valsK[k] = the sum, over
+ * elements e and local pairs (a, b) such that entry k is row elems[e][b], column
+ * elems[e][a], of pagesK[e*nlb^2 + a + b*nlb]; the same for M.
+ * Pages ne x nlb x nlb column-major of type prec, as pf_elem_stiffness_mass (P1) and
+ * pf_p2_elements (P2) write them; device pointers.  Each value is summed exactly on a grid
+ * fixed by its largest contribution, as in pf_assemble.  valsK or valsM nullable (not both);
+ * each output needs its pages.  PF_ELIMIT if 16 consecutive rows hold more entries than the
+ * kernel's LDS budget (4096 FP32, 2730 FP64). */
+pf_status pf_csr_assemble_pages(const pf_csr* csr, pf_dtype prec, const void* pagesK,
+                                const void* pagesM, void* valsK, void* valsM, void* stream);
+
 /* Read the structure: sizes on the host, device pointers owned by the handle. */
 pf_status pf_csr_info(const pf_csr* csr, int64_t* nn, int64_t* nnz, const int32_t** row_ptr,
                       const int32_t** col_idx);

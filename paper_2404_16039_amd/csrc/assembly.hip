@@ -41,6 +41,8 @@ struct pf_csr {
     int32_t* cnt = nullptr;   // per-node counts / cursors / row lengths
     int32_t* colblk = nullptr;  // sorted columns of every row-pattern block, RR * MAXROW per block
     uint64_t* look = nullptr;   // published counts / prefixes of the row-offset tiles
+    uint64_t* pk2 = nullptr;    // P2 structures: row positions of the other nodes, 7 bits each
+    bool p2 = false;            // built from P2 elements (pf_csr_symbolic_p2)
     int64_t* bsum = nullptr;  // scan workspace
     int64_t* info = nullptr;  // [0] error bits, [1] adjacency total, [2] nnz, [3..6] block stats
     void* work = nullptr;     // workspace of the energy reductions (pf_energies)
@@ -55,7 +57,7 @@ struct pf_csr {
     int64_t cap_fcount = 0, cap_bcount = 0, cap_fptr = 0, cap_bptr = 0, cap_faces = 0, cap_fel = 0,
             cap_bfaces = 0, cap_bel = 0, cap_finfo = 0, cap_dpos = 0, cap_esign = 0;
     int64_t cap_adj_len = 0, cap_row_ptr = 0, cap_cnt = 0, cap_adj = 0, cap_pk = 0, cap_nnz = 0, cap_bsum = 0,
-            cap_info = 0, cap_colblk = 0, cap_look = 0, cap_work = 0;
+            cap_info = 0, cap_colblk = 0, cap_look = 0, cap_work = 0, cap_pk2 = 0;
     bool built = false;
     // per-stage timing of pf_csr_symbolic (events e0..e5: start, after the adjacency, after
     // the pattern, after the scan; around the compaction)
@@ -189,6 +191,7 @@ __device__ __forceinline__ int ag_hash(int32_t node) {
 // downstream depends on it (the numeric phase sums exactly, so its result does not depend
 // on the entry order).  Out-of-range node ids and rows beyond MAXADJ set error bits and are
 // not stored.
+template <int ASH>  // bits of the local index in an adjacency entry: 2 (P1), 4 (P2)
 __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ elems, int64_t m, int nlb, int64_t nn,
                                                    int32_t* __restrict__ adj_len, int32_t* __restrict__ adj,
                                                    int64_t* __restrict__ info) {
@@ -265,11 +268,12 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
     for (int q = 0; q < AG_ITEMS; ++q) {
         if (slot[q] >= 0) {
             const int64_t t = t0 + q * AG_BS + threadIdx.x;
-            const int64_t e = nlb == 4 ? (t >> 2) : static_cast<int64_t>(static_cast<uint64_t>(t) / 3u);
+            const int64_t e = nlb == 4 ? (t >> 2)
+                                       : static_cast<int64_t>(static_cast<uint32_t>(t) / static_cast<uint32_t>(nlb));
             const int a = static_cast<int>(t - e * nlb);
             const int64_t node = keys[slot[q]];
             const int off = atomicAdd(vals + slot[q], 1);
-            if (off < MAXADJ) adj[node * MAXADJ + off] = static_cast<int32_t>((e << 2) | a);
+            if (off < MAXADJ) adj[node * MAXADJ + off] = static_cast<int32_t>((e << ASH) | a);
         }
     }
 }
@@ -506,6 +510,172 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
     }
 }
 
+// ---------------------------------------------------------------------------- P2 row pattern
+// The same block-cooperative pattern for P2 meshes (6 or 10 nodes per element): rows hold up
+// to MAXROW2 nonzeros (a vertex of the Kuhn cube's P2 mesh has 65), in 128-slot tables, and
+// every adjacency entry (element << 4 | local index a) gets pk2 = the row positions of the
+// element's other nodes in local order, 7 bits each (9 x 7 = 63 bits).  The block's sorted
+// columns go to its region of RR * MAXROW2 words of colblk, as in the P1 kernel.
+constexpr int MAXROW2 = 128;
+constexpr int RSUB2 = MAXROW2;
+constexpr int RT2 = 128;
+static_assert(RT2 >= RR && RT2 >= 64, "one thread per row and a full first wave");
+
+__device__ __forceinline__ int rsub2_hash(int32_t v) {
+    return static_cast<int>((static_cast<uint32_t>(v) * 2654435761u) >> 25);  // 7 bits
+}
+
+template <int NLB>
+__global__ __launch_bounds__(RT2) void k_pattern_p2(int64_t nn, const int32_t* __restrict__ elems,
+                                                   const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
+                                                   int32_t* __restrict__ rowlen, int32_t* __restrict__ colblk,
+                                                   uint64_t* __restrict__ pk2, int32_t* __restrict__ dpos,
+                                                   int64_t* __restrict__ info) {
+    constexpr int NO = NLB - 1;
+    static_assert(NO * 7 <= 64, "the positions of the other nodes fit one 64-bit word");
+    __shared__ int32_t tab[RR * RSUB2];
+    __shared__ int32_t guard[RT2];
+    __shared__ int32_t seg[RR * MAXROW2];
+    __shared__ int32_t srt[RR * MAXROW2];
+    __shared__ uint8_t seg_h[RR * MAXROW2];
+    __shared__ uint8_t slot_rank[RR * RSUB2];
+    __shared__ uint64_t eslot[RR * MAXADJ];  // per item: table slot of other node k << 7k
+    __shared__ int32_t cnt[RR];
+    __shared__ int32_t cpre[RR + 1];
+    __shared__ int32_t alen[RR];
+    __shared__ int32_t maxl;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RR;
+    const int nr = static_cast<int>((r0 + RR < nn) ? RR : nn - r0);
+    const int64_t e0 = r0 * MAXADJ;
+    for (int h = threadIdx.x; h < RR * RSUB2; h += RT2) tab[h] = -1;
+    guard[threadIdx.x] = -2;
+    if (threadIdx.x == 0) maxl = 0;
+    __syncthreads();
+    if (threadIdx.x < RR) {
+        const int r = threadIdx.x;
+        const int L = r < nr ? min(adj_len[r0 + r], MAXADJ) : 0;
+        alen[r] = L;
+        if (r < nr && L == 0) dpos[r0 + r] = 0;
+        if (L > 0) {
+            const int32_t self = static_cast<int32_t>(r0 + r);
+            tab[r * RSUB2 + rsub2_hash(self)] = self;
+            atomicMax(&maxl, L);
+        }
+    }
+    bool bad = false;
+    __syncthreads();
+    const int items = RR * maxl;
+    for (int idx = threadIdx.x; idx < items; idx += RT2) {
+        const int r = idx % RR, j = idx / RR;
+        const bool ok = j < alen[r];
+        const int32_t w = adj[e0 + (ok ? r * MAXADJ + j : 0)];
+        const int a = ok ? (w & 15) : 0;
+        const int64_t e = ok ? (static_cast<uint32_t>(w) >> 4) : 0;
+        int32_t nd[NLB];
+#pragma unroll
+        for (int k = 0; k < NLB; ++k) nd[k] = elems[e * NLB + k];
+        // first probes of the element's other nodes together; an empty item probes the guard
+        int32_t ov[NO], cq[NO];
+#pragma unroll
+        for (int k = 0; k < NO; ++k) {
+            ov[k] = k < a ? nd[k] : nd[k + 1];
+            cq[k] = atomicCAS(ok ? tab + r * RSUB2 + rsub2_hash(ov[k]) : guard + threadIdx.x, -1, ov[k]);
+        }
+        if (!ok) continue;
+        int32_t* rt = tab + r * RSUB2;
+        uint64_t word = 0;
+#pragma unroll
+        for (int k = 0; k < NO; ++k) {
+            const int32_t v = ov[k];
+            int h = rsub2_hash(v);
+            int32_t cur = cq[k];
+#pragma unroll 1
+            for (int probe = 1; cur != -1 && cur != v; ++probe) {  // taken: linear probing
+                if (probe == RSUB2) {
+                    h = -1;
+                    break;
+                }
+                h = (h + 1) & (RSUB2 - 1);
+                cur = atomicCAS(rt + h, -1, v);
+            }
+            if (h < 0) {
+                bad = true;
+                continue;
+            }
+            word |= static_cast<uint64_t>(h) << (7 * k);
+        }
+        eslot[idx] = word;
+    }
+    if (bad) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
+    __syncthreads();
+    // each row's list: its used table slots (one wave per row and half table, lane = slot)
+    static_assert(RSUB2 == 128 && MAXROW2 == 128, "two table halves per row");
+    for (int r = threadIdx.x >> 6; r < RR; r += RT2 / 64) {
+        const int lane = threadIdx.x & 63;
+        const int32_t v0 = tab[r * RSUB2 + lane], v1 = tab[r * RSUB2 + 64 + lane];
+        const unsigned long long m0 = __ballot(v0 != -1), m1 = __ballot(v1 != -1);
+        const int below = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m0 >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m0), 0u));
+        const int below1 = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m1 >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m1), 0u));
+        const int n0 = __popcll(m0);
+        if (v0 != -1) {
+            seg[r * MAXROW2 + below] = v0;
+            seg_h[r * MAXROW2 + below] = static_cast<uint8_t>(lane);
+        }
+        if (v1 != -1) {
+            seg[r * MAXROW2 + n0 + below1] = v1;
+            seg_h[r * MAXROW2 + n0 + below1] = static_cast<uint8_t>(64 + lane);
+        }
+        if (lane == 0) cnt[r] = n0 + __popcll(m1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const int v = lane < nr ? cnt[lane] : 0;
+        int x = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(x, d, 64);
+            if (lane >= d) x += y;
+        }
+        if (lane < nr) cpre[lane] = x - v;
+        if (lane == nr - 1) cpre[nr] = x;
+    }
+    if (threadIdx.x < nr) rowlen[r0 + threadIdx.x] = cnt[threadIdx.x];
+    __syncthreads();
+    for (int q = threadIdx.x; q < cpre[nr]; q += RT2) {
+        const int r = upper_pos(cpre, nr, q);
+        const int p = q - cpre[r];
+        const int n = cnt[r];
+        const int32_t v = seg[r * MAXROW2 + p];
+        int rank = 0;
+        const int32_t* sr = seg + r * MAXROW2;
+        int j = 0;
+        for (; j + 4 <= n; j += 4) {
+            const int32_t a0 = sr[j], a1 = sr[j + 1], a2 = sr[j + 2], a3 = sr[j + 3];
+            rank += (a0 < v) + (a1 < v) + (a2 < v) + (a3 < v);
+        }
+        for (; j < n; ++j) rank += sr[j] < v;
+        slot_rank[r * RSUB2 + seg_h[r * MAXROW2 + p]] = static_cast<uint8_t>(rank);
+        if (v == r0 + r) dpos[r0 + r] = rank;
+        srt[cpre[r] + rank] = v;
+    }
+    __syncthreads();
+    int32_t* dst = colblk + static_cast<int64_t>(blockIdx.x) * (RR * MAXROW2);
+    for (int q = threadIdx.x; q < cpre[nr]; q += RT2) dst[q] = srt[q];
+    for (int idx = threadIdx.x; idx < items; idx += RT2) {
+        const int r = idx % RR, j = idx / RR;
+        if (j >= alen[r]) continue;
+        const uint64_t w = eslot[idx];
+        uint64_t word = 0;
+#pragma unroll
+        for (int k = 0; k < NO; ++k)
+            word |= static_cast<uint64_t>(slot_rank[r * RSUB2 + static_cast<int>((w >> (7 * k)) & 127)]) << (7 * k);
+        pk2[e0 + r * MAXADJ + j] = word;
+    }
+}
+
 // ---------------------------------------------------------------------------- row offsets
 // row_ptr, col_idx and the numeric launch statistics in one pass over tiles of SCAN_TILE
 // rows (a single-pass scan with decoupled look-back).  Tile t publishes its nonzero count
@@ -558,7 +728,9 @@ __device__ int64_t lb_exclusive(const uint64_t* look, int64_t t, bool& timeout) 
 // around a node, and stores them as tstat[4t .. 4t+3] (no atomics on shared words: those
 // serialise across the whole device); k_row_stats reduces them.
 static_assert(SCAN_ITEMS == RR && SCAN_ITEMS == 8, "a scan thread owns one row-pattern block of 8 rows");
-static_assert(RR * MAXROW >= 128, "a row-pattern block's region holds the 128 words read at once");
+
+// RW: words of a row-pattern block's region in colblk; NRD: rounds of 64 words read at once
+template <int RW, int NRD>
 __global__ __launch_bounds__(SBS) void k_row_offsets(int64_t nn, const int32_t* __restrict__ rowlen,
                                                      const int32_t* __restrict__ adj_len,
                                                      const int32_t* __restrict__ colblk, int32_t* __restrict__ row_ptr,
@@ -628,7 +800,7 @@ __global__ __launch_bounds__(SBS) void k_row_offsets(int64_t nn, const int32_t* 
         o += v[i];
     }
     // columns: each wave moves groups of 4 consecutive row-pattern blocks (wave w takes groups
-    // w, w + 4, ...): the first 128 words of the 4 blocks as 8 loads in flight per lane
+    // w, w + 4, ...): the first 64 NRD words of the 4 blocks as 4 NRD loads in flight per lane
     // (consecutive lanes on consecutive words of a block), then the rest of any longer block
     const int64_t blk0 = t * SBS;  // the tile's first row-pattern block
     const int64_t nblk = (nn + RR - 1) / RR;
@@ -643,21 +815,22 @@ __global__ __launch_bounds__(SBS) void k_row_offsets(int64_t nn, const int32_t* 
             const int b = min(g + j, nb - 1);
             n[j] = g + j < nb ? bcnt[b] : 0;
             o[j] = boff[b];
-            src[j] = colblk + (blk0 + b) * (RR * MAXROW);
+            src[j] = colblk + (blk0 + b) * RW;
         }
-        int32_t v[4][2];
+        static_assert(RW >= 64 * NRD, "a row-pattern block's region holds the words read at once");
+        int32_t v[4][NRD];
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int r = 0; r < 2; ++r) v[j][r] = src[j][lane + 64 * r];  // inside the block's region
+            for (int r = 0; r < NRD; ++r) v[j][r] = src[j][lane + 64 * r];  // inside the block's region
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int r = 0; r < 2; ++r)
+            for (int r = 0; r < NRD; ++r)
                 if (lane + 64 * r < n[j]) dst[o[j] + lane + 64 * r] = v[j][r];
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            for (int w = 128 + lane; w < n[j]; w += 64) dst[o[j] + w] = src[j][w];
+            for (int w = 64 * NRD + lane; w < n[j]; w += 64) dst[o[j] + w] = src[j][w];
     }
 }
 
@@ -1400,7 +1573,7 @@ pf_status numeric_launch_many(int dim, pf_dtype prec, int nr, const NumericJob* 
 
 size_t csr_bytes(const pf_csr* c) {
     return static_cast<size_t>(c->cap_adj_len + c->cap_row_ptr + c->cap_cnt + c->cap_adj + c->cap_nnz + c->cap_colblk) * 4 +
-           static_cast<size_t>(c->cap_pk) * 4 + static_cast<size_t>(c->cap_bsum + c->cap_info + c->cap_work + c->cap_look) * 8 +
+           static_cast<size_t>(c->cap_pk) * 4 + static_cast<size_t>(c->cap_bsum + c->cap_info + c->cap_work + c->cap_look + c->cap_pk2) * 8 +
            static_cast<size_t>(c->cap_fcount + c->cap_bcount + c->cap_fptr + c->cap_bptr + c->cap_faces + c->cap_fel +
                                c->cap_bfaces + c->cap_bel + c->cap_dpos) * 4 + static_cast<size_t>(c->cap_finfo) * 8 +
            static_cast<size_t>(c->cap_esign);
@@ -1410,7 +1583,23 @@ int64_t csr_nnz(const pf_csr* c) { return c->built ? c->nnz : -1; }
 int64_t csr_nn(const pf_csr* c) { return c->nn; }
 int csr_dim(const pf_csr* c) { return c->dim; }
 int64_t csr_ne(const pf_csr* c) { return c->ne; }
-bool csr_built(const pf_csr* c) { return c->built; }
+bool csr_built(const pf_csr* c) { return c->built && !c->p2; }
+bool csr_view(const pf_csr* c, CsrView* v) {
+    if (!c->built) return false;
+    v->nn = c->nn;
+    v->ne = c->ne;
+    v->nnz = c->nnz;
+    v->dim = c->dim;
+    v->nlb = c->nlb;
+    v->row_ptr = c->row_ptr;
+    v->adj_len = c->adj_len;
+    v->adj = c->adj;
+    v->pk = c->p2 ? nullptr : c->pk;
+    v->pk2 = c->p2 ? c->pk2 : nullptr;
+    v->dpos = c->dpos;
+    v->wmax16 = c->wmax_mid;
+    return true;
+}
 const int32_t* csr_adj(const pf_csr* c) { return c->adj; }
 const int32_t* csr_adj_len(const pf_csr* c) { return c->adj_len; }
 
@@ -1446,6 +1635,7 @@ void pf_csr_destroy(pf_csr* c) {
     (void)hipFree(c->cnt);
     (void)hipFree(c->colblk);
     (void)hipFree(c->look);
+    (void)hipFree(c->pk2);
     (void)hipFree(c->bsum);
     (void)hipFree(c->info);
     (void)hipFree(c->work);
@@ -1498,14 +1688,15 @@ pf_status pf_csr_stage_times(pf_csr* c, double* ms, int64_t* calls) {
     return PF_OK;
 }
 
-pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int32_t* elems, void* stream) {
-    if (!c) return fail(PF_EINVAL, "pf_csr_symbolic: null handle");
-    if (dim != 2 && dim != 3) return fail(PF_EORDER, "pf_csr_symbolic: dim must be 2 or 3");
-    if (nn < 0 || ne < 0) return fail(PF_EINVAL, "pf_csr_symbolic: negative size");
-    const int nlb = dim + 1;
-    if (nn >= INT32_MAX || ne * nlb >= INT32_MAX || ne >= (int64_t(1) << 29))
-        return fail(PF_ELIMIT, "pf_csr_symbolic: mesh too large for 32-bit indices");
-    if (ne > 0 && !elems) return fail(PF_EINVAL, "pf_csr_symbolic: null elems");
+namespace {
+// the structure of a P1 (nlb = dim + 1) or P2 (nlb = 6, 10) mesh
+pf_status symbolic(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const int32_t* elems, void* stream,
+                   const char* who) {
+    const bool p2 = nlb > dim + 1;
+    const int maxrow = p2 ? MAXROW2 : MAXROW;
+    if (nn >= INT32_MAX || ne * nlb >= INT32_MAX || ne >= (int64_t(1) << (p2 ? 27 : 29)))
+        return fail(PF_ELIMIT, std::string(who) + ": mesh too large for 32-bit indices");
+    if (ne > 0 && !elems) return fail(PF_EINVAL, std::string(who) + ": null elems");
     hipStream_t s = as_stream(stream);
     c->built = false;
     c->faces_built = false;
@@ -1516,7 +1707,11 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     if ((st = grow(c->row_ptr, c->cap_row_ptr, nn + 1))) return st;
     if ((st = grow(c->cnt, c->cap_cnt, nn + 1))) return st;
     if ((st = grow(c->adj, c->cap_adj, nn * MAXADJ))) return st;
-    if ((st = grow(c->pk, c->cap_pk, nn * MAXADJ))) return st;
+    if (p2) {
+        if ((st = grow(c->pk2, c->cap_pk2, nn * MAXADJ))) return st;
+    } else {
+        if ((st = grow(c->pk, c->cap_pk, nn * MAXADJ))) return st;
+    }
     const int64_t nb = std::max<int64_t>(ceil_div(nn + 1, SCAN_TILE), 1);
     if ((st = grow(c->bsum, c->cap_bsum, nb))) return st;
     if ((st = grow(c->info, c->cap_info, 8))) return st;
@@ -1524,20 +1719,32 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, c->info, int64_t(8), int64_t(0));
     if (nn > 0) hipLaunchKernelGGL(k_fill_i32, dim3(flat_grid(nn)), dim3(SBS), 0, s, c->adj_len, nn, 0);
     const unsigned gtile = static_cast<unsigned>(std::max<int64_t>(ceil_div(m, AG_TILE), 1));
-    if (m > 0)
-        hipLaunchKernelGGL(k_scatter, dim3(gtile), dim3(AG_BS), 0, s, elems, m, nlb, nn, c->adj_len, c->adj, c->info);
+    if (m > 0) {
+        if (p2)
+            hipLaunchKernelGGL(k_scatter<4>, dim3(gtile), dim3(AG_BS), 0, s, elems, m, nlb, nn, c->adj_len, c->adj,
+                               c->info);
+        else
+            hipLaunchKernelGGL(k_scatter<2>, dim3(gtile), dim3(AG_BS), 0, s, elems, m, nlb, nn, c->adj_len, c->adj,
+                               c->info);
+    }
     const int64_t grows = ceil_div(nn, RR);
     const int64_t tiles = ceil_div(nn, SCAN_TILE);
-    // nnz is known only after the pattern: col_idx holds MAXROW columns per row
-    if ((st = grow(c->colblk, c->cap_colblk, std::max<int64_t>(grows * RR * MAXROW, 1)))) return st;
-    if ((st = grow(c->col_idx, c->cap_nnz, std::max<int64_t>(nn * MAXROW, 1)))) return st;
+    // nnz is known only after the pattern: col_idx holds maxrow columns per row
+    if ((st = grow(c->colblk, c->cap_colblk, std::max<int64_t>(grows * RR * maxrow, 1)))) return st;
+    if ((st = grow(c->col_idx, c->cap_nnz, std::max<int64_t>(nn * maxrow, 1)))) return st;
     if ((st = grow(c->dpos, c->cap_dpos, nn + 1))) return st;
     // tile descriptors, then 4 int32 statistics per tile
     if ((st = grow(c->look, c->cap_look, 3 * std::max<int64_t>(tiles, 1) + 1))) return st;
     if ((st = mark(c, 1, s))) return st;
     if (nn > 0) {
         const unsigned g = static_cast<unsigned>(grows);
-        if (nlb == 4)
+        if (nlb == 10)
+            hipLaunchKernelGGL((k_pattern_p2<10>), dim3(g), dim3(RT2), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
+                               c->colblk, c->pk2, c->dpos, c->info);
+        else if (nlb == 6)
+            hipLaunchKernelGGL((k_pattern_p2<6>), dim3(g), dim3(RT2), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
+                               c->colblk, c->pk2, c->dpos, c->info);
+        else if (nlb == 4)
             hipLaunchKernelGGL((k_pattern<4>), dim3(g), dim3(RT), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
                                c->colblk, c->pk, c->dpos, c->info);
         else
@@ -1549,27 +1756,32 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
         hipLaunchKernelGGL(k_fill_i64, dim3(flat_grid(tiles)), dim3(SBS), 0, s, reinterpret_cast<int64_t*>(c->look),
                            tiles, int64_t(0));
         int32_t* tstat = reinterpret_cast<int32_t*>(c->look + ((tiles + 1) & ~int64_t(1)));  // 16-byte aligned
-        hipLaunchKernelGGL(k_row_offsets, dim3(static_cast<unsigned>(tiles)), dim3(SBS), 0, s, nn, c->cnt, c->adj_len,
-                           c->colblk, c->row_ptr, c->col_idx, c->look, tstat, c->info);
+        if (p2)
+            hipLaunchKernelGGL((k_row_offsets<RR * MAXROW2, 4>), dim3(static_cast<unsigned>(tiles)), dim3(SBS), 0, s, nn,
+                               c->cnt, c->adj_len, c->colblk, c->row_ptr, c->col_idx, c->look, tstat, c->info);
+        else
+            hipLaunchKernelGGL((k_row_offsets<RR * MAXROW, 2>), dim3(static_cast<unsigned>(tiles)), dim3(SBS), 0, s, nn,
+                               c->cnt, c->adj_len, c->colblk, c->row_ptr, c->col_idx, c->look, tstat, c->info);
         hipLaunchKernelGGL(k_row_stats, dim3(1), dim3(SBS), 0, s, tiles, tstat, c->info);
     } else {
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, c->row_ptr, int64_t(1), 0);
     }
     if ((st = mark(c, 3, s))) return st;
-    if ((st = launch_check("pf_csr_symbolic"))) return st;
+    if ((st = launch_check(who))) return st;
     c->pending = c->timing;
     int64_t info[8];
     PF_HIP_TRY(hipMemcpyAsync(info, c->info, sizeof(info), hipMemcpyDeviceToHost, s));
     PF_HIP_TRY(hipStreamSynchronize(s));
-    if (info[0] & ERR_INDEX) return fail(PF_EINDEX, "pf_csr_symbolic: node index out of range in elems");
+    if (info[0] & ERR_INDEX) return fail(PF_EINDEX, std::string(who) + ": node index out of range in elems");
     if (info[0] & ERR_ROW)
-        return fail(PF_ELIMIT, "pf_csr_symbolic: a node belongs to more than 64 elements or a row has more than 64 "
-                               "nonzeros");
-    if (info[0] & ERR_SCAN) return fail(PF_EINVAL, "pf_csr_symbolic: the row offsets could not be formed");
-    if (info[2] >= INT32_MAX) return fail(PF_ELIMIT, "pf_csr_symbolic: nnz must be < 2^31");
+        return fail(PF_ELIMIT, std::string(who) + ": a node belongs to more than 64 elements or a row has more than " +
+                                   std::to_string(maxrow) + " nonzeros");
+    if (info[0] & ERR_SCAN) return fail(PF_EINVAL, std::string(who) + ": the row offsets could not be formed");
+    if (info[2] >= INT32_MAX) return fail(PF_ELIMIT, std::string(who) + ": nnz must be < 2^31");
     const int64_t nnz = info[2];
     c->dim = dim;
     c->nlb = nlb;
+    c->p2 = p2;
     c->nn = nn;
     c->ne = ne;
     c->nnz = nnz;
@@ -1580,12 +1792,28 @@ pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int3
     c->built = true;
     return PF_OK;
 }
+}  // namespace
+
+pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int32_t* elems, void* stream) {
+    if (!c) return fail(PF_EINVAL, "pf_csr_symbolic: null handle");
+    if (dim != 2 && dim != 3) return fail(PF_EORDER, "pf_csr_symbolic: dim must be 2 or 3");
+    if (nn < 0 || ne < 0) return fail(PF_EINVAL, "pf_csr_symbolic: negative size");
+    return symbolic(c, dim, dim + 1, nn, ne, elems, stream, "pf_csr_symbolic");
+}
+
+pf_status pf_csr_symbolic_p2(pf_csr* c, int dim, int64_t nn, int64_t ne, const int32_t* elems2, void* stream) {
+    if (!c) return fail(PF_EINVAL, "pf_csr_symbolic_p2: null handle");
+    if (dim != 2 && dim != 3) return fail(PF_EORDER, "pf_csr_symbolic_p2: dim must be 2 or 3");
+    if (nn < 0 || ne < 0) return fail(PF_EINVAL, "pf_csr_symbolic_p2: negative size");
+    return symbolic(c, dim, dim == 2 ? 6 : 10, nn, ne, elems2, stream, "pf_csr_symbolic_p2");
+}
 
 pf_status pf_assemble_quad(const pf_csr* c, pf_dtype prec, const double* coords, int order, const void* cKq,
                            const void* cMq, void* valsK, void* valsM, const pf_fallback* fb, int64_t* d_counters,
                            void* stream) {
     if (!c) return fail(PF_EINVAL, "pf_assemble_quad: null handle");
     if (!c->built) return fail(PF_ESTATE, "pf_assemble_quad: structure not built");
+    if (c->p2) return fail(PF_ESTATE, "pf_assemble_quad: a P2 structure (pf_p2_assemble assembles it)");
     const int qn = quad_count(c->dim, order);
     if (!qn) return fail(PF_EINVAL, "pf_assemble_quad: order must be 1 or 2");
     if (c->nn == 0 || c->nnz == 0) return PF_OK;
@@ -1610,6 +1838,7 @@ pf_status pf_assemble_quad(const pf_csr* c, pf_dtype prec, const double* coords,
 pf_status pf_csr_faces(pf_csr* c, const double* coords, const int32_t* elems, void* stream) {
     if (!c) return fail(PF_EINVAL, "pf_csr_faces: null handle");
     if (!c->built) return fail(PF_ESTATE, "pf_csr_faces: structure not built");
+    if (c->p2) return fail(PF_ESTATE, "pf_csr_faces: a P2 structure");
     if (c->ne > 0 && (!coords || !elems)) return fail(PF_EINVAL, "pf_csr_faces: null coords or elems");
     hipStream_t s = as_stream(stream);
     c->faces_built = false;
@@ -1697,6 +1926,7 @@ pf_status pf_assemble(const pf_csr* c, pf_dtype prec, const double* coords, cons
                       void* stream) {
     if (!c) return fail(PF_EINVAL, "pf_assemble: null handle");
     if (!c->built) return fail(PF_ESTATE, "pf_assemble: structure not built");
+    if (c->p2) return fail(PF_ESTATE, "pf_assemble: a P2 structure (pf_p2_assemble assembles it)");
     if (c->nn == 0 || c->nnz == 0) return PF_OK;
     if (!coords || !valsK) return fail(PF_EINVAL, "pf_assemble: null coords or valsK");
     (void)elems;  // the structure carries the connectivity it was built from

@@ -38,7 +38,23 @@ int64_t csr_nnz(const pf_csr* c);
 int64_t csr_nn(const pf_csr* c);
 int csr_dim(const pf_csr* c);
 int64_t csr_ne(const pf_csr* c);
-bool csr_built(const pf_csr* c);
+bool csr_built(const pf_csr* c);  // a built P1 structure
+// a built structure, P1 or P2: adjacency entries (element << 2 | local index) with pk (P1:
+// row positions of the element's other nodes in local order, 8 bits each from bit 2), or
+// (element << 4 | local index) with pk2 (P2: 7 bits each from bit 0); dpos = the diagonal's
+// position in each row; wmax16 = the largest CSR window of 16 consecutive rows
+struct CsrView {
+    int64_t nn, ne, nnz;
+    int dim, nlb;
+    const int32_t* row_ptr;
+    const int32_t* adj_len;
+    const int32_t* adj;
+    const uint32_t* pk;
+    const uint64_t* pk2;
+    const int32_t* dpos;
+    int wmax16;
+};
+bool csr_view(const pf_csr* c, CsrView* v);  // false unless built
 // node -> element adjacency of the structure: entries (element << 2 | local index) of node i
 // at adj[i * CSR_MAXADJ ...], adj_len[i] of them
 constexpr int CSR_MAXADJ = 64;

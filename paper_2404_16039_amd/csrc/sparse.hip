@@ -1,0 +1,175 @@
+// sparse.hip -- assembly of element pages into the CSR structure: the sparse(X3D(:),
+// Y3D(:), K3D(:)) step that ends the P1 and P2 listings of section 3.6, for pages computed
+// by any kernel (pf_elem_stiffness_mass, pf_p2_elements) or by the caller.
+//
+// In the listings Y3D(a, b, e) = elems(e, a) and X3D is its page transpose, so the page
+// entry (a, b) of element e goes to row elems(e, b), column elems(e, a).  Row-owned and
+// exact, like the fused P1 numeric phase: a block owns PR consecutive rows (a contiguous
+// window of the CSR arrays); every adjacency entry of a row (element e with the row's node
+// at local index a) reads column a of its element's page (contiguous), entry (b, a) for all
+// b, and adds it to the slot of node b; the slot positions come from the structure (the
+// diagonal position, and pk / pk2 for the other nodes).  Each slot's largest contribution
+// fixes its grid, the contributions are rounded to it once and summed exactly in integers,
+// so the result does not depend on the order of the additions.
+#include "exact.hpp"
+#include "internal.hpp"
+
+#include <string>
+
+namespace pf {
+
+constexpr int PR = 8;      // rows per block
+constexpr int PBT = 256;   // threads per block
+constexpr int PITEMS = 2;  // adjacency entries per thread (held in registers)
+static_assert(PITEMS * PBT / PR >= CSR_MAXADJ, "a block covers the longest adjacency list");
+
+// NB nodes per element; P2: entries are (element << 4 | a) with pk2, else (element << 2 | a)
+// with pk.  pages: ne x NB x NB, column-major (entry (a, b) at a + b NB).
+template <int NB, bool P2, typename T>
+__global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_t* __restrict__ row_ptr,
+                                                        const int32_t* __restrict__ adj_len,
+                                                        const int32_t* __restrict__ adj, const uint32_t* __restrict__ pk,
+                                                        const uint64_t* __restrict__ pk2, const int32_t* __restrict__ dpos,
+                                                        const T* __restrict__ pagesK, const T* __restrict__ pagesM,
+                                                        T* __restrict__ valsK, T* __restrict__ valsM) {
+    using A = typename Exact<T>::acc;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int32_t rp[PR + 1], alen[PR], dslot[PR];
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * PR;
+    const int nr = static_cast<int>((r0 + PR < nn) ? PR : nn - r0);
+    if (threadIdx.x <= PR) rp[threadIdx.x] = row_ptr[r0 + (threadIdx.x <= nr ? threadIdx.x : nr)];
+    if (threadIdx.x < PR) {
+        const int r = threadIdx.x;
+        alen[r] = r < nr ? min(adj_len[r0 + r], CSR_MAXADJ) : 0;
+        dslot[r] = r < nr ? dpos[r0 + r] : 0;
+    }
+    __syncthreads();
+    const int32_t w0 = rp[0];
+    const int W = rp[nr] - w0;
+    A* accK = reinterpret_cast<A*>(smem);
+    A* accM = accK + W;
+    int32_t* shK = reinterpret_cast<int32_t*>(accM + W);
+    int32_t* shM = shK + W;
+    for (int w = threadIdx.x; w < W; w += PBT) {
+        accK[w] = A(0);
+        accM[w] = A(0);
+        shK[w] = 0;
+        shM[w] = 0;
+    }
+    // this thread's entries: row r = item % PR, entry j = item / PR; loads without branches
+    int rq[PITEMS];
+    int64_t eq[PITEMS];
+    int aq[PITEMS];
+    uint64_t pq[PITEMS];
+#pragma unroll
+    for (int q = 0; q < PITEMS; ++q) {
+        const int idx = threadIdx.x + q * PBT;
+        const int r = idx % PR, j = idx / PR;
+        const bool ok = j < alen[r];
+        const int64_t t = ok ? (r0 + r) * CSR_MAXADJ + j : r0 * CSR_MAXADJ;
+        const int32_t w = adj[t];
+        pq[q] = P2 ? pk2[t] : static_cast<uint64_t>(pk[t]);
+        rq[q] = ok ? r : -1;
+        eq[q] = ok ? static_cast<int64_t>(static_cast<uint32_t>(w) >> (P2 ? 4 : 2)) : 0;
+        aq[q] = ok ? (w & (P2 ? 15 : 3)) : 0;
+    }
+    __syncthreads();  // accumulators cleared
+    // window position of local node b of the entry's element in its row
+    auto slot = [&](int q, int b) -> int {
+        const int r = rq[q], a = aq[q];
+        if (b == a) return rp[r] - w0 + dslot[r];
+        const int k = b < a ? b : b - 1;
+        const int pos = P2 ? static_cast<int>((pq[q] >> (7 * k)) & 127) : static_cast<int>((pq[q] >> (2 + 8 * k)) & 255);
+        return rp[r] - w0 + pos;
+    };
+    T kv[PITEMS][NB], mv[PITEMS][NB];
+#pragma unroll
+    for (int q = 0; q < PITEMS; ++q) {
+        const int64_t base = eq[q] * (NB * NB) + aq[q] * NB;  // column a
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            kv[q][b] = pagesK ? pagesK[base + b] : T(0);
+            mv[q][b] = pagesM ? pagesM[base + b] : T(0);
+        }
+    }
+    // per-slot grid: the largest contribution
+#pragma unroll
+    for (int q = 0; q < PITEMS; ++q) {
+        if (rq[q] < 0) continue;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int s = slot(q, b);
+            atomicMax(reinterpret_cast<uint32_t*>(shK + s), Exact<T>::mag(kv[q][b]));
+            atomicMax(reinterpret_cast<uint32_t*>(shM + s), Exact<T>::mag(mv[q][b]));
+        }
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < W; w += PBT) {
+        shK[w] = Exact<T>::shift(static_cast<uint32_t>(shK[w]));
+        shM[w] = Exact<T>::shift(static_cast<uint32_t>(shM[w]));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PITEMS; ++q) {
+        if (rq[q] < 0) continue;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int s = slot(q, b);
+            atomicAdd(accK + s, Exact<T>::quant(kv[q][b], shK[s]));
+            atomicAdd(accM + s, Exact<T>::quant(mv[q][b], shM[s]));
+        }
+    }
+    __syncthreads();
+    for (int w = threadIdx.x; w < W; w += PBT) {
+        if (valsK) valsK[w0 + w] = Exact<T>::back(accK[w], shK[w]);
+        if (valsM) valsM[w0 + w] = Exact<T>::back(accM[w], shM[w]);
+    }
+}
+
+template <int NB, bool P2, typename T>
+void launch_pages(const CsrView& v, const void* pK, const void* pM, void* vK, void* vM, hipStream_t s) {
+    const size_t shm = static_cast<size_t>(v.wmax16) * (2 * sizeof(typename Exact<T>::acc) + 8);
+    const unsigned g = static_cast<unsigned>(ceil_div(v.nn, PR));
+    hipLaunchKernelGGL((k_assemble_pages<NB, P2, T>), dim3(g), dim3(PBT), shm, s, v.nn, v.row_ptr, v.adj_len, v.adj,
+                       v.pk, v.pk2, v.dpos, static_cast<const T*>(pK), static_cast<const T*>(pM), static_cast<T*>(vK),
+                       static_cast<T*>(vM));
+}
+
+}  // namespace pf
+
+using namespace pf;
+
+pf_status pf_csr_assemble_pages(const pf_csr* csr, pf_dtype prec, const void* pagesK, const void* pagesM, void* valsK,
+                                void* valsM, void* stream) {
+    if (!csr) return fail(PF_EINVAL, "pf_csr_assemble_pages: null handle");
+    CsrView v{};
+    if (!csr_view(csr, &v)) return fail(PF_ESTATE, "pf_csr_assemble_pages: structure not built");
+    if (prec != PF_F32 && prec != PF_F64) return fail(PF_EDTYPE, "pf_csr_assemble_pages: prec must be PF_F32 or PF_F64");
+    if ((valsK && !pagesK) || (valsM && !pagesM) || (!valsK && !valsM))
+        return fail(PF_EINVAL, "pf_csr_assemble_pages: each output needs its pages, and one output is needed");
+    if (v.nn == 0 || v.nnz == 0) return PF_OK;
+    const size_t shm = static_cast<size_t>(v.wmax16) * (prec == PF_F32 ? 16 : 24);
+    if (shm > 65536) return fail(PF_ELIMIT, "pf_csr_assemble_pages: a CSR window of 16 rows exceeds the LDS budget");
+    hipStream_t s = as_stream(stream);
+    // an output without its request still gets the other's pages read as zero
+    const void* pK = valsK ? pagesK : nullptr;
+    const void* pM = valsM ? pagesM : nullptr;
+    const bool f32 = prec == PF_F32;
+    switch (v.nlb) {
+        case 3:
+            f32 ? launch_pages<3, false, float>(v, pK, pM, valsK, valsM, s) : launch_pages<3, false, double>(v, pK, pM, valsK, valsM, s);
+            break;
+        case 4:
+            f32 ? launch_pages<4, false, float>(v, pK, pM, valsK, valsM, s) : launch_pages<4, false, double>(v, pK, pM, valsK, valsM, s);
+            break;
+        case 6:
+            f32 ? launch_pages<6, true, float>(v, pK, pM, valsK, valsM, s) : launch_pages<6, true, double>(v, pK, pM, valsK, valsM, s);
+            break;
+        case 10:
+            f32 ? launch_pages<10, true, float>(v, pK, pM, valsK, valsM, s) : launch_pages<10, true, double>(v, pK, pM, valsK, valsM, s);
+            break;
+        default:
+            return fail(PF_EINVAL, "pf_csr_assemble_pages: unsupported element");
+    }
+    return launch_check("pf_csr_assemble_pages");
+}

@@ -143,6 +143,8 @@ _sig = {
     "pf_energies": ([P, I32, P, P, I32, P, P, P, P, P, P, FP, P, P], C.c_int),
     "pf_csr_create": ([C.POINTER(P)], C.c_int),
     "pf_csr_symbolic": ([P, I32, I64, I64, P, P], C.c_int),
+    "pf_csr_symbolic_p2": ([P, I32, I64, I64, P, P], C.c_int),
+    "pf_csr_assemble_pages": ([P, I32, P, P, P, P, P], C.c_int),
     "pf_csr_info": ([P, C.POINTER(I64), C.POINTER(I64), C.POINTER(P), C.POINTER(P)], C.c_int),
     "pf_csr_set_timing": ([P, C.c_int], C.c_int),
     "pf_csr_stage_times": ([P, C.POINTER(C.c_double), C.POINTER(I64)], C.c_int),
@@ -321,6 +323,20 @@ class Csr:
         _chk(_lib.pf_csr_symbolic(self._h, int(dim), int(nn), elems.shape[0], _p(elems), _s(stream)),
              "pf_csr_symbolic")
         return self
+
+    def symbolic_p2(self, dim, nn, elems2, stream=None):
+        """Structure of a P2 mesh (elems2: ne x 6 or 10 int32)."""
+        if elems2.dtype != torch.int32 or not elems2.is_contiguous():
+            raise ValueError("elems2 must be contiguous int32")
+        self._dim = int(dim)
+        _chk(_lib.pf_csr_symbolic_p2(self._h, int(dim), int(nn), elems2.shape[0], _p(elems2), _s(stream)),
+             "pf_csr_symbolic_p2")
+        return self
+
+    def assemble_pages(self, prec, pagesK=None, pagesM=None, valsK=None, valsM=None, stream=None):
+        """sparse() of element pages (ne x nlb x nlb column-major) into valsK / valsM (nnz)."""
+        _chk(_lib.pf_csr_assemble_pages(self._h, prec, _p(pagesK), _p(pagesM), _p(valsK), _p(valsM), _s(stream)),
+             "pf_csr_assemble_pages")
 
     def info(self):
         nn, nnz, rp, ci = I64(), I64(), P(), P()

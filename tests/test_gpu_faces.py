@@ -150,3 +150,42 @@ def test_gi_deterministic_and_edge_cases(lib):
     with pytest.raises(lib.PagefemError):
         csr.face_lists()
     csr.close()
+
+
+@pytest.mark.parametrize("case", ["tet27", "tet1", "tet64", "tri9", "edge3"])
+def test_simplex_points_parity(lib, case):
+    """Points of caller-given rules on every cell (section 3.5: the coordinates combined with
+    the rule's barycentric points) against the oracle: tetrahedra with 27, 1 and 64 points,
+    triangles, and boundary edges, over several blocks of cells with a ragged last one."""
+    say("simplex points", case)
+    if case.startswith("tet"):
+        coords, cells, _ = cube(6)
+        nq = int(case[3:])
+        lam = np.full((1, 4), 0.25) if nq == 1 else _stroud(3, 3 if nq == 27 else 4)[0]
+    elif case == "tri9":
+        coords, cells, _ = square(40)
+        lam = _stroud(2, 3)[0]
+    else:
+        coords, _, cells = square(40)  # the boundary edges
+        g, _ = np.polynomial.legendre.leggauss(3)
+        t = (g + 1) / 2
+        lam = np.stack([1 - t, t], axis=1)
+    X = host(lib.simplex_points(dev(coords), dev(cells), lam))
+    Xo = oracle.simplex_points(coords, cells, lam)
+    assert X.shape == Xo.shape == (cells.shape[0], lam.shape[0], coords.shape[1])
+    assert np.allclose(X, Xo, rtol=0, atol=4e-16 * np.abs(coords).max() * 4), np.abs(X - Xo).max()
+
+
+def test_simplex_points_bad_node(lib):
+    """A cell with a node index out of range gets NaN points; every other cell is unaffected."""
+    say("simplex points bad node")
+    coords, cells, _ = cube(6)
+    lam = _stroud(3, 3)[0]
+    bad = cells.copy()
+    bad[700, 2] = coords.shape[0] + 3
+    X = host(lib.simplex_points(dev(coords), dev(bad), lam))
+    Xo = oracle.simplex_points(coords, cells, lam)
+    assert np.all(np.isnan(X[700]))
+    keep = np.ones(cells.shape[0], dtype=bool)
+    keep[700] = False
+    assert np.allclose(X[keep], Xo[keep], rtol=0, atol=4e-15)
