@@ -1597,7 +1597,10 @@ bool csr_view(const pf_csr* c, CsrView* v) {
     v->pk = c->p2 ? nullptr : c->pk;
     v->pk2 = c->p2 ? c->pk2 : nullptr;
     v->dpos = c->dpos;
+    v->wmax4 = c->wmax_small;
     v->wmax16 = c->wmax_mid;
+    v->wmax32 = c->wmax_big;
+    v->max_adj = c->max_adj;
     return true;
 }
 const int32_t* csr_adj(const pf_csr* c) { return c->adj; }

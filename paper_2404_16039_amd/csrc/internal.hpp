@@ -42,7 +42,8 @@ bool csr_built(const pf_csr* c);  // a built P1 structure
 // a built structure, P1 or P2: adjacency entries (element << 2 | local index) with pk (P1:
 // row positions of the element's other nodes in local order, 8 bits each from bit 2), or
 // (element << 4 | local index) with pk2 (P2: 7 bits each from bit 0); dpos = the diagonal's
-// position in each row; wmax16 = the largest CSR window of 16 consecutive rows
+// position in each row; wmax4 / wmax16 / wmax32 = the largest CSR window of 4 / 16 / 32
+// consecutive rows starting at a multiple of their count; max_adj = the longest adjacency list
 struct CsrView {
     int64_t nn, ne, nnz;
     int dim, nlb;
@@ -52,7 +53,8 @@ struct CsrView {
     const uint32_t* pk;
     const uint64_t* pk2;
     const int32_t* dpos;
-    int wmax16;
+    int wmax4, wmax16, wmax32;
+    int max_adj;
 };
 bool csr_view(const pf_csr* c, CsrView* v);  // false unless built
 // node -> element adjacency of the structure: entries (element << 2 | local index) of node i

@@ -18,14 +18,27 @@
 
 namespace pf {
 
-constexpr int PR = 8;      // rows per block
 constexpr int PBT = 256;   // threads per block
 constexpr int PITEMS = 2;  // adjacency entries per thread (held in registers)
-static_assert(PITEMS * PBT / PR >= CSR_MAXADJ, "a block covers the longest adjacency list");
+constexpr int PCAP = PITEMS * PBT;  // entries per block at most
+static_assert(PCAP >= 4 * CSR_MAXADJ, "the smallest blocks (4 rows) cover any admissible rows");
+
+__device__ __forceinline__ int last_le(const int32_t* v, int n, int x) {
+    // last index r in [0, n) with v[r] <= x (v ascending, v[0] <= x)
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (v[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
 
 // NB nodes per element; P2: entries are (element << 4 | a) with pk2, else (element << 2 | a)
-// with pk.  pages: ne x NB x NB, column-major (entry (a, b) at a + b NB).
-template <int NB, bool P2, typename T>
+// with pk.  pages: ne x NB x NB, column-major (entry (a, b) at a + b NB).  PR rows per block,
+// chosen by the host so that PR times the longest adjacency list fits PCAP; the block's
+// entries are dealt flat (row after row), entry k to thread k mod PBT.
+template <int NB, bool P2, typename T, int PR>
 __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_t* __restrict__ row_ptr,
                                                         const int32_t* __restrict__ adj_len,
                                                         const int32_t* __restrict__ adj, const uint32_t* __restrict__ pk,
@@ -34,14 +47,22 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_
                                                         T* __restrict__ valsK, T* __restrict__ valsM) {
     using A = typename Exact<T>::acc;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int32_t rp[PR + 1], alen[PR], dslot[PR];
+    __shared__ int32_t rp[PR + 1], apre[PR + 1], dslot[PR];
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * PR;
     const int nr = static_cast<int>((r0 + PR < nn) ? PR : nn - r0);
     if (threadIdx.x <= PR) rp[threadIdx.x] = row_ptr[r0 + (threadIdx.x <= nr ? threadIdx.x : nr)];
-    if (threadIdx.x < PR) {
+    if (threadIdx.x < 64) {  // prefix of the rows' adjacency lengths in wave 0
         const int r = threadIdx.x;
-        alen[r] = r < nr ? min(adj_len[r0 + r], CSR_MAXADJ) : 0;
-        dslot[r] = r < nr ? dpos[r0 + r] : 0;
+        const int L = r < nr ? min(adj_len[r0 + r], CSR_MAXADJ) : 0;
+        if (r < PR) dslot[r] = r < nr ? dpos[r0 + r] : 0;
+        int x = L;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(x, d, 64);
+            if (r >= d) x += y;
+        }
+        if (r < PR) apre[r] = x - L;
+        if (r == PR - 1) apre[PR] = x;
     }
     __syncthreads();
     const int32_t w0 = rp[0];
@@ -56,7 +77,8 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_
         shK[w] = 0;
         shM[w] = 0;
     }
-    // this thread's entries: row r = item % PR, entry j = item / PR; loads without branches
+    // this thread's entries k = thread + q PBT of the block's flat list; loads without branches
+    static_assert(PR <= 64, "the row prefix runs in one wave");
     int rq[PITEMS];
     int64_t eq[PITEMS];
     int aq[PITEMS];
@@ -64,8 +86,8 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_
 #pragma unroll
     for (int q = 0; q < PITEMS; ++q) {
         const int idx = threadIdx.x + q * PBT;
-        const int r = idx % PR, j = idx / PR;
-        const bool ok = j < alen[r];
+        const bool ok = idx < apre[PR];
+        const int r = ok ? last_le(apre, PR, idx) : 0, j = idx - apre[r];
         const int64_t t = ok ? (r0 + r) * CSR_MAXADJ + j : r0 * CSR_MAXADJ;
         const int32_t w = adj[t];
         pq[q] = P2 ? pk2[t] : static_cast<uint64_t>(pk[t]);
@@ -126,13 +148,37 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_
     }
 }
 
-template <int NB, bool P2, typename T>
-void launch_pages(const CsrView& v, const void* pK, const void* pM, void* vK, void* vM, hipStream_t s) {
-    const size_t shm = static_cast<size_t>(v.wmax16) * (2 * sizeof(typename Exact<T>::acc) + 8);
+constexpr size_t PLDS = 65536;  // LDS budget of the window
+
+template <typename T>
+size_t window_bytes(int w) {
+    return static_cast<size_t>(w) * (2 * sizeof(typename Exact<T>::acc) + 8);
+}
+
+// rows per block: the largest of 32, 16, 8, 4 whose entries fit PCAP and whose window fits
+template <typename T>
+int pages_rows(const CsrView& v) {
+    if (32 * v.max_adj <= PCAP && window_bytes<T>(v.wmax32) <= PLDS) return 32;
+    if (16 * v.max_adj <= PCAP && window_bytes<T>(v.wmax16) <= PLDS) return 16;
+    if (8 * v.max_adj <= PCAP && window_bytes<T>(v.wmax16) <= PLDS) return 8;
+    return window_bytes<T>(v.wmax4) <= PLDS ? 4 : 0;
+}
+
+template <int NB, bool P2, typename T, int PR>
+void launch_pages_rows(const CsrView& v, const void* pK, const void* pM, void* vK, void* vM, hipStream_t s) {
+    const int w = PR == 32 ? v.wmax32 : PR == 4 ? v.wmax4 : v.wmax16;  // 8 rows lie inside an aligned 16
     const unsigned g = static_cast<unsigned>(ceil_div(v.nn, PR));
-    hipLaunchKernelGGL((k_assemble_pages<NB, P2, T>), dim3(g), dim3(PBT), shm, s, v.nn, v.row_ptr, v.adj_len, v.adj,
-                       v.pk, v.pk2, v.dpos, static_cast<const T*>(pK), static_cast<const T*>(pM), static_cast<T*>(vK),
-                       static_cast<T*>(vM));
+    hipLaunchKernelGGL((k_assemble_pages<NB, P2, T, PR>), dim3(g), dim3(PBT), window_bytes<T>(w), s, v.nn, v.row_ptr,
+                       v.adj_len, v.adj, v.pk, v.pk2, v.dpos, static_cast<const T*>(pK), static_cast<const T*>(pM),
+                       static_cast<T*>(vK), static_cast<T*>(vM));
+}
+
+template <int NB, bool P2, typename T>
+void launch_pages(const CsrView& v, int pr, const void* pK, const void* pM, void* vK, void* vM, hipStream_t s) {
+    if (pr == 32) launch_pages_rows<NB, P2, T, 32>(v, pK, pM, vK, vM, s);
+    else if (pr == 16) launch_pages_rows<NB, P2, T, 16>(v, pK, pM, vK, vM, s);
+    else if (pr == 8) launch_pages_rows<NB, P2, T, 8>(v, pK, pM, vK, vM, s);
+    else launch_pages_rows<NB, P2, T, 4>(v, pK, pM, vK, vM, s);
 }
 
 }  // namespace pf
@@ -148,25 +194,25 @@ pf_status pf_csr_assemble_pages(const pf_csr* csr, pf_dtype prec, const void* pa
     if ((valsK && !pagesK) || (valsM && !pagesM) || (!valsK && !valsM))
         return fail(PF_EINVAL, "pf_csr_assemble_pages: each output needs its pages, and one output is needed");
     if (v.nn == 0 || v.nnz == 0) return PF_OK;
-    const size_t shm = static_cast<size_t>(v.wmax16) * (prec == PF_F32 ? 16 : 24);
-    if (shm > 65536) return fail(PF_ELIMIT, "pf_csr_assemble_pages: a CSR window of 16 rows exceeds the LDS budget");
+    const bool f32 = prec == PF_F32;
+    const int pr = f32 ? pages_rows<float>(v) : pages_rows<double>(v);
+    if (pr == 0) return fail(PF_ELIMIT, "pf_csr_assemble_pages: a CSR window of 4 rows exceeds the LDS budget");
     hipStream_t s = as_stream(stream);
     // an output without its request still gets the other's pages read as zero
     const void* pK = valsK ? pagesK : nullptr;
     const void* pM = valsM ? pagesM : nullptr;
-    const bool f32 = prec == PF_F32;
     switch (v.nlb) {
         case 3:
-            f32 ? launch_pages<3, false, float>(v, pK, pM, valsK, valsM, s) : launch_pages<3, false, double>(v, pK, pM, valsK, valsM, s);
+            f32 ? launch_pages<3, false, float>(v, pr, pK, pM, valsK, valsM, s) : launch_pages<3, false, double>(v, pr, pK, pM, valsK, valsM, s);
             break;
         case 4:
-            f32 ? launch_pages<4, false, float>(v, pK, pM, valsK, valsM, s) : launch_pages<4, false, double>(v, pK, pM, valsK, valsM, s);
+            f32 ? launch_pages<4, false, float>(v, pr, pK, pM, valsK, valsM, s) : launch_pages<4, false, double>(v, pr, pK, pM, valsK, valsM, s);
             break;
         case 6:
-            f32 ? launch_pages<6, true, float>(v, pK, pM, valsK, valsM, s) : launch_pages<6, true, double>(v, pK, pM, valsK, valsM, s);
+            f32 ? launch_pages<6, true, float>(v, pr, pK, pM, valsK, valsM, s) : launch_pages<6, true, double>(v, pr, pK, pM, valsK, valsM, s);
             break;
         case 10:
-            f32 ? launch_pages<10, true, float>(v, pK, pM, valsK, valsM, s) : launch_pages<10, true, double>(v, pK, pM, valsK, valsM, s);
+            f32 ? launch_pages<10, true, float>(v, pr, pK, pM, valsK, valsM, s) : launch_pages<10, true, double>(v, pr, pK, pM, valsK, valsM, s);
             break;
         default:
             return fail(PF_EINVAL, "pf_csr_assemble_pages: unsupported element");
