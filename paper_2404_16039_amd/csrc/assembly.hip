@@ -347,13 +347,25 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RR;
     const int nr = static_cast<int>((r0 + RR < nn) ? RR : nn - r0);
     const int64_t e0 = r0 * MAXADJ;  // the block's adjacency rows start here (padded layout)
+    // the first batch of entries is read together with the row lengths (padded rows: every
+    // entry below MAXADJ of a row of the matrix is in bounds; entries past a row's length are
+    // dropped once the lengths are known), so the element gathers wait for one round trip
+    static_assert(RT * RBATCH / RR <= MAXADJ, "the first batch lies inside the padded rows");
+    int32_t apre[RBATCH];
+#pragma unroll
+    for (int b = 0; b < RBATCH; ++b) {
+        const int idx = static_cast<int>(threadIdx.x) + b * RT;
+        const int r = idx % RR, j = idx / RR;
+        apre[b] = adj[e0 + (r < nr ? r : 0) * MAXADJ + j];
+    }
+    const int32_t lpre = adj_len[r0 + (static_cast<int>(threadIdx.x) < nr ? threadIdx.x : 0)];
     for (int h = threadIdx.x; h < RR * RSUB; h += RT) tab[h] = -1;
     guard[threadIdx.x] = -2;
     if (threadIdx.x == 0) maxl = 0;
     __syncthreads();
     if (threadIdx.x < RR) {
         const int r = threadIdx.x;
-        const int L = r < nr ? min(adj_len[r0 + r], MAXADJ) : 0;  // longer rows raised an error already
+        const int L = r < nr ? min(lpre, MAXADJ) : 0;  // longer rows raised an error already
         alen[r] = L;
         cnt[r] = 0;
         if (r < nr && L == 0) dpos[r0 + r] = 0;  // a node of no element has an empty row
@@ -378,6 +390,7 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
         int32_t aq[RBATCH];
         // loads without branches (an empty item reads entry 0 and element 0, and is dropped),
         // so all of them are in flight together
+        const bool first = base == static_cast<int>(threadIdx.x);
 #pragma unroll
         for (int b = 0; b < RBATCH; ++b) {
             const int idx = base + b * RT;
@@ -385,7 +398,7 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
             const bool ok = idx < items && j < alen[r];
             rq[b] = ok ? r : -1;
             tq[b] = ok ? r * MAXADJ + j : 0;
-            aq[b] = adj[e0 + tq[b]];
+            aq[b] = first ? apre[b] : adj[e0 + tq[b]];
         }
 #pragma unroll
         for (int b = 0; b < RBATCH; ++b) aq[b] = rq[b] >= 0 ? aq[b] : 0;
@@ -536,7 +549,6 @@ __global__ __launch_bounds__(RT2) void k_pattern_p2(int64_t nn, const int32_t* _
     __shared__ int32_t tab[RR * RSUB2];
     __shared__ int32_t guard[RT2];
     __shared__ int32_t seg[RR * MAXROW2];
-    __shared__ int32_t srt[RR * MAXROW2];
     __shared__ uint8_t seg_h[RR * MAXROW2];
     __shared__ uint8_t slot_rank[RR * RSUB2];
     __shared__ uint64_t eslot[RR * MAXADJ];  // per item: table slot of other node k << 7k
@@ -544,16 +556,30 @@ __global__ __launch_bounds__(RT2) void k_pattern_p2(int64_t nn, const int32_t* _
     __shared__ int32_t cpre[RR + 1];
     __shared__ int32_t alen[RR];
     __shared__ int32_t maxl;
+    static_assert(RSUB2 == MAXROW2, "the sorted columns reuse the tables");
+    int32_t* srt = tab;  // the block's columns in CSR order, once the row lists are built
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RR;
     const int nr = static_cast<int>((r0 + RR < nn) ? RR : nn - r0);
     const int64_t e0 = r0 * MAXADJ;
+    // the first batch of entries is read together with the row lengths (padded rows: every
+    // entry below MAXADJ of a row of the matrix is in bounds; entries past a row's length are
+    // dropped once the lengths are known)
+    static_assert(RT2 * RBATCH / RR <= MAXADJ, "the first batch lies inside the padded rows");
+    int32_t apre[RBATCH];
+#pragma unroll
+    for (int b = 0; b < RBATCH; ++b) {
+        const int idx = static_cast<int>(threadIdx.x) + b * RT2;
+        const int r = idx % RR, j = idx / RR;
+        apre[b] = adj[e0 + (r < nr ? r : 0) * MAXADJ + j];
+    }
+    const int32_t lpre = adj_len[r0 + (static_cast<int>(threadIdx.x) < nr ? threadIdx.x : 0)];
     for (int h = threadIdx.x; h < RR * RSUB2; h += RT2) tab[h] = -1;
     guard[threadIdx.x] = -2;
     if (threadIdx.x == 0) maxl = 0;
     __syncthreads();
     if (threadIdx.x < RR) {
         const int r = threadIdx.x;
-        const int L = r < nr ? min(adj_len[r0 + r], MAXADJ) : 0;
+        const int L = r < nr ? min(lpre, MAXADJ) : 0;
         alen[r] = L;
         if (r < nr && L == 0) dpos[r0 + r] = 0;
         if (L > 0) {
@@ -565,46 +591,77 @@ __global__ __launch_bounds__(RT2) void k_pattern_p2(int64_t nn, const int32_t* _
     bool bad = false;
     __syncthreads();
     const int items = RR * maxl;
-    for (int idx = threadIdx.x; idx < items; idx += RT2) {
-        const int r = idx % RR, j = idx / RR;
-        const bool ok = j < alen[r];
-        const int32_t w = adj[e0 + (ok ? r * MAXADJ + j : 0)];
-        const int a = ok ? (w & 15) : 0;
-        const int64_t e = ok ? (static_cast<uint32_t>(w) >> 4) : 0;
-        int32_t nd[NLB];
+    // element node ids in 8-byte loads (NLB even: an element's ids start 8-byte aligned)
+    static_assert(NLB % 2 == 0, "P2 elements have 6 or 10 nodes");
+    const bool al8 = (reinterpret_cast<uintptr_t>(elems) & 7) == 0;
+    for (int base = threadIdx.x; base < items; base += RT2 * RBATCH) {
+        const bool first = base == static_cast<int>(threadIdx.x);
+        int rq[RBATCH], aq[RBATCH];
+        int64_t eq[RBATCH];
 #pragma unroll
-        for (int k = 0; k < NLB; ++k) nd[k] = elems[e * NLB + k];
-        // first probes of the element's other nodes together; an empty item probes the guard
-        int32_t ov[NO], cq[NO];
-#pragma unroll
-        for (int k = 0; k < NO; ++k) {
-            ov[k] = k < a ? nd[k] : nd[k + 1];
-            cq[k] = atomicCAS(ok ? tab + r * RSUB2 + rsub2_hash(ov[k]) : guard + threadIdx.x, -1, ov[k]);
+        for (int b = 0; b < RBATCH; ++b) {
+            const int idx = base + b * RT2;
+            const int r = idx % RR, j = idx / RR;
+            const bool ok = idx < items && j < alen[r];
+            const int32_t w = first ? apre[b] : adj[e0 + (ok ? r * MAXADJ + j : 0)];
+            rq[b] = ok ? r : -1;
+            aq[b] = ok ? (w & 15) : 0;
+            eq[b] = ok ? (static_cast<uint32_t>(w) >> 4) : 0;
         }
-        if (!ok) continue;
-        int32_t* rt = tab + r * RSUB2;
-        uint64_t word = 0;
+        int32_t nd[RBATCH][NLB];
 #pragma unroll
-        for (int k = 0; k < NO; ++k) {
-            const int32_t v = ov[k];
-            int h = rsub2_hash(v);
-            int32_t cur = cq[k];
-#pragma unroll 1
-            for (int probe = 1; cur != -1 && cur != v; ++probe) {  // taken: linear probing
-                if (probe == RSUB2) {
-                    h = -1;
-                    break;
+        for (int b = 0; b < RBATCH; ++b) {
+            if (al8) {
+                const int2* pe = reinterpret_cast<const int2*>(elems + eq[b] * NLB);
+#pragma unroll
+                for (int k = 0; k < NLB / 2; ++k) {
+                    const int2 v = pe[k];
+                    nd[b][2 * k] = v.x;
+                    nd[b][2 * k + 1] = v.y;
                 }
-                h = (h + 1) & (RSUB2 - 1);
-                cur = atomicCAS(rt + h, -1, v);
+            } else {
+#pragma unroll
+                for (int k = 0; k < NLB; ++k) nd[b][k] = elems[eq[b] * NLB + k];
             }
-            if (h < 0) {
-                bad = true;
-                continue;
-            }
-            word |= static_cast<uint64_t>(h) << (7 * k);
         }
-        eslot[idx] = word;
+        // first probes of the elements' other nodes together; an empty item probes the guard
+        int32_t ov[RBATCH][NO], cq[RBATCH][NO];
+#pragma unroll
+        for (int b = 0; b < RBATCH; ++b) {
+#pragma unroll
+            for (int k = 0; k < NO; ++k) {
+                ov[b][k] = k < aq[b] ? nd[b][k] : nd[b][k + 1];
+                cq[b][k] = atomicCAS(rq[b] >= 0 ? tab + rq[b] * RSUB2 + rsub2_hash(ov[b][k]) : guard + threadIdx.x, -1,
+                                     ov[b][k]);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < RBATCH; ++b) {
+            if (rq[b] < 0) continue;
+            int32_t* rt = tab + rq[b] * RSUB2;
+            uint64_t word = 0;
+#pragma unroll
+            for (int k = 0; k < NO; ++k) {
+                const int32_t v = ov[b][k];
+                int h = rsub2_hash(v);
+                int32_t cur = cq[b][k];
+#pragma unroll 1
+                for (int probe = 1; cur != -1 && cur != v; ++probe) {  // taken: linear probing
+                    if (probe == RSUB2) {
+                        h = -1;
+                        break;
+                    }
+                    h = (h + 1) & (RSUB2 - 1);
+                    cur = atomicCAS(rt + h, -1, v);
+                }
+                if (h < 0) {
+                    bad = true;
+                    continue;
+                }
+                word |= static_cast<uint64_t>(h) << (7 * k);
+            }
+            eslot[base + b * RT2] = word;
+        }
     }
     if (bad) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
     __syncthreads();
