@@ -1011,8 +1011,44 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
     __shared__ int16_t list[FR * FSUB];  // used slots of each row
     __shared__ int32_t nlist[FR], dslot[FR], alen[FR], lpre[FR + 1];
     __shared__ int32_t maxl;
+    __shared__ int32_t rowp[FR], rowf[FR], rowb[FR];
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * FR;
     const int nr = static_cast<int>((r0 + FR < nn) ? FR : nn - r0);
+    // every load that does not depend on another is issued first: the row lengths, diagonal
+    // positions and (pass 1) offsets of the rows, and the first FPRE batches of entries
+    // (padded rows: every entry below MAXADJ of a row of the matrix is in bounds; entries
+    // past a row's length are dropped once the lengths are known)
+    constexpr int FPRE = 2;
+    static_assert(FT * FPRE / FR <= MAXADJ, "the first batches lie inside the padded rows");
+    int32_t wpre[FPRE];
+    uint32_t ppre[FPRE];
+#pragma unroll
+    for (int b = 0; b < FPRE; ++b) {
+        const int idx = static_cast<int>(threadIdx.x) + b * FT;
+        const int r = idx % FR, j = idx / FR;
+        const int64_t t = (r0 + (r < nr ? r : 0)) * MAXADJ + j;
+        wpre[b] = adj[t];
+        ppre[b] = pk[t];
+    }
+    {
+        const int r = static_cast<int>(threadIdx.x) < nr ? static_cast<int>(threadIdx.x) : 0;
+        const int32_t lv = adj_len[r0 + r], dv = dpos[r0 + r];
+        int32_t pv = 0, fv = 0, bv = 0;
+        if constexpr (PASS == 1) {
+            pv = row_ptr[r0 + r];
+            fv = fptr[r0 + r];
+            bv = bptr[r0 + r];
+        }
+        if (threadIdx.x < FR) {
+            const int L = static_cast<int>(threadIdx.x) < nr ? min(lv, MAXADJ) : 0;
+            alen[threadIdx.x] = L;
+            nlist[threadIdx.x] = 0;
+            dslot[threadIdx.x] = L > 0 ? dv : 0;
+            rowp[threadIdx.x] = pv;
+            rowf[threadIdx.x] = fv;
+            rowb[threadIdx.x] = bv;
+        }
+    }
     for (int h = threadIdx.x; h < FR * FSUB; h += FT) {
         key[h] = -1;
         cnt[h] = 0;
@@ -1020,24 +1056,12 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
         wmax[h] = 0ull;
     }
     if (threadIdx.x == 0) maxl = 0;
-    if (threadIdx.x < FR) {
-        const int r = threadIdx.x;
-        const int L = r < nr ? min(adj_len[r0 + r], MAXADJ) : 0;
-        alen[r] = L;
-        nlist[r] = 0;
-        dslot[r] = L > 0 ? dpos[r0 + r] : 0;
-    }
     __syncthreads();
     if (threadIdx.x < FR) atomicMax(&maxl, alen[threadIdx.x]);
     __syncthreads();
     bool full = false;
     // entries dealt r + FR j: the faces each one owns go into its row's table
-    for (int idx = threadIdx.x; idx < FR * maxl; idx += FT) {
-        const int r = idx % FR, j = idx / FR;
-        if (j >= alen[r]) continue;
-        const int64_t t = (r0 + r) * MAXADJ + j;
-        const int32_t w = adj[t];
-        const uint32_t p = pk[t];
+    auto entry = [&](int r, int32_t w, uint32_t p) {
         const unsigned long long e = static_cast<uint32_t>(w) >> 2;
         const int a = w & 3;
         int s[NV];
@@ -1068,6 +1092,18 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
             atomicMin(&wmin[r * FSUB + h], word);
             atomicMax(&wmax[r * FSUB + h], word);
         }
+    };
+#pragma unroll
+    for (int b = 0; b < FPRE; ++b) {
+        const int idx = static_cast<int>(threadIdx.x) + b * FT;
+        const int r = idx % FR, j = idx / FR;
+        if (j < alen[r]) entry(r, wpre[b], ppre[b]);
+    }
+    for (int idx = threadIdx.x + FPRE * FT; idx < FR * maxl; idx += FT) {
+        const int r = idx % FR, j = idx / FR;
+        if (j >= alen[r]) continue;
+        const int64_t t = (r0 + r) * MAXADJ + j;
+        entry(r, adj[t], pk[t]);
     }
     __syncthreads();
     if constexpr (PASS == 0) {
@@ -1116,9 +1152,9 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
             const uint32_t p1 = static_cast<uint32_t>(w1 & 0x3ffffffu);
             const int a1 = static_cast<int>(p1 & 3);  // local index of node i in e1
             const bool flip = esign[e1] != 0;
-            const int32_t rb = row_ptr[i];
-            const int64_t f = fptr[i] + rank;
-            const int64_t fb = c == 1 ? bptr[i] + brank : -1;
+            const int32_t rb = rowp[r];
+            const int64_t f = rowf[r] + rank;
+            const int64_t fb = c == 1 ? rowb[r] + brank : -1;
 #pragma unroll
             for (int t = 0; t < NV; ++t) {
                 const int L = face_local(NLB, opp, flip ? NV - 1 - t : t);  // local node of e1
