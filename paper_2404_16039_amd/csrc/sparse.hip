@@ -15,6 +15,7 @@
 #include "internal.hpp"
 
 #include <string>
+#include <type_traits>
 
 namespace pf {
 
@@ -34,11 +35,49 @@ __device__ __forceinline__ int last_le(const int32_t* v, int n, int x) {
     return lo;
 }
 
+// column a of a page (NB consecutive values from base) into v, zeros without pages.  With
+// NB even a column starts 8 bytes (FP32) or 16 bytes (FP64) into an aligned page array, and
+// 16 bytes in FP32 when NB = 4, so VEC (the host found the arrays 16-byte aligned) allows
+// vector loads; a compile-time choice, so no scalar copy of the loads exists beside them.
+template <int NB, typename T, bool VEC>
+__device__ __forceinline__ void load_column(const T* __restrict__ pg, int64_t base, T (&v)[NB]) {
+    constexpr bool vec = VEC;
+    if (pg == nullptr) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) v[b] = T(0);
+        return;
+    }
+    if constexpr (sizeof(T) == 4 && NB == 4) {
+        if constexpr (vec) {
+            const float4 x = *reinterpret_cast<const float4*>(pg + base);
+            v[0] = x.x;
+            v[1] = x.y;
+            v[2] = x.z;
+            v[3] = x.w;
+            return;
+        }
+    } else if constexpr (NB % 2 == 0) {
+        using V2 = typename std::conditional<sizeof(T) == 4, float2, double2>::type;
+        if constexpr (vec) {
+            const V2* x = reinterpret_cast<const V2*>(pg + base);
+#pragma unroll
+            for (int k = 0; k < NB / 2; ++k) {
+                const V2 y = x[k];
+                v[2 * k] = y.x;
+                v[2 * k + 1] = y.y;
+            }
+            return;
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) v[b] = pg[base + b];
+}
+
 // NB nodes per element; P2: entries are (element << 4 | a) with pk2, else (element << 2 | a)
 // with pk.  pages: ne x NB x NB, column-major (entry (a, b) at a + b NB).  PR rows per block,
 // chosen by the host so that PR times the longest adjacency list fits PCAP; the block's
 // entries are dealt flat (row after row), entry k to thread k mod PBT.
-template <int NB, bool P2, typename T, int PR>
+template <int NB, bool P2, typename T, int PR, bool VEC>
 __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_t* __restrict__ row_ptr,
                                                         const int32_t* __restrict__ adj_len,
                                                         const int32_t* __restrict__ adj, const uint32_t* __restrict__ pk,
@@ -108,11 +147,8 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_
 #pragma unroll
     for (int q = 0; q < PITEMS; ++q) {
         const int64_t base = eq[q] * (NB * NB) + aq[q] * NB;  // column a
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            kv[q][b] = pagesK ? pagesK[base + b] : T(0);
-            mv[q][b] = pagesM ? pagesM[base + b] : T(0);
-        }
+        load_column<NB, T, VEC>(pagesK, base, kv[q]);
+        load_column<NB, T, VEC>(pagesM, base, mv[q]);
     }
     // per-slot grid: the largest contribution
 #pragma unroll
@@ -168,9 +204,16 @@ template <int NB, bool P2, typename T, int PR>
 void launch_pages_rows(const CsrView& v, const void* pK, const void* pM, void* vK, void* vM, hipStream_t s) {
     const int w = PR == 32 ? v.wmax32 : PR == 4 ? v.wmax4 : v.wmax16;  // 8 rows lie inside an aligned 16
     const unsigned g = static_cast<unsigned>(ceil_div(v.nn, PR));
-    hipLaunchKernelGGL((k_assemble_pages<NB, P2, T, PR>), dim3(g), dim3(PBT), window_bytes<T>(w), s, v.nn, v.row_ptr,
-                       v.adj_len, v.adj, v.pk, v.pk2, v.dpos, static_cast<const T*>(pK), static_cast<const T*>(pM),
-                       static_cast<T*>(vK), static_cast<T*>(vM));
+    // vector column loads: an even page order and 16-byte aligned page arrays
+    const bool vec = NB % 2 == 0 && (reinterpret_cast<uintptr_t>(pK) & 15) == 0 && (reinterpret_cast<uintptr_t>(pM) & 15) == 0;
+    if (vec)
+        hipLaunchKernelGGL((k_assemble_pages<NB, P2, T, PR, NB % 2 == 0>), dim3(g), dim3(PBT), window_bytes<T>(w), s, v.nn,
+                           v.row_ptr, v.adj_len, v.adj, v.pk, v.pk2, v.dpos, static_cast<const T*>(pK),
+                           static_cast<const T*>(pM), static_cast<T*>(vK), static_cast<T*>(vM));
+    else
+        hipLaunchKernelGGL((k_assemble_pages<NB, P2, T, PR, false>), dim3(g), dim3(PBT), window_bytes<T>(w), s, v.nn,
+                           v.row_ptr, v.adj_len, v.adj, v.pk, v.pk2, v.dpos, static_cast<const T*>(pK),
+                           static_cast<const T*>(pM), static_cast<T*>(vK), static_cast<T*>(vM));
 }
 
 template <int NB, bool P2, typename T>
