@@ -942,12 +942,17 @@ __device__ __forceinline__ int fsub_hash(int32_t k) {
 static_assert(FSUB == 128, "fsub_hash yields 7 bits");
 
 // find or insert k in a row's face table (one compare-and-swap per probe); -1 when full
+// A face table word holds the face's key (bits 0-23) and the number of elements that
+// reached it (bits 24-30: at most 64, the elements around a node), -1 when empty.
+constexpr int32_t FKEY = (1 << 24) - 1;
+constexpr int FCNT = 24;
+
 __device__ __forceinline__ int fsub_insert(int32_t* tab, int32_t k, bool& fresh) {
     int h = fsub_hash(k);
 #pragma unroll 1
     for (int probe = 0; probe < FSUB; ++probe) {
         const int32_t cur = atomicCAS(tab + h, -1, k);
-        if (cur == -1 || cur == k) {
+        if (cur == -1 || (cur & FKEY) == k) {
             fresh = cur == -1;
             return h;
         }
@@ -1003,11 +1008,12 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
                                               int32_t* __restrict__ bfaces, int32_t* __restrict__ bel,
                                               int64_t* __restrict__ info) {
     constexpr int NV = NLB - 1;  // nodes of a face = other nodes of an element
-    __shared__ int32_t key[FR * FSUB];
-    __shared__ int32_t cnt[FR * FSUB];
+    __shared__ int32_t key[FR * FSUB];  // face key | element count << FCNT
     // element << 32 | slot word of its entry | opposite local node << 26: the smallest and the
-    // largest element of each face, with what it takes to name the face's nodes
-    __shared__ unsigned long long wmin[FR * FSUB], wmax[FR * FSUB];
+    // largest element of each face, with what it takes to name the face's nodes (pass 1 only:
+    // the counting pass keeps its LDS small, for more resident blocks)
+    constexpr int WS = PASS == 1 ? FR * FSUB : 1;
+    __shared__ unsigned long long wmin[WS], wmax[WS];
     __shared__ int16_t list[FR * FSUB];  // used slots of each row
     __shared__ int32_t nlist[FR], dslot[FR], alen[FR], lpre[FR + 1];
     __shared__ int32_t maxl;
@@ -1051,9 +1057,10 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
     }
     for (int h = threadIdx.x; h < FR * FSUB; h += FT) {
         key[h] = -1;
-        cnt[h] = 0;
-        wmin[h] = ~0ull;
-        wmax[h] = 0ull;
+        if constexpr (PASS == 1) {
+            wmin[h] = ~0ull;
+            wmax[h] = 0ull;
+        }
     }
     if (threadIdx.x == 0) maxl = 0;
     __syncthreads();
@@ -1086,11 +1093,14 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
                 continue;
             }
             if (fresh) list[r * FSUB + atomicAdd(&nlist[r], 1)] = static_cast<int16_t>(h);
-            atomicAdd(&cnt[r * FSUB + h], 1);
-            const int opp = k < a ? k : k + 1;  // local index of the opposite node
-            const unsigned long long word = (e << 32) | (static_cast<unsigned long long>(opp) << 26) | (p & 0x3ffffffu);
-            atomicMin(&wmin[r * FSUB + h], word);
-            atomicMax(&wmax[r * FSUB + h], word);
+            atomicAdd(&key[r * FSUB + h], 1 << FCNT);
+            if constexpr (PASS == 1) {
+                const int opp = k < a ? k : k + 1;  // local index of the opposite node
+                const unsigned long long word =
+                    (e << 32) | (static_cast<unsigned long long>(opp) << 26) | (p & 0x3ffffffu);
+                atomicMin(&wmin[r * FSUB + h], word);
+                atomicMax(&wmax[r * FSUB + h], word);
+            }
         }
     };
 #pragma unroll
@@ -1112,7 +1122,7 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
             const int r = threadIdx.x;
             int nb = 0;
             for (int u = 0; u < nlist[r]; ++u) {
-                const int c = cnt[r * FSUB + list[r * FSUB + u]];
+                const int c = key[r * FSUB + list[r * FSUB + u]] >> FCNT;
                 nb += c == 1;
                 bad = bad || c > 2;
             }
@@ -1136,14 +1146,15 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
             int r = 0;
             while (q >= lpre[r + 1]) ++r;
             const int h = list[r * FSUB + (q - lpre[r])];
-            const int32_t kk = key[r * FSUB + h];
-            const int c = cnt[r * FSUB + h];
+            const int32_t kk = key[r * FSUB + h] & FKEY;
+            const int c = key[r * FSUB + h] >> FCNT;
             int rank = 0, brank = 0;
             for (int v = 0; v < nlist[r]; ++v) {
                 const int h2 = list[r * FSUB + v];
-                const bool before = key[r * FSUB + h2] < kk;
+                const int32_t w2 = key[r * FSUB + h2];
+                const bool before = (w2 & FKEY) < kk;
                 rank += before;
-                brank += before && cnt[r * FSUB + h2] == 1;
+                brank += before && (w2 >> FCNT) == 1;
             }
             const int64_t i = r0 + r;
             const unsigned long long w1 = wmin[r * FSUB + h];
