@@ -197,7 +197,9 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
                                                    int64_t* __restrict__ info) {
     __shared__ int32_t keys[AG_HASH];
     __shared__ int32_t vals[AG_HASH];
-    __shared__ int32_t uniq[AG_TILE];  // table slots of the tile's distinct nodes
+    __shared__ int16_t uniq[AG_TILE];  // table slots of the tile's distinct nodes (16 bits: LDS
+                                       // under 20 KB, eight resident blocks per CU)
+    static_assert(AG_HASH <= 32768, "table slots fit 16 bits");
     __shared__ int32_t nuniq;
     __shared__ int32_t guard[AG_BS];  // never -1: the first probes of empty entries
     for (int h = threadIdx.x; h < AG_HASH; h += AG_BS) {
@@ -236,7 +238,7 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
             c = atomicCAS(keys + h, -1, node[q]);
         }
         slot[q] = h;
-        if (c == -1) uniq[atomicAdd(&nuniq, 1)] = h;
+        if (c == -1) uniq[atomicAdd(&nuniq, 1)] = static_cast<int16_t>(h);
         atomicAdd(vals + h, 1);
     }
     if (bad) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_INDEX));
