@@ -1502,8 +1502,15 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
     }
 }
 
+// waves per SIMD the numeric kernel is compiled for: 8 (at most 64 VGPRs) where the FP32
+// body fits them without spilling (constant coefficients), else the compiler's choice
+template <typename T, int QN>
+constexpr int numeric_waves() {
+    return sizeof(T) == 4 && QN == 0 ? 8 : 1;
+}
+
 template <int DIM, typename T, bool COEF, int NR, int QN = 0>
-__global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __restrict__ coords,
+__global__ __launch_bounds__(NBT, (numeric_waves<T, QN>())) void k_numeric(int64_t nn, const double* __restrict__ coords,
                                                  const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
                                                  const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
                                                  const uint32_t* __restrict__ pk, const T* __restrict__ cK,
