@@ -105,14 +105,21 @@ __global__ __launch_bounds__(RBS) void k_rhs_nodes(int64_t nn, int nlb, const in
     int L[RHS_ROWS];
     int32_t w0[RHS_ROWS];
     T v0[RHS_ROWS], v1[RHS_ROWS];
+    // the rows' lengths and their first 128 bytes (one line each) are read together: every
+    // word of a padded row is in bounds, and words past the row's length are dropped
+    int32_t Lr[RHS_ROWS];
 #pragma unroll
     for (int k = 0; k < RHS_ROWS; ++k) {  // every lane takes part in the shuffles
         i[k] = h * RHS_ROWS + k;
-        L[k] = i[k] < nn ? min(adj_len[i[k]], CSR_MAXADJ) : 0;
+        const int64_t ic = i[k] < nn ? i[k] : nn - 1;
+        Lr[k] = adj_len[ic];
+        w0[k] = adj[ic * CSR_MAXADJ + l];
     }
 #pragma unroll
-    for (int k = 0; k < RHS_ROWS; ++k)  // the rows' first 128 bytes: one line each
-        w0[k] = l < L[k] ? adj[i[k] * CSR_MAXADJ + l] : 0;
+    for (int k = 0; k < RHS_ROWS; ++k) {
+        L[k] = i[k] < nn ? min(Lr[k], CSR_MAXADJ) : 0;
+        w0[k] = l < L[k] ? w0[k] : 0;
+    }
 #pragma unroll
     for (int k = 0; k < RHS_ROWS; ++k) {
         v0[k] = l < L[k] ? b2D[static_cast<int64_t>(w0[k] >> 2) * nlb + (w0[k] & 3)] : T(0);
