@@ -219,8 +219,11 @@ pf_status pf_csr_symbolic_p2(pf_csr* csr, int dim, int64_t nn, int64_t ne, const
  * Pages ne x nlb x nlb column-major of type prec, as pf_elem_stiffness_mass (P1) and
  * pf_p2_elements (P2) write them; device pointers.  Each value is summed exactly on a grid
  * fixed by its largest contribution, as in pf_assemble.  valsK or valsM nullable (not both);
- * each output needs its pages.  PF_ELIMIT if 16 consecutive rows hold more entries than the
- * kernel's LDS budget (4096 FP32, 2730 FP64). */
+ * each output needs its pages.  Rows are taken 32, 16, 8 or 4 at a time, as the longest
+ * adjacency list and the LDS budget allow; PF_ELIMIT if 4 consecutive rows (starting at a
+ * multiple of 4) hold more entries than that budget (4096 FP32, 2730 FP64).  Page arrays
+ * that start 16-byte aligned are read with vector loads (any alignment of the type is
+ * accepted). */
 pf_status pf_csr_assemble_pages(const pf_csr* csr, pf_dtype prec, const void* pagesK,
                                 const void* pagesM, void* valsK, void* valsM, void* stream);
 

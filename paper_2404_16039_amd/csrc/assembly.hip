@@ -876,20 +876,26 @@ __global__ __launch_bounds__(SBS) void k_row_offsets(int64_t nn, const int32_t* 
             o[j] = boff[b];
             src[j] = colblk + (blk0 + b) * RW;
         }
-        static_assert(RW >= 64 * NRD, "a row-pattern block's region holds the words read at once");
-        int32_t v[4][NRD];
+        static_assert(RW % (64 * NRD) == 0, "rounds of 64 NRD words tile a row-pattern block's region");
+        // rounds of 64 NRD words per block, all loads of a round (4 blocks) in flight before
+        // its stores; the first round is read whole (inside the blocks' regions), later ones
+        // only where a block has words left (wave-uniform count of rounds)
+        const int nmax = max(max(n[0], n[1]), max(n[2], n[3]));
+        for (int w0 = 0; w0 < nmax; w0 += 64 * NRD) {
+            int32_t v[4][NRD];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int r = 0; r < NRD; ++r) v[j][r] = src[j][lane + 64 * r];  // inside the block's region
+                for (int r = 0; r < NRD; ++r) {
+                    const int w = w0 + lane + 64 * r;
+                    v[j][r] = (w0 == 0 || w < n[j]) ? src[j][w] : 0;
+                }
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int r = 0; r < NRD; ++r)
-                if (lane + 64 * r < n[j]) dst[o[j] + lane + 64 * r] = v[j][r];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            for (int w = 64 * NRD + lane; w < n[j]; w += 64) dst[o[j] + w] = src[j][w];
+                for (int r = 0; r < NRD; ++r)
+                    if (w0 + lane + 64 * r < n[j]) dst[o[j] + w0 + lane + 64 * r] = v[j][r];
+        }
     }
 }
 
