@@ -72,7 +72,13 @@ __device__ __forceinline__ C p2_kentry(int a, int b, const C (&G)[DIM + 1][DIM +
     return s;
 }
 
-// K and M of one element into the staging pages kp, mp (nullable: not requested); ck, cm:
+// position of entry (a, b), a >= b, of a symmetric page stored as its lower triangle
+__device__ __forceinline__ constexpr int tri(int a, int b) {
+    return a * (a + 1) / 2 + b;
+}
+
+// K and M of one element into the staging pages kp, mp (nullable: not requested), each a
+// lower triangle (entry (a, b), a >= b, at tri(a, b): both matrices are symmetric); ck, cm:
 // the element's coefficients at the points of each rule (nullable: 1)
 template <int DIM, typename C, typename T>
 __device__ __forceinline__ void p2_write(const P1Geom<DIM, C>& g, const P2Rules& R, const T* ck, const T* cm, T* kp,
@@ -123,9 +129,7 @@ __device__ __forceinline__ void p2_write(const P1Geom<DIM, C>& g, const P2Rules&
         for (int b = 0; b < NB; ++b)
 #pragma unroll
             for (int a = b; a < NB; ++a) {
-                const T v = static_cast<T>(vol * p2_kentry<DIM, C>(a, b, G, S0, S1, S2));
-                kp[a + b * NB] = v;
-                kp[b + a * NB] = v;
+                kp[tri(a, b)] = static_cast<T>(vol * p2_kentry<DIM, C>(a, b, G, S0, S1, S2));
             }
     }
     if (mp) {
@@ -154,17 +158,17 @@ __device__ __forceinline__ void p2_write(const P1Geom<DIM, C>& g, const P2Rules&
         for (int a = 0; a < NB; ++a)
 #pragma unroll
             for (int b = 0; b <= a; ++b) {
-                const T v = static_cast<T>(vol * m[a][b]);
-                mp[a + b * NB] = v;
-                mp[b + a * NB] = v;
+                mp[tri(a, b)] = static_cast<T>(vol * m[a][b]);
             }
     }
 }
 
-// One element per lane.  The lanes build their pages in LDS (row stride NB*NB + 1 words,
-// so the lanes' writes fall in different banks), then the block copies its elements'
-// contiguous run of pages out with consecutive lanes on consecutive words (coalesced):
-// first the K pages, then the M pages through the same staging area.
+// One element per lane.  The lanes build their pages in LDS as lower triangles (stride
+// NB(NB+1)/2 words, odd, so the lanes' writes fall in different banks; half the LDS of full
+// pages, hence more resident waves), then the block copies its elements' contiguous run of
+// full pages out with consecutive lanes on consecutive words (coalesced), each word read
+// from its triangle position: first the K pages, then the M pages through the same
+// staging area.
 template <int DIM, typename T>
 __global__ __launch_bounds__(P2BS) void k_p2_elem(int64_t nn, const double* __restrict__ coords, int64_t ne,
                                                   const int32_t* __restrict__ elems2, P2Rules R,
@@ -172,7 +176,8 @@ __global__ __launch_bounds__(P2BS) void k_p2_elem(int64_t nn, const double* __re
                                                   T* __restrict__ K3D, T* __restrict__ M3D, Fallback fb,
                                                   int64_t* d_counters) {
     constexpr int NB = P2Local<DIM>::NB;
-    constexpr int PS = NB * NB + 1;  // staging stride of one page
+    constexpr int PS = NB * (NB + 1) / 2;  // staging stride of one page (its lower triangle)
+    static_assert(PS % 2 == 1, "an odd stride spreads the lanes over the banks");
     __shared__ T stage[P2BS * PS];
     const int64_t e0 = static_cast<int64_t>(blockIdx.x) * P2BS;
     const int64_t e = e0 + threadIdx.x;
@@ -199,7 +204,7 @@ __global__ __launch_bounds__(P2BS) void k_p2_elem(int64_t nn, const double* __re
         const T* cl = cq ? cq + e * nq : nullptr;
         if (e < ne) {
             if (bad) {
-                for (int k = 0; k < NB * NB; ++k) page[k] = static_cast<T>(NAN);
+                for (int k = 0; k < PS; ++k) page[k] = static_cast<T>(NAN);
             } else {
                 T* kp = which == 0 ? page : nullptr;
                 T* mp = which == 1 ? page : nullptr;
@@ -220,7 +225,10 @@ __global__ __launch_bounds__(P2BS) void k_p2_elem(int64_t nn, const double* __re
         }
         __syncthreads();
         T* dst = out + e0 * (NB * NB);
-        for (int k = threadIdx.x; k < nel * NB * NB; k += P2BS) dst[k] = stage[(k / (NB * NB)) * PS + k % (NB * NB)];
+        for (int k = threadIdx.x; k < nel * NB * NB; k += P2BS) {
+            const int w = k % (NB * NB), a = w % NB, b = w / NB;  // column-major (a, b)
+            dst[k] = stage[(k / (NB * NB)) * PS + (a >= b ? tri(a, b) : tri(b, a))];
+        }
         __syncthreads();
     }
     count_wave(d_counters, 0, routed);
