@@ -948,6 +948,58 @@ def test_p2_reproduces_quadratics(d):
     assert np.allclose(M.sum(axis=(1, 2)), vol, rtol=1e-13, atol=0)
 
 
+@pytest.mark.parametrize("d", [2, 3])
+def test_p2_global_assembly(d):
+    """sparse() of P2 pages (the triples, sort and run sums of section 3.6, on 6- and 10-node
+    elements): the pattern is every node pair of an element, the values equal a brute-force
+    dense accumulation of every page entry (a, b) at row elems[e][b], column elems[e][a], and
+    the assembled forms of a quadratic v at the P2 nodes give the exact int |grad v|^2 and
+    int v^2 over the unit square / cube."""
+    coords, elems, _ = gen.square_mesh(3, jitter=0.2) if d == 2 else gen.cube_mesh(2, jitter=0.15)
+    c2, e2, _ = gen.p2_mesh(coords, elems)
+    nn2, nb = c2.shape[0], e2.shape[1]
+    o = oracle.p2_elements(c2, e2, oracle.stroud_rule(d, 2), oracle.stroud_rule(d, 3))
+    A = oracle.assemble(e2, nn2, o["K3D"], o["M3D"])
+    Kp = o["K3D"].reshape(-1, nb, nb)  # [e, b, a] = page entry (a, b) (column-major pages)
+    Mp = o["M3D"].reshape(-1, nb, nb)
+    DK, DM = np.zeros((nn2, nn2)), np.zeros((nn2, nn2))
+    P = np.zeros((nn2, nn2), dtype=bool)
+    for e in range(e2.shape[0]):
+        for a in range(nb):
+            for b in range(nb):
+                DK[e2[e, b], e2[e, a]] += Kp[e, b, a]
+                DM[e2[e, b], e2[e, a]] += Mp[e, b, a]
+                P[e2[e, b], e2[e, a]] = True
+    rp, ci = A["row_ptr"], A["col_idx"]
+    CK, CM = np.zeros((nn2, nn2)), np.zeros((nn2, nn2))
+    CP = np.zeros((nn2, nn2), dtype=bool)
+    for r in range(nn2):
+        cols = ci[rp[r]:rp[r + 1]]
+        assert np.all(np.diff(cols) > 0)
+        CK[r, cols] = A["valK"][rp[r]:rp[r + 1]]
+        CM[r, cols] = A["valM"][rp[r]:rp[r + 1]]
+        CP[r, cols] = True
+    assert np.array_equal(CP, P) and A["nnz"] == int(P.sum())
+    assert np.abs(CK - DK).max() <= 1e-14 * np.abs(DK).max()
+    assert np.abs(CM - DM).max() <= 1e-14 * np.abs(DM).max()
+
+    def v(x):
+        return x[..., 0] ** 2 + 2 * x[..., 1] * x[..., -1] - x[..., -1] + 0.5
+
+    def grad2(x):
+        g0 = 2 * x[..., 0]
+        if d == 2:  # v = x^2 + 2 y^2 - y + 0.5
+            return g0 ** 2 + (4 * x[..., 1] - 1) ** 2
+        return g0 ** 2 + (2 * x[..., 2]) ** 2 + (2 * x[..., 1] - 1) ** 2
+    gl, gw = np.polynomial.legendre.leggauss(4)
+    gl, gw = (gl + 1) / 2, gw / 2
+    grid = np.stack(np.meshgrid(*([gl] * d), indexing="ij"), axis=-1).reshape(-1, d)
+    wts = np.prod(np.stack(np.meshgrid(*([gw] * d), indexing="ij"), axis=-1).reshape(-1, d), axis=1)
+    vn = v(c2)
+    assert abs(vn @ CK @ vn - (wts * grad2(grid)).sum()) < 1e-12
+    assert abs(vn @ CM @ vn - (wts * v(grid) ** 2).sum()) < 1e-13
+
+
 def test_p2_energies_fourth_order():
     """The section 3.6 3-D benchmark with P2 elements (c_K = c_M = exp(x1+x2+x3) at the points
     of degree-5 rules, v = cos(pi x1) cos(pi x2) cos(pi x3) interpolated at the P2 nodes): the
