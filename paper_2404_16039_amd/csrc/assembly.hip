@@ -59,8 +59,8 @@ struct pf_csr {
     int64_t cap_adj_len = 0, cap_row_ptr = 0, cap_cnt = 0, cap_adj = 0, cap_pk = 0, cap_nnz = 0, cap_bsum = 0,
             cap_info = 0, cap_colblk = 0, cap_look = 0, cap_work = 0, cap_pk2 = 0;
     bool built = false;
-    // per-stage timing of pf_csr_symbolic (events e0..e5: start, after the adjacency, after
-    // the pattern, after the scan; around the compaction)
+    // per-stage timing of pf_csr_symbolic (events e0..e3: start, after the adjacency, after
+    // the pattern, after the row offsets)
     bool timing = false, pending = false;
     hipEvent_t ev[PF_CSR_STAGES + 1] = {};
     double stage_ms[PF_CSR_STAGES] = {};
