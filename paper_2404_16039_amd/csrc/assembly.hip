@@ -527,86 +527,84 @@ __global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __res
 
 // ---------------------------------------------------------------------------- P2 row pattern
 // The same block-cooperative pattern for P2 meshes (6 or 10 nodes per element): rows hold up
-// to MAXROW2 nonzeros (a vertex of the Kuhn cube's P2 mesh has 65), in 128-slot tables, and
-// every adjacency entry (element << 4 | local index a) gets pk2 = the row positions of the
-// element's other nodes in local order, 7 bits each (9 x 7 = 63 bits).  The block's sorted
-// columns go to its region of RR * MAXROW2 words of colblk, as in the P1 kernel.
+// to MAXROW2 nonzeros (a vertex of the Kuhn cube's P2 mesh has 65), and every adjacency
+// entry (element << 4 | local index a) gets pk2 = the row positions of the element's other
+// nodes in local order, 7 bits each (9 x 7 = 63 bits).  A block takes RR2 = 16 rows and 1024
+// table words: when every one of its rows can hold at most 64 nonzeros (1 + (NLB - 1) x its
+// number of elements, which covers the mid-edge rows of a P2 mesh), all 16 rows go in one
+// pass with 64-slot tables; otherwise in two passes of 8 rows with 128-slot tables.  Either
+// way the sorted columns of rows 8k .. 8k+7 go to the region of RR * MAXROW2 words of
+// colblk that the row offsets expect for that 8-row group.
 constexpr int MAXROW2 = 128;
-constexpr int RSUB2 = MAXROW2;
 constexpr int RT2 = 128;
-static_assert(RT2 >= RR && RT2 >= 64, "one thread per row and a full first wave");
+constexpr int RR2 = 2 * RR;          // rows of a P2 pattern block
+constexpr int TAB2 = RR * MAXROW2;  // table (and list) words of a block: 16 x 64 or 8 x 128
+static_assert(RT2 >= RR2 && RT2 >= 64 && RR2 <= 64, "one thread per row, one wave for the row prefix");
+static_assert(RR2 * 64 == TAB2, "the two table layouts of a block take the same LDS");
 
-__device__ __forceinline__ int rsub2_hash(int32_t v) {
-    return static_cast<int>((static_cast<uint32_t>(v) * 2654435761u) >> 25);  // 7 bits
+template <int TS>
+__device__ __forceinline__ int tsub_hash(int32_t v) {
+    static_assert(TS == 64 || TS == 128, "6- or 7-bit table slots");
+    return static_cast<int>((static_cast<uint32_t>(v) * 2654435761u) >> (TS == 64 ? 26 : 25));
 }
 
-template <int NLB>
-__global__ __launch_bounds__(RT2) void k_pattern_p2(int64_t nn, const int32_t* __restrict__ elems,
-                                                   const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
-                                                   int32_t* __restrict__ rowlen, int32_t* __restrict__ colblk,
-                                                   uint64_t* __restrict__ pk2, int32_t* __restrict__ dpos,
-                                                   int64_t* __restrict__ info) {
+struct P2Pattern {                  // LDS of a P2 pattern block
+    int32_t tab[TAB2];              // node ids, -1 empty; then the sorted columns
+    int32_t guard[RT2];             // never -1: the first probes of empty items
+    int32_t seg[TAB2];              // each row's nodes (table order), rows TS words apart
+    uint8_t seg_h[TAB2];            // table slot of each list item
+    uint8_t slot_rank[TAB2];        // rank (column position) of each used table slot
+    uint64_t eslot[RR * MAXADJ];    // per item: table slot of other node k << 7k
+    int32_t cnt[RR2];
+    int32_t cpre[RR2 + 1];
+    int32_t maxl;
+};
+
+// One pass over NRW rows (nrw of them in the matrix) starting at row rq, with TS-slot tables.
+// alen: the rows' numbers of elements (LDS); dst: the colblk region of the pass's first 8
+// rows (rows 8 .. 15 of a 16-row pass go to the next region); apre: this thread's entries of
+// the first batch (item r + NRW j), read at block start, used when `pre`.
+template <int NLB, int NRW, int TS>
+__device__ __forceinline__ void p2_pattern_pass(P2Pattern& S, const int32_t* alen, int64_t rq, int nrw,
+                                                const int32_t* __restrict__ elems, const int32_t* __restrict__ adj,
+                                                int32_t* __restrict__ rowlen, int32_t* __restrict__ dst,
+                                                uint64_t* __restrict__ pk2, int32_t* __restrict__ dpos,
+                                                const int32_t (&apre)[RBATCH], bool pre, bool& bad) {
     constexpr int NO = NLB - 1;
     static_assert(NO * 7 <= 64, "the positions of the other nodes fit one 64-bit word");
-    __shared__ int32_t tab[RR * RSUB2];
-    __shared__ int32_t guard[RT2];
-    __shared__ int32_t seg[RR * MAXROW2];
-    __shared__ uint8_t seg_h[RR * MAXROW2];
-    __shared__ uint8_t slot_rank[RR * RSUB2];
-    __shared__ uint64_t eslot[RR * MAXADJ];  // per item: table slot of other node k << 7k
-    __shared__ int32_t cnt[RR];
-    __shared__ int32_t cpre[RR + 1];
-    __shared__ int32_t alen[RR];
-    __shared__ int32_t maxl;
-    static_assert(RSUB2 == MAXROW2, "the sorted columns reuse the tables");
-    int32_t* srt = tab;  // the block's columns in CSR order, once the row lists are built
-    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RR;
-    const int nr = static_cast<int>((r0 + RR < nn) ? RR : nn - r0);
-    const int64_t e0 = r0 * MAXADJ;
-    // the first batch of entries is read together with the row lengths (padded rows: every
-    // entry below MAXADJ of a row of the matrix is in bounds; entries past a row's length are
-    // dropped once the lengths are known)
-    static_assert(RT2 * RBATCH / RR <= MAXADJ, "the first batch lies inside the padded rows");
-    int32_t apre[RBATCH];
-#pragma unroll
-    for (int b = 0; b < RBATCH; ++b) {
-        const int idx = static_cast<int>(threadIdx.x) + b * RT2;
-        const int r = idx % RR, j = idx / RR;
-        apre[b] = adj[e0 + (r < nr ? r : 0) * MAXADJ + j];
-    }
-    const int32_t lpre = adj_len[r0 + (static_cast<int>(threadIdx.x) < nr ? threadIdx.x : 0)];
-    for (int h = threadIdx.x; h < RR * RSUB2; h += RT2) tab[h] = -1;
-    guard[threadIdx.x] = -2;
-    if (threadIdx.x == 0) maxl = 0;
+    static_assert(NRW * TS == TAB2, "a pass fills the block's tables");
+    static_assert((NRW & (NRW - 1)) == 0, "NRW is a power of two");
+    const int64_t e0 = rq * MAXADJ;
+    for (int h = threadIdx.x; h < TAB2; h += RT2) S.tab[h] = -1;
+    S.guard[threadIdx.x] = -2;
+    if (threadIdx.x == 0) S.maxl = 0;
     __syncthreads();
-    if (threadIdx.x < RR) {
+    if (threadIdx.x < NRW) {
         const int r = threadIdx.x;
-        const int L = r < nr ? min(lpre, MAXADJ) : 0;
-        alen[r] = L;
-        if (r < nr && L == 0) dpos[r0 + r] = 0;
-        if (L > 0) {
-            const int32_t self = static_cast<int32_t>(r0 + r);
-            tab[r * RSUB2 + rsub2_hash(self)] = self;
-            atomicMax(&maxl, L);
+        const int L = r < nrw ? alen[r] : 0;
+        if (r < nrw && L == 0) dpos[rq + r] = 0;  // a node of no element has an empty row
+        if (L > 0) {                              // the diagonal
+            const int32_t self = static_cast<int32_t>(rq + r);
+            S.tab[r * TS + tsub_hash<TS>(self)] = self;
+            atomicMax(&S.maxl, L);
         }
     }
-    bool bad = false;
     __syncthreads();
-    const int items = RR * maxl;
+    const int items = NRW * S.maxl;
     // element node ids in 8-byte loads (NLB even: an element's ids start 8-byte aligned)
     static_assert(NLB % 2 == 0, "P2 elements have 6 or 10 nodes");
     const bool al8 = (reinterpret_cast<uintptr_t>(elems) & 7) == 0;
     for (int base = threadIdx.x; base < items; base += RT2 * RBATCH) {
-        const bool first = base == static_cast<int>(threadIdx.x);
-        int rq[RBATCH], aq[RBATCH];
+        const bool first = pre && base == static_cast<int>(threadIdx.x);
+        int rq_[RBATCH], aq[RBATCH];
         int64_t eq[RBATCH];
 #pragma unroll
         for (int b = 0; b < RBATCH; ++b) {
             const int idx = base + b * RT2;
-            const int r = idx % RR, j = idx / RR;
-            const bool ok = idx < items && j < alen[r];
+            const int r = idx % NRW, j = idx / NRW;
+            const bool ok = idx < items && j < alen[r] && r < nrw;
             const int32_t w = first ? apre[b] : adj[e0 + (ok ? r * MAXADJ + j : 0)];
-            rq[b] = ok ? r : -1;
+            rq_[b] = ok ? r : -1;
             aq[b] = ok ? (w & 15) : 0;
             eq[b] = ok ? (static_cast<uint32_t>(w) >> 4) : 0;
         }
@@ -633,27 +631,27 @@ __global__ __launch_bounds__(RT2) void k_pattern_p2(int64_t nn, const int32_t* _
 #pragma unroll
             for (int k = 0; k < NO; ++k) {
                 ov[b][k] = k < aq[b] ? nd[b][k] : nd[b][k + 1];
-                cq[b][k] = atomicCAS(rq[b] >= 0 ? tab + rq[b] * RSUB2 + rsub2_hash(ov[b][k]) : guard + threadIdx.x, -1,
-                                     ov[b][k]);
+                cq[b][k] = atomicCAS(rq_[b] >= 0 ? S.tab + rq_[b] * TS + tsub_hash<TS>(ov[b][k]) : S.guard + threadIdx.x,
+                                     -1, ov[b][k]);
             }
         }
 #pragma unroll
         for (int b = 0; b < RBATCH; ++b) {
-            if (rq[b] < 0) continue;
-            int32_t* rt = tab + rq[b] * RSUB2;
+            if (rq_[b] < 0) continue;
+            int32_t* rt = S.tab + rq_[b] * TS;
             uint64_t word = 0;
 #pragma unroll
             for (int k = 0; k < NO; ++k) {
                 const int32_t v = ov[b][k];
-                int h = rsub2_hash(v);
+                int h = tsub_hash<TS>(v);
                 int32_t cur = cq[b][k];
 #pragma unroll 1
                 for (int probe = 1; cur != -1 && cur != v; ++probe) {  // taken: linear probing
-                    if (probe == RSUB2) {
+                    if (probe == TS) {
                         h = -1;
                         break;
                     }
-                    h = (h + 1) & (RSUB2 - 1);
+                    h = (h + 1) & (TS - 1);
                     cur = atomicCAS(rt + h, -1, v);
                 }
                 if (h < 0) {
@@ -662,77 +660,122 @@ __global__ __launch_bounds__(RT2) void k_pattern_p2(int64_t nn, const int32_t* _
                 }
                 word |= static_cast<uint64_t>(h) << (7 * k);
             }
-            eslot[base + b * RT2] = word;
+            S.eslot[base + b * RT2] = word;
         }
     }
-    if (bad) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
     __syncthreads();
-    // each row's list: its used table slots (one wave per row and half table, lane = slot)
-    static_assert(RSUB2 == 128 && MAXROW2 == 128, "two table halves per row");
-    for (int r = threadIdx.x >> 6; r < RR; r += RT2 / 64) {
+    // each row's list: its used table slots (one wave per row, lane = slot of each 64)
+    for (int r = threadIdx.x >> 6; r < NRW; r += RT2 / 64) {
         const int lane = threadIdx.x & 63;
-        const int32_t v0 = tab[r * RSUB2 + lane], v1 = tab[r * RSUB2 + 64 + lane];
-        const unsigned long long m0 = __ballot(v0 != -1), m1 = __ballot(v1 != -1);
-        const int below = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m0 >> 32),
-                                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m0), 0u));
-        const int below1 = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m1 >> 32),
-                                                     __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m1), 0u));
-        const int n0 = __popcll(m0);
-        if (v0 != -1) {
-            seg[r * MAXROW2 + below] = v0;
-            seg_h[r * MAXROW2 + below] = static_cast<uint8_t>(lane);
+        int n = 0;
+#pragma unroll
+        for (int half = 0; half < TS / 64; ++half) {
+            const int32_t v = S.tab[r * TS + 64 * half + lane];
+            const unsigned long long m = __ballot(v != -1);
+            const int below = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
+            if (v != -1) {
+                S.seg[r * TS + n + below] = v;
+                S.seg_h[r * TS + n + below] = static_cast<uint8_t>(64 * half + lane);
+            }
+            n += __popcll(m);
         }
-        if (v1 != -1) {
-            seg[r * MAXROW2 + n0 + below1] = v1;
-            seg_h[r * MAXROW2 + n0 + below1] = static_cast<uint8_t>(64 + lane);
-        }
-        if (lane == 0) cnt[r] = n0 + __popcll(m1);
+        if (lane == 0) S.cnt[r] = n;
     }
     __syncthreads();
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
-        const int v = lane < nr ? cnt[lane] : 0;
+        const int v = lane < nrw ? S.cnt[lane] : 0;
         int x = v;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
             const int y = __shfl_up(x, d, 64);
             if (lane >= d) x += y;
         }
-        if (lane < nr) cpre[lane] = x - v;
-        if (lane == nr - 1) cpre[nr] = x;
+        if (lane < nrw) S.cpre[lane] = x - v;
+        if (lane == nrw - 1) S.cpre[nrw] = x;
     }
-    if (threadIdx.x < nr) rowlen[r0 + threadIdx.x] = cnt[threadIdx.x];
+    if (threadIdx.x < nrw) rowlen[rq + threadIdx.x] = S.cnt[threadIdx.x];
     __syncthreads();
-    for (int q = threadIdx.x; q < cpre[nr]; q += RT2) {
-        const int r = upper_pos(cpre, nr, q);
-        const int p = q - cpre[r];
-        const int n = cnt[r];
-        const int32_t v = seg[r * MAXROW2 + p];
+    int32_t* srt = S.tab;  // the pass's columns in CSR order (the tables are no longer read)
+    for (int q = threadIdx.x; q < S.cpre[nrw]; q += RT2) {
+        const int r = upper_pos(S.cpre, nrw, q);
+        const int p = q - S.cpre[r];
+        const int n = S.cnt[r];
+        const int32_t v = S.seg[r * TS + p];
         int rank = 0;
-        const int32_t* sr = seg + r * MAXROW2;
+        const int32_t* sr = S.seg + r * TS;
         int j = 0;
         for (; j + 4 <= n; j += 4) {
             const int32_t a0 = sr[j], a1 = sr[j + 1], a2 = sr[j + 2], a3 = sr[j + 3];
             rank += (a0 < v) + (a1 < v) + (a2 < v) + (a3 < v);
         }
         for (; j < n; ++j) rank += sr[j] < v;
-        slot_rank[r * RSUB2 + seg_h[r * MAXROW2 + p]] = static_cast<uint8_t>(rank);
-        if (v == r0 + r) dpos[r0 + r] = rank;
-        srt[cpre[r] + rank] = v;
+        S.slot_rank[r * TS + S.seg_h[r * TS + p]] = static_cast<uint8_t>(rank);
+        if (v == rq + r) dpos[rq + r] = rank;
+        srt[S.cpre[r] + rank] = v;
     }
     __syncthreads();
-    int32_t* dst = colblk + static_cast<int64_t>(blockIdx.x) * (RR * MAXROW2);
-    for (int q = threadIdx.x; q < cpre[nr]; q += RT2) dst[q] = srt[q];
+    // rows 0 .. 7 of the pass to its first region, rows 8 .. 15 (a 16-row pass) to the next
+    const int split = NRW > RR && nrw > RR ? S.cpre[RR] : S.cpre[nrw];
+    for (int q = threadIdx.x; q < S.cpre[nrw]; q += RT2)
+        dst[q < split ? q : RR * MAXROW2 + (q - split)] = srt[q];
     for (int idx = threadIdx.x; idx < items; idx += RT2) {
-        const int r = idx % RR, j = idx / RR;
-        if (j >= alen[r]) continue;
-        const uint64_t w = eslot[idx];
+        const int r = idx % NRW, j = idx / NRW;
+        if (r >= nrw || j >= alen[r]) continue;
+        const uint64_t w = S.eslot[idx];
         uint64_t word = 0;
 #pragma unroll
         for (int k = 0; k < NO; ++k)
-            word |= static_cast<uint64_t>(slot_rank[r * RSUB2 + static_cast<int>((w >> (7 * k)) & 127)]) << (7 * k);
+            word |= static_cast<uint64_t>(S.slot_rank[r * TS + static_cast<int>((w >> (7 * k)) & 127)]) << (7 * k);
         pk2[e0 + r * MAXADJ + j] = word;
     }
+    __syncthreads();  // the LDS is free for the next pass
+}
+
+template <int NLB>
+__global__ __launch_bounds__(RT2) void k_pattern_p2(int64_t nn, const int32_t* __restrict__ elems,
+                                                   const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
+                                                   int32_t* __restrict__ rowlen, int32_t* __restrict__ colblk,
+                                                   uint64_t* __restrict__ pk2, int32_t* __restrict__ dpos,
+                                                   int64_t* __restrict__ info) {
+    constexpr int NO = NLB - 1;
+    __shared__ P2Pattern S;
+    __shared__ int32_t alen[RR2];
+    __shared__ int32_t longrows;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RR2;
+    const int nr = static_cast<int>((r0 + RR2 < nn) ? RR2 : nn - r0);
+    // the first batch of entries of the one-pass layout (item r + RR2 j) is read together with
+    // the row lengths (padded rows: every entry below MAXADJ of a row of the matrix is in
+    // bounds; entries past a row's length are dropped once the lengths are known)
+    static_assert(RT2 * RBATCH / RR2 <= MAXADJ, "the first batch lies inside the padded rows");
+    int32_t apre[RBATCH];
+#pragma unroll
+    for (int b = 0; b < RBATCH; ++b) {
+        const int idx = static_cast<int>(threadIdx.x) + b * RT2;
+        const int r = idx % RR2, j = idx / RR2;
+        apre[b] = adj[(r0 + (r < nr ? r : 0)) * MAXADJ + j];
+    }
+    const int32_t lv = adj_len[r0 + (static_cast<int>(threadIdx.x) < nr ? threadIdx.x : 0)];
+    if (threadIdx.x < 64) {  // row lengths, and whether a row may hold more than 64 nonzeros (wave 0)
+        const int L = static_cast<int>(threadIdx.x) < nr ? min(lv, MAXADJ) : 0;
+        if (threadIdx.x < RR2) alen[threadIdx.x] = L;
+        const unsigned long long lg = __ballot(1 + NO * L > 64);
+        if (threadIdx.x == 0) longrows = lg != 0ull;
+    }
+    __syncthreads();
+    bool bad = false;
+    int32_t* dst = colblk + (static_cast<int64_t>(blockIdx.x) * 2) * (RR * MAXROW2);
+    if (!longrows) {
+        p2_pattern_pass<NLB, RR2, 64>(S, alen, r0, nr, elems, adj, rowlen, dst, pk2, dpos, apre, true, bad);
+    } else {
+        p2_pattern_pass<NLB, RR, MAXROW2>(S, alen, r0, min(nr, RR), elems, adj, rowlen, dst, pk2, dpos, apre, false,
+                                          bad);
+        if (nr > RR)
+            p2_pattern_pass<NLB, RR, MAXROW2>(S, alen + RR, r0 + RR, nr - RR, elems, adj, rowlen, dst + RR * MAXROW2,
+                                              pk2, dpos, apre, false, bad);
+    }
+    if (bad) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
 }
 
 // ---------------------------------------------------------------------------- row offsets
@@ -1531,7 +1574,7 @@ __global__ __launch_bounds__(NBT, (numeric_waves<T, QN>())) void k_numeric(int64
 // structure, coordinates, outputs, routing thresholds and counters, and its rows are
 // computed exactly as by k_numeric, so a job's values do not depend on its batch.
 template <int DIM, typename T, int NR>
-__global__ __launch_bounds__(NBT) void k_numeric_jobs(const NumericJob* __restrict__ jobs, int njobs, int wmax) {
+__global__ __launch_bounds__(NBT, (numeric_waves<T, 0>())) void k_numeric_jobs(const NumericJob* __restrict__ jobs, int njobs, int wmax) {
     int lo = 0, hi = njobs - 1;
     const int64_t b = blockIdx.x;
     while (lo < hi) {
@@ -1852,7 +1895,9 @@ pf_status symbolic(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const in
     const int64_t grows = ceil_div(nn, RR);
     const int64_t tiles = ceil_div(nn, SCAN_TILE);
     // nnz is known only after the pattern: col_idx holds maxrow columns per row
-    if ((st = grow(c->colblk, c->cap_colblk, std::max<int64_t>(grows * RR * maxrow, 1)))) return st;
+    // (P2 pattern blocks of 16 rows write the regions of 8-row groups 2b and 2b + 1)
+    const int64_t regions = p2 ? 2 * ceil_div(nn, RR2) : grows;
+    if ((st = grow(c->colblk, c->cap_colblk, std::max<int64_t>(regions * RR * maxrow, 1)))) return st;
     if ((st = grow(c->col_idx, c->cap_nnz, std::max<int64_t>(nn * maxrow, 1)))) return st;
     if ((st = grow(c->dpos, c->cap_dpos, nn + 1))) return st;
     // tile descriptors, then 4 int32 statistics per tile
@@ -1860,11 +1905,12 @@ pf_status symbolic(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const in
     if ((st = mark(c, 1, s))) return st;
     if (nn > 0) {
         const unsigned g = static_cast<unsigned>(grows);
+        const unsigned g2 = static_cast<unsigned>(ceil_div(nn, RR2));  // P2: 16-row blocks
         if (nlb == 10)
-            hipLaunchKernelGGL((k_pattern_p2<10>), dim3(g), dim3(RT2), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
+            hipLaunchKernelGGL((k_pattern_p2<10>), dim3(g2), dim3(RT2), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
                                c->colblk, c->pk2, c->dpos, c->info);
         else if (nlb == 6)
-            hipLaunchKernelGGL((k_pattern_p2<6>), dim3(g), dim3(RT2), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
+            hipLaunchKernelGGL((k_pattern_p2<6>), dim3(g2), dim3(RT2), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
                                c->colblk, c->pk2, c->dpos, c->info);
         else if (nlb == 4)
             hipLaunchKernelGGL((k_pattern<4>), dim3(g), dim3(RT), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
