@@ -286,3 +286,48 @@ def test_p1_pages_assembly_matches_fused(lib):
     within(host(a[2]), cs["valK"], cs["scaleK"], TOL[torch.float64], "P1 fused K (CS scale)")
     within(host(a[3]), host(a[1]), cs["scaleM"], TOL[torch.float64], "P1 fused M")
     csr.close()
+
+
+def _unaligned(t):
+    """A copy of t in device memory that starts one element past a 16-byte boundary."""
+    buf = torch.empty(t.numel() + 1, dtype=t.dtype, device="cuda")
+    buf[1:].copy_(t)
+    v = buf[1:]
+    assert v.data_ptr() % 16 != 0
+    return v
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_pages_assembly_unaligned_pages(lib, dtype):
+    """sparse() reads page columns with vector loads only from 16-byte aligned page arrays;
+    arrays that start elsewhere take element loads and give the same values bit for bit (P2
+    pages of 10 nodes, P1 pages of 4 nodes, and one output alone)."""
+    say("pages unaligned", dtype)
+    coords, elems, _ = cube(3)
+    c2, e2, _ = gen.p2_mesh(coords, elems)
+    r = oracle.stroud_rule(3, 2)
+    a = _gpu_p2_global(lib, c2, e2, dtype, r, r)
+    K = torch.from_numpy(a["K"]).cuda()
+    M = torch.from_numpy(a["M"]).cuda()
+    nnz = a["vK"].shape[0]
+    vK = torch.empty(nnz, dtype=dtype, device="cuda")
+    vM = torch.empty(nnz, dtype=dtype, device="cuda")
+    a["csr"].assemble_pages(prec_of(dtype), _unaligned(K), _unaligned(M), vK, vM)
+    assert np.array_equal(host(vK), a["vK"]) and np.array_equal(host(vM), a["vM"])
+    vK.fill_(0)
+    a["csr"].assemble_pages(prec_of(dtype), _unaligned(K), None, vK, None)
+    assert np.array_equal(host(vK), a["vK"])
+    a["csr"].close()
+    # P1 pages (4 x 4: one 16-byte vector per FP32 column when aligned)
+    tc, te = dev(coords), dev(elems)
+    csr = lib.Csr().symbolic(3, coords.shape[0], te)
+    _, nnz1, _, _ = csr.info()
+    ne = elems.shape[0]
+    K1 = torch.empty(ne * 16, dtype=dtype, device="cuda")
+    M1 = torch.empty(ne * 16, dtype=dtype, device="cuda")
+    lib.elem_stiffness_mass(prec_of(dtype), tc, te, K3D=K1, M3D=M1)
+    out = [torch.empty(nnz1, dtype=dtype, device="cuda") for _ in range(4)]
+    csr.assemble_pages(prec_of(dtype), K1, M1, out[0], out[1])
+    csr.assemble_pages(prec_of(dtype), _unaligned(K1), _unaligned(M1), out[2], out[3])
+    assert np.array_equal(host(out[0]), host(out[2])) and np.array_equal(host(out[1]), host(out[3]))
+    csr.close()
