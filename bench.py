@@ -751,7 +751,7 @@ def run_serve(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: pagefem runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the assembly would shard by rows: each GPU owns a node range and the elements around it)", file=sys.stderr)
         sys.exit(2)
 
