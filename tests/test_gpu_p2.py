@@ -331,3 +331,31 @@ def test_pages_assembly_unaligned_pages(lib, dtype):
     csr.assemble_pages(prec_of(dtype), _unaligned(K1), _unaligned(M1), out[2], out[3])
     assert np.array_equal(host(out[0]), host(out[2])) and np.array_equal(host(out[1]), host(out[3]))
     csr.close()
+
+
+def test_p2_routed_slivers(lib):
+    """FP32 pages of elements whose Jacobian fails the routing test (isolated slivers with det
+    down to 1e-6 h^3) are recomputed in FP64: every page matches the FP64 oracle within 1e-5
+    of each entry's scale, and the routed count is exactly the number of slivers."""
+    say("p2 routed slivers")
+    n, ns = 4, 96
+    h = 1.0 / n
+    coords, elems, _ = cube(n)
+    cs, es, _ = gen.append_slivers(coords, elems, ns, h)
+    c2, e2, _ = gen.p2_mesh(cs, es)
+    r = oracle.stroud_rule(3, 2)
+    ne, nb = e2.shape
+    K = torch.empty(ne * nb * nb, dtype=torch.float32, device="cuda")
+    M = torch.empty(ne * nb * nb, dtype=torch.float32, device="cuda")
+    ctr = counters()
+    lib.p2_elements(lib.F32, dev(c2), dev(e2), r, r, K3D=K, M3D=M, fb=lib.fallback(1e-3 * h ** 3, 1e6, True),
+                    counters=ctr)
+    ctr = host(ctr)
+    assert ctr[0] == ns and ctr[2] == 0, ctr
+    ref = oracle.p2_elements(c2, e2, r, r)
+    within(host(K).reshape(ne, nb * nb), ref["K3D"], ref["Kabs"], TOL[torch.float32], "P2 K3D with slivers")
+    within(host(M).reshape(ne, nb * nb), ref["M3D"], ref["Mabs"], TOL[torch.float32], "P2 M3D with slivers")
+    # K alone takes the same path
+    K2 = torch.empty_like(K)
+    lib.p2_elements(lib.F32, dev(c2), dev(e2), r, None, K3D=K2, fb=lib.fallback(1e-3 * h ** 3, 1e6, True))
+    assert np.array_equal(host(K2), host(K))
