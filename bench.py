@@ -55,6 +55,8 @@ P2_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "p2_cube64_traffic.json")
 P2_SOURCES = ["p2.hip", "sparse.hip", "assembly.hip", "p1elem.hpp", "smallmat.hpp", "common.hpp", "exact.hpp",
               "internal.hpp"]
 BATCH_SOURCES = ["batch.hip", "smallmat.hpp", "common.hpp"]
+PAGES_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "page_ops_1e7_traffic.json")
+PAGES_SOURCES = ["page_ops.hip", "smallmat.hpp", "common.hpp"]
 
 
 def kernel_hash(files=KERNEL_SOURCES) -> str:
@@ -199,7 +201,9 @@ def run_pages(args):
                    "pages": count},
         "roofline": {"kernel": "k_page_inv<float,3,true> (pf_page_inv)", "bound": "hbm",
                      "achieved": head["gbps"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": head["frac"],
-                     "traffic": None, "algorithmic_bytes_per_launch": head["bytes_per_page"] * count},
+                     "traffic": traffic_of(PAGES_TRAFFIC_FILE, PAGES_SOURCES, kernel="k_page_inv<float,3,true>",
+                                           pages=count),
+                     "algorithmic_bytes_per_launch": head["bytes_per_page"] * count},
         "ops": rows,
     }
     if not args.no_cpu_baseline:
