@@ -1172,8 +1172,22 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
         if (threadIdx.x < nr) {
             const int r = threadIdx.x;
             int nb = 0;
-            for (int u = 0; u < nlist[r]; ++u) {
-                const int c = key[r * FSUB + list[r * FSUB + u]] >> FCNT;
+            const int nl = nlist[r];
+            const int16_t* lr = list + r * FSUB;
+            const int32_t* kr = key + r * FSUB;
+            int u = 0;
+            for (; u + 4 <= nl; u += 4) {  // four independent slot and key reads in flight
+                int c[4];
+#pragma unroll
+                for (int z = 0; z < 4; ++z) c[z] = kr[lr[u + z]] >> FCNT;
+#pragma unroll
+                for (int z = 0; z < 4; ++z) {
+                    nb += c[z] == 1;
+                    bad = bad || c[z] > 2;
+                }
+            }
+            for (; u < nl; ++u) {
+                const int c = kr[lr[u]] >> FCNT;
                 nb += c == 1;
                 bad = bad || c > 2;
             }
@@ -1200,9 +1214,23 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
             const int32_t kk = key[r * FSUB + h] & FKEY;
             const int c = key[r * FSUB + h] >> FCNT;
             int rank = 0, brank = 0;
-            for (int v = 0; v < nlist[r]; ++v) {
-                const int h2 = list[r * FSUB + v];
-                const int32_t w2 = key[r * FSUB + h2];
+            const int nl = nlist[r];
+            const int16_t* lr = list + r * FSUB;
+            const int32_t* kr = key + r * FSUB;
+            int v = 0;
+            for (; v + 4 <= nl; v += 4) {  // four independent slot and key reads in flight
+                int32_t w2[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) w2[u] = kr[lr[v + u]];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool before = (w2[u] & FKEY) < kk;
+                    rank += before;
+                    brank += before && (w2[u] >> FCNT) == 1;
+                }
+            }
+            for (; v < nl; ++v) {
+                const int32_t w2 = kr[lr[v]];
                 const bool before = (w2 & FKEY) < kk;
                 rank += before;
                 brank += before && (w2 >> FCNT) == 1;
