@@ -823,13 +823,14 @@ __device__ int64_t lb_exclusive(const uint64_t* look, int64_t t, bool& timeout) 
     }
 }
 
-// Thread i of a tile holds rows 8i .. 8i+7, i.e. exactly one row-pattern block, whose
-// columns lie contiguous in colblk.  Besides the offsets, the tile measures the largest
+// Thread i of a tile holds rows 8i .. 8i+7, one 8-row group (a P1 row-pattern block, or half
+// of a P2 one), whose columns lie contiguous at the start of the group's region of colblk
+// (called a row-pattern block below).  Besides the offsets, the tile measures the largest
 // CSR window of the numeric block classes (NR_BIG rows, NR_MID rows as sums over 4 and 2
 // neighbouring lanes, NR_SMALL = 4 rows per half thread) and the largest number of elements
 // around a node, and stores them as tstat[4t .. 4t+3] (no atomics on shared words: those
 // serialise across the whole device); k_row_stats reduces them.
-static_assert(SCAN_ITEMS == RR && SCAN_ITEMS == 8, "a scan thread owns one row-pattern block of 8 rows");
+static_assert(SCAN_ITEMS == RR && SCAN_ITEMS == 8, "a scan thread owns one 8-row group");
 
 // RW: words of a row-pattern block's region in colblk; NRD: rounds of 64 words read at once
 template <int RW, int NRD>
