@@ -830,7 +830,7 @@ __device__ int64_t lb_exclusive(const uint64_t* look, int64_t t, bool& timeout) 
 // neighbouring lanes, NR_SMALL = 4 rows per half thread) and the largest number of elements
 // around a node, and stores them as tstat[4t .. 4t+3] (no atomics on shared words: those
 // serialise across the whole device); k_row_stats reduces them.
-static_assert(SCAN_ITEMS == RR && SCAN_ITEMS == 8, "a scan thread owns one 8-row group");
+static_assert(SCAN_ITEMS == RR && SCAN_ITEMS == 8, "a scan thread owns one row-pattern block of 8 rows");
 
 // RW: words of a row-pattern block's region in colblk; NRD: rounds of 64 words read at once
 template <int RW, int NRD>
