@@ -642,7 +642,7 @@ def run_p2(args):
     }
     if not args.no_cpu_baseline:
         import oracle
-        cn = 32
+        cn = 48  # about 10 s of oracle work
         cc, ce, _ = gen.cube_mesh(cn, jitter=0.15, with_faces=False)
         cc2, ce2, _ = gen.p2_mesh(cc, ce)
         cqq = np.exp(oracle.simplex_points(cc, ce, rule[0]).sum(axis=-1))
