@@ -397,13 +397,16 @@ def run_energy(args):
         f2, ck2, cm2 = np.sin(3.0 * s2) + 0.5 * xq2[..., 0], np.exp(s2), 1.0 + xq2[..., 2] ** 2
         u2 = np.cos(2.0 * c2[:, 0]) + c2[:, 1] ** 2 - 0.3 * c2[:, 2]
         t1 = time.perf_counter()
-        r = oracle.rhs_p1(c2, e2, 2, f2)
-        oracle.local_energies(c2, e2, 2, u2, cKq=ck2, cMq=cm2, b2D=r["b2D"])
+        passes = 0
+        while passes == 0 or time.perf_counter() - t1 < 10.0:  # whole passes, >= 10 s in total
+            r = oracle.rhs_p1(c2, e2, 2, f2)
+            oracle.local_energies(c2, e2, 2, u2, cKq=ck2, cMq=cm2, b2D=r["b2D"])
+            passes += 1
         dt = time.perf_counter() - t1
-        out["cpu_baseline"] = {"value": e2.shape[0] / dt, "unit": "tets/s", "cores": 1, "kind": "oracle",
+        out["cpu_baseline"] = {"value": passes * e2.shape[0] / dt, "unit": "tets/s", "cores": 1, "kind": "oracle",
                                "sample": "FP64 oracle load vector (local vectors + accumarray) and local energies "
                                          "(element matrices + page bilinear forms), single thread, %d^3 Kuhn mesh, "
-                                         "%d tets, %.1f s" % (cn, e2.shape[0], dt)}
+                                         "%d tets, %d pass(es), %.1f s" % (cn, e2.shape[0], passes, dt)}
     csr.close()
     print(json.dumps(out))
 
@@ -533,13 +536,17 @@ def run_faces(args):
         cn = args.cpu_n
         c2, e2, _ = gen.cube_mesh(cn, jitter=0.15, with_faces=False)
         t1 = time.perf_counter()
-        F2, FE2 = oracle.faces(c2, e2)
-        oracle.boundary(c2, F2)
+        passes = 0
+        while passes == 0 or time.perf_counter() - t1 < 10.0:  # whole passes, >= 10 s in total
+            F2, FE2 = oracle.faces(c2, e2)
+            oracle.boundary(c2, F2)
+            del F2, FE2
+            passes += 1
         dt = time.perf_counter() - t1
-        out["cpu_baseline"] = {"value": e2.shape[0] / dt, "unit": "tets/s", "cores": 1, "kind": "oracle",
+        out["cpu_baseline"] = {"value": passes * e2.shape[0] / dt, "unit": "tets/s", "cores": 1, "kind": "oracle",
                                "sample": "FP64 oracle: all faces by sorting the element faces, then the normals and "
-                                         "areas of all faces, single thread, %d^3 Kuhn mesh, %d tets, %.1f s"
-                                         % (cn, e2.shape[0], dt)}
+                                         "areas of all faces, single thread, %d^3 Kuhn mesh, %d tets, %d pass(es), "
+                                         "%.1f s" % (cn, e2.shape[0], passes, dt)}
     csr.close()
     print(json.dumps(out))
 
