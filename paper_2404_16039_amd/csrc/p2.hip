@@ -179,6 +179,11 @@ __global__ __launch_bounds__(P2BS) void k_p2_elem(int64_t nn, const double* __re
     constexpr int PS = NB * (NB + 1) / 2;  // staging stride of one page (its lower triangle)
     static_assert(PS % 2 == 1, "an odd stride spreads the lanes over the banks");
     __shared__ T stage[P2BS * PS];
+    __shared__ uint8_t trimap[NB * NB];  // column-major page word -> its triangle position
+    for (int w = threadIdx.x; w < NB * NB; w += P2BS) {
+        const int a = w % NB, b = w / NB;
+        trimap[w] = static_cast<uint8_t>(a >= b ? tri(a, b) : tri(b, a));
+    }
     const int64_t e0 = static_cast<int64_t>(blockIdx.x) * P2BS;
     const int64_t e = e0 + threadIdx.x;
     const int nel = static_cast<int>(ne - e0 < P2BS ? ne - e0 : P2BS);
@@ -225,9 +230,28 @@ __global__ __launch_bounds__(P2BS) void k_p2_elem(int64_t nn, const double* __re
         }
         __syncthreads();
         T* dst = out + e0 * (NB * NB);
-        for (int k = threadIdx.x; k < nel * NB * NB; k += P2BS) {
-            const int w = k % (NB * NB), a = w % NB, b = w / NB;  // column-major (a, b)
-            dst[k] = stage[(k / (NB * NB)) * PS + (a >= b ? tri(a, b) : tri(b, a))];
+        static_assert((NB * NB) % 4 == 0, "a page is a whole number of 4-word groups");
+        bool vec = false;
+        if constexpr (sizeof(T) == 4) {
+            vec = (reinterpret_cast<uintptr_t>(dst) & 15) == 0;
+            if (vec) {  // 16-byte stores: four consecutive words per lane
+                for (int k = 4 * threadIdx.x; k < nel * NB * NB; k += 4 * P2BS) {
+                    const int el = k / (NB * NB), w = k - el * (NB * NB);
+                    const T* sp = stage + el * PS;
+                    float4 v;
+                    v.x = sp[trimap[w]];
+                    v.y = sp[trimap[w + 1]];
+                    v.z = sp[trimap[w + 2]];
+                    v.w = sp[trimap[w + 3]];
+                    *reinterpret_cast<float4*>(dst + k) = v;
+                }
+            }
+        }
+        if (!vec) {
+            for (int k = threadIdx.x; k < nel * NB * NB; k += P2BS) {
+                const int el = k / (NB * NB);
+                dst[k] = stage[el * PS + trimap[k - el * (NB * NB)]];
+            }
         }
         __syncthreads();
     }
