@@ -62,6 +62,7 @@ struct pf_csr {
     // per-stage timing of pf_csr_symbolic (events e0..e3: start, after the adjacency, after
     // the pattern, after the row offsets)
     bool timing = false, pending = false;
+    int64_t* hinfo = nullptr;  // pinned host words for the status readbacks (allocated once)
     hipEvent_t ev[PF_CSR_STAGES + 1] = {};
     double stage_ms[PF_CSR_STAGES] = {};
     int64_t stage_calls = 0;
@@ -1837,6 +1838,7 @@ void pf_csr_destroy(pf_csr* c) {
         (void)hipFree(q);
     (void)hipFree(c->esign);
     (void)hipFree(c->finfo);
+    if (c->hinfo) (void)hipHostFree(c->hinfo);
     delete c;
 }
 
@@ -1966,8 +1968,9 @@ pf_status symbolic(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const in
     if ((st = mark(c, 3, s))) return st;
     if ((st = launch_check(who))) return st;
     c->pending = c->timing;
-    int64_t info[8];
-    PF_HIP_TRY(hipMemcpyAsync(info, c->info, sizeof(info), hipMemcpyDeviceToHost, s));
+    if (!c->hinfo) PF_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hinfo), 8 * sizeof(int64_t)));
+    int64_t* info = c->hinfo;  // pinned: a direct copy, no staging through pageable memory
+    PF_HIP_TRY(hipMemcpyAsync(info, c->info, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     PF_HIP_TRY(hipStreamSynchronize(s));
     if (info[0] & ERR_INDEX) return fail(PF_EINDEX, std::string(who) + ": node index out of range in elems");
     if (info[0] & ERR_ROW)
@@ -2066,8 +2069,9 @@ pf_status pf_csr_faces(pf_csr* c, const double* coords, const int32_t* elems, vo
     }
     if ((st = scan(c->fcount, nn, c->fptr, c->bsum, c->finfo + 1, s))) return st;
     if ((st = scan(c->bcount, nn, c->bptr, c->bsum, c->finfo + 2, s))) return st;
-    int64_t info[4];
-    PF_HIP_TRY(hipMemcpyAsync(info, c->finfo, sizeof(info), hipMemcpyDeviceToHost, s));
+    if (!c->hinfo) PF_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hinfo), 8 * sizeof(int64_t)));
+    int64_t* info = c->hinfo;
+    PF_HIP_TRY(hipMemcpyAsync(info, c->finfo, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     PF_HIP_TRY(hipStreamSynchronize(s));
     if (info[0] & ERR_FACE)
         return fail(PF_EINVAL, "pf_csr_faces: a face belongs to more than two elements (not a conforming mesh)");
