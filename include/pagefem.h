@@ -11,6 +11,8 @@
  *                svamt, aminv, amt, amdet, avtamav
  *   section 3.1  the coords3D / vectors3D structures
  *   section 3.2  volumes and normals
+ *   section 3.3  volume integrals (integration points of a rule on every cell)
+ *   section 3.4  the GI function
  *   section 3.5  surface integrals (boundary faces, their normals and areas)
  *   section 3.6  derivative routine, P1 stiffness and mass matrices, sparse() assembly
  *
@@ -231,6 +233,13 @@ pf_status pf_csr_assemble_pages(const pf_csr* csr, pf_dtype prec, const void* pa
 pf_status pf_csr_info(const pf_csr* csr, int64_t* nn, int64_t* nnz, const int32_t** row_ptr,
                       const int32_t** col_idx);
 
+/* Launch shape of pf_assemble and pf_assemble_quad on a built P1 structure in precision
+ * prec (a diagnostic, e.g. for tests that must reach every variant of the numeric kernel):
+ * rows per workgroup of the numeric launch and the largest number of elements around one
+ * node (both nullable).  PF_ESTATE for a P2 or unbuilt structure. */
+pf_status pf_csr_numeric_info(const pf_csr* csr, pf_dtype prec, int32_t* rows_per_block,
+                              int32_t* max_adj);
+
 /* Per-stage device time of pf_csr_symbolic, a profiling aid.  pf_csr_set_timing(csr, 1)
  * clears the sums and makes every later pf_csr_symbolic call on the handle record HIP
  * events on its stream between its stages (0 stops recording).  pf_csr_stage_times waits
@@ -304,7 +313,8 @@ pf_status pf_p2_elements(int dim, pf_dtype prec, int64_t nn, const double* coord
                          int64_t* d_counters, void* stream);
 
 /* ----------------------------------------------------------------------------------
- * Integration over cells (sections 3.5, 3.6): points of a rule and the GI function.
+ * Integration over cells (sections 3.3-3.5): points of a rule (X_ip = amsm(coords3D, ip)) and the
+ * GI function (section 3.4).
  * A rule is nq barycentric points lam (host, nq x nv, row-major) with weights w (host, nq)
  * summing to 1; at most PF_RULE_MAX points.
  * ---------------------------------------------------------------------------------- */
@@ -318,7 +328,7 @@ pf_status pf_p2_elements(int dim, pf_dtype prec, int64_t nn, const double* coord
 pf_status pf_simplex_points(int dim, int nv, int64_t nn, const double* coords, int64_t nc,
                             const int32_t* cells, int nq, const double* lam, double* X, void* stream);
 
-/* The GI function (section 3.5): value = sum_c sizes[c] f_c with
+/* The GI function (section 3.4): value = sum_c sizes[c] f_c with
  * f_c = sum_i normals[c*d + i] sum_q w_q fip[(c*nq + q)*d + i] (normals nullable: the plain
  * sum over the d components, d = 1 for a scalar), i.e. the integral of a scalar function or
  * the flux of a vector field through oriented cells.  fip, sizes, normals: device, type prec;

@@ -777,7 +777,7 @@ int64_t or_faces(int dim, int64_t nn, const double* coords, int64_t ne, const in
     return nf;
 }
 
-/* Points of an integration rule on every cell (section 3.5/3.6, X_ip = amsm(coords3D, ip)):
+/* Points of an integration rule on every cell (sections 3.3 and 3.5, X_ip = amsm(coords3D, ip)):
  * X[(c*nq + q)*dim + i] = sum_j lam[q*nv + j] * coords[cells[c*nv + j]*dim + i]. */
 int or_simplex_points(int dim, int nv, int64_t nn, const double* coords, int64_t nc, const int32_t* cells, int nq,
                       const double* lam, double* X) {
@@ -795,7 +795,7 @@ int or_simplex_points(int dim, int nv, int64_t nn, const double* coords, int64_t
     return 0;
 }
 
-/* The GI function (section 3.5): value = sum_c sizes[c] * f_c with f_c = sum_q w_q fip[c, q]
+/* The GI function (section 3.4): value = sum_c sizes[c] * f_c with f_c = sum_q w_q fip[c, q]
  * for a scalar (d = 1), or f_c = sum_i n_ci sum_q w_q fip[c, q, i] for a vector field with
  * normals n (nc x d).  fip: nc x nq x d, component fastest.  Plain sum in cell order. */
 double or_gi(int64_t nc, int nq, int d, const double* fip, const double* w, const double* sizes,

@@ -1396,6 +1396,8 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
     int32_t* alen = rp + (NR + 1);                               // [NR + 1] elements around each row node
     int32_t* dslot = alen + (NR + 1);                            // [NR + 1]
     int32_t* maxlen = dslot + (NR + 1);                          // [1]
+    static_assert(lds_carve_aligned<Vec4<T>, A, A, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t>(),
+                  "numeric LDS carve-out: every array naturally aligned");
 
     // Items are dealt by NR (row r = item % NR, a power of two); rows past the end of the
     // matrix in the last block are empty (no elements, no slots).
@@ -2119,6 +2121,15 @@ pf_status pf_csr_info(const pf_csr* c, int64_t* nn, int64_t* nnz, const int32_t*
     if (nnz) *nnz = c->nnz;
     if (row_ptr) *row_ptr = c->row_ptr;
     if (col_idx) *col_idx = c->col_idx;
+    return PF_OK;
+}
+
+pf_status pf_csr_numeric_info(const pf_csr* c, pf_dtype prec, int32_t* rows_per_block, int32_t* max_adj) {
+    if (!c) return fail(PF_EINVAL, "pf_csr_numeric_info: null handle");
+    if (!c->built || c->p2) return fail(PF_ESTATE, "pf_csr_numeric_info: no P1 structure built");
+    if (prec != PF_F32 && prec != PF_F64) return fail(PF_EDTYPE, "pf_csr_numeric_info: prec must be PF_F32 or PF_F64");
+    if (rows_per_block) *rows_per_block = numeric_class(c, prec);
+    if (max_adj) *max_adj = c->max_adj;
     return PF_OK;
 }
 

@@ -531,6 +531,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_plan(const uint8_t* __restrict__
     constexpr int BS = WAVES * 64;
     extern __shared__ __align__(16) unsigned char plan_lds[];
     T* lds = reinterpret_cast<T*>(plan_lds);
+    static_assert(lds_carve_aligned<T>(), "plan LDS: one naturally aligned array");
     const PlanHeader* hdr = reinterpret_cast<const PlanHeader*>(wl);
     const PlanGroup* grp = reinterpret_cast<const PlanGroup*>(wl + PLAN_GROUPS_OFFSET);
     const Fallback fb = hdr->fb;

@@ -37,6 +37,26 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ------------------------------------------------------------------------------------
+// dynamic LDS carved into consecutive arrays
+// ------------------------------------------------------------------------------------
+// A kernel that carves its dynamic LDS (16-byte aligned base) into arrays of types
+// T0, T1, ... with run-time counts starts array k at sum_{j<k} n_j sizeof(Tj).  That offset
+// is a multiple of alignof(Tk) for every count when each earlier element size is: the
+// condition checked here, at compile time, for every carve-out (a 64-bit LDS atomic on a
+// misaligned address faults the wave).
+template <typename... Ts>
+constexpr bool lds_carve_aligned() {
+    constexpr size_t sz[] = {sizeof(Ts)...};
+    constexpr size_t al[] = {alignof(Ts)...};
+    for (size_t k = 0; k < sizeof...(Ts); ++k) {
+        if (al[k] > 16) return false;
+        for (size_t j = 0; j < k; ++j)
+            if (sz[j] % al[k] != 0) return false;
+    }
+    return true;
+}
+
+// ------------------------------------------------------------------------------------
 // device: error-free transformations and compensated small determinants
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }

@@ -1,5 +1,5 @@
 // integrals.hip -- integration points of a rule on every cell and the GI function
-// (sections 3.5 and 3.6: X_ip = amsm(coords3D, ip) and GI(fip, w, sizes, normals)).
+// (section 3.3 and 3.5: X_ip = amsm(coords3D, ip); section 3.4: GI(fip, w, sizes, normals)).
 //
 // A rule is given by the caller as barycentric points (nq x nv) and weights summing to 1,
 // so any order the caller needs (the paper's Gauss_points for a chosen gqo) runs through

@@ -110,6 +110,7 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_
     A* accM = accK + W;
     int32_t* shK = reinterpret_cast<int32_t*>(accM + W);
     int32_t* shM = shK + W;
+    static_assert(lds_carve_aligned<A, A, int32_t, int32_t>(), "page assembly LDS carve-out: every array naturally aligned");
     for (int w = threadIdx.x; w < W; w += PBT) {
         accK[w] = A(0);
         accM[w] = A(0);

@@ -42,6 +42,7 @@ STREAM_SLIVER = 6
 STREAM_MIXED = 7
 STREAM_SERVE = 8
 STREAM_PERM = 9
+STREAM_FAN = 10
 
 
 def rng(stream: int, sub: int | None = None) -> np.random.Generator:
@@ -282,6 +283,40 @@ def append_slivers(coords: np.ndarray, elems: np.ndarray, count: int, h: float,
     new_elems = np.concatenate(
         [elems, (nn0 + np.arange(4 * count, dtype=np.int64)).reshape(count, 4).astype(np.int32)], axis=0)
     return new_coords, new_elems, t
+
+
+def fan_mesh(dim: int, k: int, seed_sub: int = 0, stream: int = STREAM_FAN):
+    """A closed fan of k simplices around one hub, i.e. a node in k elements (high valence).
+
+    2-D: hub at the origin, k rim nodes on a jittered circle, triangles (hub, r_i, r_i+1).
+    3-D: an axis edge (a, b) at z = -1 and z = +1 with k rim nodes on a jittered circle in the
+    plane z = 0, tetrahedra (a, b, r_i, r_i+1): both axis nodes lie in k elements and their
+    rows hold k + 2 nonzeros.  Rim angles are jittered by up to a quarter of the spacing and
+    radii by up to 20%, from the seeded stream.  Returns (coords, elems).
+    """
+    g = rng(stream, seed_sub)
+    ang = 2.0 * math.pi * (np.arange(k) + g.uniform(-0.25, 0.25, k)) / k
+    rad = 1.0 + g.uniform(-0.2, 0.2, k)
+    rim = np.stack([rad * np.cos(ang), rad * np.sin(ang)], axis=1)
+    nxt = (np.arange(k) + 1) % k
+    if dim == 2:
+        coords = np.concatenate([[[0.0, 0.0]], rim])
+        elems = np.stack([np.zeros(k, np.int64), 1 + np.arange(k), 1 + nxt], axis=1)
+    else:
+        axis = np.array([[0.0, 0.0, -1.0], [0.0, 0.0, 1.0]]) + g.uniform(-0.1, 0.1, (2, 3)) * [1, 1, 0]
+        coords = np.concatenate([axis, np.concatenate([rim, np.zeros((k, 1))], axis=1)])
+        elems = np.stack([np.zeros(k, np.int64), np.ones(k, np.int64), 2 + np.arange(k), 2 + nxt], axis=1)
+    return coords.astype(np.float64), elems.astype(np.int32)
+
+
+def join_meshes(*meshes):
+    """Disjoint union of (coords, elems) meshes: node ids of each later mesh shifted."""
+    cs, es, off = [], [], 0
+    for c, e in meshes:
+        cs.append(np.asarray(c, np.float64))
+        es.append(np.asarray(e, np.int64) + off)
+        off += c.shape[0]
+    return np.concatenate(cs), np.concatenate(es).astype(np.int32)
 
 
 def permute_nodes(coords: np.ndarray, elems: np.ndarray, faces=None, stream: int = STREAM_PERM):

@@ -146,6 +146,7 @@ _sig = {
     "pf_csr_symbolic_p2": ([P, I32, I64, I64, P, P], C.c_int),
     "pf_csr_assemble_pages": ([P, I32, P, P, P, P, P], C.c_int),
     "pf_csr_info": ([P, C.POINTER(I64), C.POINTER(I64), C.POINTER(P), C.POINTER(P)], C.c_int),
+    "pf_csr_numeric_info": ([P, I32, C.POINTER(I32), C.POINTER(I32)], C.c_int),
     "pf_csr_set_timing": ([P, C.c_int], C.c_int),
     "pf_csr_stage_times": ([P, C.POINTER(C.c_double), C.POINTER(I64)], C.c_int),
     "pf_assemble": ([P, I32, P, P, P, P, P, P, FP, P, P], C.c_int),
@@ -342,6 +343,12 @@ class Csr:
         nn, nnz, rp, ci = I64(), I64(), P(), P()
         _chk(_lib.pf_csr_info(self._h, C.byref(nn), C.byref(nnz), C.byref(rp), C.byref(ci)), "pf_csr_info")
         return nn.value, nnz.value, rp.value, ci.value
+
+    def numeric_info(self, prec):
+        """(rows per workgroup of the numeric launch, largest number of elements around a node)"""
+        rows, madj = I32(), I32()
+        _chk(_lib.pf_csr_numeric_info(self._h, prec, C.byref(rows), C.byref(madj)), "pf_csr_numeric_info")
+        return rows.value, madj.value
 
     CSR_STAGES = ("adjacency", "pattern", "row offsets")
 

@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import oracle
-from helpers import TOL, counters, cube, dev, host, prec_of, say, square, within
+from helpers import TOL, counters, cube, dev, host, kuhn_pattern, prec_of, say, square, within
 from paper_2404_16039_amd import gen
 
 pytestmark = pytest.mark.gpu
@@ -66,8 +66,11 @@ def test_cfg1_square_32(lib, dtype):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("n", [1, 2, 7])
+@pytest.mark.parametrize("n", [1, 2, 7, 16, 24])
 def test_cube_small_full(lib, dtype, n):
+    """Every entry against the oracle's sparse(); 16^3 and 24^3 cubes (4,913 and 15,625
+    nodes) span several tiles of the row-offset scan, so the look-back path is compared bit for
+    bit too."""
     say("assemble cube", n, dtype)
     coords, elems, _ = cube(n)
     g = np.random.default_rng(n)
@@ -193,7 +196,8 @@ def _structure_properties(got, nn, expect_nnz):
 
 def test_cfg3_full_size_fp32(lib):
     """128^3 cubes x 6 tets (12,582,912 tets, 2,146,689 nodes), jitter 0.15 h, FP32 values,
-    FP64 fallback below 1e-3 h^3: structure properties everywhere, oracle rows sampled."""
+    FP64 fallback below 1e-3 h^3: the whole structure against the mesh's closed-form pattern,
+    oracle values on sampled rows, K 1 = 0 and 1^T M 1 = 1 over all rows."""
     n = 128
     h = 1.0 / n
     say("cfg3 full size")
@@ -202,6 +206,10 @@ def test_cfg3_full_size_fp32(lib):
     got = _assemble(lib, coords, elems, torch.float32, fb=fb)
     cnt = gen.kuhn_counts(n)
     row_of = _structure_properties(got, coords.shape[0], cnt["nnz"])
+    # every row, bit for bit, against the closed-form pattern of the Kuhn mesh
+    krp, kci = kuhn_pattern(n)
+    assert np.array_equal(got["row_ptr"], krp) and np.array_equal(got["col_idx"], kci)
+    del krp, kci
     assert got["ctr"][0] == 0 and got["ctr"][2] == 0  # no element is routed, no bad index
     g = np.random.default_rng(11)
     rows = np.unique(np.concatenate([g.choice(coords.shape[0], 600, replace=False), [0, coords.shape[0] - 1]]))

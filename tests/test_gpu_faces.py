@@ -1,6 +1,6 @@
 """Parity of the face lists (section 3.2, normals of all faces or of boundary faces) against
 the oracle's sorted face keys, the 128^3 counts of the section 3.2 normals table, and the
-GI function (section 3.5) with integration points: the divergence theorem by a volume and
+GI function (section 3.4) with integration points: the divergence theorem by a volume and
 a surface integral, against the oracle's GI."""
 import os
 

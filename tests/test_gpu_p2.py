@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import oracle
-from helpers import TOL, counters, cube, dev, host, prec_of, say, square, within
+from helpers import TOL, counters, cube, dev, host, pair_pattern, prec_of, say, square, within
 from paper_2404_16039_amd import gen
 
 pytestmark = pytest.mark.gpu
@@ -142,11 +142,12 @@ def _gpu_p2_global(L, coords2, elems2, dtype, ruleK, ruleM, cK=None, cM=None, cs
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("mesh", ["cube3", "square7", "cube3_perm"])
+@pytest.mark.parametrize("mesh", ["cube3", "square7", "cube3_perm", "cube8", "square24"])
 def test_p2_global_assembly(lib, dtype, mesh):
     """The global P2 K and M (section 3.6: sparse() of the P2 pages): the structure equals the
     oracle's sparse() pattern bit for bit, the values equal the oracle's sums of the same
-    pages, and of the oracle's own pages, within the tolerance."""
+    pages, and of the oracle's own pages, within the tolerance.  cube8 (4,913 P2 nodes) and
+    square24 (2,401) span several tiles of the row-offset scan."""
     say("p2 global", mesh, dtype)
     base = mesh.split("_")[0]
     coords, elems, _ = cube(int(base[4:])) if base.startswith("cube") else square(int(base[6:]))
@@ -196,7 +197,8 @@ def test_p2_global_permutation_bitwise(lib):
 
 def test_p2_global_full_size_properties(lib):
     """The 64^3 P2 mesh of the section 3.6 benchmark (2,146,689 nodes), FP32 with c = exp(x1+x2+x3)
-    at 27 points: interior vertex rows hold 65 entries, K rows sum to 0, the entries of M sum to 1,
+    at 27 points: the structure equals every node pair of the elements (all rows), interior
+    vertex rows hold 65 entries, K rows sum to 0, the entries of M sum to 1,
     v^T K v and v^T M v of a quadratic v equal its exact energies with c = 1, and sampled rows
     equal the FP64 sums of their pages."""
     say("p2 global 64^3")
@@ -207,6 +209,10 @@ def test_p2_global_full_size_properties(lib):
     got = _gpu_p2_global(lib, c2, e2, torch.float32, r, r)
     rp, ci, vK, vM = got["rp"], got["ci"], got["vK"].astype(np.float64), got["vM"].astype(np.float64)
     assert c2.shape[0] == 2146689 and np.diff(rp).max() == 65
+    # the whole structure, bit for bit, against the sorted node pairs of the elements
+    prp, pci = pair_pattern(e2, c2.shape[0], chunk=1 << 19)
+    assert np.array_equal(rp.astype(np.int64), prp) and np.array_equal(ci, pci)
+    del prp, pci
     rows = np.repeat(np.arange(c2.shape[0]), np.diff(rp))
     rs = np.bincount(rows, weights=vK, minlength=c2.shape[0])
     ra = np.bincount(rows, weights=np.abs(vK), minlength=c2.shape[0])

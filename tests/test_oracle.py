@@ -809,7 +809,7 @@ def test_faces_2d_edges():
 
 
 def test_gi_divergence_theorem_exact_rules():
-    """GI (section 3.5): for F = (x1^3 (x2^2 + x3^2)/3, x2^5/5, x2^2 x3^3/3), div F =
+    """GI (section 3.4): for F = (x1^3 (x2^2 + x3^2)/3, x2^5/5, x2^2 x3^3/3), div F =
     (x1^2 + x2^2)(x2^2 + x3^2); with rules exact for the degrees (4 in the volume, 5 on
     the faces) the volume integral of div F over the jittered unit-cube mesh and the flux
     of F through its boundary both equal the closed form 8/15; the mass of rho = x1^2 + x2^2
@@ -1033,3 +1033,22 @@ def test_p2_energies_fourth_order():
             assert 13.0 < errs[a][k] / errs[b][k] < 19.0, errs
     for n, (pk, pm) in printed.items():
         assert pk / 3 < errs[n][0] < 3 * pk and abs(errs[n][1] / pm - 1) < 0.1, (n, errs[n])
+
+
+def test_pattern_generators_match_oracle_sparse():
+    """The test-side pattern generators (closed-form Kuhn stencil; sorted element node pairs)
+    equal the structure of the oracle's sparse() on small meshes, P1 and P2."""
+    import sys
+    sys.path.insert(0, os.path.dirname(__file__))
+    from helpers import kuhn_pattern, pair_pattern
+    for n in (1, 2, 3, 4):
+        coords, elems, _ = gen.cube_mesh(n)
+        el = oracle.p1_elements(coords, elems)
+        ref = oracle.assemble(elems, coords.shape[0], el["Ke"], el["Me"], el["Kabs"])
+        for rp, ci in (kuhn_pattern(n), pair_pattern(elems, coords.shape[0], chunk=7)):
+            assert np.array_equal(rp, ref["row_ptr"]) and np.array_equal(ci, ref["col_idx"])
+    coords, elems, _ = gen.cube_mesh(2)
+    c2, e2, _ = gen.p2_mesh(coords, elems)
+    ref = oracle.assemble(e2, c2.shape[0], np.ones((e2.shape[0], 100)))
+    rp, ci = pair_pattern(e2, c2.shape[0], chunk=5)
+    assert np.array_equal(rp, ref["row_ptr"]) and np.array_equal(ci, ref["col_idx"])
