@@ -368,6 +368,21 @@ pf_status pf_energies(pf_csr* csr, pf_dtype prec, const double* coords, const in
                       void* J, double* totals, const pf_fallback* fb, int64_t* d_counters,
                       void* stream);
 
+/* pf_energies for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops and harnesses that forbid hipMalloc): the same arguments, kernels and results
+ * (J and totals bit for bit those of pf_energies), but the FP64 block sums live in a static
+ * per-device array of the library (3 x 2048 doubles, 48 KiB, held on every device the call runs
+ * on until the process ends) instead of a workspace of the handle, so the handle is const and
+ * the call makes no hipMalloc, hipFree or other allocating call.  The array's address on the
+ * current device is looked up once, at the first call on that device.  The block count of the
+ * energy kernel is capped at 2048 for any mesh, so no mesh is too large; PF_EINVAL would report
+ * a need beyond the array.  All calls on one device share the array: calls that overlap on a
+ * device (two streams, or two threads) race on it and give undefined totals; serialise them. */
+pf_status pf_energies_noalloc(const pf_csr* csr, pf_dtype prec, const double* coords,
+                              const int32_t* elems, int order, const void* cKq, const void* cMq,
+                              const void* u, const void* b2D, void* J, double* totals,
+                              const pf_fallback* fb, int64_t* d_counters, void* stream);
+
 void pf_csr_destroy(pf_csr* csr);
 
 /* ----------------------------------------------------------------------------------

@@ -20,6 +20,7 @@
 #include "exact.hpp"
 #include "internal.hpp"
 
+#include <mutex>
 #include <string>
 
 namespace pf {
@@ -346,22 +347,19 @@ pf_status pf_rhs(const pf_csr* csr, pf_dtype prec, const double* coords, const i
     return PF_OK;
 }
 
-pf_status pf_energies(pf_csr* csr, pf_dtype prec, const double* coords, const int32_t* elems, int order,
-                      const void* cKq, const void* cMq, const void* u, const void* b2D, void* J, double* totals,
-                      const pf_fallback* fb, int64_t* d_counters, void* stream) {
-    pf_status st = check_csr_mesh(csr, coords, elems, "pf_energies");
-    if (st) return st;
+namespace pf {
+namespace {
+
+// Shared body of pf_energies and pf_energies_noalloc: `part` holds 3 FP64 block sums per
+// block of the energy kernel (every block writes its three, so nothing needs clearing).
+pf_status energies_into(const pf_csr* csr, pf_dtype prec, const double* coords, const int32_t* elems, int order,
+                        const void* cKq, const void* cMq, const void* u, const void* b2D, void* J, double* totals,
+                        const pf_fallback* fb, int64_t* d_counters, hipStream_t s, double* part, int grid) {
     const int dim = csr_dim(csr);
     const int qn = quad_count(dim, order);
-    if (!qn) return fail(PF_EINVAL, "pf_energies: order must be 1 or 2");
-    if (prec != PF_F32 && prec != PF_F64) return fail(PF_EDTYPE, "pf_energies: prec must be PF_F32 or PF_F64");
     const int64_t nn = csr_nn(csr), ne = csr_ne(csr);
-    if (ne > 0 && !u) return fail(PF_EINVAL, "pf_energies: null u");
-    hipStream_t s = as_stream(stream);
     const Fallback f = make_fallback(fb);
-    const int grid = static_cast<int>(std::max<int64_t>(std::min<int64_t>(ceil_div(ne, RBS), ETOT_BLOCKS), 1));
-    double* part = nullptr;
-    if ((st = csr_workspace(csr, 3 * static_cast<int64_t>(grid), &part))) return st;
+    pf_status st;
     if (dim == 3) {
         if (prec == PF_F32)
             launch_energies<3, float>(qn, grid, nn, coords, ne, elems, cKq, cMq, u, b2D, J, part, f, d_counters, s);
@@ -379,4 +377,75 @@ pf_status pf_energies(pf_csr* csr, pf_dtype prec, const double* coords, const in
         if ((st = launch_check("pf_energies totals"))) return st;
     }
     return PF_OK;
+}
+
+// argument checks of both entry points; on success *grid = the energy kernel's block count
+pf_status energies_check(const pf_csr* csr, pf_dtype prec, const double* coords, const int32_t* elems, int order,
+                         const void* u, const char* who, int* grid) {
+    pf_status st = check_csr_mesh(csr, coords, elems, who);
+    if (st) return st;
+    if (!quad_count(csr_dim(csr), order)) return fail(PF_EINVAL, std::string(who) + ": order must be 1 or 2");
+    if (prec != PF_F32 && prec != PF_F64)
+        return fail(PF_EDTYPE, std::string(who) + ": prec must be PF_F32 or PF_F64");
+    const int64_t ne = csr_ne(csr);
+    if (ne > 0 && !u) return fail(PF_EINVAL, std::string(who) + ": null u");
+    *grid = static_cast<int>(std::max<int64_t>(std::min<int64_t>(ceil_div(ne, RBS), ETOT_BLOCKS), 1));
+    return PF_OK;
+}
+
+// Block sums of pf_energies_noalloc: one copy of this array per device, held until the process
+// ends.  Host code never passes the array's name to a kernel (on the host it is a stand-in,
+// not a device address): it uses the address hipGetSymbolAddress returns for the current
+// device, kept in scratch_dev.
+constexpr int SCRATCH_WORDS = 3 * ETOT_BLOCKS;
+__device__ __align__(256) double scratch[SCRATCH_WORDS];
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex scratch_mu;
+double* scratch_dev[SCRATCH_DEVICES] = {};
+
+pf_status scratch_of_current_device(double** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(PF_EHIP, "pf_energies_noalloc: hipGetDevice failed");
+    if (dev < 0 || dev >= SCRATCH_DEVICES)
+        return fail(PF_EINVAL, "pf_energies_noalloc: device ordinal beyond the supported 64");
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PF_EHIP, std::string("pf_energies_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+        scratch_dev[dev] = static_cast<double*>(p);
+    }
+    *out = scratch_dev[dev];
+    return PF_OK;
+}
+
+}  // namespace
+}  // namespace pf
+
+pf_status pf_energies(pf_csr* csr, pf_dtype prec, const double* coords, const int32_t* elems, int order,
+                      const void* cKq, const void* cMq, const void* u, const void* b2D, void* J, double* totals,
+                      const pf_fallback* fb, int64_t* d_counters, void* stream) {
+    int grid = 0;
+    pf_status st = energies_check(csr, prec, coords, elems, order, u, "pf_energies", &grid);
+    if (st) return st;
+    double* part = nullptr;
+    if ((st = csr_workspace(csr, 3 * static_cast<int64_t>(grid), &part))) return st;
+    return energies_into(csr, prec, coords, elems, order, cKq, cMq, u, b2D, J, totals, fb, d_counters,
+                         as_stream(stream), part, grid);
+}
+
+pf_status pf_energies_noalloc(const pf_csr* csr, pf_dtype prec, const double* coords, const int32_t* elems,
+                              int order, const void* cKq, const void* cMq, const void* u, const void* b2D, void* J,
+                              double* totals, const pf_fallback* fb, int64_t* d_counters, void* stream) {
+    int grid = 0;
+    pf_status st = energies_check(csr, prec, coords, elems, order, u, "pf_energies_noalloc", &grid);
+    if (st) return st;
+    if (3 * grid > SCRATCH_WORDS)
+        return fail(PF_EINVAL, "pf_energies_noalloc: the energy kernel needs more block sums than the static "
+                               "scratch holds");
+    double* part = nullptr;
+    if ((st = scratch_of_current_device(&part))) return st;
+    return energies_into(csr, prec, coords, elems, order, cKq, cMq, u, b2D, J, totals, fb, d_counters,
+                         as_stream(stream), part, grid);
 }

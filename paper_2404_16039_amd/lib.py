@@ -141,6 +141,7 @@ _sig = {
     "pf_gi": ([I32, I64, I32, I32, P, P, P, P, P, P, P], C.c_int),
     "pf_rhs": ([P, I32, P, P, I32, P, P, P, FP, P, P], C.c_int),
     "pf_energies": ([P, I32, P, P, I32, P, P, P, P, P, P, FP, P, P], C.c_int),
+    "pf_energies_noalloc": ([P, I32, P, P, I32, P, P, P, P, P, P, FP, P, P], C.c_int),
     "pf_csr_create": ([C.POINTER(P)], C.c_int),
     "pf_csr_symbolic": ([P, I32, I64, I64, P, P], C.c_int),
     "pf_csr_symbolic_p2": ([P, I32, I64, I64, P, P], C.c_int),
@@ -414,6 +415,13 @@ class Csr:
         """Local energy parts into J (3 x ne) and/or their FP64 sums into totals (3 doubles)."""
         _chk(_lib.pf_energies(self._h, prec, _p(coords), _p(elems), int(order), _p(cKq), _p(cMq), _p(u), _p(b2D),
                               _p(J), _p(totals), _ref(fb, Fallback), _p(counters), _s(stream)), "pf_energies")
+
+    def energies_noalloc(self, prec, coords, elems, order, u, cKq=None, cMq=None, b2D=None, J=None, totals=None,
+                         fb=None, counters=None, stream=None):
+        """energies() with the block sums in the library's static per-device array (no allocation)."""
+        _chk(_lib.pf_energies_noalloc(self._h, prec, _p(coords), _p(elems), int(order), _p(cKq), _p(cMq), _p(u),
+                                      _p(b2D), _p(J), _p(totals), _ref(fb, Fallback), _p(counters), _s(stream)),
+             "pf_energies_noalloc")
 
     def close(self):
         if self._h:
