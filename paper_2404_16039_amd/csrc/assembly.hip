@@ -32,6 +32,8 @@ struct pf_csr {
     int wmax_big = 0;    // largest CSR window of a numeric block of NR_BIG rows
     int wmax_mid = 0;    // ... of NR_MID rows
     int wmax_small = 0;  // ... of NR_SMALL rows
+    int wmax8 = 0;       // ... of 8 rows
+    int wmax2 = 0;       // ... of 2 rows
     int max_adj = 0;     // largest number of elements around one node
     int32_t* adj_len = nullptr;  // elements around each node
     int32_t* adj = nullptr;   // node i's entries (element << 2 | local index) at i * MAXADJ ...
@@ -76,6 +78,7 @@ constexpr int SCAN_TILE = SBS * SCAN_ITEMS;
 constexpr size_t LDS_BYTES = 65536;  // dynamic LDS budget of one numeric block
 
 constexpr int64_t ERR_INDEX = 1, ERR_ROW = 4;
+constexpr int INFO_WORDS = 16;  // status and statistics words of a symbolic build
 constexpr int MAXADJ = 64;  // elements per node (adjacency rows are padded to this length)
 constexpr int MAXROW = 64;  // nonzeros per row
 
@@ -829,9 +832,10 @@ __device__ int64_t lb_exclusive(const uint64_t* look, int64_t t, bool& timeout) 
 // (called a row-pattern block below).  Besides the offsets, the tile measures the largest
 // CSR window of the numeric block classes (NR_BIG rows, NR_MID rows as sums over 4 and 2
 // neighbouring lanes, NR_SMALL = 4 rows per half thread) and the largest number of elements
-// around a node, and stores them as tstat[4t .. 4t+3] (no atomics on shared words: those
+// around a node, and stores them as tstat[8t .. 8t+7] (no atomics on shared words: those
 // serialise across the whole device); k_row_stats reduces them.
 static_assert(SCAN_ITEMS == RR && SCAN_ITEMS == 8, "a scan thread owns one row-pattern block of 8 rows");
+constexpr int TSTAT = 8;  // int32 statistics per tile (two 16-byte words)
 
 // RW: words of a row-pattern block's region in colblk; NRD: rounds of 64 words read at once
 template <int RW, int NRD>
@@ -842,7 +846,7 @@ __global__ __launch_bounds__(SBS) void k_row_offsets(int64_t nn, const int32_t* 
                                                      int32_t* __restrict__ tstat, int64_t* __restrict__ info) {
     __shared__ int32_t boff[SBS];  // offset of each thread's block inside the tile
     __shared__ int32_t bcnt[SBS];
-    __shared__ int red[4][SBS / 64];
+    __shared__ int red[TSTAT][SBS / 64];
     __shared__ int64_t excl_s;
     const int64_t t = blockIdx.x;
     const int64_t row0 = t * SCAN_TILE + static_cast<int64_t>(threadIdx.x) * SCAN_ITEMS;
@@ -860,15 +864,20 @@ __global__ __launch_bounds__(SBS) void k_row_offsets(int64_t nn, const int32_t* 
     if (threadIdx.x == 0) lb_publish(look, t, (t == 0 ? LB_INC : LB_AGG) | static_cast<uint64_t>(total));
     boff[threadIdx.x] = static_cast<int32_t>(pre);
     bcnt[threadIdx.x] = sum;
-    // launch statistics: 4-, 16- and 32-row windows (tiles and threads start on multiples of 32 and 8 rows)
-    int m[4];
+    // launch statistics: 2-, 4-, 8-, 16- and 32-row windows (tiles and threads start on
+    // multiples of 32 and 8 rows)
+    int m[TSTAT];
     const int w4a = v[0] + v[1] + v[2] + v[3], w4b = v[4] + v[5] + v[6] + v[7];
     m[2] = max(w4a, w4b);
     m[1] = sum + __shfl_xor(sum, 1, 64);
     m[0] = m[1] + __shfl_xor(m[1], 2, 64);
     m[3] = amax;
+    m[4] = sum;
+    m[5] = max(max(v[0] + v[1], v[2] + v[3]), max(v[4] + v[5], v[6] + v[7]));
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 6; c < TSTAT; ++c) m[c] = 0;
+#pragma unroll
+    for (int c = 0; c < TSTAT; ++c) {
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) m[c] = max(m[c], __shfl_xor(m[c], d, 64));
         if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = m[c];
@@ -889,12 +898,12 @@ __global__ __launch_bounds__(SBS) void k_row_offsets(int64_t nn, const int32_t* 
         }
     }
     __syncthreads();
-    if (threadIdx.x < 4) {
+    if (threadIdx.x < TSTAT) {
         const int c = threadIdx.x;
         int x = red[c][0];
 #pragma unroll
         for (int w = 1; w < SBS / 64; ++w) x = max(x, red[c][w]);
-        tstat[t * 4 + c] = x;
+        tstat[t * TSTAT + c] = x;
     }
     const int64_t base = excl_s;
     int64_t o = base + pre;
@@ -944,32 +953,38 @@ __global__ __launch_bounds__(SBS) void k_row_offsets(int64_t nn, const int32_t* 
     }
 }
 
-// the tiles' statistics into info[3] (NR_BIG windows), info[4] (NR_MID), info[5] (NR_SMALL)
-// and info[7] (elements around a node); one block
+// the tiles' statistics into info[3] (32-row windows), info[4] (16 rows), info[5] (4 rows),
+// info[7] (elements around a node), info[8] (8 rows) and info[9] (2 rows); one block
 __global__ __launch_bounds__(SBS) void k_row_stats(int64_t tiles, const int32_t* __restrict__ tstat,
                                                    int64_t* __restrict__ info) {
-    __shared__ int red[4][SBS / 64];
-    int m[4] = {0, 0, 0, 0};
+    __shared__ int red[TSTAT][SBS / 64];
+    int m[TSTAT];
+#pragma unroll
+    for (int c = 0; c < TSTAT; ++c) m[c] = 0;
     for (int64_t t = threadIdx.x; t < tiles; t += SBS) {
-        const int4 v = *reinterpret_cast<const int4*>(tstat + t * 4);
+        const int4 v = *reinterpret_cast<const int4*>(tstat + t * TSTAT);
+        const int4 w = *reinterpret_cast<const int4*>(tstat + t * TSTAT + 4);
         m[0] = max(m[0], v.x);
         m[1] = max(m[1], v.y);
         m[2] = max(m[2], v.z);
         m[3] = max(m[3], v.w);
+        m[4] = max(m[4], w.x);
+        m[5] = max(m[5], w.y);
     }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < TSTAT; ++c) {
 #pragma unroll
         for (int d = 32; d >= 1; d >>= 1) m[c] = max(m[c], __shfl_xor(m[c], d, 64));
         if ((threadIdx.x & 63) == 0) red[c][threadIdx.x >> 6] = m[c];
     }
     __syncthreads();
-    if (threadIdx.x < 4) {
+    if (threadIdx.x < 6) {
         const int c = threadIdx.x;
         int x = red[c][0];
 #pragma unroll
         for (int w = 1; w < SBS / 64; ++w) x = max(x, red[c][w]);
-        info[c < 3 ? 3 + c : 7] = x;
+        constexpr int slot[6] = {3, 4, 5, 7, 8, 9};
+        info[slot[c]] = x;
     }
 }
 
@@ -1278,6 +1293,14 @@ constexpr int NITEMS = PF_NUMERIC_ITEMS;    // adjacency entries per thread (hel
 static_assert(MAXADJ <= NITEMS * NBT / NR_SMALL, "the small numeric blocks must cover any admissible row");
 static_assert(NR_SMALL == 4 && NR_MID == 16 && NR_BIG == 32, "k_row_offsets measures windows of 4, 16 and 32 rows");
 static_assert(MAXADJ == CSR_MAXADJ, "one padded adjacency layout");
+// FP32 blocks: NT32 threads, with 8, 16 or 32 threads per row (rows per block NT32 / 8,
+// NT32 / 16, NT32 / 32) so that NITEMS entries per thread cover 24, 48 or 96 elements per node
+#ifndef PF_F32_THREADS
+#define PF_F32_THREADS 128
+#endif
+constexpr int NT32 = PF_F32_THREADS;
+static_assert(NT32 == 64 || NT32 == 128 || NT32 == 256, "FP32 numeric blocks of one, two or four waves");
+static_assert(MAXADJ <= NITEMS * 32, "the FP32 class with 32 threads per row covers any admissible row");
 
 template <typename T>
 struct alignas(16) Vec4 {  // 16-byte LDS reads; the layout keeps Vec4 arrays 16-byte aligned
@@ -1356,6 +1379,7 @@ __device__ __forceinline__ bool route32(float det, float absterms, float tau_abs
     return enable && !keep;
 }
 
+// dynamic LDS of one numeric block of numeric_block
 template <int DIM, typename T>
 constexpr size_t numeric_lds_bytes(int nr, int wmax) {
     return static_cast<size_t>(wmax) * (2 * sizeof(typename Exact<T>::acc) + sizeof(Vec4<T>) + 8) +
@@ -1583,41 +1607,331 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
     }
 }
 
-// waves per SIMD the numeric kernel is compiled for: 8 (at most 64 VGPRs) where the FP32
-// body fits them without spilling (constant coefficients), else the compiler's choice
-template <typename T, int QN>
-constexpr int numeric_waves() {
-    return sizeof(T) == 4 && QN == 0 ? 8 : 1;
+// LDS of one FP32 numeric block: per slot an edge vector, the two integer sums and the slot's
+// row; per row the window bounds and the two row maxima
+template <int DIM>
+constexpr size_t numeric_lds_bytes_f32(int nr, int wmax) {
+    return static_cast<size_t>(wmax) * (sizeof(Vec4<float>) + 2 * sizeof(uint64_t) + 1) +
+           static_cast<size_t>(3 * (nr + 1)) * 4;
+}
+
+// FP32 numeric assembly, NR rows per block of NT threads; thread t owns row t % NR: its
+// adjacency entries j = t / NR + q NT / NR (q < NITEMS) and its slots k = t / NR + u NT / NR.
+//   round trip 1  every load that depends on nothing: the window bounds, the row's adjacency
+//                 length, diagonal position and node coordinates, the entries' packed words;
+//   round trips 2, 3  the columns of the thread's slots, then their coordinates (two slots of
+//                 a row per pass, all loads in flight), giving every slot the edge vector from
+//                 its row's node to its column's node (FP64 difference rounded once) in LDS;
+//   phase 1a  every entry computes its element's row of K_e and M_e in registers (geometry
+//             with the fast determinant, routed elements in FP64); every thread enters the
+//             largest magnitude of its contributions into its row's maximum (one LDS atomic per
+//             matrix);
+//   phase 1b  every contribution is rounded onto its row's grid (RowGrid32) and added as a
+//             64-bit integer: exact, so the order of the adds does not matter; a thread adds
+//             its entries' diagonal contributions in registers first and enters them with one
+//             atomic each;
+//   phase 2   one slot per thread converts its sums and stores them (coalesced).
+// A row that receives a non-finite contribution (a degenerate element, or a non-finite
+// coefficient) is NaN in every slot.
+template <int DIM, bool COEF, int NR, int NT, int QN = 0>
+__device__ __forceinline__ void numeric_block_f32(int64_t r0, int64_t nn, const double* __restrict__ coords,
+                                                  const int32_t* __restrict__ row_ptr,
+                                                  const int32_t* __restrict__ col_idx,
+                                                  const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
+                                                  const uint32_t* __restrict__ pk, const int32_t* __restrict__ dpos,
+                                                  const float* __restrict__ cK, const float* __restrict__ cM,
+                                                  float* __restrict__ valsK, float* __restrict__ valsM,
+                                                  const Fallback& fb, int64_t* d_counters, int wmax) {
+    constexpr int NLB = DIM + 1;
+    constexpr int JS = NT / NR;  // stride of a thread's entries and slots within its row
+    using G = RowGrid32;
+    extern __shared__ __align__(16) unsigned char smem[];
+    Vec4<float>* f = reinterpret_cast<Vec4<float>*>(smem);         // [wmax] edge vector per slot
+    uint64_t* accK = reinterpret_cast<uint64_t*>(f + wmax);         // [wmax]
+    uint64_t* accM = accK + wmax;                                   // [wmax]
+    int32_t* rp = reinterpret_cast<int32_t*>(accM + wmax);          // [NR + 1]
+    uint32_t* rmK = reinterpret_cast<uint32_t*>(rp + (NR + 1));     // [NR + 1] row maxima (bits of |x|)
+    uint32_t* rmM = rmK + (NR + 1);                                 // [NR + 1]
+    uint8_t* rowof = reinterpret_cast<uint8_t*>(rmM + (NR + 1));    // [wmax] row of each slot
+    static_assert(lds_carve_aligned<Vec4<float>, uint64_t, uint64_t, int32_t, uint32_t, uint32_t, uint8_t>(),
+                  "FP32 numeric LDS carve-out: every array naturally aligned");
+    static_assert((NR & (NR - 1)) == 0 && NT % NR == 0 && NR <= 256, "a thread's items share one row");
+    static_assert(NITEMS * JS >= 1, "items per row");
+
+    const int nr = static_cast<int>((r0 + NR < nn) ? NR : nn - r0);
+    const int t = static_cast<int>(threadIdx.x);
+    const int r = t % NR, jt = t / NR;
+    const int64_t row = r0 + (r < nr ? r : nr - 1);  // in bounds for the loads of rows past the end
+
+    // round trip 1 (no load waits for another)
+    const int32_t rpv = row_ptr[r0 + (t <= nr ? t : nr)];
+    const int32_t alv = adj_len[row];
+    const int32_t dpv = dpos[row];
+    double pi[DIM];
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) pi[c] = coords[row * DIM + c];
+    uint32_t pw[NITEMS];
+    int64_t tt[NITEMS];
+#pragma unroll
+    for (int q = 0; q < NITEMS; ++q) {
+        const int j = jt + q * JS;
+        tt[q] = row * MAXADJ + (j < MAXADJ ? j : MAXADJ - 1);  // padded adjacency rows
+        pw[q] = pk[tt[q]];
+    }
+    if (t <= NR) rp[t] = rpv;
+    if (t < NR) {
+        rmK[t] = 0u;
+        rmM[t] = 0u;
+    }
+    __syncthreads();
+    const int32_t w0 = rp[0];
+    const int W = rp[nr] - w0;
+    const int s0 = rp[r] - w0;
+    const int len = rp[r + 1] - rp[r];  // 0 for rows past the end
+    const int L = r < nr ? alv : 0;     // elements around the row's node
+    bool okq[NITEMS];
+#pragma unroll
+    for (int q = 0; q < NITEMS; ++q) okq[q] = jt + q * JS < L;  // the host keeps NITEMS * JS >= L
+
+    // coefficients of the thread's entries (their loads overlap the slot passes)
+    float ckq[NITEMS], cmq0[NITEMS];
+    float cmq[QN > 0 ? NITEMS : 1][QN > 0 ? QN : 1];
+#pragma unroll
+    for (int q = 0; q < NITEMS; ++q) {
+        ckq[q] = 1.0f;
+        cmq0[q] = 1.0f;
+        if constexpr (COEF || QN > 0) {
+            const int64_t e = okq[q] ? (adj[tt[q]] >> 2) : 0;
+            if constexpr (QN == 0) {
+                if (cK) ckq[q] = cK[e];
+                if (cM) cmq0[q] = cM[e];
+            } else {
+                float sk = 0.0f;
+#pragma unroll
+                for (int iq = 0; iq < QN; ++iq) {
+                    sk += cK ? cK[e * QN + iq] : 1.0f;
+                    cmq[q][iq] = cM ? cM[e * QN + iq] : 1.0f;
+                }
+                ckq[q] = sk * static_cast<float>(1.0 / QN);  // equal weights: the mean of the stiffness coefficient
+            }
+        }
+    }
+
+    // round trips 2 and 3: edge vectors of the thread's slots, two per pass; sums cleared
+    for (int k0 = jt; k0 < len; k0 += 2 * JS) {
+        const int k1 = k0 + JS;
+        const bool two = k1 < len;
+        const int64_t c0 = col_idx[w0 + s0 + k0];
+        const int64_t c1 = col_idx[w0 + s0 + (two ? k1 : k0)];
+        double x0[DIM], x1[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            x0[c] = coords[c0 * DIM + c];
+            x1[c] = coords[c1 * DIM + c];
+        }
+        Vec4<float> v;
+        v.x = static_cast<float>(x0[0] - pi[0]);
+        v.y = static_cast<float>(x0[1] - pi[1]);
+        v.z = DIM == 3 ? static_cast<float>(x0[DIM - 1] - pi[DIM - 1]) : 0.0f;
+        v.w = 0.0f;
+        f[s0 + k0] = v;
+        accK[s0 + k0] = 0;
+        accM[s0 + k0] = 0;
+        rowof[s0 + k0] = static_cast<uint8_t>(r);
+        if (two) {
+            v.x = static_cast<float>(x1[0] - pi[0]);
+            v.y = static_cast<float>(x1[1] - pi[1]);
+            v.z = DIM == 3 ? static_cast<float>(x1[DIM - 1] - pi[DIM - 1]) : 0.0f;
+            f[s0 + k1] = v;
+            accK[s0 + k1] = 0;
+            accM[s0 + k1] = 0;
+            rowof[s0 + k1] = static_cast<uint8_t>(r);
+        }
+    }
+    __syncthreads();
+
+    // phase 1a: rows of the adjacent elements in registers; the thread's maxima
+    const float tau_abs = static_cast<float>(fb.tau_abs), tau_cond = static_cast<float>(fb.tau_cond);
+    constexpr int MQ = QN > 0 ? DIM + 1 : 1;  // mass values per row: one per node with a rule, else one
+    float kr[NITEMS][NLB], mr[NITEMS][MQ];
+    int64_t routed = 0;
+    float mk = 0.0f, mm = 0.0f;
+    bool finite = true;
+#pragma unroll
+    for (int q = 0; q < NITEMS; ++q) {
+        if (!okq[q]) continue;
+        const uint32_t p = pw[q];
+        const float ck = ckq[q], cm = cmq0[q];
+        float u[DIM][DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const Vec4<float> v = f[s0 + static_cast<int>((p >> (2 + 8 * k)) & 255)];
+            u[k][0] = v.x;
+            u[k][1] = v.y;
+            if constexpr (DIM == 3) u[k][2] = v.z;
+        }
+        P1Geom<DIM, float> g;
+        p1_geom_edges_fast<DIM>(u, g);
+        const bool route = route32(g.det, g.absterms, tau_abs, tau_cond, fb.enable);
+        const float adet_t = fabsf(g.det);
+        double adet_d = 0.0;
+        if (route) {
+            // FP64 recomputation from the coordinates of the row's node (read again: a rare path
+            // that should not keep them in registers) and the three others
+            double ev[DIM][DIM];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                const int64_t col = col_idx[w0 + s0 + static_cast<int>((p >> (2 + 8 * k)) & 255)];
+#pragma unroll
+                for (int c = 0; c < DIM; ++c) ev[k][c] = coords[col * DIM + c] - coords[row * DIM + c];
+            }
+            double kd[NLB], md;
+            origin_row_f64<DIM>(ev, ck, cm, kd, md, adet_d);
+#pragma unroll
+            for (int b = 0; b < NLB; ++b) kr[q][b] = static_cast<float>(kd[b]);
+            mr[q][0] = static_cast<float>(md);
+            if ((p & 3) == 0) ++routed;  // count each element once, at its first node's row
+        } else {
+            origin_row<DIM, float>(g, ck, cm, kr[q], mr[q][0]);
+        }
+        if constexpr (QN > 0) {
+            // mass row by the rule: |det| sum_q w cM_q lam_a(q) lam_b(q), b = the row's node,
+            // then the other nodes in local order
+            const int a = static_cast<int>(p & 3);
+            float ms[NLB];
+#pragma unroll
+            for (int b = 0; b < NLB; ++b) ms[b] = 0.0f;
+#pragma unroll
+            for (int iq = 0; iq < QN; ++iq) {
+                const float wl =
+                    static_cast<float>(quad_weight<DIM, QN>() * QuadRule<DIM, QN>::lam(iq, a)) * cmq[QN > 0 ? q : 0][iq];
+#pragma unroll
+                for (int b = 0; b < NLB; ++b) {
+                    const int lb = b == 0 ? a : (b - 1 < a ? b - 1 : b);
+                    ms[b] = fmaf(wl, static_cast<float>(QuadRule<DIM, QN>::lam(iq, lb)), ms[b]);
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < NLB; ++b) {
+                mr[q][b] = route ? static_cast<float>(adet_d * static_cast<double>(ms[b])) : adet_t * ms[b];
+                mm = fmaxf(mm, fabsf(mr[q][b]));
+            }
+        } else {
+            mm = fmaxf(mm, fabsf(mr[q][0] + mr[q][0]));  // the diagonal takes 2 mo
+        }
+#pragma unroll
+        for (int b = 0; b < NLB; ++b) mk = fmaxf(mk, fabsf(kr[q][b]));
+        // K_e's row is kf times dot products of finite cofactors: all of it is finite exactly
+        // when its diagonal entry kf |c_0|^2 is; the mass row carries |det| in its first entry
+        finite = finite && __builtin_isfinite(kr[q][0]) && __builtin_isfinite(mr[q][0]);
+    }
+    if (routed) count_add(d_counters, 0, routed);
+    if (okq[0]) {  // items are dealt in order: a thread with any entry has its first
+        atomicMax(rmK + r, finite ? G::mag(mk) : G::POISON);
+        atomicMax(rmM + r, G::mag(mm));
+    }
+    __syncthreads();
+
+    // phase 1b: every contribution onto its row's grid, exact integer sums
+    const uint32_t mKr = rmK[r];
+    if (okq[0] && mKr != G::POISON) {
+        const int shK = G::shift(mKr), shM = G::shift(rmM[r]);
+        uint64_t dK = 0, dM = 0;
+#pragma unroll
+        for (int q = 0; q < NITEMS; ++q) {
+            if (!okq[q]) continue;
+            dK += G::quant(kr[q][0], shK);
+            uint64_t qm = 0;
+            if constexpr (QN > 0) dM += G::quant(mr[q][0], shM);
+            else {
+                qm = G::quant(mr[q][0], shM);
+                dM += qm + qm;
+            }
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                const int sl = s0 + static_cast<int>((pw[q] >> (2 + 8 * k)) & 255);
+                atomicAdd(accK + sl, G::quant(kr[q][1 + k], shK));
+                atomicAdd(accM + sl, QN > 0 ? G::quant(mr[q][QN > 0 ? 1 + k : 0], shM) : qm);
+            }
+        }
+        const int sd = s0 + dpv;
+        atomicAdd(accK + sd, dK);
+        atomicAdd(accM + sd, dM);
+    }
+    __syncthreads();
+
+    // phase 2: one slot per thread, coalesced stores
+    for (int w = t; w < W; w += NT) {
+        const int rr = rowof[w];
+        const uint32_t mK = rmK[rr];
+        const bool poison = mK == G::POISON;
+        valsK[w0 + w] = poison ? __builtin_nanf("") : G::back(accK[w], G::shift(mK));
+        if (valsM) valsM[w0 + w] = poison ? __builtin_nanf("") : G::back(accM[w], G::shift(rmM[rr]));
+    }
+}
+
+// waves per SIMD the numeric kernels are compiled for: the FP32 body with constant
+// coefficients and 8 or more rows per block fits 64 VGPRs (8 waves) without spilling; the
+// other variants keep the compiler's choice
+template <int QN, bool COEF, int NR>
+constexpr int numeric32_waves() {
+    return QN == 0 && !COEF && NR >= 8 ? 8 : 1;
 }
 
 template <int DIM, typename T, bool COEF, int NR, int QN = 0>
-__global__ __launch_bounds__(NBT, (numeric_waves<T, QN>())) void k_numeric(int64_t nn, const double* __restrict__ coords,
+__global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __restrict__ coords,
                                                  const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
                                                  const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
                                                  const uint32_t* __restrict__ pk, const T* __restrict__ cK,
                                                  const T* __restrict__ cM, T* __restrict__ valsK, T* __restrict__ valsM,
                                                  Fallback fb, int64_t* d_counters, int wmax) {
-    numeric_block<DIM, T, COEF, NR, QN>(static_cast<int64_t>(blockIdx.x) * NR, nn, coords, row_ptr, col_idx, adj_len, adj,
-                                    pk, cK, cM, valsK, valsM, fb, d_counters, wmax);
+    numeric_block<DIM, T, COEF, NR, QN>(static_cast<int64_t>(blockIdx.x) * NR, nn, coords, row_ptr, col_idx, adj_len,
+                                        adj, pk, cK, cM, valsK, valsM, fb, d_counters, wmax);
 }
 
-// The numeric phase of several meshes in one launch: block b belongs to the job whose
-// block range holds b (binary search over the jobs' first blocks); every job keeps its own
-// structure, coordinates, outputs, routing thresholds and counters, and its rows are
-// computed exactly as by k_numeric, so a job's values do not depend on its batch.
-template <int DIM, typename T, int NR>
-__global__ __launch_bounds__(NBT, (numeric_waves<T, 0>())) void k_numeric_jobs(const NumericJob* __restrict__ jobs, int njobs, int wmax) {
+template <int DIM, bool COEF, int NR, int NT, int QN = 0>
+__global__ __launch_bounds__(NT, (numeric32_waves<QN, COEF, NR>())) void k_numeric32(
+    int64_t nn, const double* __restrict__ coords, const int32_t* __restrict__ row_ptr,
+    const int32_t* __restrict__ col_idx, const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
+    const uint32_t* __restrict__ pk, const int32_t* __restrict__ dpos, const float* __restrict__ cK,
+    const float* __restrict__ cM, float* __restrict__ valsK, float* __restrict__ valsM, Fallback fb,
+    int64_t* d_counters, int wmax) {
+    numeric_block_f32<DIM, COEF, NR, NT, QN>(static_cast<int64_t>(blockIdx.x) * NR, nn, coords, row_ptr, col_idx,
+                                             adj_len, adj, pk, dpos, cK, cM, valsK, valsM, fb, d_counters, wmax);
+}
+
+// block b of a multi-mesh launch belongs to the job whose block range holds b
+__device__ __forceinline__ const NumericJob& job_of_block(const NumericJob* __restrict__ jobs, int njobs, int64_t b) {
     int lo = 0, hi = njobs - 1;
-    const int64_t b = blockIdx.x;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (jobs[mid].block0 <= b) lo = mid;
         else hi = mid - 1;
     }
-    const NumericJob& j = jobs[lo];
-    numeric_block<DIM, T, false, NR>((b - j.block0) * NR, j.nn, j.coords, j.row_ptr, j.col_idx, j.adj_len, j.adj, j.pk,
-                                     nullptr, nullptr, static_cast<T*>(j.valsK), static_cast<T*>(j.valsM), j.fb,
-                                     j.counters, wmax);
+    return jobs[lo];
+}
+
+// The numeric phase of several meshes in one launch: block b belongs to the job whose block
+// range holds b (binary search over the jobs' first blocks); every job keeps its own
+// structure, coordinates, outputs, routing thresholds and counters, and its rows are
+// computed exactly as by k_numeric / k_numeric32, so a job's values do not depend on its batch.
+template <int DIM, int NR>
+__global__ __launch_bounds__(NBT) void k_numeric_jobs(const NumericJob* __restrict__ jobs, int njobs, int wmax) {
+    const int64_t b = blockIdx.x;
+    const NumericJob& j = job_of_block(jobs, njobs, b);
+    numeric_block<DIM, double, false, NR>((b - j.block0) * NR, j.nn, j.coords, j.row_ptr, j.col_idx, j.adj_len, j.adj,
+                                          j.pk, nullptr, nullptr, static_cast<double*>(j.valsK),
+                                          static_cast<double*>(j.valsM), j.fb, j.counters, wmax);
+}
+
+template <int DIM, int NR, int NT>
+__global__ __launch_bounds__(NT, (numeric32_waves<0, false, NR>())) void k_numeric_jobs32(
+    const NumericJob* __restrict__ jobs, int njobs, int wmax) {
+    const int64_t b = blockIdx.x;
+    const NumericJob& j = job_of_block(jobs, njobs, b);
+    numeric_block_f32<DIM, false, NR, NT>((b - j.block0) * NR, j.nn, j.coords, j.row_ptr, j.col_idx, j.adj_len,
+                                          j.adj, j.pk, j.dpos, nullptr, nullptr, static_cast<float*>(j.valsK),
+                                          static_cast<float*>(j.valsM), j.fb, j.counters, wmax);
 }
 
 // ---------------------------------------------------------------------------- host
@@ -1664,8 +1978,19 @@ pf_status launch_numeric(const pf_csr* c, const double* coords, const void* cK, 
     return launch_check("pf_assemble");
 }
 
-// rows per block: the largest of NR_BIG, NR_MID, NR_SMALL whose window fits the LDS budget
-// and whose item budget covers the longest adjacency row
+// largest CSR window of nr consecutive rows starting at a multiple of nr
+int window_of(const pf_csr* c, int nr) {
+    switch (nr) {
+        case 32: return c->wmax_big;
+        case 16: return c->wmax_mid;
+        case 8: return c->wmax8;
+        case 4: return c->wmax_small;
+        default: return c->wmax2;
+    }
+}
+
+// rows per block (FP64): the largest of NR_BIG, NR_MID, NR_SMALL whose window fits the LDS
+// budget and whose item budget covers the longest adjacency row
 template <int DIM, typename T>
 int numeric_rows(const pf_csr* c) {
     if (numeric_lds_bytes<DIM, T>(NR_BIG, c->wmax_big) <= LDS_BYTES && c->max_adj <= NITEMS * NBT / NR_BIG)
@@ -1675,10 +2000,48 @@ int numeric_rows(const pf_csr* c) {
     return NR_SMALL;  // 4 rows of at most MAXROW nonzeros and MAXADJ elements always fit
 }
 
+// rows per FP32 block: 8, 16 or 32 threads per row, the fewest that cover the longest
+// adjacency row and whose window fits the LDS budget
+template <int DIM>
+int numeric_rows32(const pf_csr* c) {
+    constexpr int R8 = NT32 / 8, R16 = NT32 / 16;
+    if (c->max_adj <= NITEMS * 8 && numeric_lds_bytes_f32<DIM>(R8, window_of(c, R8)) <= LDS_BYTES) return R8;
+    if (c->max_adj <= NITEMS * 16 && numeric_lds_bytes_f32<DIM>(R16, window_of(c, R16)) <= LDS_BYTES) return R16;
+    return NT32 / 32;  // at most NT32 / 32 rows of MAXROW nonzeros: always fits
+}
+
+template <int DIM, bool COEF, int NR, int QN = 0>
+pf_status launch_numeric32(const pf_csr* c, const double* coords, const void* cK, const void* cM, void* valsK,
+                           void* valsM, Fallback f, int64_t* ctr, hipStream_t s) {
+    const int wmax = window_of(c, NR);
+    const size_t shm = numeric_lds_bytes_f32<DIM>(NR, wmax);
+    const unsigned g = static_cast<unsigned>(ceil_div(c->nn, NR));
+    hipLaunchKernelGGL((k_numeric32<DIM, COEF, NR, NT32, QN>), dim3(g), dim3(NT32), shm, s, c->nn, coords, c->row_ptr,
+                       c->col_idx, c->adj_len, c->adj, c->pk, c->dpos, static_cast<const float*>(cK),
+                       static_cast<const float*>(cM), static_cast<float*>(valsK), static_cast<float*>(valsM), f, ctr,
+                       wmax);
+    return launch_check("pf_assemble");
+}
+
+template <int DIM, bool COEF, int QN = 0>
+pf_status numeric_dispatch32(const pf_csr* c, const double* coords, const void* cK, const void* cM, void* valsK,
+                             void* valsM, Fallback f, int64_t* ctr, hipStream_t s) {
+    const int nr = numeric_rows32<DIM>(c);
+    if (nr == NT32 / 8)
+        return launch_numeric32<DIM, COEF, NT32 / 8, QN>(c, coords, cK, cM, valsK, valsM, f, ctr, s);
+    if (nr == NT32 / 16)
+        return launch_numeric32<DIM, COEF, NT32 / 16, QN>(c, coords, cK, cM, valsK, valsM, f, ctr, s);
+    return launch_numeric32<DIM, COEF, NT32 / 32, QN>(c, coords, cK, cM, valsK, valsM, f, ctr, s);
+}
+
 template <int DIM, typename T>
 pf_status numeric_dispatch(const pf_csr* c, const double* coords, const void* cK, const void* cM, void* valsK,
                            void* valsM, Fallback f, int64_t* ctr, hipStream_t s) {
     const bool coef = cK || cM;
+    if constexpr (sizeof(T) == 4) {
+        return coef ? numeric_dispatch32<DIM, true>(c, coords, cK, cM, valsK, valsM, f, ctr, s)
+                    : numeric_dispatch32<DIM, false>(c, coords, cK, cM, valsK, valsM, f, ctr, s);
+    }
     switch (numeric_rows<DIM, T>(c)) {
         case NR_BIG:
             return coef ? launch_numeric<DIM, T, true, NR_BIG>(c, coords, cK, cM, valsK, valsM, f, ctr, c->wmax_big, s)
@@ -1698,6 +2061,7 @@ pf_status numeric_dispatch(const pf_csr* c, const double* coords, const void* cK
 template <int DIM, typename T, int QN>
 pf_status numeric_dispatch_quad(const pf_csr* c, const double* coords, const void* cKq, const void* cMq, void* valsK,
                                 void* valsM, Fallback f, int64_t* ctr, hipStream_t s) {
+    if constexpr (sizeof(T) == 4) return numeric_dispatch32<DIM, false, QN>(c, coords, cKq, cMq, valsK, valsM, f, ctr, s);
     switch (numeric_rows<DIM, T>(c)) {
         case NR_BIG:
             return launch_numeric<DIM, T, false, NR_BIG, QN>(c, coords, cKq, cMq, valsK, valsM, f, ctr, c->wmax_big, s);
@@ -1713,8 +2077,8 @@ pf_status numeric_dispatch_quad(const pf_csr* c, const double* coords, const voi
 
 // rows per block of a job's numeric phase (as pf_assemble chooses)
 int numeric_class(const pf_csr* c, pf_dtype prec) {
-    if (c->dim == 3) return prec == PF_F32 ? numeric_rows<3, float>(c) : numeric_rows<3, double>(c);
-    return prec == PF_F32 ? numeric_rows<2, float>(c) : numeric_rows<2, double>(c);
+    if (c->dim == 3) return prec == PF_F32 ? numeric_rows32<3>(c) : numeric_rows<3, double>(c);
+    return prec == PF_F32 ? numeric_rows32<2>(c) : numeric_rows<2, double>(c);
 }
 
 int64_t numeric_blocks(const pf_csr* c, pf_dtype prec) { return ceil_div(c->nn, numeric_class(c, prec)); }
@@ -1728,6 +2092,7 @@ void numeric_describe(const pf_csr* c, const double* coords, void* valsK, void* 
     out->adj_len = c->adj_len;
     out->adj = c->adj;
     out->pk = c->pk;
+    out->dpos = c->dpos;
     out->valsK = valsK;
     out->valsM = valsM;
     out->counters = counters;
@@ -1735,34 +2100,46 @@ void numeric_describe(const pf_csr* c, const double* coords, void* valsK, void* 
     out->block0 = block0;
 }
 
-int numeric_wmax(const pf_csr* c, int nr) {
-    return nr == NR_BIG ? c->wmax_big : (nr == NR_MID ? c->wmax_mid : c->wmax_small);
-}
+int numeric_wmax(const pf_csr* c, int nr) { return window_of(c, nr); }
 
-template <int DIM, typename T, int NR>
-pf_status launch_jobs(const NumericJob* d_jobs, int njobs, int64_t nblocks, int wmax, hipStream_t s) {
-    const size_t shm = numeric_lds_bytes<DIM, T>(NR, wmax);
-    hipLaunchKernelGGL((k_numeric_jobs<DIM, T, NR>), dim3(static_cast<unsigned>(nblocks)), dim3(NBT), shm, s, d_jobs,
+namespace {
+template <int DIM, int NR>
+pf_status launch_jobs64(const NumericJob* d_jobs, int njobs, int64_t nblocks, int wmax, hipStream_t s) {
+    const size_t shm = numeric_lds_bytes<DIM, double>(NR, wmax);
+    hipLaunchKernelGGL((k_numeric_jobs<DIM, NR>), dim3(static_cast<unsigned>(nblocks)), dim3(NBT), shm, s, d_jobs,
                        njobs, wmax);
     return launch_check("numeric batch");
 }
+
+template <int DIM, int NR>
+pf_status launch_jobs32(const NumericJob* d_jobs, int njobs, int64_t nblocks, int wmax, hipStream_t s) {
+    const size_t shm = numeric_lds_bytes_f32<DIM>(NR, wmax);
+    hipLaunchKernelGGL((k_numeric_jobs32<DIM, NR, NT32>), dim3(static_cast<unsigned>(nblocks)), dim3(NT32), shm, s,
+                       d_jobs, njobs, wmax);
+    return launch_check("numeric batch");
+}
+}  // namespace
 
 pf_status numeric_launch_many(int dim, pf_dtype prec, int nr, const NumericJob* d_jobs, int njobs, int64_t nblocks,
                               int wmax, hipStream_t s) {
     if (njobs <= 0 || nblocks <= 0) return PF_OK;
     if (nblocks >= (int64_t(1) << 31)) return fail(PF_ELIMIT, "numeric batch: too many row blocks");
+    if (prec == PF_F32) {
+        auto pick = [&](auto big, auto mid, auto small) {
+            return nr == NT32 / 8 ? big(d_jobs, njobs, nblocks, wmax, s)
+                                  : (nr == NT32 / 16 ? mid(d_jobs, njobs, nblocks, wmax, s)
+                                                     : small(d_jobs, njobs, nblocks, wmax, s));
+        };
+        if (dim == 3)
+            return pick(launch_jobs32<3, NT32 / 8>, launch_jobs32<3, NT32 / 16>, launch_jobs32<3, NT32 / 32>);
+        return pick(launch_jobs32<2, NT32 / 8>, launch_jobs32<2, NT32 / 16>, launch_jobs32<2, NT32 / 32>);
+    }
     auto pick = [&](auto big, auto mid, auto small) {
         return nr == NR_BIG ? big(d_jobs, njobs, nblocks, wmax, s)
                             : (nr == NR_MID ? mid(d_jobs, njobs, nblocks, wmax, s) : small(d_jobs, njobs, nblocks, wmax, s));
     };
-    if (dim == 3) {
-        if (prec == PF_F32)
-            return pick(launch_jobs<3, float, NR_BIG>, launch_jobs<3, float, NR_MID>, launch_jobs<3, float, NR_SMALL>);
-        return pick(launch_jobs<3, double, NR_BIG>, launch_jobs<3, double, NR_MID>, launch_jobs<3, double, NR_SMALL>);
-    }
-    if (prec == PF_F32)
-        return pick(launch_jobs<2, float, NR_BIG>, launch_jobs<2, float, NR_MID>, launch_jobs<2, float, NR_SMALL>);
-    return pick(launch_jobs<2, double, NR_BIG>, launch_jobs<2, double, NR_MID>, launch_jobs<2, double, NR_SMALL>);
+    if (dim == 3) return pick(launch_jobs64<3, NR_BIG>, launch_jobs64<3, NR_MID>, launch_jobs64<3, NR_SMALL>);
+    return pick(launch_jobs64<2, NR_BIG>, launch_jobs64<2, NR_MID>, launch_jobs64<2, NR_SMALL>);
 }
 
 size_t csr_bytes(const pf_csr* c) {
@@ -1912,9 +2289,9 @@ pf_status symbolic(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const in
     }
     const int64_t nb = std::max<int64_t>(ceil_div(nn + 1, SCAN_TILE), 1);
     if ((st = grow(c->bsum, c->cap_bsum, nb))) return st;
-    if ((st = grow(c->info, c->cap_info, 8))) return st;
+    if ((st = grow(c->info, c->cap_info, INFO_WORDS))) return st;
     if ((st = mark(c, 0, s))) return st;
-    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, c->info, int64_t(8), int64_t(0));
+    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, c->info, int64_t(INFO_WORDS), int64_t(0));
     if (nn > 0) hipLaunchKernelGGL(k_fill_i32, dim3(flat_grid(nn)), dim3(SBS), 0, s, c->adj_len, nn, 0);
     const unsigned gtile = static_cast<unsigned>(std::max<int64_t>(ceil_div(m, AG_TILE), 1));
     if (m > 0) {
@@ -1933,8 +2310,8 @@ pf_status symbolic(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const in
     if ((st = grow(c->colblk, c->cap_colblk, std::max<int64_t>(regions * RR * maxrow, 1)))) return st;
     if ((st = grow(c->col_idx, c->cap_nnz, std::max<int64_t>(nn * maxrow, 1)))) return st;
     if ((st = grow(c->dpos, c->cap_dpos, nn + 1))) return st;
-    // tile descriptors, then 4 int32 statistics per tile
-    if ((st = grow(c->look, c->cap_look, 3 * std::max<int64_t>(tiles, 1) + 1))) return st;
+    // tile descriptors, then TSTAT int32 statistics per tile
+    if ((st = grow(c->look, c->cap_look, (1 + TSTAT / 2) * std::max<int64_t>(tiles, 1) + 1))) return st;
     if ((st = mark(c, 1, s))) return st;
     if (nn > 0) {
         const unsigned g = static_cast<unsigned>(grows);
@@ -1970,9 +2347,9 @@ pf_status symbolic(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const in
     if ((st = mark(c, 3, s))) return st;
     if ((st = launch_check(who))) return st;
     c->pending = c->timing;
-    if (!c->hinfo) PF_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hinfo), 8 * sizeof(int64_t)));
+    if (!c->hinfo) PF_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hinfo), INFO_WORDS * sizeof(int64_t)));
     int64_t* info = c->hinfo;  // pinned: a direct copy, no staging through pageable memory
-    PF_HIP_TRY(hipMemcpyAsync(info, c->info, 8 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    PF_HIP_TRY(hipMemcpyAsync(info, c->info, INFO_WORDS * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     PF_HIP_TRY(hipStreamSynchronize(s));
     if (info[0] & ERR_INDEX) return fail(PF_EINDEX, std::string(who) + ": node index out of range in elems");
     if (info[0] & ERR_ROW)
@@ -1991,6 +2368,8 @@ pf_status symbolic(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const in
     c->wmax_mid = static_cast<int>(info[4]);
     c->wmax_small = static_cast<int>(info[5]);
     c->max_adj = static_cast<int>(info[7]);
+    c->wmax8 = static_cast<int>(info[8]);
+    c->wmax2 = static_cast<int>(info[9]);
     c->built = true;
     return PF_OK;
 }
@@ -2071,7 +2450,7 @@ pf_status pf_csr_faces(pf_csr* c, const double* coords, const int32_t* elems, vo
     }
     if ((st = scan(c->fcount, nn, c->fptr, c->bsum, c->finfo + 1, s))) return st;
     if ((st = scan(c->bcount, nn, c->bptr, c->bsum, c->finfo + 2, s))) return st;
-    if (!c->hinfo) PF_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hinfo), 8 * sizeof(int64_t)));
+    if (!c->hinfo) PF_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hinfo), INFO_WORDS * sizeof(int64_t)));
     int64_t* info = c->hinfo;
     PF_HIP_TRY(hipMemcpyAsync(info, c->finfo, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     PF_HIP_TRY(hipStreamSynchronize(s));

@@ -54,4 +54,29 @@ struct Exact<double> {
     __device__ static double back(acc a, int sh) { return ldexp(static_cast<double>(static_cast<long long>(a)), -sh); }
 };
 
+// FP32 contributions of one CSR row, summed exactly as 64-bit integers: the grid is 2^(e-44)
+// with e the exponent of the row's largest |contribution| (found in a first pass), so every
+// contribution rounds onto it as an integer below 2^45 in magnitude and sums of up to 256 of
+// them stay below 2^53 -- exact, in any order of the adds.  The rounding to the grid is done
+// by one FP64 add of 3 * 2^51 (the value is then an integer in the low bits of the double);
+// subtracting that constant's bit pattern (whose low 32 bits are zero) leaves the integer in
+// two's complement.  A contribution's grid error is at most 2^-45 of the row maximum's power
+// of two, far below the FP32 result's own rounding, which happens once, in back().  Maxima are
+// kept as the bits of |x| (ordered as unsigned integers for non-negative floats); the value
+// POISON marks a row that received a non-finite contribution.
+struct RowGrid32 {
+    static constexpr uint32_t POISON = 0xffffffffu;
+    __device__ static uint32_t mag(float x) { return __float_as_uint(fabsf(x)); }
+    // 44 - e for a normal maximum; a zero or subnormal maximum takes e = -127 (every
+    // contribution is then below 2^-126 and scales below 2^44)
+    __device__ static int shift(uint32_t m) { return 171 - static_cast<int>((m >> 23) & 255); }
+    __device__ static uint64_t quant(float x, int sh) {
+        const double d = static_cast<double>(__builtin_amdgcn_ldexpf(x, sh)) + 6755399441055744.0;
+        return static_cast<uint64_t>(__double_as_longlong(d)) - 0x4338000000000000ull;
+    }
+    __device__ static float back(uint64_t a, int sh) {
+        return static_cast<float>(ldexp(static_cast<double>(static_cast<int64_t>(a)), -sh));
+    }
+};
+
 }  // namespace pf

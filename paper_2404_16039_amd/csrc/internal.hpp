@@ -16,6 +16,7 @@ struct NumericJob {
     const int32_t* adj_len;
     const int32_t* adj;
     const uint32_t* pk;
+    const int32_t* dpos;
     void* valsK;
     void* valsM;
     int64_t* counters;

@@ -60,6 +60,42 @@ __device__ __forceinline__ void p1_geom_edges(const C (&u)[DIM][DIM], P1Geom<DIM
     }
 }
 
+// FP32 geometry for the bulk of well-shaped elements: c_1 and det are first evaluated with one
+// rounding per product (FMA), which is within (3 kappa + 2 kappa_L) u of |det| (kappa the
+// det-condition, kappa_L the sum of the six |Leibniz products| over |det|); only where kappa > 4
+// (or det is not finite) are c_1 and det recomputed compensated as in p1_geom_edges, so the
+// determinant of every element is within a few tens of u of the exact one, and within
+// (1 + 2 kappa) u wherever kappa is large.  2-D elements take p1_geom_edges.
+template <int DIM>
+__device__ __forceinline__ void p1_geom_edges_fast(const float (&u)[DIM][DIM], P1Geom<DIM, float>& g) {
+    if constexpr (DIM == 3) {
+        g.c[1][0] = fmaf(u[1][1], u[2][2], -(u[1][2] * u[2][1]));
+        g.c[1][1] = fmaf(u[1][2], u[2][0], -(u[1][0] * u[2][2]));
+        g.c[1][2] = fmaf(u[1][0], u[2][1], -(u[1][1] * u[2][0]));
+        g.det = fmaf(u[0][0], g.c[1][0], fmaf(u[0][1], g.c[1][1], u[0][2] * g.c[1][2]));
+        g.absterms = fmaf(fabsf(u[0][0]), fabsf(g.c[1][0]),
+                          fmaf(fabsf(u[0][1]), fabsf(g.c[1][1]), fabsf(u[0][2]) * fabsf(g.c[1][2])));
+        if (!(g.absterms <= 4.0f * fabsf(g.det))) {
+            g.c[1][0] = det2(u[1][1], u[1][2], u[2][1], u[2][2]);
+            g.c[1][1] = det2(u[1][2], u[1][0], u[2][2], u[2][0]);
+            g.c[1][2] = det2(u[1][0], u[1][1], u[2][0], u[2][1]);
+            g.det = dot_comp<float, 3>(u[0], g.c[1], g.absterms);
+        }
+#pragma unroll
+        for (int j = 2; j <= 3; ++j) {
+            const float* x = u[j % 3];
+            const float* y = u[(j + 1) % 3];
+            g.c[j][0] = fmaf(x[1], y[2], -(x[2] * y[1]));
+            g.c[j][1] = fmaf(x[2], y[0], -(x[0] * y[2]));
+            g.c[j][2] = fmaf(x[0], y[1], -(x[1] * y[0]));
+        }
+#pragma unroll
+        for (int i = 0; i < 3; ++i) g.c[0][i] = -(g.c[1][i] + g.c[2][i] + g.c[3][i]);
+    } else {
+        p1_geom_edges<DIM, float>(u, g);
+    }
+}
+
 // Geometry from FP64 edge vectors, rounded once to precision C.
 template <int DIM, typename C>
 __device__ __forceinline__ void p1_geom(const double (&e)[DIM][DIM], P1Geom<DIM, C>& g) {

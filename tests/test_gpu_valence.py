@@ -25,10 +25,14 @@ MESHES = {
 }
 
 
-def expected_rows_per_block(max_adj):
-    """workgroup shape of the numeric kernel for the longest adjacency list (32 rows cover
-    24 elements per node, 16 rows 48, 4 rows any admissible list)"""
-    return 32 if max_adj <= 24 else (16 if max_adj <= 48 else 4)
+def expected_rows_per_block(max_adj, dtype):
+    """workgroup shape of the numeric kernel for the longest adjacency list: FP64 blocks of
+    256 threads take 32 rows (24 elements per node), 16 rows (48) or 4 rows (any admissible
+    list); FP32 blocks of 128 threads take 16, 8 or 4 rows (8, 16 or 32 threads per row,
+    three entries each: 24, 48 or 96 elements per node)"""
+    if dtype == torch.float64:
+        return 32 if max_adj <= 24 else (16 if max_adj <= 48 else 4)
+    return 16 if max_adj <= 24 else (8 if max_adj <= 48 else 4)
 
 
 @pytest.fixture(scope="module")
@@ -59,7 +63,7 @@ def test_high_valence_assembly(lib, name, coef, dtype):
     counts = np.bincount(elems.ravel(), minlength=nn)
     rows, madj = csr.numeric_info(prec_of(dtype))
     assert madj == counts.max()
-    assert rows == expected_rows_per_block(madj), (rows, madj)
+    assert rows == expected_rows_per_block(madj, dtype), (rows, madj)
     vk = torch.empty(nnz, dtype=dtype, device="cuda")
     vm = torch.empty(nnz, dtype=dtype, device="cuda")
     ctr = counters()
@@ -98,6 +102,6 @@ def test_launch_shapes_cover_every_variant(lib):
         say("launch shape", name)
         csr = lib.Csr().symbolic(coords.shape[1], coords.shape[0], dev(elems))
         for p in (0, 1):
-            seen.add(csr.numeric_info(p)[0])
+            seen.add((p, csr.numeric_info(p)[0]))
         csr.close()
-    assert seen == {32, 16, 4}, seen
+    assert seen == {(1, 32), (1, 16), (1, 4), (0, 16), (0, 8), (0, 4)}, seen
