@@ -97,7 +97,8 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=128, help="cubes per side of the CPU oracle sample")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
-    ap.add_argument("--workload", choices=["assembly", "pages", "batch", "serve", "energy", "faces", "p2"],
+    ap.add_argument("--workload", choices=["assembly", "square", "elements", "pages", "batch", "serve", "energy",
+                                           "faces", "p2"],
                     default="assembly")
     ap.add_argument("--coef", choices=["one", "quad"], default="one",
                     help="assembly coefficients: c = 1, or c = exp(x1+x2+x3) at the 4 points of the degree-2 rule "
@@ -105,6 +106,10 @@ def parse():
     ap.add_argument("--jobs", type=int, default=1000, help="jobs of the serving trace")
     ap.add_argument("--rate", type=float, default=200.0, help="arrival rate of the serving trace (jobs/s)")
     ap.add_argument("--tuner-cache", default=None, help="JSON schedule cache of the batch workload")
+    ap.add_argument("--prec", choices=["f32", "f64"], default="f32",
+                    help="assembly precision: FP32 bulk with FP64 fallback, or FP64 throughout")
+    ap.add_argument("--rotate", type=int, default=4,
+                    help="copies of the assembly inputs used in turn (defeats the last-level cache)")
     return ap.parse_args()
 
 
@@ -768,6 +773,10 @@ def main():
 
     if args.workload == "pages":
         return run_pages(args)
+    if args.workload == "square":
+        return run_square(args)
+    if args.workload == "elements":
+        return run_elements(args)
     if args.workload == "batch":
         return run_batch(args)
     if args.workload == "serve":
@@ -779,6 +788,271 @@ def main():
     if args.workload == "p2":
         return run_p2(args)
 
+    return run_assembly(args)
+
+
+def run_square(args):
+    """Latency of the whole 2-D P1 FP64 pipeline on the unit square cut into 32 x 32 squares
+    (2,048 triangles, 1,089 nodes): per-triangle Jacobian determinant, inverse (the gradients
+    of the barycentric coordinates hold J^-T), element stiffness and mass matrices, the CSR
+    structure and the assembly of K and M."""
+    import numpy as np
+    import torch
+
+    from paper_2404_16039_amd import gen
+    from paper_2404_16039_amd import lib as L
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    n = 32
+    coords, elems, _ = gen.square_mesh(n)
+    nn, ne = coords.shape[0], elems.shape[0]
+    tc, te = torch.from_numpy(coords).cuda(), torch.from_numpy(elems).cuda()
+    f64 = torch.float64
+    det = torch.empty(ne, dtype=f64, device="cuda")
+    vol = torch.empty(ne, dtype=f64, device="cuda")
+    grads = torch.empty(ne * 6, dtype=f64, device="cuda")
+    K3D = torch.empty(ne * 9, dtype=f64, device="cuda")
+    M3D = torch.empty(ne * 9, dtype=f64, device="cuda")
+    csr = L.Csr()
+    csr.symbolic(2, nn, te)
+    _, nnz, _, _ = csr.info()
+    vk = torch.empty(nnz, dtype=f64, device="cuda")
+    vm = torch.empty(nnz, dtype=f64, device="cuda")
+    ctr = torch.zeros(4, dtype=torch.int64, device="cuda")
+
+    def step():
+        L.elem_geometry(L.F64, tc, te, det=det, vol=vol, grads=grads, counters=ctr, stream=stream)
+        L.elem_stiffness_mass(L.F64, tc, te, K3D=K3D, M3D=M3D, counters=ctr, stream=stream)
+        csr.symbolic(2, nn, te, stream=stream)
+        csr.assemble(L.F64, tc, te, vk, vm, counters=ctr, stream=stream)
+
+    steps = max(args.steps, 200)
+    t = _timed(step, steps, max(args.warmup, 20), stream)
+    med = float(np.median(t))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3 / steps
+    out = {
+        "metric": "triangles/s of the whole 2-D P1 FP64 pipeline (latency-bound)",
+        "value": ne / (med * 1e-3), "unit": "triangles/s", "n_gpus": 1, "steps": steps,
+        "warmup": max(args.warmup, 20), "ms_per_step": med, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "2-D P1 plain FP64: unit square, 32 x 32 squares x 2 triangles, jitter 0.2 h; "
+                               "Jacobian det and inverse, 3 x 3 element K and M, CSR structure and assembly",
+                   "triangles": ne, "nodes": nn, "nnz": int(nnz)},
+        "latency_us": {"median": round(med * 1e3, 2), "p10": round(float(np.percentile(t, 10)) * 1e3, 2),
+                       "p90": round(float(np.percentile(t, 90)) * 1e3, 2),
+                       "host_wall_per_step": round(wall_ms * 1e3, 2)},
+        "note": "194 KB of data per step: launch- and latency-bound, so no roofline fraction is reported",
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        hi = host_info()
+        t1 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t1 < 5.0:
+            el = oracle.p1_elements(coords, elems)
+            ref = oracle.assemble(elems, nn, el["Ke"], el["Me"], el["Kabs"])
+            reps += 1
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": reps * ne / dt, "unit": "triangles/s", "cores": 1, "kind": "oracle",
+                               "sample": "FP64 oracle (element matrices incl. Jacobian inverse + stable-sort sparse "
+                                         "assembly), the same 2,048 triangles repeated %d times in %.1f s" % (reps, dt),
+                               "host": hi}
+        rp, ci = csr.structure()
+        out["errors_vs_oracle"] = {
+            "structure_identical": bool(np.array_equal(rp.cpu().numpy(), ref["row_ptr"]) and
+                                        np.array_equal(ci.cpu().numpy(), ref["col_idx"])),
+            "K": value_errors(vk.cpu().numpy(), {"val": ref["valK"], "scale": ref["scaleK"]}, 1e-12),
+            "M": value_errors(vm.cpu().numpy(), {"val": ref["valM"], "scale": ref["scaleM"]}, 1e-12),
+            "det_max_rel": float(np.max(np.abs(det.cpu().numpy() - el["det"]) / np.abs(el["det"])))}
+    print(json.dumps(out))
+    csr.close()
+
+
+def run_elements(args):
+    """Per-element work on the 3-D cube (section 3.2 volumes and normals, section 3.6 element
+    matrices), FP32 with FP64 fallback: one launch for det, volume and the outward normals of
+    the four faces (normals3D), one for the 4 x 4 element stiffness and mass pages."""
+    import numpy as np
+    import torch
+
+    from paper_2404_16039_amd import gen
+    from paper_2404_16039_amd import lib as L
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    n = args.n
+    h = 1.0 / n
+    coords, elems, _ = gen.cube_mesh(n, jitter=0.15, with_faces=False)
+    nn, ne = coords.shape[0], elems.shape[0]
+    R = max(1, args.rotate)
+    tcs = [torch.from_numpy(coords).cuda() for _ in range(R)]
+    tes = [torch.from_numpy(elems).cuda() for _ in range(R)]
+    fb = L.fallback(1e-3 * h ** 3, 1e6, True)
+    f32 = torch.float32
+    det = torch.empty(ne, dtype=f32, device="cuda")
+    vol = torch.empty(ne, dtype=f32, device="cuda")
+    nrm = torch.empty(ne * 12, dtype=f32, device="cuda")
+    K3D = torch.empty(ne * 16, dtype=f32, device="cuda")
+    M3D = torch.empty(ne * 16, dtype=f32, device="cuda")
+    ctr = torch.zeros(4, dtype=torch.int64, device="cuda")
+    geo = [lambda k=k: L.elem_geometry(L.F32, tcs[k], tes[k], det=det, vol=vol, normals=nrm, fb=fb, counters=ctr,
+                                       stream=stream) for k in range(R)]
+    mats = [lambda k=k: L.elem_stiffness_mass(L.F32, tcs[k], tes[k], K3D=K3D, M3D=M3D, fb=fb, counters=ctr,
+                                              stream=stream) for k in range(R)]
+    for w in range(args.warmup):
+        geo[w % R]()
+        mats[w % R]()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        evs[k][0].record(stream)
+        geo[k % R]()
+        evs[k][1].record(stream)
+        mats[k % R]()
+        evs[k][2].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tg = np.array([e[0].elapsed_time(e[1]) for e in evs])
+    tm = np.array([e[1].elapsed_time(e[2]) for e in evs])
+    # algorithmic bytes: elems 16 B/tet and FP64 coordinates 24 B/node read once; written:
+    # det + volume 8 B/tet and normals3D 48 B/tet, or the two 4 x 4 FP32 pages 128 B/tet
+    alg_g = 16 * ne + 24 * nn + 56 * ne
+    alg_m = 16 * ne + 24 * nn + 128 * ne
+    ms_step = wall * 1e3 / args.steps
+
+    def roof(name, alg, ms):
+        gbs = alg / (ms * 1e-3) / 1e9
+        return {"kernel": name, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": alg,
+                "launch_us": round(ms * 1e3, 1)}
+    rg = roof("k_elem<3,float> (det, volume, normals3D)", alg_g, float(np.median(tg)))
+    rm = roof("k_elem<3,float> (K3D, M3D)", alg_m, float(np.median(tm)))
+    out = {
+        "metric": "P1 tets/s: volumes + normals3D, then element K and M pages",
+        "value": ne / (ms_step * 1e-3), "unit": "tets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "3-D P1 tets, FP32 with FP64 fallback: unit cube, %d^3 cubes x 6 Kuhn tets, jitter "
+                               "0.15 h; det, volume and normals3D per tet, then the 4 x 4 K and M pages" % n,
+                   "tets": ne, "nodes": nn, "input_sets_rotated": R},
+        "roofline": rm if rm["launch_us"] >= rg["launch_us"] else rg,
+        "rooflines": [rg, rm],
+        "paper_context": {"what": "MATLAB timings at 12,582,912 tets (hardware not stated): volumes 4.42 s "
+                                  "(with mesh generation), normals of all faces 10.9 s"},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        hi = host_info()
+        m = ne
+        t1 = time.perf_counter()
+        passes = 0
+        while time.perf_counter() - t1 < 10.0:  # whole passes over the mesh, >= 10 s in total
+            el = oracle.p1_elements(coords, elems)
+            passes += 1
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": passes * ne / dt, "unit": "tets/s", "cores": 1, "kind": "oracle",
+                               "sample": "FP64 oracle element loop (det, volume, gradients, K_e, M_e, facet "
+                                         "measures) over all %d tets, %d pass(es), single thread, %.1f s"
+                                         % (ne, passes, dt), "host": hi}
+        d = det.cpu().numpy()[:m].astype(np.float64)
+        out["errors_vs_oracle"] = {
+            "det_max_rel": float(np.max(np.abs(d - el["det"]) / np.abs(el["det"]))),
+            "K3D_max_err_over_scale": float(np.max(np.abs(K3D.cpu().numpy().reshape(ne, 16)[:m] - el["Ke"]) /
+                                                   el["Kabs"])),
+            "normals_max_rel": float(np.max(np.abs(-nrm.cpu().numpy().reshape(ne, 12)[:m] - el["grads"]) /
+                                            np.abs(el["grads"]).max(axis=1, keepdims=True)))}
+    print(json.dumps(out))
+
+
+def host_info():
+    """Host cores this process may use and the CPU model (for the oracle legs)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    cap = int(os.environ.get("OMP_NUM_THREADS", avail) or avail)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": avail, "threads": max(1, min(avail, cap)), "cpu_model": model}
+
+
+def _flush(buf):
+    """Overwrite a 1 GiB device buffer (evicts the 256 MB last-level cache); not timed."""
+    buf.fill_(0)
+
+
+def oracle_p1_rate(coords, elems, threads, quad=None):
+    """The oracle's element matrices and sparse() over `elems`: one thread on the whole mesh,
+    or `threads` threads on contiguous element chunks (each chunk assembled on its own, then
+    the chunk matrices summed).  Returns (tets/s, seconds, result of the single-thread run)."""
+    import threading
+
+    import numpy as np
+
+    import oracle
+    nn, ne = coords.shape[0], elems.shape[0]
+
+    def one(c0, c1, out, k):
+        e = elems[c0:c1]
+        if quad is not None:
+            el = oracle.p1_elements_q(coords, e, 2, quad[c0:c1], quad[c0:c1])
+        else:
+            el = oracle.p1_elements(coords, e)
+        out[k] = oracle.assemble(e, nn, el["Ke"], el["Me"], el["Kabs"])
+
+    if threads == 1:
+        res = [None]
+        t0 = time.perf_counter()
+        one(0, ne, res, 0)
+        dt = time.perf_counter() - t0
+        return ne / dt, dt, res[0]
+    import scipy.sparse as sp
+    cuts = np.linspace(0, ne, threads + 1).astype(np.int64)
+    res = [None] * threads
+    t0 = time.perf_counter()
+    th = [threading.Thread(target=one, args=(int(cuts[k]), int(cuts[k + 1]), res, k)) for k in range(threads)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    # chunk matrices summed (in the timed region): their entries concatenated, duplicates added
+    rows = np.concatenate([np.repeat(np.arange(nn, dtype=np.int64), np.diff(r["row_ptr"])) for r in res])
+    cols = np.concatenate([r["col_idx"] for r in res])
+    for key in ("valK", "valM"):
+        sp.coo_matrix((np.concatenate([r[key] for r in res]), (rows, cols)), shape=(nn, nn)).tocsr()
+    dt = time.perf_counter() - t0
+    return ne / dt, dt, None
+
+
+def value_errors(got, ref, tol):
+    """Largest error of every value against the oracle's, relative to the oracle's error scale
+    (the sum of the magnitudes of the contributions), and how many exceed the tolerance."""
+    import numpy as np
+    got = np.asarray(got, dtype=np.float64)
+    e = np.abs(got - ref["val"]) / np.maximum(ref["scale"], 1e-300)
+    big = np.abs(ref["val"]) >= 1e-3 * ref["scale"]
+    rel = np.abs(got - ref["val"])[big] / np.abs(ref["val"][big]) if big.any() else np.zeros(1)
+    return {"max_err_over_scale": float(e.max()) if e.size else 0.0, "over_tol": int((e > tol).sum()),
+            "tol": tol, "max_rel_err_where_not_cancelling": float(rel.max()),
+            "frobenius_rel": float(np.linalg.norm(got - ref["val"]) / max(np.linalg.norm(ref["val"]), 1e-300))}
+
+
+def run_assembly(args):
+    """The headline step: CSR structure + numeric K and M + boundary normals on the 3-D cube."""
     import numpy as np
     import torch
 
@@ -788,55 +1062,60 @@ def main():
     torch.cuda.set_device(0)
     n = args.n
     h = 1.0 / n
+    f64 = args.prec == "f64"
+    dt_val = torch.float64 if f64 else torch.float32
+    prec = L.F64 if f64 else L.F32
+    es = 8 if f64 else 4
     coords, elems, faces = gen.cube_mesh(n, jitter=0.15)
     nn, ne, nf = coords.shape[0], elems.shape[0], faces.shape[0]
-    tc = torch.from_numpy(coords).cuda()
-    te = torch.from_numpy(elems).cuda()
+    # R copies of the inputs, used in turn: R x (elems + coords) well above the 256 MB
+    # last-level cache, so no step finds its inputs left in the cache by the step before
+    R = max(1, args.rotate)
+    tcs = [torch.from_numpy(coords).cuda() for _ in range(R)]
+    tes = [torch.from_numpy(elems).cuda() for _ in range(R)]
     tf = torch.from_numpy(faces).cuda()
     fb = L.fallback(1e-3 * h ** 3, 1e6, True)
     stream = torch.cuda.current_stream()
-
-    if args.copy_calib_mib:
-        nbytes = args.copy_calib_mib << 20
-        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    _calib_copy(args.copy_calib_mib)
 
     quad = args.coef == "quad"
+    cqs = []
     if quad:  # coefficient values at the integration points: inputs resident in HBM before the clock
-        xq = L.quad_points(tc, te, 2)
-        cq = torch.exp(xq.sum(dim=2)).to(torch.float32).contiguous()
-        del xq
+        for k in range(R):
+            xq = L.quad_points(tcs[k], tes[k], 2)
+            cqs.append(torch.exp(xq.sum(dim=2)).to(dt_val).contiguous())
+            del xq
     csr = L.Csr()
-    csr.symbolic(3, nn, te)
+    csr.symbolic(3, nn, tes[0])
     _, nnz, _, _ = csr.info()
-    valsK = torch.empty(nnz, dtype=torch.float32, device="cuda")
-    valsM = torch.empty(nnz, dtype=torch.float32, device="cuda")
-    unit = torch.empty(nf * 3, dtype=torch.float32, device="cuda")
-    area = torch.empty(nf, dtype=torch.float32, device="cuda")
+    valsK = torch.empty(nnz, dtype=dt_val, device="cuda")
+    valsM = torch.empty(nnz, dtype=dt_val, device="cuda")
+    unit = torch.empty(nf * 3, dtype=dt_val, device="cuda")
+    area = torch.empty(nf, dtype=dt_val, device="cuda")
     ctr = torch.zeros(4, dtype=torch.int64, device="cuda")
 
-    def step(ev=None):
+    def numeric(k):
+        if quad:
+            csr.assemble_quad(prec, tcs[k], 2, valsK, valsM, cKq=cqs[k], cMq=cqs[k], fb=fb, counters=ctr,
+                              stream=stream)
+        else:
+            csr.assemble(prec, tcs[k], tes[k], valsK, valsM, fb=fb, counters=ctr, stream=stream)
+
+    def step(k, ev=None):
         if ev:
             ev[0].record(stream)
-        csr.symbolic(3, nn, te, stream=stream)
+        csr.symbolic(3, nn, tes[k], stream=stream)
         if ev:
             ev[1].record(stream)
-        if quad:
-            csr.assemble_quad(L.F32, tc, 2, valsK, valsM, cKq=cq, cMq=cq, fb=fb, counters=ctr, stream=stream)
-        else:
-            csr.assemble(L.F32, tc, te, valsK, valsM, fb=fb, counters=ctr, stream=stream)
+        numeric(k)
         if ev:
             ev[2].record(stream)
-        L.boundary_normals(L.F32, tc, tf, unit=unit, measure=area, stream=stream)
+        L.boundary_normals(prec, tcs[k], tf, unit=unit, measure=area, stream=stream)
         if ev:
             ev[3].record(stream)
 
-    for _ in range(args.warmup):
-        step()
+    for w in range(args.warmup):
+        step(w % R)
     torch.cuda.synchronize()
     ctr.zero_()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
@@ -844,47 +1123,67 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(evs[k])
+        step(k % R, evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     stage_ms, stage_calls = csr.stage_times()
+    csr.set_timing(False)
     sym = np.array([e[0].elapsed_time(e[1]) for e in evs])
     num = np.array([e[1].elapsed_time(e[2]) for e in evs])
     bnd = np.array([e[2].elapsed_time(e[3]) for e in evs])
     routed = int(ctr[0].item()) // max(args.steps, 1)
     bad = int(ctr[2].item())
+    step_out = (valsK.cpu().numpy(), valsM.cpu().numpy(), csr.structure())
+
+    # the numeric phase alone on the resident structure (the roofline's kernel): a 1 GiB
+    # buffer is overwritten between repetitions, outside the events
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    reps = max(args.steps, 5)
+    tn = []
+    for r in range(reps):
+        _flush(flush)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        numeric(r % R)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        tn.append(e0.elapsed_time(e1))
+    tn = np.array(tn)
+    del flush
 
     ms_step = wall * 1e3 / args.steps
     value = ne / (wall / args.steps)
     # algorithmic bytes of the numeric assembly kernel: elems (16 B/tet), FP64 coordinates
-    # (24 B/node), FP32 K and M values (8 B/nonzero); with quadrature also the FP32
-    # coefficients at 4 points for K and for M (32 B/tet)
-    alg_num = 16 * ne + 24 * nn + 8 * nnz + (32 * ne if quad else 0)
-    # whole step: numeric + the structure written once (row_ptr, col_idx) + boundary faces
-    # (12 B of indices and 16 B of FP32 outputs per face; their coordinates are counted above)
-    alg_step = alg_num + 4 * (nn + 1) + 4 * nnz + nf * (12 + 16)
-    num_ms = float(num.mean())
-    phases = {"symbolic_ms": round(float(sym.mean()), 4), "numeric_ms": round(num_ms, 4),
-              "boundary_ms": round(float(bnd.mean()), 4)}
-    # per-kernel launch durations (HIP events on the launch stream) and algorithmic bytes
-    # per launch; the symbolic stages are timed inside pf_csr_symbolic (pf_csr_stage_times)
-    kname = "k_numeric<3,float%s>" % (",QN=4" if quad else "")
-    kernels = {
-        "k_scatter": (stage_ms["adjacency"] / stage_calls, 16 * ne + 16 * ne + 4 * nn),
-        "k_pattern<4>": (stage_ms["pattern"] / stage_calls, 16 * ne + 16 * ne + 16 * ne + 4 * nnz + 4 * nn),
-        "k_row_offsets": (stage_ms["row offsets"] / stage_calls, 12 * nn + 8 * nnz),
-        kname: (num_ms, alg_num),
-    }
-
-    def roofline(name):
-        ms, alg = kernels[name]
-        gbs = alg / (ms * 1e-3) / 1e9
-        tr = None if quad else traffic_of(TRAFFIC_FILE, KERNEL_SOURCES, kernel=name.split(" ")[0], n=n)
-        return {"kernel": name, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": gbs / HBM_PEAK_GBS, "traffic": tr, "algorithmic_bytes_per_launch": alg,
-                "launch_us": round(ms * 1e3, 1)}
-
-    dominant = max(kernels, key=lambda k: kernels[k][0])
+    # (24 B/node), K and M values (2 x es B/nonzero); with quadrature also the coefficients at
+    # 4 points for K and for M (8 es B/tet)
+    alg_num = 16 * ne + 24 * nn + 2 * es * nnz + (8 * es * ne if quad else 0)
+    # symbolic phase: the method's bytes are the connectivity read and the structure written
+    alg_sym = 16 * ne + 4 * (nn + 1) + 4 * nnz
+    # whole step: numeric + the structure written once + boundary faces (12 B of indices and
+    # 4 es B of outputs per face)
+    alg_step = alg_num + 4 * (nn + 1) + 4 * nnz + nf * (12 + 4 * es)
+    num_ms = float(np.median(tn))
+    sym_ms = float(sym.mean())
+    phases = {"symbolic_ms": round(sym_ms, 4), "numeric_ms": round(float(num.mean()), 4),
+              "boundary_ms": round(float(bnd.mean()), 4), "numeric_flushed_ms_median": round(num_ms, 4),
+              "numeric_flushed_ms_p10": round(float(np.percentile(tn, 10)), 4),
+              "numeric_flushed_ms_p90": round(float(np.percentile(tn, 90)), 4)}
+    kname = ("k_numeric<3,double>" if f64 else "k_numeric32<3>") + (" (QN=4)" if quad else "")
+    stage_names = {"adjacency": "k_scatter", "pattern": "k_pattern<4>", "row offsets": "k_row_offsets"}
+    kernels_us = {stage_names.get(k, k): round(v / stage_calls * 1e3, 1) for k, v in stage_ms.items()}
+    kernels_us[kname] = round(num_ms * 1e3, 1)
+    gbs = alg_num / (num_ms * 1e-3) / 1e9
+    tr = None if (quad or f64) else traffic_of(TRAFFIC_FILE, KERNEL_SOURCES, kernel=kname, n=n)
+    roof = {"kernel": kname, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": tr, "algorithmic_bytes_per_launch": alg_num,
+            "launch_us": round(num_ms * 1e3, 1),
+            "bytes": "16 B/tet (elems) + 24 B/node (FP64 coords) + %d B/nonzero (K, M)%s"
+                     % (2 * es, " + 8 coefficients/tet" if quad else "")}
+    sgbs = alg_sym / (sym_ms * 1e-3) / 1e9
+    roof_sym = {"phase": "symbolic (k_scatter + k_pattern + k_row_offsets)", "bound": "hbm", "achieved": sgbs,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": sgbs / HBM_PEAK_GBS,
+                "algorithmic_bytes": alg_sym, "ms": round(sym_ms, 4),
+                "bytes": "16 B/tet (elems read) + 4 B/row (row_ptr) + 4 B/nonzero (col_idx) written"}
     # the paper's level-7 cube (2,146,689 nodes, 12,582,912 tets), K + M with c = exp(x1+x2+x3)
     # at quadrature points: 66.6 s + 20.4 s in MATLAB (hardware not stated)
     paper_tets_per_s = 12582912 / (66.6 + 20.4)
@@ -901,46 +1200,55 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": vs,
-        "dtype": "f32",
+        "dtype": "f64" if f64 else "f32",
         "data": "synthetic",
-        "config": {"workload": "3-D P1 tets, FP32 bulk with FP64 fallback: unit cube, %d^3 cubes x 6 Kuhn tets, "
-                               "jitter 0.15 h; K + M CSR assembly (symbolic + numeric) and boundary normals/areas%s"
-                               % (n, "; c_K = c_M = exp(x1+x2+x3) at the 4 points of the degree-2 rule" if quad else
-                                  ""),
+        "config": {"workload": "3-D P1 tets, %s: unit cube, %d^3 cubes x 6 Kuhn tets, jitter 0.15 h; K + M CSR "
+                               "assembly (symbolic + numeric) and boundary normals/areas%s"
+                               % ("FP64" if f64 else "FP32 bulk with FP64 fallback", n,
+                                  "; c_K = c_M = exp(x1+x2+x3) at the 4 points of the degree-2 rule" if quad else ""),
                    "tets": ne, "nodes": nn, "nnz": int(nnz), "boundary_faces": nf,
-                   "fallback": "det < 1e-3 h^3 or det-condition > 1e6 -> FP64", "coords": "f64"},
+                   "fallback": None if f64 else "det < 1e-3 h^3 or det-condition > 1e6 -> FP64", "coords": "f64",
+                   "input_sets_rotated": R},
         "hbm_gbps_step": alg_step / (ms_step * 1e-3) / 1e9,
         "phases_ms": phases,
         "numeric_tets_per_s": ne / (num_ms * 1e-3),
         "routed_per_step": routed,
         "bad_index": bad,
-        "kernels_us": {k: round(v[0] * 1e3, 1) for k, v in kernels.items()},
-        "roofline": roofline(dominant),
-        "roofline_numeric": roofline(kname),
+        "kernels_us": kernels_us,
+        "roofline": roof,
+        "roofline_symbolic": roof_sym,
         "paper_context": {"what": "MATLAB page-function library, 3-D P1 K and M at 2,146,689 nodes (level 7), "
                                   "hardware not stated, c = exp(x1+x2+x3) with quadrature",
                           "K_s": 66.6, "M_s": 20.4},
     }
 
     if not args.no_cpu_baseline:
-        import oracle
+        hi = host_info()
         cn = args.cpu_n
-        c2, e2, _ = gen.cube_mesh(cn, jitter=0.15, with_faces=False)
-        t1 = time.perf_counter()
+        c2, e2, _ = (coords, elems, None) if cn == n else gen.cube_mesh(cn, jitter=0.15, with_faces=False)
+        q2 = None
         if quad:  # coefficients at the integration points are inputs, as on the GPU side
-            xq2 = oracle.quad_points(c2, e2, 2)
-            cq2 = np.exp(xq2.sum(axis=2))
-            t1 = time.perf_counter()
-            el = oracle.p1_elements_q(c2, e2, 2, cq2, cq2)
-        else:
-            el = oracle.p1_elements(c2, e2)
-        oracle.assemble(e2, c2.shape[0], el["Ke"], el["Me"], el["Kabs"])
-        dt = time.perf_counter() - t1
-        out["cpu_baseline"] = {"value": e2.shape[0] / dt, "unit": "tets/s", "cores": 1, "kind": "oracle",
-                               "sample": "FP64 oracle (element matrices%s + stable-sort sparse assembly of K and M, "
-                                         "single thread) on the %d^3 Kuhn mesh, %d tets, %.1f s"
-                                         % (" with coefficients at the integration points" if quad else "", cn,
-                                            e2.shape[0], dt)}
+            import oracle
+            q2 = np.exp(oracle.quad_points(c2, e2, 2).sum(axis=2))
+        rate1, dt1, ref = oracle_p1_rate(c2, e2, 1, q2)
+        rateT, dtT, _ = oracle_p1_rate(c2, e2, hi["threads"], q2) if hi["threads"] > 1 else (rate1, dt1, None)
+        out["cpu_baseline"] = {
+            "value": rateT, "unit": "tets/s", "cores": hi["threads"], "kind": "oracle",
+            "sample": "FP64 oracle (element matrices%s + stable-sort sparse assembly of K and M) on the %d^3 Kuhn "
+                      "mesh, %d tets: %d threads on contiguous element chunks, chunk matrices summed, %.2f s; "
+                      "one thread on the whole mesh %.1f s"
+                      % (" with coefficients at the integration points" if quad else "", cn, e2.shape[0],
+                         hi["threads"], dtT, dt1),
+            "single_core": {"value": rate1, "cores": 1, "seconds": round(dt1, 2)},
+            "host": hi}
+        if cn == n:  # the step's results against the oracle's (every nonzero)
+            vk, vm, (rp, ci) = step_out
+            tol = 1e-12 if f64 else 1e-5
+            out["errors_vs_oracle"] = {
+                "structure_identical": bool(np.array_equal(rp.cpu().numpy(), ref["row_ptr"]) and
+                                            np.array_equal(ci.cpu().numpy(), ref["col_idx"])),
+                "K": value_errors(vk, {"val": ref["valK"], "scale": ref["scaleK"]}, tol),
+                "M": value_errors(vm, {"val": ref["valM"], "scale": ref["scaleM"]}, tol)}
     print(json.dumps(out))
     csr.close()
 
