@@ -65,6 +65,10 @@ struct pf_csr {
     // the pattern, after the row offsets)
     bool timing = false, pending = false;
     int64_t* hinfo = nullptr;  // pinned host words for the status readbacks (allocated once)
+    hipEvent_t ready = nullptr;  // recorded after the status readback of an enqueued build
+    bool enqueued = false;       // a build was enqueued and not yet finished
+    int q_dim = 0, q_nlb = 0;    // ... and its shape
+    int64_t q_nn = 0, q_ne = 0;
     hipEvent_t ev[PF_CSR_STAGES + 1] = {};
     double stage_ms[PF_CSR_STAGES] = {};
     int64_t stage_calls = 0;
@@ -320,213 +324,6 @@ __device__ __forceinline__ int upper_pos(const int32_t* v, int n, int32_t x) {
         else hi = mid;
     }
     return lo;
-}
-
-// One pass per block of RR rows: insert, rank, and write (a) each row's length, (b) the
-// block's sorted columns, row after row, at the start of its own region of RR * MAXROW
-// words of colblk (moved to col_idx once the row lengths are scanned; a contiguous run, so
-// both moves are coalesced), (c) the packed slots pk of every adjacency entry (bits 0-1
-// local index a, bits 2+8k .. 9+8k row position of the k-th other node of the element, in
-// local order).  A row with elements holds its own node (the diagonal), which is entered once
-// before the entries, so each entry inserts only the element's other nodes.  The table slot
-// of every inserted node is kept per entry in LDS and ranking labels each used table slot
-// with its column position, so pk needs no second gather of the element and no second
-// table lookup.
-template <int NLB>
-__global__ __launch_bounds__(RT) void k_pattern(int64_t nn, const int32_t* __restrict__ elems,
-                                                const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
-                                                int32_t* __restrict__ rowlen, int32_t* __restrict__ colblk,
-                                                uint32_t* __restrict__ pk, int32_t* __restrict__ dpos,
-                                                int64_t* __restrict__ info) {
-    constexpr int NO = NLB - 1;               // other nodes of an element
-    __shared__ int32_t tab[RR * RSUB];       // node ids, -1 empty
-    __shared__ int32_t guard[RT];            // never -1: the first probes of empty items
-    __shared__ int32_t seg[RR * MAXROW];      // each row's nodes, insertion order
-    __shared__ int32_t srt[RR * MAXROW];      // the block's columns in CSR order
-    __shared__ uint8_t seg_h[RR * MAXROW];    // table slot of each list item
-    __shared__ uint8_t slot_rank[RR * RSUB];  // rank (column position) of each used table slot
-    __shared__ uint32_t eslot[RR * MAXADJ];   // per item: a | table slot of other node k << (2 + 6k)
-    __shared__ int32_t cnt[RR];
-    __shared__ int32_t cpre[RR + 1];
-    __shared__ int32_t alen[RR];
-    __shared__ int32_t maxl;
-    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RR;
-    const int nr = static_cast<int>((r0 + RR < nn) ? RR : nn - r0);
-    const int64_t e0 = r0 * MAXADJ;  // the block's adjacency rows start here (padded layout)
-    // the first batch of entries is read together with the row lengths (padded rows: every
-    // entry below MAXADJ of a row of the matrix is in bounds; entries past a row's length are
-    // dropped once the lengths are known), so the element gathers wait for one round trip
-    static_assert(RT * RBATCH / RR <= MAXADJ, "the first batch lies inside the padded rows");
-    int32_t apre[RBATCH];
-#pragma unroll
-    for (int b = 0; b < RBATCH; ++b) {
-        const int idx = static_cast<int>(threadIdx.x) + b * RT;
-        const int r = idx % RR, j = idx / RR;
-        apre[b] = adj[e0 + (r < nr ? r : 0) * MAXADJ + j];
-    }
-    const int32_t lpre = adj_len[r0 + (static_cast<int>(threadIdx.x) < nr ? threadIdx.x : 0)];
-    for (int h = threadIdx.x; h < RR * RSUB; h += RT) tab[h] = -1;
-    guard[threadIdx.x] = -2;
-    if (threadIdx.x == 0) maxl = 0;
-    __syncthreads();
-    if (threadIdx.x < RR) {
-        const int r = threadIdx.x;
-        const int L = r < nr ? min(lpre, MAXADJ) : 0;  // longer rows raised an error already
-        alen[r] = L;
-        cnt[r] = 0;
-        if (r < nr && L == 0) dpos[r0 + r] = 0;  // a node of no element has an empty row
-        if (L > 0) {  // the diagonal
-            const int32_t self = static_cast<int32_t>(r0 + r);
-            const int h = rsub_hash(self);
-            tab[r * RSUB + h] = self;
-            seg_h[r * MAXROW] = static_cast<uint8_t>(h);
-            seg[r * MAXROW] = self;
-            cnt[r] = 1;
-            atomicMax(&maxl, L);
-        }
-    }
-    bool bad = false;
-    __syncthreads();
-    // entry j of row r is item r + RR j; rows past the end of the matrix are empty
-    static_assert((RR & (RR - 1)) == 0, "RR is a power of two");
-    const int items = RR * maxl;
-    for (int base = threadIdx.x; base < items; base += RT * RBATCH) {
-        int nd[RBATCH][4];
-        int rq[RBATCH], tq[RBATCH];  // row, and block-local entry index r * MAXADJ + j
-        int32_t aq[RBATCH];
-        // loads without branches (an empty item reads entry 0 and element 0, and is dropped),
-        // so all of them are in flight together
-        const bool first = base == static_cast<int>(threadIdx.x);
-#pragma unroll
-        for (int b = 0; b < RBATCH; ++b) {
-            const int idx = base + b * RT;
-            const int r = idx % RR, j = idx / RR;
-            const bool ok = idx < items && j < alen[r];
-            rq[b] = ok ? r : -1;
-            tq[b] = ok ? r * MAXADJ + j : 0;
-            aq[b] = first ? apre[b] : adj[e0 + tq[b]];
-        }
-#pragma unroll
-        for (int b = 0; b < RBATCH; ++b) aq[b] = rq[b] >= 0 ? aq[b] : 0;
-        if (NLB == 4 && (reinterpret_cast<uintptr_t>(elems) & 15) == 0) {
-#pragma unroll
-            for (int b = 0; b < RBATCH; ++b) {
-                const int4 v = *reinterpret_cast<const int4*>(elems + static_cast<int64_t>(aq[b] >> 2) * 4);
-                nd[b][0] = v.x;
-                nd[b][1] = v.y;
-                nd[b][2] = v.z;
-                nd[b][3] = v.w;
-            }
-        } else {
-#pragma unroll
-            for (int b = 0; b < RBATCH; ++b)
-#pragma unroll
-                for (int k = 0; k < NLB; ++k) nd[b][k] = elems[static_cast<int64_t>(aq[b] >> 2) * NLB + k];
-        }
-        // the first probe of every insert of the lane, all in flight together; an empty item
-        // probes the lane's own guard word (never -1, so nothing is stored)
-        int32_t ov[RBATCH][NO], cq[RBATCH][NO];
-        int hq[RBATCH][NO];
-#pragma unroll
-        for (int b = 0; b < RBATCH; ++b) {
-            const int a = aq[b] & 3;
-#pragma unroll
-            for (int k = 0; k < NO; ++k) {
-                ov[b][k] = k < a ? nd[b][k] : nd[b][k + 1];
-                hq[b][k] = rsub_hash(ov[b][k]);
-                int32_t* w = rq[b] >= 0 ? tab + rq[b] * RSUB + hq[b][k] : guard + threadIdx.x;
-                cq[b][k] = atomicCAS(w, -1, ov[b][k]);
-            }
-        }
-#pragma unroll
-        for (int b = 0; b < RBATCH; ++b) {
-            const int r = rq[b];
-            if (r < 0) continue;
-            int32_t* rt = tab + r * RSUB;
-            uint32_t word = static_cast<uint32_t>(aq[b] & 3);
-#pragma unroll
-            for (int k = 0; k < NO; ++k) {
-                const int32_t v = ov[b][k];
-                int h = hq[b][k];
-                int32_t cur = cq[b][k];
-#pragma unroll 1
-                for (int probe = 1; cur != -1 && cur != v; ++probe) {  // taken: linear probing
-                    if (probe == RSUB) {
-                        h = -1;
-                        break;
-                    }
-                    h = (h + 1) & (RSUB - 1);
-                    cur = atomicCAS(rt + h, -1, v);
-                }
-                if (h < 0) {
-                    bad = true;
-                    continue;
-                }
-                word |= static_cast<uint32_t>(h) << (2 + 6 * k);
-                if (cur == -1) {
-                    const int p = atomicAdd(cnt + r, 1);
-                    if (p < MAXROW) {
-                        seg[r * MAXROW + p] = v;
-                        seg_h[r * MAXROW + p] = static_cast<uint8_t>(h);
-                    } else {
-                        bad = true;
-                    }
-                }
-            }
-            eslot[base + b * RT] = word;  // by item: consecutive lanes, consecutive words
-        }
-    }
-    if (bad) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
-    __syncthreads();
-    // rank every row list (ascending node id): padded columns and row lengths
-    if (threadIdx.x < 64) {  // exclusive prefix of the (capped) row counts in wave 0
-        const int lane = threadIdx.x;
-        const int v = lane < nr ? min(cnt[lane], MAXROW) : 0;
-        int x = v;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int y = __shfl_up(x, d, 64);
-            if (lane >= d) x += y;
-        }
-        if (lane < nr) cpre[lane] = x - v;
-        if (lane == nr - 1) cpre[nr] = x;
-    }
-    if (threadIdx.x < nr) rowlen[r0 + threadIdx.x] = cnt[threadIdx.x] <= MAXROW ? cnt[threadIdx.x] : 0;
-    __syncthreads();
-    for (int q = threadIdx.x; q < cpre[nr]; q += RT) {
-        const int r = upper_pos(cpre, nr, q);
-        const int p = q - cpre[r];
-        const int n = min(cnt[r], MAXROW);
-        const int32_t v = seg[r * MAXROW + p];
-        int rank = 0;
-        const int32_t* sr = seg + r * MAXROW;
-        int j = 0;
-        for (; j + 4 <= n; j += 4) {  // four independent LDS reads per step
-            const int32_t a0 = sr[j], a1 = sr[j + 1], a2 = sr[j + 2], a3 = sr[j + 3];
-            rank += (a0 < v) + (a1 < v) + (a2 < v) + (a3 < v);
-        }
-        for (; j < n; ++j) rank += sr[j] < v;
-        slot_rank[r * RSUB + seg_h[r * MAXROW + p]] = static_cast<uint8_t>(rank);
-        if (p == 0) dpos[r0 + r] = rank;  // item 0 is the row's own node
-        srt[cpre[r] + rank] = v;
-    }
-    __syncthreads();
-    int32_t* dst = colblk + static_cast<int64_t>(blockIdx.x) * (RR * MAXROW);
-    for (int q = threadIdx.x; q < cpre[nr]; q += RT) dst[q] = srt[q];
-    // packed slots of every adjacency entry from its kept table slots (row-interleaved)
-    for (int idx = threadIdx.x; idx < items; idx += RT) {
-        const int r = idx % RR, j = idx / RR;
-        if (j >= alen[r]) continue;
-        const int t = r * MAXADJ + j;
-        const uint32_t w = eslot[idx];
-        uint32_t word = w & 3;
-#pragma unroll
-        for (int k = 0; k < NO; ++k) {
-            const int h = static_cast<int>((w >> (2 + 6 * k)) & (RSUB - 1));
-            word |= static_cast<uint32_t>(slot_rank[r * RSUB + h]) << (2 + 8 * k);
-        }
-        pk[e0 + t] = word;
-    }
 }
 
 // ---------------------------------------------------------------------------- P2 row pattern
@@ -985,6 +782,216 @@ __global__ __launch_bounds__(SBS) void k_row_stats(int64_t tiles, const int32_t*
         for (int w = 1; w < SBS / 64; ++w) x = max(x, red[c][w]);
         constexpr int slot[6] = {3, 4, 5, 7, 8, 9};
         info[slot[c]] = x;
+    }
+}
+
+// ---------------------------------------------------------------------------- P1 rows
+// The row pattern of a P1 mesh and its row offsets in one pass.  A block of PR = 32 rows and
+// 256 threads: thread t owns row t % 32 (its adjacency entries t / 32 + 8 q and its distinct
+// nodes t / 32 + 8 u), so no phase leaves lanes idle on per-row work.  Every entry enters the
+// element's other nodes into its row's 64-slot LDS table (one compare-and-swap per probe, the
+// first probes of a batch of entries issued together); the first inserter of a node appends it
+// to the row's list; a row's own node is entered once, by the thread holding its first entry.
+// Each list item's rank (ascending node id) is its column position.  The block writes the row
+// lengths, the diagonal positions, every 8-row group's sorted columns at the start of the
+// group's region of 8 x 64 words of colblk (the layout k_row_offsets moves into col_idx once
+// the lengths are scanned), and the packed slot words pk of every adjacency entry (bits 0-1
+// local index, bits 2+8k .. 9+8k column position of the k-th other node, in local order).
+constexpr int PR = 32;            // rows per block
+constexpr int PT = 256;           // threads per block
+constexpr int PJ = PT / PR;       // threads per row
+constexpr int PS = MAXROW + 1;    // LDS stride of a row's table (odd: rows fall in different banks)
+constexpr int PL = MAXROW + 4;    // LDS stride of a row's list (16-byte rows for four-word reads)
+constexpr int PB = 3;             // entries per thread per batch (all loads of a batch in flight)
+constexpr int PQ = MAXADJ / PJ;   // entries per thread at most
+static_assert(PT % PR == 0 && PQ * PJ == MAXADJ && MAXROW == 64 && PR % RR == 0, "row-block shape");
+
+template <int NLB>
+__global__ __launch_bounds__(PT) void k_rows_p1(int64_t nn, const int32_t* __restrict__ elems,
+                                                const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
+                                                int32_t* __restrict__ rowlen, int32_t* __restrict__ colblk,
+                                                uint32_t* __restrict__ pk, int32_t* __restrict__ dpos,
+                                                int64_t* __restrict__ info) {
+    constexpr int NO = NLB - 1;        // other nodes of an element
+    constexpr int NC = PB * NO;        // inserts of a batch
+    static_assert(NC <= 32, "a batch's inserts fit one mask word");
+    __shared__ int32_t tab[PR * PS];               // node ids, -1 empty
+    __shared__ __align__(16) int32_t lst[PR * PL];  // each row's distinct nodes, insertion order
+    __shared__ uint8_t lsth[PR * PL];              // table slot of each list item
+    __shared__ uint8_t srank[PR * PS];             // column position of each used table slot
+    __shared__ int32_t cnt[PR];
+    __shared__ int32_t cpre[PR + 1];
+    __shared__ int32_t guard[PT];                  // never -1: the first probes of empty entries
+    const int t = static_cast<int>(threadIdx.x);
+    for (int h = t; h < PR * PS; h += PT) tab[h] = -1;
+    if (t < PR) cnt[t] = 0;
+    guard[t] = -2;
+    __syncthreads();
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * PR;
+    const int nr = static_cast<int>((r0 + PR < nn) ? PR : nn - r0);
+    const int r = t % PR, jt = t / PR;
+    const int64_t row = r0 + (r < nr ? r : nr - 1);  // in bounds for the loads of rows past the end
+    const int32_t self = static_cast<int32_t>(r0 + r);
+    const int L = r < nr ? min(adj_len[row], MAXADJ) : 0;  // longer lists raised an error already
+    int32_t* rt = tab + r * PS;
+    int32_t* rl = lst + r * PL;
+    uint8_t* rh = lsth + r * PL;
+    bool bad = false;
+
+    // rare path: linear probing from slot h after a first probe that found another node
+    auto probe_on = [&](int32_t v, int h, int32_t& cur) -> int {
+#pragma unroll 1
+        for (int probe = 1; cur != -1 && cur != v; ++probe) {
+            if (probe == MAXROW) return -1;
+            h = (h + 1) & (MAXROW - 1);
+            cur = atomicCAS(rt + h, -1, v);
+        }
+        return h;
+    };
+    if (jt == 0 && L > 0) {  // the diagonal
+        const int h0 = rsub_hash(self);
+        int32_t cur = atomicCAS(rt + h0, -1, self);
+        const int h = probe_on(self, h0, cur);
+        bad = bad || h < 0;
+        if (h >= 0 && cur == -1) {
+            const int p = atomicAdd(cnt + r, 1);
+            if (p < MAXROW) {
+                rl[p] = self;
+                rh[p] = static_cast<uint8_t>(h);
+            }
+        }
+    }
+    uint32_t iw[PQ];  // per entry: local index | table slot of the k-th other node << (2 + 6k)
+#pragma unroll
+    for (int q0 = 0; q0 < PQ; q0 += PB) {
+        if (jt + q0 * PJ >= L) break;
+        int32_t aq[PB];
+        int nd[PB][4];
+        bool okq[PB];
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {  // loads without branches: an empty entry reads entry 0 and is dropped
+            const int q = q0 + i;
+            const int j = jt + q * PJ;
+            okq[i] = q < PQ && j < L;
+            aq[i] = adj[row * MAXADJ + (okq[i] ? j : 0)];
+        }
+#pragma unroll
+        for (int i = 0; i < PB; ++i) aq[i] = okq[i] ? aq[i] : 0;
+        if (NLB == 4 && (reinterpret_cast<uintptr_t>(elems) & 15) == 0) {
+#pragma unroll
+            for (int i = 0; i < PB; ++i) {
+                const int4 v = *reinterpret_cast<const int4*>(elems + static_cast<int64_t>(aq[i] >> 2) * 4);
+                nd[i][0] = v.x;
+                nd[i][1] = v.y;
+                nd[i][2] = v.z;
+                nd[i][3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < PB; ++i)
+#pragma unroll
+                for (int k = 0; k < NLB; ++k) nd[i][k] = elems[static_cast<int64_t>(aq[i] >> 2) * NLB + k];
+        }
+        // the first probe of every insert of the batch, all in flight together; an empty entry
+        // probes the thread's own guard word (never -1, so nothing is stored)
+        int32_t ov[NC], cq[NC];
+        int hq[NC];
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            const int a = aq[i] & 3;
+#pragma unroll
+            for (int k = 0; k < NO; ++k) {
+                const int c = i * NO + k;
+                ov[c] = k < a ? nd[i][k] : nd[i][k + 1];
+                hq[c] = rsub_hash(ov[c]);
+                cq[c] = atomicCAS(okq[i] ? rt + hq[c] : guard + t, -1, ov[c]);
+            }
+        }
+        // most first probes find the node or an empty slot; the others probe on (rarely)
+        bool coll = false;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) coll = coll || (okq[c / NO] && cq[c] != -1 && cq[c] != ov[c]);
+        if (__any(coll)) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (okq[c / NO] && cq[c] != -1 && cq[c] != ov[c]) {
+                    hq[c] = probe_on(ov[c], hq[c], cq[c]);
+                    bad = bad || hq[c] < 0;
+                }
+            }
+        }
+        // the nodes this thread entered first go to the row's list: one atomic per batch
+        uint32_t fresh = 0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) fresh |= static_cast<uint32_t>(okq[c / NO] && cq[c] == -1 && hq[c] >= 0) << c;
+        if (fresh) {
+            const int base = atomicAdd(cnt + r, __popc(fresh));
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const int p = base + __popc(fresh & ((1u << c) - 1u));
+                if (((fresh >> c) & 1u) && p < MAXROW) {
+                    rl[p] = ov[c];
+                    rh[p] = static_cast<uint8_t>(hq[c]);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < PB; ++i) {
+            if (q0 + i >= PQ) break;
+            uint32_t w = static_cast<uint32_t>(aq[i] & 3);
+#pragma unroll
+            for (int k = 0; k < NO; ++k) w |= static_cast<uint32_t>(hq[i * NO + k] & (MAXROW - 1)) << (2 + 6 * k);
+            iw[q0 + i] = w;
+        }
+    }
+    __syncthreads();
+
+    // ranks: column position of every list item (four list words per LDS read)
+    const int n = min(cnt[r], MAXROW);
+    bad = bad || cnt[r] > MAXROW;
+    for (int k = jt; k < n; k += PJ) {
+        const int32_t v = rl[k];
+        int rank = 0;
+        for (int m = 0; m < n; m += 4) {
+            const int4 w = *reinterpret_cast<const int4*>(rl + m);  // words past n are stale: masked
+            rank += (w.x < v) + (m + 1 < n && w.y < v) + (m + 2 < n && w.z < v) + (m + 3 < n && w.w < v);
+        }
+        srank[r * PS + rh[k]] = static_cast<uint8_t>(rank);
+        if (v == self) dpos[r0 + r] = rank;
+    }
+    if (jt == 0 && r < nr && L == 0) dpos[r0 + r] = 0;  // a node of no element has an empty row
+    // row lengths, and each 8-row group's prefix (wave 0)
+    if (t < 64) {
+        const int lane = t;
+        const int v = lane < PR ? (lane < nr ? n : 0) : 0;
+        int x = v;
+#pragma unroll
+        for (int d = 1; d < RR; d <<= 1) {  // inclusive prefix inside each group of RR lanes
+            const int y = __shfl_up(x, d, 64);
+            if ((lane & (RR - 1)) >= d) x += y;
+        }
+        if (lane < PR) cpre[lane] = x - v;
+        if (lane < nr) rowlen[r0 + lane] = v;
+    }
+    if (bad) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
+    __syncthreads();
+    {
+        int32_t* dst = colblk + (r0 + (r & ~(RR - 1))) * MAXROW + cpre[r];  // the row's group region
+        for (int k = jt; k < n; k += PJ) dst[srank[r * PS + rh[k]]] = rl[k];
+    }
+    // packed slots of every adjacency entry from its kept table slots
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) {
+        const int j = jt + q * PJ;
+        if (j >= L) break;
+        const uint32_t w = iw[q];
+        uint32_t word = w & 3;
+#pragma unroll
+        for (int k = 0; k < NO; ++k) {
+            const int h = static_cast<int>((w >> (2 + 6 * k)) & (MAXROW - 1));
+            word |= static_cast<uint32_t>(srank[r * PS + h]) << (2 + 8 * k);
+        }
+        pk[row * MAXADJ + j] = word;
     }
 }
 
@@ -2217,6 +2224,7 @@ void pf_csr_destroy(pf_csr* c) {
         (void)hipFree(q);
     (void)hipFree(c->esign);
     (void)hipFree(c->finfo);
+    if (c->ready) (void)hipEventDestroy(c->ready);
     if (c->hinfo) (void)hipHostFree(c->hinfo);
     delete c;
 }
@@ -2265,14 +2273,18 @@ pf_status pf_csr_stage_times(pf_csr* c, double* ms, int64_t* calls) {
 
 namespace {
 // the structure of a P1 (nlb = dim + 1) or P2 (nlb = 6, 10) mesh
-pf_status symbolic(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const int32_t* elems, void* stream,
-                   const char* who) {
+pf_status symbolic_enqueue(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const int32_t* elems, void* stream,
+                           const char* who) {
     const bool p2 = nlb > dim + 1;
     const int maxrow = p2 ? MAXROW2 : MAXROW;
     if (nn >= INT32_MAX || ne * nlb >= INT32_MAX || ne >= (int64_t(1) << (p2 ? 27 : 29)))
         return fail(PF_ELIMIT, std::string(who) + ": mesh too large for 32-bit indices");
     if (ne > 0 && !elems) return fail(PF_EINVAL, std::string(who) + ": null elems");
     hipStream_t s = as_stream(stream);
+    if (c->enqueued) {  // an unfinished earlier build: its status is dropped
+        PF_HIP_TRY(hipEventSynchronize(c->ready));
+        c->enqueued = false;
+    }
     c->built = false;
     c->faces_built = false;
     const int64_t m = ne * nlb;
@@ -2280,7 +2292,6 @@ pf_status symbolic(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const in
     if ((st = collect_stage_times(c))) return st;  // the previous call's events are reused below
     if ((st = grow(c->adj_len, c->cap_adj_len, nn + 1))) return st;
     if ((st = grow(c->row_ptr, c->cap_row_ptr, nn + 1))) return st;
-    if ((st = grow(c->cnt, c->cap_cnt, nn + 1))) return st;
     if ((st = grow(c->adj, c->cap_adj, nn * MAXADJ))) return st;
     if (p2) {
         if ((st = grow(c->pk2, c->cap_pk2, nn * MAXADJ))) return st;
@@ -2302,55 +2313,78 @@ pf_status symbolic(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const in
             hipLaunchKernelGGL(k_scatter<2>, dim3(gtile), dim3(AG_BS), 0, s, elems, m, nlb, nn, c->adj_len, c->adj,
                                c->info);
     }
-    const int64_t grows = ceil_div(nn, RR);
-    const int64_t tiles = ceil_div(nn, SCAN_TILE);
-    // nnz is known only after the pattern: col_idx holds maxrow columns per row
-    // (P2 pattern blocks of 16 rows write the regions of 8-row groups 2b and 2b + 1)
-    const int64_t regions = p2 ? 2 * ceil_div(nn, RR2) : grows;
-    if ((st = grow(c->colblk, c->cap_colblk, std::max<int64_t>(regions * RR * maxrow, 1)))) return st;
-    if ((st = grow(c->col_idx, c->cap_nnz, std::max<int64_t>(nn * maxrow, 1)))) return st;
     if ((st = grow(c->dpos, c->cap_dpos, nn + 1))) return st;
-    // tile descriptors, then TSTAT int32 statistics per tile
-    if ((st = grow(c->look, c->cap_look, (1 + TSTAT / 2) * std::max<int64_t>(tiles, 1) + 1))) return st;
-    if ((st = mark(c, 1, s))) return st;
-    if (nn > 0) {
-        const unsigned g = static_cast<unsigned>(grows);
-        const unsigned g2 = static_cast<unsigned>(ceil_div(nn, RR2));  // P2: 16-row blocks
-        if (nlb == 10)
-            hipLaunchKernelGGL((k_pattern_p2<10>), dim3(g2), dim3(RT2), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
-                               c->colblk, c->pk2, c->dpos, c->info);
-        else if (nlb == 6)
-            hipLaunchKernelGGL((k_pattern_p2<6>), dim3(g2), dim3(RT2), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
-                               c->colblk, c->pk2, c->dpos, c->info);
-        else if (nlb == 4)
-            hipLaunchKernelGGL((k_pattern<4>), dim3(g), dim3(RT), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
-                               c->colblk, c->pk, c->dpos, c->info);
-        else
-            hipLaunchKernelGGL((k_pattern<3>), dim3(g), dim3(RT), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
-                               c->colblk, c->pk, c->dpos, c->info);
-    }
-    if ((st = mark(c, 2, s))) return st;
-    if (nn > 0) {
-        hipLaunchKernelGGL(k_fill_i64, dim3(flat_grid(tiles)), dim3(SBS), 0, s, reinterpret_cast<int64_t*>(c->look),
-                           tiles, int64_t(0));
-        int32_t* tstat = reinterpret_cast<int32_t*>(c->look + ((tiles + 1) & ~int64_t(1)));  // 16-byte aligned
-        if (p2)
-            hipLaunchKernelGGL((k_row_offsets<RR * MAXROW2, 4>), dim3(static_cast<unsigned>(tiles)), dim3(SBS), 0, s, nn,
-                               c->cnt, c->adj_len, c->colblk, c->row_ptr, c->col_idx, c->look, tstat, c->info);
-        else
-            hipLaunchKernelGGL((k_row_offsets<RR * MAXROW, 2>), dim3(static_cast<unsigned>(tiles)), dim3(SBS), 0, s, nn,
-                               c->cnt, c->adj_len, c->colblk, c->row_ptr, c->col_idx, c->look, tstat, c->info);
-        hipLaunchKernelGGL(k_row_stats, dim3(1), dim3(SBS), 0, s, tiles, tstat, c->info);
-    } else {
-        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, c->row_ptr, int64_t(1), 0);
-    }
-    if ((st = mark(c, 3, s))) return st;
-    if ((st = launch_check(who))) return st;
-    c->pending = c->timing;
     if (!c->hinfo) PF_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hinfo), INFO_WORDS * sizeof(int64_t)));
     int64_t* info = c->hinfo;  // pinned: a direct copy, no staging through pageable memory
-    PF_HIP_TRY(hipMemcpyAsync(info, c->info, INFO_WORDS * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    PF_HIP_TRY(hipStreamSynchronize(s));
+    {
+        const int64_t tiles = ceil_div(nn, SCAN_TILE);
+        // nnz is known only after the pattern: col_idx holds maxrow columns per row, and every
+        // 8-row group's sorted columns wait at the start of its region of colblk (P1 pattern
+        // blocks of 32 rows write 4 groups; P2 blocks of 16 rows write groups 2b and 2b + 1)
+        const int64_t regions = p2 ? 2 * ceil_div(nn, RR2) : (PR / RR) * ceil_div(nn, PR);
+        if ((st = grow(c->cnt, c->cap_cnt, nn + 1))) return st;
+        if ((st = grow(c->colblk, c->cap_colblk, std::max<int64_t>(regions * RR * maxrow, 1)))) return st;
+        if ((st = grow(c->col_idx, c->cap_nnz, std::max<int64_t>(nn * maxrow, 1)))) return st;
+        // tile descriptors, then TSTAT int32 statistics per tile
+        if ((st = grow(c->look, c->cap_look, (1 + TSTAT / 2) * std::max<int64_t>(tiles, 1) + 1))) return st;
+        if ((st = mark(c, 1, s))) return st;
+        if (nn > 0) {
+            const unsigned g1 = static_cast<unsigned>(ceil_div(nn, PR));   // P1: 32-row blocks
+            const unsigned g2 = static_cast<unsigned>(ceil_div(nn, RR2));  // P2: 16-row blocks
+            if (nlb == 10)
+                hipLaunchKernelGGL((k_pattern_p2<10>), dim3(g2), dim3(RT2), 0, s, nn, elems, c->adj_len, c->adj,
+                                   c->cnt, c->colblk, c->pk2, c->dpos, c->info);
+            else if (nlb == 6)
+                hipLaunchKernelGGL((k_pattern_p2<6>), dim3(g2), dim3(RT2), 0, s, nn, elems, c->adj_len, c->adj,
+                                   c->cnt, c->colblk, c->pk2, c->dpos, c->info);
+            else if (nlb == 4)
+                hipLaunchKernelGGL((k_rows_p1<4>), dim3(g1), dim3(PT), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
+                                   c->colblk, c->pk, c->dpos, c->info);
+            else
+                hipLaunchKernelGGL((k_rows_p1<3>), dim3(g1), dim3(PT), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
+                                   c->colblk, c->pk, c->dpos, c->info);
+        }
+        if ((st = mark(c, 2, s))) return st;
+        if (nn > 0) {
+            hipLaunchKernelGGL(k_fill_i64, dim3(flat_grid(tiles)), dim3(SBS), 0, s, reinterpret_cast<int64_t*>(c->look),
+                               tiles, int64_t(0));
+            int32_t* tstat = reinterpret_cast<int32_t*>(c->look + ((tiles + 1) & ~int64_t(1)));  // 16-byte aligned
+            if (p2)
+                hipLaunchKernelGGL((k_row_offsets<RR * MAXROW2, 4>), dim3(static_cast<unsigned>(tiles)), dim3(SBS), 0,
+                                   s, nn, c->cnt, c->adj_len, c->colblk, c->row_ptr, c->col_idx, c->look, tstat,
+                                   c->info);
+            else
+                hipLaunchKernelGGL((k_row_offsets<RR * MAXROW, 2>), dim3(static_cast<unsigned>(tiles)), dim3(SBS), 0,
+                                   s, nn, c->cnt, c->adj_len, c->colblk, c->row_ptr, c->col_idx, c->look, tstat,
+                                   c->info);
+            hipLaunchKernelGGL(k_row_stats, dim3(1), dim3(SBS), 0, s, tiles, tstat, c->info);
+        } else {
+            hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, c->row_ptr, int64_t(1), 0);
+        }
+        if ((st = mark(c, 3, s))) return st;
+        if ((st = launch_check(who))) return st;
+        c->pending = c->timing;
+        PF_HIP_TRY(hipMemcpyAsync(info, c->info, INFO_WORDS * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        if (!c->ready) PF_HIP_TRY(hipEventCreateWithFlags(&c->ready, hipEventDisableTiming));
+        PF_HIP_TRY(hipEventRecord(c->ready, s));
+    }
+    c->enqueued = true;
+    c->q_dim = dim;
+    c->q_nlb = nlb;
+    c->q_nn = nn;
+    c->q_ne = ne;
+    return PF_OK;
+}
+
+// the second half of a build: its status words have reached the host (the ready event has
+// completed); check them and fix the structure's sizes and launch statistics
+pf_status symbolic_finish(pf_csr* c, const char* who) {
+    c->enqueued = false;
+    const int64_t* info = c->hinfo;
+    const int dim = c->q_dim, nlb = c->q_nlb;
+    const int64_t nn = c->q_nn, ne = c->q_ne;
+    const bool p2 = nlb > dim + 1;
+    const int maxrow = p2 ? MAXROW2 : MAXROW;
     if (info[0] & ERR_INDEX) return fail(PF_EINDEX, std::string(who) + ": node index out of range in elems");
     if (info[0] & ERR_ROW)
         return fail(PF_ELIMIT, std::string(who) + ": a node belongs to more than 64 elements or a row has more than " +
@@ -2373,6 +2407,45 @@ pf_status symbolic(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const in
     c->built = true;
     return PF_OK;
 }
+
+pf_status symbolic(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const int32_t* elems, void* stream,
+                   const char* who) {
+    pf_status st = symbolic_enqueue(c, dim, nlb, nn, ne, elems, stream, who);
+    if (st != PF_OK) return st;
+    PF_HIP_TRY(hipEventSynchronize(c->ready));
+    return symbolic_finish(c, who);
+}
+}  // namespace
+
+}  // extern "C"
+
+namespace pf {
+pf_status csr_symbolic_enqueue(pf_csr* c, int dim, int64_t nn, int64_t ne, const int32_t* elems, hipStream_t s) {
+    if (dim != 2 && dim != 3) return fail(PF_EORDER, "pf_server: dim must be 2 or 3");
+    return symbolic_enqueue(c, dim, dim + 1, nn, ne, elems, s, "pf_server build");
+}
+
+int csr_symbolic_poll(pf_csr* c, pf_status* st) {
+    if (!c->enqueued) {
+        *st = c->built ? PF_OK : fail(PF_ESTATE, "pf_server build: nothing enqueued");
+        return 1;
+    }
+    const hipError_t e = hipEventQuery(c->ready);
+    if (e == hipErrorNotReady) return 0;
+    if (e != hipSuccess) {
+        c->enqueued = false;
+        *st = fail(PF_EHIP, std::string("pf_server build: ") + hipGetErrorString(e));
+        return 1;
+    }
+    *st = symbolic_finish(c, "pf_server build");
+    return 1;
+}
+
+}  // namespace pf
+
+extern "C" {
+
+namespace {
 }  // namespace
 
 pf_status pf_csr_symbolic(pf_csr* c, int dim, int64_t nn, int64_t ne, const int32_t* elems, void* stream) {
