@@ -470,45 +470,65 @@ pf_status pf_plan_info(const pf_plan* plan, int64_t* ntiles, int32_t* grid, int3
 void pf_plan_destroy(pf_plan* plan);
 
 /* ----------------------------------------------------------------------------------
- * Serving loop: assembly jobs (the section 3.6 K and M of one P1 mesh each) submitted
- * from host memory are admitted by a device-memory budget and a slot limit, and every
- * scheduler tick runs the numeric phase of all jobs admitted in that tick as one
- * launch per (dimension, precision) class.  Meshes with the same non-zero topology key
- * share their connectivity and CSR structure, which stay resident (least recently used
- * structures are evicted when the budget needs room).
+ * Serving loop: assembly jobs (the section 3.6 K and M of one P1 mesh each) and page-op jobs
+ * (the section 2.3-2.4 page-wise inverse with determinant and page product of one batch of
+ * pages each), submitted from host memory, are admitted by a device-memory budget and a
+ * slot limit.  Every scheduler tick runs the numeric phase of all assembly jobs that are
+ * ready in that tick as one launch per (dimension, precision, rows-per-block) class, and
+ * all page-op jobs admitted in that tick as one persistent batch-plan launch per precision
+ * (the mixed-order plan of pf_plan_run, replayed from its HIP graph).  Meshes with the same
+ * non-zero topology key share their connectivity and CSR structure, which stay resident
+ * (least recently used structures are evicted when the budget needs room); a new structure
+ * is built on a stream of its own while the scheduler goes on admitting, launching and
+ * completing other jobs, and its jobs join the tick in which the build has finished.
  *
  * A server owns one scheduler thread and one HIP stream on the device that is current
- * when it is created.  Per job: host-to-device copy of the coordinates (and of the
+ * when it is created.  Per assembly job: host-to-device copy of the coordinates (and of the
  * connectivity plus the symbolic phase when the topology is not resident), the numeric
- * phase, then the device-to-host copy of the values when output buffers are given.
- * Times are seconds on the server clock (pf_server_now, steady clock, 0 at creation).
- * Latency = end of the numeric phase - arrival; the copy back is reported apart.
- * Job values are bitwise those of pf_csr_symbolic + pf_assemble on the same mesh, alone
- * or in any batch.  Coefficients are 1 (no cK/cM).
+ * phase, then the device-to-host copy of the values when output buffers are given.  Per
+ * page-op job: copies of its pages in, the batched page operations, copies of the results
+ * out.  Times are seconds on the server clock (pf_server_now, steady clock, 0 at creation).
+ * Latency = end of the job's compute launch - arrival; the copy back is reported apart.
+ * Assembly values are bitwise those of pf_csr_symbolic + pf_assemble on the same mesh, and
+ * page results bitwise those of the same pages in a plan of their own, alone or in any
+ * batch.  Assembly coefficients are 1 (no cK/cM); page jobs are routed with the default
+ * fallback (tau_abs 0, tau_cond 1e6) and report routed = -1 (their pages share the launch's
+ * counters).
  * ---------------------------------------------------------------------------------- */
 typedef struct pf_server pf_server;
 
 enum { PF_SERVER_NOFUSE = 1, PF_SERVER_NOCACHE = 2 };
+enum { PF_JOB_ASSEMBLY = 0, PF_JOB_PAGES = 1 };
 
 typedef struct {
-    int32_t dim;             /* 2 (triangles) or 3 (tetrahedra)                               */
+    int32_t dim;             /* assembly: 2 (triangles) or 3 (tetrahedra)                      */
     int32_t prec;            /* pf_dtype of the arithmetic and of the values                  */
-    int64_t nn, ne;          /* nodes, elements (both > 0)                                     */
-    const double* coords;    /* HOST nn x dim, row-major (pinned memory: asynchronous copy)    */
-    const int32_t* elems;    /* HOST ne x (dim+1), 0-based                                     */
-    uint64_t topology;       /* non-zero: jobs with equal keys have identical elems            */
+    int64_t nn, ne;          /* assembly: nodes, elements (both > 0)                           */
+    const double* coords;    /* assembly: HOST nn x dim, row-major (pinned: asynchronous copy) */
+    const int32_t* elems;    /* assembly: HOST ne x (dim+1), 0-based                           */
+    uint64_t topology;       /* assembly: non-zero: jobs with equal keys have identical elems  */
     double arrival;          /* arrival time on the server clock; < 0: the time of submission   */
-    pf_fallback fb;          /* routing of FP32 jobs                                           */
-    void* valsK;             /* HOST output, nullable: nnz values of K in CSR order            */
-    void* valsM;             /* HOST output, nullable: nnz values of M                         */
-    int64_t vals_cap;        /* capacity of valsK / valsM in values (PF_ELIMIT if nnz exceeds) */
+    pf_fallback fb;          /* assembly: routing of FP32 jobs                                 */
+    void* valsK;             /* assembly: HOST output, nullable: nnz values of K in CSR order  */
+    void* valsM;             /* assembly: HOST output, nullable: nnz values of M               */
+    int64_t vals_cap;        /* assembly: capacity of valsK / valsM in values (PF_ELIMIT if nnz exceeds) */
+    int32_t kind;            /* PF_JOB_ASSEMBLY (0, the fields above) or PF_JOB_PAGES (below)  */
+    int32_t order;           /* pages: n, 1..4                                                 */
+    int32_t ops;             /* pages: PF_OP_INV and/or PF_OP_MTIMES                           */
+    int32_t reserved;        /* 0                                                              */
+    int64_t count;           /* pages: number of pages (> 0)                                   */
+    const void* a;           /* pages: HOST count n x n pages A (paper layout), type prec      */
+    const void* b;           /* pages: HOST count pages B (PF_OP_MTIMES), else ignored         */
+    void* x;                 /* pages: HOST output inv(A) (PF_OP_INV), nullable                */
+    void* c;                 /* pages: HOST output A*B (PF_OP_MTIMES), nullable                */
+    void* det;               /* pages: HOST output det(A) (PF_OP_INV), nullable                */
 } pf_job;
 
 typedef struct {
     int32_t status;          /* pf_status of the job (valid once done)                       */
     int32_t done;            /* 1 once the job has finished (values copied back)              */
-    int64_t nnz;             /* nonzeros of the job's CSR structure                           */
-    int64_t routed;          /* elements recomputed in FP64                                   */
+    int64_t nnz;             /* nonzeros of the job's CSR structure (0 for page-op jobs)      */
+    int64_t routed;          /* elements recomputed in FP64 (-1 for page-op jobs)             */
     double arrival, admitted, finished, copied;  /* server clock                             */
 } pf_job_result;
 
@@ -521,6 +541,8 @@ typedef struct {
     double first_arrival, last_finish; /* server clock                                        */
     double jobs_per_s, elements_per_s; /* completed work over [first_arrival, last_finish]    */
     int64_t hbm_in_use, hbm_high_water;  /* accounted device bytes                            */
+    int64_t pages;                     /* pages of the completed page-op jobs                  */
+    double pages_per_s;                /* over [first_arrival, last_finish]                     */
 } pf_stats;
 
 /* Create a server with a device-memory budget (bytes of job inputs, outputs and resident

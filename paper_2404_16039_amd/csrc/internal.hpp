@@ -63,6 +63,12 @@ bool csr_view(const pf_csr* c, CsrView* v);  // false unless built
 constexpr int CSR_MAXADJ = 64;
 const int32_t* csr_adj(const pf_csr* c);
 const int32_t* csr_adj_len(const pf_csr* c);
+// asynchronous structure build (the serving loop): csr_symbolic_enqueue issues every step of
+// pf_csr_symbolic on stream s without waiting; csr_symbolic_poll returns 1 once the build's
+// status words have reached the host (*st: its outcome, the structure usable if PF_OK), 0
+// while it runs
+pf_status csr_symbolic_enqueue(pf_csr* c, int dim, int64_t nn, int64_t ne, const int32_t* elems, hipStream_t s);
+int csr_symbolic_poll(pf_csr* c, pf_status* st);
 // a device workspace of at least `words` doubles owned by the handle (grown when needed)
 pf_status csr_workspace(pf_csr* c, int64_t words, double** out);
 

@@ -1,12 +1,16 @@
-// server.hip -- serving loop for assembly jobs: admission by a device-memory budget and a
-// slot limit, resident connectivity and CSR structures keyed by topology, and one fused
-// numeric launch per (dimension, precision, rows-per-block) class in every scheduler tick.
+// server.hip -- serving loop for assembly jobs and page-op jobs: admission by a
+// device-memory budget and a slot limit, resident connectivity and CSR structures keyed by
+// topology and built without stopping the scheduler, one fused numeric launch per
+// (dimension, precision, rows-per-block) class and one batch-plan launch per precision for
+// the page-op jobs in every scheduler tick.
 //
 // The scheduler thread owns every HIP call of the server (one compute stream plus one
-// stream for structure builds, which synchronise).  Public calls only touch host state
-// under the server mutex.  Job lifecycle:
-//   pending --admit--> in flight (inputs copied, numeric launched, copy-back queued)
-//           --numeric event--> finished (latency taken) --copy event--> done (memory freed)
+// stream for structure builds).  Public calls only touch host state under the server mutex.
+// Job lifecycle:
+//   pending --admit--> waiting for its structure (assembly jobs whose structure is being
+//   built; the build is polled every tick) --ready--> in flight (inputs copied, compute
+//   launched, copy-back queued) --compute event--> finished (latency taken) --copy event-->
+//   done (memory freed)
 #include "internal.hpp"
 
 #include <algorithm>
@@ -36,7 +40,8 @@ struct Topo {
     size_t bytes = 0;  // accounted device bytes (estimate until built)
     int refs = 0;
     uint64_t last_use = 0;
-    bool built = false;
+    enum { NEW, BUILDING, BUILT, FAILED } state = NEW;
+    pf_status status = PF_OK;  // of a failed build
     bool cached = false;
 };
 
@@ -57,13 +62,15 @@ struct SJob {
     void* d_valsK = nullptr;
     void* d_valsM = nullptr;
     int64_t* d_ctr = nullptr;
+    void* d_pg = nullptr;  // page-op jobs: A, B, inv(A), A*B and det(A) in one allocation
     int slot = -1;  // row of the pinned counter block
     size_t bytes = 0;
-    int stage = 0;  // 0 pending, 1 in flight, 2 numeric done, 3 done
+    int stage = 0;  // 0 pending, 1 waiting or in flight, 2 compute done, 3 done
     std::shared_ptr<TickEvents> ev;
 };
 
 size_t elem_bytes(int32_t prec) { return prec == PF_F32 ? 4 : 8; }
+bool is_pages(const pf_job& j) { return j.kind == PF_JOB_PAGES; }
 
 // upper bound of the nonzeros before the structure is built
 int64_t nnz_bound(const pf_job& j) {
@@ -72,6 +79,7 @@ int64_t nnz_bound(const pf_job& j) {
 }
 
 size_t topo_estimate(const pf_job& j) {
+    if (is_pages(j)) return 0;
     const int64_t nlb = j.dim + 1;
     return static_cast<size_t>(j.ne * nlb * 4)                                     // elems
            + static_cast<size_t>(16 * (j.nn + 1) + 512 * j.nn)  // row arrays, padded adjacency and slot words
@@ -80,7 +88,31 @@ size_t topo_estimate(const pf_job& j) {
            + static_cast<size_t>(j.nn / 256) + 4096;
 }
 
+// the device arrays of a page-op job, in one allocation: A, then B, inv(A), A*B (each
+// count n^2 values, present when the ops need them), then det(A); offsets in values
+struct PageLayout {
+    int64_t a, b, x, c, det, total;
+};
+PageLayout page_layout(const pf_job& j) {
+    const int64_t pg = j.count * j.order * j.order;
+    PageLayout L{};
+    int64_t o = 0;
+    L.a = o;
+    o += pg;
+    L.b = (j.ops & PF_OP_MTIMES) ? o : -1;
+    o += (j.ops & PF_OP_MTIMES) ? pg : 0;
+    L.x = (j.ops & PF_OP_INV) ? o : -1;
+    o += (j.ops & PF_OP_INV) ? pg : 0;
+    L.c = (j.ops & PF_OP_MTIMES) ? o : -1;
+    o += (j.ops & PF_OP_MTIMES) ? pg : 0;
+    L.det = (j.ops & PF_OP_INV) ? o : -1;
+    o += (j.ops & PF_OP_INV) ? j.count : 0;
+    L.total = o;
+    return L;
+}
+
 size_t job_estimate(const pf_job& j, int64_t nnz) {
+    if (is_pages(j)) return static_cast<size_t>(page_layout(j).total) * elem_bytes(j.prec) + 256;
     return static_cast<size_t>(j.nn * j.dim * 8) + 2 * static_cast<size_t>(nnz) * elem_bytes(j.prec) + 64;
 }
 
@@ -96,6 +128,7 @@ struct pf_server {
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<SJob*> pending;
+    std::vector<SJob*> waiting;  // admitted assembly jobs whose structure is being built
     std::vector<SJob*> active;
     std::unordered_map<uint64_t, std::unique_ptr<SJob>> jobs;
     std::map<uint64_t, Topo*> cache;
@@ -113,6 +146,8 @@ struct pf_server {
     hipEvent_t tab_ev[RING] = {};
     bool tab_used[RING] = {};
     int ring = 0;
+    pf_plan* plans[2][RING] = {};  // page-op jobs: per precision, a ring of batch plans
+    int pring[2] = {0, 0};
     int64_t* h_ctr = nullptr;  // pinned, 4 per slot
     std::vector<int> free_slots;
     std::thread th;
@@ -166,21 +201,40 @@ Topo* topo_for(pf_server* S, SJob* j, size_t& extra, bool& cacheable) {
     return nullptr;
 }
 
-pf_status build_topo(pf_server* S, SJob* j, Topo* t) {
+// start the build of a job's structure on the build stream (connectivity copied in, the
+// symbolic phase enqueued); its end is found by poll_build
+pf_status start_build(pf_server* S, SJob* j, Topo* t) {
     const pf_job& q = j->spec;
     const size_t eb = static_cast<size_t>(q.ne * (q.dim + 1)) * 4;
+    t->state = Topo::BUILDING;
     PF_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&t->d_elems), eb));
     PF_HIP_TRY(hipMemcpyAsync(t->d_elems, q.elems, eb, hipMemcpyHostToDevice, S->sbuild));
     pf_status st = pf_csr_create(&t->csr);
     if (st != PF_OK) return st;
-    st = pf_csr_symbolic(t->csr, q.dim, q.nn, q.ne, t->d_elems, S->sbuild);  // synchronises sbuild
-    if (st != PF_OK) return st;
-    const size_t exact = eb + csr_bytes(t->csr);
+    return csr_symbolic_enqueue(t->csr, q.dim, q.nn, q.ne, t->d_elems, S->sbuild);
+}
+
+// a building structure whose status has reached the host becomes BUILT (exact bytes
+// accounted) or FAILED; returns whether its state changed
+bool poll_build(pf_server* S, Topo* t) {
+    if (t->state != Topo::BUILDING) return false;
+    pf_status st;
+    if (!csr_symbolic_poll(t->csr, &st)) return false;
     std::lock_guard<std::mutex> lk(S->mu);
-    account(S, static_cast<long long>(exact) - static_cast<long long>(t->bytes));
-    t->bytes = exact;
-    t->built = true;
-    return PF_OK;
+    if (st == PF_OK) {
+        const size_t exact = static_cast<size_t>(t->ne * (t->dim + 1)) * 4 + csr_bytes(t->csr);
+        account(S, static_cast<long long>(exact) - static_cast<long long>(t->bytes));
+        t->bytes = exact;
+        t->state = Topo::BUILT;
+    } else {
+        t->state = Topo::FAILED;
+        t->status = st;
+        if (t->cached) {  // a failed build never serves another job
+            S->cache.erase(t->key);
+            t->cached = false;
+        }
+    }
+    return true;
 }
 
 void finish(pf_server* S, SJob* j, pf_status status) {
@@ -191,7 +245,8 @@ void finish(pf_server* S, SJob* j, pf_status status) {
     --S->unfinished;
     if (status == PF_OK) {
         ++S->st.completed;
-        S->st.elements += j->spec.ne;
+        if (is_pages(j->spec)) S->st.pages += j->spec.count;
+        else S->st.elements += j->spec.ne;
         S->lat.push_back(j->res.finished - j->res.arrival);
         if (S->st.completed == 1 || j->res.arrival < S->st.first_arrival) S->st.first_arrival = j->res.arrival;
         S->st.last_finish = std::max(S->st.last_finish, j->res.finished);
@@ -202,20 +257,22 @@ void finish(pf_server* S, SJob* j, pf_status status) {
 
 // release a job's device memory (stream-ordered) and its structure reference
 void release(pf_server* S, SJob* j) {
-    if (j->d_coords) (void)hipFreeAsync(j->d_coords, S->s);
-    if (j->d_valsK) (void)hipFreeAsync(j->d_valsK, S->s);
-    if (j->d_valsM) (void)hipFreeAsync(j->d_valsM, S->s);
-    if (j->d_ctr) (void)hipFreeAsync(j->d_ctr, S->s);
-    j->d_coords = nullptr;
-    j->d_valsK = j->d_valsM = nullptr;
-    j->d_ctr = nullptr;
+    for (void** p : {reinterpret_cast<void**>(&j->d_coords), &j->d_valsK, &j->d_valsM,
+                     reinterpret_cast<void**>(&j->d_ctr), &j->d_pg}) {
+        if (*p) (void)hipFreeAsync(*p, S->s);
+        *p = nullptr;
+    }
     account(S, -static_cast<long long>(j->bytes));
     j->bytes = 0;
     if (j->slot >= 0) S->free_slots.push_back(j->slot);
     j->slot = -1;
     if (Topo* t = j->topo) {
         --t->refs;
-        if (!t->cached && t->refs == 0) destroy_topo(S, t);
+        if (!t->cached && t->refs == 0) {
+            // a structure still building is destroyed once its build has ended
+            if (t->state == Topo::BUILDING) (void)hipStreamSynchronize(S->sbuild);
+            destroy_topo(S, t);
+        }
         j->topo = nullptr;
     }
 }
@@ -223,13 +280,14 @@ void release(pf_server* S, SJob* j) {
 // Stage 1 of a tick, under the lock: move admissible pending jobs into `batch`.
 void admit(pf_server* S, std::vector<SJob*>& batch) {
     const double t = S->now();
-    while (!S->pending.empty() && static_cast<int>(S->active.size() + batch.size()) < S->max_slots) {
+    while (!S->pending.empty() &&
+           static_cast<int>(S->active.size() + S->waiting.size() + batch.size()) < S->max_slots) {
         SJob* j = S->pending.front();
         if (j->res.arrival > t) break;  // not arrived yet (a pre-submitted trace)
         size_t extra = 0;
         bool cacheable = false;
-        Topo* hit = topo_for(S, j, extra, cacheable);
-        const int64_t nnz = (hit && hit->built) ? csr_nnz(hit->csr) : nnz_bound(j->spec);
+        Topo* hit = is_pages(j->spec) ? nullptr : topo_for(S, j, extra, cacheable);
+        const int64_t nnz = (hit && hit->state == Topo::BUILT) ? csr_nnz(hit->csr) : nnz_bound(j->spec);
         const size_t need = job_estimate(j->spec, nnz) + extra;
         if (S->used + need > S->budget) make_room(S, need);
         if (S->used + need > S->budget) break;  // head of the queue waits for memory
@@ -237,21 +295,23 @@ void admit(pf_server* S, std::vector<SJob*>& batch) {
         if (hit) {
             j->topo = hit;
             ++S->st.cache_hits;
-        } else {
-            Topo* t = new Topo();
-            t->key = j->spec.topology;
-            t->dim = j->spec.dim;
-            t->nn = j->spec.nn;
-            t->ne = j->spec.ne;
-            t->bytes = extra;
-            t->cached = cacheable;
+        } else if (!is_pages(j->spec)) {
+            Topo* tp = new Topo();
+            tp->key = j->spec.topology;
+            tp->dim = j->spec.dim;
+            tp->nn = j->spec.nn;
+            tp->ne = j->spec.ne;
+            tp->bytes = extra;
+            tp->cached = cacheable;
             account(S, static_cast<long long>(extra));
-            if (t->cached) S->cache[t->key] = t;
-            j->topo = t;
+            if (tp->cached) S->cache[tp->key] = tp;
+            j->topo = tp;
             ++S->st.cache_misses;
         }
-        j->topo->refs++;
-        j->topo->last_use = ++S->use_clock;
+        if (j->topo) {
+            j->topo->refs++;
+            j->topo->last_use = ++S->use_clock;
+        }
         j->bytes = job_estimate(j->spec, nnz);
         account(S, static_cast<long long>(j->bytes));
         j->slot = S->free_slots.back();
@@ -262,57 +322,65 @@ void admit(pf_server* S, std::vector<SJob*>& batch) {
     }
 }
 
-// Stage 2 of a tick, without the lock: structures, inputs, fused numeric launches, copies.
-// Returns the jobs that failed (with their status) so the caller can finish them.
 struct TickCounts {
     int64_t launches = 0, launched = 0;
 };
 
-void run_tick(pf_server* S, std::vector<SJob*>& batch, std::vector<std::pair<SJob*, pf_status>>& failed,
-              TickCounts& tc) {
-    std::vector<SJob*> ok;
-    for (SJob* j : batch) {
-        const pf_job& q = j->spec;
-        pf_status st = PF_OK;
-        Topo* t = j->topo;
-        if (!t->built) {
-            st = build_topo(S, j, t);
-            if (st != PF_OK) {
-                std::lock_guard<std::mutex> lk(S->mu);
-                if (t->cached) {  // a failed build never serves another job
-                    S->cache.erase(t->key);
-                    t->cached = false;
-                }
-            }
-        }
-        if (st == PF_OK) {
-            const int64_t nnz = csr_nnz(t->csr);
-            if ((q.valsK || q.valsM) && nnz > q.vals_cap) st = fail(PF_ELIMIT, "pf_server: vals_cap below nnz");
-            if (st == PF_OK) {
-                const size_t es = elem_bytes(q.prec);
-                const size_t exact = job_estimate(q, nnz);
-                {
-                    std::lock_guard<std::mutex> lk(S->mu);
-                    account(S, static_cast<long long>(exact) - static_cast<long long>(j->bytes));
-                    j->bytes = exact;
-                    j->res.nnz = nnz;
-                }
-                hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&j->d_coords), q.nn * q.dim * 8, S->s);
-                if (e == hipSuccess) e = hipMallocAsync(&j->d_valsK, std::max<size_t>(nnz * es, 16), S->s);
-                if (e == hipSuccess) e = hipMallocAsync(&j->d_valsM, std::max<size_t>(nnz * es, 16), S->s);
-                if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&j->d_ctr), 32, S->s);
-                if (e == hipSuccess)
-                    e = hipMemcpyAsync(j->d_coords, q.coords, q.nn * q.dim * 8, hipMemcpyHostToDevice, S->s);
-                if (e == hipSuccess) e = hipMemsetAsync(j->d_ctr, 0, 32, S->s);
-                if (e != hipSuccess)
-                    st = fail(e == hipErrorOutOfMemory ? PF_ENOMEM : PF_EHIP,
-                              std::string("pf_server: job inputs: ") + hipGetErrorString(e));
-            }
-        }
-        if (st == PF_OK) ok.push_back(j);
-        else failed.emplace_back(j, st);
+// inputs of a ready assembly job (values sized by its structure), or the error
+pf_status assembly_inputs(pf_server* S, SJob* j) {
+    const pf_job& q = j->spec;
+    const int64_t nnz = csr_nnz(j->topo->csr);
+    if ((q.valsK || q.valsM) && nnz > q.vals_cap) return fail(PF_ELIMIT, "pf_server: vals_cap below nnz");
+    const size_t es = elem_bytes(q.prec);
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        const size_t exact = job_estimate(q, nnz);
+        account(S, static_cast<long long>(exact) - static_cast<long long>(j->bytes));
+        j->bytes = exact;
+        j->res.nnz = nnz;
     }
-    if (ok.empty()) return;
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&j->d_coords), q.nn * q.dim * 8, S->s);
+    if (e == hipSuccess) e = hipMallocAsync(&j->d_valsK, std::max<size_t>(nnz * es, 16), S->s);
+    if (e == hipSuccess) e = hipMallocAsync(&j->d_valsM, std::max<size_t>(nnz * es, 16), S->s);
+    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&j->d_ctr), 32, S->s);
+    if (e == hipSuccess) e = hipMemcpyAsync(j->d_coords, q.coords, q.nn * q.dim * 8, hipMemcpyHostToDevice, S->s);
+    if (e == hipSuccess) e = hipMemsetAsync(j->d_ctr, 0, 32, S->s);
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? PF_ENOMEM : PF_EHIP,
+                    std::string("pf_server: job inputs: ") + hipGetErrorString(e));
+    return PF_OK;
+}
+
+// inputs of a page-op job: one device allocation, pages A (and B) copied in
+pf_status page_inputs(pf_server* S, SJob* j) {
+    const pf_job& q = j->spec;
+    const PageLayout L = page_layout(q);
+    const size_t es = elem_bytes(q.prec);
+    const size_t pg = static_cast<size_t>(q.count * q.order * q.order) * es;
+    hipError_t e = hipMallocAsync(&j->d_pg, static_cast<size_t>(L.total) * es, S->s);
+    char* base = static_cast<char*>(j->d_pg);
+    if (e == hipSuccess) e = hipMemcpyAsync(base + L.a * es, q.a, pg, hipMemcpyHostToDevice, S->s);
+    if (e == hipSuccess && L.b >= 0) e = hipMemcpyAsync(base + L.b * es, q.b, pg, hipMemcpyHostToDevice, S->s);
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? PF_ENOMEM : PF_EHIP,
+                    std::string("pf_server: page inputs: ") + hipGetErrorString(e));
+    j->res.nnz = 0;
+    j->res.routed = -1;
+    return PF_OK;
+}
+
+// Stage 2 of a tick, without the lock: inputs of the ready jobs, fused compute launches,
+// copies back.  Jobs that fail go to `failed` with their status.
+void run_tick(pf_server* S, std::vector<SJob*>& ready, std::vector<std::pair<SJob*, pf_status>>& failed,
+              TickCounts& tc) {
+    std::vector<SJob*> ok, pages;
+    for (SJob* j : ready) {
+        const pf_status st = is_pages(j->spec) ? page_inputs(S, j) : assembly_inputs(S, j);
+        if (st != PF_OK) failed.emplace_back(j, st);
+        else if (is_pages(j->spec)) pages.push_back(j);
+        else ok.push_back(j);
+    }
+    if (ok.empty() && pages.empty()) return;
     auto ev = std::make_shared<TickEvents>();
     (void)hipEventCreateWithFlags(&ev->num, hipEventDisableTiming);
     (void)hipEventCreateWithFlags(&ev->copy, hipEventDisableTiming);
@@ -328,7 +396,7 @@ void run_tick(pf_server* S, std::vector<SJob*>& batch, std::vector<std::pair<SJo
                 failed.emplace_back(j, st);
             }
         }
-    } else {
+    } else if (!ok.empty()) {
         // group by class, fill the ring's staging table, one copy, one launch per class
         const int r = S->ring;
         S->ring = (S->ring + 1) % RING;
@@ -377,13 +445,63 @@ void run_tick(pf_server* S, std::vector<SJob*>& batch, std::vector<std::pair<SJo
             ++tc.launches;
         }
     }
+    // page-op jobs: one batch-plan launch per precision (its graph replayed), or one plan
+    // launch per job without fusion
+    for (int pi = 0; pi < 2 && !pages.empty(); ++pi) {
+        const pf_dtype pr = pi == 0 ? PF_F32 : PF_F64;
+        std::vector<SJob*> js;
+        for (SJob* j : pages)
+            if (j->spec.prec == pr) js.push_back(j);
+        const size_t nfuse = (S->flags & PF_SERVER_NOFUSE) ? 1 : js.size();
+        for (size_t k0 = 0; k0 < js.size(); k0 += nfuse) {
+            const size_t k1 = std::min(js.size(), k0 + nfuse);
+            pf_plan*& plan = S->plans[pi][S->pring[pi]];
+            S->pring[pi] = (S->pring[pi] + 1) % RING;
+            pf_status st = plan ? PF_OK : pf_plan_create(pr, S->max_slots, nullptr, &plan);
+            std::vector<pf_group> gs;
+            for (size_t k = k0; k < k1; ++k) {
+                SJob* j = js[k];
+                const PageLayout L = page_layout(j->spec);
+                char* base = static_cast<char*>(j->d_pg);
+                const size_t es = elem_bytes(pr);
+                pf_group g{};
+                g.order = j->spec.order;
+                g.ops = j->spec.ops;
+                g.count = j->spec.count;
+                g.a = base + L.a * es;
+                g.b = L.b >= 0 ? base + L.b * es : nullptr;
+                g.x = L.x >= 0 ? base + L.x * es : nullptr;
+                g.c = L.c >= 0 ? base + L.c * es : nullptr;
+                g.det = L.det >= 0 ? base + L.det * es : nullptr;
+                gs.push_back(g);
+            }
+            if (st == PF_OK) st = pf_plan_set_groups(plan, gs.data(), static_cast<int32_t>(gs.size()));
+            if (st == PF_OK) st = pf_plan_run(plan, nullptr, S->s);
+            for (size_t k = k0; k < k1; ++k) {
+                if (st == PF_OK) launched.push_back(js[k]);
+                else failed.emplace_back(js[k], st);
+            }
+            ++tc.launches;
+        }
+    }
     (void)hipEventRecord(ev->num, S->s);
     for (SJob* j : launched) {
         const pf_job& q = j->spec;
-        const size_t bytes = static_cast<size_t>(j->res.nnz) * elem_bytes(q.prec);
-        if (q.valsK && bytes) (void)hipMemcpyAsync(q.valsK, j->d_valsK, bytes, hipMemcpyDeviceToHost, S->s);
-        if (q.valsM && bytes) (void)hipMemcpyAsync(q.valsM, j->d_valsM, bytes, hipMemcpyDeviceToHost, S->s);
-        (void)hipMemcpyAsync(S->h_ctr + 4 * j->slot, j->d_ctr, 32, hipMemcpyDeviceToHost, S->s);
+        const size_t es = elem_bytes(q.prec);
+        if (is_pages(q)) {
+            const PageLayout L = page_layout(q);
+            const char* base = static_cast<const char*>(j->d_pg);
+            const size_t pg = static_cast<size_t>(q.count * q.order * q.order) * es;
+            if (q.x && L.x >= 0) (void)hipMemcpyAsync(q.x, base + L.x * es, pg, hipMemcpyDeviceToHost, S->s);
+            if (q.c && L.c >= 0) (void)hipMemcpyAsync(q.c, base + L.c * es, pg, hipMemcpyDeviceToHost, S->s);
+            if (q.det && L.det >= 0)
+                (void)hipMemcpyAsync(q.det, base + L.det * es, q.count * es, hipMemcpyDeviceToHost, S->s);
+        } else {
+            const size_t bytes = static_cast<size_t>(j->res.nnz) * es;
+            if (q.valsK && bytes) (void)hipMemcpyAsync(q.valsK, j->d_valsK, bytes, hipMemcpyDeviceToHost, S->s);
+            if (q.valsM && bytes) (void)hipMemcpyAsync(q.valsM, j->d_valsM, bytes, hipMemcpyDeviceToHost, S->s);
+            (void)hipMemcpyAsync(S->h_ctr + 4 * j->slot, j->d_ctr, 32, hipMemcpyDeviceToHost, S->s);
+        }
         j->ev = ev;
     }
     (void)hipEventRecord(ev->copy, S->s);
@@ -392,27 +510,65 @@ void run_tick(pf_server* S, std::vector<SJob*>& batch, std::vector<std::pair<SJo
 
 void loop(pf_server* S) {
     (void)hipSetDevice(S->device);
-    std::vector<SJob*> batch;
+    std::vector<SJob*> batch, ready, still;
     std::vector<std::pair<SJob*, pf_status>> failed;
     for (;;) {
         batch.clear();
+        ready.clear();
         failed.clear();
         bool progress = false;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             if (S->stop && S->unfinished == 0) break;
-            if (S->pending.empty() && S->active.empty()) {
+            if (S->pending.empty() && S->active.empty() && S->waiting.empty()) {
                 S->cv_work.wait_for(lk, std::chrono::milliseconds(2));
                 continue;
             }
             admit(S, batch);
         }
-        if (!batch.empty()) {
+        // newly admitted jobs: page jobs and jobs with a built structure are ready now; a
+        // new structure starts building (at most one build per structure)
+        for (SJob* j : batch) {
+            if (is_pages(j->spec)) {
+                ready.push_back(j);
+                continue;
+            }
+            Topo* t = j->topo;
+            if (t->state == Topo::NEW) {
+                const pf_status st = start_build(S, j, t);
+                if (st != PF_OK) {
+                    std::lock_guard<std::mutex> lk(S->mu);
+                    t->state = Topo::FAILED;
+                    t->status = st;
+                    if (t->cached) {
+                        S->cache.erase(t->key);
+                        t->cached = false;
+                    }
+                }
+            }
+            if (t->state == Topo::BUILT) ready.push_back(j);
+            else if (t->state == Topo::FAILED) failed.emplace_back(j, t->status);
+            else S->waiting.push_back(j);
+        }
+        // structures whose build has ended release their waiting jobs
+        still.clear();
+        for (SJob* j : S->waiting) {
+            Topo* t = j->topo;
+            if (poll_build(S, t)) progress = true;
+            if (t->state == Topo::BUILT) ready.push_back(j);
+            else if (t->state == Topo::FAILED) failed.emplace_back(j, t->status);
+            else still.push_back(j);
+        }
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->waiting.swap(still);
+        }
+        if (!ready.empty()) {
             TickCounts tc;
-            run_tick(S, batch, failed, tc);
+            run_tick(S, ready, failed, tc);
             progress = true;
             std::lock_guard<std::mutex> lk(S->mu);
-            for (SJob* j : batch) S->active.push_back(j);
+            for (SJob* j : ready) S->active.push_back(j);
             ++S->st.ticks;
             S->st.launches += tc.launches;
             S->st.max_batch = std::max(S->st.max_batch, tc.launched);
@@ -437,7 +593,7 @@ void loop(pf_server* S) {
                 }
                 if (j->stage == 2 && hipEventQuery(j->ev->copy) == hipSuccess) {
                     j->res.copied = S->now();
-                    j->res.routed = S->h_ctr[4 * j->slot];
+                    if (!is_pages(j->spec)) j->res.routed = S->h_ctr[4 * j->slot];
                     release(S, j);
                     finish(S, j, PF_OK);
                     j->ev.reset();
@@ -456,8 +612,18 @@ void loop(pf_server* S) {
 
 pf_status check_job(const pf_job* q) {
     if (!q) return fail(PF_EINVAL, "pf_server_submit: job is NULL");
-    if (q->dim != 2 && q->dim != 3) return fail(PF_EORDER, "pf_server_submit: dim must be 2 or 3");
     if (q->prec != PF_F32 && q->prec != PF_F64) return fail(PF_EDTYPE, "pf_server_submit: prec");
+    if (q->kind == PF_JOB_PAGES) {
+        if (q->order < 1 || q->order > 4) return fail(PF_EORDER, "pf_server_submit: page order must be 1..4");
+        if (q->ops <= 0 || (q->ops & ~(PF_OP_INV | PF_OP_MTIMES)))
+            return fail(PF_EINVAL, "pf_server_submit: page ops must be PF_OP_INV and/or PF_OP_MTIMES");
+        if (q->count <= 0 || !q->a || ((q->ops & PF_OP_MTIMES) && !q->b))
+            return fail(PF_EINVAL, "pf_server_submit: empty page job or NULL host pages");
+        if (q->count >= (int64_t(1) << 40)) return fail(PF_ELIMIT, "pf_server_submit: too many pages");
+        return PF_OK;
+    }
+    if (q->kind != PF_JOB_ASSEMBLY) return fail(PF_EINVAL, "pf_server_submit: unknown job kind");
+    if (q->dim != 2 && q->dim != 3) return fail(PF_EORDER, "pf_server_submit: dim must be 2 or 3");
     if (q->nn <= 0 || q->ne <= 0 || !q->coords || !q->elems)
         return fail(PF_EINVAL, "pf_server_submit: empty mesh or NULL host arrays");
     if (q->vals_cap < 0) return fail(PF_EINVAL, "pf_server_submit: negative vals_cap");
@@ -586,6 +752,7 @@ pf_status pf_server_stats(pf_server* S, pf_stats* out) {
     const double span = out->last_finish - out->first_arrival;
     out->jobs_per_s = span > 0 ? out->completed / span : 0.0;
     out->elements_per_s = span > 0 ? out->elements / span : 0.0;
+    out->pages_per_s = span > 0 ? out->pages / span : 0.0;
     out->hbm_in_use = static_cast<int64_t>(S->used);
     out->hbm_high_water = static_cast<int64_t>(S->high);
     return PF_OK;
@@ -604,6 +771,9 @@ void pf_server_destroy(pf_server* S) {
     if (S->s) (void)hipStreamSynchronize(S->s);
     for (auto& kv : S->cache) destroy_topo(S, kv.second);
     S->cache.clear();
+    for (auto& ring : S->plans)
+        for (pf_plan* p : ring)
+            if (p) pf_plan_destroy(p);
     for (int r = 0; r < RING; ++r) {
         if (S->h_tab[r]) (void)hipHostFree(S->h_tab[r]);
         if (S->d_tab[r]) (void)hipFree(S->d_tab[r]);

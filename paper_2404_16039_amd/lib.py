@@ -78,7 +78,10 @@ class Schedule(C.Structure):
 class Job(C.Structure):
     _fields_ = [("dim", C.c_int32), ("prec", C.c_int32), ("nn", C.c_int64), ("ne", C.c_int64),
                 ("coords", C.c_void_p), ("elems", C.c_void_p), ("topology", C.c_uint64), ("arrival", C.c_double),
-                ("fb", Fallback), ("valsK", C.c_void_p), ("valsM", C.c_void_p), ("vals_cap", C.c_int64)]
+                ("fb", Fallback), ("valsK", C.c_void_p), ("valsM", C.c_void_p), ("vals_cap", C.c_int64),
+                ("kind", C.c_int32), ("order", C.c_int32), ("ops", C.c_int32), ("reserved", C.c_int32),
+                ("count", C.c_int64), ("a", C.c_void_p), ("b", C.c_void_p), ("x", C.c_void_p), ("c", C.c_void_p),
+                ("det", C.c_void_p)]
 
 
 class JobResult(C.Structure):
@@ -97,13 +100,14 @@ class Stats(C.Structure):
                 ("latency_p50", C.c_double), ("latency_p99", C.c_double), ("latency_mean", C.c_double),
                 ("latency_max", C.c_double), ("first_arrival", C.c_double), ("last_finish", C.c_double),
                 ("jobs_per_s", C.c_double), ("elements_per_s", C.c_double), ("hbm_in_use", C.c_int64),
-                ("hbm_high_water", C.c_int64)]
+                ("hbm_high_water", C.c_int64), ("pages", C.c_int64), ("pages_per_s", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 SERVER_NOFUSE, SERVER_NOCACHE = 1, 2
+JOB_ASSEMBLY, JOB_PAGES = 0, 1
 OP_INV, OP_MTIMES = 1, 2
 TUNE_CACHED, TUNE_FORCE, TUNE_DEFAULT = 0, 1, 2
 
@@ -581,8 +585,8 @@ def server_footprint(dim, prec, nn, ne):
 
 
 class Server:
-    """Owner of a pf_server handle: assembly jobs from host memory, admitted by a device
-    memory budget, batched per scheduler tick, with resident structures per topology."""
+    """Owner of a pf_server handle: assembly and page-op jobs from host memory, admitted by a
+    device memory budget, batched per scheduler tick, with resident structures per topology."""
 
     def __init__(self, hbm_budget, max_slots=256, flags=0):
         h = P()
@@ -604,6 +608,23 @@ class Server:
         t = C.c_uint64()
         _chk(_lib.pf_server_submit(self._h, C.byref(job), C.byref(t)), "pf_server_submit")
         self._keep[t.value] = (coords, elems, valsK, valsM)  # alive until the job is done
+        return t.value
+
+    def submit_pages(self, prec, order, ops, a, b=None, x=None, c=None, det=None, arrival=-1.0):
+        """A page-op job: count n x n pages a (and b) in host memory (paper layout); outputs
+        inv(a) into x, a*b into c, det(a) into det (host arrays, each nullable)."""
+        count = a.shape[0]
+        job = Job()
+        job.kind = JOB_PAGES
+        job.prec = int(prec)
+        job.order = int(order)
+        job.ops = int(ops)
+        job.count = int(count)
+        job.arrival = float(arrival)
+        job.a, job.b, job.x, job.c, job.det = (_host_ptr(v) for v in (a, b, x, c, det))
+        t = C.c_uint64()
+        _chk(_lib.pf_server_submit(self._h, C.byref(job), C.byref(t)), "pf_server_submit")
+        self._keep[t.value] = (a, b, x, c, det)
         return t.value
 
     def poll(self, ticket):

@@ -205,3 +205,104 @@ def test_poisson_trace(lib):
     assert 0 < s["latency_p50"] <= s["latency_p99"] <= s["latency_max"]
     assert s["jobs_per_s"] > 0 and s["elements"] == sum(m[1].shape[0] for m in meshes.values())
     srv.close()
+
+
+# page-op jobs: (prec, order, ops, count)
+PAGE_SPEC = [(0, 3, 3, 5000), (1, 2, 1, 777), (0, 4, 2, 1234), (1, 3, 3, 3000), (0, 1, 3, 99), (1, 4, 3, 2500)]
+
+
+def _page_job_arrays(prec, n, ops, count, sub):
+    dt = np.float32 if prec == 0 else np.float64
+    a = gen.page_batch(count, n, sub=sub).astype(dt)
+    b = gen.page_batch(count, n, stream=gen.STREAM_PAGES_B, sub=sub).astype(dt)
+    x = np.full((count, n * n), np.nan, dtype=dt) if ops & 1 else None
+    c = np.full((count, n * n), np.nan, dtype=dt) if ops & 2 else None
+    d = np.full(count, np.nan, dtype=dt) if ops & 1 else None
+    return a, (b if ops & 2 else None), x, c, d
+
+
+def _submit_pages(srv, spec, sub, arrival=-1.0):
+    prec, n, ops, count = spec
+    a, b, x, c, d = _page_job_arrays(prec, n, ops, count, sub)
+    t = srv.submit_pages(prec, n, ops, a, b=b, x=x, c=c, det=d, arrival=arrival)
+    return t, (a, b, x, c, d)
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_page_jobs_alone_and_in_a_mix(lib, flags):
+    """Page-op jobs (inverse with determinant, product; orders 1..4, FP32 and FP64) submitted
+    together with assembly jobs, all arriving in one tick: each page job's results are bitwise
+    those of the same job through a server of its own, and match the oracle."""
+    say("server page jobs", flags)
+    srv = lib.Server(1 << 30, 32, flags)
+    start = srv.now() + 0.05
+    mixed = []
+    for k, sp in enumerate(PAGE_SPEC):
+        mixed.append((sp, k) + _submit_pages(srv, sp, 300 + k, arrival=start))
+        if k % 2 == 0:  # assembly jobs in the same tick
+            dim, prec, n = SPEC[k]
+            c, e = _mesh(dim, n, k)
+            srv.submit(dim, prec, torch.from_numpy(c).pin_memory(), torch.from_numpy(e).pin_memory(),
+                       topology=2000 + k, arrival=start)
+    srv.drain()
+    s = srv.stats()
+    assert s["failed"] == 0 and s["completed"] == len(PAGE_SPEC) + (len(PAGE_SPEC) + 1) // 2
+    assert s["pages"] == sum(sp[3] for sp in PAGE_SPEC)
+    if flags == 0:  # one batch-plan launch per precision, plus the numeric classes
+        assert s["max_batch"] == s["completed"] and s["launches"] <= 2 + 4
+    srv.close()
+    for sp, k, t, (a, b, x, c, d) in mixed:
+        prec, n, ops, count = sp
+        alone = lib.Server(1 << 28, 2, flags)
+        t2, (a2, b2, x2, c2, d2) = _submit_pages(alone, sp, 300 + k)
+        r = alone.wait(t2)
+        assert r["status"] == 0 and r["routed"] == -1 and r["nnz"] == 0
+        alone.close()
+        for got, ref in ((x, x2), (c, c2), (d, d2)):
+            if got is not None:
+                assert np.array_equal(got, ref), f"page job {k} differs from alone"
+        tol = TOL[torch.float32 if prec == 0 else torch.float64]
+        a64 = a.astype(np.float64)
+        if ops & 1:
+            inv, sing, sc = oracle.page_inv(a64, n)
+            assert not sing.any()
+            within(x, inv, sc, tol, f"page job {k} inverse")
+            det, perm = oracle.page_det(a64, n)
+            within(d, det, perm, tol, f"page job {k} det")
+        if ops & 2:
+            cm, ab = oracle.page_mtimes(a64, b.astype(np.float64), n, n, n)
+            within(c, cm, ab, tol, f"page job {k} product")
+
+
+def test_shared_new_structure_built_once(lib):
+    """Jobs of one new topology arriving in one tick share one structure build (one miss,
+    the others hits) and get their own values; a build that fails (bad node id) fails every
+    job that shares it, and the server goes on."""
+    say("server shared build")
+    srv = lib.Server(1 << 29, 16)
+    start = srv.now() + 0.05
+    jobs = []
+    for k in range(3):
+        c, e = _mesh(3, 7, 400 + k)  # one connectivity, three jitters
+        cap = gen.kuhn_counts(7)["nnz"]
+        vk, vm = _outputs(cap, 0)
+        t = srv.submit(3, lib.F32, torch.from_numpy(c).pin_memory(), torch.from_numpy(e).pin_memory(),
+                       topology=555, arrival=start, valsK=vk, valsM=vm)
+        jobs.append((t, c, e, vk, vm))
+    c2, e2 = _mesh(2, 5, 9)
+    bad = e2.copy()
+    bad[2, 0] = -5
+    fails = [srv.submit(2, lib.F64, c2, bad, topology=666, arrival=start) for _ in range(2)]
+    srv.drain()
+    s = srv.stats()
+    assert s["cache_misses"] == 2 and s["cache_hits"] == 3, s
+    assert s["completed"] == 3 and s["failed"] == 2
+    for t, c, e, vk, vm in jobs:
+        assert srv.poll(t)["status"] == 0
+        ak, am, _, _ = _alone(lib, 3, lib.F32, c, e)
+        assert np.array_equal(vk.numpy(), ak) and np.array_equal(vm.numpy(), am)
+    for t in fails:
+        assert srv.poll(t)["status"] == 6
+    r = srv.wait(srv.submit(2, lib.F64, c2, e2, topology=666))  # the key builds again, correctly
+    assert r["status"] == 0
+    srv.close()
