@@ -103,7 +103,9 @@ def parse():
     ap.add_argument("--coef", choices=["one", "quad"], default="one",
                     help="assembly coefficients: c = 1, or c = exp(x1+x2+x3) at the 4 points of the degree-2 rule "
                          "(the paper's section 3.6 benchmark)")
-    ap.add_argument("--jobs", type=int, default=1000, help="jobs of the serving trace")
+    ap.add_argument("--jobs", type=int, default=10000, help="jobs of the serving trace")
+    ap.add_argument("--page-frac", type=float, default=0.25, help="share of page-op jobs in the serving trace")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0, help="device-memory budget of the server")
     ap.add_argument("--rate", type=float, default=200.0, help="arrival rate of the serving trace (jobs/s)")
     ap.add_argument("--tuner-cache", default=None, help="JSON schedule cache of the batch workload")
     ap.add_argument("--prec", choices=["f32", "f64"], default="f32",
@@ -671,7 +673,7 @@ def run_p2(args):
 
 
 def run_serve(args):
-    """Poisson stream of assembly jobs through the serving loop."""
+    """Poisson stream of assembly and page-op jobs through the serving loop."""
     import numpy as np
     import torch
 
@@ -680,25 +682,58 @@ def run_serve(args):
 
     torch.cuda.set_device(0)
     trace = gen.serving_trace(args.jobs, rate=args.rate)
-    elems_of, meshes = {}, []
+    kinds = gen.serving_page_jobs(args.jobs, frac=args.page_frac)
+    base_of, meshes = {}, []
     t_gen = time.perf_counter()
-    for j in trace:  # meshes in host memory before the clock starts (coordinates pinned)
-        if j["dim"] == 2:
-            c, e, _ = gen.square_mesh(j["n"], seed_sub=j["id"], stream=gen.STREAM_SERVE)
-        else:
-            c, e, _ = gen.cube_mesh(j["n"], seed_sub=j["id"], stream=gen.STREAM_SERVE, with_faces=False)
+    for j, pg in zip(trace, kinds):  # inputs in host memory before the clock starts (pinned)
+        if pg is not None:
+            meshes.append(None)
+            continue
         key = (j["dim"] << 32) | j["n"]
-        e = elems_of.setdefault(key, e)
-        meshes.append((torch.from_numpy(c).pin_memory(), e, key))
+        if key not in base_of:  # one connectivity (and unjittered coordinates) per mesh size
+            if j["dim"] == 2:
+                c0, e0, _ = gen.square_mesh(j["n"], jitter=0.0)
+            else:
+                c0, e0, _ = gen.cube_mesh(j["n"], jitter=0.0, with_faces=False)
+            base_of[key] = (c0, e0)
+        c0, e0 = base_of[key]
+        c = gen.jittered_coords(c0, j["n"], j["dim"], j["id"], stream=gen.STREAM_SERVE)
+        meshes.append((torch.from_numpy(c).pin_memory(), e0, key))
+    # page-op jobs read prefixes of one pool of pages per (order, precision); their results
+    # are computed on the device, and the first 64 page jobs also copy them back
+    pool = {}
+    for pg in kinds:
+        if pg is not None:
+            k = (pg["order"], pg["prec"])
+            pool[k] = max(pool.get(k, 0), pg["count"])
+    for (n, prec), cnt in list(pool.items()):
+        dt = np.float32 if prec == 0 else np.float64
+        a = gen.page_batch(cnt, n, sub=100 + n).astype(dt)
+        b = gen.page_batch(cnt, n, stream=gen.STREAM_PAGES_B, sub=100 + n).astype(dt)
+        pool[(n, prec)] = (torch.from_numpy(a).pin_memory(), torch.from_numpy(b).pin_memory())
     t_gen = time.perf_counter() - t_gen
-    total_el = sum(m[1].shape[0] for m in meshes)
-    n_out = min(64, len(trace))  # these jobs also copy their values back (pinned outputs)
-    outs = []
-    for j in trace[:n_out]:
+    print(f"serve: inputs ready in {t_gen:.1f} s", file=sys.stderr, flush=True)
+    asm = [k for k, m in enumerate(meshes) if m is not None]
+    pgs = [k for k, m in enumerate(meshes) if m is None]
+    total_el = sum(meshes[k][1].shape[0] for k in asm)
+    total_pages = sum(kinds[k]["count"] for k in pgs)
+    n_out = 64  # these jobs of each kind also copy their results back (pinned outputs)
+    outs = {}
+    for k in asm[:n_out]:
+        j = trace[k]
         cnt = gen.square_counts(j["n"]) if j["dim"] == 2 else gen.kuhn_counts(j["n"])
         dt = torch.float64 if j["dim"] == 2 else torch.float32
-        outs.append((torch.empty(cnt["nnz"], dtype=dt).pin_memory(), torch.empty(cnt["nnz"], dtype=dt).pin_memory()))
-    budget = 64 << 30
+        outs[k] = (torch.empty(cnt["nnz"], dtype=dt).pin_memory(), torch.empty(cnt["nnz"], dtype=dt).pin_memory())
+    for k in pgs[:n_out]:
+        pg = kinds[k]
+        dt = torch.float32 if pg["prec"] == 0 else torch.float64
+        nn2 = pg["count"] * pg["order"] ** 2
+        outs[k] = (torch.empty(nn2, dtype=dt).pin_memory(), torch.empty(nn2, dtype=dt).pin_memory(),
+                   torch.empty(pg["count"], dtype=dt).pin_memory())
+    budget = int(args.serve_budget_gib * (1 << 30))
+
+    def pct(v, q):
+        return float(np.percentile(np.asarray(v), q)) * 1e3 if len(v) else None
 
     def replay(flags, speed):
         srv = L.Server(budget, 256, flags)
@@ -708,48 +743,74 @@ def run_serve(args):
             at = t0 + j["t"] / speed
             while srv.now() < at:
                 pass
-            c, e, key = meshes[k]
-            prec = L.F64 if j["dim"] == 2 else L.F32
-            vk, vm = outs[k] if k < n_out else (None, None)
-            tickets.append(srv.submit(j["dim"], prec, c, e, topology=key, arrival=at, valsK=vk, valsM=vm))
+            if k % 1000 == 0:
+                print(f"serve: flags {flags} speed {speed}: {k} jobs submitted", file=sys.stderr, flush=True)
+            pg = kinds[k]
+            if pg is None:
+                c, e, key = meshes[k]
+                prec = L.F64 if j["dim"] == 2 else L.F32
+                vk, vm = outs.get(k, (None, None))
+                tickets.append(srv.submit(j["dim"], prec, c, e, topology=key, arrival=at, valsK=vk, valsM=vm))
+            else:
+                a, b = pool[(pg["order"], pg["prec"])]
+                cnt = pg["count"]
+                x, cc, d = outs.get(k, (None, None, None))
+                tickets.append(srv.submit_pages(pg["prec"], pg["order"], L.OP_INV | L.OP_MTIMES, a[:cnt], b=b[:cnt],
+                                                x=x, c=cc, det=d, arrival=at))
         srv.drain()
         st = srv.stats()
         res = [srv.poll(t) for t in tickets]
         srv.close()
+        print(f"serve: flags {flags} speed {speed}: done, p50 {st['latency_p50'] * 1e3:.2f} ms", file=sys.stderr,
+              flush=True)
         bad = [r for r in res if r["status"] != 0]
         if bad:
             raise RuntimeError(f"{len(bad)} serving jobs failed, first status {bad[0]['status']}")
-        copy = [r["copied"] - r["finished"] for r in res[:n_out]]
-        return {"jobs": st["completed"], "elements": st["elements"],
+        lat_a = [res[k]["finished"] - res[k]["arrival"] for k in asm]
+        lat_p = [res[k]["finished"] - res[k]["arrival"] for k in pgs]
+        copy = [res[k]["copied"] - res[k]["finished"] for k in outs]
+        return {"jobs": st["completed"], "elements": st["elements"], "pages": st["pages"],
                 "latency_ms": {"p50": st["latency_p50"] * 1e3, "p99": st["latency_p99"] * 1e3,
                                "mean": st["latency_mean"] * 1e3, "max": st["latency_max"] * 1e3},
+                "latency_ms_assembly": {"p50": pct(lat_a, 50), "p99": pct(lat_a, 99)},
+                "latency_ms_pages": {"p50": pct(lat_p, 50), "p99": pct(lat_p, 99)},
                 "jobs_per_s": st["jobs_per_s"], "elements_per_s": st["elements_per_s"],
+                "pages_per_s": st["pages_per_s"],
                 "copy_back_ms_median": float(np.median(copy)) * 1e3 if copy else None,
                 "ticks": st["ticks"], "launches": st["launches"], "max_batch": st["max_batch"],
                 "structure_hits": st["cache_hits"], "structure_misses": st["cache_misses"],
+                "evictions": st["evictions"], "admit_waits": st["admit_waits"],
+                "scheduler_s": {"evict": round(st["evict_s"], 3), "build_start": round(st["build_start_s"], 3),
+                                "tick": round(st["tick_s"], 3)},
                 "hbm_high_water_bytes": st["hbm_high_water"], "span_s": st["last_finish"] - st["first_arrival"]}
 
     served = replay(0, 1.0)
     plain = replay(L.SERVER_NOFUSE | L.SERVER_NOCACHE, 1.0)
     overload = replay(0, 10.0)
     out = {
-        "metric": "P1 elements assembled/s under a Poisson stream of assembly jobs (+ p50/p99 job latency)",
+        "metric": "P1 elements assembled/s under a Poisson stream of assembly and page-op jobs (+ p50/p99 job "
+                  "latency)",
         "value": served["elements_per_s"], "unit": "elements/s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": served["span_s"] * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64 (2-D jobs) / f32 (3-D jobs)", "data": "synthetic",
-        "config": {"workload": "%d jobs, Poisson arrivals %.0f jobs/s, dim 2 (FP64) or 3 (FP32 + FP64 fallback) "
-                               "with p = 1/2, 10^U(3, log10 2e6) elements, jittered structured meshes, "
-                               "64 GiB budget, 256 slots" % (len(trace), args.rate),
-                   "elements": total_el, "mesh_generation_s": round(t_gen, 1)},
+        "dtype": "f64 (2-D jobs) / f32 (3-D jobs); page jobs f32 or f64", "data": "synthetic",
+        "config": {"workload": "%d jobs, Poisson arrivals %.0f jobs/s; %.0f%% page-op jobs (inverse with det + "
+                               "product, order 2..4, 10^U(3,6) pages, FP32 or FP64), the others assembly jobs of "
+                               "dim 2 (FP64) or 3 (FP32 + FP64 fallback) with p = 1/2, 10^U(3, log10 2e6) "
+                               "elements, jittered structured meshes, 64 GiB budget, 256 slots"
+                               % (len(trace), args.rate, 100 * args.page_frac),
+                   "assembly_jobs": len(asm), "page_jobs": len(pgs), "elements": total_el, "pages": total_pages,
+                   "input_generation_s": round(t_gen, 1)},
         "served": served, "one_launch_per_job_no_resident_structures": plain, "overload_10x": overload,
         "roofline": None,
-        "roofline_note": "latency-bound job stream; the kernels' rooflines are those of the assembly workload",
+        "roofline_note": "latency-bound job stream; the kernels' rooflines are those of the assembly and pages "
+                         "workloads",
     }
     if not args.no_cpu_baseline:
         import oracle
+        hi = host_info()
         t1 = time.perf_counter()
         done = 0
-        for k, j in enumerate(trace):
+        for k in asm:
             c, e, _ = meshes[k]
             cn = c.numpy()
             el = oracle.p1_elements(cn, e)
@@ -759,8 +820,9 @@ def run_serve(args):
                 break
         dt = time.perf_counter() - t1
         out["cpu_baseline"] = {"value": done / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-                               "sample": "FP64 oracle element matrices + sparse assembly of the first %d jobs of the "
-                                         "trace (%d elements), single thread, %.1f s" % (k + 1, done, dt)}
+                               "sample": "FP64 oracle element matrices + sparse assembly of the trace's first "
+                                         "assembly jobs (%d elements), single thread, %.1f s" % (done, dt),
+                               "host": hi}
     print(json.dumps(out))
 
 

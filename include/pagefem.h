@@ -543,6 +543,11 @@ typedef struct {
     int64_t hbm_in_use, hbm_high_water;  /* accounted device bytes                            */
     int64_t pages;                     /* pages of the completed page-op jobs                  */
     double pages_per_s;                /* over [first_arrival, last_finish]                     */
+    /* scheduler thread, host seconds spent: freeing evicted structures, starting structure
+     * builds, preparing and launching ticks; admissions that found the queue head waiting
+     * for memory                                                                             */
+    double evict_s, build_start_s, tick_s;
+    int64_t admit_waits;
 } pf_stats;
 
 /* Create a server with a device-memory budget (bytes of job inputs, outputs and resident

@@ -179,7 +179,9 @@ void make_room(pf_server* S, size_t need) {
             if (kv.second->refs == 0 && (!victim || kv.second->last_use < victim->last_use)) victim = kv.second;
         if (!victim) return;
         S->cache.erase(victim->key);
+        const auto t0 = std::chrono::steady_clock::now();
         destroy_topo(S, victim);
+        S->st.evict_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         ++S->st.evictions;
     }
 }
@@ -290,7 +292,10 @@ void admit(pf_server* S, std::vector<SJob*>& batch) {
         const int64_t nnz = (hit && hit->state == Topo::BUILT) ? csr_nnz(hit->csr) : nnz_bound(j->spec);
         const size_t need = job_estimate(j->spec, nnz) + extra;
         if (S->used + need > S->budget) make_room(S, need);
-        if (S->used + need > S->budget) break;  // head of the queue waits for memory
+        if (S->used + need > S->budget) {  // head of the queue waits for memory
+            ++S->st.admit_waits;
+            break;
+        }
         S->pending.pop_front();
         if (hit) {
             j->topo = hit;
@@ -535,7 +540,9 @@ void loop(pf_server* S) {
             }
             Topo* t = j->topo;
             if (t->state == Topo::NEW) {
+                const auto b0 = std::chrono::steady_clock::now();
                 const pf_status st = start_build(S, j, t);
+                S->st.build_start_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - b0).count();
                 if (st != PF_OK) {
                     std::lock_guard<std::mutex> lk(S->mu);
                     t->state = Topo::FAILED;
@@ -565,9 +572,12 @@ void loop(pf_server* S) {
         }
         if (!ready.empty()) {
             TickCounts tc;
+            const auto k0 = std::chrono::steady_clock::now();
             run_tick(S, ready, failed, tc);
+            const double dk = std::chrono::duration<double>(std::chrono::steady_clock::now() - k0).count();
             progress = true;
             std::lock_guard<std::mutex> lk(S->mu);
+            S->st.tick_s += dk;
             for (SJob* j : ready) S->active.push_back(j);
             ++S->st.ticks;
             S->st.launches += tc.launches;

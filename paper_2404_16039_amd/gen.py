@@ -43,6 +43,7 @@ STREAM_MIXED = 7
 STREAM_SERVE = 8
 STREAM_PERM = 9
 STREAM_FAN = 10
+STREAM_SERVE_PAGES = 11
 
 
 def rng(stream: int, sub: int | None = None) -> np.random.Generator:
@@ -391,6 +392,36 @@ def serving_trace(njobs: int, rate: float = 200.0, lo: float = 1e3, hi: float = 
             n = max(1, int(round((tgt[k] / 6.0) ** (1.0 / 3.0))))
         jobs.append({"id": k, "t": float(t[k]), "dim": d, "n": n, "target": float(tgt[k])})
     return jobs
+
+
+def jittered_coords(base: np.ndarray, n: int, dim: int, seed_sub: int, stream: int = STREAM_SERVE,
+                    jitter: float | None = None) -> np.ndarray:
+    """The coordinates square_mesh / cube_mesh(n, seed_sub=seed_sub, stream=stream) return,
+    from the same mesh's unjittered coordinates `base` (jitter 0.2 h in 2-D, 0.15 h in 3-D
+    unless given): the same draws, so serving traces can keep one connectivity per size."""
+    if jitter is None:
+        jitter = 0.2 if dim == 2 else 0.15
+    h = 1.0 / n
+    g = rng(stream, seed_sub)
+    d = g.uniform(-jitter * h, jitter * h, size=base.shape)
+    inner = _interior_mask_grid(n + 1, dim)
+    c = base.copy()
+    c[inner] += d[inner]
+    return c
+
+
+def serving_page_jobs(njobs: int, frac: float = 0.25, lo: float = 1e3, hi: float = 1e6,
+                      stream: int = STREAM_SERVE_PAGES):
+    """Which jobs of a serving trace are page-op jobs, and their shape: a list with None for
+    an assembly job, else {order, count, prec} (order uniform in {2,3,4}, count log-uniform in
+    [lo, hi], FP32 or FP64 with p = 1/2) for a page-op job (probability `frac`)."""
+    g = rng(stream)
+    is_page = g.random(njobs) < frac
+    order = g.integers(2, 5, size=njobs)
+    count = np.round(10.0 ** g.uniform(math.log10(lo), math.log10(hi), size=njobs)).astype(np.int64)
+    prec = g.integers(0, 2, size=njobs)
+    return [{"order": int(order[k]), "count": int(count[k]), "prec": int(prec[k])} if is_page[k] else None
+            for k in range(njobs)]
 
 
 def kuhn_counts(n: int) -> dict:

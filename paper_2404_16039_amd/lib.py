@@ -100,7 +100,9 @@ class Stats(C.Structure):
                 ("latency_p50", C.c_double), ("latency_p99", C.c_double), ("latency_mean", C.c_double),
                 ("latency_max", C.c_double), ("first_arrival", C.c_double), ("last_finish", C.c_double),
                 ("jobs_per_s", C.c_double), ("elements_per_s", C.c_double), ("hbm_in_use", C.c_int64),
-                ("hbm_high_water", C.c_int64), ("pages", C.c_int64), ("pages_per_s", C.c_double)]
+                ("hbm_high_water", C.c_int64), ("pages", C.c_int64), ("pages_per_s", C.c_double),
+                ("evict_s", C.c_double), ("build_start_s", C.c_double), ("tick_s", C.c_double),
+                ("admit_waits", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
