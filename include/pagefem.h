@@ -194,9 +194,16 @@ typedef struct pf_csr pf_csr;
 pf_status pf_csr_create(pf_csr** out);
 
 /* Build (or rebuild) the CSR structure of a P1 mesh: node-to-element adjacency and the
- * row pattern.  Device buffers are kept in the handle and grown when needed (col_idx is
- * sized for 64 entries per row, since nnz is known only once the pattern is built).  This
- * call synchronises `stream` once (it reads nnz and the error word back to the host).
+ * row pattern.  The handle keeps the CSR pattern (row_ptr, and col_idx of exactly nnz
+ * words), the node-to-element adjacency in CSR form (4*ne entries with their packed column
+ * positions) and each row's diagonal position: 12 (nn + 1) + 4 nnz + 32 ne bytes for a 3-D
+ * mesh.  Its device memory comes from a stream-ordered pool of the library (enqueued on
+ * `stream`); the build's own scratch (padded adjacency rows and row-pattern columns, about
+ * 520 bytes per node) is released when the build ends.  This call synchronises `stream`
+ * once, to read nnz and the error word back (the exact size of col_idx), and returns with
+ * the build's last step (the columns) enqueued on `stream`: the library's later calls on
+ * the handle order their work after it on any stream (a device-side wait, no host wait),
+ * and pf_csr_info, which hands out device pointers, waits for it on the host.
  * Limits: 4*ne < 2^31, nnz < 2^31, at most 64 elements per node and 64 nonzeros per row
  * (PF_ELIMIT otherwise).  Out-of-range node ids give PF_EINDEX; PF_EINVAL if the row
  * offsets could not be formed (a bounded wait between the workgroups of the row-offset
@@ -245,9 +252,11 @@ pf_status pf_csr_numeric_info(const pf_csr* csr, pf_dtype prec, int32_t* rows_pe
  * events on its stream between its stages (0 stops recording).  pf_csr_stage_times waits
  * for the events of the last call and writes ms[PF_CSR_STAGES], the summed milliseconds
  * of each stage since timing was switched on, and *calls, the number of calls summed
- * (nullable).  Stages: adjacency (counting scatter), row pattern, row offsets (the scan
- * of the row lengths with row_ptr, col_idx and the numeric launch statistics). */
-#define PF_CSR_STAGES 3
+ * (nullable).  Stages: adjacency (counting scatter and the scan of the adjacency lengths),
+ * row pattern, row offsets (the scan of the row lengths with row_ptr, nnz and the numeric
+ * launch statistics), columns (col_idx, enqueued once nnz has reached the host; the host's
+ * wait between the row offsets and the columns belongs to no stage). */
+#define PF_CSR_STAGES 4
 pf_status pf_csr_set_timing(pf_csr* csr, int on);
 pf_status pf_csr_stage_times(pf_csr* csr, double* ms, int64_t* calls);
 
@@ -383,6 +392,8 @@ pf_status pf_energies_noalloc(const pf_csr* csr, pf_dtype prec, const double* co
                               const void* u, const void* b2D, void* J, double* totals,
                               const pf_fallback* fb, int64_t* d_counters, void* stream);
 
+/* Release a structure handle: waits for the device (as hipFree would), returns the handle's
+ * memory to the library's pool and the pool's unused memory to the device.  NULL is a no-op. */
 void pf_csr_destroy(pf_csr* csr);
 
 /* ----------------------------------------------------------------------------------

@@ -23,6 +23,8 @@
 #include "exact.hpp"
 
 #include <algorithm>
+#include <cstdint>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -35,15 +37,21 @@ struct pf_csr {
     int wmax8 = 0;       // ... of 8 rows
     int wmax2 = 0;       // ... of 2 rows
     int max_adj = 0;     // largest number of elements around one node
-    int32_t* adj_len = nullptr;  // elements around each node
-    int32_t* adj = nullptr;   // node i's entries (element << 2 | local index) at i * MAXADJ ...
-    uint32_t* pk = nullptr;   // per adjacency entry (same layout): local index, slots of the other nodes
+    // resident: the CSR pattern, the node -> element adjacency in CSR form (node i's entries
+    // at aptr[i] .. aptr[i+1]) with the packed slot words of every entry, the diagonal positions
+    int32_t* aptr = nullptr;  // adjacency offsets (nn + 1)
+    int32_t* adj = nullptr;   // entries (element << 2 | local index; P2: << 4), ne * nlb of them
+    uint32_t* pk = nullptr;   // per adjacency entry: local index, slots of the other nodes
+    uint64_t* pk2 = nullptr;  // P2 structures: row positions of the other nodes, 7 bits each
     int32_t* row_ptr = nullptr;
-    int32_t* col_idx = nullptr;
-    int32_t* cnt = nullptr;   // per-node counts / cursors / row lengths
-    int32_t* colblk = nullptr;  // sorted columns of every row-pattern block, RR * MAXROW per block
-    uint64_t* look = nullptr;   // published counts / prefixes of the row-offset tiles
-    uint64_t* pk2 = nullptr;    // P2 structures: row positions of the other nodes, 7 bits each
+    int32_t* col_idx = nullptr;  // exactly nnz words
+    // build scratch: one block (one pool allocation, one release when the build ends) holding
+    int32_t* adj_len = nullptr;  // elements around each node (scatter cursors)
+    int32_t* adj_pad = nullptr;  // node i's entries at i * MAXADJ ... (scatter output)
+    int32_t* cnt = nullptr;      // row lengths
+    int32_t* colblk = nullptr;   // sorted columns of every row-pattern block, RR * MAXROW per block
+    uint64_t* look = nullptr;    // published counts / prefixes of the row-offset tiles
+    unsigned char* scratch = nullptr;
     bool p2 = false;            // built from P2 elements (pf_csr_symbolic_p2)
     int64_t* bsum = nullptr;  // scan workspace
     int64_t* info = nullptr;  // [0] error bits, [1] adjacency total, [2] nnz, [3..6] block stats
@@ -57,19 +65,25 @@ struct pf_csr {
     int64_t nf = 0, nfb = 0;
     bool faces_built = false;
     int64_t cap_fcount = 0, cap_bcount = 0, cap_fptr = 0, cap_bptr = 0, cap_faces = 0, cap_fel = 0,
-            cap_bfaces = 0, cap_bel = 0, cap_finfo = 0, cap_dpos = 0, cap_esign = 0;
-    int64_t cap_adj_len = 0, cap_row_ptr = 0, cap_cnt = 0, cap_adj = 0, cap_pk = 0, cap_nnz = 0, cap_bsum = 0,
-            cap_info = 0, cap_colblk = 0, cap_look = 0, cap_work = 0, cap_pk2 = 0;
+            cap_bfaces = 0, cap_bel = 0, cap_finfo = 0, cap_esign = 0;
+    // the resident arrays sized before the pattern (aptr, row_ptr, dpos, adj, pk or pk2, bsum,
+    // info) share one block (one pool allocation); col_idx, sized by nnz, is its own
+    unsigned char* res = nullptr;
+    int64_t cap_res = 0, cap_nnz = 0, cap_work = 0, cap_scratch = 0;
     bool built = false;
     // per-stage timing of pf_csr_symbolic (events e0..e3: start, after the adjacency, after
     // the pattern, after the row offsets)
     bool timing = false, pending = false;
     int64_t* hinfo = nullptr;  // pinned host words for the status readbacks (allocated once)
-    hipEvent_t ready = nullptr;  // recorded after the status readback of an enqueued build
-    bool enqueued = false;       // a build was enqueued and not yet finished
-    int q_dim = 0, q_nlb = 0;    // ... and its shape
+    hipEvent_t ready = nullptr;  // recorded at the end of each enqueued build phase
+    int stage = 0;               // 0 idle, 1 pattern phase enqueued, 2 column phase enqueued
+    // pf_csr_symbolic returned with the column phase enqueued on q_stream and not yet seen
+    // complete: work on another stream first waits for the ready event
+    mutable bool cols_pending = false;
+    int q_dim = 0, q_nlb = 0;    // ... the build's shape and stream
     int64_t q_nn = 0, q_ne = 0;
-    hipEvent_t ev[PF_CSR_STAGES + 1] = {};
+    hipStream_t q_stream = nullptr;
+    hipEvent_t ev[PF_CSR_STAGES + 2] = {};  // stage k: ev[STAGE_EV[k][0]] .. ev[STAGE_EV[k][1]]
     double stage_ms[PF_CSR_STAGES] = {};
     int64_t stage_calls = 0;
 };
@@ -362,13 +376,15 @@ struct P2Pattern {                  // LDS of a P2 pattern block
 };
 
 // One pass over NRW rows (nrw of them in the matrix) starting at row rq, with TS-slot tables.
-// alen: the rows' numbers of elements (LDS); dst: the colblk region of the pass's first 8
-// rows (rows 8 .. 15 of a 16-row pass go to the next region); apre: this thread's entries of
-// the first batch (item r + NRW j), read at block start, used when `pre`.
+// alen: the rows' numbers of elements, abase: their first compact adjacency entries (LDS); dst:
+// the colblk region of the pass's first 8 rows (rows 8 .. 15 of a 16-row pass go to the next
+// region); apre: this thread's entries of the first batch (item r + NRW j), read at block
+// start, used when `pre`.  Every entry is copied to its compact place, with its pk2 word.
 template <int NLB, int NRW, int TS>
-__device__ __forceinline__ void p2_pattern_pass(P2Pattern& S, const int32_t* alen, int64_t rq, int nrw,
-                                                const int32_t* __restrict__ elems, const int32_t* __restrict__ adj,
-                                                int32_t* __restrict__ rowlen, int32_t* __restrict__ dst,
+__device__ __forceinline__ void p2_pattern_pass(P2Pattern& S, const int32_t* alen, const int32_t* abase, int64_t rq,
+                                                int nrw, const int32_t* __restrict__ elems,
+                                                const int32_t* __restrict__ adj, int32_t* __restrict__ rowlen,
+                                                int32_t* __restrict__ dst, int32_t* __restrict__ adjc,
                                                 uint64_t* __restrict__ pk2, int32_t* __restrict__ dpos,
                                                 const int32_t (&apre)[RBATCH], bool pre, bool& bad) {
     constexpr int NO = NLB - 1;
@@ -405,6 +421,7 @@ __device__ __forceinline__ void p2_pattern_pass(P2Pattern& S, const int32_t* ale
             const int r = idx % NRW, j = idx / NRW;
             const bool ok = idx < items && j < alen[r] && r < nrw;
             const int32_t w = first ? apre[b] : adj[e0 + (ok ? r * MAXADJ + j : 0)];
+            if (ok) adjc[abase[r] + j] = w;
             rq_[b] = ok ? r : -1;
             aq[b] = ok ? (w & 15) : 0;
             eq[b] = ok ? (static_cast<uint32_t>(w) >> 4) : 0;
@@ -529,7 +546,7 @@ __device__ __forceinline__ void p2_pattern_pass(P2Pattern& S, const int32_t* ale
 #pragma unroll
         for (int k = 0; k < NO; ++k)
             word |= static_cast<uint64_t>(S.slot_rank[r * TS + static_cast<int>((w >> (7 * k)) & 127)]) << (7 * k);
-        pk2[e0 + r * MAXADJ + j] = word;
+        pk2[abase[r] + j] = word;
     }
     __syncthreads();  // the LDS is free for the next pass
 }
@@ -537,12 +554,14 @@ __device__ __forceinline__ void p2_pattern_pass(P2Pattern& S, const int32_t* ale
 template <int NLB>
 __global__ __launch_bounds__(RT2) void k_pattern_p2(int64_t nn, const int32_t* __restrict__ elems,
                                                    const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
-                                                   int32_t* __restrict__ rowlen, int32_t* __restrict__ colblk,
+                                                   const int32_t* __restrict__ aptr, int32_t* __restrict__ rowlen,
+                                                   int32_t* __restrict__ colblk, int32_t* __restrict__ adjc,
                                                    uint64_t* __restrict__ pk2, int32_t* __restrict__ dpos,
                                                    int64_t* __restrict__ info) {
     constexpr int NO = NLB - 1;
     __shared__ P2Pattern S;
     __shared__ int32_t alen[RR2];
+    __shared__ int32_t abase[RR2];
     __shared__ int32_t longrows;
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RR2;
     const int nr = static_cast<int>((r0 + RR2 < nn) ? RR2 : nn - r0);
@@ -558,9 +577,13 @@ __global__ __launch_bounds__(RT2) void k_pattern_p2(int64_t nn, const int32_t* _
         apre[b] = adj[(r0 + (r < nr ? r : 0)) * MAXADJ + j];
     }
     const int32_t lv = adj_len[r0 + (static_cast<int>(threadIdx.x) < nr ? threadIdx.x : 0)];
+    const int32_t av = aptr[r0 + (static_cast<int>(threadIdx.x) < nr ? threadIdx.x : 0)];
     if (threadIdx.x < 64) {  // row lengths, and whether a row may hold more than 64 nonzeros (wave 0)
         const int L = static_cast<int>(threadIdx.x) < nr ? min(lv, MAXADJ) : 0;
-        if (threadIdx.x < RR2) alen[threadIdx.x] = L;
+        if (threadIdx.x < RR2) {
+            alen[threadIdx.x] = L;
+            abase[threadIdx.x] = av;
+        }
         const unsigned long long lg = __ballot(1 + NO * L > 64);
         if (threadIdx.x == 0) longrows = lg != 0ull;
     }
@@ -568,20 +591,22 @@ __global__ __launch_bounds__(RT2) void k_pattern_p2(int64_t nn, const int32_t* _
     bool bad = false;
     int32_t* dst = colblk + (static_cast<int64_t>(blockIdx.x) * 2) * (RR * MAXROW2);
     if (!longrows) {
-        p2_pattern_pass<NLB, RR2, 64>(S, alen, r0, nr, elems, adj, rowlen, dst, pk2, dpos, apre, true, bad);
+        p2_pattern_pass<NLB, RR2, 64>(S, alen, abase, r0, nr, elems, adj, rowlen, dst, adjc, pk2, dpos, apre, true,
+                                      bad);
     } else {
-        p2_pattern_pass<NLB, RR, MAXROW2>(S, alen, r0, min(nr, RR), elems, adj, rowlen, dst, pk2, dpos, apre, false,
-                                          bad);
+        p2_pattern_pass<NLB, RR, MAXROW2>(S, alen, abase, r0, min(nr, RR), elems, adj, rowlen, dst, adjc, pk2, dpos,
+                                          apre, false, bad);
         if (nr > RR)
-            p2_pattern_pass<NLB, RR, MAXROW2>(S, alen + RR, r0 + RR, nr - RR, elems, adj, rowlen, dst + RR * MAXROW2,
-                                              pk2, dpos, apre, false, bad);
+            p2_pattern_pass<NLB, RR, MAXROW2>(S, alen + RR, abase + RR, r0 + RR, nr - RR, elems, adj, rowlen,
+                                              dst + RR * MAXROW2, adjc, pk2, dpos, apre, false, bad);
     }
     if (bad) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
 }
 
 // ---------------------------------------------------------------------------- row offsets
-// row_ptr, col_idx and the numeric launch statistics in one pass over tiles of SCAN_TILE
-// rows (a single-pass scan with decoupled look-back).  Tile t publishes its nonzero count
+// row_ptr, nnz and the numeric launch statistics in one pass over tiles of SCAN_TILE rows (a
+// single-pass scan with decoupled look-back); the columns follow once col_idx is allocated
+// for exactly nnz words (k_row_columns).  Tile t publishes its nonzero count
 // as soon as it has summed its row lengths (status AGG), then sums the published values of
 // the tiles before it, nearest first, 64 at a time, until it meets one holding its
 // inclusive prefix (status INC), and publishes its own.  A tile waits only for tiles of
@@ -625,8 +650,7 @@ __device__ int64_t lb_exclusive(const uint64_t* look, int64_t t, bool& timeout) 
 }
 
 // Thread i of a tile holds rows 8i .. 8i+7, one 8-row group (a P1 row-pattern block, or half
-// of a P2 one), whose columns lie contiguous at the start of the group's region of colblk
-// (called a row-pattern block below).  Besides the offsets, the tile measures the largest
+// of a P2 one: a row-pattern block below).  Besides the offsets, the tile measures the largest
 // CSR window of the numeric block classes (NR_BIG rows, NR_MID rows as sums over 4 and 2
 // neighbouring lanes, NR_SMALL = 4 rows per half thread) and the largest number of elements
 // around a node, and stores them as tstat[8t .. 8t+7] (no atomics on shared words: those
@@ -634,15 +658,10 @@ __device__ int64_t lb_exclusive(const uint64_t* look, int64_t t, bool& timeout) 
 static_assert(SCAN_ITEMS == RR && SCAN_ITEMS == 8, "a scan thread owns one row-pattern block of 8 rows");
 constexpr int TSTAT = 8;  // int32 statistics per tile (two 16-byte words)
 
-// RW: words of a row-pattern block's region in colblk; NRD: rounds of 64 words read at once
-template <int RW, int NRD>
 __global__ __launch_bounds__(SBS) void k_row_offsets(int64_t nn, const int32_t* __restrict__ rowlen,
-                                                     const int32_t* __restrict__ adj_len,
-                                                     const int32_t* __restrict__ colblk, int32_t* __restrict__ row_ptr,
-                                                     int32_t* __restrict__ col_idx, uint64_t* __restrict__ look,
-                                                     int32_t* __restrict__ tstat, int64_t* __restrict__ info) {
-    __shared__ int32_t boff[SBS];  // offset of each thread's block inside the tile
-    __shared__ int32_t bcnt[SBS];
+                                                     const int32_t* __restrict__ adj_len, int32_t* __restrict__ row_ptr,
+                                                     uint64_t* __restrict__ look, int32_t* __restrict__ tstat,
+                                                     int64_t* __restrict__ info) {
     __shared__ int red[TSTAT][SBS / 64];
     __shared__ int64_t excl_s;
     const int64_t t = blockIdx.x;
@@ -659,8 +678,6 @@ __global__ __launch_bounds__(SBS) void k_row_offsets(int64_t nn, const int32_t* 
     int64_t total;
     const int64_t pre = block_exclusive_scan(sum, total);  // synchronises the block
     if (threadIdx.x == 0) lb_publish(look, t, (t == 0 ? LB_INC : LB_AGG) | static_cast<uint64_t>(total));
-    boff[threadIdx.x] = static_cast<int32_t>(pre);
-    bcnt[threadIdx.x] = sum;
     // launch statistics: 2-, 4-, 8-, 16- and 32-row windows (tiles and threads start on
     // multiples of 32 and 8 rows)
     int m[TSTAT];
@@ -702,21 +719,38 @@ __global__ __launch_bounds__(SBS) void k_row_offsets(int64_t nn, const int32_t* 
         for (int w = 1; w < SBS / 64; ++w) x = max(x, red[c][w]);
         tstat[t * TSTAT + c] = x;
     }
-    const int64_t base = excl_s;
-    int64_t o = base + pre;
+    int64_t o = excl_s + pre;
 #pragma unroll
     for (int i = 0; i < SCAN_ITEMS; ++i) {
         if (row0 + i < nn) row_ptr[row0 + i] = static_cast<int32_t>(o);
         o += v[i];
     }
-    // columns: each wave moves groups of 4 consecutive row-pattern blocks (wave w takes groups
-    // w, w + 4, ...): the first 64 NRD words of the 4 blocks as 4 NRD loads in flight per lane
-    // (consecutive lanes on consecutive words of a block), then the rest of any longer block
-    const int64_t blk0 = t * SBS;  // the tile's first row-pattern block
+}
+
+// The columns of every row into col_idx (sized exactly nnz), once the row offsets are known:
+// tile t moves the row-pattern blocks of its SCAN_TILE rows (thread i: block t SBS + i, rows
+// 8i .. 8i+7 of the tile, whose columns lie contiguous at the start of the block's region of
+// colblk).  Each wave moves groups of 4 consecutive blocks (wave w takes groups w, w + 4,
+// ...): the first 64 NRD words of the 4 blocks as 4 NRD loads in flight per lane
+// (consecutive lanes on consecutive words of a block), then the rest of any longer block.
+template <int RW, int NRD>
+__global__ __launch_bounds__(SBS) void k_row_columns(int64_t nn, const int32_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ colblk,
+                                                     int32_t* __restrict__ col_idx) {
+    __shared__ int32_t boff[SBS];  // offset of each block's first column in col_idx
+    __shared__ int32_t bcnt[SBS];  // its number of columns
+    const int64_t blk0 = static_cast<int64_t>(blockIdx.x) * SBS;  // the tile's first row-pattern block
     const int64_t nblk = (nn + RR - 1) / RR;
     const int nb = static_cast<int>(nblk - blk0 < SBS ? nblk - blk0 : SBS);
+    {
+        const int64_t b = blk0 + (static_cast<int>(threadIdx.x) < nb ? threadIdx.x : nb - 1);
+        const int32_t lo = row_ptr[b * RR];
+        const int32_t hi = row_ptr[(b + 1) * RR < nn ? (b + 1) * RR : nn];
+        boff[threadIdx.x] = lo;
+        bcnt[threadIdx.x] = hi - lo;
+    }
+    __syncthreads();
     const int lane = threadIdx.x & 63;
-    int32_t* dst = col_idx + base;
     for (int g = (threadIdx.x >> 6) * 4; g < nb; g += (SBS / 64) * 4) {
         int n[4], o[4];
         const int32_t* src[4];
@@ -745,7 +779,7 @@ __global__ __launch_bounds__(SBS) void k_row_offsets(int64_t nn, const int32_t* 
             for (int j = 0; j < 4; ++j)
 #pragma unroll
                 for (int r = 0; r < NRD; ++r)
-                    if (w0 + lane + 64 * r < n[j]) dst[o[j] + w0 + lane + 64 * r] = v[j][r];
+                    if (w0 + lane + 64 * r < n[j]) col_idx[o[j] + w0 + lane + 64 * r] = v[j][r];
         }
     }
 }
@@ -794,9 +828,10 @@ __global__ __launch_bounds__(SBS) void k_row_stats(int64_t tiles, const int32_t*
 // to the row's list; a row's own node is entered once, by the thread holding its first entry.
 // Each list item's rank (ascending node id) is its column position.  The block writes the row
 // lengths, the diagonal positions, every 8-row group's sorted columns at the start of the
-// group's region of 8 x 64 words of colblk (the layout k_row_offsets moves into col_idx once
-// the lengths are scanned), and the packed slot words pk of every adjacency entry (bits 0-1
-// local index, bits 2+8k .. 9+8k column position of the k-th other node, in local order).
+// group's region of 8 x 64 words of colblk (the layout the column phase moves into col_idx once
+// the lengths are scanned), and, at the entry's place aptr[row] + j of the compact adjacency,
+// the entry itself and its packed slot word pk (bits 0-1 local index, bits 2+8k .. 9+8k column
+// position of the k-th other node, in local order).
 constexpr int PR = 32;            // rows per block
 constexpr int PT = 256;           // threads per block
 constexpr int PJ = PT / PR;       // threads per row
@@ -809,7 +844,8 @@ static_assert(PT % PR == 0 && PQ * PJ == MAXADJ && MAXROW == 64 && PR % RR == 0,
 template <int NLB>
 __global__ __launch_bounds__(PT) void k_rows_p1(int64_t nn, const int32_t* __restrict__ elems,
                                                 const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
-                                                int32_t* __restrict__ rowlen, int32_t* __restrict__ colblk,
+                                                const int32_t* __restrict__ aptr, int32_t* __restrict__ rowlen,
+                                                int32_t* __restrict__ colblk, int32_t* __restrict__ adjc,
                                                 uint32_t* __restrict__ pk, int32_t* __restrict__ dpos,
                                                 int64_t* __restrict__ info) {
     constexpr int NO = NLB - 1;        // other nodes of an element
@@ -833,6 +869,8 @@ __global__ __launch_bounds__(PT) void k_rows_p1(int64_t nn, const int32_t* __res
     const int64_t row = r0 + (r < nr ? r : nr - 1);  // in bounds for the loads of rows past the end
     const int32_t self = static_cast<int32_t>(r0 + r);
     const int L = r < nr ? min(adj_len[row], MAXADJ) : 0;  // longer lists raised an error already
+    const int64_t ao = aptr[row];                           // the row's first compact entry
+    const int32_t ablk0 = aptr[r0], ablk1 = aptr[r0 + nr];  // the block's compact entries
     int32_t* rt = tab + r * PS;
     int32_t* rl = lst + r * PL;
     uint8_t* rh = lsth + r * PL;
@@ -862,6 +900,7 @@ __global__ __launch_bounds__(PT) void k_rows_p1(int64_t nn, const int32_t* __res
         }
     }
     uint32_t iw[PQ];  // per entry: local index | table slot of the k-th other node << (2 + 6k)
+    int32_t aw[PQ];   // the entries themselves
 #pragma unroll
     for (int q0 = 0; q0 < PQ; q0 += PB) {
         if (jt + q0 * PJ >= L) break;
@@ -876,7 +915,10 @@ __global__ __launch_bounds__(PT) void k_rows_p1(int64_t nn, const int32_t* __res
             aq[i] = adj[row * MAXADJ + (okq[i] ? j : 0)];
         }
 #pragma unroll
-        for (int i = 0; i < PB; ++i) aq[i] = okq[i] ? aq[i] : 0;
+        for (int i = 0; i < PB; ++i) {
+            aq[i] = okq[i] ? aq[i] : 0;
+            if (q0 + i < PQ) aw[q0 + i] = aq[i];
+        }
         if (NLB == 4 && (reinterpret_cast<uintptr_t>(elems) & 15) == 0) {
 #pragma unroll
             for (int i = 0; i < PB; ++i) {
@@ -979,7 +1021,14 @@ __global__ __launch_bounds__(PT) void k_rows_p1(int64_t nn, const int32_t* __res
         int32_t* dst = colblk + (r0 + (r & ~(RR - 1))) * MAXROW + cpre[r];  // the row's group region
         for (int k = jt; k < n; k += PJ) dst[srank[r * PS + rh[k]]] = rl[k];
     }
-    // packed slots of every adjacency entry from its kept table slots
+    // packed slots of every adjacency entry from its kept table slots.  The block's entries
+    // are one contiguous range of the compact adjacency: they are gathered in the (no longer
+    // read) tables and stored with consecutive lanes on consecutive words, unless the range
+    // is longer than the tables hold (then each entry is stored at its place directly)
+    const int nent = ablk1 - ablk0;
+    constexpr int STG = PR * PS / 2;  // entries the tables hold (entry words, then slot words)
+    const bool staged = nent <= STG;  // the same for the whole block
+    int32_t* stg = tab;
 #pragma unroll
     for (int q = 0; q < PQ; ++q) {
         const int j = jt + q * PJ;
@@ -991,7 +1040,21 @@ __global__ __launch_bounds__(PT) void k_rows_p1(int64_t nn, const int32_t* __res
             const int h = static_cast<int>((w >> (2 + 6 * k)) & (MAXROW - 1));
             word |= static_cast<uint32_t>(srank[r * PS + h]) << (2 + 8 * k);
         }
-        pk[row * MAXADJ + j] = word;
+        if (staged) {
+            const int loc = static_cast<int>(ao - ablk0) + j;
+            stg[loc] = aw[q];
+            stg[STG + loc] = static_cast<int32_t>(word);
+        } else {
+            adjc[ao + j] = aw[q];
+            pk[ao + j] = word;
+        }
+    }
+    if (staged) {
+        __syncthreads();
+        for (int k = t; k < nent; k += PT) {
+            adjc[ablk0 + k] = stg[k];
+            pk[ablk0 + k] = static_cast<uint32_t>(stg[STG + k]);
+        }
     }
 }
 
@@ -1074,7 +1137,7 @@ __global__ __launch_bounds__(SBS) void k_elem_sign(int64_t ne, const double* __r
 
 template <int NLB, int PASS>
 __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restrict__ row_ptr,
-                                              const int32_t* __restrict__ col_idx, const int32_t* __restrict__ adj_len,
+                                              const int32_t* __restrict__ col_idx, const int32_t* __restrict__ aptr,
                                               const int32_t* __restrict__ adj, const uint32_t* __restrict__ pk,
                                               const int32_t* __restrict__ dpos, const uint8_t* __restrict__ esign,
                                               int32_t* __restrict__ fcount, int32_t* __restrict__ bcount,
@@ -1090,30 +1153,16 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
     constexpr int WS = PASS == 1 ? FR * FSUB : 1;
     __shared__ unsigned long long wmin[WS], wmax[WS];
     __shared__ int16_t list[FR * FSUB];  // used slots of each row
-    __shared__ int32_t nlist[FR], dslot[FR], alen[FR], lpre[FR + 1];
+    __shared__ int32_t nlist[FR], dslot[FR], alen[FR], abase[FR], lpre[FR + 1];
     __shared__ int32_t maxl;
     __shared__ int32_t rowp[FR], rowf[FR], rowb[FR];
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * FR;
     const int nr = static_cast<int>((r0 + FR < nn) ? FR : nn - r0);
-    // every load that does not depend on another is issued first: the row lengths, diagonal
-    // positions and (pass 1) offsets of the rows, and the first FPRE batches of entries
-    // (padded rows: every entry below MAXADJ of a row of the matrix is in bounds; entries
-    // past a row's length are dropped once the lengths are known)
-    constexpr int FPRE = 2;
-    static_assert(FT * FPRE / FR <= MAXADJ, "the first batches lie inside the padded rows");
-    int32_t wpre[FPRE];
-    uint32_t ppre[FPRE];
-#pragma unroll
-    for (int b = 0; b < FPRE; ++b) {
-        const int idx = static_cast<int>(threadIdx.x) + b * FT;
-        const int r = idx % FR, j = idx / FR;
-        const int64_t t = (r0 + (r < nr ? r : 0)) * MAXADJ + j;
-        wpre[b] = adj[t];
-        ppre[b] = pk[t];
-    }
+    // every load that does not depend on another is issued first: the rows' adjacency
+    // offsets, diagonal positions and (pass 1) offsets; then the first FPRE batches of entries
     {
         const int r = static_cast<int>(threadIdx.x) < nr ? static_cast<int>(threadIdx.x) : 0;
-        const int32_t lv = adj_len[r0 + r], dv = dpos[r0 + r];
+        const int32_t a0 = aptr[r0 + r], a1 = aptr[r0 + r + 1], dv = dpos[r0 + r];
         int32_t pv = 0, fv = 0, bv = 0;
         if constexpr (PASS == 1) {
             pv = row_ptr[r0 + r];
@@ -1121,8 +1170,9 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
             bv = bptr[r0 + r];
         }
         if (threadIdx.x < FR) {
-            const int L = static_cast<int>(threadIdx.x) < nr ? min(lv, MAXADJ) : 0;
+            const int L = static_cast<int>(threadIdx.x) < nr ? min(a1 - a0, MAXADJ) : 0;
             alen[threadIdx.x] = L;
+            abase[threadIdx.x] = a0;
             nlist[threadIdx.x] = 0;
             dslot[threadIdx.x] = L > 0 ? dv : 0;
             rowp[threadIdx.x] = pv;
@@ -1140,6 +1190,19 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
     if (threadIdx.x == 0) maxl = 0;
     __syncthreads();
     if (threadIdx.x < FR) atomicMax(&maxl, alen[threadIdx.x]);
+    // the first FPRE batches of entries, in flight together (an entry past its row's length
+    // reads entry 0 and is dropped)
+    constexpr int FPRE = 2;
+    int32_t wpre[FPRE];
+    uint32_t ppre[FPRE];
+#pragma unroll
+    for (int b = 0; b < FPRE; ++b) {
+        const int idx = static_cast<int>(threadIdx.x) + b * FT;
+        const int r = idx % FR, j = idx / FR;
+        const int64_t t = j < alen[r] ? static_cast<int64_t>(abase[r]) + j : 0;
+        wpre[b] = adj[t];
+        ppre[b] = pk[t];
+    }
     __syncthreads();
     bool full = false;
     // entries dealt r + FR j: the faces each one owns go into its row's table
@@ -1187,7 +1250,7 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
     for (int idx = threadIdx.x + FPRE * FT; idx < FR * maxl; idx += FT) {
         const int r = idx % FR, j = idx / FR;
         if (j >= alen[r]) continue;
-        const int64_t t = (r0 + r) * MAXADJ + j;
+        const int64_t t = static_cast<int64_t>(abase[r]) + j;
         entry(r, adj[t], pk[t]);
     }
     __syncthreads();
@@ -1410,7 +1473,7 @@ constexpr size_t numeric_lds_bytes(int nr, int wmax) {
 template <int DIM, typename T, bool COEF, int NR, int QN = 0>
 __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const double* __restrict__ coords,
                                               const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
-                                              const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
+                                              const int32_t* __restrict__ aptr, const int32_t* __restrict__ adj,
                                               const uint32_t* __restrict__ pk, const T* __restrict__ cK,
                                               const T* __restrict__ cM, T* __restrict__ valsK, T* __restrict__ valsM,
                                               const Fallback& fb, int64_t* d_counters, int wmax) {
@@ -1424,8 +1487,8 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
     int32_t* shK = reinterpret_cast<int32_t*>(accM + wmax);      // [wmax] max bits, then shift
     int32_t* shM = shK + wmax;                                   // [wmax]
     int32_t* rp = shM + wmax;                                    // [NR + 1]
-    int32_t* alen = rp + (NR + 1);                               // [NR + 1] elements around each row node
-    int32_t* dslot = alen + (NR + 1);                            // [NR + 1]
+    int32_t* ap = rp + (NR + 1);                                 // [NR + 1] adjacency offsets of the rows
+    int32_t* dslot = ap + (NR + 1);                              // [NR + 1]
     int32_t* maxlen = dslot + (NR + 1);                          // [1]
     static_assert(lds_carve_aligned<Vec4<T>, A, A, int32_t, int32_t, int32_t, int32_t, int32_t, int32_t>(),
                   "numeric LDS carve-out: every array naturally aligned");
@@ -1437,9 +1500,9 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
     {
         const int t = static_cast<int>(threadIdx.x);
         const int32_t rpv = row_ptr[r0 + (t <= nr ? t : nr)];  // both loads unconditional
-        const int32_t alv = adj_len[r0 + (t < nr ? t : nr - 1)];
+        const int32_t apv = aptr[r0 + (t <= nr ? t : nr)];  // rows past the end: no elements
         if (t <= NR) rp[t] = rpv;
-        if (t < NR) alen[t] = t < nr ? alv : 0;
+        if (t <= NR) ap[t] = apv;
     }
     if (threadIdx.x == 0) *maxlen = 0;
     __syncthreads();
@@ -1447,8 +1510,8 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
     const int32_t w0 = rp[0];
     const int W = rp[nr] - w0;
     // packed entries of this thread's items, loaded before phase 0 so their latency overlaps
-    // it; the loads take no branch (an empty item reads the block's first entry and drops
-    // it), so all of them are in flight together
+    // it; the loads take no branch (an empty item reads entry 0 and drops it), so all of them
+    // are in flight together
     uint32_t pw[NITEMS];
     int rr[NITEMS];
     int64_t tt[NITEMS];
@@ -1457,9 +1520,9 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
         // the host guarantees that NITEMS * NBT / NR covers the longest adjacency list
         const int idx = threadIdx.x + q * NBT;
         const int r = idx % NR, j = idx / NR;
-        const bool ok = j < alen[r];
+        const bool ok = j < ap[r + 1] - ap[r];
         rr[q] = ok ? r : -1;
-        tt[q] = ok ? (r0 + r) * MAXADJ + j : r0 * MAXADJ;  // padded adjacency rows
+        tt[q] = ok ? static_cast<int64_t>(ap[r]) + j : 0;
         pw[q] = pk[tt[q]];
     }
     __syncthreads();
@@ -1625,7 +1688,8 @@ constexpr size_t numeric_lds_bytes_f32(int nr, int wmax) {
 // FP32 numeric assembly, NR rows per block of NT threads; thread t owns row t % NR: its
 // adjacency entries j = t / NR + q NT / NR (q < NITEMS) and its slots k = t / NR + u NT / NR.
 //   round trip 1  every load that depends on nothing: the window bounds, the row's adjacency
-//                 length, diagonal position and node coordinates, the entries' packed words;
+//                 offsets, diagonal position and node coordinates (the entries' packed words
+//                 follow as soon as the offsets arrive);
 //   round trips 2, 3  the columns of the thread's slots, then their coordinates (two slots of
 //                 a row per pass, all loads in flight), giving every slot the edge vector from
 //                 its row's node to its column's node (FP64 difference rounded once) in LDS;
@@ -1644,7 +1708,7 @@ template <int DIM, bool COEF, int NR, int NT, int QN = 0>
 __device__ __forceinline__ void numeric_block_f32(int64_t r0, int64_t nn, const double* __restrict__ coords,
                                                   const int32_t* __restrict__ row_ptr,
                                                   const int32_t* __restrict__ col_idx,
-                                                  const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
+                                                  const int32_t* __restrict__ aptr, const int32_t* __restrict__ adj,
                                                   const uint32_t* __restrict__ pk, const int32_t* __restrict__ dpos,
                                                   const float* __restrict__ cK, const float* __restrict__ cM,
                                                   float* __restrict__ valsK, float* __restrict__ valsM,
@@ -1672,17 +1736,21 @@ __device__ __forceinline__ void numeric_block_f32(int64_t r0, int64_t nn, const 
 
     // round trip 1 (no load waits for another)
     const int32_t rpv = row_ptr[r0 + (t <= nr ? t : nr)];
-    const int32_t alv = adj_len[row];
+    const int32_t a0v = aptr[row], a1v = aptr[row + 1];
     const int32_t dpv = dpos[row];
     double pi[DIM];
 #pragma unroll
     for (int c = 0; c < DIM; ++c) pi[c] = coords[row * DIM + c];
+    const int L = r < nr ? a1v - a0v : 0;  // elements around the row's node
+    bool okq[NITEMS];
+#pragma unroll
+    for (int q = 0; q < NITEMS; ++q) okq[q] = jt + q * JS < L;  // the host keeps NITEMS * JS >= L
+    // the entries' packed words (an empty item reads entry 0 and drops it)
     uint32_t pw[NITEMS];
     int64_t tt[NITEMS];
 #pragma unroll
     for (int q = 0; q < NITEMS; ++q) {
-        const int j = jt + q * JS;
-        tt[q] = row * MAXADJ + (j < MAXADJ ? j : MAXADJ - 1);  // padded adjacency rows
+        tt[q] = okq[q] ? static_cast<int64_t>(a0v) + jt + q * JS : 0;
         pw[q] = pk[tt[q]];
     }
     if (t <= NR) rp[t] = rpv;
@@ -1695,10 +1763,6 @@ __device__ __forceinline__ void numeric_block_f32(int64_t r0, int64_t nn, const 
     const int W = rp[nr] - w0;
     const int s0 = rp[r] - w0;
     const int len = rp[r + 1] - rp[r];  // 0 for rows past the end
-    const int L = r < nr ? alv : 0;     // elements around the row's node
-    bool okq[NITEMS];
-#pragma unroll
-    for (int q = 0; q < NITEMS; ++q) okq[q] = jt + q * JS < L;  // the host keeps NITEMS * JS >= L
 
     // coefficients of the thread's entries (their loads overlap the slot passes)
     float ckq[NITEMS], cmq0[NITEMS];
@@ -1888,23 +1952,23 @@ constexpr int numeric32_waves() {
 template <int DIM, typename T, bool COEF, int NR, int QN = 0>
 __global__ __launch_bounds__(NBT) void k_numeric(int64_t nn, const double* __restrict__ coords,
                                                  const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
-                                                 const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
+                                                 const int32_t* __restrict__ aptr, const int32_t* __restrict__ adj,
                                                  const uint32_t* __restrict__ pk, const T* __restrict__ cK,
                                                  const T* __restrict__ cM, T* __restrict__ valsK, T* __restrict__ valsM,
                                                  Fallback fb, int64_t* d_counters, int wmax) {
-    numeric_block<DIM, T, COEF, NR, QN>(static_cast<int64_t>(blockIdx.x) * NR, nn, coords, row_ptr, col_idx, adj_len,
+    numeric_block<DIM, T, COEF, NR, QN>(static_cast<int64_t>(blockIdx.x) * NR, nn, coords, row_ptr, col_idx, aptr,
                                         adj, pk, cK, cM, valsK, valsM, fb, d_counters, wmax);
 }
 
 template <int DIM, bool COEF, int NR, int NT, int QN = 0>
 __global__ __launch_bounds__(NT, (numeric32_waves<QN, COEF, NR>())) void k_numeric32(
     int64_t nn, const double* __restrict__ coords, const int32_t* __restrict__ row_ptr,
-    const int32_t* __restrict__ col_idx, const int32_t* __restrict__ adj_len, const int32_t* __restrict__ adj,
+    const int32_t* __restrict__ col_idx, const int32_t* __restrict__ aptr, const int32_t* __restrict__ adj,
     const uint32_t* __restrict__ pk, const int32_t* __restrict__ dpos, const float* __restrict__ cK,
     const float* __restrict__ cM, float* __restrict__ valsK, float* __restrict__ valsM, Fallback fb,
     int64_t* d_counters, int wmax) {
     numeric_block_f32<DIM, COEF, NR, NT, QN>(static_cast<int64_t>(blockIdx.x) * NR, nn, coords, row_ptr, col_idx,
-                                             adj_len, adj, pk, dpos, cK, cM, valsK, valsM, fb, d_counters, wmax);
+                                             aptr, adj, pk, dpos, cK, cM, valsK, valsM, fb, d_counters, wmax);
 }
 
 // block b of a multi-mesh launch belongs to the job whose block range holds b
@@ -1926,7 +1990,7 @@ template <int DIM, int NR>
 __global__ __launch_bounds__(NBT) void k_numeric_jobs(const NumericJob* __restrict__ jobs, int njobs, int wmax) {
     const int64_t b = blockIdx.x;
     const NumericJob& j = job_of_block(jobs, njobs, b);
-    numeric_block<DIM, double, false, NR>((b - j.block0) * NR, j.nn, j.coords, j.row_ptr, j.col_idx, j.adj_len, j.adj,
+    numeric_block<DIM, double, false, NR>((b - j.block0) * NR, j.nn, j.coords, j.row_ptr, j.col_idx, j.aptr, j.adj,
                                           j.pk, nullptr, nullptr, static_cast<double*>(j.valsK),
                                           static_cast<double*>(j.valsM), j.fb, j.counters, wmax);
 }
@@ -1936,7 +2000,7 @@ __global__ __launch_bounds__(NT, (numeric32_waves<0, false, NR>())) void k_numer
     const NumericJob* __restrict__ jobs, int njobs, int wmax) {
     const int64_t b = blockIdx.x;
     const NumericJob& j = job_of_block(jobs, njobs, b);
-    numeric_block_f32<DIM, false, NR, NT>((b - j.block0) * NR, j.nn, j.coords, j.row_ptr, j.col_idx, j.adj_len,
+    numeric_block_f32<DIM, false, NR, NT>((b - j.block0) * NR, j.nn, j.coords, j.row_ptr, j.col_idx, j.aptr,
                                           j.adj, j.pk, j.dpos, nullptr, nullptr, static_cast<float*>(j.valsK),
                                           static_cast<float*>(j.valsM), j.fb, j.counters, wmax);
 }
@@ -1944,19 +2008,88 @@ __global__ __launch_bounds__(NT, (numeric32_waves<0, false, NR>())) void k_numer
 // ---------------------------------------------------------------------------- host
 namespace {
 
+// Device memory of the structures comes from one stream-ordered memory pool per device that
+// keeps released blocks for reuse (no release threshold): a build after another structure
+// was released takes its pages back without mapping new ones, and a release enqueued on a
+// stream (hipFreeAsync) waits for no device work.  pf_csr_destroy trims the pool.
+constexpr int MAX_POOL_DEVICES = 64;
+std::mutex g_pool_mu;
+hipMemPool_t g_pool[MAX_POOL_DEVICES] = {};
+
+pf_status pool_of_current(hipMemPool_t* out) {
+    int dev = 0;
+    PF_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_POOL_DEVICES) return fail(PF_EINVAL, "device index beyond the pool table");
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (!g_pool[dev]) {
+        hipMemPoolProps props = {};
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        hipMemPool_t pool = nullptr;
+        PF_HIP_TRY(hipMemPoolCreate(&pool, &props));
+        uint64_t keep = UINT64_MAX;
+        PF_HIP_TRY(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+        g_pool[dev] = pool;
+    }
+    *out = g_pool[dev];
+    return PF_OK;
+}
+
+// an array of `need` elements on stream s; an existing smaller one is released first (after
+// a device synchronisation: work on any stream may still read it)
 template <typename P>
-pf_status grow(P*& p, int64_t& cap, int64_t need) {
+pf_status grow(P*& p, int64_t& cap, int64_t need, hipStream_t s) {
     if (need <= cap && p) return PF_OK;
     if (p) {
-        PF_HIP_TRY(hipFree(p));
+        PF_HIP_TRY(hipDeviceSynchronize());
+        PF_HIP_TRY(hipFreeAsync(p, s));
         p = nullptr;
     }
     cap = 0;
+    hipMemPool_t pool = nullptr;
+    if (pf_status st = pool_of_current(&pool)) return st;
     const size_t bytes = sizeof(P) * static_cast<size_t>(need > 0 ? need : 1);
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), bytes);
-    if (e != hipSuccess) return fail(PF_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+    hipError_t e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&p), bytes, pool, s);
+    if (e != hipSuccess) {
+        p = nullptr;
+        return fail(PF_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+    }
     cap = need;
     return PF_OK;
+}
+
+// release an array in the order of stream s
+template <typename P>
+void drop(P*& p, int64_t& cap, hipStream_t s) {
+    if (p) (void)hipFreeAsync(p, s);
+    p = nullptr;
+    cap = 0;
+}
+
+// pinned host words for the status readbacks, recycled across handles (pinning and unpinning
+// host memory is slow, and its release may wait for the device)
+std::mutex g_pin_mu;
+std::vector<int64_t*> g_pin_free;
+
+pf_status pinned_words(int64_t** out) {
+    {
+        std::lock_guard<std::mutex> lk(g_pin_mu);
+        if (!g_pin_free.empty()) {
+            *out = g_pin_free.back();
+            g_pin_free.pop_back();
+            return PF_OK;
+        }
+    }
+    PF_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(out), INFO_WORDS * sizeof(int64_t)));
+    return PF_OK;
+}
+
+void recycle_pinned(int64_t* p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    g_pin_free.push_back(p);
 }
 
 unsigned flat_grid(int64_t n) {
@@ -1980,7 +2113,7 @@ pf_status launch_numeric(const pf_csr* c, const double* coords, const void* cK, 
     const size_t shm = numeric_lds_bytes<DIM, T>(NRB, wmax);
     const unsigned g = static_cast<unsigned>(ceil_div(c->nn, NRB));
     hipLaunchKernelGGL((k_numeric<DIM, T, COEF, NRB, QN>), dim3(g), dim3(NBT), shm, s, c->nn, coords, c->row_ptr,
-                       c->col_idx, c->adj_len, c->adj, c->pk, static_cast<const T*>(cK), static_cast<const T*>(cM),
+                       c->col_idx, c->aptr, c->adj, c->pk, static_cast<const T*>(cK), static_cast<const T*>(cM),
                        static_cast<T*>(valsK), static_cast<T*>(valsM), f, ctr, wmax);
     return launch_check("pf_assemble");
 }
@@ -2024,7 +2157,7 @@ pf_status launch_numeric32(const pf_csr* c, const double* coords, const void* cK
     const size_t shm = numeric_lds_bytes_f32<DIM>(NR, wmax);
     const unsigned g = static_cast<unsigned>(ceil_div(c->nn, NR));
     hipLaunchKernelGGL((k_numeric32<DIM, COEF, NR, NT32, QN>), dim3(g), dim3(NT32), shm, s, c->nn, coords, c->row_ptr,
-                       c->col_idx, c->adj_len, c->adj, c->pk, c->dpos, static_cast<const float*>(cK),
+                       c->col_idx, c->aptr, c->adj, c->pk, c->dpos, static_cast<const float*>(cK),
                        static_cast<const float*>(cM), static_cast<float*>(valsK), static_cast<float*>(valsM), f, ctr,
                        wmax);
     return launch_check("pf_assemble");
@@ -2096,7 +2229,7 @@ void numeric_describe(const pf_csr* c, const double* coords, void* valsK, void* 
     out->coords = coords;
     out->row_ptr = c->row_ptr;
     out->col_idx = c->col_idx;
-    out->adj_len = c->adj_len;
+    out->aptr = c->aptr;
     out->adj = c->adj;
     out->pk = c->pk;
     out->dpos = c->dpos;
@@ -2150,10 +2283,10 @@ pf_status numeric_launch_many(int dim, pf_dtype prec, int nr, const NumericJob* 
 }
 
 size_t csr_bytes(const pf_csr* c) {
-    return static_cast<size_t>(c->cap_adj_len + c->cap_row_ptr + c->cap_cnt + c->cap_adj + c->cap_nnz + c->cap_colblk) * 4 +
-           static_cast<size_t>(c->cap_pk) * 4 + static_cast<size_t>(c->cap_bsum + c->cap_info + c->cap_work + c->cap_look + c->cap_pk2) * 8 +
+    return static_cast<size_t>(c->cap_scratch + c->cap_res) + static_cast<size_t>(c->cap_nnz) * 4 +
+           static_cast<size_t>(c->cap_work) * 8 +
            static_cast<size_t>(c->cap_fcount + c->cap_bcount + c->cap_fptr + c->cap_bptr + c->cap_faces + c->cap_fel +
-                               c->cap_bfaces + c->cap_bel + c->cap_dpos) * 4 + static_cast<size_t>(c->cap_finfo) * 8 +
+                               c->cap_bfaces + c->cap_bel) * 4 + static_cast<size_t>(c->cap_finfo) * 8 +
            static_cast<size_t>(c->cap_esign);
 }
 
@@ -2170,7 +2303,7 @@ bool csr_view(const pf_csr* c, CsrView* v) {
     v->dim = c->dim;
     v->nlb = c->nlb;
     v->row_ptr = c->row_ptr;
-    v->adj_len = c->adj_len;
+    v->aptr = c->aptr;
     v->adj = c->adj;
     v->pk = c->p2 ? nullptr : c->pk;
     v->pk2 = c->p2 ? c->pk2 : nullptr;
@@ -2182,13 +2315,54 @@ bool csr_view(const pf_csr* c, CsrView* v) {
     return true;
 }
 const int32_t* csr_adj(const pf_csr* c) { return c->adj; }
-const int32_t* csr_adj_len(const pf_csr* c) { return c->adj_len; }
+const int32_t* csr_aptr(const pf_csr* c) { return c->aptr; }
 
-pf_status csr_workspace(pf_csr* c, int64_t words, double** out) {
+pf_status csr_order(const pf_csr* c, hipStream_t s) {
+    if (!c->cols_pending) return PF_OK;
+    const hipError_t e = hipEventQuery(c->ready);
+    if (e == hipSuccess) {
+        c->cols_pending = false;
+        return PF_OK;
+    }
+    if (e != hipErrorNotReady) return fail(PF_EHIP, std::string("structure build: ") + hipGetErrorString(e));
+    if (s != c->q_stream) PF_HIP_TRY(hipStreamWaitEvent(s, c->ready, 0));
+    return PF_OK;
+}
+
+pf_status csr_workspace(pf_csr* c, int64_t words, double** out, hipStream_t s) {
     pf_status st;
-    if ((st = grow(reinterpret_cast<double*&>(c->work), c->cap_work, words))) return st;
+    if ((st = grow(reinterpret_cast<double*&>(c->work), c->cap_work, words, s))) return st;
     *out = static_cast<double*>(c->work);
     return PF_OK;
+}
+
+void csr_pool_trim() {
+    hipMemPool_t pool = nullptr;
+    if (pool_of_current(&pool) == PF_OK) (void)hipMemPoolTrimTo(pool, 0);
+}
+
+void csr_release(pf_csr* c, hipStream_t s) {
+    if (!c) return;
+    if ((c->stage != 0 || c->cols_pending) && c->ready) (void)hipEventSynchronize(c->ready);  // a build in flight
+    for (hipEvent_t& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    drop(c->scratch, c->cap_scratch, s);
+    drop(c->res, c->cap_res, s);
+    drop(c->col_idx, c->cap_nnz, s);
+    drop(c->work, c->cap_work, s);
+    drop(c->fcount, c->cap_fcount, s);
+    drop(c->bcount, c->cap_bcount, s);
+    drop(c->fptr, c->cap_fptr, s);
+    drop(c->bptr, c->cap_bptr, s);
+    drop(c->faces, c->cap_faces, s);
+    drop(c->fel, c->cap_fel, s);
+    drop(c->bfaces, c->cap_bfaces, s);
+    drop(c->bel, c->cap_bel, s);
+    drop(c->esign, c->cap_esign, s);
+    drop(c->finfo, c->cap_finfo, s);
+    if (c->ready) (void)hipEventDestroy(c->ready);
+    recycle_pinned(c->hinfo);
+    delete c;
 }
 
 }  // namespace pf
@@ -2206,38 +2380,26 @@ pf_status pf_csr_create(pf_csr** out) {
 
 void pf_csr_destroy(pf_csr* c) {
     if (!c) return;
-    for (hipEvent_t& e : c->ev)
-        if (e) (void)hipEventDestroy(e);
-    (void)hipFree(c->adj_len);
-    (void)hipFree(c->adj);
-    (void)hipFree(c->pk);
-    (void)hipFree(c->row_ptr);
-    (void)hipFree(c->col_idx);
-    (void)hipFree(c->cnt);
-    (void)hipFree(c->colblk);
-    (void)hipFree(c->look);
-    (void)hipFree(c->pk2);
-    (void)hipFree(c->bsum);
-    (void)hipFree(c->info);
-    (void)hipFree(c->work);
-    for (int32_t* q : {c->fcount, c->bcount, c->fptr, c->bptr, c->faces, c->fel, c->bfaces, c->bel, c->dpos})
-        (void)hipFree(q);
-    (void)hipFree(c->esign);
-    (void)hipFree(c->finfo);
-    if (c->ready) (void)hipEventDestroy(c->ready);
-    if (c->hinfo) (void)hipHostFree(c->hinfo);
-    delete c;
+    // nothing may still read the arrays (as hipFree would, wait for the whole device)
+    (void)hipDeviceSynchronize();
+    csr_release(c, nullptr);
+    (void)hipStreamSynchronize(nullptr);
+    csr_pool_trim();
 }
 
 namespace {
 // add the stage times of the last timed call to the sums
+// the events that open and close each stage: the first three follow each other on the
+// stream; the columns open when the host enqueues them, after the status readback
+constexpr int STAGE_EV[PF_CSR_STAGES][2] = {{0, 1}, {1, 2}, {2, 3}, {4, 5}};
+
 pf_status collect_stage_times(pf_csr* c) {
     if (!c->pending) return PF_OK;
     c->pending = false;
-    PF_HIP_TRY(hipEventSynchronize(c->ev[PF_CSR_STAGES]));
+    PF_HIP_TRY(hipEventSynchronize(c->ev[PF_CSR_STAGES + 1]));
     for (int k = 0; k < PF_CSR_STAGES; ++k) {
         float ms = 0.0f;
-        PF_HIP_TRY(hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]));
+        PF_HIP_TRY(hipEventElapsedTime(&ms, c->ev[STAGE_EV[k][0]], c->ev[STAGE_EV[k][1]]));
         c->stage_ms[k] += ms;
     }
     ++c->stage_calls;
@@ -2272,7 +2434,14 @@ pf_status pf_csr_stage_times(pf_csr* c, double* ms, int64_t* calls) {
 }
 
 namespace {
-// the structure of a P1 (nlb = dim + 1) or P2 (nlb = 6, 10) mesh
+// The structure of a P1 (nlb = dim + 1) or P2 (nlb = 6, 10) mesh, in two phases.  Phase 1
+// (symbolic_enqueue): the adjacency scattered into padded rows, its offsets (a scan of the
+// lengths), the row patterns (every 8-row group's sorted columns, the compact adjacency with
+// the packed slot words of its entries, the diagonal positions), the row offsets, nnz and
+// the launch statistics; it ends with the status words' copy to pinned host memory and the
+// ready event.  Phase 2 (symbolic_columns, once the host holds nnz): col_idx allocated for
+// exactly nnz words, the columns moved into it, the build's scratch released; it ends with
+// the ready event again.  Every step is enqueued on one stream; nothing waits in between.
 pf_status symbolic_enqueue(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const int32_t* elems, void* stream,
                            const char* who) {
     const bool p2 = nlb > dim + 1;
@@ -2281,117 +2450,155 @@ pf_status symbolic_enqueue(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, 
         return fail(PF_ELIMIT, std::string(who) + ": mesh too large for 32-bit indices");
     if (ne > 0 && !elems) return fail(PF_EINVAL, std::string(who) + ": null elems");
     hipStream_t s = as_stream(stream);
-    if (c->enqueued) {  // an unfinished earlier build: its status is dropped
+    if (c->stage != 0) {  // an unfinished earlier build: its status is dropped
         PF_HIP_TRY(hipEventSynchronize(c->ready));
-        c->enqueued = false;
+        c->stage = 0;
     }
+    pf_status st;
+    if ((st = csr_order(c, s))) return st;  // the previous build's columns, on another stream
     c->built = false;
     c->faces_built = false;
     const int64_t m = ne * nlb;
-    pf_status st;
     if ((st = collect_stage_times(c))) return st;  // the previous call's events are reused below
-    if ((st = grow(c->adj_len, c->cap_adj_len, nn + 1))) return st;
-    if ((st = grow(c->row_ptr, c->cap_row_ptr, nn + 1))) return st;
-    if ((st = grow(c->adj, c->cap_adj, nn * MAXADJ))) return st;
-    if (p2) {
-        if ((st = grow(c->pk2, c->cap_pk2, nn * MAXADJ))) return st;
-    } else {
-        if ((st = grow(c->pk, c->cap_pk, nn * MAXADJ))) return st;
+    auto part = [](int64_t bytes) { return (std::max<int64_t>(bytes, 1) + 255) & ~int64_t(255); };
+    {
+        const int64_t nb = std::max<int64_t>(ceil_div(nn + 1, SCAN_TILE), 1);
+        const int64_t b_rows = part(4 * (nn + 1)), b_adj = part(4 * m), b_pk = part((p2 ? 8 : 4) * m);
+        const int64_t b_bsum = part(8 * nb), b_info = part(8 * INFO_WORDS);
+        if ((st = grow(c->res, c->cap_res, 3 * b_rows + b_adj + b_pk + b_bsum + b_info, s))) return st;
+        unsigned char* q = c->res;
+        c->aptr = reinterpret_cast<int32_t*>(q);
+        c->row_ptr = reinterpret_cast<int32_t*>(q + b_rows);
+        c->dpos = reinterpret_cast<int32_t*>(q + 2 * b_rows);
+        q += 3 * b_rows;
+        c->adj = reinterpret_cast<int32_t*>(q);
+        c->pk = p2 ? nullptr : reinterpret_cast<uint32_t*>(q + b_adj);
+        c->pk2 = p2 ? reinterpret_cast<uint64_t*>(q + b_adj) : nullptr;
+        c->bsum = reinterpret_cast<int64_t*>(q + b_adj + b_pk);
+        c->info = reinterpret_cast<int64_t*>(q + b_adj + b_pk + b_bsum);
     }
-    const int64_t nb = std::max<int64_t>(ceil_div(nn + 1, SCAN_TILE), 1);
-    if ((st = grow(c->bsum, c->cap_bsum, nb))) return st;
-    if ((st = grow(c->info, c->cap_info, INFO_WORDS))) return st;
+    const int64_t tiles = ceil_div(nn, SCAN_TILE);
+    {
+        // every 8-row group's sorted columns wait at the start of its region of colblk (P1
+        // pattern blocks of 32 rows write 4 groups; P2 blocks of 16 rows write groups 2b, 2b + 1);
+        // look: tile descriptors, then TSTAT int32 statistics per tile
+        const int64_t regions = p2 ? 2 * ceil_div(nn, RR2) : (PR / RR) * ceil_div(nn, PR);
+        const int64_t b_len = part(4 * (nn + 1)), b_pad = part(4 * nn * MAXADJ), b_cnt = part(4 * (nn + 1));
+        const int64_t b_blk = part(4 * std::max<int64_t>(regions * RR * maxrow, 1));
+        const int64_t b_look = part(8 * ((1 + TSTAT / 2) * std::max<int64_t>(tiles, 1) + 1));
+        if ((st = grow(c->scratch, c->cap_scratch, b_len + b_pad + b_cnt + b_blk + b_look, s))) return st;
+        unsigned char* q = c->scratch;
+        c->adj_len = reinterpret_cast<int32_t*>(q);
+        c->adj_pad = reinterpret_cast<int32_t*>(q + b_len);
+        c->cnt = reinterpret_cast<int32_t*>(q + b_len + b_pad);
+        c->colblk = reinterpret_cast<int32_t*>(q + b_len + b_pad + b_cnt);
+        c->look = reinterpret_cast<uint64_t*>(q + b_len + b_pad + b_cnt + b_blk);
+    }
+    if (!c->hinfo && (st = pinned_words(&c->hinfo))) return st;
     if ((st = mark(c, 0, s))) return st;
     hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, c->info, int64_t(INFO_WORDS), int64_t(0));
     if (nn > 0) hipLaunchKernelGGL(k_fill_i32, dim3(flat_grid(nn)), dim3(SBS), 0, s, c->adj_len, nn, 0);
     const unsigned gtile = static_cast<unsigned>(std::max<int64_t>(ceil_div(m, AG_TILE), 1));
     if (m > 0) {
         if (p2)
-            hipLaunchKernelGGL(k_scatter<4>, dim3(gtile), dim3(AG_BS), 0, s, elems, m, nlb, nn, c->adj_len, c->adj,
+            hipLaunchKernelGGL(k_scatter<4>, dim3(gtile), dim3(AG_BS), 0, s, elems, m, nlb, nn, c->adj_len, c->adj_pad,
                                c->info);
         else
-            hipLaunchKernelGGL(k_scatter<2>, dim3(gtile), dim3(AG_BS), 0, s, elems, m, nlb, nn, c->adj_len, c->adj,
+            hipLaunchKernelGGL(k_scatter<2>, dim3(gtile), dim3(AG_BS), 0, s, elems, m, nlb, nn, c->adj_len, c->adj_pad,
                                c->info);
     }
-    if ((st = grow(c->dpos, c->cap_dpos, nn + 1))) return st;
-    if (!c->hinfo) PF_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hinfo), INFO_WORDS * sizeof(int64_t)));
-    int64_t* info = c->hinfo;  // pinned: a direct copy, no staging through pageable memory
-    {
-        const int64_t tiles = ceil_div(nn, SCAN_TILE);
-        // nnz is known only after the pattern: col_idx holds maxrow columns per row, and every
-        // 8-row group's sorted columns wait at the start of its region of colblk (P1 pattern
-        // blocks of 32 rows write 4 groups; P2 blocks of 16 rows write groups 2b and 2b + 1)
-        const int64_t regions = p2 ? 2 * ceil_div(nn, RR2) : (PR / RR) * ceil_div(nn, PR);
-        if ((st = grow(c->cnt, c->cap_cnt, nn + 1))) return st;
-        if ((st = grow(c->colblk, c->cap_colblk, std::max<int64_t>(regions * RR * maxrow, 1)))) return st;
-        if ((st = grow(c->col_idx, c->cap_nnz, std::max<int64_t>(nn * maxrow, 1)))) return st;
-        // tile descriptors, then TSTAT int32 statistics per tile
-        if ((st = grow(c->look, c->cap_look, (1 + TSTAT / 2) * std::max<int64_t>(tiles, 1) + 1))) return st;
-        if ((st = mark(c, 1, s))) return st;
-        if (nn > 0) {
-            const unsigned g1 = static_cast<unsigned>(ceil_div(nn, PR));   // P1: 32-row blocks
-            const unsigned g2 = static_cast<unsigned>(ceil_div(nn, RR2));  // P2: 16-row blocks
-            if (nlb == 10)
-                hipLaunchKernelGGL((k_pattern_p2<10>), dim3(g2), dim3(RT2), 0, s, nn, elems, c->adj_len, c->adj,
-                                   c->cnt, c->colblk, c->pk2, c->dpos, c->info);
-            else if (nlb == 6)
-                hipLaunchKernelGGL((k_pattern_p2<6>), dim3(g2), dim3(RT2), 0, s, nn, elems, c->adj_len, c->adj,
-                                   c->cnt, c->colblk, c->pk2, c->dpos, c->info);
-            else if (nlb == 4)
-                hipLaunchKernelGGL((k_rows_p1<4>), dim3(g1), dim3(PT), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
-                                   c->colblk, c->pk, c->dpos, c->info);
-            else
-                hipLaunchKernelGGL((k_rows_p1<3>), dim3(g1), dim3(PT), 0, s, nn, elems, c->adj_len, c->adj, c->cnt,
-                                   c->colblk, c->pk, c->dpos, c->info);
-        }
-        if ((st = mark(c, 2, s))) return st;
-        if (nn > 0) {
-            hipLaunchKernelGGL(k_fill_i64, dim3(flat_grid(tiles)), dim3(SBS), 0, s, reinterpret_cast<int64_t*>(c->look),
-                               tiles, int64_t(0));
-            int32_t* tstat = reinterpret_cast<int32_t*>(c->look + ((tiles + 1) & ~int64_t(1)));  // 16-byte aligned
-            if (p2)
-                hipLaunchKernelGGL((k_row_offsets<RR * MAXROW2, 4>), dim3(static_cast<unsigned>(tiles)), dim3(SBS), 0,
-                                   s, nn, c->cnt, c->adj_len, c->colblk, c->row_ptr, c->col_idx, c->look, tstat,
-                                   c->info);
-            else
-                hipLaunchKernelGGL((k_row_offsets<RR * MAXROW, 2>), dim3(static_cast<unsigned>(tiles)), dim3(SBS), 0,
-                                   s, nn, c->cnt, c->adj_len, c->colblk, c->row_ptr, c->col_idx, c->look, tstat,
-                                   c->info);
-            hipLaunchKernelGGL(k_row_stats, dim3(1), dim3(SBS), 0, s, tiles, tstat, c->info);
-        } else {
-            hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, c->row_ptr, int64_t(1), 0);
-        }
-        if ((st = mark(c, 3, s))) return st;
-        if ((st = launch_check(who))) return st;
-        c->pending = c->timing;
-        PF_HIP_TRY(hipMemcpyAsync(info, c->info, INFO_WORDS * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        if (!c->ready) PF_HIP_TRY(hipEventCreateWithFlags(&c->ready, hipEventDisableTiming));
-        PF_HIP_TRY(hipEventRecord(c->ready, s));
+    // adjacency offsets (aptr[nn] = the adjacency total, into info[1])
+    if ((st = scan(c->adj_len, nn, c->aptr, c->bsum, c->info + 1, s))) return st;
+    if ((st = mark(c, 1, s))) return st;
+    if (nn > 0) {
+        const unsigned g1 = static_cast<unsigned>(ceil_div(nn, PR));   // P1: 32-row blocks
+        const unsigned g2 = static_cast<unsigned>(ceil_div(nn, RR2));  // P2: 16-row blocks
+        if (nlb == 10)
+            hipLaunchKernelGGL((k_pattern_p2<10>), dim3(g2), dim3(RT2), 0, s, nn, elems, c->adj_len, c->adj_pad,
+                               c->aptr, c->cnt, c->colblk, c->adj, c->pk2, c->dpos, c->info);
+        else if (nlb == 6)
+            hipLaunchKernelGGL((k_pattern_p2<6>), dim3(g2), dim3(RT2), 0, s, nn, elems, c->adj_len, c->adj_pad,
+                               c->aptr, c->cnt, c->colblk, c->adj, c->pk2, c->dpos, c->info);
+        else if (nlb == 4)
+            hipLaunchKernelGGL((k_rows_p1<4>), dim3(g1), dim3(PT), 0, s, nn, elems, c->adj_len, c->adj_pad, c->aptr,
+                               c->cnt, c->colblk, c->adj, c->pk, c->dpos, c->info);
+        else
+            hipLaunchKernelGGL((k_rows_p1<3>), dim3(g1), dim3(PT), 0, s, nn, elems, c->adj_len, c->adj_pad, c->aptr,
+                               c->cnt, c->colblk, c->adj, c->pk, c->dpos, c->info);
     }
-    c->enqueued = true;
+    if ((st = mark(c, 2, s))) return st;
+    if (nn > 0) {
+        hipLaunchKernelGGL(k_fill_i64, dim3(flat_grid(tiles)), dim3(SBS), 0, s, reinterpret_cast<int64_t*>(c->look),
+                           tiles, int64_t(0));
+        int32_t* tstat = reinterpret_cast<int32_t*>(c->look + ((tiles + 1) & ~int64_t(1)));  // 16-byte aligned
+        hipLaunchKernelGGL(k_row_offsets, dim3(static_cast<unsigned>(tiles)), dim3(SBS), 0, s, nn, c->cnt, c->adj_len,
+                           c->row_ptr, c->look, tstat, c->info);
+        hipLaunchKernelGGL(k_row_stats, dim3(1), dim3(SBS), 0, s, tiles, tstat, c->info);
+    } else {
+        hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, c->row_ptr, int64_t(1), 0);
+    }
+    if ((st = mark(c, 3, s))) return st;
+    if ((st = launch_check(who))) return st;
+    c->pending = c->timing;
+    // pinned: a direct copy, no staging through pageable memory
+    PF_HIP_TRY(hipMemcpyAsync(c->hinfo, c->info, INFO_WORDS * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (!c->ready) PF_HIP_TRY(hipEventCreateWithFlags(&c->ready, hipEventDisableTiming));
+    PF_HIP_TRY(hipEventRecord(c->ready, s));
+    c->stage = 1;
     c->q_dim = dim;
     c->q_nlb = nlb;
     c->q_nn = nn;
     c->q_ne = ne;
+    c->q_stream = s;
     return PF_OK;
 }
 
-// the second half of a build: its status words have reached the host (the ready event has
-// completed); check them and fix the structure's sizes and launch statistics
-pf_status symbolic_finish(pf_csr* c, const char* who) {
-    c->enqueued = false;
+// the build's scratch, released in the order of its stream
+void drop_scratch(pf_csr* c, hipStream_t s) {
+    drop(c->scratch, c->cap_scratch, s);
+    c->adj_len = c->adj_pad = c->cnt = c->colblk = nullptr;
+    c->look = nullptr;
+}
+
+// phase 2: phase 1's status words have reached the host (its ready event has completed);
+// check them, fix the structure's sizes and launch statistics, and enqueue the columns
+pf_status symbolic_columns(pf_csr* c, const char* who) {
+    c->stage = 0;
+    hipStream_t s = c->q_stream;
     const int64_t* info = c->hinfo;
     const int dim = c->q_dim, nlb = c->q_nlb;
     const int64_t nn = c->q_nn, ne = c->q_ne;
     const bool p2 = nlb > dim + 1;
     const int maxrow = p2 ? MAXROW2 : MAXROW;
-    if (info[0] & ERR_INDEX) return fail(PF_EINDEX, std::string(who) + ": node index out of range in elems");
-    if (info[0] & ERR_ROW)
-        return fail(PF_ELIMIT, std::string(who) + ": a node belongs to more than 64 elements or a row has more than " +
-                                   std::to_string(maxrow) + " nonzeros");
-    if (info[0] & ERR_SCAN) return fail(PF_EINVAL, std::string(who) + ": the row offsets could not be formed");
-    if (info[2] >= INT32_MAX) return fail(PF_ELIMIT, std::string(who) + ": nnz must be < 2^31");
+    pf_status st = PF_OK;
+    if (info[0] & ERR_INDEX) st = fail(PF_EINDEX, std::string(who) + ": node index out of range in elems");
+    else if (info[0] & ERR_ROW)
+        st = fail(PF_ELIMIT, std::string(who) + ": a node belongs to more than 64 elements or a row has more than " +
+                                 std::to_string(maxrow) + " nonzeros");
+    else if (info[0] & ERR_SCAN) st = fail(PF_EINVAL, std::string(who) + ": the row offsets could not be formed");
+    else if (info[2] >= INT32_MAX) st = fail(PF_ELIMIT, std::string(who) + ": nnz must be < 2^31");
     const int64_t nnz = info[2];
+    if (st == PF_OK) st = grow(c->col_idx, c->cap_nnz, std::max<int64_t>(nnz, 1), s);
+    if (st != PF_OK) {
+        c->pending = false;  // the stage events of this call are incomplete
+        drop_scratch(c, s);
+        return st;
+    }
+    if ((st = mark(c, 4, s))) return st;
+    if (nn > 0) {
+        const unsigned tiles = static_cast<unsigned>(ceil_div(nn, SCAN_TILE));
+        if (p2)
+            hipLaunchKernelGGL((k_row_columns<RR * MAXROW2, 4>), dim3(tiles), dim3(SBS), 0, s, nn, c->row_ptr,
+                               c->colblk, c->col_idx);
+        else
+            hipLaunchKernelGGL((k_row_columns<RR * MAXROW, 2>), dim3(tiles), dim3(SBS), 0, s, nn, c->row_ptr,
+                               c->colblk, c->col_idx);
+    }
+    if ((st = mark(c, 5, s))) return st;
+    if ((st = launch_check(who))) return st;
+    drop_scratch(c, s);
+    PF_HIP_TRY(hipEventRecord(c->ready, s));
+    c->stage = 2;
     c->dim = dim;
     c->nlb = nlb;
     c->p2 = p2;
@@ -2404,7 +2611,6 @@ pf_status symbolic_finish(pf_csr* c, const char* who) {
     c->max_adj = static_cast<int>(info[7]);
     c->wmax8 = static_cast<int>(info[8]);
     c->wmax2 = static_cast<int>(info[9]);
-    c->built = true;
     return PF_OK;
 }
 
@@ -2413,7 +2619,13 @@ pf_status symbolic(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const in
     pf_status st = symbolic_enqueue(c, dim, nlb, nn, ne, elems, stream, who);
     if (st != PF_OK) return st;
     PF_HIP_TRY(hipEventSynchronize(c->ready));
-    return symbolic_finish(c, who);
+    if ((st = symbolic_columns(c, who))) return st;
+    // the columns complete in the order of the stream: no wait here (csr_order orders the
+    // work of other streams after them)
+    c->stage = 0;
+    c->built = true;
+    c->cols_pending = true;
+    return PF_OK;
 }
 }  // namespace
 
@@ -2421,23 +2633,34 @@ pf_status symbolic(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const in
 
 namespace pf {
 pf_status csr_symbolic_enqueue(pf_csr* c, int dim, int64_t nn, int64_t ne, const int32_t* elems, hipStream_t s) {
-    if (dim != 2 && dim != 3) return fail(PF_EORDER, "pf_server: dim must be 2 or 3");
+    if (dim != 2 && dim != 3) return fail(PF_EORDER, "pf_server build: dim must be 2 or 3");
     return symbolic_enqueue(c, dim, dim + 1, nn, ne, elems, s, "pf_server build");
 }
 
 int csr_symbolic_poll(pf_csr* c, pf_status* st) {
-    if (!c->enqueued) {
+    if (c->stage == 0) {
         *st = c->built ? PF_OK : fail(PF_ESTATE, "pf_server build: nothing enqueued");
         return 1;
     }
     const hipError_t e = hipEventQuery(c->ready);
     if (e == hipErrorNotReady) return 0;
     if (e != hipSuccess) {
-        c->enqueued = false;
+        c->stage = 0;
         *st = fail(PF_EHIP, std::string("pf_server build: ") + hipGetErrorString(e));
         return 1;
     }
-    *st = symbolic_finish(c, "pf_server build");
+    if (c->stage == 1) {  // the pattern phase ended: the columns follow
+        const pf_status s1 = symbolic_columns(c, "pf_server build");
+        if (s1 != PF_OK) {
+            c->stage = 0;
+            *st = s1;
+            return 1;
+        }
+        return 0;
+    }
+    c->stage = 0;
+    c->built = true;
+    *st = PF_OK;
     return 1;
 }
 
@@ -2474,6 +2697,7 @@ pf_status pf_assemble_quad(const pf_csr* c, pf_dtype prec, const double* coords,
     if (!coords || !valsK) return fail(PF_EINVAL, "pf_assemble_quad: null coords or valsK");
     if (prec != PF_F32 && prec != PF_F64) return fail(PF_EDTYPE, "pf_assemble_quad: prec must be PF_F32 or PF_F64");
     hipStream_t s = as_stream(stream);
+    if (pf_status st = csr_order(c, s)) return st;
     Fallback f = make_fallback(fb);
     if (c->dim == 3) {
         if (prec == PF_F32)
@@ -2495,15 +2719,16 @@ pf_status pf_csr_faces(pf_csr* c, const double* coords, const int32_t* elems, vo
     if (c->p2) return fail(PF_ESTATE, "pf_csr_faces: a P2 structure");
     if (c->ne > 0 && (!coords || !elems)) return fail(PF_EINVAL, "pf_csr_faces: null coords or elems");
     hipStream_t s = as_stream(stream);
+    if (pf_status st = csr_order(c, s)) return st;
     c->faces_built = false;
     const int64_t nn = c->nn;
     pf_status st;
-    if ((st = grow(c->fcount, c->cap_fcount, nn + 1))) return st;
-    if ((st = grow(c->bcount, c->cap_bcount, nn + 1))) return st;
-    if ((st = grow(c->fptr, c->cap_fptr, nn + 1))) return st;
-    if ((st = grow(c->bptr, c->cap_bptr, nn + 1))) return st;
-    if ((st = grow(c->finfo, c->cap_finfo, 4))) return st;
-    if ((st = grow(c->esign, c->cap_esign, std::max<int64_t>(c->ne, 1)))) return st;
+    if ((st = grow(c->fcount, c->cap_fcount, nn + 1, s))) return st;
+    if ((st = grow(c->bcount, c->cap_bcount, nn + 1, s))) return st;
+    if ((st = grow(c->fptr, c->cap_fptr, nn + 1, s))) return st;
+    if ((st = grow(c->bptr, c->cap_bptr, nn + 1, s))) return st;
+    if ((st = grow(c->finfo, c->cap_finfo, 4, s))) return st;
+    if ((st = grow(c->esign, c->cap_esign, std::max<int64_t>(c->ne, 1), s))) return st;
     hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, c->finfo, int64_t(4), int64_t(0));
     if (c->ne > 0) {
         const unsigned ge = static_cast<unsigned>(ceil_div(c->ne, SBS));
@@ -2513,17 +2738,17 @@ pf_status pf_csr_faces(pf_csr* c, const double* coords, const int32_t* elems, vo
     const unsigned g = static_cast<unsigned>(std::max<int64_t>(ceil_div(nn, FR), 1));
     if (nn > 0) {
         if (c->nlb == 4)
-            hipLaunchKernelGGL((k_faces<4, 0>), dim3(g), dim3(FT), 0, s, nn, c->row_ptr, c->col_idx, c->adj_len,
+            hipLaunchKernelGGL((k_faces<4, 0>), dim3(g), dim3(FT), 0, s, nn, c->row_ptr, c->col_idx, c->aptr,
                                c->adj, c->pk, c->dpos, c->esign, c->fcount, c->bcount, nullptr, nullptr, nullptr,
                                nullptr, nullptr, nullptr, c->finfo);
         else
-            hipLaunchKernelGGL((k_faces<3, 0>), dim3(g), dim3(FT), 0, s, nn, c->row_ptr, c->col_idx, c->adj_len,
+            hipLaunchKernelGGL((k_faces<3, 0>), dim3(g), dim3(FT), 0, s, nn, c->row_ptr, c->col_idx, c->aptr,
                                c->adj, c->pk, c->dpos, c->esign, c->fcount, c->bcount, nullptr, nullptr, nullptr,
                                nullptr, nullptr, nullptr, c->finfo);
     }
     if ((st = scan(c->fcount, nn, c->fptr, c->bsum, c->finfo + 1, s))) return st;
     if ((st = scan(c->bcount, nn, c->bptr, c->bsum, c->finfo + 2, s))) return st;
-    if (!c->hinfo) PF_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&c->hinfo), INFO_WORDS * sizeof(int64_t)));
+    if (!c->hinfo && (st = pinned_words(&c->hinfo))) return st;
     int64_t* info = c->hinfo;
     PF_HIP_TRY(hipMemcpyAsync(info, c->finfo, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     PF_HIP_TRY(hipStreamSynchronize(s));
@@ -2532,17 +2757,17 @@ pf_status pf_csr_faces(pf_csr* c, const double* coords, const int32_t* elems, vo
     if (info[0] & ERR_ROW) return fail(PF_ELIMIT, "pf_csr_faces: a node owns more than 128 faces");
     const int64_t nf = info[1], nfb = info[2];
     const int nv = c->dim;
-    if ((st = grow(c->faces, c->cap_faces, nf * nv))) return st;
-    if ((st = grow(c->fel, c->cap_fel, 2 * nf))) return st;
-    if ((st = grow(c->bfaces, c->cap_bfaces, nfb * nv))) return st;
-    if ((st = grow(c->bel, c->cap_bel, nfb))) return st;
+    if ((st = grow(c->faces, c->cap_faces, nf * nv, s))) return st;
+    if ((st = grow(c->fel, c->cap_fel, 2 * nf, s))) return st;
+    if ((st = grow(c->bfaces, c->cap_bfaces, nfb * nv, s))) return st;
+    if ((st = grow(c->bel, c->cap_bel, nfb, s))) return st;
     if (nn > 0 && nf > 0) {
         if (c->nlb == 4)
-            hipLaunchKernelGGL((k_faces<4, 1>), dim3(g), dim3(FT), 0, s, nn, c->row_ptr, c->col_idx, c->adj_len,
+            hipLaunchKernelGGL((k_faces<4, 1>), dim3(g), dim3(FT), 0, s, nn, c->row_ptr, c->col_idx, c->aptr,
                                c->adj, c->pk, c->dpos, c->esign, nullptr, nullptr, c->fptr, c->bptr, c->faces,
                                c->fel, c->bfaces, c->bel, c->finfo);
         else
-            hipLaunchKernelGGL((k_faces<3, 1>), dim3(g), dim3(FT), 0, s, nn, c->row_ptr, c->col_idx, c->adj_len,
+            hipLaunchKernelGGL((k_faces<3, 1>), dim3(g), dim3(FT), 0, s, nn, c->row_ptr, c->col_idx, c->aptr,
                                c->adj, c->pk, c->dpos, c->esign, nullptr, nullptr, c->fptr, c->bptr, c->faces,
                                c->fel, c->bfaces, c->bel, c->finfo);
     }
@@ -2569,6 +2794,10 @@ pf_status pf_csr_faces_info(const pf_csr* c, int64_t* nf, int64_t* nfb, const in
 pf_status pf_csr_info(const pf_csr* c, int64_t* nn, int64_t* nnz, const int32_t** row_ptr, const int32_t** col_idx) {
     if (!c) return fail(PF_EINVAL, "pf_csr_info: null handle");
     if (!c->built) return fail(PF_ESTATE, "pf_csr_info: structure not built");
+    if (c->cols_pending) {  // device pointers handed out: the arrays are complete
+        PF_HIP_TRY(hipEventSynchronize(c->ready));
+        c->cols_pending = false;
+    }
     if (nn) *nn = c->nn;
     if (nnz) *nnz = c->nnz;
     if (row_ptr) *row_ptr = c->row_ptr;
@@ -2596,6 +2825,7 @@ pf_status pf_assemble(const pf_csr* c, pf_dtype prec, const double* coords, cons
     (void)elems;  // the structure carries the connectivity it was built from
     if (prec != PF_F32 && prec != PF_F64) return fail(PF_EDTYPE, "pf_assemble: prec must be PF_F32 or PF_F64");
     hipStream_t s = as_stream(stream);
+    if (pf_status st = csr_order(c, s)) return st;
     Fallback f = make_fallback(fb);
     if (prec == PF_F32)
         return c->dim == 3 ? numeric_dispatch<3, float>(c, coords, cK, cM, valsK, valsM, f, d_counters, s)

@@ -89,13 +89,13 @@ __global__ __launch_bounds__(RBS) void k_rhs_elem(int64_t nn, const double* __re
 
 // b[i] = sum of the entries of the elements around node i, exact on the grid of the node's
 // largest entry.  Half a wave per node: lane l reads adjacency entries l and l + 32 of the
-// row (contiguous words) and gathers their local-vector values; the row maximum and then
+// node (contiguous words from aptr[i]) and gathers their local-vector values; the row maximum and then
 // the integer sum of the rounded values are reduced across the 32 lanes with shuffles
 // (integer adds: exact, so the result does not depend on the entry order).  Each half wave
 // takes RHS_ROWS nodes at once, issuing all of their loads before the first reduction.
 constexpr int RHS_ROWS = 8;
 template <typename T>
-__global__ __launch_bounds__(RBS) void k_rhs_nodes(int64_t nn, int nlb, const int32_t* __restrict__ adj_len,
+__global__ __launch_bounds__(RBS) void k_rhs_nodes(int64_t nn, int nlb, const int32_t* __restrict__ aptr,
                                                    const int32_t* __restrict__ adj, const T* __restrict__ b2D,
                                                    T* __restrict__ b) {
     using A = typename Exact<T>::acc;
@@ -106,27 +106,29 @@ __global__ __launch_bounds__(RBS) void k_rhs_nodes(int64_t nn, int nlb, const in
     int L[RHS_ROWS];
     int32_t w0[RHS_ROWS];
     T v0[RHS_ROWS], v1[RHS_ROWS];
-    // the rows' lengths and their first 128 bytes (one line each) are read together: every
-    // word of a padded row is in bounds, and words past the row's length are dropped
-    int32_t Lr[RHS_ROWS];
+    // the rows' adjacency offsets, then their first 32 entries (a lane past its row's
+    // length reads entry 0 and drops it)
+    int32_t a0[RHS_ROWS], a1[RHS_ROWS];
 #pragma unroll
     for (int k = 0; k < RHS_ROWS; ++k) {  // every lane takes part in the shuffles
         i[k] = h * RHS_ROWS + k;
         const int64_t ic = i[k] < nn ? i[k] : nn - 1;
-        Lr[k] = adj_len[ic];
-        w0[k] = adj[ic * CSR_MAXADJ + l];
+        a0[k] = aptr[ic];
+        a1[k] = aptr[ic + 1];
     }
 #pragma unroll
     for (int k = 0; k < RHS_ROWS; ++k) {
-        L[k] = i[k] < nn ? min(Lr[k], CSR_MAXADJ) : 0;
-        w0[k] = l < L[k] ? w0[k] : 0;
+        L[k] = i[k] < nn ? min(a1[k] - a0[k], CSR_MAXADJ) : 0;
+        w0[k] = adj[l < L[k] ? static_cast<int64_t>(a0[k]) + l : 0];
     }
+#pragma unroll
+    for (int k = 0; k < RHS_ROWS; ++k) w0[k] = l < L[k] ? w0[k] : 0;
 #pragma unroll
     for (int k = 0; k < RHS_ROWS; ++k) {
         v0[k] = l < L[k] ? b2D[static_cast<int64_t>(w0[k] >> 2) * nlb + (w0[k] & 3)] : T(0);
         v1[k] = T(0);
         if (l + 32 < L[k]) {  // only nodes with more than 32 elements read the second half
-            const int32_t w1 = adj[i[k] * CSR_MAXADJ + l + 32];
+            const int32_t w1 = adj[static_cast<int64_t>(a0[k]) + l + 32];
             v1[k] = b2D[static_cast<int64_t>(w1 >> 2) * nlb + (w1 & 3)];
         }
     }
@@ -323,6 +325,7 @@ pf_status pf_rhs(const pf_csr* csr, pf_dtype prec, const double* coords, const i
     const int64_t nn = csr_nn(csr), ne = csr_ne(csr);
     if (ne > 0 && (!fq || !b2D)) return fail(PF_EINVAL, "pf_rhs: null fq or b2D");
     hipStream_t s = as_stream(stream);
+    if ((st = csr_order(csr, s))) return st;
     const Fallback f = make_fallback(fb);
     if (ne > 0) {
         if (dim == 3) {
@@ -337,10 +340,10 @@ pf_status pf_rhs(const pf_csr* csr, pf_dtype prec, const double* coords, const i
     if (b && nn > 0) {
         const unsigned g = static_cast<unsigned>(ceil_div(ceil_div(nn, RHS_ROWS) * 32, RBS));  // half waves
         if (prec == PF_F32)
-            hipLaunchKernelGGL(k_rhs_nodes<float>, dim3(g), dim3(RBS), 0, s, nn, dim + 1, csr_adj_len(csr),
+            hipLaunchKernelGGL(k_rhs_nodes<float>, dim3(g), dim3(RBS), 0, s, nn, dim + 1, csr_aptr(csr),
                                csr_adj(csr), static_cast<const float*>(b2D), static_cast<float*>(b));
         else
-            hipLaunchKernelGGL(k_rhs_nodes<double>, dim3(g), dim3(RBS), 0, s, nn, dim + 1, csr_adj_len(csr),
+            hipLaunchKernelGGL(k_rhs_nodes<double>, dim3(g), dim3(RBS), 0, s, nn, dim + 1, csr_aptr(csr),
                                csr_adj(csr), static_cast<const double*>(b2D), static_cast<double*>(b));
         if ((st = launch_check("pf_rhs nodes"))) return st;
     }
@@ -430,7 +433,7 @@ pf_status pf_energies(pf_csr* csr, pf_dtype prec, const double* coords, const in
     pf_status st = energies_check(csr, prec, coords, elems, order, u, "pf_energies", &grid);
     if (st) return st;
     double* part = nullptr;
-    if ((st = csr_workspace(csr, 3 * static_cast<int64_t>(grid), &part))) return st;
+    if ((st = csr_workspace(csr, 3 * static_cast<int64_t>(grid), &part, as_stream(stream)))) return st;
     return energies_into(csr, prec, coords, elems, order, cKq, cMq, u, b2D, J, totals, fb, d_counters,
                          as_stream(stream), part, grid);
 }

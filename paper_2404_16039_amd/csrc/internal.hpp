@@ -13,7 +13,7 @@ struct NumericJob {
     const double* coords;
     const int32_t* row_ptr;
     const int32_t* col_idx;
-    const int32_t* adj_len;
+    const int32_t* aptr;
     const int32_t* adj;
     const uint32_t* pk;
     const int32_t* dpos;
@@ -40,16 +40,17 @@ int64_t csr_nn(const pf_csr* c);
 int csr_dim(const pf_csr* c);
 int64_t csr_ne(const pf_csr* c);
 bool csr_built(const pf_csr* c);  // a built P1 structure
-// a built structure, P1 or P2: adjacency entries (element << 2 | local index) with pk (P1:
-// row positions of the element's other nodes in local order, 8 bits each from bit 2), or
-// (element << 4 | local index) with pk2 (P2: 7 bits each from bit 0); dpos = the diagonal's
+// a built structure, P1 or P2: node i's adjacency entries at aptr[i] .. aptr[i+1] of adj,
+// (element << 2 | local index) with pk (P1: row positions of the element's other nodes in
+// local order, 8 bits each from bit 2), or (element << 4 | local index) with pk2 (P2: 7 bits
+// each from bit 0), at most CSR_MAXADJ per node; dpos = the diagonal's
 // position in each row; wmax4 / wmax16 / wmax32 = the largest CSR window of 4 / 16 / 32
 // consecutive rows starting at a multiple of their count; max_adj = the longest adjacency list
 struct CsrView {
     int64_t nn, ne, nnz;
     int dim, nlb;
     const int32_t* row_ptr;
-    const int32_t* adj_len;
+    const int32_t* aptr;
     const int32_t* adj;
     const uint32_t* pk;
     const uint64_t* pk2;
@@ -59,17 +60,28 @@ struct CsrView {
 };
 bool csr_view(const pf_csr* c, CsrView* v);  // false unless built
 // node -> element adjacency of the structure: entries (element << 2 | local index) of node i
-// at adj[i * CSR_MAXADJ ...], adj_len[i] of them
+// at adj[aptr[i]] .. adj[aptr[i+1] - 1], at most CSR_MAXADJ of them
 constexpr int CSR_MAXADJ = 64;
 const int32_t* csr_adj(const pf_csr* c);
-const int32_t* csr_adj_len(const pf_csr* c);
-// asynchronous structure build (the serving loop): csr_symbolic_enqueue issues every step of
-// pf_csr_symbolic on stream s without waiting; csr_symbolic_poll returns 1 once the build's
-// status words have reached the host (*st: its outcome, the structure usable if PF_OK), 0
-// while it runs
+const int32_t* csr_aptr(const pf_csr* c);
+// asynchronous structure build (the serving loop): csr_symbolic_enqueue issues the first
+// phase of pf_csr_symbolic on stream s without waiting; csr_symbolic_poll, called until it
+// returns 1, enqueues the second phase once the first one's status words have reached the
+// host and returns 1 when the build has ended (*st: its outcome, the structure usable on any
+// stream if PF_OK), 0 while it runs
 pf_status csr_symbolic_enqueue(pf_csr* c, int dim, int64_t nn, int64_t ne, const int32_t* elems, hipStream_t s);
 int csr_symbolic_poll(pf_csr* c, pf_status* st);
-// a device workspace of at least `words` doubles owned by the handle (grown when needed)
-pf_status csr_workspace(pf_csr* c, int64_t words, double** out);
+// a device workspace of at least `words` doubles owned by the handle (grown on stream s when
+// needed)
+pf_status csr_workspace(pf_csr* c, int64_t words, double** out, hipStream_t s);
+// pf_csr_destroy without its device-wide wait: the handle's arrays are released in the order
+// of stream s (every earlier use of the structure must be ordered before that point of s, or
+// have completed); a build still in flight is waited for first
+void csr_release(pf_csr* c, hipStream_t s);
+// return the unused blocks of the current device's structure pool to the device
+void csr_pool_trim();
+// order the work about to be enqueued on stream s after the end of the structure's build
+// (pf_csr_symbolic returns with its last phase still in flight on its own stream)
+pf_status csr_order(const pf_csr* c, hipStream_t s);
 
 }  // namespace pf

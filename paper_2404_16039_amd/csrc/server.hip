@@ -58,10 +58,12 @@ struct SJob {
     pf_job spec{};
     pf_job_result res{};
     Topo* topo = nullptr;
+    // assembly jobs: counters, coordinates, K and M values, parts of one allocation d_mem
     double* d_coords = nullptr;
     void* d_valsK = nullptr;
     void* d_valsM = nullptr;
     int64_t* d_ctr = nullptr;
+    void* d_mem = nullptr;
     void* d_pg = nullptr;  // page-op jobs: A, B, inv(A), A*B and det(A) in one allocation
     int slot = -1;  // row of the pinned counter block
     size_t bytes = 0;
@@ -78,13 +80,15 @@ int64_t nnz_bound(const pf_job& j) {
     return std::min<int64_t>(j.ne * nlb * nlb, j.nn * 64);
 }
 
+// device bytes a structure may hold while it is built (its largest moment: the connectivity,
+// the resident arrays and the build's scratch); once built it holds csr_bytes
 size_t topo_estimate(const pf_job& j) {
     if (is_pages(j)) return 0;
-    const int64_t nlb = j.dim + 1;
-    return static_cast<size_t>(j.ne * nlb * 4)                                     // elems
-           + static_cast<size_t>(16 * (j.nn + 1) + 512 * j.nn)  // row arrays, padded adjacency and slot words
-           + static_cast<size_t>(256 * (j.nn + 8))             // col_idx (sized for 64 columns a row)
-           + static_cast<size_t>(256 * (j.nn + 8))             // columns of the row-pattern blocks (scratch)
+    const int64_t m = j.ne * (j.dim + 1);
+    return static_cast<size_t>(4 * m)                        // elems (released when the build ends)
+           + static_cast<size_t>(8 * m + 12 * (j.nn + 1))     // compact adjacency, slot words, offsets, diagonal
+           + static_cast<size_t>(4 * nnz_bound(j))            // col_idx
+           + static_cast<size_t>(520 * (j.nn + 64))           // scratch: padded adjacency, row-pattern columns
            + static_cast<size_t>(j.nn / 256) + 4096;
 }
 
@@ -113,7 +117,7 @@ PageLayout page_layout(const pf_job& j) {
 
 size_t job_estimate(const pf_job& j, int64_t nnz) {
     if (is_pages(j)) return static_cast<size_t>(page_layout(j).total) * elem_bytes(j.prec) + 256;
-    return static_cast<size_t>(j.nn * j.dim * 8) + 2 * static_cast<size_t>(nnz) * elem_bytes(j.prec) + 64;
+    return static_cast<size_t>(j.nn * j.dim * 8) + 2 * static_cast<size_t>(nnz) * elem_bytes(j.prec) + 1280;
 }
 
 }  // namespace
@@ -164,9 +168,11 @@ void account(pf_server* S, long long delta) {
     S->high = std::max(S->high, S->used);
 }
 
+// a structure's memory goes back to the pool in the order of the serving stream, which
+// every use of it was enqueued on (its build, on the build stream, has ended): nothing waits
 void destroy_topo(pf_server* S, Topo* t) {
-    if (t->csr) pf_csr_destroy(t->csr);
-    if (t->d_elems) (void)hipFree(t->d_elems);
+    if (t->csr) csr_release(t->csr, S->s);
+    if (t->d_elems) (void)hipFreeAsync(t->d_elems, S->s);
     account(S, -static_cast<long long>(t->bytes));
     delete t;
 }
@@ -209,7 +215,7 @@ pf_status start_build(pf_server* S, SJob* j, Topo* t) {
     const pf_job& q = j->spec;
     const size_t eb = static_cast<size_t>(q.ne * (q.dim + 1)) * 4;
     t->state = Topo::BUILDING;
-    PF_HIP_TRY(hipMalloc(reinterpret_cast<void**>(&t->d_elems), eb));
+    PF_HIP_TRY(hipMallocAsync(reinterpret_cast<void**>(&t->d_elems), std::max<size_t>(eb, 16), S->sbuild));
     PF_HIP_TRY(hipMemcpyAsync(t->d_elems, q.elems, eb, hipMemcpyHostToDevice, S->sbuild));
     pf_status st = pf_csr_create(&t->csr);
     if (st != PF_OK) return st;
@@ -223,8 +229,12 @@ bool poll_build(pf_server* S, Topo* t) {
     pf_status st;
     if (!csr_symbolic_poll(t->csr, &st)) return false;
     std::lock_guard<std::mutex> lk(S->mu);
+    if (t->d_elems) {  // the numeric phase reads only the structure and the coordinates
+        (void)hipFreeAsync(t->d_elems, S->sbuild);
+        t->d_elems = nullptr;
+    }
     if (st == PF_OK) {
-        const size_t exact = static_cast<size_t>(t->ne * (t->dim + 1)) * 4 + csr_bytes(t->csr);
+        const size_t exact = csr_bytes(t->csr);
         account(S, static_cast<long long>(exact) - static_cast<long long>(t->bytes));
         t->bytes = exact;
         t->state = Topo::BUILT;
@@ -259,11 +269,13 @@ void finish(pf_server* S, SJob* j, pf_status status) {
 
 // release a job's device memory (stream-ordered) and its structure reference
 void release(pf_server* S, SJob* j) {
-    for (void** p : {reinterpret_cast<void**>(&j->d_coords), &j->d_valsK, &j->d_valsM,
-                     reinterpret_cast<void**>(&j->d_ctr), &j->d_pg}) {
+    for (void** p : {&j->d_mem, &j->d_pg}) {
         if (*p) (void)hipFreeAsync(*p, S->s);
         *p = nullptr;
     }
+    j->d_coords = nullptr;
+    j->d_valsK = j->d_valsM = nullptr;
+    j->d_ctr = nullptr;
     account(S, -static_cast<long long>(j->bytes));
     j->bytes = 0;
     if (j->slot >= 0) S->free_slots.push_back(j->slot);
@@ -344,11 +356,18 @@ pf_status assembly_inputs(pf_server* S, SJob* j) {
         j->bytes = exact;
         j->res.nnz = nnz;
     }
-    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&j->d_coords), q.nn * q.dim * 8, S->s);
-    if (e == hipSuccess) e = hipMallocAsync(&j->d_valsK, std::max<size_t>(nnz * es, 16), S->s);
-    if (e == hipSuccess) e = hipMallocAsync(&j->d_valsM, std::max<size_t>(nnz * es, 16), S->s);
-    if (e == hipSuccess) e = hipMallocAsync(reinterpret_cast<void**>(&j->d_ctr), 32, S->s);
-    if (e == hipSuccess) e = hipMemcpyAsync(j->d_coords, q.coords, q.nn * q.dim * 8, hipMemcpyHostToDevice, S->s);
+    // one stream-ordered allocation (its release, like any, costs the scheduler a runtime call)
+    auto part = [](size_t b) { return (std::max<size_t>(b, 16) + 255) & ~size_t(255); };
+    const size_t b_ctr = part(32), b_xyz = part(q.nn * q.dim * 8), b_val = part(nnz * es);
+    hipError_t e = hipMallocAsync(&j->d_mem, b_ctr + b_xyz + 2 * b_val, S->s);
+    if (e == hipSuccess) {
+        char* base = static_cast<char*>(j->d_mem);
+        j->d_ctr = reinterpret_cast<int64_t*>(base);
+        j->d_coords = reinterpret_cast<double*>(base + b_ctr);
+        j->d_valsK = base + b_ctr + b_xyz;
+        j->d_valsM = base + b_ctr + b_xyz + b_val;
+        e = hipMemcpyAsync(j->d_coords, q.coords, q.nn * q.dim * 8, hipMemcpyHostToDevice, S->s);
+    }
     if (e == hipSuccess) e = hipMemsetAsync(j->d_ctr, 0, 32, S->s);
     if (e != hipSuccess)
         return fail(e == hipErrorOutOfMemory ? PF_ENOMEM : PF_EHIP,
@@ -781,6 +800,8 @@ void pf_server_destroy(pf_server* S) {
     if (S->s) (void)hipStreamSynchronize(S->s);
     for (auto& kv : S->cache) destroy_topo(S, kv.second);
     S->cache.clear();
+    if (S->s) (void)hipStreamSynchronize(S->s);
+    csr_pool_trim();
     for (auto& ring : S->plans)
         for (pf_plan* p : ring)
             if (p) pf_plan_destroy(p);

@@ -79,7 +79,7 @@ __device__ __forceinline__ void load_column(const T* __restrict__ pg, int64_t ba
 // entries are dealt flat (row after row), entry k to thread k mod PBT.
 template <int NB, bool P2, typename T, int PR, bool VEC>
 __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_t* __restrict__ row_ptr,
-                                                        const int32_t* __restrict__ adj_len,
+                                                        const int32_t* __restrict__ aptr,
                                                         const int32_t* __restrict__ adj, const uint32_t* __restrict__ pk,
                                                         const uint64_t* __restrict__ pk2, const int32_t* __restrict__ dpos,
                                                         const T* __restrict__ pagesK, const T* __restrict__ pagesM,
@@ -89,21 +89,14 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_
     __shared__ int32_t rp[PR + 1], apre[PR + 1], dslot[PR];
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * PR;
     const int nr = static_cast<int>((r0 + PR < nn) ? PR : nn - r0);
-    if (threadIdx.x <= PR) rp[threadIdx.x] = row_ptr[r0 + (threadIdx.x <= nr ? threadIdx.x : nr)];
-    if (threadIdx.x < 64) {  // prefix of the rows' adjacency lengths in wave 0
-        const int r = threadIdx.x;
-        const int L = r < nr ? min(adj_len[r0 + r], CSR_MAXADJ) : 0;
-        if (r < PR) dslot[r] = r < nr ? dpos[r0 + r] : 0;
-        int x = L;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int y = __shfl_up(x, d, 64);
-            if (r >= d) x += y;
-        }
-        if (r < PR) apre[r] = x - L;
-        if (r == PR - 1) apre[PR] = x;
+    if (threadIdx.x <= PR) {  // rows past the end: no slots, no entries
+        const int r = threadIdx.x <= nr ? threadIdx.x : nr;
+        rp[threadIdx.x] = row_ptr[r0 + r];
+        apre[threadIdx.x] = aptr[r0 + r];
     }
+    if (threadIdx.x < PR) dslot[threadIdx.x] = static_cast<int>(threadIdx.x) < nr ? dpos[r0 + threadIdx.x] : 0;
     __syncthreads();
+    const int32_t a00 = apre[0];  // the block's entries are a00 .. apre[nr] - 1 of the adjacency
     const int32_t w0 = rp[0];
     const int W = rp[nr] - w0;
     A* accK = reinterpret_cast<A*>(smem);
@@ -118,7 +111,7 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_
         shM[w] = 0;
     }
     // this thread's entries k = thread + q PBT of the block's flat list; loads without branches
-    static_assert(PR <= 64, "the row prefix runs in one wave");
+    static_assert(PR <= 64, "a block's rows");
     int rq[PITEMS];
     int64_t eq[PITEMS];
     int aq[PITEMS];
@@ -126,9 +119,9 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_
 #pragma unroll
     for (int q = 0; q < PITEMS; ++q) {
         const int idx = threadIdx.x + q * PBT;
-        const bool ok = idx < apre[PR];
-        const int r = ok ? last_le(apre, PR, idx) : 0, j = idx - apre[r];
-        const int64_t t = ok ? (r0 + r) * CSR_MAXADJ + j : r0 * CSR_MAXADJ;
+        const bool ok = idx < apre[PR] - a00;
+        const int r = ok ? last_le(apre, PR, a00 + idx) : 0;
+        const int64_t t = ok ? static_cast<int64_t>(a00) + idx : 0;
         const int32_t w = adj[t];
         pq[q] = P2 ? pk2[t] : static_cast<uint64_t>(pk[t]);
         rq[q] = ok ? r : -1;
@@ -209,11 +202,11 @@ void launch_pages_rows(const CsrView& v, const void* pK, const void* pM, void* v
     const bool vec = NB % 2 == 0 && (reinterpret_cast<uintptr_t>(pK) & 15) == 0 && (reinterpret_cast<uintptr_t>(pM) & 15) == 0;
     if (vec)
         hipLaunchKernelGGL((k_assemble_pages<NB, P2, T, PR, NB % 2 == 0>), dim3(g), dim3(PBT), window_bytes<T>(w), s, v.nn,
-                           v.row_ptr, v.adj_len, v.adj, v.pk, v.pk2, v.dpos, static_cast<const T*>(pK),
+                           v.row_ptr, v.aptr, v.adj, v.pk, v.pk2, v.dpos, static_cast<const T*>(pK),
                            static_cast<const T*>(pM), static_cast<T*>(vK), static_cast<T*>(vM));
     else
         hipLaunchKernelGGL((k_assemble_pages<NB, P2, T, PR, false>), dim3(g), dim3(PBT), window_bytes<T>(w), s, v.nn,
-                           v.row_ptr, v.adj_len, v.adj, v.pk, v.pk2, v.dpos, static_cast<const T*>(pK),
+                           v.row_ptr, v.aptr, v.adj, v.pk, v.pk2, v.dpos, static_cast<const T*>(pK),
                            static_cast<const T*>(pM), static_cast<T*>(vK), static_cast<T*>(vM));
 }
 
@@ -242,6 +235,7 @@ pf_status pf_csr_assemble_pages(const pf_csr* csr, pf_dtype prec, const void* pa
     const int pr = f32 ? pages_rows<float>(v) : pages_rows<double>(v);
     if (pr == 0) return fail(PF_ELIMIT, "pf_csr_assemble_pages: a CSR window of 4 rows exceeds the LDS budget");
     hipStream_t s = as_stream(stream);
+    if (pf_status st = csr_order(csr, s)) return st;
     // an output without its request still gets the other's pages read as zero
     const void* pK = valsK ? pagesK : nullptr;
     const void* pM = valsM ? pagesM : nullptr;

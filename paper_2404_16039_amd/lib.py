@@ -357,7 +357,7 @@ class Csr:
         _chk(_lib.pf_csr_numeric_info(self._h, prec, C.byref(rows), C.byref(madj)), "pf_csr_numeric_info")
         return rows.value, madj.value
 
-    CSR_STAGES = ("adjacency", "pattern", "row offsets")
+    CSR_STAGES = ("adjacency", "pattern", "row offsets", "columns")
 
     def set_timing(self, on=True):
         """Record per-stage events in every later symbolic call (and clear the sums)."""

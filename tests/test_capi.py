@@ -91,7 +91,7 @@ def test_csr_handle_states_without_gpu():
     assert L.pf_energies(None, lib.F32, None, None, 2, None, None, None, None, None, None, None, None, None) == 1
     assert L.pf_energies(h, lib.F32, None, None, 2, None, None, None, None, None, None, None, None, None) == 9
     stages = re.search(r"#define PF_CSR_STAGES (\d+)", open(os.path.join(ROOT, "include", "pagefem.h")).read())
-    assert int(stages.group(1)) == len(lib.Csr.CSR_STAGES) == 3
+    assert int(stages.group(1)) == len(lib.Csr.CSR_STAGES) == 4
     L.pf_csr_destroy(h)
     L.pf_csr_destroy(None)
 
