@@ -240,6 +240,12 @@ pf_status pf_csr_assemble_pages(const pf_csr* csr, pf_dtype prec, const void* pa
 pf_status pf_csr_info(const pf_csr* csr, int64_t* nn, int64_t* nnz, const int32_t** row_ptr,
                       const int32_t** col_idx);
 
+/* Device bytes the handle holds (a memory-planning aid): *resident = the structure's own
+ * arrays (the CSR pattern, the compact adjacency with its slot words, the diagonal
+ * positions, and the face lists and energy workspace once built); *scratch = build scratch
+ * still held (non-zero only while a build is in flight).  Both nullable; host call. */
+pf_status pf_csr_memory(const pf_csr* csr, int64_t* resident, int64_t* scratch);
+
 /* Launch shape of pf_assemble and pf_assemble_quad on a built P1 structure in precision
  * prec (a diagnostic, e.g. for tests that must reach every variant of the numeric kernel):
  * rows per workgroup of the numeric launch and the largest number of elements around one

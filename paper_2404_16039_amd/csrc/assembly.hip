@@ -2805,6 +2805,14 @@ pf_status pf_csr_info(const pf_csr* c, int64_t* nn, int64_t* nnz, const int32_t*
     return PF_OK;
 }
 
+pf_status pf_csr_memory(const pf_csr* c, int64_t* resident, int64_t* scratch) {
+    if (!c) return fail(PF_EINVAL, "pf_csr_memory: null handle");
+    const int64_t all = static_cast<int64_t>(csr_bytes(c));
+    if (resident) *resident = all - c->cap_scratch;
+    if (scratch) *scratch = c->cap_scratch;
+    return PF_OK;
+}
+
 pf_status pf_csr_numeric_info(const pf_csr* c, pf_dtype prec, int32_t* rows_per_block, int32_t* max_adj) {
     if (!c) return fail(PF_EINVAL, "pf_csr_numeric_info: null handle");
     if (!c->built || c->p2) return fail(PF_ESTATE, "pf_csr_numeric_info: no P1 structure built");

@@ -154,6 +154,7 @@ _sig = {
     "pf_csr_assemble_pages": ([P, I32, P, P, P, P, P], C.c_int),
     "pf_csr_info": ([P, C.POINTER(I64), C.POINTER(I64), C.POINTER(P), C.POINTER(P)], C.c_int),
     "pf_csr_numeric_info": ([P, I32, C.POINTER(I32), C.POINTER(I32)], C.c_int),
+    "pf_csr_memory": ([P, C.POINTER(I64), C.POINTER(I64)], C.c_int),
     "pf_csr_set_timing": ([P, C.c_int], C.c_int),
     "pf_csr_stage_times": ([P, C.POINTER(C.c_double), C.POINTER(I64)], C.c_int),
     "pf_assemble": ([P, I32, P, P, P, P, P, P, FP, P, P], C.c_int),
@@ -350,6 +351,12 @@ class Csr:
         nn, nnz, rp, ci = I64(), I64(), P(), P()
         _chk(_lib.pf_csr_info(self._h, C.byref(nn), C.byref(nnz), C.byref(rp), C.byref(ci)), "pf_csr_info")
         return nn.value, nnz.value, rp.value, ci.value
+
+    def memory(self):
+        """(resident device bytes of the structure, build scratch still held)"""
+        res, scr = I64(), I64()
+        _chk(_lib.pf_csr_memory(self._h, C.byref(res), C.byref(scr)), "pf_csr_memory")
+        return res.value, scr.value
 
     def numeric_info(self, prec):
         """(rows per workgroup of the numeric launch, largest number of elements around a node)"""
