@@ -204,8 +204,13 @@ pf_status pf_csr_create(pf_csr** out);
  * the build's last step (the columns) enqueued on `stream`: the library's later calls on
  * the handle order their work after it on any stream (a device-side wait, no host wait),
  * and pf_csr_info, which hands out device pointers, waits for it on the host.
- * Limits: 4*ne < 2^31, nnz < 2^31, at most 64 elements per node and 64 nonzeros per row
- * (PF_ELIMIT otherwise).  Out-of-range node ids give PF_EINDEX; PF_EINVAL if the row
+ * Rows whose node lies in more than 64 elements, or that hold more than 64 nonzeros, are
+ * long rows: the build lists them (one more synchronisation of `stream`, only then) and
+ * builds them with one workgroup per row, and pf_assemble, pf_assemble_quad,
+ * pf_csr_assemble_pages and pf_rhs assemble them the same way (exactly, in FP64, rounded
+ * once to the output type); pf_csr_faces refuses a structure with long rows.
+ * Limits: 4*ne < 2^31, nnz < 2^31, at most 256 nonzeros per row (PF_ELIMIT otherwise).
+ * Out-of-range node ids give PF_EINDEX; PF_EINVAL if the row
  * offsets could not be formed (a bounded wait between the workgroups of the row-offset
  * scan ran out, which the device's in-order start of workgroups rules out). */
 pf_status pf_csr_symbolic(pf_csr* csr, int dim, int64_t nn, int64_t ne, const int32_t* elems,
@@ -298,8 +303,8 @@ pf_status pf_assemble_quad(const pf_csr* csr, pf_dtype prec, const double* coord
  * list of their own (the section 3.5 facesB) with their elements.  Built from the
  * structure's adjacency and row patterns inside the handle; synchronises `stream` once
  * (the counts size the lists).  PF_EINVAL if a face belongs to more than two elements,
- * PF_ELIMIT if a node owns more than 128 faces (the faces whose smallest node it is).  A
- * later pf_csr_symbolic invalidates it. */
+ * PF_ELIMIT if a node owns more than 128 faces (the faces whose smallest node it is) or the
+ * structure has long rows (see pf_csr_symbolic).  A later pf_csr_symbolic invalidates it. */
 pf_status pf_csr_faces(pf_csr* csr, const double* coords, const int32_t* elems, void* stream);
 
 /* The face lists of pf_csr_faces: counts on the host, device pointers owned by the handle:

@@ -51,7 +51,14 @@ struct pf_csr {
     int32_t* cnt = nullptr;      // row lengths
     int32_t* colblk = nullptr;   // sorted columns of every row-pattern block, RR * MAXROW per block
     uint64_t* look = nullptr;    // published counts / prefixes of the row-offset tiles
+    int32_t* lrows_s = nullptr;  // the long rows found by the row-block pass
     unsigned char* scratch = nullptr;
+    int32_t* lcol = nullptr;     // each long row's columns, LCAP words apiece (long-row phase)
+    int64_t cap_lcol = 0;
+    // long rows (more than MAXADJ elements or MAXROW nonzeros): their list (resident)
+    int64_t nlong = 0;
+    int32_t* lrows = nullptr;
+    int64_t cap_lrows = 0;
     bool p2 = false;            // built from P2 elements (pf_csr_symbolic_p2)
     int64_t* bsum = nullptr;  // scan workspace
     int64_t* info = nullptr;  // [0] error bits, [1] adjacency total, [2] nnz, [3..6] block stats
@@ -76,13 +83,15 @@ struct pf_csr {
     bool timing = false, pending = false;
     int64_t* hinfo = nullptr;  // pinned host words for the status readbacks (allocated once)
     hipEvent_t ready = nullptr;  // recorded at the end of each enqueued build phase
-    int stage = 0;               // 0 idle, 1 pattern phase enqueued, 2 column phase enqueued
+    int stage = 0;               // 0 idle, 1 pattern phase enqueued, 3 long-row phase, 2 columns
     // pf_csr_symbolic returned with the column phase enqueued on q_stream and not yet seen
     // complete: work on another stream first waits for the ready event
     mutable bool cols_pending = false;
     int q_dim = 0, q_nlb = 0;    // ... the build's shape and stream
     int64_t q_nn = 0, q_ne = 0;
     hipStream_t q_stream = nullptr;
+    const int32_t* q_elems = nullptr;
+    bool q_long = false;  // the long-row phase has run for this build
     hipEvent_t ev[PF_CSR_STAGES + 2] = {};  // stage k: ev[STAGE_EV[k][0]] .. ev[STAGE_EV[k][1]]
     double stage_ms[PF_CSR_STAGES] = {};
     int64_t stage_calls = 0;
@@ -97,6 +106,12 @@ constexpr size_t LDS_BYTES = 65536;  // dynamic LDS budget of one numeric block
 
 constexpr int64_t ERR_INDEX = 1, ERR_ROW = 4;
 constexpr int INFO_WORDS = 16;  // status and statistics words of a symbolic build
+constexpr int INFO_NLONG = 10;  // ... the number of long rows
+// Long rows: a P1 row whose node lies in more than MAXADJ elements or that holds more than
+// MAXROW nonzeros.  The row-block kernels skip them; kernels of one workgroup per long row
+// build and assemble them.  A long row holds at most LCAP nonzeros (the packed slot words
+// give a column position 8 bits).
+constexpr int LCAP = 256;
 constexpr int MAXADJ = 64;  // elements per node (adjacency rows are padded to this length)
 constexpr int MAXROW = 64;  // nonzeros per row
 
@@ -211,8 +226,9 @@ __device__ __forceinline__ int ag_hash(int32_t node) {
 // table slot, so the block issues the global atomics of all its distinct nodes at once (one
 // round trip) instead of sweeping the table.  The order inside a row is not fixed: nothing
 // downstream depends on it (the numeric phase sums exactly, so its result does not depend
-// on the entry order).  Out-of-range node ids and rows beyond MAXADJ set error bits and are
-// not stored.
+// on the entry order).  Out-of-range node ids set an error bit and are not stored; entries
+// beyond MAXADJ are not stored either (an error for P2; for P1 the node's row is a long row,
+// whose entries the long-row phase places again), while the length counts them all.
 template <int ASH>  // bits of the local index in an adjacency entry: 2 (P1), 4 (P2)
 __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ elems, int64_t m, int nlb, int64_t nn,
                                                    int32_t* __restrict__ adj_len, int32_t* __restrict__ adj,
@@ -286,7 +302,9 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
             vals[h] = old[q];  // the tile's first position in the node's row
         }
     }
-    if (over) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
+    // P1 nodes beyond MAXADJ elements are long rows (their entries are placed again by the
+    // long-row phase); P2 structures have no long rows
+    if (over && ASH == 4) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < AG_ITEMS; ++q) {
@@ -672,7 +690,8 @@ __global__ __launch_bounds__(SBS) void k_row_offsets(int64_t nn, const int32_t* 
     for (int i = 0; i < SCAN_ITEMS; ++i) {
         const bool in = row0 + i < nn;
         v[i] = in ? rowlen[row0 + i] : 0;
-        amax = max(amax, in ? adj_len[row0 + i] : 0);
+        const int al = in ? adj_len[row0 + i] : 0;
+        amax = max(amax, al <= MAXADJ ? al : 0);  // long rows have a kernel of their own
         sum += v[i];
     }
     int64_t total;
@@ -757,7 +776,9 @@ __global__ __launch_bounds__(SBS) void k_row_columns(int64_t nn, const int32_t* 
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int b = min(g + j, nb - 1);
-            n[j] = g + j < nb ? bcnt[b] : 0;
+            // a group with a long row holds more columns than its region: its columns are
+            // rewritten by k_long_columns, here only the region is read
+            n[j] = g + j < nb ? min(bcnt[b], RW) : 0;
             o[j] = boff[b];
             src[j] = colblk + (blk0 + b) * RW;
         }
@@ -847,7 +868,7 @@ __global__ __launch_bounds__(PT) void k_rows_p1(int64_t nn, const int32_t* __res
                                                 const int32_t* __restrict__ aptr, int32_t* __restrict__ rowlen,
                                                 int32_t* __restrict__ colblk, int32_t* __restrict__ adjc,
                                                 uint32_t* __restrict__ pk, int32_t* __restrict__ dpos,
-                                                int64_t* __restrict__ info) {
+                                                int32_t* __restrict__ lrows, int64_t* __restrict__ info) {
     constexpr int NO = NLB - 1;        // other nodes of an element
     constexpr int NC = PB * NO;        // inserts of a batch
     static_assert(NC <= 32, "a batch's inserts fit one mask word");
@@ -856,11 +877,15 @@ __global__ __launch_bounds__(PT) void k_rows_p1(int64_t nn, const int32_t* __res
     __shared__ uint8_t lsth[PR * PL];              // table slot of each list item
     __shared__ uint8_t srank[PR * PS];             // column position of each used table slot
     __shared__ int32_t cnt[PR];
+    __shared__ int32_t rlong[PR];                  // a probe of the row found its table full
     __shared__ int32_t cpre[PR + 1];
     __shared__ int32_t guard[PT];                  // never -1: the first probes of empty entries
     const int t = static_cast<int>(threadIdx.x);
     for (int h = t; h < PR * PS; h += PT) tab[h] = -1;
-    if (t < PR) cnt[t] = 0;
+    if (t < PR) {
+        cnt[t] = 0;
+        rlong[t] = 0;
+    }
     guard[t] = -2;
     __syncthreads();
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * PR;
@@ -868,7 +893,9 @@ __global__ __launch_bounds__(PT) void k_rows_p1(int64_t nn, const int32_t* __res
     const int r = t % PR, jt = t / PR;
     const int64_t row = r0 + (r < nr ? r : nr - 1);  // in bounds for the loads of rows past the end
     const int32_t self = static_cast<int32_t>(r0 + r);
-    const int L = r < nr ? min(adj_len[row], MAXADJ) : 0;  // longer lists raised an error already
+    const int32_t Lfull = adj_len[row];
+    // a node of more than MAXADJ elements heads a long row: left to the long-row phase
+    const int L = r < nr && Lfull <= MAXADJ ? Lfull : 0;
     const int64_t ao = aptr[row];                           // the row's first compact entry
     const int32_t ablk0 = aptr[r0], ablk1 = aptr[r0 + nr];  // the block's compact entries
     int32_t* rt = tab + r * PS;
@@ -886,7 +913,7 @@ __global__ __launch_bounds__(PT) void k_rows_p1(int64_t nn, const int32_t* __res
         }
         return h;
     };
-    if (jt == 0 && L > 0) {  // the diagonal
+    if (jt == 0 && L > 0) {  // the diagonal (a row of entries always holds its own node)
         const int h0 = rsub_hash(self);
         int32_t cur = atomicCAS(rt + h0, -1, self);
         const int h = probe_on(self, h0, cur);
@@ -986,11 +1013,18 @@ __global__ __launch_bounds__(PT) void k_rows_p1(int64_t nn, const int32_t* __res
             iw[q0 + i] = w;
         }
     }
+    if (bad) rlong[r] = 1;
     __syncthreads();
 
-    // ranks: column position of every list item (four list words per LDS read)
-    const int n = min(cnt[r], MAXROW);
-    bad = bad || cnt[r] > MAXROW;
+    // a row whose distinct nodes overflow its table (more than MAXROW nonzeros), or whose node
+    // has more than MAXADJ elements, is a long row: no columns here, its diagonal position
+    // -1 (the mark the long-row phase reads), and it joins the list of long rows
+    const bool lng = r < nr && (Lfull > MAXADJ || rlong[r] != 0);
+    const int n = lng ? 0 : min(cnt[r], MAXROW);
+    if (lng && jt == 0) {
+        dpos[r0 + r] = -1;
+        lrows[atomicAdd(reinterpret_cast<unsigned long long*>(info + INFO_NLONG), 1ull)] = static_cast<int32_t>(r0 + r);
+    }
     for (int k = jt; k < n; k += PJ) {
         const int32_t v = rl[k];
         int rank = 0;
@@ -1001,7 +1035,7 @@ __global__ __launch_bounds__(PT) void k_rows_p1(int64_t nn, const int32_t* __res
         srank[r * PS + rh[k]] = static_cast<uint8_t>(rank);
         if (v == self) dpos[r0 + r] = rank;
     }
-    if (jt == 0 && r < nr && L == 0) dpos[r0 + r] = 0;  // a node of no element has an empty row
+    if (jt == 0 && r < nr && Lfull == 0) dpos[r0 + r] = 0;  // a node of no element has an empty row
     // row lengths, and each 8-row group's prefix (wave 0)
     if (t < 64) {
         const int lane = t;
@@ -1015,7 +1049,6 @@ __global__ __launch_bounds__(PT) void k_rows_p1(int64_t nn, const int32_t* __res
         if (lane < PR) cpre[lane] = x - v;
         if (lane < nr) rowlen[r0 + lane] = v;
     }
-    if (bad) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
     __syncthreads();
     {
         int32_t* dst = colblk + (r0 + (r & ~(RR - 1))) * MAXROW + cpre[r];  // the row's group region
@@ -1032,7 +1065,7 @@ __global__ __launch_bounds__(PT) void k_rows_p1(int64_t nn, const int32_t* __res
 #pragma unroll
     for (int q = 0; q < PQ; ++q) {
         const int j = jt + q * PJ;
-        if (j >= L) break;
+        if (j >= L || lng) break;  // a long row's entries are placed by the long-row phase
         const uint32_t w = iw[q];
         uint32_t word = w & 3;
 #pragma unroll
@@ -1055,6 +1088,144 @@ __global__ __launch_bounds__(PT) void k_rows_p1(int64_t nn, const int32_t* __res
             adjc[ablk0 + k] = stg[k];
             pk[ablk0 + k] = static_cast<uint32_t>(stg[STG + k]);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------- long rows, structure
+// Long rows (LCAP above) are built after the row-block pass has listed them: their nodes'
+// compact adjacency, then one workgroup per long row for the pattern.
+constexpr int LT = 256;     // threads of a long-row workgroup
+constexpr int LTAB = 1024;  // slots of a long row's hash table (at most LCAP nodes: load <= 1/4)
+
+static_assert(CSR_MAXADJ == MAXADJ && CSR_MAXROW == MAXROW && CSR_LCAP == LCAP, "one long-row rule");
+__device__ __forceinline__ bool is_long_row(int elements, int nonzeros) { return csr_long_row(elements, nonzeros); }
+
+// every entry of a long row's node (diagonal position -1) at aptr[node] + a cursor; the
+// cursor is the node's row length, which the row-block pass left at 0 for long rows
+__global__ __launch_bounds__(SBS) void k_long_adj(const int32_t* __restrict__ elems, int64_t m, int nlb,
+                                                  const int32_t* __restrict__ dpos, const int32_t* __restrict__ aptr,
+                                                  int32_t* __restrict__ cur, int32_t* __restrict__ adjc) {
+    for (int64_t t = static_cast<int64_t>(blockIdx.x) * SBS + threadIdx.x; t < m;
+         t += static_cast<int64_t>(gridDim.x) * SBS) {
+        const int32_t node = elems[t];
+        if (dpos[node] != -1) continue;
+        const int64_t e = t / nlb;
+        const int a = static_cast<int>(t - e * nlb);
+        const int pos = atomicAdd(cur + node, 1);
+        adjc[aptr[node] + pos] = static_cast<int32_t>((e << 2) | a);
+    }
+}
+
+__device__ __forceinline__ int long_hash(int32_t v) {
+    return static_cast<int>((static_cast<uint32_t>(v) * 2654435761u) >> 22);  // 10 bits
+}
+static_assert(LTAB == 1024, "long_hash yields 10 bits");
+
+// One workgroup per long row: the other nodes of all its entries (and the row's own) enter an
+// LDS hash table; the distinct nodes are ranked (ascending: the column positions), written to
+// the row's list in lcol (LCAP words per long row), and every entry's slot word is formed
+// from the ranks of its element's other nodes.  More than LCAP distinct nodes: ERR_ROW.
+template <int NLB>
+__global__ __launch_bounds__(LT) void k_rows_long(const int32_t* __restrict__ lrows, const int32_t* __restrict__ elems,
+                                                  const int32_t* __restrict__ aptr, const int32_t* __restrict__ adjc,
+                                                  int32_t* __restrict__ rowlen, int32_t* __restrict__ lcol,
+                                                  uint32_t* __restrict__ pk, int32_t* __restrict__ dpos,
+                                                  int64_t* __restrict__ info) {
+    constexpr int NO = NLB - 1;
+    __shared__ int32_t tab[LTAB];
+    __shared__ uint8_t trank[LTAB];
+    __shared__ int32_t lst[LCAP];
+    __shared__ int16_t lsth[LCAP];
+    __shared__ int32_t nlst;
+    const int t = static_cast<int>(threadIdx.x);
+    const int32_t row = lrows[blockIdx.x];
+    const int64_t a0 = aptr[row];
+    const int L = aptr[row + 1] - static_cast<int>(a0);
+    for (int h = t; h < LTAB; h += LT) tab[h] = -1;
+    if (t == 0) nlst = 0;
+    __syncthreads();
+    auto insert = [&](int32_t v) {
+        int h = long_hash(v);
+        for (int probe = 0; probe < LTAB; ++probe) {  // the table never fills: probing ends
+            const int32_t c = atomicCAS(tab + h, -1, v);
+            if (c == -1) {
+                const int p = atomicAdd(&nlst, 1);
+                if (p < LCAP) {
+                    lst[p] = v;
+                    lsth[p] = static_cast<int16_t>(h);
+                }
+                return;
+            }
+            if (c == v) return;
+            h = (h + 1) & (LTAB - 1);
+        }
+    };
+    if (t == 0) insert(row);
+    for (int j = t; j < L; j += LT) {
+        const int32_t w = adjc[a0 + j];
+        const int64_t e = static_cast<uint32_t>(w) >> 2;
+        const int a = w & 3;
+#pragma unroll
+        for (int k = 0; k < NO; ++k) insert(elems[e * NLB + (k < a ? k : k + 1)]);
+    }
+    __syncthreads();
+    const int n = nlst;  // the same for every thread
+    if (n > LCAP) {
+        if (t == 0) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
+        return;
+    }
+    int32_t* out = lcol + static_cast<int64_t>(blockIdx.x) * LCAP;
+    for (int k = t; k < n; k += LT) {
+        const int32_t v = lst[k];
+        int rank = 0;
+        for (int u = 0; u < n; ++u) rank += lst[u] < v;
+        trank[lsth[k]] = static_cast<uint8_t>(rank);
+        out[rank] = v;
+        if (v == row) dpos[row] = rank;
+    }
+    if (t == 0) rowlen[row] = n;
+    __syncthreads();
+    for (int j = t; j < L; j += LT) {
+        const int32_t w = adjc[a0 + j];
+        const int64_t e = static_cast<uint32_t>(w) >> 2;
+        const int a = w & 3;
+        uint32_t word = static_cast<uint32_t>(a);
+#pragma unroll
+        for (int k = 0; k < NO; ++k) {
+            const int32_t v = elems[e * NLB + (k < a ? k : k + 1)];
+            int h = long_hash(v);
+            while (tab[h] != v) h = (h + 1) & (LTAB - 1);  // present: entered above
+            word |= static_cast<uint32_t>(trank[h]) << (2 + 8 * k);
+        }
+        pk[a0 + j] = word;
+    }
+}
+
+// The columns of the 8-row groups that hold a long row, rewritten once col_idx is sized: the
+// long row's from its list, the group's other rows from the group's colblk region (in row
+// order, lengths from row_ptr).  Two long rows of one group write the same words for the
+// group's other rows.
+__global__ __launch_bounds__(LT) void k_long_columns(const int32_t* __restrict__ lrows, int64_t nn,
+                                                     const int32_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ aptr,
+                                                     const int32_t* __restrict__ colblk,
+                                                     const int32_t* __restrict__ lcol, int32_t* __restrict__ col_idx) {
+    const int t = static_cast<int>(threadIdx.x);
+    const int64_t row = lrows[blockIdx.x];
+    {
+        const int64_t w0 = row_ptr[row];
+        const int len = row_ptr[row + 1] - static_cast<int>(w0);
+        for (int k = t; k < len; k += LT) col_idx[w0 + k] = lcol[static_cast<int64_t>(blockIdx.x) * LCAP + k];
+    }
+    const int64_t g0 = row / RR * RR;
+    const int32_t* src = colblk + g0 * MAXROW;  // the group's region
+    int off = 0;
+    for (int64_t r = g0; r < g0 + RR && r < nn; ++r) {
+        const int64_t w0 = row_ptr[r];
+        const int len = row_ptr[r + 1] - static_cast<int>(w0);
+        if (is_long_row(aptr[r + 1] - aptr[r], len)) continue;
+        for (int k = t; k < len; k += LT) col_idx[w0 + k] = src[off + k];
+        off += len;
     }
 }
 
@@ -1520,7 +1691,8 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
         // the host guarantees that NITEMS * NBT / NR covers the longest adjacency list
         const int idx = threadIdx.x + q * NBT;
         const int r = idx % NR, j = idx / NR;
-        const bool ok = j < ap[r + 1] - ap[r];
+        const int La = ap[r + 1] - ap[r];
+        const bool ok = j < La && !is_long_row(La, rp[r + 1] - rp[r]);  // long rows: own workgroups
         rr[q] = ok ? r : -1;
         tt[q] = ok ? static_cast<int64_t>(ap[r]) + j : 0;
         pw[q] = pk[tt[q]];
@@ -1537,7 +1709,8 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
         if (col == i) dslot[r] = w;
         accK[w] = A(0);
         accM[w] = A(0);
-        shK[w] = 0;
+        // a long row's slots are marked: neither graded nor stored here
+        shK[w] = is_long_row(ap[r + 1] - ap[r], rp[r + 1] - rp[r]) ? INT32_MIN : 0;
         shM[w] = 0;
         Vec4<T> v;
         v.x = static_cast<T>(coords[col * DIM] - coords[i * DIM]);
@@ -1646,6 +1819,7 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
     __syncthreads();
     // per-slot grid: maximum bits -> shift
     for (int w = threadIdx.x; w < W; w += NBT) {
+        if (shK[w] == INT32_MIN) continue;
         shK[w] = Exact<T>::shift(static_cast<uint32_t>(shK[w]));
         shM[w] = Exact<T>::shift(static_cast<uint32_t>(shM[w]));
     }
@@ -1672,6 +1846,7 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
 
     // phase 2: one slot per thread, coalesced stores
     for (int w = threadIdx.x; w < W; w += NBT) {
+        if (shK[w] == INT32_MIN) continue;
         valsK[w0 + w] = Exact<T>::back(accK[w], shK[w]);
         if (valsM) valsM[w0 + w] = Exact<T>::back(accM[w], shM[w]);
     }
@@ -1763,6 +1938,11 @@ __device__ __forceinline__ void numeric_block_f32(int64_t r0, int64_t nn, const 
     const int W = rp[nr] - w0;
     const int s0 = rp[r] - w0;
     const int len = rp[r + 1] - rp[r];  // 0 for rows past the end
+    if (is_long_row(L, len)) {  // a long row: assembled by its own workgroup, not here
+#pragma unroll
+        for (int q = 0; q < NITEMS; ++q) okq[q] = false;
+        if (jt == 0) rmK[r] = G::SKIP;
+    }
 
     // coefficients of the thread's entries (their loads overlap the slot passes)
     float ckq[NITEMS], cmq0[NITEMS];
@@ -1935,6 +2115,7 @@ __device__ __forceinline__ void numeric_block_f32(int64_t r0, int64_t nn, const 
     for (int w = t; w < W; w += NT) {
         const int rr = rowof[w];
         const uint32_t mK = rmK[rr];
+        if (mK == G::SKIP) continue;
         const bool poison = mK == G::POISON;
         valsK[w0 + w] = poison ? __builtin_nanf("") : G::back(accK[w], G::shift(mK));
         if (valsM) valsM[w0 + w] = poison ? __builtin_nanf("") : G::back(accM[w], G::shift(rmM[rr]));
@@ -2003,6 +2184,148 @@ __global__ __launch_bounds__(NT, (numeric32_waves<0, false, NR>())) void k_numer
     numeric_block_f32<DIM, false, NR, NT>((b - j.block0) * NR, j.nn, j.coords, j.row_ptr, j.col_idx, j.aptr,
                                           j.adj, j.pk, j.dpos, nullptr, nullptr, static_cast<float*>(j.valsK),
                                           static_cast<float*>(j.valsM), j.fb, j.counters, wmax);
+}
+
+// ---------------------------------------------------------------------------- long rows, numeric
+// One workgroup per long row (at most LCAP slots): every adjacency entry's row of K_e and M_e
+// in FP64 from the coordinates of the row's node and of the element's other nodes (reached
+// through the entry's slot word), entered in two passes -- the largest magnitude of each
+// slot, then every contribution on the slot's LongGrid as a 64-bit integer (exact, so the
+// result does not depend on the order of the adds).  FP32 outputs round the FP64 sum once.
+// The routed counter counts, at each element's first node, the elements the FP32 geometry
+// would route, as the row-block kernels do.
+template <int DIM, typename T, bool COEF, int QN>
+__device__ __forceinline__ void long_entry(int64_t row, int64_t w0, int sd, uint32_t p, int64_t e,
+                                           const double* __restrict__ coords, const int32_t* __restrict__ col_idx,
+                                           const T* __restrict__ cK, const T* __restrict__ cM, double (&kd)[DIM + 1],
+                                           double (&md)[DIM + 1], int (&sl)[DIM + 1], double (&ev)[DIM][DIM]) {
+    constexpr int NLB = DIM + 1;
+    sl[0] = sd;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        sl[1 + k] = static_cast<int>((p >> (2 + 8 * k)) & 255);
+        const int64_t col = col_idx[w0 + sl[1 + k]];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) ev[k][c] = coords[col * DIM + c] - coords[row * DIM + c];
+    }
+    double ck = 1.0, cm = 1.0;
+    double cmq[QN > 0 ? QN : 1];
+    if constexpr (COEF && QN == 0) {
+        if (cK) ck = static_cast<double>(cK[e]);
+        if (cM) cm = static_cast<double>(cM[e]);
+    }
+    if constexpr (QN > 0) {
+        double sk = 0.0;
+#pragma unroll
+        for (int iq = 0; iq < QN; ++iq) {
+            sk += cK ? static_cast<double>(cK[e * QN + iq]) : 1.0;
+            cmq[iq] = cM ? static_cast<double>(cM[e * QN + iq]) : 1.0;
+        }
+        ck = sk * (1.0 / QN);
+    }
+    double mo, adet;
+    origin_row_f64<DIM>(ev, ck, cm, kd, mo, adet);
+    if constexpr (QN > 0) {
+        const int a = static_cast<int>(p & 3);
+#pragma unroll
+        for (int b = 0; b < NLB; ++b) md[b] = 0.0;
+#pragma unroll
+        for (int iq = 0; iq < QN; ++iq) {
+            const double wl = quad_weight<DIM, QN>() * QuadRule<DIM, QN>::lam(iq, a) * cmq[iq];
+#pragma unroll
+            for (int b = 0; b < NLB; ++b) {
+                const int lb = b == 0 ? a : (b - 1 < a ? b - 1 : b);
+                md[b] = fma(wl, QuadRule<DIM, QN>::lam(iq, lb), md[b]);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < NLB; ++b) md[b] *= adet;
+    } else {
+        md[0] = mo + mo;
+#pragma unroll
+        for (int b = 1; b < NLB; ++b) md[b] = mo;
+    }
+}
+
+template <int DIM, typename T, bool COEF, int QN>
+__global__ __launch_bounds__(LT) void k_numeric_long(const int32_t* __restrict__ lrows,
+                                                     const double* __restrict__ coords,
+                                                     const int32_t* __restrict__ row_ptr,
+                                                     const int32_t* __restrict__ col_idx,
+                                                     const int32_t* __restrict__ aptr, const int32_t* __restrict__ adj,
+                                                     const uint32_t* __restrict__ pk, const int32_t* __restrict__ dpos,
+                                                     const T* __restrict__ cK, const T* __restrict__ cM,
+                                                     T* __restrict__ valsK, T* __restrict__ valsM, Fallback fb,
+                                                     int64_t* d_counters) {
+    constexpr int NLB = DIM + 1;
+    using G = LongGrid;
+    __shared__ uint32_t mxK[LCAP], mxM[LCAP];
+    __shared__ int32_t shK[LCAP], shM[LCAP];
+    __shared__ unsigned long long accK[LCAP], accM[LCAP];
+    const int t = static_cast<int>(threadIdx.x);
+    const int64_t row = lrows[blockIdx.x];
+    const int64_t w0 = row_ptr[row];
+    const int len = row_ptr[row + 1] - static_cast<int>(w0);  // at most LCAP
+    const int64_t a0 = aptr[row];
+    const int L = aptr[row + 1] - static_cast<int>(a0);
+    const int sd = dpos[row];
+    const int hb = G::headroom(L);
+    for (int k = t; k < LCAP; k += LT) {
+        mxK[k] = mxM[k] = 0u;
+        accK[k] = accM[k] = 0ull;
+    }
+    __syncthreads();
+    int64_t routed = 0;
+    for (int j = t; j < L; j += LT) {  // pass 1: each slot's largest magnitude
+        const uint32_t p = pk[a0 + j];
+        const int64_t e = static_cast<uint32_t>(adj[a0 + j]) >> 2;
+        double kd[NLB], md[NLB], ev[DIM][DIM];
+        int sl[NLB];
+        long_entry<DIM, T, COEF, QN>(row, w0, sd, p, e, coords, col_idx, cK, cM, kd, md, sl, ev);
+#pragma unroll
+        for (int b = 0; b < NLB; ++b) {
+            atomicMax(mxK + sl[b], G::mag(kd[b]));
+            atomicMax(mxM + sl[b], G::mag(md[b]));
+        }
+        if constexpr (sizeof(T) == 4) {
+            if ((p & 3) == 0) {  // what the FP32 path would route, counted at the element's first node
+                float u[DIM][DIM];
+#pragma unroll
+                for (int k = 0; k < DIM; ++k)
+#pragma unroll
+                    for (int c = 0; c < DIM; ++c) u[k][c] = static_cast<float>(ev[k][c]);
+                P1Geom<DIM, float> g;
+                p1_geom_edges_fast<DIM>(u, g);
+                if (route32(g.det, g.absterms, static_cast<float>(fb.tau_abs), static_cast<float>(fb.tau_cond),
+                            fb.enable))
+                    ++routed;
+            }
+        }
+    }
+    if (routed) count_add(d_counters, 0, routed);
+    __syncthreads();
+    for (int k = t; k < len; k += LT) {
+        shK[k] = mxK[k] == G::POISON ? 0 : G::shift(mxK[k], hb);
+        shM[k] = mxM[k] == G::POISON ? 0 : G::shift(mxM[k], hb);
+    }
+    __syncthreads();
+    for (int j = t; j < L; j += LT) {  // pass 2: exact sums
+        const uint32_t p = pk[a0 + j];
+        const int64_t e = static_cast<uint32_t>(adj[a0 + j]) >> 2;
+        double kd[NLB], md[NLB], ev[DIM][DIM];
+        int sl[NLB];
+        long_entry<DIM, T, COEF, QN>(row, w0, sd, p, e, coords, col_idx, cK, cM, kd, md, sl, ev);
+#pragma unroll
+        for (int b = 0; b < NLB; ++b) {
+            if (mxK[sl[b]] != G::POISON) atomicAdd(accK + sl[b], G::quant(kd[b], shK[sl[b]]));
+            if (mxM[sl[b]] != G::POISON) atomicAdd(accM + sl[b], G::quant(md[b], shM[sl[b]]));
+        }
+    }
+    __syncthreads();
+    for (int k = t; k < len; k += LT) {
+        valsK[w0 + k] = mxK[k] == G::POISON ? static_cast<T>(NAN) : static_cast<T>(G::back(accK[k], shK[k]));
+        if (valsM) valsM[w0 + k] = mxM[k] == G::POISON ? static_cast<T>(NAN) : static_cast<T>(G::back(accM[k], shM[k]));
+    }
 }
 
 // ---------------------------------------------------------------------------- host
@@ -2174,9 +2497,21 @@ pf_status numeric_dispatch32(const pf_csr* c, const double* coords, const void* 
     return launch_numeric32<DIM, COEF, NT32 / 32, QN>(c, coords, cK, cM, valsK, valsM, f, ctr, s);
 }
 
+// the long rows of a structure (none for most meshes): one workgroup each
+template <int DIM, typename T, bool COEF, int QN>
+pf_status launch_long(const pf_csr* c, const double* coords, const void* cK, const void* cM, void* valsK, void* valsM,
+                      Fallback f, int64_t* ctr, hipStream_t s) {
+    if (c->nlong == 0) return PF_OK;
+    hipLaunchKernelGGL((k_numeric_long<DIM, T, COEF, QN>), dim3(static_cast<unsigned>(c->nlong)), dim3(LT), 0, s,
+                       c->lrows, coords, c->row_ptr, c->col_idx, c->aptr, c->adj, c->pk, c->dpos,
+                       static_cast<const T*>(cK), static_cast<const T*>(cM), static_cast<T*>(valsK),
+                       static_cast<T*>(valsM), f, ctr);
+    return launch_check("pf_assemble (long rows)");
+}
+
 template <int DIM, typename T>
-pf_status numeric_dispatch(const pf_csr* c, const double* coords, const void* cK, const void* cM, void* valsK,
-                           void* valsM, Fallback f, int64_t* ctr, hipStream_t s) {
+pf_status numeric_dispatch_rows(const pf_csr* c, const double* coords, const void* cK, const void* cM, void* valsK,
+                                void* valsM, Fallback f, int64_t* ctr, hipStream_t s) {
     const bool coef = cK || cM;
     if constexpr (sizeof(T) == 4) {
         return coef ? numeric_dispatch32<DIM, true>(c, coords, cK, cM, valsK, valsM, f, ctr, s)
@@ -2197,10 +2532,19 @@ pf_status numeric_dispatch(const pf_csr* c, const double* coords, const void* cK
     }
 }
 
+template <int DIM, typename T>
+pf_status numeric_dispatch(const pf_csr* c, const double* coords, const void* cK, const void* cM, void* valsK,
+                           void* valsM, Fallback f, int64_t* ctr, hipStream_t s) {
+    pf_status st = numeric_dispatch_rows<DIM, T>(c, coords, cK, cM, valsK, valsM, f, ctr, s);
+    if (st != PF_OK) return st;
+    return (cK || cM) ? launch_long<DIM, T, true, 0>(c, coords, cK, cM, valsK, valsM, f, ctr, s)
+                      : launch_long<DIM, T, false, 0>(c, coords, cK, cM, valsK, valsM, f, ctr, s);
+}
+
 // coefficients at the QN integration points of every element
 template <int DIM, typename T, int QN>
-pf_status numeric_dispatch_quad(const pf_csr* c, const double* coords, const void* cKq, const void* cMq, void* valsK,
-                                void* valsM, Fallback f, int64_t* ctr, hipStream_t s) {
+pf_status numeric_dispatch_quad_rows(const pf_csr* c, const double* coords, const void* cKq, const void* cMq,
+                                     void* valsK, void* valsM, Fallback f, int64_t* ctr, hipStream_t s) {
     if constexpr (sizeof(T) == 4) return numeric_dispatch32<DIM, false, QN>(c, coords, cKq, cMq, valsK, valsM, f, ctr, s);
     switch (numeric_rows<DIM, T>(c)) {
         case NR_BIG:
@@ -2213,7 +2557,27 @@ pf_status numeric_dispatch_quad(const pf_csr* c, const double* coords, const voi
     }
 }
 
+template <int DIM, typename T, int QN>
+pf_status numeric_dispatch_quad(const pf_csr* c, const double* coords, const void* cKq, const void* cMq, void* valsK,
+                                void* valsM, Fallback f, int64_t* ctr, hipStream_t s) {
+    pf_status st = numeric_dispatch_quad_rows<DIM, T, QN>(c, coords, cKq, cMq, valsK, valsM, f, ctr, s);
+    if (st != PF_OK) return st;
+    return launch_long<DIM, T, false, QN>(c, coords, cKq, cMq, valsK, valsM, f, ctr, s);
+}
+
 }  // namespace
+
+// the long rows of a structure alone (the serving loop's fused launches skip them)
+pf_status numeric_long(const pf_csr* c, pf_dtype prec, const double* coords, void* valsK, void* valsM,
+                       const pf_fallback* fb, int64_t* ctr, hipStream_t s) {
+    if (c->nlong == 0) return PF_OK;
+    const Fallback f = make_fallback(fb);
+    if (c->dim == 3)
+        return prec == PF_F32 ? launch_long<3, float, false, 0>(c, coords, nullptr, nullptr, valsK, valsM, f, ctr, s)
+                              : launch_long<3, double, false, 0>(c, coords, nullptr, nullptr, valsK, valsM, f, ctr, s);
+    return prec == PF_F32 ? launch_long<2, float, false, 0>(c, coords, nullptr, nullptr, valsK, valsM, f, ctr, s)
+                          : launch_long<2, double, false, 0>(c, coords, nullptr, nullptr, valsK, valsM, f, ctr, s);
+}
 
 // rows per block of a job's numeric phase (as pf_assemble chooses)
 int numeric_class(const pf_csr* c, pf_dtype prec) {
@@ -2283,7 +2647,7 @@ pf_status numeric_launch_many(int dim, pf_dtype prec, int nr, const NumericJob* 
 }
 
 size_t csr_bytes(const pf_csr* c) {
-    return static_cast<size_t>(c->cap_scratch + c->cap_res) + static_cast<size_t>(c->cap_nnz) * 4 +
+    return static_cast<size_t>(c->cap_scratch + c->cap_res) + static_cast<size_t>(c->cap_nnz + c->cap_lrows + c->cap_lcol) * 4 +
            static_cast<size_t>(c->cap_work) * 8 +
            static_cast<size_t>(c->cap_fcount + c->cap_bcount + c->cap_fptr + c->cap_bptr + c->cap_faces + c->cap_fel +
                                c->cap_bfaces + c->cap_bel) * 4 + static_cast<size_t>(c->cap_finfo) * 8 +
@@ -2312,6 +2676,8 @@ bool csr_view(const pf_csr* c, CsrView* v) {
     v->wmax16 = c->wmax_mid;
     v->wmax32 = c->wmax_big;
     v->max_adj = c->max_adj;
+    v->nlong = c->nlong;
+    v->lrows = c->lrows;
     return true;
 }
 const int32_t* csr_adj(const pf_csr* c) { return c->adj; }
@@ -2348,6 +2714,7 @@ void csr_release(pf_csr* c, hipStream_t s) {
         if (e) (void)hipEventDestroy(e);
     drop(c->scratch, c->cap_scratch, s);
     drop(c->res, c->cap_res, s);
+    drop(c->lrows, c->cap_lrows, s);
     drop(c->col_idx, c->cap_nnz, s);
     drop(c->work, c->cap_work, s);
     drop(c->fcount, c->cap_fcount, s);
@@ -2486,14 +2853,18 @@ pf_status symbolic_enqueue(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, 
         const int64_t b_len = part(4 * (nn + 1)), b_pad = part(4 * nn * MAXADJ), b_cnt = part(4 * (nn + 1));
         const int64_t b_blk = part(4 * std::max<int64_t>(regions * RR * maxrow, 1));
         const int64_t b_look = part(8 * ((1 + TSTAT / 2) * std::max<int64_t>(tiles, 1) + 1));
-        if ((st = grow(c->scratch, c->cap_scratch, b_len + b_pad + b_cnt + b_blk + b_look, s))) return st;
+        const int64_t b_lst = part(4 * nn);  // the long rows' list
+        if ((st = grow(c->scratch, c->cap_scratch, b_len + b_pad + b_cnt + b_blk + b_look + b_lst, s))) return st;
         unsigned char* q = c->scratch;
         c->adj_len = reinterpret_cast<int32_t*>(q);
         c->adj_pad = reinterpret_cast<int32_t*>(q + b_len);
         c->cnt = reinterpret_cast<int32_t*>(q + b_len + b_pad);
         c->colblk = reinterpret_cast<int32_t*>(q + b_len + b_pad + b_cnt);
         c->look = reinterpret_cast<uint64_t*>(q + b_len + b_pad + b_cnt + b_blk);
+        c->lrows_s = reinterpret_cast<int32_t*>(q + b_len + b_pad + b_cnt + b_blk + b_look);
     }
+    c->nlong = 0;
+    c->q_long = false;
     if (!c->hinfo && (st = pinned_words(&c->hinfo))) return st;
     if ((st = mark(c, 0, s))) return st;
     hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, c->info, int64_t(INFO_WORDS), int64_t(0));
@@ -2521,10 +2892,10 @@ pf_status symbolic_enqueue(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, 
                                c->aptr, c->cnt, c->colblk, c->adj, c->pk2, c->dpos, c->info);
         else if (nlb == 4)
             hipLaunchKernelGGL((k_rows_p1<4>), dim3(g1), dim3(PT), 0, s, nn, elems, c->adj_len, c->adj_pad, c->aptr,
-                               c->cnt, c->colblk, c->adj, c->pk, c->dpos, c->info);
+                               c->cnt, c->colblk, c->adj, c->pk, c->dpos, c->lrows_s, c->info);
         else
             hipLaunchKernelGGL((k_rows_p1<3>), dim3(g1), dim3(PT), 0, s, nn, elems, c->adj_len, c->adj_pad, c->aptr,
-                               c->cnt, c->colblk, c->adj, c->pk, c->dpos, c->info);
+                               c->cnt, c->colblk, c->adj, c->pk, c->dpos, c->lrows_s, c->info);
     }
     if ((st = mark(c, 2, s))) return st;
     if (nn > 0) {
@@ -2550,18 +2921,58 @@ pf_status symbolic_enqueue(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, 
     c->q_nn = nn;
     c->q_ne = ne;
     c->q_stream = s;
+    c->q_elems = elems;
     return PF_OK;
 }
 
 // the build's scratch, released in the order of its stream
 void drop_scratch(pf_csr* c, hipStream_t s) {
     drop(c->scratch, c->cap_scratch, s);
-    c->adj_len = c->adj_pad = c->cnt = c->colblk = nullptr;
+    drop(c->lcol, c->cap_lcol, s);
+    c->adj_len = c->adj_pad = c->cnt = c->colblk = c->lrows_s = nullptr;
     c->look = nullptr;
 }
 
-// phase 2: phase 1's status words have reached the host (its ready event has completed);
-// check them, fix the structure's sizes and launch statistics, and enqueue the columns
+// Phase 1b, only for a P1 mesh whose phase 1 listed long rows: their list made resident,
+// their nodes' compact adjacency, one workgroup per long row for its pattern (columns into
+// lcol, slot words, diagonal position, row length), then the row offsets and statistics again
+// with the long rows' lengths; ends with the status readback and the ready event.
+pf_status symbolic_long(pf_csr* c, const char* who) {
+    hipStream_t s = c->q_stream;
+    const int64_t nlong = c->hinfo[INFO_NLONG];
+    const int64_t nn = c->q_nn, m = c->q_ne * c->q_nlb;
+    pf_status st;
+    if ((st = grow(c->lrows, c->cap_lrows, nlong, s))) return st;
+    if ((st = grow(c->lcol, c->cap_lcol, nlong * LCAP, s))) return st;
+    c->nlong = nlong;
+    c->q_long = true;
+    PF_HIP_TRY(hipMemcpyAsync(c->lrows, c->lrows_s, nlong * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_long_adj, dim3(flat_grid(m)), dim3(SBS), 0, s, c->q_elems, m, c->q_nlb, c->dpos, c->aptr,
+                       c->cnt, c->adj);
+    const unsigned g = static_cast<unsigned>(nlong);
+    if (c->q_nlb == 4)
+        hipLaunchKernelGGL((k_rows_long<4>), dim3(g), dim3(LT), 0, s, c->lrows, c->q_elems, c->aptr, c->adj, c->cnt,
+                           c->lcol, c->pk, c->dpos, c->info);
+    else
+        hipLaunchKernelGGL((k_rows_long<3>), dim3(g), dim3(LT), 0, s, c->lrows, c->q_elems, c->aptr, c->adj, c->cnt,
+                           c->lcol, c->pk, c->dpos, c->info);
+    const int64_t tiles = ceil_div(nn, SCAN_TILE);
+    hipLaunchKernelGGL(k_fill_i64, dim3(flat_grid(tiles)), dim3(SBS), 0, s, reinterpret_cast<int64_t*>(c->look), tiles,
+                       int64_t(0));
+    int32_t* tstat = reinterpret_cast<int32_t*>(c->look + ((tiles + 1) & ~int64_t(1)));
+    hipLaunchKernelGGL(k_row_offsets, dim3(static_cast<unsigned>(tiles)), dim3(SBS), 0, s, nn, c->cnt, c->adj_len,
+                       c->row_ptr, c->look, tstat, c->info);
+    hipLaunchKernelGGL(k_row_stats, dim3(1), dim3(SBS), 0, s, tiles, tstat, c->info);
+    if ((st = launch_check(who))) return st;
+    PF_HIP_TRY(hipMemcpyAsync(c->hinfo, c->info, INFO_WORDS * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    PF_HIP_TRY(hipEventRecord(c->ready, s));
+    c->stage = 3;
+    return PF_OK;
+}
+
+// After phase 1 (or 1b): its status words have reached the host (the ready event has
+// completed).  Check them; if phase 1 listed long rows, enqueue phase 1b; otherwise fix the
+// structure's sizes and launch statistics and enqueue phase 2 (the columns).
 pf_status symbolic_columns(pf_csr* c, const char* who) {
     c->stage = 0;
     hipStream_t s = c->q_stream;
@@ -2569,14 +2980,17 @@ pf_status symbolic_columns(pf_csr* c, const char* who) {
     const int dim = c->q_dim, nlb = c->q_nlb;
     const int64_t nn = c->q_nn, ne = c->q_ne;
     const bool p2 = nlb > dim + 1;
-    const int maxrow = p2 ? MAXROW2 : MAXROW;
     pf_status st = PF_OK;
     if (info[0] & ERR_INDEX) st = fail(PF_EINDEX, std::string(who) + ": node index out of range in elems");
     else if (info[0] & ERR_ROW)
-        st = fail(PF_ELIMIT, std::string(who) + ": a node belongs to more than 64 elements or a row has more than " +
-                                 std::to_string(maxrow) + " nonzeros");
+        st = p2 ? fail(PF_ELIMIT, std::string(who) + ": a node belongs to more than 64 elements or a row has more "
+                                  "than " + std::to_string(MAXROW2) + " nonzeros")
+                : fail(PF_ELIMIT, std::string(who) + ": a row has more than " + std::to_string(LCAP) + " nonzeros");
     else if (info[0] & ERR_SCAN) st = fail(PF_EINVAL, std::string(who) + ": the row offsets could not be formed");
     else if (info[2] >= INT32_MAX) st = fail(PF_ELIMIT, std::string(who) + ": nnz must be < 2^31");
+    if (st == PF_OK && !p2 && !c->q_long && info[INFO_NLONG] > 0) {
+        if ((st = symbolic_long(c, who)) == PF_OK) return PF_OK;
+    }
     const int64_t nnz = info[2];
     if (st == PF_OK) st = grow(c->col_idx, c->cap_nnz, std::max<int64_t>(nnz, 1), s);
     if (st != PF_OK) {
@@ -2593,6 +3007,9 @@ pf_status symbolic_columns(pf_csr* c, const char* who) {
         else
             hipLaunchKernelGGL((k_row_columns<RR * MAXROW, 2>), dim3(tiles), dim3(SBS), 0, s, nn, c->row_ptr,
                                c->colblk, c->col_idx);
+        if (c->nlong > 0)
+            hipLaunchKernelGGL(k_long_columns, dim3(static_cast<unsigned>(c->nlong)), dim3(LT), 0, s, c->lrows, nn,
+                               c->row_ptr, c->aptr, c->colblk, c->lcol, c->col_idx);
     }
     if ((st = mark(c, 5, s))) return st;
     if ((st = launch_check(who))) return st;
@@ -2620,6 +3037,10 @@ pf_status symbolic(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const in
     if (st != PF_OK) return st;
     PF_HIP_TRY(hipEventSynchronize(c->ready));
     if ((st = symbolic_columns(c, who))) return st;
+    if (c->stage == 3) {  // the long-row phase ran: its status, then the columns
+        PF_HIP_TRY(hipEventSynchronize(c->ready));
+        if ((st = symbolic_columns(c, who))) return st;
+    }
     // the columns complete in the order of the stream: no wait here (csr_order orders the
     // work of other streams after them)
     c->stage = 0;
@@ -2649,7 +3070,7 @@ int csr_symbolic_poll(pf_csr* c, pf_status* st) {
         *st = fail(PF_EHIP, std::string("pf_server build: ") + hipGetErrorString(e));
         return 1;
     }
-    if (c->stage == 1) {  // the pattern phase ended: the columns follow
+    if (c->stage == 1 || c->stage == 3) {  // the pattern (or long-row) phase ended: what follows
         const pf_status s1 = symbolic_columns(c, "pf_server build");
         if (s1 != PF_OK) {
             c->stage = 0;
@@ -2717,6 +3138,9 @@ pf_status pf_csr_faces(pf_csr* c, const double* coords, const int32_t* elems, vo
     if (!c) return fail(PF_EINVAL, "pf_csr_faces: null handle");
     if (!c->built) return fail(PF_ESTATE, "pf_csr_faces: structure not built");
     if (c->p2) return fail(PF_ESTATE, "pf_csr_faces: a P2 structure");
+    if (c->nlong > 0)
+        return fail(PF_ELIMIT, "pf_csr_faces: a node lies in more than 64 elements or a row holds more than 64 "
+                               "nonzeros (faces need rows of the row-block path)");
     if (c->ne > 0 && (!coords || !elems)) return fail(PF_EINVAL, "pf_csr_faces: null coords or elems");
     hipStream_t s = as_stream(stream);
     if (pf_status st = csr_order(c, s)) return st;
@@ -2808,8 +3232,9 @@ pf_status pf_csr_info(const pf_csr* c, int64_t* nn, int64_t* nnz, const int32_t*
 pf_status pf_csr_memory(const pf_csr* c, int64_t* resident, int64_t* scratch) {
     if (!c) return fail(PF_EINVAL, "pf_csr_memory: null handle");
     const int64_t all = static_cast<int64_t>(csr_bytes(c));
-    if (resident) *resident = all - c->cap_scratch;
-    if (scratch) *scratch = c->cap_scratch;
+    const int64_t scr = c->cap_scratch + 4 * c->cap_lcol;
+    if (resident) *resident = all - scr;
+    if (scratch) *scratch = scr;
     return PF_OK;
 }
 

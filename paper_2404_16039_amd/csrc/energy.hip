@@ -88,7 +88,7 @@ __global__ __launch_bounds__(RBS) void k_rhs_elem(int64_t nn, const double* __re
 }
 
 // b[i] = sum of the entries of the elements around node i, exact on the grid of the node's
-// largest entry.  Half a wave per node: lane l reads adjacency entries l and l + 32 of the
+// largest entry (a node of more than 64 elements: on a LongGrid, every entry in turn).  Half a wave per node: lane l reads adjacency entries l and l + 32 of the
 // node (contiguous words from aptr[i]) and gathers their local-vector values; the row maximum and then
 // the integer sum of the rounded values are reduced across the 32 lanes with shuffles
 // (integer adds: exact, so the result does not depend on the entry order).  Each half wave
@@ -134,6 +134,30 @@ __global__ __launch_bounds__(RBS) void k_rhs_nodes(int64_t nn, int nlb, const in
     }
 #pragma unroll
     for (int k = 0; k < RHS_ROWS; ++k) {
+        const int Lf = i[k] < nn ? a1[k] - a0[k] : 0;  // the same for the half wave
+        if (Lf > CSR_MAXADJ) {
+            // a node of more than 64 elements: every entry in turn, summed on a LongGrid
+            using G = LongGrid;
+            const int hb = G::headroom(Lf);
+            uint32_t mx = 0u;
+            for (int j = l; j < Lf; j += 32) {
+                const int32_t w = adj[static_cast<int64_t>(a0[k]) + j];
+                mx = max(mx, G::mag(static_cast<double>(b2D[static_cast<int64_t>(w >> 2) * nlb + (w & 3)])));
+            }
+#pragma unroll
+            for (int d = 16; d >= 1; d >>= 1)
+                mx = max(mx, static_cast<uint32_t>(__shfl_xor(static_cast<int>(mx), d, 32)));
+            const int sh = mx == G::POISON ? 0 : G::shift(mx, hb);
+            unsigned long long acc = 0ull;
+            for (int j = l; j < Lf; j += 32) {
+                const int32_t w = adj[static_cast<int64_t>(a0[k]) + j];
+                acc += G::quant(static_cast<double>(b2D[static_cast<int64_t>(w >> 2) * nlb + (w & 3)]), sh);
+            }
+#pragma unroll
+            for (int d = 16; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 32);
+            if (l == 0) b[i[k]] = mx == G::POISON ? static_cast<T>(NAN) : static_cast<T>(G::back(acc, sh));
+            continue;
+        }
         uint32_t mx = max(Exact<T>::mag(v0[k]), Exact<T>::mag(v1[k]));
 #pragma unroll
         for (int d = 16; d >= 1; d >>= 1)

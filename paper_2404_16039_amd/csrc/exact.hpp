@@ -66,6 +66,7 @@ struct Exact<double> {
 // POISON marks a row that received a non-finite contribution.
 struct RowGrid32 {
     static constexpr uint32_t POISON = 0xffffffffu;
+    static constexpr uint32_t SKIP = 0xfffffffeu;  // a row left to another kernel (no stores)
     __device__ static uint32_t mag(float x) { return __float_as_uint(fabsf(x)); }
     // 44 - e for a normal maximum; a zero or subnormal maximum takes e = -127 (every
     // contribution is then below 2^-126 and scales below 2^44)
@@ -76,6 +77,32 @@ struct RowGrid32 {
     }
     __device__ static float back(uint64_t a, int sh) {
         return static_cast<float>(ldexp(static_cast<double>(static_cast<int64_t>(a)), -sh));
+    }
+};
+
+// Per-slot grid of the long-row kernels (a slot there may receive thousands of contributions):
+// FP64 contributions are rounded onto 2^(e + 1 - (62 - HB)), e the exponent of the slot's
+// largest one and HB = (bit length of the entry count) + 1 bits of headroom, and summed as
+// 64-bit integers: exact, so the order of the adds does not matter, and no sum of at most the
+// entry count of them can overflow.  Each contribution's rounding error is at most 2^(HB - 62)
+// of the largest one's power of two (for 1000 entries, 2^-51).  POISON marks a slot that got
+// a non-finite contribution.
+struct LongGrid {
+    static constexpr uint32_t POISON = 0xffffffffu;
+    static __device__ __forceinline__ uint32_t mag(double x) {  // the high word of |x|: ordered
+        return __builtin_isfinite(x) ? static_cast<uint32_t>(static_cast<uint64_t>(__double_as_longlong(fabs(x))) >> 32)
+                                     : POISON;
+    }
+    static __device__ __forceinline__ int headroom(int entries) { return 33 - __clz(entries | 1); }
+    static __device__ __forceinline__ int shift(uint32_t m, int hb) {
+        const int e = static_cast<int>((m >> 20) & 0x7ff);  // |x| < 2^(e - 1022)
+        return (62 - hb) - (e - 1022);
+    }
+    static __device__ __forceinline__ unsigned long long quant(double x, int sh) {
+        return static_cast<unsigned long long>(__double2ll_rn(ldexp(x, sh)));
+    }
+    static __device__ __forceinline__ double back(unsigned long long a, int sh) {
+        return ldexp(static_cast<double>(static_cast<long long>(a)), -sh);
     }
 };
 

@@ -34,6 +34,10 @@ void numeric_describe(const pf_csr* c, const double* coords, void* valsK, void* 
 // block; wmax = the largest window of those jobs, nblocks = the total block count
 pf_status numeric_launch_many(int dim, pf_dtype prec, int nr, const NumericJob* d_jobs, int njobs, int64_t nblocks,
                               int wmax, hipStream_t s);
+// the numeric phase of the structure's long rows alone, constant coefficients (the fused
+// multi-mesh launches skip long rows)
+pf_status numeric_long(const pf_csr* c, pf_dtype prec, const double* coords, void* valsK, void* valsM,
+                       const pf_fallback* fb, int64_t* counters, hipStream_t s);
 size_t csr_bytes(const pf_csr* c);
 int64_t csr_nnz(const pf_csr* c);
 int64_t csr_nn(const pf_csr* c);
@@ -57,11 +61,22 @@ struct CsrView {
     const int32_t* dpos;
     int wmax4, wmax16, wmax32;
     int max_adj;
+    int64_t nlong;         // long rows (P1 only) ...
+    const int32_t* lrows;  // ... and their list
 };
 bool csr_view(const pf_csr* c, CsrView* v);  // false unless built
 // node -> element adjacency of the structure: entries (element << 2 | local index) of node i
 // at adj[aptr[i]] .. adj[aptr[i+1] - 1], at most CSR_MAXADJ of them
 constexpr int CSR_MAXADJ = 64;
+// A P1 row is long when its node lies in more than CSR_MAXADJ elements or the row holds
+// more than CSR_MAXROW nonzeros: the row-block kernels skip it, and kernels of one workgroup
+// per long row (listed in lrows, nlong of them) assemble it; a long row holds at most
+// CSR_LCAP nonzeros.
+constexpr int CSR_MAXROW = 64;
+constexpr int CSR_LCAP = 256;
+__host__ __device__ inline bool csr_long_row(int elements, int nonzeros) {
+    return elements > CSR_MAXADJ || nonzeros > CSR_MAXROW;
+}
 const int32_t* csr_adj(const pf_csr* c);
 const int32_t* csr_aptr(const pf_csr* c);
 // asynchronous structure build (the serving loop): csr_symbolic_enqueue issues the first

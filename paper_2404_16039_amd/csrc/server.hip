@@ -463,8 +463,13 @@ void run_tick(pf_server* S, std::vector<SJob*>& ready, std::vector<std::pair<SJo
             for (auto& kv : cls)
                 if (std::get<0>(kv.first) == L.dim && std::get<1>(kv.first) == L.prec && std::get<2>(kv.first) == L.nr)
                     for (SJob* j : kv.second) {
-                        if (st == PF_OK) launched.push_back(j);
-                        else failed.emplace_back(j, st);
+                        // the job's long rows (rare), which the fused launch skips
+                        pf_status sj = st;
+                        if (sj == PF_OK)
+                            sj = numeric_long(j->topo->csr, static_cast<pf_dtype>(L.prec), j->d_coords, j->d_valsK,
+                                              j->d_valsM, &j->spec.fb, j->d_ctr, S->s);
+                        if (sj == PF_OK) launched.push_back(j);
+                        else failed.emplace_back(j, sj);
                     }
             ++tc.launches;
         }

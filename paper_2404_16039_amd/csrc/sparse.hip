@@ -86,17 +86,35 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_
                                                         T* __restrict__ valsK, T* __restrict__ valsM) {
     using A = typename Exact<T>::acc;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int32_t rp[PR + 1], apre[PR + 1], dslot[PR];
+    __shared__ int32_t rp[PR + 1], abase[PR + 1], apre[PR + 1], dslot[PR];
+    __shared__ int32_t anylong;
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * PR;
     const int nr = static_cast<int>((r0 + PR < nn) ? PR : nn - r0);
     if (threadIdx.x <= PR) {  // rows past the end: no slots, no entries
         const int r = threadIdx.x <= nr ? threadIdx.x : nr;
         rp[threadIdx.x] = row_ptr[r0 + r];
-        apre[threadIdx.x] = aptr[r0 + r];
+        abase[threadIdx.x] = aptr[r0 + r];
     }
     if (threadIdx.x < PR) dslot[threadIdx.x] = static_cast<int>(threadIdx.x) < nr ? dpos[r0 + threadIdx.x] : 0;
     __syncthreads();
-    const int32_t a00 = apre[0];  // the block's entries are a00 .. apre[nr] - 1 of the adjacency
+    static_assert(PR <= 64, "the row prefix runs in one wave");
+    if (threadIdx.x < 64) {  // prefix of the rows' entries in wave 0; P1 long rows count none
+        const int r = threadIdx.x;
+        const int La = r < nr ? abase[r + 1] - abase[r] : 0;
+        const bool lng = !P2 && r < nr && csr_long_row(La, rp[r + 1] - rp[r]);
+        const int Lk = lng ? 0 : La;
+        int x = Lk;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(x, d, 64);
+            if (r >= d) x += y;
+        }
+        if (r < PR) apre[r] = x - Lk;
+        if (r == PR - 1) apre[PR] = x;
+        const unsigned long long lm = __ballot(lng);
+        if (r == 0) anylong = lm != 0ull;
+    }
+    __syncthreads();
     const int32_t w0 = rp[0];
     const int W = rp[nr] - w0;
     A* accK = reinterpret_cast<A*>(smem);
@@ -111,7 +129,6 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_
         shM[w] = 0;
     }
     // this thread's entries k = thread + q PBT of the block's flat list; loads without branches
-    static_assert(PR <= 64, "a block's rows");
     int rq[PITEMS];
     int64_t eq[PITEMS];
     int aq[PITEMS];
@@ -119,9 +136,9 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_
 #pragma unroll
     for (int q = 0; q < PITEMS; ++q) {
         const int idx = threadIdx.x + q * PBT;
-        const bool ok = idx < apre[PR] - a00;
-        const int r = ok ? last_le(apre, PR, a00 + idx) : 0;
-        const int64_t t = ok ? static_cast<int64_t>(a00) + idx : 0;
+        const bool ok = idx < apre[PR];
+        const int r = ok ? last_le(apre, PR, idx) : 0;
+        const int64_t t = ok ? static_cast<int64_t>(abase[r]) + (idx - apre[r]) : 0;
         const int32_t w = adj[t];
         pq[q] = P2 ? pk2[t] : static_cast<uint64_t>(pk[t]);
         rq[q] = ok ? r : -1;
@@ -129,6 +146,12 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_
         aq[q] = ok ? (w & (P2 ? 15 : 3)) : 0;
     }
     __syncthreads();  // accumulators cleared
+    if (anylong) {  // a long row's slots are marked: neither graded nor stored here
+        for (int r = 0; r < nr; ++r)
+            if (csr_long_row(abase[r + 1] - abase[r], rp[r + 1] - rp[r]))
+                for (int k = rp[r] - w0 + threadIdx.x; k < rp[r + 1] - w0; k += PBT) shK[k] = INT32_MIN;
+        __syncthreads();
+    }
     // window position of local node b of the entry's element in its row
     auto slot = [&](int q, int b) -> int {
         const int r = rq[q], a = aq[q];
@@ -157,6 +180,7 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_
     }
     __syncthreads();
     for (int w = threadIdx.x; w < W; w += PBT) {
+        if (shK[w] == INT32_MIN) continue;
         shK[w] = Exact<T>::shift(static_cast<uint32_t>(shK[w]));
         shM[w] = Exact<T>::shift(static_cast<uint32_t>(shM[w]));
     }
@@ -173,8 +197,84 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_
     }
     __syncthreads();
     for (int w = threadIdx.x; w < W; w += PBT) {
+        if (shK[w] == INT32_MIN) continue;
         if (valsK) valsK[w0 + w] = Exact<T>::back(accK[w], shK[w]);
         if (valsM) valsM[w0 + w] = Exact<T>::back(accM[w], shM[w]);
+    }
+}
+
+// The long rows of a P1 structure (one workgroup each, at most CSR_LCAP slots): every entry's
+// column of its element's pages, graded and summed on each slot's LongGrid as in the
+// long-row numeric kernel (page values are exact in FP64).
+template <int NB, typename T>
+__global__ __launch_bounds__(PBT) void k_assemble_pages_long(const int32_t* __restrict__ lrows,
+                                                             const int32_t* __restrict__ row_ptr,
+                                                             const int32_t* __restrict__ aptr,
+                                                             const int32_t* __restrict__ adj,
+                                                             const uint32_t* __restrict__ pk,
+                                                             const int32_t* __restrict__ dpos,
+                                                             const T* __restrict__ pagesK, const T* __restrict__ pagesM,
+                                                             T* __restrict__ valsK, T* __restrict__ valsM) {
+    using G = LongGrid;
+    __shared__ uint32_t mxK[CSR_LCAP], mxM[CSR_LCAP];
+    __shared__ int32_t shK[CSR_LCAP], shM[CSR_LCAP];
+    __shared__ unsigned long long accK[CSR_LCAP], accM[CSR_LCAP];
+    const int t = static_cast<int>(threadIdx.x);
+    const int64_t row = lrows[blockIdx.x];
+    const int64_t w0 = row_ptr[row];
+    const int len = row_ptr[row + 1] - static_cast<int>(w0);
+    const int64_t a0 = aptr[row];
+    const int L = aptr[row + 1] - static_cast<int>(a0);
+    const int sd = dpos[row];
+    const int hb = G::headroom(L);
+    for (int k = t; k < CSR_LCAP; k += PBT) {
+        mxK[k] = mxM[k] = 0u;
+        accK[k] = accM[k] = 0ull;
+    }
+    __syncthreads();
+    auto entry = [&](int j, double (&kv)[NB], double (&mv)[NB], int (&sl)[NB]) {
+        const int32_t w = adj[a0 + j];
+        const uint32_t p = pk[a0 + j];
+        const int64_t e = static_cast<uint32_t>(w) >> 2;
+        const int a = w & 3;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            sl[b] = b == a ? sd : static_cast<int>((p >> (2 + 8 * (b < a ? b : b - 1))) & 255);
+            const int64_t idx = e * (NB * NB) + a * NB + b;  // column a, entry b
+            kv[b] = pagesK ? static_cast<double>(pagesK[idx]) : 0.0;
+            mv[b] = pagesM ? static_cast<double>(pagesM[idx]) : 0.0;
+        }
+    };
+    for (int j = t; j < L; j += PBT) {
+        double kv[NB], mv[NB];
+        int sl[NB];
+        entry(j, kv, mv, sl);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            atomicMax(mxK + sl[b], G::mag(kv[b]));
+            atomicMax(mxM + sl[b], G::mag(mv[b]));
+        }
+    }
+    __syncthreads();
+    for (int k = t; k < len; k += PBT) {
+        shK[k] = mxK[k] == G::POISON ? 0 : G::shift(mxK[k], hb);
+        shM[k] = mxM[k] == G::POISON ? 0 : G::shift(mxM[k], hb);
+    }
+    __syncthreads();
+    for (int j = t; j < L; j += PBT) {
+        double kv[NB], mv[NB];
+        int sl[NB];
+        entry(j, kv, mv, sl);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if (mxK[sl[b]] != G::POISON) atomicAdd(accK + sl[b], G::quant(kv[b], shK[sl[b]]));
+            if (mxM[sl[b]] != G::POISON) atomicAdd(accM + sl[b], G::quant(mv[b], shM[sl[b]]));
+        }
+    }
+    __syncthreads();
+    for (int k = t; k < len; k += PBT) {
+        if (valsK) valsK[w0 + k] = mxK[k] == G::POISON ? static_cast<T>(NAN) : static_cast<T>(G::back(accK[k], shK[k]));
+        if (valsM) valsM[w0 + k] = mxM[k] == G::POISON ? static_cast<T>(NAN) : static_cast<T>(G::back(accM[k], shM[k]));
     }
 }
 
@@ -254,6 +354,30 @@ pf_status pf_csr_assemble_pages(const pf_csr* csr, pf_dtype prec, const void* pa
             break;
         default:
             return fail(PF_EINVAL, "pf_csr_assemble_pages: unsupported element");
+    }
+    if (v.nlong > 0) {  // the long rows (P1), one workgroup each
+        const unsigned g = static_cast<unsigned>(v.nlong);
+        if (v.nlb == 3) {
+            if (f32)
+                hipLaunchKernelGGL((k_assemble_pages_long<3, float>), dim3(g), dim3(PBT), 0, s, v.lrows, v.row_ptr,
+                                   v.aptr, v.adj, v.pk, v.dpos, static_cast<const float*>(pK),
+                                   static_cast<const float*>(pM), static_cast<float*>(valsK), static_cast<float*>(valsM));
+            else
+                hipLaunchKernelGGL((k_assemble_pages_long<3, double>), dim3(g), dim3(PBT), 0, s, v.lrows, v.row_ptr,
+                                   v.aptr, v.adj, v.pk, v.dpos, static_cast<const double*>(pK),
+                                   static_cast<const double*>(pM), static_cast<double*>(valsK),
+                                   static_cast<double*>(valsM));
+        } else {
+            if (f32)
+                hipLaunchKernelGGL((k_assemble_pages_long<4, float>), dim3(g), dim3(PBT), 0, s, v.lrows, v.row_ptr,
+                                   v.aptr, v.adj, v.pk, v.dpos, static_cast<const float*>(pK),
+                                   static_cast<const float*>(pM), static_cast<float*>(valsK), static_cast<float*>(valsM));
+            else
+                hipLaunchKernelGGL((k_assemble_pages_long<4, double>), dim3(g), dim3(PBT), 0, s, v.lrows, v.row_ptr,
+                                   v.aptr, v.adj, v.pk, v.dpos, static_cast<const double*>(pK),
+                                   static_cast<const double*>(pM), static_cast<double*>(valsK),
+                                   static_cast<double*>(valsM));
+        }
     }
     return launch_check("pf_csr_assemble_pages");
 }

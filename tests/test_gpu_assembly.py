@@ -158,15 +158,13 @@ def test_edge_cases(lib):
     with pytest.raises(lib.PagefemError) as ei:
         lib.Csr().symbolic(3, 4, bad)
     assert ei.value.code == 6
-    # a node in more than 64 elements (a fan of 70 triangles) is a documented limit
-    k = 70
-    ang = np.linspace(0, 2 * np.pi, k, endpoint=False)
-    fan_c = np.concatenate([[[0.0, 0.0]], np.stack([np.cos(ang), np.sin(ang)], 1)])
+    # a row of more than 256 nonzeros (a fan of 300 triangles) is the documented limit; nodes
+    # in more than 64 elements are long rows (tests/test_gpu_longrows.py)
+    k = 300
     fan_e = np.array([[0, 1 + i, 1 + (i + 1) % k] for i in range(k)], np.int32)
     with pytest.raises(lib.PagefemError) as ei:
         lib.Csr().symbolic(2, k + 1, dev(fan_e))
     assert ei.value.code == 7
-    del fan_c
 
 
 def _sampled_rows_check(got, coords, elems, rows, dtype):
