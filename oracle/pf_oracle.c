@@ -77,7 +77,10 @@ static double leibniz(const double* a, int n, double* perm_abs) {
 
 /* Gauss-Jordan with partial pivoting on [A | I].  Returns 1 if a zero pivot occurs. */
 static int gauss_jordan(const double* a, int n, double* inv) {
-    double m[OR_MAXN][2 * OR_MAXN];
+    /* extended precision (64-bit significand on x86-64), one rounding to FP64 at the end:
+     * FP64 elimination loses up to ~10 bits on pages where partial pivoting still leaves a
+     * cancelling back substitution, more than the inverse's error scale allows */
+    long double m[OR_MAXN][2 * OR_MAXN];
     for (int r = 0; r < n; r++) {
         for (int c = 0; c < n; c++) m[r][c] = AT(a, n, r, c);
         for (int c = 0; c < n; c++) m[r][n + c] = (r == c) ? 1.0 : 0.0;
@@ -85,24 +88,24 @@ static int gauss_jordan(const double* a, int n, double* inv) {
     for (int col = 0; col < n; col++) {
         int piv = col;
         for (int r = col + 1; r < n; r++)
-            if (fabs(m[r][col]) > fabs(m[piv][col])) piv = r;
-        if (m[piv][col] == 0.0) {
+            if (fabsl(m[r][col]) > fabsl(m[piv][col])) piv = r;
+        if (m[piv][col] == 0.0L) {
             for (int i = 0; i < n * n; i++) inv[i] = NAN;
             return 1;
         }
         if (piv != col)
-            for (int c = 0; c < 2 * n; c++) { double t = m[col][c]; m[col][c] = m[piv][c]; m[piv][c] = t; }
-        double d = m[col][col];
+            for (int c = 0; c < 2 * n; c++) { long double t = m[col][c]; m[col][c] = m[piv][c]; m[piv][c] = t; }
+        long double d = m[col][col];
         for (int c = 0; c < 2 * n; c++) m[col][c] /= d;
         for (int r = 0; r < n; r++) {
             if (r == col) continue;
-            double f = m[r][col];
-            if (f != 0.0)
+            long double f = m[r][col];
+            if (f != 0.0L)
                 for (int c = 0; c < 2 * n; c++) m[r][c] -= f * m[col][c];
         }
     }
     for (int r = 0; r < n; r++)
-        for (int c = 0; c < n; c++) AT(inv, n, r, c) = m[r][n + c];
+        for (int c = 0; c < n; c++) AT(inv, n, r, c) = (double)m[r][n + c];
     return 0;
 }
 

@@ -196,6 +196,44 @@ def test_inverse_exact_rational(n):
                 assert abs(X[i, j] - float(ex[i][j])) <= 64 * 2.0 ** -53 * S[i, j]
 
 
+def _det_int(m):
+    """exact determinant of an integer matrix (lists of Python ints), first-row expansion"""
+    if len(m) == 1:
+        return m[0][0]
+    return sum((-1) ** j * m[0][j] * _det_int([row[:j] + row[j + 1:] for row in m[1:]]) for j in range(len(m)))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_inverse_exact_rational_10k(n):
+    """10^4 pages per order: each FP64 page is D^-1 times an integer matrix N (D its common
+    power-of-two denominator), so inv(A) = D adj(N) / det(N) exactly; every entry of the
+    oracle's inverse is checked in exact arithmetic, |X det(N) - D adj(N)| <= 64 u S |det(N)|
+    (S the oracle's error scale), and so is its determinant."""
+    cnt = 10000
+    A = gen.page_batch(cnt, n, sub=21)
+    inv, sing, scale = oracle.page_inv(A, n)
+    det, pa = oracle.page_det(A, n)
+    assert not sing.any()
+    u = Fr(1, 2 ** 53)
+    for k in range(cnt):
+        m = [[Fr(float(v)) for v in row] for row in _page(A[k], n, n)]
+        D = max(x.denominator for row in m for x in row)  # powers of two: the largest divides none
+        N = [[int(x * D) for x in row] for row in m]
+        dN = _det_int(N)
+        assert dN != 0
+        # det(A) = det(N) / D^n
+        assert abs(Fr(float(det[k])) - Fr(dN, D ** n)) <= 8 * u * Fr(float(pa[k]))
+        X = _page(inv[k], n, n)
+        S = _page(scale[k], n, n)
+        for i in range(n):
+            for j in range(n):
+                # cofactor C_ji of N: the (i, j) entry of adj(N)
+                minor = [row[:i] + row[i + 1:] for r, row in enumerate(N) if r != j] if n > 1 else []
+                adj = (-1) ** (i + j) * (_det_int(minor) if n > 1 else 1)
+                err = abs(Fr(float(X[i, j])) * dN - D * adj)
+                assert err <= 64 * u * Fr(float(S[i, j])) * abs(dN), (k, i, j)
+
+
 @pytest.mark.parametrize("n", [2, 3, 4])
 def test_inverse_identities_and_singular(n):
     A = gen.page_batch(100, n, sub=12)
@@ -240,7 +278,17 @@ def test_transpose_and_products_vs_library():
     assert np.array_equal(T, fa)
     s = g.standard_normal(30)
     Sc = oracle.page_scale(s, fa, m, k)
-    assert np.array_equal(Sc, fa * s[:, None])
+    # pinned through other routines: the product with the page s I (every other term an
+    # exact zero, so the same bits), det(s A) = s^n det(A), and powers of two (exact)
+    sI = np.stack([_colmajor(np.eye(m) * v) for v in s])
+    P, _ = oracle.page_mtimes(sI, fa, m, m, k)
+    assert np.array_equal(Sc, P)
+    if m == k:
+        d0, p0 = oracle.page_det(fa, m)
+        d1, _ = oracle.page_det(Sc, m)
+        assert np.all(np.abs(d1 - s ** m * d0) <= 16 * 2.0 ** -53 * np.abs(s) ** m * p0)
+    two = 2.0 ** g.integers(-20, 21, 30)
+    assert np.array_equal(oracle.page_scale(two, oracle.page_scale(1 / two, fa, m, k), m, k), fa)
     u = g.standard_normal((30, 3))
     v = g.standard_normal((30, 3))
     M3 = g.standard_normal((30, 3, 3))
