@@ -17,42 +17,47 @@ struct ElemOut {
     void* M3D;
 };
 
-// Compute every requested output of one element in precision C and store it as T.
+// Every output of one element in precision C, rounded to T, in registers: the gradients of
+// the barycentric functions (their negatives are the normals3D columns), the facet measures,
+// the K page (column-major, symmetric) and the two values of the M page.
+template <int DIM, typename T>
+struct ElemVals {
+    static constexpr int NLB = DIM + 1;
+    T det, vol;
+    T grad[DIM * NLB];
+    T facet[NLB];
+    T K[NLB * NLB];
+    T mo, md;
+};
+
 template <int DIM, typename C, typename T>
-__device__ __forceinline__ void elem_outputs(const P1Geom<DIM, C>& g, int64_t e, C ck, C cm, const ElemOut& o) {
+__device__ __forceinline__ void elem_values(const P1Geom<DIM, C>& g, C ck, C cm, const ElemOut& o,
+                                            ElemVals<DIM, T>& v) {
     constexpr int NLB = DIM + 1;
     const C det = g.det;
     const C adet = fabs(det);
     const C vol = adet / static_cast<C>(fact_dim<DIM>());
-    const C inv_det = C(1) / det;
-    if (o.det) static_cast<T*>(o.det)[e] = static_cast<T>(det);
-    if (o.vol) static_cast<T*>(o.vol)[e] = static_cast<T>(vol);
+    v.det = static_cast<T>(det);
+    v.vol = static_cast<T>(vol);
     if (o.grads || o.normals) {
-        T* gp = o.grads ? static_cast<T*>(o.grads) + e * (DIM * NLB) : nullptr;
-        T* np = o.normals ? static_cast<T*>(o.normals) + e * (DIM * NLB) : nullptr;
+        const C inv_det = C(1) / det;
 #pragma unroll
         for (int j = 0; j < NLB; ++j)
 #pragma unroll
-            for (int i = 0; i < DIM; ++i) {
-                const C gv = g.c[j][i] * inv_det;
-                if (gp) gp[i + j * DIM] = static_cast<T>(gv);
-                if (np) np[i + j * DIM] = static_cast<T>(-gv);
-            }
+            for (int i = 0; i < DIM; ++i) v.grad[i + j * DIM] = static_cast<T>(g.c[j][i] * inv_det);
     }
     if (o.facet) {
         // facet opposite node j: dim |T| |grad phi_j| = |c_j| / (dim-1)!
-        T* fp = static_cast<T*>(o.facet) + e * NLB;
 #pragma unroll
         for (int j = 0; j < NLB; ++j) {
             C s = g.c[j][0] * g.c[j][0];
 #pragma unroll
             for (int i = 1; i < DIM; ++i) s = fmaT(g.c[j][i], g.c[j][i], s);
-            fp[j] = static_cast<T>(DIM == 3 ? C(0.5) * sqrt(s) : sqrt(s));
+            v.facet[j] = static_cast<T>(DIM == 3 ? C(0.5) * sqrt(s) : sqrt(s));
         }
     }
     if (o.K3D) {
         const C kf = ck / (static_cast<C>(fact_dim<DIM>()) * adet);
-        T* kp = static_cast<T*>(o.K3D) + e * (NLB * NLB);
 #pragma unroll
         for (int b = 0; b < NLB; ++b)
 #pragma unroll
@@ -60,20 +65,34 @@ __device__ __forceinline__ void elem_outputs(const P1Geom<DIM, C>& g, int64_t e,
                 C s = g.c[a][0] * g.c[b][0];
 #pragma unroll
                 for (int i = 1; i < DIM; ++i) s = fmaT(g.c[a][i], g.c[b][i], s);
-                const T v = static_cast<T>(kf * s);
-                kp[a + b * NLB] = v;
-                kp[b + a * NLB] = v;
+                const T x = static_cast<T>(kf * s);
+                v.K[a + b * NLB] = x;
+                v.K[b + a * NLB] = x;
             }
     }
     if (o.M3D) {
         const C mo = cm * vol / static_cast<C>((DIM + 1) * (DIM + 2));
-        const C md = mo + mo;
-        T* mp = static_cast<T*>(o.M3D) + e * (NLB * NLB);
-#pragma unroll
-        for (int b = 0; b < NLB; ++b)
-#pragma unroll
-            for (int a = 0; a < NLB; ++a) mp[a + b * NLB] = static_cast<T>(a == b ? md : mo);
+        v.mo = static_cast<T>(mo);
+        v.md = static_cast<T>(mo + mo);
     }
+}
+
+// One output array of W values per element, through LDS: every lane puts its element's
+// values at stride W + 1 (odd: the lanes of a wave hit different banks), then the block
+// stores its elements' contiguous run with consecutive lanes on consecutive words.  Elements
+// with a bad node index (okb 0) keep the caller's values.  Called by every thread.
+template <int W, typename T>
+__device__ __forceinline__ void stage_store(T* __restrict__ out, int64_t e0, int nloc, const T (&v)[W],
+                                            T* __restrict__ buf, const uint8_t* __restrict__ okb) {
+    const int t = static_cast<int>(threadIdx.x);
+#pragma unroll
+    for (int i = 0; i < W; ++i) buf[t * (W + 1) + i] = v[i];
+    __syncthreads();
+    for (int k = t; k < nloc * W; k += EBS) {
+        const int el = k / W;
+        if (okb[el]) out[e0 * W + k] = buf[el * (W + 1) + (k - el * W)];
+    }
+    __syncthreads();
 }
 
 template <int DIM, typename T>
@@ -81,8 +100,15 @@ __global__ __launch_bounds__(EBS) void k_elem(int64_t nn, const double* __restri
                                               const int32_t* __restrict__ elems, const T* __restrict__ cK,
                                               const T* __restrict__ cM, ElemOut o, Fallback fb,
                                               uint8_t* __restrict__ flags, int64_t* d_counters) {
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * EBS + threadIdx.x;
+    constexpr int NLB = DIM + 1;
+    constexpr int WMAX = NLB * NLB;
+    __shared__ __align__(16) T buf[EBS * (WMAX + 1)];
+    __shared__ uint8_t okb[EBS];
+    const int64_t e0 = static_cast<int64_t>(blockIdx.x) * EBS;
+    const int64_t e = e0 + threadIdx.x;
+    const int nloc = static_cast<int>(ne - e0 < EBS ? ne - e0 : EBS);
     bool routed = false, sing = false, bad = false;
+    ElemVals<DIM, T> v{};
     if (e < ne) {
         int nd[DIM + 1];
         load_nodes<DIM>(elems, e, nd);
@@ -99,24 +125,47 @@ __global__ __launch_bounds__(EBS) void k_elem(int64_t nn, const double* __restri
                     P1Geom<DIM, double> gd;
                     p1_geom<DIM, double>(ev, gd);
                     sing = (gd.det == 0.0);
-                    elem_outputs<DIM, double, T>(gd, e, ck, cm, o);
+                    elem_values<DIM, double, T>(gd, ck, cm, o, v);
                 } else {
                     sing = (g.det == 0.0f);
-                    elem_outputs<DIM, float, T>(g, e, ck, cm, o);
+                    elem_values<DIM, float, T>(g, ck, cm, o, v);
                 }
             } else {
                 P1Geom<DIM, double> gd;
                 p1_geom<DIM, double>(ev, gd);
                 sing = (gd.det == 0.0);
-                elem_outputs<DIM, double, T>(gd, e, ck, cm, o);
+                elem_values<DIM, double, T>(gd, ck, cm, o, v);
             }
+            // one value per element: consecutive lanes, consecutive words already
+            if (o.det) static_cast<T*>(o.det)[e] = v.det;
+            if (o.vol) static_cast<T*>(o.vol)[e] = v.vol;
         }
         if (flags)
             flags[e] = (sing ? FLAG_SINGULAR : 0) | (routed ? FLAG_ROUTED : 0) | (bad ? FLAG_BADINDEX : 0);
     }
+    okb[threadIdx.x] = (e < ne && !bad) ? 1 : 0;
     count_wave(d_counters, 0, routed);
     count_wave(d_counters, 1, sing);
     count_wave(d_counters, 2, bad);
+    // the multi-value outputs, one array at a time through LDS (the requests are the same for
+    // the whole block)
+    if (o.grads) stage_store<DIM * NLB, T>(static_cast<T*>(o.grads), e0, nloc, v.grad, buf, okb);
+    if (o.normals) {
+        T nv[DIM * NLB];
+#pragma unroll
+        for (int i = 0; i < DIM * NLB; ++i) nv[i] = -v.grad[i];
+        stage_store<DIM * NLB, T>(static_cast<T*>(o.normals), e0, nloc, nv, buf, okb);
+    }
+    if (o.facet) stage_store<NLB, T>(static_cast<T*>(o.facet), e0, nloc, v.facet, buf, okb);
+    if (o.K3D) stage_store<NLB * NLB, T>(static_cast<T*>(o.K3D), e0, nloc, v.K, buf, okb);
+    if (o.M3D) {
+        T mv[NLB * NLB];
+#pragma unroll
+        for (int b = 0; b < NLB; ++b)
+#pragma unroll
+            for (int a = 0; a < NLB; ++a) mv[a + b * NLB] = a == b ? v.md : v.mo;
+        stage_store<NLB * NLB, T>(static_cast<T*>(o.M3D), e0, nloc, mv, buf, okb);
+    }
 }
 
 // boundary facets: 3-D triangles (a,b,c): n = (b-a) x (c-a), measure |n|/2;
