@@ -57,6 +57,8 @@ P2_SOURCES = ["p2.hip", "sparse.hip", "assembly.hip", "p1elem.hpp", "smallmat.hp
 BATCH_SOURCES = ["batch.hip", "smallmat.hpp", "common.hpp"]
 PAGES_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "page_ops_1e7_traffic.json")
 PAGES_SOURCES = ["page_ops.hip", "smallmat.hpp", "common.hpp"]
+ELEM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "elements_cube128_traffic.json")
+ELEM_SOURCES = ["elements.hip", "p1elem.hpp", "smallmat.hpp", "common.hpp", "quadrature.hpp"]
 
 
 def kernel_hash(files=KERNEL_SOURCES) -> str:
@@ -616,16 +618,17 @@ def run_p2(args):
     #  pages (K and M): the 10 node ids 40 B/tet, FP64 vertex coordinates 24 B per vertex node, the
     #    coefficient at 27 points for K and for M (2 x 108 B/tet), two FP32 10 x 10 pages 800 B/tet
     #  scatter: node ids 40 B/tet read, adjacency entries 40 B/tet written, 4 B/node counts
-    #  pattern: adjacency 40 B/tet, node ids once 40 B/tet, position words 80 B/tet, 4 B/nonzero
-    #    (columns), 8 B/node (row lengths, diagonal positions)
-    #  row offsets: 12 B/node, 8 B/nonzero;  sparse(): adjacency + position words 120 B/tet, the
-    #    pages once 800 B/tet, 12 B/node, FP32 K and M 8 B/nonzero
+    #  pattern: adjacency 40 B/tet, node ids once 40 B/tet, compact entries 40 B/tet and position
+    #    words 80 B/tet written, 4 B/nonzero (columns), 8 B/node (row lengths, diagonal positions)
+    #  row offsets: 12 B/node; columns: 8 B/nonzero + 4 B/node;  sparse(): adjacency + position
+    #    words 120 B/tet, the pages once 800 B/tet, 12 B/node, FP32 K and M 8 B/nonzero
     nv = coords.shape[0]
     kernels = {
         "k_p2_elem<3,float> K+M": (float(np.mean(t_km)), 40 * ne + 24 * nv + 2 * 4 * nq * ne + 800 * ne),
         "k_scatter<4> (P2)": (stage_ms["adjacency"] / stage_calls, 80 * ne + 4 * nn2),
-        "k_pattern_p2<10>": (stage_ms["pattern"] / stage_calls, 160 * ne + 4 * nnz + 8 * nn2),
-        "k_row_offsets<1024,4>": (stage_ms["row offsets"] / stage_calls, 12 * nn2 + 8 * nnz),
+        "k_pattern_p2<10>": (stage_ms["pattern"] / stage_calls, 200 * ne + 4 * nnz + 8 * nn2),
+        "k_row_offsets": (stage_ms["row offsets"] / stage_calls, 12 * nn2),
+        "k_row_columns<1024,4>": (stage_ms["columns"] / stage_calls, 8 * nnz + 4 * nn2),
         "k_assemble_pages<10,P2,float>": (float(np.mean(t_sp)), 920 * ne + 12 * nn2 + 8 * nnz),
     }
     dominant = max(kernels, key=lambda k: kernels[k][0])
@@ -956,6 +959,7 @@ def run_elements(args):
     tcs = [torch.from_numpy(coords).cuda() for _ in range(R)]
     tes = [torch.from_numpy(elems).cuda() for _ in range(R)]
     fb = L.fallback(1e-3 * h ** 3, 1e6, True)
+    _calib_copy(args.copy_calib_mib)
     f32 = torch.float32
     det = torch.empty(ne, dtype=f32, device="cuda")
     vol = torch.empty(ne, dtype=f32, device="cuda")
@@ -989,13 +993,13 @@ def run_elements(args):
     alg_m = 16 * ne + 24 * nn + 128 * ne
     ms_step = wall * 1e3 / args.steps
 
-    def roof(name, alg, ms):
+    def roof(name, key, alg, ms):
         gbs = alg / (ms * 1e-3) / 1e9
         return {"kernel": name, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": gbs / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_launch": alg,
-                "launch_us": round(ms * 1e3, 1)}
-    rg = roof("k_elem<3,float> (det, volume, normals3D)", alg_g, float(np.median(tg)))
-    rm = roof("k_elem<3,float> (K3D, M3D)", alg_m, float(np.median(tm)))
+                "frac": gbs / HBM_PEAK_GBS, "traffic": traffic_of(ELEM_TRAFFIC_FILE, ELEM_SOURCES, kernel=key, n=n),
+                "algorithmic_bytes_per_launch": alg, "launch_us": round(ms * 1e3, 1)}
+    rg = roof("k_elem<3,float> (det, volume, normals3D)", "k_elem<3,float>/geometry", alg_g, float(np.median(tg)))
+    rm = roof("k_elem<3,float> (K3D, M3D)", "k_elem<3,float>/pages", alg_m, float(np.median(tm)))
     out = {
         "metric": "P1 tets/s: volumes + normals3D, then element K and M pages",
         "value": ne / (ms_step * 1e-3), "unit": "tets/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
