@@ -881,6 +881,45 @@ __global__ __launch_bounds__(PT) void k_rows_p1(int64_t nn, const int32_t* __res
     __shared__ int32_t cpre[PR + 1];
     __shared__ int32_t guard[PT];                  // never -1: the first probes of empty entries
     const int t = static_cast<int>(threadIdx.x);
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * PR;
+    const int nr = static_cast<int>((r0 + PR < nn) ? PR : nn - r0);
+    const int r = t % PR, jt = t / PR;
+    const int64_t row = r0 + (r < nr ? r : nr - 1);  // in bounds for the loads of rows past the end
+    const int32_t self = static_cast<int32_t>(r0 + r);
+    // Round trip 1, before the tables are set up: the row's length, its adjacency offsets and
+    // the block's, and the thread's first batch of padded entries (every word of a padded row
+    // lies in the scratch; words past the length are dropped below).
+    const int32_t Lfull = adj_len[row];
+    const int64_t ao = aptr[row];                           // the row's first compact entry
+    const int32_t ablk0 = aptr[r0], ablk1 = aptr[r0 + nr];  // the block's compact entries
+    static_assert(PB * PJ <= MAXADJ, "the first batch lies inside the padded rows");
+    int32_t apre[PB];
+#pragma unroll
+    for (int i = 0; i < PB; ++i) apre[i] = adj[row * MAXADJ + jt + i * PJ];
+    // a node of more than MAXADJ elements heads a long row: left to the long-row phase
+    const int L = r < nr && Lfull <= MAXADJ ? Lfull : 0;
+    // round trip 2: the first batch's element node ids, in flight while the tables are cleared
+    int ndpre[PB][4];
+#pragma unroll
+    for (int i = 0; i < PB; ++i) apre[i] = jt + i * PJ < L ? apre[i] : 0;
+    auto gather = [&](const int32_t (&aqv)[PB], int (&ndv)[PB][4]) {
+        if (NLB == 4 && (reinterpret_cast<uintptr_t>(elems) & 15) == 0) {
+#pragma unroll
+            for (int i = 0; i < PB; ++i) {
+                const int4 v = *reinterpret_cast<const int4*>(elems + static_cast<int64_t>(aqv[i] >> 2) * 4);
+                ndv[i][0] = v.x;
+                ndv[i][1] = v.y;
+                ndv[i][2] = v.z;
+                ndv[i][3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < PB; ++i)
+#pragma unroll
+                for (int k = 0; k < NLB; ++k) ndv[i][k] = elems[static_cast<int64_t>(aqv[i] >> 2) * NLB + k];
+        }
+    };
+    if (jt < L) gather(apre, ndpre);  // a thread with an entry (so the mesh has elements)
     for (int h = t; h < PR * PS; h += PT) tab[h] = -1;
     if (t < PR) {
         cnt[t] = 0;
@@ -888,16 +927,6 @@ __global__ __launch_bounds__(PT) void k_rows_p1(int64_t nn, const int32_t* __res
     }
     guard[t] = -2;
     __syncthreads();
-    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * PR;
-    const int nr = static_cast<int>((r0 + PR < nn) ? PR : nn - r0);
-    const int r = t % PR, jt = t / PR;
-    const int64_t row = r0 + (r < nr ? r : nr - 1);  // in bounds for the loads of rows past the end
-    const int32_t self = static_cast<int32_t>(r0 + r);
-    const int32_t Lfull = adj_len[row];
-    // a node of more than MAXADJ elements heads a long row: left to the long-row phase
-    const int L = r < nr && Lfull <= MAXADJ ? Lfull : 0;
-    const int64_t ao = aptr[row];                           // the row's first compact entry
-    const int32_t ablk0 = aptr[r0], ablk1 = aptr[r0 + nr];  // the block's compact entries
     int32_t* rt = tab + r * PS;
     int32_t* rl = lst + r * PL;
     uint8_t* rh = lsth + r * PL;
@@ -939,27 +968,21 @@ __global__ __launch_bounds__(PT) void k_rows_p1(int64_t nn, const int32_t* __res
             const int q = q0 + i;
             const int j = jt + q * PJ;
             okq[i] = q < PQ && j < L;
-            aq[i] = adj[row * MAXADJ + (okq[i] ? j : 0)];
+            if (q0 == 0) aq[i] = apre[i];  // read at the start, already masked
+            else aq[i] = adj[row * MAXADJ + (okq[i] ? j : 0)];
         }
 #pragma unroll
         for (int i = 0; i < PB; ++i) {
             aq[i] = okq[i] ? aq[i] : 0;
             if (q0 + i < PQ) aw[q0 + i] = aq[i];
         }
-        if (NLB == 4 && (reinterpret_cast<uintptr_t>(elems) & 15) == 0) {
-#pragma unroll
-            for (int i = 0; i < PB; ++i) {
-                const int4 v = *reinterpret_cast<const int4*>(elems + static_cast<int64_t>(aq[i] >> 2) * 4);
-                nd[i][0] = v.x;
-                nd[i][1] = v.y;
-                nd[i][2] = v.z;
-                nd[i][3] = v.w;
-            }
-        } else {
+        if (q0 == 0) {
 #pragma unroll
             for (int i = 0; i < PB; ++i)
 #pragma unroll
-                for (int k = 0; k < NLB; ++k) nd[i][k] = elems[static_cast<int64_t>(aq[i] >> 2) * NLB + k];
+                for (int k = 0; k < 4; ++k) nd[i][k] = ndpre[i][k];
+        } else {
+            gather(aq, nd);
         }
         // the first probe of every insert of the batch, all in flight together; an empty entry
         // probes the thread's own guard word (never -1, so nothing is stored)
