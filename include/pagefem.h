@@ -200,10 +200,12 @@ pf_status pf_csr_create(pf_csr** out);
  * mesh.  Its device memory comes from a stream-ordered pool of the library (enqueued on
  * `stream`); the build's own scratch (padded adjacency rows and row-pattern columns, about
  * 520 bytes per node) is released when the build ends.  This call synchronises `stream`
- * once, to read nnz and the error word back (the exact size of col_idx), and returns with
- * the build's last step (the columns) enqueued on `stream`: the library's later calls on
- * the handle order their work after it on any stream (a device-side wait, no host wait),
- * and pf_csr_info, which hands out device pointers, waits for it on the host.
+ * once, to read nnz and the error word back (the exact size of col_idx).  A rebuild whose
+ * nonzeros fit the col_idx of an earlier build in the handle is then complete; otherwise the
+ * call returns with the last step (the columns into a col_idx of exactly nnz words) enqueued
+ * on `stream`: the library's later calls on the handle order their work after it on any
+ * stream (a device-side wait, no host wait), and pf_csr_info, which hands out device
+ * pointers, waits for it on the host.
  * Rows whose node lies in more than 64 elements, or that hold more than 64 nonzeros, are
  * long rows: the build lists them (one more synchronisation of `stream`, only then) and
  * builds them with one workgroup per row, and pf_assemble, pf_assemble_quad,

@@ -53,6 +53,7 @@ struct pf_csr {
     uint64_t* look = nullptr;    // published counts / prefixes of the row-offset tiles
     int32_t* lrows_s = nullptr;  // the long rows found by the row-block pass
     unsigned char* scratch = nullptr;
+    bool scratch_owned = false;  // a block of its own, not the device's scratch arena
     int32_t* lcol = nullptr;     // each long row's columns, LCAP words apiece (long-row phase)
     int64_t cap_lcol = 0;
     // long rows (more than MAXADJ elements or MAXROW nonzeros): their list (resident)
@@ -92,6 +93,7 @@ struct pf_csr {
     hipStream_t q_stream = nullptr;
     const int32_t* q_elems = nullptr;
     bool q_long = false;  // the long-row phase has run for this build
+    bool q_cols = false;  // phase 1 moved the columns into the col_idx kept from a former build
     hipEvent_t ev[PF_CSR_STAGES + 2] = {};  // stage k: ev[STAGE_EV[k][0]] .. ev[STAGE_EV[k][1]]
     double stage_ms[PF_CSR_STAGES] = {};
     int64_t stage_calls = 0;
@@ -240,6 +242,15 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
     static_assert(AG_HASH <= 32768, "table slots fit 16 bits");
     __shared__ int32_t nuniq;
     __shared__ int32_t guard[AG_BS];  // never -1: the first probes of empty entries
+    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * AG_TILE;
+    int slot[AG_ITEMS];
+    int32_t node[AG_ITEMS], cur[AG_ITEMS];
+    bool bad = false;
+#pragma unroll
+    for (int q = 0; q < AG_ITEMS; ++q) {  // all loads in flight together, while the table is cleared
+        const int64_t t = t0 + q * AG_BS + threadIdx.x;
+        node[q] = elems[t < m ? t : m - 1];
+    }
     for (int h = threadIdx.x; h < AG_HASH; h += AG_BS) {
         keys[h] = -1;
         vals[h] = 0;
@@ -247,15 +258,6 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
     guard[threadIdx.x] = -2;
     if (threadIdx.x == 0) nuniq = 0;
     __syncthreads();
-    const int64_t t0 = static_cast<int64_t>(blockIdx.x) * AG_TILE;
-    int slot[AG_ITEMS];
-    int32_t node[AG_ITEMS], cur[AG_ITEMS];
-    bool bad = false;
-#pragma unroll
-    for (int q = 0; q < AG_ITEMS; ++q) {  // all loads in flight together
-        const int64_t t = t0 + q * AG_BS + threadIdx.x;
-        node[q] = elems[t < m ? t : m - 1];
-    }
     // first probes of all the lane's entries together; an entry outside the tile or with a
     // bad node id probes the lane's guard word (never -1, so nothing is stored)
 #pragma unroll
@@ -755,9 +757,12 @@ __global__ __launch_bounds__(SBS) void k_row_offsets(int64_t nn, const int32_t* 
 template <int RW, int NRD>
 __global__ __launch_bounds__(SBS) void k_row_columns(int64_t nn, const int32_t* __restrict__ row_ptr,
                                                      const int32_t* __restrict__ colblk,
-                                                     int32_t* __restrict__ col_idx) {
+                                                     int32_t* __restrict__ col_idx, int64_t cap) {
     __shared__ int32_t boff[SBS];  // offset of each block's first column in col_idx
     __shared__ int32_t bcnt[SBS];  // its number of columns
+    // enqueued ahead of the host's knowledge of nnz (col_idx kept from an earlier build):
+    // nothing is written unless every column fits
+    if (row_ptr[nn] > cap) return;
     const int64_t blk0 = static_cast<int64_t>(blockIdx.x) * SBS;  // the tile's first row-pattern block
     const int64_t nblk = (nn + RR - 1) / RR;
     const int nb = static_cast<int>(nblk - blk0 < SBS ? nblk - blk0 : SBS);
@@ -2438,6 +2443,86 @@ void recycle_pinned(int64_t* p) {
     g_pin_free.push_back(p);
 }
 
+// The build scratch of one device: a block that one build at a time borrows and hands back
+// by recording an event on its stream (no allocation or release call, each of which costs the
+// host tens of microseconds); the next borrower's stream waits for that event on the device.
+// A build that finds the block in use allocates scratch of its own from the pool.
+struct ScratchArena {
+    unsigned char* p = nullptr;
+    int64_t cap = 0;
+    bool busy = false;
+    hipEvent_t done = nullptr;  // recorded when the last borrower's build stopped using it
+    bool recorded = false;
+};
+ScratchArena g_arena[MAX_POOL_DEVICES];
+
+// scratch of `bytes` for a build on stream s: the arena's block (*owned = false) or a block
+// of the pool's (*owned = true)
+pf_status scratch_borrow(int64_t bytes, hipStream_t s, unsigned char** out, bool* owned) {
+    int dev = 0;
+    PF_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_POOL_DEVICES) return fail(PF_EINVAL, "device index beyond the pool table");
+    hipMemPool_t pool = nullptr;
+    if (pf_status st = pool_of_current(&pool)) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        ScratchArena& a = g_arena[dev];
+        if (!a.busy) {
+            a.busy = true;
+            if (a.recorded) PF_HIP_TRY(hipStreamWaitEvent(s, a.done, 0));  // the last borrower is done
+            if (a.cap < bytes) {
+                if (a.p) PF_HIP_TRY(hipFreeAsync(a.p, s));
+                a.p = nullptr;
+                a.cap = 0;
+                const hipError_t e = hipMallocFromPoolAsync(reinterpret_cast<void**>(&a.p), bytes, pool, s);
+                if (e != hipSuccess) {
+                    a.busy = false;
+                    return fail(PF_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+                }
+                a.cap = bytes;
+            }
+            *out = a.p;
+            *owned = false;
+            return PF_OK;
+        }
+    }
+    const hipError_t e = hipMallocFromPoolAsync(reinterpret_cast<void**>(out), bytes, pool, s);
+    if (e != hipSuccess) return fail(PF_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+    *owned = true;
+    return PF_OK;
+}
+
+// hand the scratch back: the arena's block once the work enqueued on s so far is done
+void scratch_return(unsigned char* p, bool owned, hipStream_t s) {
+    if (!p) return;
+    if (owned) {
+        (void)hipFreeAsync(p, s);
+        return;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_POOL_DEVICES) return;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    ScratchArena& a = g_arena[dev];
+    if (!a.done && hipEventCreateWithFlags(&a.done, hipEventDisableTiming) != hipSuccess) a.done = nullptr;
+    a.recorded = a.done && hipEventRecord(a.done, s) == hipSuccess;
+    if (!a.recorded) (void)hipStreamSynchronize(s);  // no event: wait here instead
+    a.busy = false;
+}
+
+// release the arena's block of the current device (when no build holds it)
+void scratch_trim() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_POOL_DEVICES) return;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    ScratchArena& a = g_arena[dev];
+    if (a.busy || !a.p) return;
+    if (a.recorded) (void)hipEventSynchronize(a.done);
+    (void)hipFreeAsync(a.p, nullptr);
+    (void)hipStreamSynchronize(nullptr);
+    a.p = nullptr;
+    a.cap = 0;
+}
+
 unsigned flat_grid(int64_t n) {
     int64_t g = ceil_div(n, SBS);
     if (g > 65536) g = 65536;
@@ -2726,6 +2811,7 @@ pf_status csr_workspace(pf_csr* c, int64_t words, double** out, hipStream_t s) {
 }
 
 void csr_pool_trim() {
+    scratch_trim();
     hipMemPool_t pool = nullptr;
     if (pool_of_current(&pool) == PF_OK) (void)hipMemPoolTrimTo(pool, 0);
 }
@@ -2735,7 +2821,9 @@ void csr_release(pf_csr* c, hipStream_t s) {
     if ((c->stage != 0 || c->cols_pending) && c->ready) (void)hipEventSynchronize(c->ready);  // a build in flight
     for (hipEvent_t& e : c->ev)
         if (e) (void)hipEventDestroy(e);
-    drop(c->scratch, c->cap_scratch, s);
+    scratch_return(c->scratch, c->scratch_owned, s);
+    c->scratch = nullptr;
+    c->cap_scratch = 0;
     drop(c->res, c->cap_res, s);
     drop(c->lrows, c->cap_lrows, s);
     drop(c->col_idx, c->cap_nnz, s);
@@ -2824,6 +2912,8 @@ pf_status pf_csr_stage_times(pf_csr* c, double* ms, int64_t* calls) {
 }
 
 namespace {
+pf_status enqueue_columns(pf_csr* c, hipStream_t s, const char* who);
+
 // The structure of a P1 (nlb = dim + 1) or P2 (nlb = 6, 10) mesh, in two phases.  Phase 1
 // (symbolic_enqueue): the adjacency scattered into padded rows, its offsets (a scan of the
 // lengths), the row patterns (every 8-row group's sorted columns, the compact adjacency with
@@ -2831,7 +2921,9 @@ namespace {
 // the launch statistics; it ends with the status words' copy to pinned host memory and the
 // ready event.  Phase 2 (symbolic_columns, once the host holds nnz): col_idx allocated for
 // exactly nnz words, the columns moved into it, the build's scratch released; it ends with
-// the ready event again.  Every step is enqueued on one stream; nothing waits in between.
+// the ready event again.  A rebuild in a handle whose col_idx already holds the new nnz moves
+// the columns in phase 1 and needs no phase 2.  Every step is enqueued on one stream; nothing
+// waits in between.
 pf_status symbolic_enqueue(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const int32_t* elems, void* stream,
                            const char* who) {
     const bool p2 = nlb > dim + 1;
@@ -2877,7 +2969,13 @@ pf_status symbolic_enqueue(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, 
         const int64_t b_blk = part(4 * std::max<int64_t>(regions * RR * maxrow, 1));
         const int64_t b_look = part(8 * ((1 + TSTAT / 2) * std::max<int64_t>(tiles, 1) + 1));
         const int64_t b_lst = part(4 * nn);  // the long rows' list
-        if ((st = grow(c->scratch, c->cap_scratch, b_len + b_pad + b_cnt + b_blk + b_look + b_lst, s))) return st;
+        if (c->scratch) {  // an earlier build's, still held (an error ended it early)
+            scratch_return(c->scratch, c->scratch_owned, s);
+            c->scratch = nullptr;
+        }
+        const int64_t bytes = b_len + b_pad + b_cnt + b_blk + b_look + b_lst;
+        if ((st = scratch_borrow(bytes, s, &c->scratch, &c->scratch_owned))) return st;
+        c->cap_scratch = bytes;
         unsigned char* q = c->scratch;
         c->adj_len = reinterpret_cast<int32_t*>(q);
         c->adj_pad = reinterpret_cast<int32_t*>(q + b_len);
@@ -2932,6 +3030,14 @@ pf_status symbolic_enqueue(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, 
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, c->row_ptr, int64_t(1), 0);
     }
     if ((st = mark(c, 3, s))) return st;
+    // a col_idx kept from an earlier build of the handle: the columns go in now (the kernel
+    // writes nothing if nnz exceeds it), so that a rebuild of a mesh of no more nonzeros and no
+    // long rows ends with this phase's readback
+    c->q_cols = c->col_idx != nullptr && c->cap_nnz > 0 && nn > 0;
+    c->q_nn = nn;  // (the helper reads the build's shape)
+    c->q_dim = dim;
+    c->q_nlb = nlb;
+    if (c->q_cols && (st = enqueue_columns(c, s, who))) return st;  // no long rows listed yet: nlong is 0
     if ((st = launch_check(who))) return st;
     c->pending = c->timing;
     // pinned: a direct copy, no staging through pageable memory
@@ -2950,7 +3056,9 @@ pf_status symbolic_enqueue(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, 
 
 // the build's scratch, released in the order of its stream
 void drop_scratch(pf_csr* c, hipStream_t s) {
-    drop(c->scratch, c->cap_scratch, s);
+    scratch_return(c->scratch, c->scratch_owned, s);
+    c->scratch = nullptr;
+    c->cap_scratch = 0;
     drop(c->lcol, c->cap_lcol, s);
     c->adj_len = c->adj_pad = c->cnt = c->colblk = c->lrows_s = nullptr;
     c->look = nullptr;
@@ -2993,6 +3101,28 @@ pf_status symbolic_long(pf_csr* c, const char* who) {
     return PF_OK;
 }
 
+// the columns of every row into col_idx (sized for at least nnz), the long rows' groups again
+pf_status enqueue_columns(pf_csr* c, hipStream_t s, const char* who) {
+    const int64_t nn = c->q_nn;
+    const bool p2 = c->q_nlb > c->q_dim + 1;
+    pf_status st;
+    if ((st = mark(c, 4, s))) return st;
+    if (nn > 0) {
+        const unsigned tiles = static_cast<unsigned>(ceil_div(nn, SCAN_TILE));
+        if (p2)
+            hipLaunchKernelGGL((k_row_columns<RR * MAXROW2, 4>), dim3(tiles), dim3(SBS), 0, s, nn, c->row_ptr,
+                               c->colblk, c->col_idx, c->cap_nnz);
+        else
+            hipLaunchKernelGGL((k_row_columns<RR * MAXROW, 2>), dim3(tiles), dim3(SBS), 0, s, nn, c->row_ptr,
+                               c->colblk, c->col_idx, c->cap_nnz);
+        if (c->nlong > 0)
+            hipLaunchKernelGGL(k_long_columns, dim3(static_cast<unsigned>(c->nlong)), dim3(LT), 0, s, c->lrows, nn,
+                               c->row_ptr, c->aptr, c->colblk, c->lcol, c->col_idx);
+    }
+    if ((st = mark(c, 5, s))) return st;
+    return launch_check(who);
+}
+
 // After phase 1 (or 1b): its status words have reached the host (the ready event has
 // completed).  Check them; if phase 1 listed long rows, enqueue phase 1b; otherwise fix the
 // structure's sizes and launch statistics and enqueue phase 2 (the columns).
@@ -3015,30 +3145,22 @@ pf_status symbolic_columns(pf_csr* c, const char* who) {
         if ((st = symbolic_long(c, who)) == PF_OK) return PF_OK;
     }
     const int64_t nnz = info[2];
-    if (st == PF_OK) st = grow(c->col_idx, c->cap_nnz, std::max<int64_t>(nnz, 1), s);
+    // phase 1 already moved the columns (they fitted, and no long rows): the build is complete
+    const bool done = st == PF_OK && c->q_cols && !c->q_long && info[INFO_NLONG] == 0 && nnz <= c->cap_nnz;
+    if (st == PF_OK && !done) st = grow(c->col_idx, c->cap_nnz, std::max<int64_t>(nnz, 1), s);
     if (st != PF_OK) {
         c->pending = false;  // the stage events of this call are incomplete
         drop_scratch(c, s);
         return st;
     }
-    if ((st = mark(c, 4, s))) return st;
-    if (nn > 0) {
-        const unsigned tiles = static_cast<unsigned>(ceil_div(nn, SCAN_TILE));
-        if (p2)
-            hipLaunchKernelGGL((k_row_columns<RR * MAXROW2, 4>), dim3(tiles), dim3(SBS), 0, s, nn, c->row_ptr,
-                               c->colblk, c->col_idx);
-        else
-            hipLaunchKernelGGL((k_row_columns<RR * MAXROW, 2>), dim3(tiles), dim3(SBS), 0, s, nn, c->row_ptr,
-                               c->colblk, c->col_idx);
-        if (c->nlong > 0)
-            hipLaunchKernelGGL(k_long_columns, dim3(static_cast<unsigned>(c->nlong)), dim3(LT), 0, s, c->lrows, nn,
-                               c->row_ptr, c->aptr, c->colblk, c->lcol, c->col_idx);
+    if (!done) {  // phase 2: the columns into col_idx, then the ready event
+        if ((st = enqueue_columns(c, s, who))) return st;
+        drop_scratch(c, s);
+        PF_HIP_TRY(hipEventRecord(c->ready, s));
+        c->stage = 2;
+    } else {
+        drop_scratch(c, s);
     }
-    if ((st = mark(c, 5, s))) return st;
-    if ((st = launch_check(who))) return st;
-    drop_scratch(c, s);
-    PF_HIP_TRY(hipEventRecord(c->ready, s));
-    c->stage = 2;
     c->dim = dim;
     c->nlb = nlb;
     c->p2 = p2;
@@ -3065,10 +3187,10 @@ pf_status symbolic(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, const in
         if ((st = symbolic_columns(c, who))) return st;
     }
     // the columns complete in the order of the stream: no wait here (csr_order orders the
-    // work of other streams after them)
+    // work of other streams after them); stage 0: phase 1 already placed them
+    c->cols_pending = c->stage == 2;
     c->stage = 0;
     c->built = true;
-    c->cols_pending = true;
     return PF_OK;
 }
 }  // namespace
@@ -3098,6 +3220,11 @@ int csr_symbolic_poll(pf_csr* c, pf_status* st) {
         if (s1 != PF_OK) {
             c->stage = 0;
             *st = s1;
+            return 1;
+        }
+        if (c->stage == 0) {  // complete already (columns placed in phase 1)
+            c->built = true;
+            *st = PF_OK;
             return 1;
         }
         return 0;
