@@ -340,7 +340,6 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
 constexpr int RR = PF_PATTERN_RR;  // rows per block in the row-pattern kernels
 constexpr int RT = PF_PATTERN_RT;  // threads per block
 constexpr int RSUB = MAXROW;     // slots of one row's table: every admissible row fits
-constexpr int RBATCH = 2;        // entries gathered together per thread (independent loads)
 static_assert(RR <= 64, "the row-count prefix runs in one wave");
 static_assert(RT >= RR && RT >= 64, "one thread per row and a full first wave");
 
@@ -384,36 +383,33 @@ __device__ __forceinline__ int tsub_hash(int32_t v) {
 }
 
 struct P2Pattern {                  // LDS of a P2 pattern block
-    int32_t tab[TAB2];              // node ids, -1 empty; then the sorted columns
-    int32_t guard[RT2];             // never -1: the first probes of empty items
-    int32_t seg[TAB2];              // each row's nodes (table order), rows TS words apart
-    uint8_t seg_h[TAB2];            // table slot of each list item
+    alignas(16) int32_t tab[TAB2];  // node ids, -1 empty; then each row's nodes, compacted
+    uint8_t seg_h[TAB2];            // table slot of each compacted node
     uint8_t slot_rank[TAB2];        // rank (column position) of each used table slot
-    uint64_t eslot[RR * MAXADJ];    // per item: table slot of other node k << 7k
     int32_t cnt[RR2];
     int32_t cpre[RR2 + 1];
     int32_t maxl;
 };
 
-// One pass over NRW rows (nrw of them in the matrix) starting at row rq, with TS-slot tables.
-// alen: the rows' numbers of elements, abase: their first compact adjacency entries (LDS); dst:
-// the colblk region of the pass's first 8 rows (rows 8 .. 15 of a 16-row pass go to the next
-// region); apre: this thread's entries of the first batch (item r + NRW j), read at block
-// start, used when `pre`.  Every entry is copied to its compact place, with its pk2 word.
+// One pass over NRW rows (nrw of them in the matrix) starting at row rq, with TS-slot tables,
+// one adjacency entry per thread at a time.  alen: the rows' numbers of elements, abase: their
+// first compact adjacency entries (LDS); dst: the colblk region of the pass's first 8 rows
+// (rows 8 .. 15 of a 16-row pass go to the next region); apre: this thread's entry of the
+// first batch (item r + NRW j, j = thread / NRW), read at block start, used when `pre`.  Every
+// entry is copied to its compact place, with its pk2 word.
 template <int NLB, int NRW, int TS>
 __device__ __forceinline__ void p2_pattern_pass(P2Pattern& S, const int32_t* alen, const int32_t* abase, int64_t rq,
                                                 int nrw, const int32_t* __restrict__ elems,
                                                 const int32_t* __restrict__ adj, int32_t* __restrict__ rowlen,
                                                 int32_t* __restrict__ dst, int32_t* __restrict__ adjc,
                                                 uint64_t* __restrict__ pk2, int32_t* __restrict__ dpos,
-                                                const int32_t (&apre)[RBATCH], bool pre, bool& bad) {
+                                                int32_t apre, bool pre, bool& bad) {
     constexpr int NO = NLB - 1;
     static_assert(NO * 7 <= 64, "the positions of the other nodes fit one 64-bit word");
     static_assert(NRW * TS == TAB2, "a pass fills the block's tables");
     static_assert((NRW & (NRW - 1)) == 0, "NRW is a power of two");
     const int64_t e0 = rq * MAXADJ;
     for (int h = threadIdx.x; h < TAB2; h += RT2) S.tab[h] = -1;
-    S.guard[threadIdx.x] = -2;
     if (threadIdx.x == 0) S.maxl = 0;
     __syncthreads();
     if (threadIdx.x < NRW) {
@@ -428,81 +424,72 @@ __device__ __forceinline__ void p2_pattern_pass(P2Pattern& S, const int32_t* ale
     }
     __syncthreads();
     const int items = NRW * S.maxl;
+    // items per thread: a one-pass row has at most 63 / NO elements, a two-pass row MAXADJ
+    constexpr int ITMAX = (NRW * (NRW == RR2 ? 63 / NO : MAXADJ) + RT2 - 1) / RT2;
     // element node ids in 8-byte loads (NLB even: an element's ids start 8-byte aligned)
     static_assert(NLB % 2 == 0, "P2 elements have 6 or 10 nodes");
     const bool al8 = (reinterpret_cast<uintptr_t>(elems) & 7) == 0;
-    for (int base = threadIdx.x; base < items; base += RT2 * RBATCH) {
-        const bool first = pre && base == static_cast<int>(threadIdx.x);
-        int rq_[RBATCH], aq[RBATCH];
-        int64_t eq[RBATCH];
+    uint64_t eslot[ITMAX];  // per item of this thread: table slot of other node k << 7k
 #pragma unroll
-        for (int b = 0; b < RBATCH; ++b) {
-            const int idx = base + b * RT2;
-            const int r = idx % NRW, j = idx / NRW;
-            const bool ok = idx < items && j < alen[r] && r < nrw;
-            const int32_t w = first ? apre[b] : adj[e0 + (ok ? r * MAXADJ + j : 0)];
-            if (ok) adjc[abase[r] + j] = w;
-            rq_[b] = ok ? r : -1;
-            aq[b] = ok ? (w & 15) : 0;
-            eq[b] = ok ? (static_cast<uint32_t>(w) >> 4) : 0;
-        }
-        int32_t nd[RBATCH][NLB];
+    for (int it = 0; it < ITMAX; ++it) {
+        const int idx = static_cast<int>(threadIdx.x) + it * RT2;
+        eslot[it] = 0;
+        if (idx >= items) break;
+        const int r = idx % NRW, j = idx / NRW;
+        const bool ok = j < alen[r] && r < nrw;
+        const int32_t w = pre && it == 0 ? apre : adj[e0 + (ok ? r * MAXADJ + j : 0)];
+        if (!ok) continue;
+        adjc[abase[r] + j] = w;
+        const int a = w & 15;
+        const int64_t e = static_cast<uint32_t>(w) >> 4;
+        int32_t nd[NLB];
+        if (al8) {
+            const int2* pe = reinterpret_cast<const int2*>(elems + e * NLB);
 #pragma unroll
-        for (int b = 0; b < RBATCH; ++b) {
-            if (al8) {
-                const int2* pe = reinterpret_cast<const int2*>(elems + eq[b] * NLB);
-#pragma unroll
-                for (int k = 0; k < NLB / 2; ++k) {
-                    const int2 v = pe[k];
-                    nd[b][2 * k] = v.x;
-                    nd[b][2 * k + 1] = v.y;
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < NLB; ++k) nd[b][k] = elems[eq[b] * NLB + k];
+            for (int k = 0; k < NLB / 2; ++k) {
+                const int2 v = pe[k];
+                nd[2 * k] = v.x;
+                nd[2 * k + 1] = v.y;
             }
-        }
-        // first probes of the elements' other nodes together; an empty item probes the guard
-        int32_t ov[RBATCH][NO], cq[RBATCH][NO];
+        } else {
 #pragma unroll
-        for (int b = 0; b < RBATCH; ++b) {
+            for (int k = 0; k < NLB; ++k) nd[k] = elems[e * NLB + k];
+        }
+        // the other nodes' first probes together, then every probe that met another node
+        // retried together (one LDS round trip per probe depth, not per node)
+        int32_t* rt = S.tab + r * TS;
+        int32_t ov[NO];
+        int hq[NO];
+        uint32_t pend = 0;
+#pragma unroll
+        for (int k = 0; k < NO; ++k) {
+            ov[k] = k < a ? nd[k] : nd[k + 1];
+            hq[k] = tsub_hash<TS>(ov[k]);
+            const int32_t cur = atomicCAS(rt + hq[k], -1, ov[k]);
+            pend |= static_cast<uint32_t>(cur != -1 && cur != ov[k]) << k;
+        }
+        for (int probe = 1; pend != 0u; ++probe) {  // linear probing
+            if (probe == TS) {                      // a full table: the row is too long
+                bad = true;
+                break;
+            }
 #pragma unroll
             for (int k = 0; k < NO; ++k) {
-                ov[b][k] = k < aq[b] ? nd[b][k] : nd[b][k + 1];
-                cq[b][k] = atomicCAS(rq_[b] >= 0 ? S.tab + rq_[b] * TS + tsub_hash<TS>(ov[b][k]) : S.guard + threadIdx.x,
-                                     -1, ov[b][k]);
+                if ((pend >> k) & 1u) {
+                    hq[k] = (hq[k] + 1) & (TS - 1);
+                    const int32_t cur = atomicCAS(rt + hq[k], -1, ov[k]);
+                    if (cur == -1 || cur == ov[k]) pend &= ~(1u << k);
+                }
             }
         }
+        uint64_t word = 0;
 #pragma unroll
-        for (int b = 0; b < RBATCH; ++b) {
-            if (rq_[b] < 0) continue;
-            int32_t* rt = S.tab + rq_[b] * TS;
-            uint64_t word = 0;
-#pragma unroll
-            for (int k = 0; k < NO; ++k) {
-                const int32_t v = ov[b][k];
-                int h = tsub_hash<TS>(v);
-                int32_t cur = cq[b][k];
-#pragma unroll 1
-                for (int probe = 1; cur != -1 && cur != v; ++probe) {  // taken: linear probing
-                    if (probe == TS) {
-                        h = -1;
-                        break;
-                    }
-                    h = (h + 1) & (TS - 1);
-                    cur = atomicCAS(rt + h, -1, v);
-                }
-                if (h < 0) {
-                    bad = true;
-                    continue;
-                }
-                word |= static_cast<uint64_t>(h) << (7 * k);
-            }
-            S.eslot[base + b * RT2] = word;
-        }
+        for (int k = 0; k < NO; ++k) word |= static_cast<uint64_t>(hq[k]) << (7 * k);
+        eslot[it] = word;
     }
     __syncthreads();
-    // each row's list: its used table slots (one wave per row, lane = slot of each 64)
+    // each row's list: its used table slots, compacted in place (one wave per row, lane = slot
+    // of each 64; a wave reads its 64 slots before it writes, and writes only below them)
     for (int r = threadIdx.x >> 6; r < NRW; r += RT2 / 64) {
         const int lane = threadIdx.x & 63;
         int n = 0;
@@ -513,7 +500,7 @@ __device__ __forceinline__ void p2_pattern_pass(P2Pattern& S, const int32_t* ale
             const int below = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
                                                         __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0u));
             if (v != -1) {
-                S.seg[r * TS + n + below] = v;
+                S.tab[r * TS + n + below] = v;
                 S.seg_h[r * TS + n + below] = static_cast<uint8_t>(64 * half + lane);
             }
             n += __popcll(m);
@@ -535,14 +522,17 @@ __device__ __forceinline__ void p2_pattern_pass(P2Pattern& S, const int32_t* ale
     }
     if (threadIdx.x < nrw) rowlen[rq + threadIdx.x] = S.cnt[threadIdx.x];
     __syncthreads();
-    int32_t* srt = S.tab;  // the pass's columns in CSR order (the tables are no longer read)
+    // each node's rank in its row = its column position; the sorted columns go straight to
+    // their region (a wave's stores cover a contiguous run of it): rows 0 .. 7 of the pass to
+    // the first region, rows 8 .. 15 (a 16-row pass) to the next
+    const int split = NRW > RR && nrw > RR ? S.cpre[RR] : S.cpre[nrw];
     for (int q = threadIdx.x; q < S.cpre[nrw]; q += RT2) {
         const int r = upper_pos(S.cpre, nrw, q);
         const int p = q - S.cpre[r];
         const int n = S.cnt[r];
-        const int32_t v = S.seg[r * TS + p];
+        const int32_t* sr = S.tab + r * TS;
+        const int32_t v = sr[p];
         int rank = 0;
-        const int32_t* sr = S.seg + r * TS;
         int j = 0;
         for (; j + 4 <= n; j += 4) {
             const int32_t a0 = sr[j], a1 = sr[j + 1], a2 = sr[j + 2], a3 = sr[j + 3];
@@ -551,17 +541,17 @@ __device__ __forceinline__ void p2_pattern_pass(P2Pattern& S, const int32_t* ale
         for (; j < n; ++j) rank += sr[j] < v;
         S.slot_rank[r * TS + S.seg_h[r * TS + p]] = static_cast<uint8_t>(rank);
         if (v == rq + r) dpos[rq + r] = rank;
-        srt[S.cpre[r] + rank] = v;
+        const int pos = S.cpre[r] + rank;
+        dst[pos < split ? pos : RR * MAXROW2 + (pos - split)] = v;
     }
     __syncthreads();
-    // rows 0 .. 7 of the pass to its first region, rows 8 .. 15 (a 16-row pass) to the next
-    const int split = NRW > RR && nrw > RR ? S.cpre[RR] : S.cpre[nrw];
-    for (int q = threadIdx.x; q < S.cpre[nrw]; q += RT2)
-        dst[q < split ? q : RR * MAXROW2 + (q - split)] = srt[q];
-    for (int idx = threadIdx.x; idx < items; idx += RT2) {
+#pragma unroll
+    for (int it = 0; it < ITMAX; ++it) {
+        const int idx = static_cast<int>(threadIdx.x) + it * RT2;
+        if (idx >= items) break;
         const int r = idx % NRW, j = idx / NRW;
         if (r >= nrw || j >= alen[r]) continue;
-        const uint64_t w = S.eslot[idx];
+        const uint64_t w = eslot[it];
         uint64_t word = 0;
 #pragma unroll
         for (int k = 0; k < NO; ++k)
@@ -588,13 +578,11 @@ __global__ __launch_bounds__(RT2) void k_pattern_p2(int64_t nn, const int32_t* _
     // the first batch of entries of the one-pass layout (item r + RR2 j) is read together with
     // the row lengths (padded rows: every entry below MAXADJ of a row of the matrix is in
     // bounds; entries past a row's length are dropped once the lengths are known)
-    static_assert(RT2 * RBATCH / RR2 <= MAXADJ, "the first batch lies inside the padded rows");
-    int32_t apre[RBATCH];
-#pragma unroll
-    for (int b = 0; b < RBATCH; ++b) {
-        const int idx = static_cast<int>(threadIdx.x) + b * RT2;
-        const int r = idx % RR2, j = idx / RR2;
-        apre[b] = adj[(r0 + (r < nr ? r : 0)) * MAXADJ + j];
+    static_assert(RT2 / RR2 <= MAXADJ, "the first batch lies inside the padded rows");
+    int32_t apre;
+    {
+        const int r = static_cast<int>(threadIdx.x) % RR2, j = static_cast<int>(threadIdx.x) / RR2;
+        apre = adj[(r0 + (r < nr ? r : 0)) * MAXADJ + j];
     }
     const int32_t lv = adj_len[r0 + (static_cast<int>(threadIdx.x) < nr ? threadIdx.x : 0)];
     const int32_t av = aptr[r0 + (static_cast<int>(threadIdx.x) < nr ? threadIdx.x : 0)];
@@ -1346,11 +1334,12 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
                                               int64_t* __restrict__ info) {
     constexpr int NV = NLB - 1;  // nodes of a face = other nodes of an element
     __shared__ int32_t key[FR * FSUB];  // face key | element count << FCNT
-    // element << 32 | slot word of its entry | opposite local node << 26: the smallest and the
-    // largest element of each face, with what it takes to name the face's nodes (pass 1 only:
-    // the counting pass keeps its LDS small, for more resident blocks)
-    constexpr int WS = PASS == 1 ? FR * FSUB : 1;
-    __shared__ unsigned long long wmin[WS], wmax[WS];
+    // the two elements of each face, in arrival order, as the position of their entry in the
+    // row's adjacency << 2 | the local node opposite the face (pass 1 only; 2 KB per block
+    // instead of two 64-bit words per slot, for twice the resident blocks): the writing phase
+    // reads the two entries back and takes the smaller element as the face's first
+    constexpr int WS = PASS == 1 ? FR * FSUB * 2 : 1;
+    __shared__ uint8_t wj[WS];
     __shared__ int16_t list[FR * FSUB];  // used slots of each row
     __shared__ int32_t nlist[FR], dslot[FR], alen[FR], abase[FR], lpre[FR + 1];
     __shared__ int32_t maxl;
@@ -1379,13 +1368,7 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
             rowb[threadIdx.x] = bv;
         }
     }
-    for (int h = threadIdx.x; h < FR * FSUB; h += FT) {
-        key[h] = -1;
-        if constexpr (PASS == 1) {
-            wmin[h] = ~0ull;
-            wmax[h] = 0ull;
-        }
-    }
+    for (int h = threadIdx.x; h < FR * FSUB; h += FT) key[h] = -1;
     if (threadIdx.x == 0) maxl = 0;
     __syncthreads();
     if (threadIdx.x < FR) atomicMax(&maxl, alen[threadIdx.x]);
@@ -1405,8 +1388,7 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
     __syncthreads();
     bool full = false;
     // entries dealt r + FR j: the faces each one owns go into its row's table
-    auto entry = [&](int r, int32_t w, uint32_t p) {
-        const unsigned long long e = static_cast<uint32_t>(w) >> 2;
+    auto entry = [&](int r, int j, int32_t w, uint32_t p) {
         const int a = w & 3;
         int s[NV];
 #pragma unroll
@@ -1430,13 +1412,10 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
                 continue;
             }
             if (fresh) list[r * FSUB + atomicAdd(&nlist[r], 1)] = static_cast<int16_t>(h);
-            atomicAdd(&key[r * FSUB + h], 1 << FCNT);
+            const int ord = atomicAdd(&key[r * FSUB + h], 1 << FCNT) >> FCNT;  // arrival order
             if constexpr (PASS == 1) {
                 const int opp = k < a ? k : k + 1;  // local index of the opposite node
-                const unsigned long long word =
-                    (e << 32) | (static_cast<unsigned long long>(opp) << 26) | (p & 0x3ffffffu);
-                atomicMin(&wmin[r * FSUB + h], word);
-                atomicMax(&wmax[r * FSUB + h], word);
+                if (ord < 2) wj[(r * FSUB + h) * 2 + ord] = static_cast<uint8_t>((j << 2) | opp);
             }
         }
     };
@@ -1444,13 +1423,13 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
     for (int b = 0; b < FPRE; ++b) {
         const int idx = static_cast<int>(threadIdx.x) + b * FT;
         const int r = idx % FR, j = idx / FR;
-        if (j < alen[r]) entry(r, wpre[b], ppre[b]);
+        if (j < alen[r]) entry(r, j, wpre[b], ppre[b]);
     }
     for (int idx = threadIdx.x + FPRE * FT; idx < FR * maxl; idx += FT) {
         const int r = idx % FR, j = idx / FR;
         if (j >= alen[r]) continue;
         const int64_t t = static_cast<int64_t>(abase[r]) + j;
-        entry(r, adj[t], pk[t]);
+        entry(r, j, adj[t], pk[t]);
     }
     __syncthreads();
     if constexpr (PASS == 0) {
@@ -1499,6 +1478,11 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
             const int h = list[r * FSUB + (q - lpre[r])];
             const int32_t kk = key[r * FSUB + h] & FKEY;
             const int c = key[r * FSUB + h] >> FCNT;
+            // the face's entries, read back while the rank is counted (both, when it has two)
+            const int c0 = wj[(r * FSUB + h) * 2], c1 = c == 2 ? wj[(r * FSUB + h) * 2 + 1] : c0;
+            const int64_t t0 = static_cast<int64_t>(abase[r]) + (c0 >> 2), t1 = static_cast<int64_t>(abase[r]) + (c1 >> 2);
+            const int32_t w0 = adj[t0], w1 = adj[t1];
+            const uint32_t q0 = pk[t0], q1 = pk[t1];
             int rank = 0, brank = 0;
             const int nl = nlist[r];
             const int16_t* lr = list + r * FSUB;
@@ -1522,10 +1506,16 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
                 brank += before && (w2 >> FCNT) == 1;
             }
             const int64_t i = r0 + r;
-            const unsigned long long w1 = wmin[r * FSUB + h];
-            const int64_t e1 = static_cast<int64_t>(w1 >> 32);
-            const int opp = static_cast<int>((w1 >> 26) & 3);
-            const uint32_t p1 = static_cast<uint32_t>(w1 & 0x3ffffffu);
+            // the smaller element first; equal elements (a degenerate mesh) ordered by the
+            // opposite node and the slot word, so the choice never depends on arrival order
+            const uint32_t ea = static_cast<uint32_t>(w0) >> 2, eb = static_cast<uint32_t>(w1) >> 2;
+            const uint32_t ka = (static_cast<uint32_t>(c0 & 3) << 26) | (q0 & 0x3ffffffu);
+            const uint32_t kb = (static_cast<uint32_t>(c1 & 3) << 26) | (q1 & 0x3ffffffu);
+            const bool second = eb < ea || (eb == ea && kb < ka);
+            const int64_t e1 = second ? eb : ea;
+            const int32_t e2 = static_cast<int32_t>(second ? ea : eb);
+            const int opp = (second ? c1 : c0) & 3;
+            const uint32_t p1 = second ? q1 : q0;
             const int a1 = static_cast<int>(p1 & 3);  // local index of node i in e1
             const bool flip = esign[e1] != 0;
             const int32_t rb = rowp[r];
@@ -1541,7 +1531,7 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
                 if (fb >= 0) bfaces[fb * NV + t] = v;
             }
             fel[2 * f] = static_cast<int32_t>(e1);
-            fel[2 * f + 1] = c == 2 ? static_cast<int32_t>(wmax[r * FSUB + h] >> 32) : -1;
+            fel[2 * f + 1] = c == 2 ? e2 : -1;
             if (fb >= 0) bel[fb] = static_cast<int32_t>(e1);
         }
     }
