@@ -305,8 +305,9 @@ pf_status pf_assemble_quad(const pf_csr* csr, pf_dtype prec, const double* coord
  * list of their own (the section 3.5 facesB) with their elements.  Built from the
  * structure's adjacency and row patterns inside the handle; synchronises `stream` once
  * (the counts size the lists).  PF_EINVAL if a face belongs to more than two elements,
- * PF_ELIMIT if a node owns more than 128 faces (the faces whose smallest node it is) or the
- * structure has long rows (see pf_csr_symbolic).  A later pf_csr_symbolic invalidates it. */
+ * PF_ELIMIT if a node owns more than 128 faces (the faces whose smallest node it is), or
+ * more than 1024 for the node of a long row (see pf_csr_symbolic).  A later
+ * pf_csr_symbolic invalidates it. */
 pf_status pf_csr_faces(pf_csr* csr, const double* coords, const int32_t* elems, void* stream);
 
 /* The face lists of pf_csr_faces: counts on the host, device pointers owned by the handle:

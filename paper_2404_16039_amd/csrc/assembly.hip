@@ -1322,6 +1322,43 @@ __global__ __launch_bounds__(SBS) void k_elem_sign(int64_t ne, const double* __r
     esign[e] = det < 0.0 ? 1 : 0;
 }
 
+// One face of row i written at its place f (and fb >= 0 in the boundary list): its first
+// element is the smaller of the two that reached it (equal ids, a degenerate mesh, ordered by
+// the opposite node and the slot word, so the choice never depends on arrival order); code:
+// entry position in the row's adjacency << 2 | local node opposite the face, w and q: the
+// entry's adjacency and slot words.  The nodes follow the face opposite that node, outward
+// of the first element (reversed when its det J < 0): node i itself, or an other node of
+// the element at its column position in row i.
+template <int NLB>
+__device__ __forceinline__ void emit_face(int64_t i, int c, int code0, int code1, int32_t w0, int32_t w1, uint32_t q0,
+                                          uint32_t q1, int32_t rb, int64_t f, int64_t fb,
+                                          const int32_t* __restrict__ col_idx, const uint8_t* __restrict__ esign,
+                                          int32_t* __restrict__ faces, int32_t* __restrict__ fel,
+                                          int32_t* __restrict__ bfaces, int32_t* __restrict__ bel) {
+    constexpr int NV = NLB - 1;
+    const uint32_t ea = static_cast<uint32_t>(w0) >> 2, eb = static_cast<uint32_t>(w1) >> 2;
+    const uint32_t ka = (static_cast<uint32_t>(code0 & 3) << 26) | (q0 & 0x3ffffffu);
+    const uint32_t kb = (static_cast<uint32_t>(code1 & 3) << 26) | (q1 & 0x3ffffffu);
+    const bool second = c == 2 && (eb < ea || (eb == ea && kb < ka));
+    const int64_t e1 = second ? eb : ea;
+    const int32_t e2 = static_cast<int32_t>(second ? ea : eb);
+    const int opp = (second ? code1 : code0) & 3;
+    const uint32_t p1 = second ? q1 : q0;
+    const int a1 = static_cast<int>(p1 & 3);  // local index of node i in e1
+    const bool flip = esign[e1] != 0;
+#pragma unroll
+    for (int t = 0; t < NV; ++t) {
+        const int L = face_local(NLB, opp, flip ? NV - 1 - t : t);  // local node of e1
+        const int32_t v = L == a1 ? static_cast<int32_t>(i)
+                                  : col_idx[rb + static_cast<int>((p1 >> (2 + 8 * (L < a1 ? L : L - 1))) & 255)];
+        faces[f * NV + t] = v;
+        if (fb >= 0) bfaces[fb * NV + t] = v;
+    }
+    fel[2 * f] = static_cast<int32_t>(e1);
+    fel[2 * f + 1] = c == 2 ? e2 : -1;
+    if (fb >= 0) bel[fb] = static_cast<int32_t>(e1);
+}
+
 template <int NLB, int PASS>
 __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restrict__ row_ptr,
                                               const int32_t* __restrict__ col_idx, const int32_t* __restrict__ aptr,
@@ -1346,19 +1383,20 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
     __shared__ int32_t rowp[FR], rowf[FR], rowb[FR];
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * FR;
     const int nr = static_cast<int>((r0 + FR < nn) ? FR : nn - r0);
-    // every load that does not depend on another is issued first: the rows' adjacency
-    // offsets, diagonal positions and (pass 1) offsets; then the first FPRE batches of entries
+    // every load that does not depend on another is issued first: the rows' adjacency and
+    // row offsets, diagonal positions and (pass 1) face offsets; then the first FPRE batches
+    // of entries.  A long row counts as empty here: k_faces_long takes it.
     {
         const int r = static_cast<int>(threadIdx.x) < nr ? static_cast<int>(threadIdx.x) : 0;
         const int32_t a0 = aptr[r0 + r], a1 = aptr[r0 + r + 1], dv = dpos[r0 + r];
-        int32_t pv = 0, fv = 0, bv = 0;
+        const int32_t pv = row_ptr[r0 + r], pv1 = row_ptr[r0 + r + 1];
+        int32_t fv = 0, bv = 0;
         if constexpr (PASS == 1) {
-            pv = row_ptr[r0 + r];
             fv = fptr[r0 + r];
             bv = bptr[r0 + r];
         }
         if (threadIdx.x < FR) {
-            const int L = static_cast<int>(threadIdx.x) < nr ? min(a1 - a0, MAXADJ) : 0;
+            const int L = static_cast<int>(threadIdx.x) < nr && !is_long_row(a1 - a0, pv1 - pv) ? a1 - a0 : 0;
             alen[threadIdx.x] = L;
             abase[threadIdx.x] = a0;
             nlist[threadIdx.x] = 0;
@@ -1505,34 +1543,141 @@ __global__ __launch_bounds__(FT) void k_faces(int64_t nn, const int32_t* __restr
                 rank += before;
                 brank += before && (w2 >> FCNT) == 1;
             }
-            const int64_t i = r0 + r;
-            // the smaller element first; equal elements (a degenerate mesh) ordered by the
-            // opposite node and the slot word, so the choice never depends on arrival order
-            const uint32_t ea = static_cast<uint32_t>(w0) >> 2, eb = static_cast<uint32_t>(w1) >> 2;
-            const uint32_t ka = (static_cast<uint32_t>(c0 & 3) << 26) | (q0 & 0x3ffffffu);
-            const uint32_t kb = (static_cast<uint32_t>(c1 & 3) << 26) | (q1 & 0x3ffffffu);
-            const bool second = eb < ea || (eb == ea && kb < ka);
-            const int64_t e1 = second ? eb : ea;
-            const int32_t e2 = static_cast<int32_t>(second ? ea : eb);
-            const int opp = (second ? c1 : c0) & 3;
-            const uint32_t p1 = second ? q1 : q0;
-            const int a1 = static_cast<int>(p1 & 3);  // local index of node i in e1
-            const bool flip = esign[e1] != 0;
-            const int32_t rb = rowp[r];
             const int64_t f = rowf[r] + rank;
             const int64_t fb = c == 1 ? rowb[r] + brank : -1;
+            emit_face<NLB>(r0 + r, c, c0, c1, w0, w1, q0, q1, rowp[r], f, fb, col_idx, esign, faces, fel, bfaces,
+                           bel);
+        }
+    }
+}
+
+// The faces of the long rows (the rows the row-block passes leave empty), one workgroup per
+// row with the same two passes: the entries' faces owned by the row go into one table of FLS
+// slots keyed by the column positions of their other nodes (8 bits each here), each arrival
+// keeps its entry position and opposite node (pass 1), and each face's rank among the row's
+// keys is its place.  A row may own FLC faces (more sets ERR_ROW): the link of a node with at
+// most 255 neighbours has fewer triangles.
+constexpr int FLT = 256;   // threads of a long-row face workgroup
+constexpr int FLS = 2048;  // slots of its table
+constexpr int FLC = 1024;  // faces one long row may own
+static_assert(FLC <= FLS / 2 && FLC <= 32767, "the table stays at most half full; list items fit 16 bits");
+
+__device__ __forceinline__ int flong_hash(int32_t k) {
+    return static_cast<int>((static_cast<uint32_t>(k) * 2654435761u) >> 21);  // 11 bits
+}
+
+template <int NLB, int PASS>
+__global__ __launch_bounds__(FLT) void k_faces_long(const int32_t* __restrict__ lrows,
+                                                    const int32_t* __restrict__ row_ptr,
+                                                    const int32_t* __restrict__ col_idx,
+                                                    const int32_t* __restrict__ aptr, const int32_t* __restrict__ adj,
+                                                    const uint32_t* __restrict__ pk, const int32_t* __restrict__ dpos,
+                                                    const uint8_t* __restrict__ esign, int32_t* __restrict__ fcount,
+                                                    int32_t* __restrict__ bcount, const int32_t* __restrict__ fptr,
+                                                    const int32_t* __restrict__ bptr, int32_t* __restrict__ faces,
+                                                    int32_t* __restrict__ fel, int32_t* __restrict__ bfaces,
+                                                    int32_t* __restrict__ bel, int64_t* __restrict__ info) {
+    constexpr int NV = NLB - 1;
+    static_assert(FKEY >= (255 << 8 | 255), "two 8-bit positions fit a key");
+    __shared__ int32_t key[FLS];  // face key | element count << FCNT
+    __shared__ int16_t list[FLC];
+    constexpr int WS = PASS == 1 ? 2 * FLS : 1;
+    __shared__ int32_t wj[WS];  // per arrival: entry position << 2 | opposite local node
+    __shared__ int32_t nlist, nbnd, flags;
+    const int t = static_cast<int>(threadIdx.x);
+    const int64_t i = lrows[blockIdx.x];
+    const int64_t a0 = aptr[i];
+    const int L = aptr[i + 1] - static_cast<int>(a0);
+    const int ds = dpos[i];
+    for (int h = t; h < FLS; h += FLT) key[h] = -1;
+    if (t == 0) {
+        nlist = 0;
+        nbnd = 0;
+        flags = 0;
+    }
+    __syncthreads();
+    bool full = false;
+    for (int j = t; j < L; j += FLT) {
+        const int32_t w = adj[a0 + j];
+        const uint32_t p = pk[a0 + j];
+        const int a = w & 3;
+        int sp[NV];
 #pragma unroll
-            for (int t = 0; t < NV; ++t) {
-                const int L = face_local(NLB, opp, flip ? NV - 1 - t : t);  // local node of e1
-                // node i itself, or the k-th other node of e1 at its column position in row i
-                const int32_t v = L == a1 ? static_cast<int32_t>(i)
-                                          : col_idx[rb + static_cast<int>((p1 >> (2 + 8 * (L < a1 ? L : L - 1))) & 255)];
-                faces[f * NV + t] = v;
-                if (fb >= 0) bfaces[fb * NV + t] = v;
+        for (int k = 0; k < NV; ++k) sp[k] = static_cast<int>((p >> (2 + 8 * k)) & 255);
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {  // the face opposite the k-th other node
+            int smin = 1 << 20, smax = -1;
+#pragma unroll
+            for (int k2 = 0; k2 < NV; ++k2) {
+                if (k2 == k) continue;
+                smin = min(smin, sp[k2]);
+                smax = max(smax, sp[k2]);
             }
-            fel[2 * f] = static_cast<int32_t>(e1);
-            fel[2 * f + 1] = c == 2 ? e2 : -1;
-            if (fb >= 0) bel[fb] = static_cast<int32_t>(e1);
+            if (smin <= ds) continue;  // a node before the row's own: another row owns it
+            const int32_t kk = NV == 3 ? (smin << 8) | smax : smin;
+            int h = flong_hash(kk);
+            int cur = -1;
+            int probe = 0;
+            for (; probe < FLS; ++probe) {  // linear probing; the table never fills (FLC <= FLS / 2)
+                cur = atomicCAS(key + h, -1, kk);
+                if (cur == -1 || (cur & FKEY) == kk) break;
+                h = (h + 1) & (FLS - 1);
+            }
+            if (probe == FLS) {
+                full = true;
+                continue;
+            }
+            if (cur == -1) {
+                const int u = atomicAdd(&nlist, 1);
+                if (u < FLC) list[u] = static_cast<int16_t>(h);
+                else full = true;
+            }
+            const int ord = atomicAdd(key + h, 1 << FCNT) >> FCNT;  // arrival order
+            if constexpr (PASS == 1) {
+                if (ord < 2) wj[2 * h + ord] = (j << 2) | (k < a ? k : k + 1);
+            }
+        }
+    }
+    if (full) atomicOr(&flags, 1);
+    __syncthreads();
+    const int nl = min(nlist, FLC);
+    if constexpr (PASS == 0) {
+        int nb = 0;
+        bool bad = false;
+        for (int u = t; u < nl; u += FLT) {
+            const int c = key[list[u]] >> FCNT;
+            nb += c == 1;
+            bad = bad || c > 2;
+        }
+        if (nb) atomicAdd(&nbnd, nb);
+        if (bad) atomicOr(&flags, 2);
+        __syncthreads();
+        if (t == 0) {
+            fcount[i] = nl;
+            bcount[i] = nbnd;
+            if (flags)
+                atomicOr(reinterpret_cast<unsigned long long*>(info),
+                         static_cast<unsigned long long>(((flags & 2) ? ERR_FACE : 0) | ((flags & 1) ? ERR_ROW : 0)));
+        }
+    } else {
+        const int32_t rb = row_ptr[i];
+        const int64_t f0 = fptr[i], b0 = bptr[i];
+        for (int q = t; q < nl; q += FLT) {
+            const int h = list[q];
+            const int32_t kk = key[h] & FKEY;
+            const int c = key[h] >> FCNT;
+            const int c0 = wj[2 * h], c1 = c == 2 ? wj[2 * h + 1] : c0;
+            const int32_t w0 = adj[a0 + (c0 >> 2)], w1 = adj[a0 + (c1 >> 2)];
+            const uint32_t q0 = pk[a0 + (c0 >> 2)], q1 = pk[a0 + (c1 >> 2)];
+            int rank = 0, brank = 0;
+            for (int u = 0; u < nl; ++u) {
+                const int32_t w2 = key[list[u]];
+                const bool before = (w2 & FKEY) < kk;
+                rank += before;
+                brank += before && (w2 >> FCNT) == 1;
+            }
+            emit_face<NLB>(i, c, c0, c1, w0, w1, q0, q1, rb, f0 + rank, c == 1 ? b0 + brank : -1, col_idx, esign,
+                           faces, fel, bfaces, bel);
         }
     }
 }
@@ -3278,9 +3423,6 @@ pf_status pf_csr_faces(pf_csr* c, const double* coords, const int32_t* elems, vo
     if (!c) return fail(PF_EINVAL, "pf_csr_faces: null handle");
     if (!c->built) return fail(PF_ESTATE, "pf_csr_faces: structure not built");
     if (c->p2) return fail(PF_ESTATE, "pf_csr_faces: a P2 structure");
-    if (c->nlong > 0)
-        return fail(PF_ELIMIT, "pf_csr_faces: a node lies in more than 64 elements or a row holds more than 64 "
-                               "nonzeros (faces need rows of the row-block path)");
     if (c->ne > 0 && (!coords || !elems)) return fail(PF_EINVAL, "pf_csr_faces: null coords or elems");
     hipStream_t s = as_stream(stream);
     if (pf_status st = csr_order(c, s)) return st;
@@ -3310,6 +3452,17 @@ pf_status pf_csr_faces(pf_csr* c, const double* coords, const int32_t* elems, vo
                                c->adj, c->pk, c->dpos, c->esign, c->fcount, c->bcount, nullptr, nullptr, nullptr,
                                nullptr, nullptr, nullptr, c->finfo);
     }
+    const unsigned gl = static_cast<unsigned>(c->nlong);  // the long rows, after the row blocks left them empty
+    if (gl > 0) {
+        if (c->nlb == 4)
+            hipLaunchKernelGGL((k_faces_long<4, 0>), dim3(gl), dim3(FLT), 0, s, c->lrows, c->row_ptr, c->col_idx,
+                               c->aptr, c->adj, c->pk, c->dpos, c->esign, c->fcount, c->bcount, nullptr, nullptr,
+                               nullptr, nullptr, nullptr, nullptr, c->finfo);
+        else
+            hipLaunchKernelGGL((k_faces_long<3, 0>), dim3(gl), dim3(FLT), 0, s, c->lrows, c->row_ptr, c->col_idx,
+                               c->aptr, c->adj, c->pk, c->dpos, c->esign, c->fcount, c->bcount, nullptr, nullptr,
+                               nullptr, nullptr, nullptr, nullptr, c->finfo);
+    }
     if ((st = scan(c->fcount, nn, c->fptr, c->bsum, c->finfo + 1, s))) return st;
     if ((st = scan(c->bcount, nn, c->bptr, c->bsum, c->finfo + 2, s))) return st;
     if (!c->hinfo && (st = pinned_words(&c->hinfo))) return st;
@@ -3318,7 +3471,9 @@ pf_status pf_csr_faces(pf_csr* c, const double* coords, const int32_t* elems, vo
     PF_HIP_TRY(hipStreamSynchronize(s));
     if (info[0] & ERR_FACE)
         return fail(PF_EINVAL, "pf_csr_faces: a face belongs to more than two elements (not a conforming mesh)");
-    if (info[0] & ERR_ROW) return fail(PF_ELIMIT, "pf_csr_faces: a node owns more than 128 faces");
+    if (info[0] & ERR_ROW)
+        return fail(PF_ELIMIT, "pf_csr_faces: a node owns more than 128 faces (1024 for a node in more than 64 "
+                               "elements or with more than 64 neighbours)");
     const int64_t nf = info[1], nfb = info[2];
     const int nv = c->dim;
     if ((st = grow(c->faces, c->cap_faces, nf * nv, s))) return st;
@@ -3334,6 +3489,16 @@ pf_status pf_csr_faces(pf_csr* c, const double* coords, const int32_t* elems, vo
             hipLaunchKernelGGL((k_faces<3, 1>), dim3(g), dim3(FT), 0, s, nn, c->row_ptr, c->col_idx, c->aptr,
                                c->adj, c->pk, c->dpos, c->esign, nullptr, nullptr, c->fptr, c->bptr, c->faces,
                                c->fel, c->bfaces, c->bel, c->finfo);
+        if (gl > 0) {
+            if (c->nlb == 4)
+                hipLaunchKernelGGL((k_faces_long<4, 1>), dim3(gl), dim3(FLT), 0, s, c->lrows, c->row_ptr, c->col_idx,
+                                   c->aptr, c->adj, c->pk, c->dpos, c->esign, nullptr, nullptr, c->fptr, c->bptr,
+                                   c->faces, c->fel, c->bfaces, c->bel, c->finfo);
+            else
+                hipLaunchKernelGGL((k_faces_long<3, 1>), dim3(gl), dim3(FLT), 0, s, c->lrows, c->row_ptr, c->col_idx,
+                                   c->aptr, c->adj, c->pk, c->dpos, c->esign, nullptr, nullptr, c->fptr, c->bptr,
+                                   c->faces, c->fel, c->bfaces, c->bel, c->finfo);
+        }
     }
     if ((st = launch_check("pf_csr_faces"))) return st;
     c->nf = nf;

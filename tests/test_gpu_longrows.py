@@ -126,11 +126,27 @@ def test_long_rows_parity(lib, name, dtype):
         within(got["valK"], ref["valK"], ref["scaleK"], TOL[dtype], f"{name} K")
         within(got["valM"], ref["valM"], ref["scaleM"], TOL[dtype], f"{name} M")
         assert got["ctr"][2] == 0
-        # the structure keeps the long rows' list; faces need the row-block path
-        with pytest.raises(lib.PagefemError) as ei:
-            csr.faces(dev(coords), dev(elems))
-        assert ei.value.code == 7
         csr.close()
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_long_rows_faces(lib, name):
+    """Every face of meshes with long rows (the long rows' own faces from the long-row face
+    kernel, the others from the row blocks), with its element pair and orientation, and the
+    boundary list, equal to the oracle's; twice on one handle (the second call reuses the
+    lists)."""
+    say("long-row faces", name)
+    coords, elems = MESHES[name]
+    te = dev(elems)
+    csr = lib.Csr().symbolic(coords.shape[1], coords.shape[0], te)
+    F, FE = oracle.faces(coords, elems)
+    b = FE[:, 1] < 0
+    for _ in range(2):
+        csr.faces(dev(coords), te)
+        f, fe, bf, be = (host(t) for t in csr.face_lists())
+        assert np.array_equal(f, F) and np.array_equal(fe, FE)
+        assert np.array_equal(bf, F[b]) and np.array_equal(be, FE[b, 0])
+    csr.close()
 
 
 def test_long_rows_are_listed(lib):
