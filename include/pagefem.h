@@ -221,8 +221,10 @@ pf_status pf_csr_symbolic(pf_csr* csr, int dim, int64_t nn, int64_t ne, const in
 /* Build the CSR structure of a P2 mesh (section 3.6: the global matrices of the
  * stiffness_matrixP2 / mass_matrixP2 listings): elems2 ne x nlb2 int32 (nlb2 = 6 for dim 2,
  * 10 for dim 3) as for pf_p2_elements; every pair of nodes that share an element is an entry.
- * Rows hold at most 128 nonzeros (a vertex of the Kuhn cube's P2 mesh has 65), nodes at
- * most 64 elements, ne < 2^27 (PF_ELIMIT otherwise); otherwise as pf_csr_symbolic.  The
+ * A row of a node in more than 64 elements, or of more than 128 nonzeros (a vertex of the
+ * Kuhn cube's P2 mesh has 65), is a long row, built and assembled by one workgroup as in
+ * pf_csr_symbolic; any row holds at most 256 nonzeros, ne < 2^27 (PF_ELIMIT otherwise);
+ * otherwise as pf_csr_symbolic.  The
  * handle then serves pf_csr_info, pf_csr_assemble_pages and the stage timing; the P1 calls
  * (pf_assemble, pf_assemble_quad, pf_csr_faces, pf_rhs, pf_energies) return PF_ESTATE. */
 pf_status pf_csr_symbolic_p2(pf_csr* csr, int dim, int64_t nn, int64_t ne, const int32_t* elems2,

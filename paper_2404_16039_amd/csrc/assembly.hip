@@ -60,6 +60,8 @@ struct pf_csr {
     int64_t nlong = 0;
     int32_t* lrows = nullptr;
     int64_t cap_lrows = 0;
+    uint8_t* pk9 = nullptr;  // P2 long rows of 10-node elements: each entry's ninth position
+    int64_t cap_pk9 = 0;
     bool p2 = false;            // built from P2 elements (pf_csr_symbolic_p2)
     int64_t* bsum = nullptr;  // scan workspace
     int64_t* info = nullptr;  // [0] error bits, [1] adjacency total, [2] nnz, [3..6] block stats
@@ -229,8 +231,8 @@ __device__ __forceinline__ int ag_hash(int32_t node) {
 // round trip) instead of sweeping the table.  The order inside a row is not fixed: nothing
 // downstream depends on it (the numeric phase sums exactly, so its result does not depend
 // on the entry order).  Out-of-range node ids set an error bit and are not stored; entries
-// beyond MAXADJ are not stored either (an error for P2; for P1 the node's row is a long row,
-// whose entries the long-row phase places again), while the length counts them all.
+// beyond MAXADJ are not stored either (the node's row is a long row, whose entries the
+// long-row phase places again), while the length counts them all.
 template <int ASH>  // bits of the local index in an adjacency entry: 2 (P1), 4 (P2)
 __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ elems, int64_t m, int nlb, int64_t nn,
                                                    int32_t* __restrict__ adj_len, int32_t* __restrict__ adj,
@@ -294,19 +296,11 @@ __global__ __launch_bounds__(AG_BS) void k_scatter(const int32_t* __restrict__ e
             old[q] = atomicAdd(adj_len + keys[h], vals[h]);
         }
     }
-    bool over = false;
 #pragma unroll
     for (int q = 0; q < AG_ITEMS; ++q) {
         const int u = threadIdx.x + q * AG_BS;
-        if (u < nu) {
-            const int h = uniq[u];
-            if (old[q] + vals[h] > MAXADJ) over = true;
-            vals[h] = old[q];  // the tile's first position in the node's row
-        }
+        if (u < nu) vals[uniq[u]] = old[q];  // the tile's first position in the node's row
     }
-    // P1 nodes beyond MAXADJ elements are long rows (their entries are placed again by the
-    // long-row phase); P2 structures have no long rows
-    if (over && ASH == 4) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < AG_ITEMS; ++q) {
@@ -392,18 +386,21 @@ struct P2Pattern {                  // LDS of a P2 pattern block
 };
 
 // One pass over NRW rows (nrw of them in the matrix) starting at row rq, with TS-slot tables,
-// one adjacency entry per thread at a time.  alen: the rows' numbers of elements, abase: their
-// first compact adjacency entries (LDS); dst: the colblk region of the pass's first 8 rows
-// (rows 8 .. 15 of a 16-row pass go to the next region); apre: this thread's entry of the
-// first batch (item r + NRW j, j = thread / NRW), read at block start, used when `pre`.  Every
-// entry is copied to its compact place, with its pk2 word.
+// one adjacency entry per thread at a time.  alen: the rows' numbers of elements (0 for a
+// long row), abase: their first compact adjacency entries, rlong: their long-row flags (all
+// LDS; a row whose table fills becomes long); dst: the colblk region of the pass's first 8
+// rows (rows 8 .. 15 of a 16-row pass go to the next region); apre: this thread's entry of
+// the first batch (item r + NRW j, j = thread / NRW), read at block start, used when `pre`.
+// Every entry of a row kept here is copied to its compact place, with its pk2 word; a long
+// row gets no columns, diagonal position -1, and joins the list of long rows.
 template <int NLB, int NRW, int TS>
-__device__ __forceinline__ void p2_pattern_pass(P2Pattern& S, const int32_t* alen, const int32_t* abase, int64_t rq,
-                                                int nrw, const int32_t* __restrict__ elems,
+__device__ __forceinline__ void p2_pattern_pass(P2Pattern& S, const int32_t* alen, const int32_t* abase,
+                                                int32_t* rlong, int64_t rq, int nrw, const int32_t* __restrict__ elems,
                                                 const int32_t* __restrict__ adj, int32_t* __restrict__ rowlen,
                                                 int32_t* __restrict__ dst, int32_t* __restrict__ adjc,
                                                 uint64_t* __restrict__ pk2, int32_t* __restrict__ dpos,
-                                                int32_t apre, bool pre, bool& bad) {
+                                                int32_t* __restrict__ lrows, int64_t* __restrict__ info, int32_t apre,
+                                                bool pre) {
     constexpr int NO = NLB - 1;
     static_assert(NO * 7 <= 64, "the positions of the other nodes fit one 64-bit word");
     static_assert(NRW * TS == TAB2, "a pass fills the block's tables");
@@ -415,7 +412,7 @@ __device__ __forceinline__ void p2_pattern_pass(P2Pattern& S, const int32_t* ale
     if (threadIdx.x < NRW) {
         const int r = threadIdx.x;
         const int L = r < nrw ? alen[r] : 0;
-        if (r < nrw && L == 0) dpos[rq + r] = 0;  // a node of no element has an empty row
+        if (r < nrw && L == 0 && !rlong[r]) dpos[rq + r] = 0;  // a node of no element has an empty row
         if (L > 0) {                              // the diagonal
             const int32_t self = static_cast<int32_t>(rq + r);
             S.tab[r * TS + tsub_hash<TS>(self)] = self;
@@ -469,8 +466,8 @@ __device__ __forceinline__ void p2_pattern_pass(P2Pattern& S, const int32_t* ale
             pend |= static_cast<uint32_t>(cur != -1 && cur != ov[k]) << k;
         }
         for (int probe = 1; pend != 0u; ++probe) {  // linear probing
-            if (probe == TS) {                      // a full table: the row is too long
-                bad = true;
+            if (probe == TS) {                      // a full table: a long row
+                rlong[r] = 1;
                 break;
             }
 #pragma unroll
@@ -492,6 +489,10 @@ __device__ __forceinline__ void p2_pattern_pass(P2Pattern& S, const int32_t* ale
     // of each 64; a wave reads its 64 slots before it writes, and writes only below them)
     for (int r = threadIdx.x >> 6; r < NRW; r += RT2 / 64) {
         const int lane = threadIdx.x & 63;
+        if (rlong[r]) {  // the same for the wave: no columns here
+            if (lane == 0) S.cnt[r] = 0;
+            continue;
+        }
         int n = 0;
 #pragma unroll
         for (int half = 0; half < TS / 64; ++half) {
@@ -520,7 +521,14 @@ __device__ __forceinline__ void p2_pattern_pass(P2Pattern& S, const int32_t* ale
         if (lane < nrw) S.cpre[lane] = x - v;
         if (lane == nrw - 1) S.cpre[nrw] = x;
     }
-    if (threadIdx.x < nrw) rowlen[rq + threadIdx.x] = S.cnt[threadIdx.x];
+    if (static_cast<int>(threadIdx.x) < nrw) {
+        rowlen[rq + threadIdx.x] = S.cnt[threadIdx.x];
+        if (rlong[threadIdx.x]) {
+            dpos[rq + threadIdx.x] = -1;
+            lrows[atomicAdd(reinterpret_cast<unsigned long long*>(info + INFO_NLONG), 1ull)] =
+                static_cast<int32_t>(rq + threadIdx.x);
+        }
+    }
     __syncthreads();
     // each node's rank in its row = its column position; the sorted columns go straight to
     // their region (a wave's stores cover a contiguous run of it): rows 0 .. 7 of the pass to
@@ -550,7 +558,7 @@ __device__ __forceinline__ void p2_pattern_pass(P2Pattern& S, const int32_t* ale
         const int idx = static_cast<int>(threadIdx.x) + it * RT2;
         if (idx >= items) break;
         const int r = idx % NRW, j = idx / NRW;
-        if (r >= nrw || j >= alen[r]) continue;
+        if (r >= nrw || j >= alen[r] || rlong[r]) continue;
         const uint64_t w = eslot[it];
         uint64_t word = 0;
 #pragma unroll
@@ -567,11 +575,12 @@ __global__ __launch_bounds__(RT2) void k_pattern_p2(int64_t nn, const int32_t* _
                                                    const int32_t* __restrict__ aptr, int32_t* __restrict__ rowlen,
                                                    int32_t* __restrict__ colblk, int32_t* __restrict__ adjc,
                                                    uint64_t* __restrict__ pk2, int32_t* __restrict__ dpos,
-                                                   int64_t* __restrict__ info) {
+                                                   int32_t* __restrict__ lrows, int64_t* __restrict__ info) {
     constexpr int NO = NLB - 1;
     __shared__ P2Pattern S;
     __shared__ int32_t alen[RR2];
     __shared__ int32_t abase[RR2];
+    __shared__ int32_t rlong[RR2];
     __shared__ int32_t longrows;
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * RR2;
     const int nr = static_cast<int>((r0 + RR2 < nn) ? RR2 : nn - r0);
@@ -587,28 +596,29 @@ __global__ __launch_bounds__(RT2) void k_pattern_p2(int64_t nn, const int32_t* _
     const int32_t lv = adj_len[r0 + (static_cast<int>(threadIdx.x) < nr ? threadIdx.x : 0)];
     const int32_t av = aptr[r0 + (static_cast<int>(threadIdx.x) < nr ? threadIdx.x : 0)];
     if (threadIdx.x < 64) {  // row lengths, and whether a row may hold more than 64 nonzeros (wave 0)
-        const int L = static_cast<int>(threadIdx.x) < nr ? min(lv, MAXADJ) : 0;
+        // a node of more than MAXADJ elements heads a long row: left to the long-row phase
+        const bool lng = static_cast<int>(threadIdx.x) < nr && lv > MAXADJ;
+        const int L = static_cast<int>(threadIdx.x) < nr && !lng ? lv : 0;
         if (threadIdx.x < RR2) {
             alen[threadIdx.x] = L;
             abase[threadIdx.x] = av;
+            rlong[threadIdx.x] = lng;
         }
         const unsigned long long lg = __ballot(1 + NO * L > 64);
         if (threadIdx.x == 0) longrows = lg != 0ull;
     }
     __syncthreads();
-    bool bad = false;
     int32_t* dst = colblk + (static_cast<int64_t>(blockIdx.x) * 2) * (RR * MAXROW2);
     if (!longrows) {
-        p2_pattern_pass<NLB, RR2, 64>(S, alen, abase, r0, nr, elems, adj, rowlen, dst, adjc, pk2, dpos, apre, true,
-                                      bad);
+        p2_pattern_pass<NLB, RR2, 64>(S, alen, abase, rlong, r0, nr, elems, adj, rowlen, dst, adjc, pk2, dpos, lrows,
+                                      info, apre, true);
     } else {
-        p2_pattern_pass<NLB, RR, MAXROW2>(S, alen, abase, r0, min(nr, RR), elems, adj, rowlen, dst, adjc, pk2, dpos,
-                                          apre, false, bad);
+        p2_pattern_pass<NLB, RR, MAXROW2>(S, alen, abase, rlong, r0, min(nr, RR), elems, adj, rowlen, dst, adjc, pk2,
+                                          dpos, lrows, info, apre, false);
         if (nr > RR)
-            p2_pattern_pass<NLB, RR, MAXROW2>(S, alen + RR, abase + RR, r0 + RR, nr - RR, elems, adj, rowlen,
-                                              dst + RR * MAXROW2, adjc, pk2, dpos, apre, false, bad);
+            p2_pattern_pass<NLB, RR, MAXROW2>(S, alen + RR, abase + RR, rlong + RR, r0 + RR, nr - RR, elems, adj,
+                                              rowlen, dst + RR * MAXROW2, adjc, pk2, dpos, lrows, info, apre, false);
     }
-    if (bad) atomicOr(reinterpret_cast<unsigned long long*>(info), static_cast<unsigned long long>(ERR_ROW));
 }
 
 // ---------------------------------------------------------------------------- row offsets
@@ -1116,9 +1126,10 @@ constexpr int LTAB = 1024;  // slots of a long row's hash table (at most LCAP no
 static_assert(CSR_MAXADJ == MAXADJ && CSR_MAXROW == MAXROW && CSR_LCAP == LCAP, "one long-row rule");
 __device__ __forceinline__ bool is_long_row(int elements, int nonzeros) { return csr_long_row(elements, nonzeros); }
 
-// every entry of a long row's node (diagonal position -1) at aptr[node] + a cursor; the
-// cursor is the node's row length, which the row-block pass left at 0 for long rows
-__global__ __launch_bounds__(SBS) void k_long_adj(const int32_t* __restrict__ elems, int64_t m, int nlb,
+// every entry (element << ash | local index) of a long row's node (diagonal position -1) at
+// aptr[node] + a cursor; the cursor is the node's row length, which the row-block pass left
+// at 0 for long rows
+__global__ __launch_bounds__(SBS) void k_long_adj(const int32_t* __restrict__ elems, int64_t m, int nlb, int ash,
                                                   const int32_t* __restrict__ dpos, const int32_t* __restrict__ aptr,
                                                   int32_t* __restrict__ cur, int32_t* __restrict__ adjc) {
     for (int64_t t = static_cast<int64_t>(blockIdx.x) * SBS + threadIdx.x; t < m;
@@ -1128,7 +1139,7 @@ __global__ __launch_bounds__(SBS) void k_long_adj(const int32_t* __restrict__ el
         const int64_t e = t / nlb;
         const int a = static_cast<int>(t - e * nlb);
         const int pos = atomicAdd(cur + node, 1);
-        adjc[aptr[node] + pos] = static_cast<int32_t>((e << 2) | a);
+        adjc[aptr[node] + pos] = static_cast<int32_t>((e << ash) | a);
     }
 }
 
@@ -1140,14 +1151,18 @@ static_assert(LTAB == 1024, "long_hash yields 10 bits");
 // One workgroup per long row: the other nodes of all its entries (and the row's own) enter an
 // LDS hash table; the distinct nodes are ranked (ascending: the column positions), written to
 // the row's list in lcol (LCAP words per long row), and every entry's slot word is formed
-// from the ranks of its element's other nodes.  More than LCAP distinct nodes: ERR_ROW.
-template <int NLB>
+// from the ranks of its element's other nodes: P1 (ASH = 2) pk as in the row-block pass, P2
+// (ASH = 4) 8-bit positions in pk2 (k < 8) and pk9 (the ninth).  More than LCAP distinct
+// nodes: ERR_ROW.
+template <int NLB, int ASH>
 __global__ __launch_bounds__(LT) void k_rows_long(const int32_t* __restrict__ lrows, const int32_t* __restrict__ elems,
                                                   const int32_t* __restrict__ aptr, const int32_t* __restrict__ adjc,
                                                   int32_t* __restrict__ rowlen, int32_t* __restrict__ lcol,
-                                                  uint32_t* __restrict__ pk, int32_t* __restrict__ dpos,
+                                                  uint32_t* __restrict__ pk, uint64_t* __restrict__ pk2,
+                                                  uint8_t* __restrict__ pk9, int32_t* __restrict__ dpos,
                                                   int64_t* __restrict__ info) {
     constexpr int NO = NLB - 1;
+    static_assert((ASH == 2 && NO <= 3) || (ASH == 4 && NO <= 9), "P1 entries: 2-bit index; P2: 4-bit");
     __shared__ int32_t tab[LTAB];
     __shared__ uint8_t trank[LTAB];
     __shared__ int32_t lst[LCAP];
@@ -1179,8 +1194,8 @@ __global__ __launch_bounds__(LT) void k_rows_long(const int32_t* __restrict__ lr
     if (t == 0) insert(row);
     for (int j = t; j < L; j += LT) {
         const int32_t w = adjc[a0 + j];
-        const int64_t e = static_cast<uint32_t>(w) >> 2;
-        const int a = w & 3;
+        const int64_t e = static_cast<uint32_t>(w) >> ASH;
+        const int a = w & ((1 << ASH) - 1);
 #pragma unroll
         for (int k = 0; k < NO; ++k) insert(elems[e * NLB + (k < a ? k : k + 1)]);
     }
@@ -1203,25 +1218,28 @@ __global__ __launch_bounds__(LT) void k_rows_long(const int32_t* __restrict__ lr
     __syncthreads();
     for (int j = t; j < L; j += LT) {
         const int32_t w = adjc[a0 + j];
-        const int64_t e = static_cast<uint32_t>(w) >> 2;
-        const int a = w & 3;
-        uint32_t word = static_cast<uint32_t>(a);
+        const int64_t e = static_cast<uint32_t>(w) >> ASH;
+        const int a = w & ((1 << ASH) - 1);
+        uint64_t word = ASH == 2 ? static_cast<uint64_t>(a) : 0ull;
 #pragma unroll
         for (int k = 0; k < NO; ++k) {
             const int32_t v = elems[e * NLB + (k < a ? k : k + 1)];
             int h = long_hash(v);
             while (tab[h] != v) h = (h + 1) & (LTAB - 1);  // present: entered above
-            word |= static_cast<uint32_t>(trank[h]) << (2 + 8 * k);
+            if constexpr (ASH == 2) word |= static_cast<uint64_t>(trank[h]) << (2 + 8 * k);
+            else if (k < 8) word |= static_cast<uint64_t>(trank[h]) << (8 * k);
+            else pk9[a0 + j] = trank[h];
         }
-        pk[a0 + j] = word;
+        if constexpr (ASH == 2) pk[a0 + j] = static_cast<uint32_t>(word);
+        else pk2[a0 + j] = word;
     }
 }
 
 // The columns of the 8-row groups that hold a long row, rewritten once col_idx is sized: the
-// long row's from its list, the group's other rows from the group's colblk region (in row
-// order, lengths from row_ptr).  Two long rows of one group write the same words for the
-// group's other rows.
-__global__ __launch_bounds__(LT) void k_long_columns(const int32_t* __restrict__ lrows, int64_t nn,
+// long row's from its list, the group's other rows from the group's colblk region (RR x
+// maxrow words: maxrow = MAXROW for P1, MAXROW2 for P2; in row order, lengths from row_ptr).
+// Two long rows of one group write the same words for the group's other rows.
+__global__ __launch_bounds__(LT) void k_long_columns(const int32_t* __restrict__ lrows, int64_t nn, int maxrow,
                                                      const int32_t* __restrict__ row_ptr,
                                                      const int32_t* __restrict__ aptr,
                                                      const int32_t* __restrict__ colblk,
@@ -1234,12 +1252,12 @@ __global__ __launch_bounds__(LT) void k_long_columns(const int32_t* __restrict__
         for (int k = t; k < len; k += LT) col_idx[w0 + k] = lcol[static_cast<int64_t>(blockIdx.x) * LCAP + k];
     }
     const int64_t g0 = row / RR * RR;
-    const int32_t* src = colblk + g0 * MAXROW;  // the group's region
+    const int32_t* src = colblk + g0 * maxrow;  // the group's region
     int off = 0;
     for (int64_t r = g0; r < g0 + RR && r < nn; ++r) {
         const int64_t w0 = row_ptr[r];
         const int len = row_ptr[r + 1] - static_cast<int>(w0);
-        if (is_long_row(aptr[r + 1] - aptr[r], len)) continue;
+        if (aptr[r + 1] - aptr[r] > MAXADJ || len > maxrow) continue;  // a long row (P1 or P2)
         for (int k = t; k < len; k += LT) col_idx[w0 + k] = src[off + k];
         off += len;
     }
@@ -2894,7 +2912,7 @@ size_t csr_bytes(const pf_csr* c) {
            static_cast<size_t>(c->cap_work) * 8 +
            static_cast<size_t>(c->cap_fcount + c->cap_bcount + c->cap_fptr + c->cap_bptr + c->cap_faces + c->cap_fel +
                                c->cap_bfaces + c->cap_bel) * 4 + static_cast<size_t>(c->cap_finfo) * 8 +
-           static_cast<size_t>(c->cap_esign);
+           static_cast<size_t>(c->cap_esign + c->cap_pk9);
 }
 
 int64_t csr_nnz(const pf_csr* c) { return c->built ? c->nnz : -1; }
@@ -2921,6 +2939,7 @@ bool csr_view(const pf_csr* c, CsrView* v) {
     v->max_adj = c->max_adj;
     v->nlong = c->nlong;
     v->lrows = c->lrows;
+    v->pk9 = c->pk9;
     return true;
 }
 const int32_t* csr_adj(const pf_csr* c) { return c->adj; }
@@ -2961,6 +2980,7 @@ void csr_release(pf_csr* c, hipStream_t s) {
     c->cap_scratch = 0;
     drop(c->res, c->cap_res, s);
     drop(c->lrows, c->cap_lrows, s);
+    drop(c->pk9, c->cap_pk9, s);
     drop(c->col_idx, c->cap_nnz, s);
     drop(c->work, c->cap_work, s);
     drop(c->fcount, c->cap_fcount, s);
@@ -3142,10 +3162,10 @@ pf_status symbolic_enqueue(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, 
         const unsigned g2 = static_cast<unsigned>(ceil_div(nn, RR2));  // P2: 16-row blocks
         if (nlb == 10)
             hipLaunchKernelGGL((k_pattern_p2<10>), dim3(g2), dim3(RT2), 0, s, nn, elems, c->adj_len, c->adj_pad,
-                               c->aptr, c->cnt, c->colblk, c->adj, c->pk2, c->dpos, c->info);
+                               c->aptr, c->cnt, c->colblk, c->adj, c->pk2, c->dpos, c->lrows_s, c->info);
         else if (nlb == 6)
             hipLaunchKernelGGL((k_pattern_p2<6>), dim3(g2), dim3(RT2), 0, s, nn, elems, c->adj_len, c->adj_pad,
-                               c->aptr, c->cnt, c->colblk, c->adj, c->pk2, c->dpos, c->info);
+                               c->aptr, c->cnt, c->colblk, c->adj, c->pk2, c->dpos, c->lrows_s, c->info);
         else if (nlb == 4)
             hipLaunchKernelGGL((k_rows_p1<4>), dim3(g1), dim3(PT), 0, s, nn, elems, c->adj_len, c->adj_pad, c->aptr,
                                c->cnt, c->colblk, c->adj, c->pk, c->dpos, c->lrows_s, c->info);
@@ -3199,29 +3219,44 @@ void drop_scratch(pf_csr* c, hipStream_t s) {
     c->look = nullptr;
 }
 
-// Phase 1b, only for a P1 mesh whose phase 1 listed long rows: their list made resident,
-// their nodes' compact adjacency, one workgroup per long row for its pattern (columns into
-// lcol, slot words, diagonal position, row length), then the row offsets and statistics again
-// with the long rows' lengths; ends with the status readback and the ready event.
+// Phase 1b, only for a mesh whose phase 1 listed long rows: their list made resident, their
+// nodes' compact adjacency, one workgroup per long row for its pattern (columns into lcol,
+// slot words, diagonal position, row length), then the row offsets and statistics again with
+// the long rows' lengths; ends with the status readback and the ready event.
 pf_status symbolic_long(pf_csr* c, const char* who) {
     hipStream_t s = c->q_stream;
     const int64_t nlong = c->hinfo[INFO_NLONG];
     const int64_t nn = c->q_nn, m = c->q_ne * c->q_nlb;
+    const int nlb = c->q_nlb;
+    const bool p2 = nlb > c->q_dim + 1;
     pf_status st;
     if ((st = grow(c->lrows, c->cap_lrows, nlong, s))) return st;
     if ((st = grow(c->lcol, c->cap_lcol, nlong * LCAP, s))) return st;
+    if (nlb == 10 && (st = grow(c->pk9, c->cap_pk9, m, s))) return st;  // the ninth position of a P2 long row's entry
     c->nlong = nlong;
     c->q_long = true;
     PF_HIP_TRY(hipMemcpyAsync(c->lrows, c->lrows_s, nlong * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_long_adj, dim3(flat_grid(m)), dim3(SBS), 0, s, c->q_elems, m, c->q_nlb, c->dpos, c->aptr,
-                       c->cnt, c->adj);
+    hipLaunchKernelGGL(k_long_adj, dim3(flat_grid(m)), dim3(SBS), 0, s, c->q_elems, m, nlb, p2 ? 4 : 2, c->dpos,
+                       c->aptr, c->cnt, c->adj);
     const unsigned g = static_cast<unsigned>(nlong);
-    if (c->q_nlb == 4)
-        hipLaunchKernelGGL((k_rows_long<4>), dim3(g), dim3(LT), 0, s, c->lrows, c->q_elems, c->aptr, c->adj, c->cnt,
-                           c->lcol, c->pk, c->dpos, c->info);
-    else
-        hipLaunchKernelGGL((k_rows_long<3>), dim3(g), dim3(LT), 0, s, c->lrows, c->q_elems, c->aptr, c->adj, c->cnt,
-                           c->lcol, c->pk, c->dpos, c->info);
+    switch (nlb) {
+        case 4:
+            hipLaunchKernelGGL((k_rows_long<4, 2>), dim3(g), dim3(LT), 0, s, c->lrows, c->q_elems, c->aptr, c->adj,
+                               c->cnt, c->lcol, c->pk, nullptr, nullptr, c->dpos, c->info);
+            break;
+        case 3:
+            hipLaunchKernelGGL((k_rows_long<3, 2>), dim3(g), dim3(LT), 0, s, c->lrows, c->q_elems, c->aptr, c->adj,
+                               c->cnt, c->lcol, c->pk, nullptr, nullptr, c->dpos, c->info);
+            break;
+        case 10:
+            hipLaunchKernelGGL((k_rows_long<10, 4>), dim3(g), dim3(LT), 0, s, c->lrows, c->q_elems, c->aptr, c->adj,
+                               c->cnt, c->lcol, nullptr, c->pk2, c->pk9, c->dpos, c->info);
+            break;
+        default:
+            hipLaunchKernelGGL((k_rows_long<6, 4>), dim3(g), dim3(LT), 0, s, c->lrows, c->q_elems, c->aptr, c->adj,
+                               c->cnt, c->lcol, nullptr, c->pk2, nullptr, c->dpos, c->info);
+            break;
+    }
     const int64_t tiles = ceil_div(nn, SCAN_TILE);
     hipLaunchKernelGGL(k_fill_i64, dim3(flat_grid(tiles)), dim3(SBS), 0, s, reinterpret_cast<int64_t*>(c->look), tiles,
                        int64_t(0));
@@ -3252,7 +3287,7 @@ pf_status enqueue_columns(pf_csr* c, hipStream_t s, const char* who) {
                                c->colblk, c->col_idx, c->cap_nnz);
         if (c->nlong > 0)
             hipLaunchKernelGGL(k_long_columns, dim3(static_cast<unsigned>(c->nlong)), dim3(LT), 0, s, c->lrows, nn,
-                               c->row_ptr, c->aptr, c->colblk, c->lcol, c->col_idx);
+                               p2 ? MAXROW2 : MAXROW, c->row_ptr, c->aptr, c->colblk, c->lcol, c->col_idx);
     }
     if ((st = mark(c, 5, s))) return st;
     return launch_check(who);
@@ -3271,12 +3306,10 @@ pf_status symbolic_columns(pf_csr* c, const char* who) {
     pf_status st = PF_OK;
     if (info[0] & ERR_INDEX) st = fail(PF_EINDEX, std::string(who) + ": node index out of range in elems");
     else if (info[0] & ERR_ROW)
-        st = p2 ? fail(PF_ELIMIT, std::string(who) + ": a node belongs to more than 64 elements or a row has more "
-                                  "than " + std::to_string(MAXROW2) + " nonzeros")
-                : fail(PF_ELIMIT, std::string(who) + ": a row has more than " + std::to_string(LCAP) + " nonzeros");
+        st = fail(PF_ELIMIT, std::string(who) + ": a row has more than " + std::to_string(LCAP) + " nonzeros");
     else if (info[0] & ERR_SCAN) st = fail(PF_EINVAL, std::string(who) + ": the row offsets could not be formed");
     else if (info[2] >= INT32_MAX) st = fail(PF_ELIMIT, std::string(who) + ": nnz must be < 2^31");
-    if (st == PF_OK && !p2 && !c->q_long && info[INFO_NLONG] > 0) {
+    if (st == PF_OK && !c->q_long && info[INFO_NLONG] > 0) {
         if ((st = symbolic_long(c, who)) == PF_OK) return PF_OK;
     }
     const int64_t nnz = info[2];

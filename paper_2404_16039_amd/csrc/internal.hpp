@@ -61,21 +61,28 @@ struct CsrView {
     const int32_t* dpos;
     int wmax4, wmax16, wmax32;
     int max_adj;
-    int64_t nlong;         // long rows (P1 only) ...
+    int64_t nlong;         // long rows ...
     const int32_t* lrows;  // ... and their list
+    const uint8_t* pk9;    // P2 long rows of 10-node elements: the ninth 8-bit position
 };
 bool csr_view(const pf_csr* c, CsrView* v);  // false unless built
 // node -> element adjacency of the structure: entries (element << 2 | local index) of node i
 // at adj[aptr[i]] .. adj[aptr[i+1] - 1], at most CSR_MAXADJ of them
 constexpr int CSR_MAXADJ = 64;
 // A P1 row is long when its node lies in more than CSR_MAXADJ elements or the row holds
-// more than CSR_MAXROW nonzeros: the row-block kernels skip it, and kernels of one workgroup
-// per long row (listed in lrows, nlong of them) assemble it; a long row holds at most
-// CSR_LCAP nonzeros.
+// more than CSR_MAXROW nonzeros (a P2 row: more than CSR_MAXROW2): the row-block kernels skip
+// it, and kernels of one workgroup per long row (listed in lrows, nlong of them) assemble it;
+// a long row holds at most CSR_LCAP nonzeros.  The slot words of a P2 long row's entries
+// hold 8-bit positions (pk2 bits 8k .. 8k+7 for the k-th other node, k < 8; the ninth of a
+// 10-node element in pk9).
 constexpr int CSR_MAXROW = 64;
+constexpr int CSR_MAXROW2 = 128;
 constexpr int CSR_LCAP = 256;
 __host__ __device__ inline bool csr_long_row(int elements, int nonzeros) {
     return elements > CSR_MAXADJ || nonzeros > CSR_MAXROW;
+}
+__host__ __device__ inline bool csr_long_row_p2(int elements, int nonzeros) {
+    return elements > CSR_MAXADJ || nonzeros > CSR_MAXROW2;
 }
 const int32_t* csr_adj(const pf_csr* c);
 const int32_t* csr_aptr(const pf_csr* c);

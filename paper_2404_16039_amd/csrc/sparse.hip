@@ -88,6 +88,9 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int32_t rp[PR + 1], abase[PR + 1], apre[PR + 1], dslot[PR];
     __shared__ int32_t anylong;
+    auto is_long = [](int elements, int nonzeros) {
+        return P2 ? csr_long_row_p2(elements, nonzeros) : csr_long_row(elements, nonzeros);
+    };
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * PR;
     const int nr = static_cast<int>((r0 + PR < nn) ? PR : nn - r0);
     if (threadIdx.x <= PR) {  // rows past the end: no slots, no entries
@@ -101,7 +104,7 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_
     if (threadIdx.x < 64) {  // prefix of the rows' entries in wave 0; P1 long rows count none
         const int r = threadIdx.x;
         const int La = r < nr ? abase[r + 1] - abase[r] : 0;
-        const bool lng = !P2 && r < nr && csr_long_row(La, rp[r + 1] - rp[r]);
+        const bool lng = r < nr && is_long(La, rp[r + 1] - rp[r]);
         const int Lk = lng ? 0 : La;
         int x = Lk;
 #pragma unroll
@@ -148,7 +151,7 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_
     __syncthreads();  // accumulators cleared
     if (anylong) {  // a long row's slots are marked: neither graded nor stored here
         for (int r = 0; r < nr; ++r)
-            if (csr_long_row(abase[r + 1] - abase[r], rp[r + 1] - rp[r]))
+            if (is_long(abase[r + 1] - abase[r], rp[r + 1] - rp[r]))
                 for (int k = rp[r] - w0 + threadIdx.x; k < rp[r + 1] - w0; k += PBT) shK[k] = INT32_MIN;
         __syncthreads();
     }
@@ -203,18 +206,22 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages(int64_t nn, const int32_
     }
 }
 
-// The long rows of a P1 structure (one workgroup each, at most CSR_LCAP slots): every entry's
-// column of its element's pages, graded and summed on each slot's LongGrid as in the
-// long-row numeric kernel (page values are exact in FP64).
-template <int NB, typename T>
+// The long rows (one workgroup each, at most CSR_LCAP slots): every entry's column of its
+// element's pages, graded and summed on each slot's LongGrid as in the long-row numeric
+// kernel (page values are exact in FP64).  Slot positions: P1 from pk, P2 from the 8-bit
+// positions of a long row's entries (pk2, and pk9 for the ninth other node).
+template <int NB, bool P2, typename T>
 __global__ __launch_bounds__(PBT) void k_assemble_pages_long(const int32_t* __restrict__ lrows,
                                                              const int32_t* __restrict__ row_ptr,
                                                              const int32_t* __restrict__ aptr,
                                                              const int32_t* __restrict__ adj,
                                                              const uint32_t* __restrict__ pk,
+                                                             const uint64_t* __restrict__ pk2,
+                                                             const uint8_t* __restrict__ pk9,
                                                              const int32_t* __restrict__ dpos,
                                                              const T* __restrict__ pagesK, const T* __restrict__ pagesM,
                                                              T* __restrict__ valsK, T* __restrict__ valsM) {
+    static_assert(P2 ? NB <= 10 : NB <= 4, "P2 long rows: 8-bit positions of up to nine other nodes");
     using G = LongGrid;
     __shared__ uint32_t mxK[CSR_LCAP], mxM[CSR_LCAP];
     __shared__ int32_t shK[CSR_LCAP], shM[CSR_LCAP];
@@ -234,12 +241,16 @@ __global__ __launch_bounds__(PBT) void k_assemble_pages_long(const int32_t* __re
     __syncthreads();
     auto entry = [&](int j, double (&kv)[NB], double (&mv)[NB], int (&sl)[NB]) {
         const int32_t w = adj[a0 + j];
-        const uint32_t p = pk[a0 + j];
-        const int64_t e = static_cast<uint32_t>(w) >> 2;
-        const int a = w & 3;
+        const uint64_t p = P2 ? pk2[a0 + j] : static_cast<uint64_t>(pk[a0 + j]);
+        const int p9 = P2 && NB == 10 ? pk9[a0 + j] : 0;
+        const int64_t e = static_cast<uint32_t>(w) >> (P2 ? 4 : 2);
+        const int a = w & (P2 ? 15 : 3);
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            sl[b] = b == a ? sd : static_cast<int>((p >> (2 + 8 * (b < a ? b : b - 1))) & 255);
+            const int k = b < a ? b : b - 1;  // index among the other nodes
+            const int pos = P2 ? (k == 8 ? p9 : static_cast<int>((p >> (8 * k)) & 255))
+                               : static_cast<int>((p >> (2 + 8 * k)) & 255);
+            sl[b] = b == a ? sd : pos;
             const int64_t idx = e * (NB * NB) + a * NB + b;  // column a, entry b
             kv[b] = pagesK ? static_cast<double>(pagesK[idx]) : 0.0;
             mv[b] = pagesM ? static_cast<double>(pagesM[idx]) : 0.0;
@@ -318,6 +329,14 @@ void launch_pages(const CsrView& v, int pr, const void* pK, const void* pM, void
     else launch_pages_rows<NB, P2, T, 4>(v, pK, pM, vK, vM, s);
 }
 
+template <int NB, bool P2, typename T>
+void launch_pages_long(const CsrView& v, unsigned g, const void* pK, const void* pM, void* vK, void* vM,
+                       hipStream_t s) {
+    hipLaunchKernelGGL((k_assemble_pages_long<NB, P2, T>), dim3(g), dim3(PBT), 0, s, v.lrows, v.row_ptr, v.aptr, v.adj,
+                       v.pk, v.pk2, v.pk9, v.dpos, static_cast<const T*>(pK), static_cast<const T*>(pM),
+                       static_cast<T*>(vK), static_cast<T*>(vM));
+}
+
 }  // namespace pf
 
 using namespace pf;
@@ -355,28 +374,25 @@ pf_status pf_csr_assemble_pages(const pf_csr* csr, pf_dtype prec, const void* pa
         default:
             return fail(PF_EINVAL, "pf_csr_assemble_pages: unsupported element");
     }
-    if (v.nlong > 0) {  // the long rows (P1), one workgroup each
+    if (v.nlong > 0) {  // the long rows, one workgroup each
         const unsigned g = static_cast<unsigned>(v.nlong);
-        if (v.nlb == 3) {
-            if (f32)
-                hipLaunchKernelGGL((k_assemble_pages_long<3, float>), dim3(g), dim3(PBT), 0, s, v.lrows, v.row_ptr,
-                                   v.aptr, v.adj, v.pk, v.dpos, static_cast<const float*>(pK),
-                                   static_cast<const float*>(pM), static_cast<float*>(valsK), static_cast<float*>(valsM));
-            else
-                hipLaunchKernelGGL((k_assemble_pages_long<3, double>), dim3(g), dim3(PBT), 0, s, v.lrows, v.row_ptr,
-                                   v.aptr, v.adj, v.pk, v.dpos, static_cast<const double*>(pK),
-                                   static_cast<const double*>(pM), static_cast<double*>(valsK),
-                                   static_cast<double*>(valsM));
-        } else {
-            if (f32)
-                hipLaunchKernelGGL((k_assemble_pages_long<4, float>), dim3(g), dim3(PBT), 0, s, v.lrows, v.row_ptr,
-                                   v.aptr, v.adj, v.pk, v.dpos, static_cast<const float*>(pK),
-                                   static_cast<const float*>(pM), static_cast<float*>(valsK), static_cast<float*>(valsM));
-            else
-                hipLaunchKernelGGL((k_assemble_pages_long<4, double>), dim3(g), dim3(PBT), 0, s, v.lrows, v.row_ptr,
-                                   v.aptr, v.adj, v.pk, v.dpos, static_cast<const double*>(pK),
-                                   static_cast<const double*>(pM), static_cast<double*>(valsK),
-                                   static_cast<double*>(valsM));
+        switch (v.nlb) {
+            case 3:
+                f32 ? launch_pages_long<3, false, float>(v, g, pK, pM, valsK, valsM, s)
+                    : launch_pages_long<3, false, double>(v, g, pK, pM, valsK, valsM, s);
+                break;
+            case 4:
+                f32 ? launch_pages_long<4, false, float>(v, g, pK, pM, valsK, valsM, s)
+                    : launch_pages_long<4, false, double>(v, g, pK, pM, valsK, valsM, s);
+                break;
+            case 6:
+                f32 ? launch_pages_long<6, true, float>(v, g, pK, pM, valsK, valsM, s)
+                    : launch_pages_long<6, true, double>(v, g, pK, pM, valsK, valsM, s);
+                break;
+            default:
+                f32 ? launch_pages_long<10, true, float>(v, g, pK, pM, valsK, valsM, s)
+                    : launch_pages_long<10, true, double>(v, g, pK, pM, valsK, valsM, s);
+                break;
         }
     }
     return launch_check("pf_csr_assemble_pages");

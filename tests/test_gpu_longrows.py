@@ -239,12 +239,67 @@ def test_long_rows_deterministic(lib):
     assert np.array_equal(ka, kp) and np.array_equal(ma, mp)
 
 
+def p2_meshes():
+    """P2 meshes (one node per edge midpoint) with long rows: a centre vertex in 80 tets (a
+    row of 205 nonzeros), one in 60 tets whose row of 155 nonzeros overflows the 128-slot
+    tables, a 2-D centre in 70 triangles (211 nonzeros); each after a Kuhn block, and
+    renumbered."""
+    base = {"p2star40": with_block(*star3d(40, 3), n=2), "p2star30": with_block(*star3d(30, 7), n=2),
+            "p2fan70": with_block(*fan2d(70, 1), n=4)}
+    out = {}
+    for name, (c, e) in base.items():
+        c2, e2, _ = gen.p2_mesh(c, e)
+        out[name] = (c2, e2)
+        out[name + "_perm"] = renumber(c2, e2, 13)
+    return out
+
+
+P2_MESHES = p2_meshes()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("name", list(P2_MESHES))
+def test_p2_long_rows(lib, name, dtype):
+    """sparse() of P2 element pages on meshes with long rows: the structure equals the
+    oracle's sparse() pattern bit for bit (long rows listed), the values the oracle's exact
+    sums of the same pages within the tolerance; the same pages again give the same bits."""
+    say("p2 long rows", name, dtype)
+    c2, e2 = P2_MESHES[name]
+    dim, nn = c2.shape[1], c2.shape[0]
+    rK, rM = oracle.stroud_rule(dim, 2), oracle.stroud_rule(dim, 3)
+    pages = oracle.p2_elements(c2, e2, rK, rM)
+    K = pages["K3D"].astype(np.float32).astype(np.float64) if dtype == torch.float32 else pages["K3D"]
+    M = pages["M3D"].astype(np.float32).astype(np.float64) if dtype == torch.float32 else pages["M3D"]
+    ref = oracle.assemble(e2, nn, K, M)
+    lens, counts = np.diff(ref["row_ptr"]), np.bincount(e2.ravel(), minlength=nn)
+    assert np.any((counts > 64) | (lens > 128))  # the mesh has P2 long rows
+    csr = lib.Csr().symbolic_p2(dim, nn, dev(e2))
+    _, nnz, _, _ = csr.info()
+    rp, ci = (host(t) for t in csr.structure())
+    assert np.array_equal(rp, ref["row_ptr"]) and np.array_equal(ci, ref["col_idx"])
+    tK, tM = dev(K.ravel(), dtype), dev(M.ravel(), dtype)
+    outs = []
+    for _ in range(2):
+        vK = torch.empty(nnz, dtype=dtype, device="cuda")
+        vM = torch.empty(nnz, dtype=dtype, device="cuda")
+        csr.assemble_pages(prec_of(dtype), tK, tM, vK, vM)
+        outs.append((host(vK), host(vM)))
+    within(outs[0][0], ref["valK"], ref["scaleK"], TOL[dtype], f"{name} P2 K")
+    within(outs[0][1], ref["valM"], ref["scaleM"], TOL[dtype], f"{name} P2 M")
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    csr.close()
+
+
 def test_row_beyond_256_nonzeros_is_refused(lib):
     """A long row holds at most 256 nonzeros (8-bit column positions of the slot words)."""
     say("long row limit")
     coords, elems = fan2d(300, 7)
     with pytest.raises(lib.PagefemError) as ei:
         lib.Csr().symbolic(2, coords.shape[0], dev(elems))
+    assert ei.value.code == 7
+    c2, e2, _ = gen.p2_mesh(*fan2d(100, 7))  # a P2 centre row of 301 nonzeros
+    with pytest.raises(lib.PagefemError) as ei:
+        lib.Csr().symbolic_p2(2, c2.shape[0], dev(e2))
     assert ei.value.code == 7
     coords, elems = fan2d(255, 8)  # a row of 256 nonzeros is still accepted
     csr, got = _gpu(lib, coords, elems, torch.float64)
