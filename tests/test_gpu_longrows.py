@@ -290,6 +290,45 @@ def test_p2_long_rows(lib, name, dtype):
     csr.close()
 
 
+def test_rebuilds_with_and_without_long_rows(lib):
+    """One handle rebuilt in turn for P2 meshes with long rows, without, and P1 meshes with
+    and without (the speculative column phase, the long-row list, the ninth-position bytes
+    and the face lists carried over from the previous build): every structure, sparse() of
+    the oracle's pages and the face lists equal the oracle's."""
+    say("long-row rebuilds")
+    c3, e3, _ = cube(3)
+    p2cube = gen.p2_mesh(c3, e3)[:2]
+    seq = [("p2", P2_MESHES["p2star40"]), ("p2", p2cube), ("p1", MESHES["star80"]), ("p2", P2_MESHES["p2fan70"]),
+           ("p1", (c3, e3)), ("p2", P2_MESHES["p2star30_perm"]), ("p1", MESHES["fan70_perm"])]
+    csr = lib.Csr()
+    for kind, (c, e) in seq:
+        dim, nn = c.shape[1], c.shape[0]
+        if kind == "p2":
+            rK, rM = oracle.stroud_rule(dim, 2), oracle.stroud_rule(dim, 3)
+            pages = oracle.p2_elements(c, e, rK, rM)
+            K, M = pages["K3D"], pages["M3D"]
+            csr.symbolic_p2(dim, nn, dev(e))
+        else:
+            el = oracle.p1_elements(c, e)
+            K, M = el["Ke"], el["Me"]
+            csr.symbolic(dim, nn, dev(e))
+        ref = oracle.assemble(e, nn, K, M)
+        _, nnz, _, _ = csr.info()
+        rp, ci = (host(t) for t in csr.structure())
+        assert np.array_equal(rp, ref["row_ptr"]) and np.array_equal(ci, ref["col_idx"]), kind
+        vK = torch.empty(nnz, dtype=torch.float64, device="cuda")
+        vM = torch.empty(nnz, dtype=torch.float64, device="cuda")
+        csr.assemble_pages(lib.F64, dev(K.ravel()), dev(M.ravel()), vK, vM)
+        within(host(vK), ref["valK"], ref["scaleK"], TOL[torch.float64], f"rebuild {kind} K")
+        within(host(vM), ref["valM"], ref["scaleM"], TOL[torch.float64], f"rebuild {kind} M")
+        if kind == "p1":
+            csr.faces(dev(c), dev(e))
+            F, FE = oracle.faces(c, e)
+            f, fe, _, _ = (host(t) for t in csr.face_lists())
+            assert np.array_equal(f, F) and np.array_equal(fe, FE)
+    csr.close()
+
+
 def test_row_beyond_256_nonzeros_is_refused(lib):
     """A long row holds at most 256 nonzeros (8-bit column positions of the slot words)."""
     say("long row limit")
