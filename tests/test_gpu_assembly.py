@@ -221,6 +221,47 @@ def test_cfg3_full_size_fp32(lib):
     assert abs(got["valM"].astype(np.float64).sum() - 1.0) < 1e-5
 
 
+def test_eight_times_full_size_fp32(lib):
+    """256^3 cubes x 6 tets: 100,663,296 tets, 16,974,593 nodes, 402,653,184 adjacency
+    entries and 253,036,801 nonzeros (8x the 128^3 workload, the largest tested): the whole
+    structure against the closed-form pattern, oracle values on sampled rows, and K 1 = 0,
+    1^T M 1 = 1 over all rows (summed on the device)."""
+    n = 256
+    h = 1.0 / n
+    say("8x full size")
+    coords, elems, _ = gen.cube_mesh(n, jitter=0.15, with_faces=False)
+    nn = coords.shape[0]
+    tc, te = dev(coords), dev(elems)
+    csr = lib.Csr().symbolic(3, nn, te)
+    _, nnz, _, _ = csr.info()
+    assert nnz == gen.kuhn_counts(n)["nnz"]
+    vk = torch.empty(nnz, dtype=torch.float32, device="cuda")
+    vm = torch.empty(nnz, dtype=torch.float32, device="cuda")
+    ctr = counters()
+    csr.assemble(lib.F32, tc, te, vk, vm, fb=lib.fallback(1e-3 * h ** 3, 1e6, True), counters=ctr)
+    rp, ci = csr.structure()
+    krp, kci = kuhn_pattern(n)
+    rph = host(rp).astype(np.int64)
+    assert np.array_equal(rph, krp) and np.array_equal(host(ci), kci)
+    del krp, kci
+    assert host(ctr)[0] == 0 and host(ctr)[2] == 0
+    row_of = torch.repeat_interleave(torch.arange(nn, device="cuda"), (rp[1:] - rp[:-1]).long())
+    k64 = vk.double()
+    rs = torch.zeros(nn, dtype=torch.float64, device="cuda").index_add_(0, row_of, k64)
+    ra = torch.zeros(nn, dtype=torch.float64, device="cuda").index_add_(0, row_of, k64.abs())
+    assert bool((rs.abs() <= 1e-5 * ra).all())
+    assert abs(float(vm.double().sum()) - 1.0) < 1e-5
+    del row_of, k64, rs, ra
+    g = np.random.default_rng(13)
+    rows = np.unique(np.concatenate([g.choice(nn, 64, replace=False), [0, nn // 2, nn - 1]])).astype(np.int32)
+    for r, (cols, rk, rm, sk, sm) in zip(rows, oracle.assemble_rows(coords, elems, rows)):
+        a, b = int(rph[r]), int(rph[r + 1])
+        assert np.array_equal(host(ci[a:b]), cols), f"row {r} pattern"
+        within(host(vk[a:b]), rk, sk, TOL[torch.float32], f"K row {r}")
+        within(host(vm[a:b]), rm, sm, TOL[torch.float32], f"M row {r}")
+    csr.close()
+
+
 def test_cfg3_sliver_variant(lib):
     """The 128^3 mesh plus 4,096 isolated slivers (det in [1e-6, 1e-3] h^3): exactly the
     slivers are routed to FP64, and their rows match the oracle."""
