@@ -17,6 +17,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pf_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# PF_ORACLE_LIB: an oracle library built elsewhere (the tests that plant mistakes in a copy
+# of pf_oracle.c and check that the pins catch them load their build through it)
+_ALT = os.environ.get("PF_ORACLE_LIB")
 _lib = None
 
 
@@ -34,9 +37,12 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build()
-        lib = C.CDLL(_LIB)
+        if _ALT:
+            lib = C.CDLL(_ALT)
+        else:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build()
+            lib = C.CDLL(_LIB)
         P = C.c_void_p
         I64 = C.c_int64
         INT = C.c_int

@@ -1,0 +1,83 @@
+"""The oracle's pins against planted mistakes: each case copies pf_oracle.c, plants one
+plausible mistake (a wrong sign, index, term, weight or transposed operand), builds the
+copy with the oracle's flags and runs the pin suite (tests/test_oracle.py) against it in a
+fresh process.  Every planted mistake must make some pin fail; the unchanged copy, built
+the same way, must pass them all.  CPU only."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+SRC = os.path.join(ROOT, "oracle", "pf_oracle.c")
+PINS = os.path.join(HERE, "test_oracle.py")
+CFLAGS = ["-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-w"]
+
+# (what is wrong, text of pf_oracle.c, the mistaken text)
+MUTATIONS = [
+    ("permutation sign reversed (Leibniz)",
+     "if (p[a] > p[b]) s = -s;", "if (p[a] < p[b]) s = -s;"),
+    ("inverse written transposed",
+     "AT(inv, n, r, c) = (double)m[r][n + c];", "AT(inv, n, c, r) = (double)m[r][n + c];"),
+    ("page transpose copies instead",
+     "AT(tk, cols, c, r) = AT(ak, rows, r, c);", "AT(tk, rows, r, c) = AT(ak, rows, r, c);"),
+    ("product reads B transposed",
+     "double bv = transB ? AT(bk, n, j, p) : AT(bk, kk, p, j);",
+     "double bv = transB ? AT(bk, n, j, p) : AT(bk, kk, j % kk, p % n);"),
+    ("P1 gradients with the transposed inverse Jacobian",
+     "double dphi[12]; /* tjac^{-1} * dshape : dim x nlb */\n        for (int r = 0; r < dim; r++)\n"
+     "            for (int j = 0; j < nlb; j++) {\n                double acc = 0.0;\n"
+     "                for (int p = 0; p < dim; p++) acc += AT(tinv, dim, r, p) * AT(ds, dim, p, j);",
+     "double dphi[12]; /* tjac^{-1} * dshape : dim x nlb */\n        for (int r = 0; r < dim; r++)\n"
+     "            for (int j = 0; j < nlb; j++) {\n                double acc = 0.0;\n"
+     "                for (int p = 0; p < dim; p++) acc += AT(tinv, dim, p, r) * AT(ds, dim, p, j);"),
+    ("stiffness off-diagonal halved",
+     "if (Ke) Ke[e * nlb * nlb + a + b * nlb] = w1 * adet * acc;",
+     "if (Ke) Ke[e * nlb * nlb + a + b * nlb] = w1 * adet * acc * (a == b ? 1.0 : 0.5);"),
+    ("mass integrand uses phi_a twice",
+     "for (int q = 0; q < nq; q++) m += wq[q] * adet * lam[q][a] * lam[q][b];",
+     "for (int q = 0; q < nq; q++) m += wq[q] * adet * lam[q][a] * lam[q][a];"),
+    ("mass rule point moved",
+     "double a = (5.0 + 3.0 * sqrt(5.0)) / 20.0", "double a = (5.0 + 2.0 * sqrt(5.0)) / 20.0"),
+    ("centroid rule weight wrong in 3-D",
+     "w[0] = (dim == 2) ? 0.5 : 1.0 / 6.0;", "w[0] = (dim == 2) ? 0.5 : 1.0 / 4.0;"),
+    ("sparse() keeps the last contribution instead of the sum",
+     "if (Ke) { sk += Ke[p];", "if (Ke) { sk = Ke[p];"),
+    ("a face of the tetrahedron listed with reversed orientation",
+     "{{1, 2, 3}, {0, 3, 2}, {0, 1, 3}, {0, 2, 1}}", "{{1, 2, 3}, {0, 2, 3}, {0, 1, 3}, {0, 2, 1}}"),
+    ("integration point with the wrong coordinate",
+     "x += lam[q * nv + j] * coords[v * dim + i];", "x += lam[q * nv + j] * coords[v * dim + (i + 1) % dim];"),
+    ("GI without the rule's weights",
+     "for (int q = 0; q < nq; q++) s += w[q] * fip[(c * nq + q) * d + i];",
+     "for (int q = 0; q < nq; q++) s += fip[(c * nq + q) * d + i];"),
+    ("P2 vertex function wrong",
+     "phi[i] = lam[i] * (2.0 * lam[i] - 1.0);", "phi[i] = lam[i] * (2.0 * lam[i] - 0.5);"),
+    ("P2 edge gradient loses a term",
+     "gphi[r + t * dim] = 4.0 * (lam[i] * glam[r + j * dim] + lam[j] * glam[r + i * dim]);",
+     "gphi[r + t * dim] = 4.0 * (lam[i] * glam[r + j * dim]);"),
+]
+
+
+def _run_pins(tmp_path, source):
+    c = tmp_path / "pf_oracle_copy.c"
+    c.write_text(source)
+    so = tmp_path / "liboracle_copy.so"
+    subprocess.run(["gcc", *CFLAGS, "-o", str(so), str(c), "-lm"], check=True)
+    env = dict(os.environ, PF_ORACLE_LIB=str(so))
+    return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
+                           PINS], cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
+
+
+def test_unchanged_copy_passes_every_pin(tmp_path):
+    r = _run_pins(tmp_path, open(SRC).read())
+    assert r.returncode == 0, r.stdout[-2000:]
+
+
+@pytest.mark.parametrize("what,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_planted_mistake_fails_a_pin(tmp_path, what, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"the text to mutate is not unique: {old}"
+    r = _run_pins(tmp_path, src.replace(old, new))
+    assert r.returncode == 1, f"planted mistake passed every pin ({what}):\n{r.stdout[-1500:]}"
