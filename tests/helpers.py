@@ -63,6 +63,15 @@ def square(n, jitter=0.2):
     return gen.square_mesh(n, jitter=jitter)
 
 
+def flip_half(elems, seed=7):
+    """The mesh with half its elements (seeded choice) given local nodes 1 and 2 swapped:
+    det J < 0 for those (the generators orient every element positively)."""
+    flip = np.random.default_rng(seed).random(len(elems)) < 0.5
+    e = np.array(elems, copy=True)
+    e[flip, 1], e[flip, 2] = elems[flip, 2], elems[flip, 1]
+    return e
+
+
 def kuhn_pattern(n):
     """CSR pattern of the Kuhn cube mesh of n^3 cubes, from its closed form (no elements):
     node v and v + d are joined by an edge iff d or -d is a nonzero 0/1 vector and both

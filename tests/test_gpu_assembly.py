@@ -6,7 +6,7 @@ import pytest
 import torch
 
 import oracle
-from helpers import TOL, counters, cube, dev, host, kuhn_pattern, prec_of, say, square, within
+from helpers import TOL, counters, cube, dev, flip_half, host, kuhn_pattern, prec_of, say, square, within
 from paper_2404_16039_amd import gen
 
 pytestmark = pytest.mark.gpu
@@ -82,6 +82,19 @@ def test_cube_small_full(lib, dtype, n):
     got = _assemble(lib, coords, elems, dtype, cK, cM)
     assert got["nnz"] == gen.kuhn_counts(n)["nnz"]
     _compare_full(got, _full_oracle(coords, elems, cK, cM), dtype)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_negatively_oriented_elements(lib, dtype, dim):
+    """Half the elements with det J < 0: every entry of K and M against the oracle, and no
+    element routed to FP64 on account of its sign."""
+    say("assemble flipped", dim, dtype)
+    coords, elems, _ = cube(5) if dim == 3 else square(9)
+    elems = flip_half(elems)
+    got = _assemble(lib, coords, elems, dtype)
+    _compare_full(got, _full_oracle(coords, elems), dtype)
+    assert got["ctr"][0] == 0 and got["ctr"][2] == 0
 
 
 def test_deterministic_and_handle_reuse(lib):

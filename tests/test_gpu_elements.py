@@ -5,7 +5,7 @@ import pytest
 import torch
 
 import oracle
-from helpers import TOL, counters, cube, dev, host, prec_of, say, square, within
+from helpers import TOL, counters, cube, dev, flip_half, host, prec_of, say, square, within
 from paper_2404_16039_amd import gen
 
 pytestmark = pytest.mark.gpu
@@ -66,6 +66,20 @@ def test_square_mesh_cfg1(lib, dtype):
     assert res["ctr"][0] == 0 and res["ctr"][1] == 0 and not res["flags"].any()
     tol_sum = 1e-12 if dtype == torch.float64 else 1e-5
     assert abs(res["vol"].astype(np.float64).sum() - 1.0) < tol_sum
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_negatively_oriented_elements(lib, dtype, dim):
+    """Half the elements with det J < 0: signed determinants, volumes, gradients, normals,
+    facets and K3D/M3D against the oracle."""
+    say("elements flipped", dim, dtype)
+    coords, elems, _ = cube(4) if dim == 3 else square(6)
+    elems = flip_half(elems)
+    res = _run_elements(lib, coords, elems, dtype)
+    _check_against_oracle(res, coords, elems, dtype)
+    assert (res["det"][:, 0] < 0).any() and (res["det"][:, 0] > 0).any()
+    assert res["ctr"][0] == 0 and not res["flags"].any()
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])

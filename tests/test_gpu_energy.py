@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import oracle
-from helpers import TOL, counters, cube, dev, host, prec_of, say, square, within
+from helpers import TOL, counters, cube, dev, flip_half, host, prec_of, say, square, within
 from paper_2404_16039_amd import gen
 
 pytestmark = pytest.mark.gpu
@@ -76,6 +76,27 @@ def test_rhs_and_energies_parity(lib, dtype, dim, order):
         want = got["J"][c].astype(np.float64).sum()
         assert abs(got["tot"][c] - want) <= 1e-12 * np.abs(got["J"][c]).sum() + 1e-300, (k, got["tot"][c], want)
     assert got["ctr"][2] == 0
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_rhs_and_energies_negatively_oriented(lib, dtype):
+    """Half the tetrahedra with det J < 0: local vectors, node sums and the energy parts
+    against the oracle."""
+    say("rhs/energies flipped", dtype)
+    coords, elems, _ = cube(5)
+    elems = flip_half(elems)
+    xq = oracle.quad_points(coords, elems, 2)
+    f, cK, cM = (_rounded(v, dtype) for v in _fields(xq, 3))
+    u = _rounded(np.cos(2.0 * coords[:, 0]) + coords[:, 1] ** 2 - 0.3 * coords[:, -1], dtype)
+    got = _gpu_rhs_energies(lib, coords, elems, dtype, 2, f, cK, cM, u)
+    tol = TOL[dtype]
+    r = oracle.rhs_p1(coords, elems, 2, f)
+    rabs = oracle.rhs_p1(coords, elems, 2, np.abs(f))
+    within(got["b2D"], r["b2D"], rabs["b2D"], tol, "b2D")
+    within(got["b"], r["b"], r["babs"], tol, "b")
+    J = oracle.local_energies(coords, elems, 2, u, cKq=cK, cMq=cM, b2D=_rounded(got["b2D"], dtype))
+    for c, k in enumerate(("J1", "J2", "J3")):
+        within(got["J"][c], J[k + "k"], J[k + "abs"], tol, k)
 
 
 def test_rhs_deterministic_across_adjacency_orders(lib):

@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import oracle
-from helpers import TOL, cube, dev, host, say, square
+from helpers import TOL, cube, dev, flip_half, host, say, square
 from paper_2404_16039_amd import gen
 
 pytestmark = pytest.mark.gpu
@@ -32,13 +32,18 @@ def _gpu_faces(L, coords, elems):
     return f, fe, bf, be
 
 
-@pytest.mark.parametrize("mesh", ["cube1", "cube2", "cube5", "square6", "cube4_perm", "square5_perm"])
+@pytest.mark.parametrize("mesh", ["cube1", "cube2", "cube5", "square6", "cube4_perm", "square5_perm", "cube4_flip",
+                                  "square5_flip"])
 def test_faces_match_oracle(lib, mesh):
+    """_perm: a random node numbering; _flip: half the elements with two local nodes swapped
+    (det J < 0), so the faces' node order follows the element's orientation."""
     say("faces", mesh)
     base, perm = mesh.split("_")[0], mesh.endswith("_perm")
     coords, elems, _ = cube(int(base[4:])) if base.startswith("cube") else square(int(base[6:]))
     if perm:
         coords, elems, _, _ = gen.permute_nodes(coords, elems)
+    if mesh.endswith("_flip"):
+        elems = flip_half(elems)
     f, fe, bf, be = _gpu_faces(lib, coords, elems)
     F, FE = oracle.faces(coords, elems)
     assert np.array_equal(f, F) and np.array_equal(fe, FE)

@@ -844,6 +844,23 @@ def test_faces_counts_orientation_and_neighbours(n):
     assert np.all(((c2 - c1) * rawi).sum(axis=1) > 0)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_faces_outward_of_negatively_oriented_elements(dim):
+    """Half the elements with two local nodes swapped (det J < 0): every face's node order
+    still gives a normal pointing out of its first element, i.e. away from that element's
+    centroid (a geometric check, independent of the local face tables)."""
+    coords, elems, _ = gen.cube_mesh(2, jitter=0.15) if dim == 3 else gen.square_mesh(3, jitter=0.2)
+    e = elems.copy()
+    flip = np.random.default_rng(7).random(len(e)) < 0.5
+    assert flip.any() and (~flip).any()
+    e[flip, 1], e[flip, 2] = elems[flip, 2], elems[flip, 1]
+    F, FE = oracle.faces(coords, e)
+    _, _, raw = oracle.boundary(coords, F)
+    c1 = coords[e[FE[:, 0]]].mean(axis=1)
+    fc = coords[F].mean(axis=1)
+    assert np.all(((fc - c1) * raw).sum(axis=1) > 0)
+
+
 def test_faces_2d_edges():
     coords, elems, bedges = gen.square_mesh(4, jitter=0.2)
     F, FE = oracle.faces(coords, elems)

@@ -57,6 +57,35 @@ MUTATIONS = [
     ("P2 edge gradient loses a term",
      "gphi[r + t * dim] = 4.0 * (lam[i] * glam[r + j * dim] + lam[j] * glam[r + i * dim]);",
      "gphi[r + t * dim] = 4.0 * (lam[i] * glam[r + j * dim]);"),
+    ("element integration point with the wrong coordinate",
+     "x += lam[q][j] * coords[node * dim + i];", "x += lam[q][j] * coords[node * dim + (i + 1) % dim];"),
+    ("stiffness coefficient squared",
+     "k += wq[q] * ck * adet * gg;", "k += wq[q] * ck * ck * adet * gg;"),
+    ("mass coefficient dropped",
+     "m += wq[q] * cm * adet * lam[q][a] * lam[q][b];", "m += wq[q] * adet * lam[q][a] * lam[q][b];"),
+    ("det-condition from the second row",
+     "s += fabs(AT(a, dim, 0, j) * cof);", "s += fabs(AT(a, dim, 1, j) * cof);"),
+    ("edge vectors of coords3D reversed",
+     "vectors3d[e * dim * (nlb - 1) + i + j * dim] = coords[node * dim + i] - coords[last * dim + i];",
+     "vectors3d[e * dim * (nlb - 1) + i + j * dim] = coords[last * dim + i] - coords[node * dim + i];"),
+    ("page scaling by the first page's scalar",
+     "c[k * ps + q] = s[k] * a[k * ps + q];", "c[k * ps + q] = s[0] * a[k * ps + q];"),
+    ("bilinear form with A transposed",
+     "acc += u[k * n + i] * AT(ak, n, i, j) * v[k * n + j];", "acc += u[k * n + i] * AT(ak, n, j, i) * v[k * n + j];"),
+    ("determinant scale without absolute values",
+     "pabs *= fabs(AT(a, n, i, p[i]));", "pabs *= AT(a, n, i, p[i]);"),
+    ("boundary normal: wrong sign of one component (3-D)",
+     "n[1] = u[2] * v[0] - u[0] * v[2];", "n[1] = u[0] * v[2] - u[2] * v[0];"),
+    ("boundary normal: wrong sign of one component (2-D)",
+     "n[1] = coords[ia * 2] - coords[ib * 2];", "n[1] = coords[ib * 2] - coords[ia * 2];"),
+    ("load vector with the first basis function only",
+     "v += wq[q] * adet * fq[e * nq + q] * lam[q][j];", "v += wq[q] * adet * fq[e * nq + q] * lam[q][0];"),
+    ("face's second element repeats the first",
+     "fel[nf * 2 + 1] = (j - i == 2) ? (int32_t)all[i + 1].e : -1;",
+     "fel[nf * 2 + 1] = (j - i == 2) ? (int32_t)all[i].e : -1;"),
+    ("face orientation ignores the element's orientation",
+     "FACE3[f->k][det < 0 ? nv - 1 - t : t] : FACE2[f->k][det < 0 ? nv - 1 - t : t]",
+     "FACE3[f->k][t] : FACE2[f->k][t]"),
 ]
 
 
