@@ -6,8 +6,7 @@ the same way, must pass them all.  CPU only."""
 import os
 import subprocess
 import sys
-
-import pytest
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -89,24 +88,29 @@ MUTATIONS = [
 ]
 
 
-def _run_pins(tmp_path, source):
-    c = tmp_path / "pf_oracle_copy.c"
-    c.write_text(source)
-    so = tmp_path / "liboracle_copy.so"
-    subprocess.run(["gcc", *CFLAGS, "-o", str(so), str(c), "-lm"], check=True)
-    env = dict(os.environ, PF_ORACLE_LIB=str(so))
+def _run_pins(workdir, tag, source):
+    c = os.path.join(workdir, f"pf_oracle_{tag}.c")
+    with open(c, "w") as f:
+        f.write(source)
+    so = os.path.join(workdir, f"liboracle_{tag}.so")
+    subprocess.run(["gcc", *CFLAGS, "-o", so, c, "-lm"], check=True)
+    env = dict(os.environ, PF_ORACLE_LIB=so)
     return subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu",
                            PINS], cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
 
 
 def test_unchanged_copy_passes_every_pin(tmp_path):
-    r = _run_pins(tmp_path, open(SRC).read())
+    r = _run_pins(str(tmp_path), "copy", open(SRC).read())
     assert r.returncode == 0, r.stdout[-2000:]
 
 
-@pytest.mark.parametrize("what,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
-def test_planted_mistake_fails_a_pin(tmp_path, what, old, new):
+def test_every_planted_mistake_fails_a_pin(tmp_path):
+    """All mutants at once, several pin runs in parallel (each in its own process)."""
     src = open(SRC).read()
-    assert src.count(old) == 1, f"the text to mutate is not unique: {old}"
-    r = _run_pins(tmp_path, src.replace(old, new))
-    assert r.returncode == 1, f"planted mistake passed every pin ({what}):\n{r.stdout[-1500:]}"
+    for what, old, _ in MUTATIONS:
+        assert src.count(old) == 1, f"the text to mutate is not unique ({what}): {old}"
+    jobs = [(i, what, src.replace(old, new)) for i, (what, old, new) in enumerate(MUTATIONS)]
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as pool:
+        results = list(pool.map(lambda j: (j[1], _run_pins(str(tmp_path), str(j[0]), j[2])), jobs))
+    survivors = [what for what, r in results if r.returncode != 1]
+    assert not survivors, f"planted mistakes that passed every pin: {survivors}"
