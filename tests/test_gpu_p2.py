@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import oracle
-from helpers import TOL, counters, cube, dev, host, pair_pattern, prec_of, say, square, within
+from helpers import TOL, counters, cube, dev, flip_half, host, pair_pattern, prec_of, say, square, within
 from paper_2404_16039_amd import gen
 
 pytestmark = pytest.mark.gpu
@@ -34,9 +34,14 @@ def _gpu_p2(L, coords2, elems2, dtype, ruleK, ruleM, cK=None, cM=None):
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("dim", [2, 3])
-def test_p2_parity(lib, dtype, dim):
-    say("p2 parity", dim, dtype)
+@pytest.mark.parametrize("flip", [False, True])
+def test_p2_parity(lib, dtype, dim, flip):
+    """flip: half the elements with det J < 0 (vertices 1 and 2 swapped before the mid-edge
+    nodes are added)."""
+    say("p2 parity", dim, dtype, flip)
     coords, elems, _ = square(9) if dim == 2 else cube(5)
+    if flip:
+        elems = flip_half(elems)
     c2, e2, _ = gen.p2_mesh(coords, elems)
     rK, rM = oracle.stroud_rule(dim, 2), oracle.stroud_rule(dim, 3)
     xK = oracle.simplex_points(coords, elems, rK[0])

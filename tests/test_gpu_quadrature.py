@@ -10,7 +10,7 @@ import pytest
 import torch
 
 import oracle
-from helpers import TOL, counters, dev, host, prec_of, say, within
+from helpers import TOL, counters, dev, flip_half, host, prec_of, say, within
 from paper_2404_16039_amd import gen
 
 pytestmark = pytest.mark.gpu
@@ -57,9 +57,13 @@ def _gpu_quad(L, coords, elems, dtype, order, fb=None):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("order", [1, 2])
 @pytest.mark.parametrize("dim,n", [(2, 12), (3, 5)])
-def test_quadrature_assembly_matches_oracle(lib, dtype, order, dim, n):
-    say("quadrature assembly", dtype, order, dim, n)
+@pytest.mark.parametrize("flip", [False, True])
+def test_quadrature_assembly_matches_oracle(lib, dtype, order, dim, n, flip):
+    """flip: half the elements with det J < 0."""
+    say("quadrature assembly", dtype, order, dim, n, flip)
     coords, elems, _ = (gen.square_mesh(n) if dim == 2 else gen.cube_mesh(n))
+    if flip:
+        elems = flip_half(elems)
     got = _gpu_quad(lib, coords, elems, dtype, order)
     xq = oracle.quad_points(coords, elems, order)
     assert np.array_equal(got["xq"], xq), "integration points differ from the oracle's"
