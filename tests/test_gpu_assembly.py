@@ -153,6 +153,20 @@ def test_node_permutation_invariance(lib):
         assert np.array_equal(a["valM"][sa][order], b["valM"][sb])
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_element_order_invariance(lib, dtype):
+    """The elements listed in a random order (each keeping its local node order) give the
+    same structure and the same K and M, bit for bit: every entry is an exact sum, so the
+    order in which the adjacency meets the elements does not matter."""
+    say("element order", dtype)
+    coords, elems, _ = cube(6)
+    e2 = elems[np.random.default_rng(21).permutation(len(elems))]
+    a = _assemble(lib, coords, elems, dtype)
+    b = _assemble(lib, coords, e2, dtype)
+    assert np.array_equal(a["row_ptr"], b["row_ptr"]) and np.array_equal(a["col_idx"], b["col_idx"])
+    assert np.array_equal(a["valK"], b["valK"]) and np.array_equal(a["valM"], b["valM"])
+
+
 def test_edge_cases(lib):
     say("edge cases")
     # one element
