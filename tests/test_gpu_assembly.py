@@ -154,6 +154,18 @@ def test_node_permutation_invariance(lib):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_mesh_far_from_the_origin(lib, dtype, dim):
+    """The mesh translated by ~3e4: every entry of K and M against the oracle (the edge
+    vectors are FP64 differences of the coordinates, rounded once)."""
+    say("assemble translated", dim, dtype)
+    coords, elems, _ = cube(5) if dim == 3 else square(9)
+    coords = coords + np.array([1.7e4, -3.1e4, 2.3e4][:dim])
+    got = _assemble(lib, coords, elems, dtype)
+    _compare_full(got, _full_oracle(coords, elems), dtype)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_element_order_invariance(lib, dtype):
     """The elements listed in a random order (each keeping its local node order) give the
     same structure and the same K and M, bit for bit: every entry is an exact sum, so the

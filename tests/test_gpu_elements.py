@@ -83,6 +83,19 @@ def test_negatively_oriented_elements(lib, dtype, dim):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_mesh_far_from_the_origin(lib, dtype, dim):
+    """The mesh translated by ~3e4 (about 2.5e5 element sizes): edge vectors are FP64
+    differences rounded once, so FP32 results keep the tolerance (FP32 coordinates would
+    lose about 3e-3 of an edge here)."""
+    say("elements translated", dim, dtype)
+    coords, elems, _ = cube(4) if dim == 3 else square(6)
+    coords = coords + np.array([1.7e4, -3.1e4, 2.3e4][:dim])
+    res = _run_elements(lib, coords, elems, dtype)
+    _check_against_oracle(res, coords, elems, dtype)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_cube_mesh_with_coefficients(lib, dtype):
     say("elements cube 6", dtype)
     coords, elems, _ = cube(6)
