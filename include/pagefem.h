@@ -77,8 +77,13 @@ typedef struct pf_pages {
 /* FP64 routing of the FP32 path: a page/element is recomputed in FP64 when its FP32
  * determinant (compensated) satisfies |det| < tau_abs, or its det-condition
  * sum_j |a_0j C_0j| / |det| (expansion along the first row) exceeds tau_cond, or det is
- * zero (infinite det-condition) or not finite.  enable = 0 turns routing off.  A NULL pf_fallback* means
- * {tau_abs = 0, tau_cond = 1e6, enable = 1}.  Ignored on the FP64 path.               */
+ * zero (infinite det-condition) or not finite.  Elements (the P1 geometry of every element
+ * kernel, P2 included, and of assembly) are in addition routed when their vertex shape seen
+ * from their first node, sigma = prod_k |p_k - p_0| / |det J|, exceeds 16: the FP32 error of
+ * the gradients and of K relative to |grad phi_a| |grad phi_b| grows as ~7 sigma u_32, which
+ * this keeps below 1e-5 on meshes of any shape (a fixed threshold, not an argument; sigma is
+ * at most 6.5 on jittered Kuhn meshes).  enable = 0 turns routing off.  A NULL pf_fallback*
+ * means {tau_abs = 0, tau_cond = 1e6, enable = 1}.  Ignored on the FP64 path.           */
 typedef struct pf_fallback {
     double tau_abs;
     double tau_cond;

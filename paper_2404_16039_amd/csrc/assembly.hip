@@ -1795,9 +1795,12 @@ __device__ __forceinline__ void origin_row_f64(const double (&u)[DIM][DIM], doub
 // FP32 routing test with thresholds already rounded to FP32: route unless 0 < |det| < inf,
 // |det| >= tau_abs and absterms <= tau_cond |det| (a NaN fails every comparison, so NaN
 // det or absterms route; an infinite absterms with finite det fails the last test)
-__device__ __forceinline__ bool route32(float det, float absterms, float tau_abs, float tau_cond, int enable) {
+__device__ __forceinline__ bool route32(float det, float absterms, double shape2, float tau_abs, float tau_cond,
+                                        int enable) {
     const float ad = fabsf(det);
-    const bool keep = ad > 0.0f && ad < __builtin_huge_valf() && ad >= tau_abs && absterms <= tau_cond * ad;
+    const double d = ad;
+    const bool keep = ad > 0.0f && ad < __builtin_huge_valf() && ad >= tau_abs && absterms <= tau_cond * ad &&
+                      shape2 <= SHAPE_MAX * SHAPE_MAX * d * d;
     return enable && !keep;
 }
 
@@ -1942,7 +1945,7 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
         P1Geom<DIM, T> g;
         p1_geom_edges<DIM, T>(u, g);
         bool route = false;
-        if constexpr (sizeof(T) == 4) route = route32(g.det, g.absterms, tau_abs, tau_cond, fb.enable);
+        if constexpr (sizeof(T) == 4) route = route32(g.det, g.absterms, g.shape2, tau_abs, tau_cond, fb.enable);
         T adet_t = fabs(g.det);
         double adet_d = 0.0;
         if (route) {
@@ -2204,7 +2207,7 @@ __device__ __forceinline__ void numeric_block_f32(int64_t r0, int64_t nn, const 
         }
         P1Geom<DIM, float> g;
         p1_geom_edges_fast<DIM>(u, g);
-        const bool route = route32(g.det, g.absterms, tau_abs, tau_cond, fb.enable);
+        const bool route = route32(g.det, g.absterms, g.shape2, tau_abs, tau_cond, fb.enable);
         const float adet_t = fabsf(g.det);
         double adet_d = 0.0;
         if (route) {
@@ -2477,7 +2480,7 @@ __global__ __launch_bounds__(LT) void k_numeric_long(const int32_t* __restrict__
                     for (int c = 0; c < DIM; ++c) u[k][c] = static_cast<float>(ev[k][c]);
                 P1Geom<DIM, float> g;
                 p1_geom_edges_fast<DIM>(u, g);
-                if (route32(g.det, g.absterms, static_cast<float>(fb.tau_abs), static_cast<float>(fb.tau_cond),
+                if (route32(g.det, g.absterms, g.shape2, static_cast<float>(fb.tau_abs), static_cast<float>(fb.tau_cond),
                             fb.enable))
                     ++routed;
             }

@@ -120,7 +120,7 @@ __global__ __launch_bounds__(EBS) void k_elem(int64_t nn, const double* __restri
             if constexpr (sizeof(T) == 4) {
                 P1Geom<DIM, float> g;
                 p1_geom<DIM, float>(ev, g);
-                routed = should_route(g.det, g.absterms, fb);
+                routed = route_elem<DIM>(g, fb);
                 if (routed) {
                     P1Geom<DIM, double> gd;
                     p1_geom<DIM, double>(ev, gd);

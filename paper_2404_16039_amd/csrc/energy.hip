@@ -43,7 +43,7 @@ __device__ __forceinline__ double abs_det(const double (&ev)[DIM][DIM], const Fa
     if constexpr (sizeof(T) == 4) {
         P1Geom<DIM, float> g;
         p1_geom<DIM, float>(ev, g);
-        routed = should_route(g.det, g.absterms, fb);
+        routed = route_elem<DIM>(g, fb);
         if (!routed) return fabsf(g.det);
     }
     P1Geom<DIM, double> gd;
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(RBS) void k_energies(int64_t nn, const double* __re
             if constexpr (sizeof(T) == 4) {
                 P1Geom<DIM, float> g;
                 p1_geom<DIM, float>(ev, g);
-                routed = should_route(g.det, g.absterms, fb);
+                routed = route_elem<DIM>(g, fb);
                 if (!routed) {
                     float Jf[2];
                     energy_parts<DIM, QN, float>(g, uj, ck, cmq, Jf);

@@ -24,7 +24,40 @@ struct P1Geom {
     C c[DIM + 1][DIM];  // c[j] = det * grad phi_j
     C det;              // signed det J (first node origin)
     C absterms;         // sum_j |e_1j c_1j|, numerator of the det-condition
+    double shape2;      // FP32 geometry: prod_k |e_k|^2 (FP64), numerator of the squared vertex shape
 };
+
+// Vertex shape of an element seen from its origin node: sigma = prod_k |e_k| / |det J|, the
+// product of the lengths of the edges from that node over the volume factor.  sigma >= 1/sin
+// of every angle between two of those edges and bounds the cancellation in the origin node's
+// gradient -(c_1 + ... + c_d), so it bounds what the FP32 rounding of the edge vectors costs
+// the gradients and the stiffness entries relative to their scale |grad phi_a| |grad phi_b|:
+// about 7 sigma u_32.  The FP32 element paths send an element with sigma > SHAPE_MAX to FP64
+// (whenever routing is enabled), which keeps that cost below 1e-5 of the scale; sigma >= the
+// det-condition / sqrt(d), so this also covers det-conditions above ~28.  Regular elements
+// have sigma of a few units (the jittered Kuhn tetrahedra at most 6.5).
+constexpr double SHAPE_MAX = 16.0;
+
+template <int DIM, typename C>
+__device__ __forceinline__ double edge_lengths2(const C (&u)[DIM][DIM]) {
+    double p = 1.0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        C l = u[k][0] * u[k][0];
+#pragma unroll
+        for (int i = 1; i < DIM; ++i) l = fmaT(u[k][i], u[k][i], l);
+        p *= static_cast<double>(l);
+    }
+    return p;
+}
+
+// the vertex shape test of an FP32 geometry (sigma > SHAPE_MAX, FP64 comparison: no range of
+// coordinates overflows it)
+template <int DIM>
+__device__ __forceinline__ bool shape_exceeds(const P1Geom<DIM, float>& g) {
+    const double d = static_cast<double>(g.det);
+    return g.shape2 > SHAPE_MAX * SHAPE_MAX * d * d;
+}
 
 // Geometry from edge vectors already in precision C (u[k] = p_{k+1} - p_origin).
 template <int DIM, typename C>
@@ -58,6 +91,7 @@ __device__ __forceinline__ void p1_geom_edges(const C (&u)[DIM][DIM], P1Geom<DIM
         for (int j = 2; j <= DIM; ++j) s += g.c[j][i];
         g.c[0][i] = -s;
     }
+    g.shape2 = sizeof(C) == 4 ? edge_lengths2<DIM, C>(u) : 0.0;
 }
 
 // FP32 geometry for the bulk of well-shaped elements: c_1 and det are first evaluated with one
@@ -91,9 +125,17 @@ __device__ __forceinline__ void p1_geom_edges_fast(const float (&u)[DIM][DIM], P
         }
 #pragma unroll
         for (int i = 0; i < 3; ++i) g.c[0][i] = -(g.c[1][i] + g.c[2][i] + g.c[3][i]);
+        g.shape2 = edge_lengths2<DIM, float>(u);
     } else {
         p1_geom_edges<DIM, float>(u, g);
     }
+}
+
+// routing of an FP32 element geometry: pf_fallback's predicate on |det| and the det-condition,
+// or (routing enabled) a vertex shape above SHAPE_MAX
+template <int DIM>
+__device__ __forceinline__ bool route_elem(const P1Geom<DIM, float>& g, const Fallback& fb) {
+    return should_route(g.det, g.absterms, fb) || (fb.enable && shape_exceeds<DIM>(g));
 }
 
 // Geometry from FP64 edge vectors, rounded once to precision C.

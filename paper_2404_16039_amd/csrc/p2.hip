@@ -217,7 +217,7 @@ __global__ __launch_bounds__(P2BS) void k_p2_elem(int64_t nn, const double* __re
                 if constexpr (sizeof(T) == 4) {
                     P1Geom<DIM, float> g;
                     p1_geom<DIM, float>(ev, g);
-                    r = should_route(g.det, g.absterms, fb);
+                    r = route_elem<DIM>(g, fb);
                     if (!r) p2_write<DIM, float, T>(g, R, cl, cl, kp, mp);
                 }
                 if (sizeof(T) == 8 || r) {

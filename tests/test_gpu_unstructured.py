@@ -1,0 +1,142 @@
+"""Unstructured meshes: Delaunay triangulations of seeded random points (scipy's Qhull), in
+2-D and 3-D.  Unlike the generated meshes these have elements of both orientations, nodes
+of very different valence (in 3-D up to ~90 tetrahedra, so long rows), and slivers that the
+FP32 path routes to FP64.  The structure is compared bit for bit with the oracle's sparse(),
+the values, face lists, load vector, energies and P2 matrices with the oracle's."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from helpers import TOL, counters, dev, host, prec_of, say, within
+from paper_2404_16039_amd import gen
+
+pytestmark = pytest.mark.gpu
+spatial = pytest.importorskip("scipy.spatial")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2404_16039_amd import lib as L
+    return L
+
+
+def delaunay(dim, n, seed):
+    pts = np.random.default_rng(seed).random((n, dim))
+    return pts, spatial.Delaunay(pts).simplices.astype(np.int32)
+
+
+MESHES = {"delaunay3d": (3, 20000, 5), "delaunay2d": (2, 5000, 6)}
+
+
+def _mesh(name):
+    dim, n, seed = MESHES[name]
+    return delaunay(dim, n, seed)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("name", list(MESHES))
+def test_unstructured_assembly(lib, name, dtype):
+    say("unstructured assembly", name, dtype)
+    coords, elems = _mesh(name)
+    dim, nn = coords.shape[1], coords.shape[0]
+    tc, te = dev(coords), dev(elems)
+    csr = lib.Csr().symbolic(dim, nn, te)
+    _, nnz, _, _ = csr.info()
+    vk = torch.empty(nnz, dtype=dtype, device="cuda")
+    vm = torch.empty(nnz, dtype=dtype, device="cuda")
+    ctr = counters()
+    csr.assemble(prec_of(dtype), tc, te, vk, vm, counters=ctr)
+    el = oracle.p1_elements(coords, elems)
+    ref = oracle.assemble(elems, nn, el["Ke"], el["Me"], el["Kabs"])
+    rp, ci = (host(t) for t in csr.structure())
+    assert np.array_equal(rp, ref["row_ptr"]) and np.array_equal(ci, ref["col_idx"])
+    within(host(vk), ref["valK"], ref["scaleK"], TOL[dtype], f"{name} K")
+    within(host(vm), ref["valM"], ref["scaleM"], TOL[dtype], f"{name} M")
+    c = host(ctr)
+    print(name, "elements routed to FP64:", int(c[0]), "nodes in more than 64 elements:",
+          int((np.bincount(elems.ravel(), minlength=nn) > 64).sum()))
+    assert c[2] == 0
+    if dtype == torch.float32:
+        # the FP32 path routes exactly the elements whose vertex shape seen from their first
+        # node, prod_k |e_k| / |det|, exceeds 16 (away from the threshold itself)
+        e = coords[elems[:, 1:]] - coords[elems[:, :1]]
+        sigma = np.prod(np.linalg.norm(e, axis=2), axis=1) / np.abs(np.linalg.det(e))
+        lo, hi = int((sigma > 16.0 * (1 + 1e-4)).sum()), int((sigma > 16.0 * (1 - 1e-4)).sum())
+        assert lo > 0 and lo <= c[0] <= hi, (lo, int(c[0]), hi)
+    else:
+        assert c[0] == 0
+    csr.close()
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_unstructured_faces(lib, name):
+    say("unstructured faces", name)
+    coords, elems = _mesh(name)
+    te = dev(elems)
+    csr = lib.Csr().symbolic(coords.shape[1], coords.shape[0], te)
+    csr.faces(dev(coords), te)
+    f, fe, bf, be = (host(t) for t in csr.face_lists())
+    F, FE = oracle.faces(coords, elems)
+    assert np.array_equal(f, F) and np.array_equal(fe, FE)
+    b = FE[:, 1] < 0
+    assert np.array_equal(bf, F[b]) and np.array_equal(be, FE[b, 0])
+    csr.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_unstructured_rhs_and_energies(lib, dtype):
+    say("unstructured rhs/energies", dtype)
+    coords, elems = _mesh("delaunay3d")
+    nn, ne = coords.shape[0], elems.shape[0]
+    rnd = (lambda a: a.astype(np.float32).astype(np.float64)) if dtype == torch.float32 else (lambda a: a)
+    xq = oracle.quad_points(coords, elems, 2)
+    f = rnd(np.sin(3.0 * xq[..., 0]) + xq[..., 1] * xq[..., 2])
+    cK = rnd(1.0 + xq[..., 0] ** 2)
+    cM = rnd(2.0 + np.cos(xq[..., 1]))
+    u = rnd(np.cos(2.0 * coords[:, 0]) + coords[:, 1] ** 2 - 0.3 * coords[:, 2])
+    te = dev(elems)
+    csr = lib.Csr().symbolic(3, nn, te)
+    b2D = torch.empty(ne * 4, dtype=dtype, device="cuda")
+    b = torch.empty(nn, dtype=dtype, device="cuda")
+    ctr = counters()
+    csr.rhs(prec_of(dtype), dev(coords), te, 2, dev(f, dtype), b2D, b, counters=ctr)
+    J = torch.empty(3 * ne, dtype=dtype, device="cuda")
+    tot = torch.empty(3, dtype=torch.float64, device="cuda")
+    csr.energies(prec_of(dtype), dev(coords), te, 2, dev(u, dtype), cKq=dev(cK, dtype), cMq=dev(cM, dtype), b2D=b2D,
+                 J=J, totals=tot, counters=ctr)
+    r = oracle.rhs_p1(coords, elems, 2, f)
+    rabs = oracle.rhs_p1(coords, elems, 2, np.abs(f))
+    within(host(b2D), r["b2D"].ravel(), rabs["b2D"].ravel(), TOL[dtype], "b2D")
+    within(host(b), r["b"], r["babs"], TOL[dtype], "b")
+    Jr = oracle.local_energies(coords, elems, 2, u, cKq=cK, cMq=cM, b2D=rnd(host(b2D).astype(np.float64)).reshape(ne, 4))
+    Jg = host(J).reshape(3, ne)
+    for c, k in enumerate(("J1", "J2", "J3")):
+        within(Jg[c], Jr[k + "k"], Jr[k + "abs"], TOL[dtype], k)
+    assert host(ctr)[2] == 0
+    csr.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_unstructured_p2(lib, dtype):
+    """P2 of a 3-D Delaunay mesh of 3000 points: structure and sparse() of the oracle's
+    element pages."""
+    say("unstructured p2", dtype)
+    coords, elems = delaunay(3, 3000, 7)
+    c2, e2, _ = gen.p2_mesh(coords, elems)
+    nn = c2.shape[0]
+    rK, rM = oracle.stroud_rule(3, 2), oracle.stroud_rule(3, 3)
+    pages = oracle.p2_elements(c2, e2, rK, rM)
+    rnd = (lambda a: a.astype(np.float32).astype(np.float64)) if dtype == torch.float32 else (lambda a: a)
+    K, M = rnd(pages["K3D"]), rnd(pages["M3D"])
+    ref = oracle.assemble(e2, nn, K, M)
+    csr = lib.Csr().symbolic_p2(3, nn, dev(e2))
+    _, nnz, _, _ = csr.info()
+    rp, ci = (host(t) for t in csr.structure())
+    assert np.array_equal(rp, ref["row_ptr"]) and np.array_equal(ci, ref["col_idx"])
+    vK = torch.empty(nnz, dtype=dtype, device="cuda")
+    vM = torch.empty(nnz, dtype=dtype, device="cuda")
+    csr.assemble_pages(prec_of(dtype), dev(K.ravel(), dtype), dev(M.ravel(), dtype), vK, vM)
+    within(host(vK), ref["valK"], ref["scaleK"], TOL[dtype], "P2 K")
+    within(host(vM), ref["valM"], ref["scaleM"], TOL[dtype], "P2 M")
+    csr.close()
