@@ -140,3 +140,85 @@ def test_unstructured_p2(lib, dtype):
     within(host(vK), ref["valK"], ref["scaleK"], TOL[dtype], "P2 K")
     within(host(vM), ref["valM"], ref["scaleM"], TOL[dtype], "P2 M")
     csr.close()
+
+
+def _sigma(coords, elems):
+    """vertex shape seen from each element's first node: prod_k |e_k| / |det|"""
+    dim = coords.shape[1]
+    e = coords[elems[:, 1:dim + 1]] - coords[elems[:, :1]]
+    return np.prod(np.linalg.norm(e, axis=2), axis=1) / np.abs(np.linalg.det(e))
+
+
+def _routed_set_ok(routed, sigma):
+    """the FP32 path routes the elements with sigma > 16 and no other (away from 16 itself)"""
+    hi, lo = sigma > 16.0 * (1 + 1e-4), sigma < 16.0 * (1 - 1e-4)
+    assert hi.any() and routed[hi].all() and not routed[lo].any(), (int(hi.sum()), int(routed.sum()))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("name", list(MESHES))
+def test_unstructured_element_kernels(lib, name, dtype):
+    """Per-element det, volume, gradients, normals, facet measures and K/M pages of the
+    Delaunay meshes against the oracle; in FP32 the routed elements are exactly those of
+    vertex shape above 16."""
+    say("unstructured element kernels", name, dtype)
+    coords, elems = _mesh(name)
+    ne, nlb = elems.shape
+    dim = coords.shape[1]
+    tc, te = dev(coords), dev(elems)
+    out = {k: torch.empty(s, dtype=dtype, device="cuda") for k, s in
+           [("det", ne), ("vol", ne), ("grads", ne * dim * nlb), ("normals", ne * dim * nlb), ("facet", ne * nlb),
+            ("K3D", ne * nlb * nlb), ("M3D", ne * nlb * nlb)]}
+    flags = torch.zeros(ne, dtype=torch.uint8, device="cuda")
+    ctr = counters()
+    p = prec_of(dtype)
+    lib.elem_geometry(p, tc, te, det=out["det"], vol=out["vol"], grads=out["grads"], normals=out["normals"],
+                      facet=out["facet"], flags=flags, counters=ctr)
+    lib.elem_stiffness_mass(p, tc, te, K3D=out["K3D"], M3D=out["M3D"], counters=ctr)
+    res = {k: host(v).reshape(ne, -1) for k, v in out.items()}
+    tol = TOL[dtype]
+    el = oracle.p1_elements(coords, elems)
+    _, perm = oracle.page_det(oracle.jacobians(coords, elems), dim)
+    within(res["det"][:, 0], el["det"], perm, tol, "det")
+    within(res["vol"][:, 0], el["vol"], el["vol"], tol, "vol")
+    gscale = np.abs(el["grads"]).max(axis=1, keepdims=True) * np.ones_like(el["grads"])
+    within(res["grads"], el["grads"], gscale, tol, "grads")
+    within(res["normals"], -el["grads"], gscale, tol, "normals")
+    within(res["facet"], el["facet"], el["facet"], tol, "facet")
+    within(res["K3D"], el["Ke"], el["Kabs"], tol, "K3D")
+    within(res["M3D"], el["Me"], np.abs(el["Me"]), tol, "M3D")
+    routed = (host(flags) & 2).astype(bool)
+    c = host(ctr)
+    assert c[2] == 0
+    if dtype == torch.float32:
+        _routed_set_ok(routed, _sigma(coords, elems))
+        assert c[0] == 2 * routed.sum()  # geometry and stiffness/mass calls both count
+    else:
+        assert not routed.any() and c[0] == 0
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_unstructured_p2_elements(lib, dtype):
+    """P2 element stiffness and mass pages (degree-2 rule for K, degree-3 for M) of a 3-D
+    Delaunay mesh against the oracle; in FP32 the routed count is that of the vertex shapes
+    above 16."""
+    say("unstructured p2 elements", dtype)
+    coords, elems = delaunay(3, 3000, 7)
+    c2, e2, _ = gen.p2_mesh(coords, elems)
+    rK, rM = oracle.stroud_rule(3, 2), oracle.stroud_rule(3, 3)
+    ne, nb = e2.shape
+    K = torch.empty(ne * nb * nb, dtype=dtype, device="cuda")
+    M = torch.empty(ne * nb * nb, dtype=dtype, device="cuda")
+    ctr = counters()
+    lib.p2_elements(prec_of(dtype), dev(c2), dev(e2), rK, rM, K3D=K, M3D=M, counters=ctr)
+    ref = oracle.p2_elements(c2, e2, rK, rM)
+    within(host(K).reshape(ne, nb * nb), ref["K3D"], ref["Kabs"], TOL[dtype], "P2 K3D")
+    within(host(M).reshape(ne, nb * nb), ref["M3D"], ref["Mabs"], TOL[dtype], "P2 M3D")
+    c = host(ctr)
+    assert c[2] == 0
+    if dtype == torch.float32:
+        s = _sigma(c2, e2[:, :4])
+        lo, hi = int((s > 16.0 * (1 + 1e-4)).sum()), int((s > 16.0 * (1 - 1e-4)).sum())
+        assert 0 < lo <= c[0] <= hi, (lo, int(c[0]), hi)
+    else:
+        assert c[0] == 0
