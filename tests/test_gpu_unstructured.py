@@ -222,3 +222,64 @@ def test_unstructured_p2_elements(lib, dtype):
         assert 0 < lo <= c[0] <= hi, (lo, int(c[0]), hi)
     else:
         assert c[0] == 0
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_unstructured_quadrature_assembly(lib, dtype):
+    """Coefficients at the 4 points of the degree-2 rule (c = exp(x1+x2+x3)) on the 3-D
+    Delaunay mesh: integration points bitwise, K and M against the oracle."""
+    say("unstructured quadrature assembly", dtype)
+    coords, elems = _mesh("delaunay3d")
+    tc, te = dev(coords), dev(elems)
+    xq = lib.quad_points(tc, te, 2)
+    assert np.array_equal(host(xq), oracle.quad_points(coords, elems, 2))
+    cq = torch.exp(xq.sum(dim=2)).to(dtype).contiguous()
+    csr = lib.Csr().symbolic(3, coords.shape[0], te)
+    _, nnz, _, _ = csr.info()
+    vk = torch.empty(nnz, dtype=dtype, device="cuda")
+    vm = torch.empty(nnz, dtype=dtype, device="cuda")
+    ctr = counters()
+    csr.assemble_quad(prec_of(dtype), tc, 2, vk, vm, cKq=cq, cMq=cq, counters=ctr)
+    c = host(cq).astype(np.float64)
+    q = oracle.p1_elements_q(coords, elems, 2, c, c)
+    ref = oracle.assemble(elems, coords.shape[0], q["Ke"], q["Me"], q["Kabs"])
+    within(host(vk), ref["valK"], ref["scaleK"], TOL[dtype], "K")
+    within(host(vm), ref["valM"], ref["scaleM"], TOL[dtype], "M")
+    assert host(ctr)[2] == 0
+    csr.close()
+
+
+def test_unstructured_server_jobs(lib):
+    """Delaunay meshes (3-D in FP32, with long rows and routed elements; 2-D in FP64) served
+    together with a Kuhn cube in one tick: each job's values are bitwise those of the mesh
+    assembled alone, and match the oracle."""
+    say("unstructured server jobs")
+    c3, e3 = delaunay(3, 4000, 11)
+    c2, e2 = delaunay(2, 3000, 12)
+    ck, ek, _ = gen.cube_mesh(6)
+    srv = lib.Server(1 << 30, 8)
+    start = srv.now() + 0.05
+    jobs = []
+    for k, (dim, prec, c, e) in enumerate([(3, lib.F32, c3, e3), (2, lib.F64, c2, e2), (3, lib.F32, ck, ek)]):
+        ref = oracle.assemble(e, c.shape[0], *[oracle.p1_elements(c, e)[x] for x in ("Ke", "Me", "Kabs")])
+        nnz = int(ref["row_ptr"][-1])
+        dt = torch.float32 if prec == lib.F32 else torch.float64
+        vk = torch.full((nnz,), float("nan"), dtype=dt).pin_memory()
+        vm = torch.full((nnz,), float("nan"), dtype=dt).pin_memory()
+        t = srv.submit(dim, prec, torch.from_numpy(c).pin_memory(), torch.from_numpy(e).pin_memory(),
+                       topology=2000 + k, arrival=start, valsK=vk, valsM=vm)
+        jobs.append((t, dim, prec, dt, c, e, vk, vm, ref))
+    srv.drain()
+    for t, dim, prec, dt, c, e, vk, vm, ref in jobs:
+        r = srv.poll(t)
+        assert r["done"] == 1 and r["status"] == 0 and r["nnz"] == len(ref["valK"])
+        csr = lib.Csr().symbolic(dim, c.shape[0], dev(e))
+        ak = torch.empty(len(ref["valK"]), dtype=dt, device="cuda")
+        am = torch.empty_like(ak)
+        csr.assemble(prec, dev(c), None, ak, am)
+        assert np.array_equal(vk.numpy(), host(ak)) and np.array_equal(vm.numpy(), host(am)), f"job {t}"
+        csr.close()
+        within(vk.numpy(), ref["valK"], ref["scaleK"], TOL[dt], f"job {t} K")
+        within(vm.numpy(), ref["valM"], ref["scaleM"], TOL[dt], f"job {t} M")
+    assert srv.stats()["failed"] == 0
+    srv.close()
