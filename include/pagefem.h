@@ -288,7 +288,11 @@ pf_status pf_csr_stage_times(pf_csr* csr, double* ms, int64_t* calls);
  * (2^-24 of its power of two for FP32, 2^-56 for FP64), so the sum is exact and does not
  * depend on the order of the additions: the same inputs give the same bits.  Every element row is computed with that row's node as the origin of the edge
  * vectors.  prec as for the element calls; cK, cM per-element coefficients, nullable
- * (= 1).  d_counters[0] counts FP64-routed elements once each. */
+ * (= 1).  d_counters[0] counts FP64-routed elements once each (FP32 with routing enabled:
+ * each workgroup stores its count in an array of the structure, one int per 4 to 16 rows,
+ * that a second launch sums into the counter; calls on one structure whose numeric phases
+ * overlap in time, on two streams, share that array and may mix their routed counts, while
+ * their values are unaffected). */
 pf_status pf_assemble(const pf_csr* csr, pf_dtype prec, const double* coords, const int32_t* elems,
                       const void* cK, const void* cM, void* valsK, void* valsM,
                       const pf_fallback* fb, int64_t* d_counters, void* stream);

@@ -65,6 +65,10 @@ struct pf_csr {
     bool p2 = false;            // built from P2 elements (pf_csr_symbolic_p2)
     int64_t* bsum = nullptr;  // scan workspace
     int64_t* info = nullptr;  // [0] error bits, [1] adjacency total, [2] nnz, [3..6] block stats
+    // routed-element count of each FP32 numeric block (P1; one int per 4 rows at most), summed
+    // into the caller's counter after the launch: calls on one structure whose numeric phases
+    // overlap in time share it, so their routed counts may mix (their values do not)
+    int32_t* bcnt = nullptr;
     void* work = nullptr;     // workspace of the energy reductions (pf_energies)
     // faces (pf_csr_faces): per-row counts and their scans, the lists, and the totals
     int32_t* dpos = nullptr;   // column position of each row's diagonal
@@ -2041,7 +2045,7 @@ __device__ __forceinline__ void numeric_block(int64_t r0, int64_t nn, const doub
 template <int DIM>
 constexpr size_t numeric_lds_bytes_f32(int nr, int wmax) {
     return static_cast<size_t>(wmax) * (sizeof(Vec4<float>) + 2 * sizeof(uint64_t) + 1) +
-           static_cast<size_t>(3 * (nr + 1)) * 4;
+           static_cast<size_t>(3 * (nr + 1) + 1) * 4;
 }
 
 // FP32 numeric assembly, NR rows per block of NT threads; thread t owns row t % NR: its
@@ -2071,7 +2075,7 @@ __device__ __forceinline__ void numeric_block_f32(int64_t r0, int64_t nn, const 
                                                   const uint32_t* __restrict__ pk, const int32_t* __restrict__ dpos,
                                                   const float* __restrict__ cK, const float* __restrict__ cM,
                                                   float* __restrict__ valsK, float* __restrict__ valsM,
-                                                  const Fallback& fb, int64_t* d_counters, int wmax) {
+                                                  const Fallback& fb, int64_t* d_counters, int32_t* bcnt, int wmax) {
     constexpr int NLB = DIM + 1;
     constexpr int JS = NT / NR;  // stride of a thread's entries and slots within its row
     using G = RowGrid32;
@@ -2082,8 +2086,9 @@ __device__ __forceinline__ void numeric_block_f32(int64_t r0, int64_t nn, const 
     int32_t* rp = reinterpret_cast<int32_t*>(accM + wmax);          // [NR + 1]
     uint32_t* rmK = reinterpret_cast<uint32_t*>(rp + (NR + 1));     // [NR + 1] row maxima (bits of |x|)
     uint32_t* rmM = rmK + (NR + 1);                                 // [NR + 1]
-    uint8_t* rowof = reinterpret_cast<uint8_t*>(rmM + (NR + 1));    // [wmax] row of each slot
-    static_assert(lds_carve_aligned<Vec4<float>, uint64_t, uint64_t, int32_t, uint32_t, uint32_t, uint8_t>(),
+    int32_t* nrouted = reinterpret_cast<int32_t*>(rmM + (NR + 1));  // [1] the block's routed elements
+    uint8_t* rowof = reinterpret_cast<uint8_t*>(nrouted + 1);       // [wmax] row of each slot
+    static_assert(lds_carve_aligned<Vec4<float>, uint64_t, uint64_t, int32_t, uint32_t, uint32_t, int32_t, uint8_t>(),
                   "FP32 numeric LDS carve-out: every array naturally aligned");
     static_assert((NR & (NR - 1)) == 0 && NT % NR == 0 && NR <= 256, "a thread's items share one row");
     static_assert(NITEMS * JS >= 1, "items per row");
@@ -2117,6 +2122,7 @@ __device__ __forceinline__ void numeric_block_f32(int64_t r0, int64_t nn, const 
         rmK[t] = 0u;
         rmM[t] = 0u;
     }
+    if (t == 0) *nrouted = 0;
     __syncthreads();
     const int32_t w0 = rp[0];
     const int W = rp[nr] - w0;
@@ -2164,11 +2170,11 @@ __device__ __forceinline__ void numeric_block_f32(int64_t r0, int64_t nn, const 
             x0[c] = coords[c0 * DIM + c];
             x1[c] = coords[c1 * DIM + c];
         }
-        Vec4<float> v;
+        Vec4<float> v;  // the edge vector, and the column's node id in the fourth lane
         v.x = static_cast<float>(x0[0] - pi[0]);
         v.y = static_cast<float>(x0[1] - pi[1]);
         v.z = DIM == 3 ? static_cast<float>(x0[DIM - 1] - pi[DIM - 1]) : 0.0f;
-        v.w = 0.0f;
+        v.w = __int_as_float(static_cast<int32_t>(c0));
         f[s0 + k0] = v;
         accK[s0 + k0] = 0;
         accM[s0 + k0] = 0;
@@ -2177,6 +2183,7 @@ __device__ __forceinline__ void numeric_block_f32(int64_t r0, int64_t nn, const 
             v.x = static_cast<float>(x1[0] - pi[0]);
             v.y = static_cast<float>(x1[1] - pi[1]);
             v.z = DIM == 3 ? static_cast<float>(x1[DIM - 1] - pi[DIM - 1]) : 0.0f;
+            v.w = __int_as_float(static_cast<int32_t>(c1));
             f[s0 + k1] = v;
             accK[s0 + k1] = 0;
             accM[s0 + k1] = 0;
@@ -2198,12 +2205,14 @@ __device__ __forceinline__ void numeric_block_f32(int64_t r0, int64_t nn, const 
         const uint32_t p = pw[q];
         const float ck = ckq[q], cm = cmq0[q];
         float u[DIM][DIM];
+        int32_t cn[DIM];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             const Vec4<float> v = f[s0 + static_cast<int>((p >> (2 + 8 * k)) & 255)];
             u[k][0] = v.x;
             u[k][1] = v.y;
             if constexpr (DIM == 3) u[k][2] = v.z;
+            cn[k] = __float_as_int(v.w);
         }
         P1Geom<DIM, float> g;
         p1_geom_edges_fast<DIM>(u, g);
@@ -2212,11 +2221,12 @@ __device__ __forceinline__ void numeric_block_f32(int64_t r0, int64_t nn, const 
         double adet_d = 0.0;
         if (route) {
             // FP64 recomputation from the coordinates of the row's node (read again: a rare path
-            // that should not keep them in registers) and the three others
+            // that should not keep them in registers) and of the three others (their node ids
+            // came with the edge vectors: one round trip)
             double ev[DIM][DIM];
 #pragma unroll
             for (int k = 0; k < DIM; ++k) {
-                const int64_t col = col_idx[w0 + s0 + static_cast<int>((p >> (2 + 8 * k)) & 255)];
+                const int64_t col = cn[k];
 #pragma unroll
                 for (int c = 0; c < DIM; ++c) ev[k][c] = coords[col * DIM + c] - coords[row * DIM + c];
             }
@@ -2260,12 +2270,17 @@ __device__ __forceinline__ void numeric_block_f32(int64_t r0, int64_t nn, const 
         // when its diagonal entry kf |c_0|^2 is; the mass row carries |det| in its first entry
         finite = finite && __builtin_isfinite(kr[q][0]) && __builtin_isfinite(mr[q][0]);
     }
-    if (routed) count_add(d_counters, 0, routed);
+    if (routed) atomicAdd(nrouted, static_cast<int32_t>(routed));
     if (okq[0]) {  // items are dealt in order: a thread with any entry has its first
         atomicMax(rmK + r, finite ? G::mag(mk) : G::POISON);
         atomicMax(rmM + r, G::mag(mm));
     }
     __syncthreads();
+    if (t == 0) {  // the block's routed count: into its slot of the launch's array, else the counter
+        const int32_t nb = *nrouted;
+        if (bcnt) bcnt[blockIdx.x] = nb;
+        else if (nb) count_add(d_counters, 0, nb);
+    }
 
     // phase 1b: every contribution onto its row's grid, exact integer sums
     const uint32_t mKr = rmK[r];
@@ -2331,9 +2346,28 @@ __global__ __launch_bounds__(NT, (numeric32_waves<QN, COEF, NR>())) void k_numer
     const int32_t* __restrict__ col_idx, const int32_t* __restrict__ aptr, const int32_t* __restrict__ adj,
     const uint32_t* __restrict__ pk, const int32_t* __restrict__ dpos, const float* __restrict__ cK,
     const float* __restrict__ cM, float* __restrict__ valsK, float* __restrict__ valsM, Fallback fb,
-    int64_t* d_counters, int wmax) {
+    int64_t* d_counters, int32_t* bcnt, int wmax) {
     numeric_block_f32<DIM, COEF, NR, NT, QN>(static_cast<int64_t>(blockIdx.x) * NR, nn, coords, row_ptr, col_idx,
-                                             aptr, adj, pk, dpos, cK, cM, valsK, valsM, fb, d_counters, wmax);
+                                             aptr, adj, pk, dpos, cK, cM, valsK, valsM, fb, d_counters, bcnt, wmax);
+}
+
+// the sum of a launch's per-block counts into one counter: 1024 counts per block (four
+// independent loads per thread), one atomic per block of this kernel instead of one per
+// block of the counting launch
+constexpr int SUM_COUNTS_PER_BLOCK = 1024;
+__global__ __launch_bounds__(256) void k_sum_counts(const int32_t* __restrict__ c, int64_t n, int64_t* d_counters,
+                                                    int which) {
+    __shared__ int64_t part[4];
+    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * SUM_COUNTS_PER_BLOCK + threadIdx.x;
+    int32_t x[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = i0 + 256 * k < n ? c[i0 + 256 * k] : 0;
+    int64_t v = static_cast<int64_t>(x[0]) + x[1] + x[2] + x[3];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) count_add(d_counters, which, part[0] + part[1] + part[2] + part[3]);
 }
 
 // block b of a multi-mesh launch belongs to the job whose block range holds b
@@ -2367,7 +2401,7 @@ __global__ __launch_bounds__(NT, (numeric32_waves<0, false, NR>())) void k_numer
     const NumericJob& j = job_of_block(jobs, njobs, b);
     numeric_block_f32<DIM, false, NR, NT>((b - j.block0) * NR, j.nn, j.coords, j.row_ptr, j.col_idx, j.aptr,
                                           j.adj, j.pk, j.dpos, nullptr, nullptr, static_cast<float*>(j.valsK),
-                                          static_cast<float*>(j.valsM), j.fb, j.counters, wmax);
+                                          static_cast<float*>(j.valsM), j.fb, j.counters, nullptr, wmax);
 }
 
 // ---------------------------------------------------------------------------- long rows, numeric
@@ -2743,10 +2777,19 @@ pf_status launch_numeric32(const pf_csr* c, const double* coords, const void* cK
     const int wmax = window_of(c, NR);
     const size_t shm = numeric_lds_bytes_f32<DIM>(NR, wmax);
     const unsigned g = static_cast<unsigned>(ceil_div(c->nn, NR));
+    // routed counts: every block stores its own in the structure's array of block counts, which
+    // one more launch sums (blocks that all add to the one counter serialise on it where many
+    // elements route)
+    int32_t* bcnt = ctr && f.enable ? c->bcnt : nullptr;
     hipLaunchKernelGGL((k_numeric32<DIM, COEF, NR, NT32, QN>), dim3(g), dim3(NT32), shm, s, c->nn, coords, c->row_ptr,
                        c->col_idx, c->aptr, c->adj, c->pk, c->dpos, static_cast<const float*>(cK),
                        static_cast<const float*>(cM), static_cast<float*>(valsK), static_cast<float*>(valsM), f, ctr,
-                       wmax);
+                       bcnt, wmax);
+    if (bcnt) {
+        const int64_t gs = ceil_div(static_cast<int64_t>(g), SUM_COUNTS_PER_BLOCK);
+        hipLaunchKernelGGL(k_sum_counts, dim3(static_cast<unsigned>(gs < 1 ? 1 : gs)), dim3(256), 0, s, bcnt,
+                           static_cast<int64_t>(g), ctr, 0);
+    }
     return launch_check("pf_assemble");
 }
 
@@ -3105,7 +3148,8 @@ pf_status symbolic_enqueue(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, 
         const int64_t nb = std::max<int64_t>(ceil_div(nn + 1, SCAN_TILE), 1);
         const int64_t b_rows = part(4 * (nn + 1)), b_adj = part(4 * m), b_pk = part((p2 ? 8 : 4) * m);
         const int64_t b_bsum = part(8 * nb), b_info = part(8 * INFO_WORDS);
-        if ((st = grow(c->res, c->cap_res, 3 * b_rows + b_adj + b_pk + b_bsum + b_info, s))) return st;
+        const int64_t b_bcnt = p2 ? 0 : part(4 * ceil_div(nn, 4));  // routed counts of the FP32 numeric blocks
+        if ((st = grow(c->res, c->cap_res, 3 * b_rows + b_adj + b_pk + b_bsum + b_info + b_bcnt, s))) return st;
         unsigned char* q = c->res;
         c->aptr = reinterpret_cast<int32_t*>(q);
         c->row_ptr = reinterpret_cast<int32_t*>(q + b_rows);
@@ -3116,6 +3160,7 @@ pf_status symbolic_enqueue(pf_csr* c, int dim, int nlb, int64_t nn, int64_t ne, 
         c->pk2 = p2 ? reinterpret_cast<uint64_t*>(q + b_adj) : nullptr;
         c->bsum = reinterpret_cast<int64_t*>(q + b_adj + b_pk);
         c->info = reinterpret_cast<int64_t*>(q + b_adj + b_pk + b_bsum);
+        c->bcnt = p2 ? nullptr : reinterpret_cast<int32_t*>(q + b_adj + b_pk + b_bsum + b_info);
     }
     const int64_t tiles = ceil_div(nn, SCAN_TILE);
     {

@@ -44,6 +44,7 @@ STREAM_SERVE = 8
 STREAM_PERM = 9
 STREAM_FAN = 10
 STREAM_SERVE_PAGES = 11
+STREAM_DELAUNAY = 12
 
 
 def rng(stream: int, sub: int | None = None) -> np.random.Generator:
@@ -333,6 +334,38 @@ def permute_nodes(coords: np.ndarray, elems: np.ndarray, faces=None, stream: int
     e2 = perm[elems].astype(np.int32)
     f2 = None if faces is None else perm[faces].astype(np.int32)
     return c2, e2, f2, perm
+
+
+def _morton_code(q: np.ndarray) -> np.ndarray:
+    """Z-order key of integer grid coordinates q (npts, dim), 21 bits per axis."""
+    def spread(v, dim):
+        v = v.astype(np.uint64) & np.uint64((1 << 21) - 1)
+        out = np.zeros_like(v)
+        for b in range(21):
+            out |= ((v >> np.uint64(b)) & np.uint64(1)) << np.uint64(dim * b)
+        return out
+    dim = q.shape[1]
+    code = np.zeros(q.shape[0], dtype=np.uint64)
+    for a in range(dim):
+        code |= spread(q[:, a], dim) << np.uint64(a)
+    return code
+
+
+def delaunay_mesh(npts: int, dim: int = 3, stream: int = STREAM_DELAUNAY, sub: int | None = None):
+    """Unstructured mesh: the Delaunay triangulation (scipy's Qhull) of npts uniform random
+    points in the unit square/cube.  Nodes are numbered along a Z-order curve of the points
+    and elements sorted by their smallest node, the locality a mesh generator's reordering
+    gives; elements keep Qhull's vertex order, so both orientations occur.  About 6.7 tets
+    (3-D) or 2 triangles (2-D) per point.  Returns (coords, elems)."""
+    from scipy.spatial import Delaunay
+
+    pts = rng(stream, sub).random((npts, dim))
+    code = _morton_code(np.minimum((pts * (1 << 21)).astype(np.int64), (1 << 21) - 1))
+    order = np.argsort(code, kind="stable")
+    coords = np.ascontiguousarray(pts[order])
+    elems = Delaunay(coords).simplices.astype(np.int32)
+    elems = elems[np.argsort(elems.min(axis=1), kind="stable")]
+    return coords, np.ascontiguousarray(elems)
 
 
 # --------------------------------------------------------------------------------------

@@ -472,6 +472,26 @@ def test_mesh_counts_match_paper_levels():
     assert rows  # fixture parsed
 
 
+def test_delaunay_mesh_generator():
+    """The unstructured input: a valid triangulation of its points (every tet of nonzero
+    volume, volumes summing to that of the points' convex hull), nodes numbered in Z-order,
+    elements sorted by their smallest node, and reproducible from its seed."""
+    spatial = pytest.importorskip("scipy.spatial")
+    c, e = gen.delaunay_mesh(3000, 3)
+    c2, e2 = gen.delaunay_mesh(3000, 3)
+    assert np.array_equal(c, c2) and np.array_equal(e, e2)
+    assert e.dtype == np.int32 and e.min() == 0 and e.max() == 2999
+    d = np.linalg.det(c[e[:, 1:]] - c[e[:, :1]])
+    assert (d != 0).all() and (d > 0).any() and (d < 0).any()
+    assert abs(np.abs(d).sum() / 6 - spatial.ConvexHull(c).volume) < 1e-12
+    q = np.minimum((c * (1 << 21)).astype(np.int64), (1 << 21) - 1)
+    code = gen._morton_code(q)
+    assert (np.diff(code.astype(np.float64)) >= 0).all()
+    assert (np.diff(e.min(axis=1)) >= 0).all()
+    # Z-order of three points by hand: x is the lowest interleaved bit, then y, then z
+    assert list(gen._morton_code(np.array([[1, 0, 0], [0, 1, 0], [0, 0, 1], [3, 0, 0]]))) == [1, 2, 4, 9]
+
+
 @pytest.mark.parametrize("n", [1, 2, 3])
 def test_kuhn_mesh_brute_force_faces(n):
     coords, elems, faces = gen.cube_mesh(n, jitter=0.15)
