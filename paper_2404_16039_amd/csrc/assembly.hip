@@ -1133,17 +1133,39 @@ __device__ __forceinline__ bool is_long_row(int elements, int nonzeros) { return
 // every entry (element << ash | local index) of a long row's node (diagonal position -1) at
 // aptr[node] + a cursor; the cursor is the node's row length, which the row-block pass left
 // at 0 for long rows
+// (four consecutive entries per thread and pass when elems is 16-byte aligned: one 16-byte
+// load, then the four diagonal-position gathers in flight together)
+__device__ __forceinline__ void long_adj_entry(int64_t t, int32_t node, int nlb, int ash,
+                                               const int32_t* __restrict__ aptr, int32_t* __restrict__ cur,
+                                               int32_t* __restrict__ adjc) {
+    const int64_t e = t / nlb;
+    const int a = static_cast<int>(t - e * nlb);
+    const int pos = atomicAdd(cur + node, 1);
+    adjc[aptr[node] + pos] = static_cast<int32_t>((e << ash) | a);
+}
+
 __global__ __launch_bounds__(SBS) void k_long_adj(const int32_t* __restrict__ elems, int64_t m, int nlb, int ash,
                                                   const int32_t* __restrict__ dpos, const int32_t* __restrict__ aptr,
                                                   int32_t* __restrict__ cur, int32_t* __restrict__ adjc) {
-    for (int64_t t = static_cast<int64_t>(blockIdx.x) * SBS + threadIdx.x; t < m;
-         t += static_cast<int64_t>(gridDim.x) * SBS) {
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * SBS;
+    int64_t t0 = 0;
+    if ((reinterpret_cast<uintptr_t>(elems) & 15) == 0) {
+        const int64_t m4 = m >> 2;
+        for (int64_t q = static_cast<int64_t>(blockIdx.x) * SBS + threadIdx.x; q < m4; q += stride) {
+            const int4 v = reinterpret_cast<const int4*>(elems)[q];
+            const int32_t nd[4] = {v.x, v.y, v.z, v.w};
+            int32_t dp[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) dp[k] = dpos[nd[k]];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (dp[k] == -1) long_adj_entry(4 * q + k, nd[k], nlb, ash, aptr, cur, adjc);
+        }
+        t0 = m4 << 2;
+    }
+    for (int64_t t = t0 + static_cast<int64_t>(blockIdx.x) * SBS + threadIdx.x; t < m; t += stride) {
         const int32_t node = elems[t];
-        if (dpos[node] != -1) continue;
-        const int64_t e = t / nlb;
-        const int a = static_cast<int>(t - e * nlb);
-        const int pos = atomicAdd(cur + node, 1);
-        adjc[aptr[node] + pos] = static_cast<int32_t>((e << ash) | a);
+        if (dpos[node] == -1) long_adj_entry(t, node, nlb, ash, aptr, cur, adjc);
     }
 }
 
@@ -3284,7 +3306,8 @@ pf_status symbolic_long(pf_csr* c, const char* who) {
     c->nlong = nlong;
     c->q_long = true;
     PF_HIP_TRY(hipMemcpyAsync(c->lrows, c->lrows_s, nlong * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_long_adj, dim3(flat_grid(m)), dim3(SBS), 0, s, c->q_elems, m, nlb, p2 ? 4 : 2, c->dpos,
+    hipLaunchKernelGGL(k_long_adj, dim3(flat_grid(ceil_div(m, 4))), dim3(SBS), 0, s, c->q_elems, m, nlb, p2 ? 4 : 2,
+                       c->dpos,
                        c->aptr, c->cnt, c->adj);
     const unsigned g = static_cast<unsigned>(nlong);
     switch (nlb) {
