@@ -2373,24 +2373,6 @@ __global__ __launch_bounds__(NT, (numeric32_waves<QN, COEF, NR>())) void k_numer
                                              aptr, adj, pk, dpos, cK, cM, valsK, valsM, fb, d_counters, bcnt, wmax);
 }
 
-// the sum of a launch's per-block counts into one counter: 1024 counts per block (four
-// independent loads per thread), one atomic per block of this kernel instead of one per
-// block of the counting launch
-constexpr int SUM_COUNTS_PER_BLOCK = 1024;
-__global__ __launch_bounds__(256) void k_sum_counts(const int32_t* __restrict__ c, int64_t n, int64_t* d_counters,
-                                                    int which) {
-    __shared__ int64_t part[4];
-    const int64_t i0 = static_cast<int64_t>(blockIdx.x) * SUM_COUNTS_PER_BLOCK + threadIdx.x;
-    int32_t x[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) x[k] = i0 + 256 * k < n ? c[i0 + 256 * k] : 0;
-    int64_t v = static_cast<int64_t>(x[0]) + x[1] + x[2] + x[3];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) count_add(d_counters, which, part[0] + part[1] + part[2] + part[3]);
-}
 
 // block b of a multi-mesh launch belongs to the job whose block range holds b
 __device__ __forceinline__ const NumericJob& job_of_block(const NumericJob* __restrict__ jobs, int njobs, int64_t b) {
@@ -2809,8 +2791,8 @@ pf_status launch_numeric32(const pf_csr* c, const double* coords, const void* cK
                        bcnt, wmax);
     if (bcnt) {
         const int64_t gs = ceil_div(static_cast<int64_t>(g), SUM_COUNTS_PER_BLOCK);
-        hipLaunchKernelGGL(k_sum_counts, dim3(static_cast<unsigned>(gs < 1 ? 1 : gs)), dim3(256), 0, s, bcnt,
-                           static_cast<int64_t>(g), ctr, 0);
+        hipLaunchKernelGGL((k_sum_counts<1>), dim3(static_cast<unsigned>(gs < 1 ? 1 : gs)), dim3(256), 0, s, bcnt,
+                           static_cast<int64_t>(g), ctr, 0, 0, 0);
     }
     return launch_check("pf_assemble");
 }
@@ -2895,6 +2877,11 @@ pf_status numeric_dispatch_quad(const pf_csr* c, const double* coords, const voi
 }
 
 }  // namespace
+
+pf_status device_scratch_borrow(int64_t bytes, hipStream_t s, unsigned char** out, bool* owned) {
+    return scratch_borrow(bytes, s, out, owned);
+}
+void device_scratch_return(unsigned char* p, bool owned, hipStream_t s) { scratch_return(p, owned, s); }
 
 // the long rows of a structure alone (the serving loop's fused launches skip them)
 pf_status numeric_long(const pf_csr* c, pf_dtype prec, const double* coords, void* valsK, void* valsM,

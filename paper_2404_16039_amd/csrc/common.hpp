@@ -167,6 +167,74 @@ __device__ __forceinline__ void count_wave(int64_t* d_counters, int which, bool 
                   static_cast<unsigned long long>(__popcll(m)));
 }
 
+// Per-workgroup counts of W integer tallies (v[k], one value per thread): each wave sums
+// its lanes, the block's waves meet in LDS, and thread 0 either stores the block's W sums at
+// bcnt[W * blockIdx.x + k] (a launch of k_sum_counts adds them to the counters afterwards:
+// no two workgroups write one word) or, with no bcnt, adds each nonzero sum to
+// d_counters[which[k]].  Every thread of the block must call it (one barrier).  Many
+// workgroups adding to the one counter address serialise on it: on meshes that route one
+// element in fifty that cost ten times the kernel itself.
+template <int W, int NT>
+__device__ __forceinline__ void block_counts(int64_t* d_counters, int32_t* bcnt, const int (&which)[W],
+                                             const int (&v)[W]) {
+    static_assert(NT % 64 == 0 && NT <= 1024, "whole waves");
+    if (!d_counters) return;  // uniform across the block
+    __shared__ int32_t wsum[NT / 64][W];
+    const int lane = static_cast<int>(threadIdx.x & 63), wv = static_cast<int>(threadIdx.x >> 6);
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        int x = v[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        if (lane == 0) wsum[wv][k] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            int32_t x = 0;
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w) x += wsum[w][k];
+            if (bcnt) bcnt[static_cast<int64_t>(W) * blockIdx.x + k] = x;
+            else if (x) count_add(d_counters, which[k], x);
+        }
+    }
+}
+
+// d_counters[w_k] += the sum over blocks b < nb of c[W b + k]: 1024 blocks' counts per
+// workgroup (four independent loads per thread and tally), one atomic per workgroup and tally
+constexpr int SUM_COUNTS_PER_BLOCK = 1024;
+template <int W>
+__global__ __launch_bounds__(256) void k_sum_counts(const int32_t* __restrict__ c, int64_t nb, int64_t* d_counters,
+                                                    int w0, int w1, int w2) {
+    __shared__ int64_t part[4][W];
+    const int64_t b0 = static_cast<int64_t>(blockIdx.x) * SUM_COUNTS_PER_BLOCK + threadIdx.x;
+    int64_t acc[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) acc[k] = 0;
+    int32_t x[4][W];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int k = 0; k < W; ++k) x[j][k] = b0 + 256 * j < nb ? c[(b0 + 256 * j) * W + k] : 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        int64_t a = static_cast<int64_t>(x[0][k]) + x[1][k] + x[2][k] + x[3][k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) a += __shfl_down(a, o);
+        acc[k] = a;
+    }
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < W; ++k) part[threadIdx.x >> 6][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int wk[3] = {w0, w1, w2};
+#pragma unroll
+        for (int k = 0; k < W; ++k) count_add(d_counters, wk[k], part[0][k] + part[1][k] + part[2][k] + part[3][k]);
+    }
+}
+
 constexpr uint8_t FLAG_SINGULAR = 1;
 constexpr uint8_t FLAG_ROUTED = 2;
 constexpr uint8_t FLAG_BADINDEX = 4;

@@ -2,6 +2,7 @@
 // boundary facet normals and measures (section 3.2).  One element (or facet) per lane.
 #include "p1elem.hpp"
 #include "quadrature.hpp"
+#include "internal.hpp"
 
 namespace pf {
 
@@ -99,7 +100,8 @@ template <int DIM, typename T>
 __global__ __launch_bounds__(EBS) void k_elem(int64_t nn, const double* __restrict__ coords, int64_t ne,
                                               const int32_t* __restrict__ elems, const T* __restrict__ cK,
                                               const T* __restrict__ cM, ElemOut o, Fallback fb,
-                                              uint8_t* __restrict__ flags, int64_t* d_counters) {
+                                              uint8_t* __restrict__ flags, int64_t* d_counters,
+                                              int32_t* __restrict__ bcnt) {
     constexpr int NLB = DIM + 1;
     constexpr int WMAX = NLB * NLB;
     __shared__ __align__(16) T buf[EBS * (WMAX + 1)];
@@ -144,9 +146,7 @@ __global__ __launch_bounds__(EBS) void k_elem(int64_t nn, const double* __restri
             flags[e] = (sing ? FLAG_SINGULAR : 0) | (routed ? FLAG_ROUTED : 0) | (bad ? FLAG_BADINDEX : 0);
     }
     okb[threadIdx.x] = (e < ne && !bad) ? 1 : 0;
-    count_wave(d_counters, 0, routed);
-    count_wave(d_counters, 1, sing);
-    count_wave(d_counters, 2, bad);
+    block_counts<3, EBS>(d_counters, bcnt, {0, 1, 2}, {routed ? 1 : 0, sing ? 1 : 0, bad ? 1 : 0});
     // the multi-value outputs, one array at a time through LDS (the requests are the same for
     // the whole block)
     if (o.grads) stage_store<DIM * NLB, T>(static_cast<T*>(o.grads), e0, nloc, v.grad, buf, okb);
@@ -263,8 +263,12 @@ pf_status check_mesh(int dim, int64_t nn, const double* coords, int64_t ne, cons
 template <int DIM, typename T>
 pf_status launch_elem(int64_t nn, const double* coords, int64_t ne, const int32_t* elems, const void* cK,
                       const void* cM, const ElemOut& o, Fallback fb, uint8_t* flags, int64_t* ctr, hipStream_t s) {
-    hipLaunchKernelGGL((k_elem<DIM, T>), dim3(static_cast<unsigned>(ceil_div(ne, EBS))), dim3(EBS), 0, s, nn, coords,
-                       ne, elems, static_cast<const T*>(cK), static_cast<const T*>(cM), o, fb, flags, ctr);
+    const int64_t g = ceil_div(ne, EBS);
+    BlockCountSlots<3> cs;
+    if (pf_status st = cs.init(ctr, g, s)) return st;
+    hipLaunchKernelGGL((k_elem<DIM, T>), dim3(static_cast<unsigned>(g)), dim3(EBS), 0, s, nn, coords, ne, elems,
+                       static_cast<const T*>(cK), static_cast<const T*>(cM), o, fb, flags, ctr, cs.slots());
+    cs.finish(ctr, s, 0, 1, 2);
     return launch_check("element kernel");
 }
 

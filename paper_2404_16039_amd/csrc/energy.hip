@@ -56,7 +56,8 @@ __device__ __forceinline__ double abs_det(const double (&ev)[DIM][DIM], const Fa
 template <int DIM, typename T, int QN>
 __global__ __launch_bounds__(RBS) void k_rhs_elem(int64_t nn, const double* __restrict__ coords, int64_t ne,
                                                   const int32_t* __restrict__ elems, const T* __restrict__ fq,
-                                                  T* __restrict__ b2D, Fallback fb, int64_t* d_counters) {
+                                                  T* __restrict__ b2D, Fallback fb, int64_t* d_counters,
+                                                  int32_t* __restrict__ bcnt) {
     constexpr int NLB = DIM + 1;
     const int64_t e = static_cast<int64_t>(blockIdx.x) * RBS + threadIdx.x;
     bool routed = false, bad = false;
@@ -83,8 +84,7 @@ __global__ __launch_bounds__(RBS) void k_rhs_elem(int64_t nn, const double* __re
                 b2D[e * NLB + j] = routed ? static_cast<T>(ad * static_cast<double>(s[j])) : static_cast<T>(ad) * s[j];
         }
     }
-    count_wave(d_counters, 0, routed);
-    count_wave(d_counters, 2, bad);
+    block_counts<2, RBS>(d_counters, bcnt, {0, 2}, {routed ? 1 : 0, bad ? 1 : 0});
 }
 
 // b[i] = sum of the entries of the elements around node i, exact on the grid of the node's
@@ -268,8 +268,8 @@ __global__ __launch_bounds__(RBS) void k_energies(int64_t nn, const double* __re
             sum[c] += static_cast<double>(v);  // the totals add the stored values
         }
     }
-    if (nrouted) count_add(d_counters, 0, nrouted);
-    if (nbad) count_add(d_counters, 2, nbad);
+    // one atomic per workgroup and tally (at most ETOT_BLOCKS workgroups)
+    block_counts<2, RBS>(d_counters, nullptr, {0, 2}, {static_cast<int>(nrouted), static_cast<int>(nbad)});
     // fixed-order block reduction: wave tree (xor shuffles), then the waves in order
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -306,16 +306,20 @@ pf_status check_csr_mesh(const pf_csr* csr, const double* coords, const int32_t*
 }
 
 template <int DIM, typename T>
-void launch_rhs_elem(int qn, int64_t nn, const double* coords, int64_t ne, const int32_t* elems, const void* fq,
-                     void* b2D, Fallback f, int64_t* ctr, hipStream_t s) {
+pf_status launch_rhs_elem(int qn, int64_t nn, const double* coords, int64_t ne, const int32_t* elems, const void* fq,
+                          void* b2D, Fallback f, int64_t* ctr, hipStream_t s) {
     const unsigned g = static_cast<unsigned>(ceil_div(ne, RBS));
     constexpr int Q2 = DIM == 2 ? 3 : 4;
+    BlockCountSlots<2> cs;
+    if (pf_status st = cs.init(ctr, g, s)) return st;
     if (qn == 1)
         hipLaunchKernelGGL((k_rhs_elem<DIM, T, 1>), dim3(g), dim3(RBS), 0, s, nn, coords, ne, elems,
-                           static_cast<const T*>(fq), static_cast<T*>(b2D), f, ctr);
+                           static_cast<const T*>(fq), static_cast<T*>(b2D), f, ctr, cs.slots());
     else
         hipLaunchKernelGGL((k_rhs_elem<DIM, T, Q2>), dim3(g), dim3(RBS), 0, s, nn, coords, ne, elems,
-                           static_cast<const T*>(fq), static_cast<T*>(b2D), f, ctr);
+                           static_cast<const T*>(fq), static_cast<T*>(b2D), f, ctr, cs.slots());
+    cs.finish(ctr, s, 0, 2);
+    return PF_OK;
 }
 
 template <int DIM, typename T>
@@ -352,13 +356,13 @@ pf_status pf_rhs(const pf_csr* csr, pf_dtype prec, const double* coords, const i
     if ((st = csr_order(csr, s))) return st;
     const Fallback f = make_fallback(fb);
     if (ne > 0) {
-        if (dim == 3) {
-            if (prec == PF_F32) launch_rhs_elem<3, float>(qn, nn, coords, ne, elems, fq, b2D, f, d_counters, s);
-            else launch_rhs_elem<3, double>(qn, nn, coords, ne, elems, fq, b2D, f, d_counters, s);
-        } else {
-            if (prec == PF_F32) launch_rhs_elem<2, float>(qn, nn, coords, ne, elems, fq, b2D, f, d_counters, s);
-            else launch_rhs_elem<2, double>(qn, nn, coords, ne, elems, fq, b2D, f, d_counters, s);
-        }
+        if (dim == 3)
+            st = prec == PF_F32 ? launch_rhs_elem<3, float>(qn, nn, coords, ne, elems, fq, b2D, f, d_counters, s)
+                                : launch_rhs_elem<3, double>(qn, nn, coords, ne, elems, fq, b2D, f, d_counters, s);
+        else
+            st = prec == PF_F32 ? launch_rhs_elem<2, float>(qn, nn, coords, ne, elems, fq, b2D, f, d_counters, s)
+                                : launch_rhs_elem<2, double>(qn, nn, coords, ne, elems, fq, b2D, f, d_counters, s);
+        if (st) return st;
         if ((st = launch_check("pf_rhs elements"))) return st;
     }
     if (b && nn > 0) {

@@ -13,6 +13,7 @@
 // phi_a phi_b is summed point by point.  G comes from the P1 cofactors (grad lam_k = c_k /
 // det) in the working precision, with the FP64 recomputation of routed elements.
 #include "p1elem.hpp"
+#include "internal.hpp"
 
 #include <string>
 
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(P2BS) void k_p2_elem(int64_t nn, const double* __re
                                                   const int32_t* __restrict__ elems2, P2Rules R,
                                                   const T* __restrict__ cKq, const T* __restrict__ cMq,
                                                   T* __restrict__ K3D, T* __restrict__ M3D, Fallback fb,
-                                                  int64_t* d_counters) {
+                                                  int64_t* d_counters, int32_t* __restrict__ bcnt) {
     constexpr int NB = P2Local<DIM>::NB;
     constexpr int PS = NB * (NB + 1) / 2;  // staging stride of one page (its lower triangle)
     static_assert(PS % 2 == 1, "an odd stride spreads the lanes over the banks");
@@ -255,8 +256,7 @@ __global__ __launch_bounds__(P2BS) void k_p2_elem(int64_t nn, const double* __re
         }
         __syncthreads();
     }
-    count_wave(d_counters, 0, routed);
-    count_wave(d_counters, 2, bad && e < ne);
+    block_counts<2, P2BS>(d_counters, bcnt, {0, 2}, {routed ? 1 : 0, (bad && e < ne) ? 1 : 0});
 }
 
 }  // namespace pf
@@ -291,24 +291,28 @@ pf_status pf_p2_elements(int dim, pf_dtype prec, int64_t nn, const double* coord
     hipStream_t s = as_stream(stream);
     const Fallback f = make_fallback(fb);
     const unsigned g = static_cast<unsigned>(ceil_div(ne, P2BS));
+    BlockCountSlots<2> cs;
+    if (pf_status st = cs.init(d_counters, g, s)) return st;
+    int32_t* bc = cs.slots();
     if (dim == 3) {
         if (prec == PF_F32)
             hipLaunchKernelGGL((k_p2_elem<3, float>), dim3(g), dim3(P2BS), 0, s, nn, coords, ne, elems2, R,
                                static_cast<const float*>(cKq), static_cast<const float*>(cMq),
-                               static_cast<float*>(K3D), static_cast<float*>(M3D), f, d_counters);
+                               static_cast<float*>(K3D), static_cast<float*>(M3D), f, d_counters, bc);
         else
             hipLaunchKernelGGL((k_p2_elem<3, double>), dim3(g), dim3(P2BS), 0, s, nn, coords, ne, elems2, R,
                                static_cast<const double*>(cKq), static_cast<const double*>(cMq),
-                               static_cast<double*>(K3D), static_cast<double*>(M3D), f, d_counters);
+                               static_cast<double*>(K3D), static_cast<double*>(M3D), f, d_counters, bc);
     } else {
         if (prec == PF_F32)
             hipLaunchKernelGGL((k_p2_elem<2, float>), dim3(g), dim3(P2BS), 0, s, nn, coords, ne, elems2, R,
                                static_cast<const float*>(cKq), static_cast<const float*>(cMq),
-                               static_cast<float*>(K3D), static_cast<float*>(M3D), f, d_counters);
+                               static_cast<float*>(K3D), static_cast<float*>(M3D), f, d_counters, bc);
         else
             hipLaunchKernelGGL((k_p2_elem<2, double>), dim3(g), dim3(P2BS), 0, s, nn, coords, ne, elems2, R,
                                static_cast<const double*>(cKq), static_cast<const double*>(cMq),
-                               static_cast<double*>(K3D), static_cast<double*>(M3D), f, d_counters);
+                               static_cast<double*>(K3D), static_cast<double*>(M3D), f, d_counters, bc);
     }
+    cs.finish(d_counters, s, 0, 2);
     return launch_check("pf_p2_elements");
 }
