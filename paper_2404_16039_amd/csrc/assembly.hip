@@ -2878,10 +2878,16 @@ pf_status numeric_dispatch_quad(const pf_csr* c, const double* coords, const voi
 
 }  // namespace
 
-pf_status device_scratch_borrow(int64_t bytes, hipStream_t s, unsigned char** out, bool* owned) {
-    return scratch_borrow(bytes, s, out, owned);
+pf_status device_pool_alloc(int64_t bytes, hipStream_t s, void** out) {
+    hipMemPool_t pool = nullptr;
+    if (pf_status st = pool_of_current(&pool)) return st;
+    const hipError_t e = hipMallocFromPoolAsync(out, static_cast<size_t>(bytes), pool, s);
+    if (e != hipSuccess) return fail(PF_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+    return PF_OK;
 }
-void device_scratch_return(unsigned char* p, bool owned, hipStream_t s) { scratch_return(p, owned, s); }
+void device_pool_free(void* p, hipStream_t s) {
+    if (p) (void)hipFreeAsync(p, s);
+}
 
 // the long rows of a structure alone (the serving loop's fused launches skip them)
 pf_status numeric_long(const pf_csr* c, pf_dtype prec, const double* coords, void* valsK, void* valsM,

@@ -97,31 +97,29 @@ int csr_symbolic_poll(pf_csr* c, pf_status* st);
 // needed)
 pf_status csr_workspace(pf_csr* c, int64_t words, double** out, hipStream_t s);
 
-// device scratch of the current device's build arena (or of the stream-ordered pool when the
-// arena is in use), handed back once the work enqueued on s so far is done
-pf_status device_scratch_borrow(int64_t bytes, hipStream_t s, unsigned char** out, bool* owned);
-void device_scratch_return(unsigned char* p, bool owned, hipStream_t s);
+// a stream-ordered block of the library's device pool, and its release on a stream
+pf_status device_pool_alloc(int64_t bytes, hipStream_t s, void** out);
+void device_pool_free(void* p, hipStream_t s);
 
-// Per-workgroup count slots for one launch of nb workgroups and W tallies (block_counts),
-// borrowed only when the caller asked for counters; finish() sums them into the counters
-// (k_sum_counts) and hands the scratch back.
+// Per-workgroup count slots for one launch of nb workgroups and W tallies (block_counts), a
+// stream-ordered pool block taken only when the caller asked for counters; finish() sums
+// them into the counters (k_sum_counts) and releases the block on the same stream.
 template <int W>
 struct BlockCountSlots {
-    unsigned char* p = nullptr;
-    bool owned = false;
+    void* p = nullptr;
     int64_t nb = 0;
     pf_status init(const int64_t* d_counters, int64_t nblocks, hipStream_t s) {
         nb = nblocks;
         if (!d_counters || nblocks <= 0) return PF_OK;
-        return device_scratch_borrow(static_cast<int64_t>(W) * 4 * nblocks, s, &p, &owned);
+        return device_pool_alloc(static_cast<int64_t>(W) * 4 * nblocks, s, &p);
     }
-    int32_t* slots() const { return reinterpret_cast<int32_t*>(p); }
+    int32_t* slots() const { return static_cast<int32_t*>(p); }
     void finish(int64_t* d_counters, hipStream_t s, int w0, int w1 = 0, int w2 = 0) {
         if (!p) return;
         const int64_t g = (nb + SUM_COUNTS_PER_BLOCK - 1) / SUM_COUNTS_PER_BLOCK;
         hipLaunchKernelGGL((k_sum_counts<W>), dim3(static_cast<unsigned>(g)), dim3(256), 0, s, slots(), nb,
                            d_counters, w0, w1, w2);
-        device_scratch_return(p, owned, s);
+        device_pool_free(p, s);
         p = nullptr;
     }
 };
