@@ -38,7 +38,11 @@
  *    nodes at elems[e*nlb .. e*nlb+nlb-1]); coordinates are float64, row-major nn x dim.
  *  - Device counters (nullable int64_t[4] in device memory, zeroed by the caller; calls
  *    add to them): [0] pages/elements routed to FP64, [1] singular pages/elements,
- *    [2] out-of-range indices met, [3] reserved.
+ *    [2] out-of-range indices met, [3] reserved.  The element-parallel calls (pf_elem_*,
+ *    pf_rhs, pf_p2_elements) and pf_assemble(_quad) count per workgroup: a call given
+ *    counters takes a small stream-ordered pool block (pf_assemble: an array of the
+ *    structure) for the workgroups' counts and one more launch that sums them in; without
+ *    counters neither happens.
  *  - Per-page flags (nullable uint8 array, one per page/element): bit 0 singular
  *    (determinant exactly zero in the final precision), bit 1 routed to FP64, bit 2 bad
  *    index.
