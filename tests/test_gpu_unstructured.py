@@ -101,6 +101,12 @@ def test_unstructured_rhs_and_energies(lib, dtype):
     b = torch.empty(nn, dtype=dtype, device="cuda")
     ctr = counters()
     csr.rhs(prec_of(dtype), dev(coords), te, 2, dev(f, dtype), b2D, b, counters=ctr)
+    n_rhs = int(host(ctr)[0])
+    if dtype == torch.float32:  # the routed count, summed from per-workgroup counts
+        s = _sigma(coords, elems)
+        assert int((s > 16.0 * (1 + 1e-4)).sum()) <= n_rhs <= int((s > 16.0 * (1 - 1e-4)).sum())
+    else:
+        assert n_rhs == 0
     J = torch.empty(3 * ne, dtype=dtype, device="cuda")
     tot = torch.empty(3, dtype=torch.float64, device="cuda")
     csr.energies(prec_of(dtype), dev(coords), te, 2, dev(u, dtype), cKq=dev(cK, dtype), cMq=dev(cM, dtype), b2D=b2D,
@@ -114,6 +120,7 @@ def test_unstructured_rhs_and_energies(lib, dtype):
     for c, k in enumerate(("J1", "J2", "J3")):
         within(Jg[c], Jr[k + "k"], Jr[k + "abs"], TOL[dtype], k)
     assert host(ctr)[2] == 0
+    assert int(host(ctr)[0]) == 2 * n_rhs  # the energies route the same elements
     csr.close()
 
 
